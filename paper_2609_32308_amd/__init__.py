@@ -1,0 +1,198 @@
+"""Python binding of libsparsedesign.so (argument marshalling only).
+
+Every step of the design DP runs in the library's gfx950 kernels; this module only converts
+arguments and results.  There is no fallback: if the shared library is missing the import of
+`lib()` raises, and without a gfx950 device `Context()` raises SDError(SD_E_DEVICE).
+"""
+from __future__ import annotations
+
+import ctypes as C
+import os
+from dataclasses import dataclass
+
+import numpy as np
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(HERE, "libsparsedesign.so")
+INF = 1 << 62
+
+STATUS = {0: "SD_OK", -1: "SD_E_ARG", -2: "SD_E_PROTEIN", -3: "SD_E_CODON_TABLE",
+          -4: "SD_E_PARAMS", -5: "SD_E_LAMBDA", -6: "SD_E_RANGE", -7: "SD_E_NOMEM",
+          -8: "SD_E_DEVICE", -9: "SD_E_BUSY", -10: "SD_E_CANCELLED", -11: "SD_E_INTERNAL"}
+
+# every function declared in include/sparsedesign.h
+EXPORTS = [
+    "sd_params_load", "sd_params_sha256", "sd_params_free", "sd_codon_table_from_weights",
+    "sd_codon_table_from_freqs", "sd_codon_table_free", "sd_context_create", "sd_context_destroy",
+    "sd_design", "sd_design_batch", "sd_design_tables", "sd_lattice_size", "sd_result_free",
+    "sd_status_str", "sd_last_error",
+]
+
+
+class SDError(RuntimeError):
+    def __init__(self, code: int, where: str, detail: str = ""):
+        super().__init__(f"{where}: {STATUS.get(code, code)} {detail}".strip())
+        self.code = code
+
+
+class Options(C.Structure):
+    _fields_ = [("retain_all", C.c_int), ("capacity_override", C.c_int), ("reserved", C.c_int * 6)]
+
+
+class _Result(C.Structure):
+    _fields_ = [
+        ("mrna", C.c_void_p), ("structure", C.c_void_p), ("energy_centi", C.c_int32),
+        ("codon_cost", C.c_double), ("objective_kcal", C.c_double), ("objective_fixed", C.c_int64),
+        ("fixed_shift", C.c_int32), ("cai", C.c_double), ("n_states", C.c_int64),
+        ("n_cells", C.c_int64), ("n_candidates", C.c_int64), ("n_visits", C.c_int64),
+        ("n_feasible", C.c_int64), ("t_fill_s", C.c_double), ("t_total_s", C.c_double),
+    ]
+
+
+_lib = None
+
+
+def lib():
+    """Load the in-tree library; raises if it has not been built."""
+    global _lib
+    if _lib is None:
+        if not os.path.exists(LIB_PATH):
+            raise ImportError(f"{LIB_PATH} is missing: build it with paper_2609_32308_amd/build.py")
+        L = C.CDLL(LIB_PATH)
+        vp, P64 = C.c_void_p, C.POINTER(C.c_int64)
+        L.sd_params_load.argtypes = [C.c_char_p, C.c_char_p, C.POINTER(vp)]
+        L.sd_params_sha256.argtypes = [vp, C.c_char_p]
+        L.sd_params_free.argtypes = [vp]
+        L.sd_codon_table_from_weights.argtypes = [C.POINTER(C.c_double), C.POINTER(vp)]
+        L.sd_codon_table_from_freqs.argtypes = [C.POINTER(C.c_double), C.POINTER(vp)]
+        L.sd_codon_table_free.argtypes = [vp]
+        L.sd_context_create.argtypes = [C.c_int, C.POINTER(Options), C.POINTER(vp)]
+        L.sd_context_destroy.argtypes = [vp]
+        L.sd_design.argtypes = [vp, C.c_char_p, vp, vp, C.c_double, C.POINTER(_Result)]
+        L.sd_design_batch.argtypes = [vp, C.c_int, C.POINTER(C.c_char_p), C.POINTER(C.c_double),
+                                      vp, vp, C.POINTER(_Result)]
+        L.sd_design_tables.argtypes = [vp, C.c_char_p, vp, vp, C.c_double, C.POINTER(_Result),
+                                       P64, P64, P64, P64, P64]
+        L.sd_lattice_size.argtypes = [C.c_char_p, P64, P64]
+        L.sd_result_free.argtypes = [C.POINTER(_Result)]
+        L.sd_status_str.argtypes = [C.c_int]
+        L.sd_status_str.restype = C.c_char_p
+        L.sd_last_error.argtypes = []
+        L.sd_last_error.restype = C.c_char_p
+        _lib = L
+    return _lib
+
+
+def _check(rc: int, where: str):
+    if rc != 0:
+        raise SDError(rc, where, lib().sd_last_error().decode(errors="replace"))
+
+
+class Params:
+    def __init__(self, path: str, expect_sha256: str | None = None):
+        h = C.c_void_p()
+        _check(lib().sd_params_load(path.encode(), expect_sha256.encode() if expect_sha256 else None,
+                                    C.byref(h)), "sd_params_load")
+        self.h = h
+
+    @property
+    def sha256(self) -> str:
+        buf = C.create_string_buffer(65)
+        _check(lib().sd_params_sha256(self.h, buf), "sd_params_sha256")
+        return buf.value.decode()
+
+    def __del__(self):
+        if getattr(self, "h", None) and _lib is not None:
+            _lib.sd_params_free(self.h)
+            self.h = None
+
+
+class CodonTable:
+    def __init__(self, weights=None, freqs=None):
+        h = C.c_void_p()
+        if weights is not None:
+            a = np.ascontiguousarray(weights, dtype=np.float64)
+            _check(lib().sd_codon_table_from_weights(a.ctypes.data_as(C.POINTER(C.c_double)), C.byref(h)),
+                   "sd_codon_table_from_weights")
+        else:
+            a = np.ascontiguousarray(freqs, dtype=np.float64)
+            _check(lib().sd_codon_table_from_freqs(a.ctypes.data_as(C.POINTER(C.c_double)), C.byref(h)),
+                   "sd_codon_table_from_freqs")
+        self.h = h
+
+    def __del__(self):
+        if getattr(self, "h", None) and _lib is not None:
+            _lib.sd_codon_table_free(self.h)
+            self.h = None
+
+
+@dataclass
+class Result:
+    mrna: str
+    structure: str
+    energy: int
+    codon_cost: float
+    objective_kcal: float
+    objective_fixed: int
+    fixed_shift: int
+    cai: float
+    n_states: int
+    n_cells: int
+    n_candidates: int
+    n_visits: int
+    n_feasible: int
+    t_fill_s: float
+    t_total_s: float
+
+
+def _convert(r: _Result) -> Result:
+    out = Result(C.string_at(r.mrna).decode(), C.string_at(r.structure).decode(), r.energy_centi,
+                 r.codon_cost, r.objective_kcal, r.objective_fixed, r.fixed_shift, r.cai, r.n_states,
+                 r.n_cells, r.n_candidates, r.n_visits, r.n_feasible, r.t_fill_s, r.t_total_s)
+    lib().sd_result_free(C.byref(r))
+    return out
+
+
+class Context:
+    def __init__(self, device: int = 0, retain_all: bool = False, capacity_override: int = 0):
+        opt = Options(int(retain_all), int(capacity_override))
+        h = C.c_void_p()
+        _check(lib().sd_context_create(device, C.byref(opt), C.byref(h)), "sd_context_create")
+        self.h = h
+
+    def close(self):
+        if getattr(self, "h", None) and _lib is not None:
+            _lib.sd_context_destroy(self.h)
+            self.h = None
+
+    __del__ = close
+
+    def design(self, protein: str, table: CodonTable, params: Params, lam: float) -> Result:
+        r = _Result()
+        _check(lib().sd_design(self.h, protein.encode(), table.h, params.h, float(lam), C.byref(r)), "sd_design")
+        return _convert(r)
+
+    def design_batch(self, proteins, lambdas, table: CodonTable, params: Params):
+        n = len(proteins)
+        arr = (C.c_char_p * n)(*[p.encode() for p in proteins])
+        lam = (C.c_double * n)(*[float(x) for x in lambdas])
+        res = (_Result * n)()
+        _check(lib().sd_design_batch(self.h, n, arr, lam, table.h, params.h, res), "sd_design_batch")
+        return [_convert(res[i]) for i in range(n)]
+
+    def design_tables(self, protein: str, table: CodonTable, params: Params, lam: float):
+        N, _ = lattice_size(protein)
+        V = np.empty((6, N, N), np.int64)
+        B, S1, S2 = (np.empty((N, N), np.int64) for _ in range(3))
+        X = np.empty(N, np.int64)
+        p = lambda a: a.ctypes.data_as(C.POINTER(C.c_int64))
+        r = _Result()
+        _check(lib().sd_design_tables(self.h, protein.encode(), table.h, params.h, float(lam), C.byref(r),
+                                      p(V), p(B), p(S1), p(S2), p(X)), "sd_design_tables")
+        return _convert(r), {"V": V, "B": B, "S1": S1, "S2": S2, "X": X}
+
+
+def lattice_size(protein: str):
+    n, c = C.c_int64(), C.c_int64()
+    _check(lib().sd_lattice_size(protein.encode(), C.byref(n), C.byref(c)), "sd_lattice_size")
+    return n.value, c.value

@@ -1,0 +1,490 @@
+// C ABI of the library: handles, validation, device memory and the plain span-step driver.
+#include <hip/hip_runtime.h>
+#include <math.h>
+#include <stdio.h>
+#include <stdlib.h>
+#include <string.h>
+
+#include <chrono>
+#include <fstream>
+#include <mutex>
+#include <sstream>
+#include <string>
+#include <vector>
+
+#include "../../include/sparsedesign.h"
+#include "sd_device.h"
+#include "sd_lattice.h"
+#include "sd_traceback.h"
+
+using namespace sd;
+
+struct sd_params {
+    Params p;
+    uint64_t uid;
+};
+struct sd_codon_table {
+    CodonTable t;
+};
+
+namespace {
+thread_local std::string g_err;
+uint64_t g_uid = 1;
+std::mutex g_uid_mu;
+
+sd_status fail(sd_status s, const std::string& msg) {
+    g_err = msg;
+    return s;
+}
+sd_status hip_fail(hipError_t e, const char* where) {
+    return fail(SD_E_DEVICE, std::string(where) + ": " + hipGetErrorString(e));
+}
+double now_s() {
+    return std::chrono::duration<double>(std::chrono::steady_clock::now().time_since_epoch()).count();
+}
+const char kCode64[65] = "KNKNTTTTRSRSIIMIQHQHPPPPRRRRLLLLEDEDAAAAGGGGVVVV*Y*YSSSS*CWCLFLF";
+}  // namespace
+
+// ------------------------------------------------------------------------------------------------
+extern "C" const char* sd_status_str(sd_status s) {
+    switch (s) {
+        case SD_OK: return "ok";
+        case SD_E_ARG: return "invalid argument";
+        case SD_E_PROTEIN: return "invalid protein";
+        case SD_E_CODON_TABLE: return "invalid codon table";
+        case SD_E_PARAMS: return "invalid parameter file";
+        case SD_E_LAMBDA: return "invalid lambda";
+        case SD_E_RANGE: return "fixed-point range exceeded";
+        case SD_E_NOMEM: return "out of memory";
+        case SD_E_DEVICE: return "device error";
+        case SD_E_BUSY: return "busy";
+        case SD_E_CANCELLED: return "cancelled";
+        case SD_E_INTERNAL: return "internal error";
+    }
+    return "unknown status";
+}
+
+extern "C" const char* sd_last_error(void) { return g_err.c_str(); }
+
+extern "C" sd_status sd_params_load(const char* path, const char* expect_sha256, sd_params** out) {
+    if (!path || !out) return fail(SD_E_ARG, "null argument");
+    *out = nullptr;
+    std::ifstream f(path, std::ios::binary);
+    if (!f) return fail(SD_E_PARAMS, std::string("cannot open ") + path);
+    std::stringstream ss;
+    ss << f.rdbuf();
+    std::string text = ss.str();
+    sd_params* p = new (std::nothrow) sd_params();
+    if (!p) return fail(SD_E_NOMEM, "host allocation");
+    std::string err;
+    int rc = parse_params(text, p->p, err);
+    if (rc) {
+        delete p;
+        return fail((sd_status)rc, err);
+    }
+    p->p.sha256 = sha256_hex(text);
+    if (expect_sha256 && p->p.sha256 != expect_sha256) {
+        delete p;
+        return fail(SD_E_PARAMS, "parameter file SHA-256 mismatch");
+    }
+    {
+        std::lock_guard<std::mutex> lk(g_uid_mu);
+        p->uid = g_uid++;
+    }
+    *out = p;
+    return SD_OK;
+}
+
+extern "C" sd_status sd_params_sha256(const sd_params* p, char out[65]) {
+    if (!p || !out) return fail(SD_E_ARG, "null argument");
+    memcpy(out, p->p.sha256.c_str(), 65);
+    return SD_OK;
+}
+
+extern "C" void sd_params_free(sd_params* p) { delete p; }
+
+extern "C" sd_status sd_codon_table_from_weights(const double w[64], sd_codon_table** out) {
+    if (!w || !out) return fail(SD_E_ARG, "null argument");
+    for (int i = 0; i < 64; i++)
+        if (!(w[i] > 0.0 && w[i] <= 1.0)) return fail(SD_E_CODON_TABLE, "weights must lie in (0,1]");
+    sd_codon_table* t = new (std::nothrow) sd_codon_table();
+    if (!t) return fail(SD_E_NOMEM, "host allocation");
+    memcpy(t->t.w, w, sizeof(double) * 64);
+    *out = t;
+    return SD_OK;
+}
+
+extern "C" sd_status sd_codon_table_from_freqs(const double f[64], sd_codon_table** out) {
+    if (!f || !out) return fail(SD_E_ARG, "null argument");
+    double w[64];
+    for (int i = 0; i < 64; i++) {
+        if (!(f[i] > 0.0) || !std::isfinite(f[i])) return fail(SD_E_CODON_TABLE, "frequencies must be positive");
+        double mx = 0.0;
+        for (int j = 0; j < 64; j++)
+            if (kCode64[j] == kCode64[i]) mx = std::max(mx, f[j]);
+        w[i] = f[i] / mx;
+    }
+    return sd_codon_table_from_weights(w, out);
+}
+
+extern "C" void sd_codon_table_free(sd_codon_table* t) { delete t; }
+
+// ------------------------------------------------------------------------------------------------
+extern "C" sd_status sd_context_create(int device, const sd_options* opt, sd_context** out) {
+    if (!out) return fail(SD_E_ARG, "null argument");
+    *out = nullptr;
+    int ndev = 0;
+    hipError_t e = hipGetDeviceCount(&ndev);
+    if (e != hipSuccess || ndev <= 0) return fail(SD_E_DEVICE, "no HIP device");
+    if (device < 0 || device >= ndev) return fail(SD_E_ARG, "device index out of range");
+    hipDeviceProp_t prop;
+    e = hipGetDeviceProperties(&prop, device);
+    if (e != hipSuccess) return hip_fail(e, "hipGetDeviceProperties");
+    if (strncmp(prop.gcnArchName, "gfx950", 6) != 0)
+        return fail(SD_E_DEVICE, std::string("kernels are built for gfx950, device is ") + prop.gcnArchName);
+    sd_context* c = new (std::nothrow) sd_context();
+    if (!c) return fail(SD_E_NOMEM, "host allocation");
+    c->device = device;
+    c->num_cu = prop.multiProcessorCount;
+    if (opt) c->opt = *opt;
+    e = hipSetDevice(device);
+    if (e == hipSuccess) e = hipStreamCreateWithFlags(&c->stream, hipStreamNonBlocking);
+    if (e == hipSuccess) e = upload_pair_order();
+    if (e == hipSuccess) e = hipEventCreate(&c->ev0);
+    if (e == hipSuccess) e = hipEventCreate(&c->ev1);
+    if (e != hipSuccess) {
+        delete c;
+        return hip_fail(e, "context setup");
+    }
+    *out = c;
+    return SD_OK;
+}
+
+extern "C" void sd_context_destroy(sd_context* c) {
+    if (!c) return;
+    hipSetDevice(c->device);
+    if (c->stream) hipStreamSynchronize(c->stream);
+    if (c->arena) hipFree(c->arena);
+    if (c->E_dev) hipFree(c->E_dev);
+    if (c->spec_dev) hipFree(c->spec_dev);
+    if (c->ev0) hipEventDestroy(c->ev0);
+    if (c->ev1) hipEventDestroy(c->ev1);
+    if (c->stream) hipStreamDestroy(c->stream);
+    delete c;
+}
+
+namespace sd {
+
+sd_status ensure_params(sd_context* c, const sd_params* p) {
+    if (c->params_uid == p->uid) return SD_OK;
+    hipError_t e = hipSuccess;
+    if (!c->E_dev) e = hipMalloc(&c->E_dev, sizeof(EnergyTables));
+    if (e == hipSuccess && !c->spec_dev) e = hipMalloc(&c->spec_dev, sizeof(int32_t) * kSpecSize);
+    if (e == hipSuccess) e = hipMemcpy(c->E_dev, &p->p.E, sizeof(EnergyTables), hipMemcpyHostToDevice);
+    if (e == hipSuccess)
+        e = hipMemcpy(c->spec_dev, p->p.spec_table.data(), sizeof(int32_t) * kSpecSize, hipMemcpyHostToDevice);
+    if (e != hipSuccess) return hip_fail(e, "parameter upload");
+    c->params_uid = p->uid;
+    return SD_OK;
+}
+
+sd_status ensure_arena(sd_context* c, size_t bytes) {
+    if (bytes <= c->arena_bytes) return SD_OK;
+    if (c->arena) {
+        hipStreamSynchronize(c->stream);
+        hipFree(c->arena);
+        c->arena = nullptr;
+        c->arena_bytes = 0;
+    }
+    size_t want = bytes + bytes / 8;
+    hipError_t e = hipMalloc(&c->arena, want);
+    if (e != hipSuccess) {
+        hipGetLastError();
+        return fail(SD_E_NOMEM, "device allocation of " + std::to_string(want) + " bytes failed");
+    }
+    c->arena_bytes = want;
+    return SD_OK;
+}
+
+// Lay out one instance's device arrays in [base, base + size) and fill the pointers of I.
+size_t layout_instance(const Lattice& L, char* base, Inst& I, bool place) {
+    size_t off = 0;
+    auto take = [&](size_t bytes) -> char* {
+        off = (off + 255) & ~(size_t)255;
+        char* p = base ? base + off : nullptr;
+        off += bytes;
+        return p;
+    };
+    const size_t N = L.N, n = L.n, nE = L.in_src.size(), cells = L.cells, slots = L.cand_slots;
+    I.layer = (int*)take(N * 4);
+    I.off = (int*)take((n + 2) * 4);
+    I.out_dst = (int*)take(4 * N * 4);
+    I.out_U = (int64_t*)take(4 * N * 8);
+    I.in_start = (int*)take((N + 1) * 4);
+    I.in_src = (int*)take(nE * 4);
+    I.in_lab = (int*)take(nE * 4);
+    I.in_U = (int64_t*)take(nE * 8);
+    I.tail = (int64_t*)take(N * 8);
+    I.pfx = (int*)take(N * 4);
+    I.P = (int64_t*)take((L.A + 1) * 8);
+    I.hp_init = (int*)take((n + 1) * 4);
+    I.rowoff = (int64_t*)take(N * 8);
+    I.coff = (int64_t*)take(N * 8);
+    I.ccap = (int*)take(N * 4);
+    I.ccnt = (int*)take(N * 4);
+    I.X = (int64_t*)take(N * 8);
+    I.stats = (unsigned long long*)take(4 * 8);
+    I.span_appends = (unsigned long long*)take((n + 1) * 8);
+    I.V = (int64_t*)take(cells * 6 * 8);
+    I.Bt = (int64_t*)take(cells * 8);
+    I.S1 = (int64_t*)take(cells * 8);
+    I.S2 = (int64_t*)take(cells * 8);
+    I.cc = (int*)take(slots * 4);
+    I.cB = (int64_t*)take(slots * 8);
+    off = (off + 255) & ~(size_t)255;
+    (void)place;
+    I.n = L.n;
+    I.N = L.N;
+    I.A = L.A;
+    I.shift = L.shift;
+    I.mlbase_fx = L.mlbase_fx;
+    return off;
+}
+
+hipError_t upload_instance(const Lattice& L, const Inst& I, hipStream_t st) {
+    struct Cp {
+        void* d;
+        const void* h;
+        size_t bytes;
+    } cps[] = {
+        {(void*)I.layer, L.layer.data(), L.layer.size() * 4},
+        {(void*)I.off, L.off.data(), L.off.size() * 4},
+        {(void*)I.out_dst, L.out_dst.data(), L.out_dst.size() * 4},
+        {(void*)I.out_U, L.out_U.data(), L.out_U.size() * 8},
+        {(void*)I.in_start, L.in_start.data(), L.in_start.size() * 4},
+        {(void*)I.in_src, L.in_src.data(), L.in_src.size() * 4},
+        {(void*)I.in_lab, L.in_lab.data(), L.in_lab.size() * 4},
+        {(void*)I.in_U, L.in_U.data(), L.in_U.size() * 8},
+        {(void*)I.tail, L.tail.data(), L.tail.size() * 8},
+        {(void*)I.pfx, L.pfx.data(), L.pfx.size() * 4},
+        {(void*)I.P, L.P.data(), L.P.size() * 8},
+        {(void*)I.hp_init, L.hp_init.data(), L.hp_init.size() * 4},
+        {(void*)I.rowoff, L.rowoff.data(), L.rowoff.size() * 8},
+        {(void*)I.coff, L.coff.data(), L.coff.size() * 8},
+        {(void*)I.ccap, L.ccap.data(), L.ccap.size() * 4},
+    };
+    for (auto& c : cps) {
+        if (!c.bytes) continue;
+        hipError_t e = hipMemcpyAsync(c.d, c.h, c.bytes, hipMemcpyHostToDevice, st);
+        if (e != hipSuccess) return e;
+    }
+    return hipSuccess;
+}
+
+// Plain mode: one span-step launch per span length.  Returns the overflow span (0 if none).
+sd_status run_plain(sd_context* c, const Lattice& L, Inst& I, int64_t* overflow_span) {
+    hipStream_t st = c->stream;
+    hipError_t e = launch_init(I, st);
+    for (int g = 1; g <= L.n && e == hipSuccess; g++)
+        e = launch_span(I, (const EnergyTables*)c->E_dev, (const int32_t*)c->spec_dev, g,
+                        g >= 2 ? L.n - g + 1 : -1, st);
+    if (e == hipSuccess) e = launch_ext(I, (const EnergyTables*)c->E_dev, 0, st);
+    unsigned long long stats[4];
+    if (e == hipSuccess) e = hipMemcpyAsync(stats, I.stats, sizeof(stats), hipMemcpyDeviceToHost, st);
+    if (e == hipSuccess) e = hipStreamSynchronize(st);
+    if (e != hipSuccess) return hip_fail(e, "span wavefront");
+    *overflow_span = stats[2] == ~0ull ? 0 : (int64_t)stats[2];
+    c->last_visits = (int64_t)stats[0];
+    c->last_appends = (int64_t)stats[1];
+    c->last_feasible = (int64_t)stats[3];
+    return SD_OK;
+}
+
+sd_status fetch_tables(sd_context* c, const Lattice& L, const Inst& I, TraceTables& T) {
+    hipStream_t st = c->stream;
+    T.V.resize(L.cells * 6);
+    T.B.resize(L.cells);
+    T.S1.resize(L.cells);
+    T.S2.resize(L.cells);
+    T.X.resize(L.N);
+    T.ccnt.resize(L.N);
+    T.cc.resize(L.cand_slots);
+    hipError_t e = hipMemcpyAsync(T.V.data(), I.V, L.cells * 48, hipMemcpyDeviceToHost, st);
+    if (e == hipSuccess) e = hipMemcpyAsync(T.B.data(), I.Bt, L.cells * 8, hipMemcpyDeviceToHost, st);
+    if (e == hipSuccess) e = hipMemcpyAsync(T.S1.data(), I.S1, L.cells * 8, hipMemcpyDeviceToHost, st);
+    if (e == hipSuccess) e = hipMemcpyAsync(T.S2.data(), I.S2, L.cells * 8, hipMemcpyDeviceToHost, st);
+    if (e == hipSuccess) e = hipMemcpyAsync(T.X.data(), I.X, L.N * 8, hipMemcpyDeviceToHost, st);
+    if (e == hipSuccess) e = hipMemcpyAsync(T.ccnt.data(), I.ccnt, L.N * 4, hipMemcpyDeviceToHost, st);
+    if (e == hipSuccess && L.cand_slots)
+        e = hipMemcpyAsync(T.cc.data(), I.cc, L.cand_slots * 4, hipMemcpyDeviceToHost, st);
+    if (e == hipSuccess) e = hipStreamSynchronize(st);
+    if (e != hipSuccess) return hip_fail(e, "table download");
+    return SD_OK;
+}
+
+char* dup_str(const std::string& s) {
+    char* p = (char*)malloc(s.size() + 1);
+    if (p) memcpy(p, s.c_str(), s.size() + 1);
+    return p;
+}
+
+sd_status fill_result(const Lattice& L, const TraceResult& R, int64_t xs, int64_t Z, int64_t visits,
+                      int64_t feasible, sd_result* out) {
+    sd_result r;
+    memset(&r, 0, sizeof(r));
+    r.mrna = dup_str(R.mrna);
+    r.structure = dup_str(R.structure);
+    if (!r.mrna || !r.structure) {
+        free(r.mrna);
+        free(r.structure);
+        return fail(SD_E_NOMEM, "host allocation");
+    }
+    r.energy_centi = R.energy;
+    r.codon_cost = R.codon_cost;
+    r.objective_kcal = (double)R.energy / 100.0 + L.lambda * R.codon_cost;
+    r.objective_fixed = xs;
+    r.fixed_shift = L.shift;
+    r.cai = exp(-R.codon_cost / (double)L.A);
+    r.n_states = L.N;
+    r.n_cells = L.cells;
+    r.n_candidates = Z;
+    r.n_visits = visits;
+    r.n_feasible = feasible;
+    *out = r;
+    return SD_OK;
+}
+
+// One plain design; optionally keeps the downloaded tables.
+sd_status design_plain(sd_context* c, const char* protein, const sd_codon_table* table,
+                       const sd_params* params, double lambda, sd_result* out, TraceTables* keep,
+                       Lattice* keepL) {
+    const double t0 = now_s();
+    if (!c || !table || !params || !out) return fail(SD_E_ARG, "null argument");
+    hipError_t he = hipSetDevice(c->device);
+    if (he != hipSuccess) return hip_fail(he, "hipSetDevice");
+    Lattice L;
+    std::string err;
+    int cap = c->opt.capacity_override;
+    int rc = build_lattice(protein, table->t, params->p, lambda, cap, L, err);
+    if (rc) return fail((sd_status)rc, err);
+    sd_status s = ensure_params(c, params);
+    if (s) return s;
+    const double tf0 = now_s();
+    Inst I;
+    memset(&I, 0, sizeof(I));
+    for (int attempt = 0; attempt < 2; attempt++) {
+        size_t bytes = layout_instance(L, nullptr, I, false);
+        s = ensure_arena(c, bytes);
+        if (s) return s;
+        layout_instance(L, (char*)c->arena, I, true);
+        I.retain_all = c->opt.retain_all;
+        he = upload_instance(L, I, c->stream);
+        if (he != hipSuccess) return hip_fail(he, "upload");
+        int64_t ovf = 0;
+        s = run_plain(c, L, I, &ovf);
+        if (s) return s;
+        if (!ovf) break;
+        // overflow of a predicted / overridden capacity: fall back to exact worst-case segments
+        if (attempt == 1) return fail(SD_E_INTERNAL, "candidate overflow with worst-case capacity");
+        c->last_overflow_span = ovf;
+        rc = build_lattice(protein, table->t, params->p, lambda, 0, L, err);
+        if (rc) return fail((sd_status)rc, err);
+    }
+    const double tf1 = now_s();
+    TraceTables T;
+    s = fetch_tables(c, L, I, T);
+    if (s) return s;
+    TraceResult R;
+    rc = trace_design(L, params->p, T, R);
+    if (rc) return fail((sd_status)rc, "traceback self-check failed");
+    int64_t Z = 0;
+    for (int v = 0; v < L.N; v++) Z += T.ccnt[v];
+    s = fill_result(L, R, T.X[0], c->opt.retain_all ? -1 : Z, c->last_visits, c->last_feasible, out);
+    if (s) return s;
+    if (c->opt.retain_all) {
+        int64_t strict = 0;
+        for (int v = 0; v < L.N; v++)
+            for (int k = 0; k < T.ccnt[v]; k++) strict += T.cc[L.coff[v] + k] >= 0;
+        out->n_candidates = strict;
+    }
+    out->t_fill_s = tf1 - tf0;
+    out->t_total_s = now_s() - t0;
+    if (keep) *keep = std::move(T);
+    if (keepL) *keepL = std::move(L);
+    return SD_OK;
+}
+
+}  // namespace sd
+
+extern "C" sd_status sd_design(sd_context* ctx, const char* protein, const sd_codon_table* table,
+                               const sd_params* params, double lambda_kcal, sd_result* out) {
+    try {
+        return design_plain(ctx, protein, table, params, lambda_kcal, out, nullptr, nullptr);
+    } catch (const std::bad_alloc&) {
+        return fail(SD_E_NOMEM, "host allocation");
+    } catch (...) {
+        return fail(SD_E_INTERNAL, "unexpected exception");
+    }
+}
+
+extern "C" sd_status sd_lattice_size(const char* protein, int64_t* n_states, int64_t* n_cells) {
+    if (!n_states || !n_cells) return fail(SD_E_ARG, "null argument");
+    int rc = check_protein(protein);
+    if (rc) return fail((sd_status)rc, "invalid protein");
+    CodonTable T;
+    for (int i = 0; i < 64; i++) T.w[i] = 1.0;
+    Params P;
+    memset(&P.E, 0, sizeof(P.E));
+    Lattice L;
+    std::string err;
+    rc = build_lattice(protein, T, P, 0.0, 0, L, err);
+    if (rc) return fail((sd_status)rc, err);
+    *n_states = L.N;
+    *n_cells = L.cells;
+    return SD_OK;
+}
+
+extern "C" sd_status sd_design_tables(sd_context* ctx, const char* protein, const sd_codon_table* table,
+                                      const sd_params* params, double lambda_kcal, sd_result* out,
+                                      int64_t* V, int64_t* B, int64_t* S1, int64_t* S2, int64_t* X) {
+    try {
+        TraceTables T;
+        Lattice L;
+        sd_status s = design_plain(ctx, protein, table, params, lambda_kcal, out, &T, &L);
+        if (s) return s;
+        const size_t N = L.N;
+        auto dense = [&](int64_t* dst, const std::vector<int64_t>& src, int stride, int t) {
+            if (!dst) return;
+            for (size_t a = 0; a < N; a++)
+                for (size_t b = 0; b < N; b++) {
+                    int64_t v = kINF;
+                    if (L.layer[a] < L.layer[b]) v = src[(L.rowoff[a] + (b - L.off[L.layer[a] + 1])) * stride + t];
+                    dst[a * N + b] = v;
+                }
+        };
+        for (int t = 0; t < 6 && V; t++) dense(V + (size_t)t * N * N, T.V, 6, t);
+        dense(B, T.B, 1, 0);
+        dense(S1, T.S1, 1, 0);
+        dense(S2, T.S2, 1, 0);
+        if (X) memcpy(X, T.X.data(), N * 8);
+        return SD_OK;
+    } catch (const std::bad_alloc&) {
+        return fail(SD_E_NOMEM, "host allocation");
+    } catch (...) {
+        return fail(SD_E_INTERNAL, "unexpected exception");
+    }
+}
+
+extern "C" void sd_result_free(sd_result* r) {
+    if (!r) return;
+    free(r->mrna);
+    free(r->structure);
+    r->mrna = nullptr;
+    r->structure = nullptr;
+}
+
+extern "C" sd_status sd_design_batch(sd_context* ctx, int n, const char* const* proteins,
+                                     const double* lambdas, const sd_codon_table* table,
+                                     const sd_params* params, sd_result* outs) {
+    return design_batch_impl(ctx, n, proteins, lambdas, table, params, outs);
+}

@@ -1,0 +1,67 @@
+// Internal layout shared by the host side of the library and its gfx950 kernels.
+//
+// Device data of one design instance (all int64 values are fixed point: energy * 2^s plus
+// rounded codon costs; kINF = 2^62 marks infeasible):
+//   automaton   layer[N], off[n+2] (first state of each layer), out_dst/out_U[N*4] (edge by
+//               label, DFA so at most one per label), in-edge CSR sorted by (source, label).
+//   gap         closed form for the codon trie: G(a,b) = tail(a) + P[k(b)] - P[k(a)+1] across
+//               codons, 0 / unreachable inside one codon (prefix test on pfx).
+//   cells       row layout over state pairs: cell(a,b) = rowoff[a] + b - off[layer(a)+1], i.e.
+//               row a holds every b of a later layer, contiguous in state order.  Per cell:
+//               V[6] (typed closed values), B (branch), S1, S2 (multiloop fragments).
+//   candidates  per right endpoint b a packed segment [coff[b], coff[b]+ccap[b]) of
+//               (cc = start state, cB = B(c,b)); ccnt[b] entries committed so far, appended in
+//               span order (each span's entries in start-state order).
+#pragma once
+#include <stdint.h>
+
+namespace sd {
+
+constexpr int64_t kINF = int64_t(1) << 62;
+constexpr int64_t kHalfINF = int64_t(1) << 61;  // anything above is infeasible
+constexpr int kMaxLoop = 30;                    // bulge / interior unpaired cap (Sec. 3)
+constexpr int kNumPairs = 496;                  // (l1,l2) with l1 + l2 <= 30
+
+// Energy tables in 0.01 kcal/mol; two-loop tables index the inner pair from inside the loop.
+struct EnergyTables {
+    int32_t stack[6][6];
+    int32_t mmH[6][4][4], mmI[6][4][4], mm1n[6][4][4], mm23[6][4][4];
+    int32_t int11[6][6][4][4];
+    int32_t int21[6][6][4][4][4];
+    int32_t int22[6][6][4][4][4][4];
+    int32_t hairpin[31], bulge[31], interior[31];
+    int32_t ml_closing, ml_intern, ml_base, terminal_au, ninio, ninio_max;
+    int32_t pad[2];
+};
+
+// Special hairpin lookup: key = base-4 number of the loop sequence (closing pair included),
+// value = listed total energy or kNoSpecial.
+constexpr int32_t kNoSpecial = 0x7fffffff;
+constexpr int kSpecOff5 = 0, kSpecOff6 = 1024, kSpecOff8 = 1024 + 4096, kSpecSize = 1024 + 4096 + 65536;
+
+struct Inst {
+    int n, N, A, shift;
+    int64_t mlbase_fx;  // ML_base * 2^s
+    const int *layer, *off;
+    const int *out_dst;
+    const int64_t *out_U;
+    const int *in_start, *in_src, *in_lab;
+    const int64_t *in_U;
+    const int64_t *tail;  // cheapest completion of the current codon from a state
+    const int *pfx;       // 2-base prefix code of a phase-2 state (4x+y), base x of phase 1
+    const int64_t *P;     // prefix sums of per-codon minimum cost, A+1 entries
+    const int *hp_init;   // hairpin initiation per size m (extrapolated above 30), n+1 entries
+    const int64_t *rowoff;
+    int64_t *V, *Bt, *S1, *S2;
+    const int64_t *coff;
+    const int *ccap;
+    int *ccnt;
+    int *cc;
+    int64_t *cB;
+    int64_t *X;
+    unsigned long long *stats;  // [0] visits [1] appends [2] overflow flag [3] feasible B
+    unsigned long long *span_appends;  // per span appended candidates (n+1), may be null
+    int retain_all;
+};
+
+}  // namespace sd

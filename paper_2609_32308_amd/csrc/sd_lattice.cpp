@@ -1,0 +1,407 @@
+// Host preparation of a design: parameter parsing, input validation, the codon trie automaton
+// (Sec. 3), fixed-point edge costs and the table layouts used by the kernels.
+#include "sd_lattice.h"
+
+#include <math.h>
+#include <string.h>
+
+#include <algorithm>
+#include <sstream>
+
+#include "../../include/sparsedesign.h"
+
+namespace sd {
+
+namespace {
+// standard genetic code, codon index 16*b1 + 4*b2 + b3 with A<C<G<U
+const char kCode[65] = "KNKNTTTTRSRSIIMIQHQHPPPPRRRRLLLLEDEDAAAAGGGGVVVV*Y*YSSSS*CWCLFLF";
+const char* kAmino = "ACDEFGHIKLMNPQRSTVWY";
+
+int nuc_code(char c) {
+    switch (c) {
+        case 'A': return 0;
+        case 'C': return 1;
+        case 'G': return 2;
+        case 'U': return 3;
+    }
+    return -1;
+}
+}  // namespace
+
+// ------------------------------------------------------------------------------------------------
+// parameter file: "SPARSEDESIGN-PARAMS 1", then [section] headers with counts
+// ------------------------------------------------------------------------------------------------
+int parse_params(const std::string& text, Params& P, std::string& err) {
+    std::istringstream in(text);
+    std::vector<std::string> tok;
+    std::string line;
+    while (std::getline(in, line)) {
+        size_t h = line.find('#');
+        if (h != std::string::npos) line = line.substr(0, h);
+        std::istringstream ls(line);
+        std::string t;
+        while (ls >> t) tok.push_back(t);
+    }
+    size_t i = 0;
+    auto need = [&](const char* what) -> const std::string* {
+        if (i >= tok.size()) {
+            err = std::string("parameter file ends inside ") + what;
+            return nullptr;
+        }
+        return &tok[i++];
+    };
+    auto as_int = [&](const std::string& s, int32_t& v, bool allow_inf) -> bool {
+        if (allow_inf && s == "INF") {
+            v = kNoSpecial;
+            return true;
+        }
+        char* end = nullptr;
+        long x = strtol(s.c_str(), &end, 10);
+        if (*end || x < -100000 || x > 100000) {
+            err = "bad integer '" + s + "'";
+            return false;
+        }
+        v = (int32_t)x;
+        return true;
+    };
+    if (tok.size() < 2 || tok[0] != "SPARSEDESIGN-PARAMS" || tok[1] != "1") {
+        err = "missing 'SPARSEDESIGN-PARAMS 1' header";
+        return SD_E_PARAMS;
+    }
+    i = 2;
+    memset(&P.E, 0, sizeof(P.E));
+    unsigned seen = 0;
+    struct Arr {
+        const char* name;
+        int32_t* dst;
+        int count;
+        bool inf;
+    } arrs[] = {
+        {"[stack]", &P.E.stack[0][0], 36, false},
+        {"[mismatch_hairpin]", &P.E.mmH[0][0][0], 96, false},
+        {"[mismatch_interior]", &P.E.mmI[0][0][0], 96, false},
+        {"[mismatch_interior_1n]", &P.E.mm1n[0][0][0], 96, false},
+        {"[mismatch_interior_23]", &P.E.mm23[0][0][0], 96, false},
+        {"[int11]", &P.E.int11[0][0][0][0], 576, false},
+        {"[int21]", &P.E.int21[0][0][0][0][0], 2304, false},
+        {"[int22]", &P.E.int22[0][0][0][0][0][0], 9216, false},
+        {"[hairpin]", P.E.hairpin, 31, true},
+        {"[bulge]", P.E.bulge, 31, true},
+        {"[interior]", P.E.interior, 31, true},
+    };
+    const char* specials[3] = {"[triloop]", "[tetraloop]", "[hexaloop]"};
+    while (i < tok.size()) {
+        const std::string sec = tok[i++];
+        if (sec == "[end]") break;
+        if (sec == "[name]") {
+            if (!need("[name]")) return SD_E_PARAMS;
+            continue;
+        }
+        if (sec == "[scalars]") {
+            for (int k = 0; k < 7; k++) {
+                const std::string* key = need("[scalars]");
+                const std::string* val = need("[scalars]");
+                if (!key || !val) return SD_E_PARAMS;
+                if (*key == "lxc") {
+                    char* end = nullptr;
+                    P.lxc = strtod(val->c_str(), &end);
+                    if (*end || !(P.lxc >= 0.0 && P.lxc < 1000.0)) {
+                        err = "bad lxc";
+                        return SD_E_PARAMS;
+                    }
+                    continue;
+                }
+                int32_t v;
+                if (!as_int(*val, v, false)) return SD_E_PARAMS;
+                if (*key == "ML_closing") P.E.ml_closing = v;
+                else if (*key == "ML_intern") P.E.ml_intern = v;
+                else if (*key == "ML_base") P.E.ml_base = v;
+                else if (*key == "TerminalAU") P.E.terminal_au = v;
+                else if (*key == "Ninio") P.E.ninio = v;
+                else if (*key == "NinioMax") P.E.ninio_max = v;
+                else {
+                    err = "unknown scalar " + *key;
+                    return SD_E_PARAMS;
+                }
+            }
+            seen |= 1u << 0;
+            continue;
+        }
+        const std::string* cnt = need(sec.c_str());
+        if (!cnt) return SD_E_PARAMS;
+        int count = atoi(cnt->c_str());
+        bool done = false;
+        for (int k = 0; k < 11 && !done; k++) {
+            if (sec != arrs[k].name) continue;
+            if (count != arrs[k].count) {
+                err = sec + " has the wrong entry count";
+                return SD_E_PARAMS;
+            }
+            for (int j = 0; j < count; j++) {
+                const std::string* s = need(sec.c_str());
+                if (!s || !as_int(*s, arrs[k].dst[j], arrs[k].inf)) return SD_E_PARAMS;
+            }
+            seen |= 1u << (1 + k);
+            done = true;
+        }
+        for (int k = 0; k < 3 && !done; k++) {
+            if (sec != specials[k]) continue;
+            const size_t len = k == 0 ? 5 : k == 1 ? 6 : 8;
+            if (count < 0 || count > 4096) {
+                err = sec + " count out of range";
+                return SD_E_PARAMS;
+            }
+            for (int j = 0; j < count; j++) {
+                const std::string* s = need(sec.c_str());
+                const std::string* v = need(sec.c_str());
+                int32_t e;
+                if (!s || !v || !as_int(*v, e, false)) return SD_E_PARAMS;
+                if (s->size() != len) {
+                    err = "special loop of wrong length in " + sec;
+                    return SD_E_PARAMS;
+                }
+                for (char c : *s)
+                    if (nuc_code(c) < 0) {
+                        err = "bad base in special loop";
+                        return SD_E_PARAMS;
+                    }
+                P.special[k].push_back(*s);
+                P.special_e[k].push_back(e);
+            }
+            seen |= 1u << (12 + k);
+            done = true;
+        }
+        if (!done) {
+            err = "unknown section " + sec;
+            return SD_E_PARAMS;
+        }
+    }
+    if (seen != (1u << 15) - 1) {
+        err = "parameter file misses a section";
+        return SD_E_PARAMS;
+    }
+    for (int m = 3; m <= 30; m++)
+        if (P.E.hairpin[m] == kNoSpecial) { err = "hairpin sizes 3..30 must be finite"; return SD_E_PARAMS; }
+    for (int m = 1; m <= 30; m++)
+        if (P.E.bulge[m] == kNoSpecial) { err = "bulge sizes 1..30 must be finite"; return SD_E_PARAMS; }
+    for (int m = 2; m <= 30; m++)
+        if (P.E.interior[m] == kNoSpecial) { err = "interior sizes 2..30 must be finite"; return SD_E_PARAMS; }
+    // largest magnitude of any finite entry (input to the fixed-point range rule)
+    int32_t mx = 0;
+    auto upd = [&](int32_t v) {
+        if (v == kNoSpecial) return;
+        int32_t a = v < 0 ? -v : v;
+        if (a > mx) mx = a;
+    };
+    for (auto& a : arrs)
+        for (int j = 0; j < a.count; j++) upd(a.dst[j]);
+    for (int k = 0; k < 3; k++)
+        for (int32_t e : P.special_e[k]) upd(e);
+    for (int32_t v : {P.E.ml_closing, P.E.ml_intern, P.E.ml_base, P.E.terminal_au, P.E.ninio, P.E.ninio_max}) upd(v);
+    P.maxabs = mx;
+    // special-loop lookup table keyed by the base-4 value of the loop sequence
+    P.spec_table.assign(kSpecSize, kNoSpecial);
+    const int offs[3] = {kSpecOff5, kSpecOff6, kSpecOff8};
+    for (int k = 0; k < 3; k++)
+        for (size_t j = 0; j < P.special[k].size(); j++) {
+            int key = 0;
+            for (char c : P.special[k][j]) key = key * 4 + nuc_code(c);
+            if (P.spec_table[offs[k] + key] == kNoSpecial) P.spec_table[offs[k] + key] = P.special_e[k][j];
+        }
+    return SD_OK;
+}
+
+// ------------------------------------------------------------------------------------------------
+int check_protein(const char* p) {
+    if (!p) return SD_E_ARG;
+    size_t A = strlen(p);
+    if (A == 0) return SD_E_PROTEIN;
+    for (size_t k = 0; k < A; k++) {
+        if (p[k] == '*') {
+            if (k + 1 != A) return SD_E_PROTEIN;
+        } else if (!strchr(kAmino, p[k])) {
+            return SD_E_PROTEIN;
+        }
+    }
+    return SD_OK;
+}
+
+int64_t host_gap(const Lattice& L, int a, int b) {
+    int la = L.layer[a], lb = L.layer[b];
+    if (la == lb) return a == b ? 0 : kINF;
+    if (la > lb) return kINF;
+    int ka = la / 3, kb = lb / 3;
+    if (ka == kb) {
+        if (la % 3 == 0) return 0;
+        return (L.pfx[b] >> 2) == L.pfx[a] ? 0 : kINF;
+    }
+    return L.tail[a] + L.P[kb] - L.P[ka + 1];
+}
+
+int build_lattice(const char* protein, const CodonTable& T, const Params& P, double lambda,
+                  int capacity_override, Lattice& L, std::string& err) {
+    int rc = check_protein(protein);
+    if (rc) {
+        err = "protein must use ACDEFGHIKLMNPQRSTVWY with an optional final '*'";
+        return rc;
+    }
+    if (!(lambda >= 0.0) || !std::isfinite(lambda)) {
+        err = "lambda must be finite and >= 0";
+        return SD_E_LAMBDA;
+    }
+    L = Lattice();
+    L.protein = protein;
+    L.lambda = lambda;
+    const int A = (int)strlen(protein), n = 3 * A;
+    L.A = A;
+    L.n = n;
+    // codon families used by the protein must be normalised (max w = 1)
+    for (int k = 0; k < A; k++) {
+        double mx = 0.0;
+        for (int c = 0; c < 64; c++)
+            if (kCode[c] == protein[k]) mx = std::max(mx, T.w[c]);
+        if (mx != 1.0) {
+            err = std::string("codon family of '") + protein[k] + "' has no weight equal to 1";
+            return SD_E_CODON_TABLE;
+        }
+    }
+    // trie states: layer 3k = codon boundary, 3k+1 = first base, 3k+2 = two-base prefix
+    L.off.assign(n + 2, 0);
+    L.layer.clear();
+    L.pfx.clear();
+    std::vector<int> first(4 * (A + 1), -1), pre(16 * (A + 1), -1), beta(A + 1, -1);
+    auto add_state = [&](int lay, int code) {
+        L.layer.push_back(lay);
+        L.pfx.push_back(code);
+        return (int)L.layer.size() - 1;
+    };
+    beta[0] = add_state(0, 0);
+    for (int k = 0; k < A; k++) {
+        bool hasx[4] = {false, false, false, false}, hasxy[16] = {};
+        for (int c = 0; c < 64; c++)
+            if (kCode[c] == protein[k]) {
+                hasx[c >> 4] = true;
+                hasxy[c >> 2] = true;
+            }
+        L.off[3 * k + 1] = (int)L.layer.size();
+        for (int x = 0; x < 4; x++)
+            if (hasx[x]) first[4 * k + x] = add_state(3 * k + 1, x);
+        L.off[3 * k + 2] = (int)L.layer.size();
+        for (int xy = 0; xy < 16; xy++)
+            if (hasxy[xy]) pre[16 * k + xy] = add_state(3 * k + 2, xy);
+        L.off[3 * k + 3] = (int)L.layer.size();
+        beta[k + 1] = add_state(3 * k + 3, 0);
+    }
+    L.off[n + 1] = (int)L.layer.size();
+    const int N = L.N = (int)L.layer.size();
+    L.out_dst.assign((size_t)4 * N, -1);
+    L.out_cod.assign((size_t)4 * N, -1);
+    L.out_q.assign((size_t)4 * N, 0.0);
+    for (int k = 0; k < A; k++)
+        for (int c = 0; c < 64; c++) {
+            if (kCode[c] != protein[k]) continue;
+            int x = c >> 4, y = (c >> 2) & 3, z = c & 3;
+            L.out_dst[4 * beta[k] + x] = first[4 * k + x];
+            L.out_dst[4 * first[4 * k + x] + y] = pre[16 * k + (c >> 2)];
+            int e = 4 * pre[16 * k + (c >> 2)] + z;
+            L.out_dst[e] = beta[k + 1];
+            L.out_cod[e] = c;
+            L.out_q[e] = -log(T.w[c]);
+        }
+    // fixed point: largest shift s in [16, 40] meeting the range rule
+    const double lam100 = 100.0 * lambda;
+    const double lnf = n > 30 ? log((double)n / 30.0) : 0.0;
+    const int64_t ext = (int64_t)ceil(P.lxc * lnf) + 1;
+    const int64_t emax = 8 * ((int64_t)P.maxabs + ext);
+    int shift = -1;
+    std::vector<int64_t> Ucode(64);
+    for (int s = 40; s >= 16 && shift < 0; s--) {
+        __int128 tot = 0;
+        for (int k = 0; k < A; k++) {
+            int64_t mx = 0;
+            for (int c = 0; c < 64; c++)
+                if (kCode[c] == protein[k]) mx = std::max<int64_t>(mx, llround(ldexp(lam100 * -log(T.w[c]), s)));
+            tot += mx;
+        }
+        tot += (__int128)(n + 1) * emax * ((__int128)1 << s);
+        if (tot < ((__int128)1 << 60)) shift = s;
+    }
+    if (shift < 0) {
+        err = "fixed-point range rule cannot be met for this length / lambda";
+        return SD_E_RANGE;
+    }
+    L.shift = shift;
+    L.mlbase_fx = (int64_t)P.E.ml_base * ((int64_t)1 << shift);
+    L.out_U.assign((size_t)4 * N, 0);
+    for (size_t e = 0; e < L.out_U.size(); e++)
+        if (L.out_cod[e] >= 0) L.out_U[e] = llround(ldexp(lam100 * L.out_q[e], shift));
+    // in-edges sorted by (source, label)
+    L.in_start.assign(N + 1, 0);
+    for (int u = 0; u < N; u++)
+        for (int x = 0; x < 4; x++)
+            if (L.out_dst[4 * u + x] >= 0) L.in_start[L.out_dst[4 * u + x] + 1]++;
+    for (int v = 0; v < N; v++) L.in_start[v + 1] += L.in_start[v];
+    const int nE = L.in_start[N];
+    L.in_src.assign(nE, 0);
+    L.in_lab.assign(nE, 0);
+    L.in_cod.assign(nE, -1);
+    L.in_U.assign(nE, 0);
+    std::vector<int> fill(N, 0);
+    for (int u = 0; u < N; u++)
+        for (int x = 0; x < 4; x++) {
+            int v = L.out_dst[4 * u + x];
+            if (v < 0) continue;
+            int j = L.in_start[v] + fill[v]++;
+            L.in_src[j] = u;
+            L.in_lab[j] = x;
+            L.in_cod[j] = L.out_cod[4 * u + x];
+            L.in_U[j] = L.out_U[4 * u + x];
+        }
+    // gap closed form: cheapest completion of the current codon, per-codon minima, prefix sums
+    L.tail.assign(N, 0);
+    L.P.assign(A + 1, 0);
+    // tail: phase 0 -> codon minimum, phase 1 -> min over its completions, phase 2 -> min over
+    // its third edges; cmin = per-codon minimum for the prefix sums P
+    std::vector<int64_t> cmin(A, kINF);
+    for (int v = 0; v < N; v++) L.tail[v] = kINF;
+    for (int k = 0; k < A; k++)
+        for (int c = 0; c < 64; c++)
+            if (kCode[c] == protein[k]) {
+                int64_t u = L.out_U[4 * pre[16 * k + (c >> 2)] + (c & 3)];
+                int sb = beta[k], sx = first[4 * k + (c >> 4)], sxy = pre[16 * k + (c >> 2)];
+                cmin[k] = std::min(cmin[k], u);
+                L.tail[sb] = std::min(L.tail[sb], u);
+                L.tail[sx] = std::min(L.tail[sx], u);
+                L.tail[sxy] = std::min(L.tail[sxy], u);
+            }
+    L.tail[beta[A]] = 0;
+    for (int k = 0; k < A; k++) L.P[k + 1] = L.P[k] + cmin[k];
+    // hairpin initiation per size, extrapolated above 30 (rounded half away from zero)
+    L.hp_init.assign(n + 1, kNoSpecial);
+    for (int m = 3; m <= n; m++)
+        L.hp_init[m] = m <= 30 ? P.E.hairpin[m]
+                               : P.E.hairpin[30] + (int32_t)lround(P.lxc * log((double)m / 30.0));
+    // row layout of cell tables and candidate segments
+    L.rowoff.assign(N, 0);
+    int64_t acc = 0;
+    for (int a = 0; a < N; a++) {
+        L.rowoff[a] = acc;
+        acc += N - L.off[L.layer[a] + 1];
+    }
+    L.cells = acc;
+    L.coff.assign(N, 0);
+    L.ccap.assign(N, 0);
+    acc = 0;
+    for (int b = 0; b < N; b++) {
+        int lb = L.layer[b];
+        int worst = lb >= 5 ? L.off[lb - 4] : 0;
+        int cap = capacity_override > 0 ? std::min(worst, capacity_override) : worst;
+        L.coff[b] = acc;
+        L.ccap[b] = cap;
+        acc += cap;
+    }
+    L.cand_slots = acc;
+    return SD_OK;
+}
+
+}  // namespace sd

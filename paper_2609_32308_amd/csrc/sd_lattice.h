@@ -1,0 +1,56 @@
+// Host-side lattice model of one design: the codon trie automaton, fixed-point costs, the
+// closed-form gap data, the row layout of the cell tables and the candidate segments.
+#pragma once
+#include <stdint.h>
+
+#include <string>
+#include <vector>
+
+#include "sd_internal.h"
+
+namespace sd {
+
+struct Params {
+    EnergyTables E;
+    double lxc = 0.0;
+    std::vector<std::string> special[3];  // triloop, tetraloop, hexaloop sequences
+    std::vector<int32_t> special_e[3];
+    int32_t maxabs = 0;
+    std::string sha256;
+    std::vector<int32_t> spec_table;  // kSpecSize entries (see sd_internal.h)
+};
+
+struct CodonTable {
+    double w[64];
+};
+
+struct Lattice {
+    int A = 0, n = 0, N = 0, shift = 0;
+    double lambda = 0.0;
+    std::string protein;
+    std::vector<int> layer, off;
+    std::vector<int> out_dst, out_cod;  // [N*4]
+    std::vector<int64_t> out_U;
+    std::vector<double> out_q;          // -ln w on third edges
+    std::vector<int> in_start, in_src, in_lab, in_cod;
+    std::vector<int64_t> in_U;
+    std::vector<int64_t> tail, P;
+    std::vector<int> pfx, hp_init;
+    std::vector<int64_t> rowoff, coff;
+    std::vector<int> ccap;
+    int64_t cells = 0, cand_slots = 0;
+    int64_t mlbase_fx = 0;
+};
+
+// validation and construction; return sd_status values
+int check_protein(const char* p);
+int build_lattice(const char* protein, const CodonTable& T, const Params& P, double lambda,
+                  int capacity_override, Lattice& L, std::string& err);
+
+// closed-form gap on the host (same definition as the kernels)
+int64_t host_gap(const Lattice& L, int a, int b);
+
+std::string sha256_hex(const std::string& data);
+int parse_params(const std::string& text, Params& P, std::string& err);
+
+}  // namespace sd

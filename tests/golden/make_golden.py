@@ -1,0 +1,72 @@
+"""Write the oracle's designs for the larger seeded workloads to tests/golden/*.json.
+
+Calls only oracle/ and sdinputs/ (the seeded generators); nothing here touches the GPU path.
+The GPU parity tests compare against these files at sizes where running the dense oracle
+inside a test would take minutes.
+
+    python tests/golden/make_golden.py config2 config3 [config4]
+"""
+import json
+import os
+import sys
+import time
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+ROOT = os.path.dirname(os.path.dirname(HERE))
+sys.path.insert(0, ROOT)
+
+import oracle as O  # noqa: E402
+import sdinputs as S  # noqa: E402
+
+WORKLOADS = {
+    "config2": [(300, seed, lam) for seed in (1, 2, 3, 4) for lam in (0.0, 4.0)],
+    "config3": [(925, 1, 0.0), (925, 1, 4.0), (1976, 1, 0.0), (1976, 1, 4.0)],
+}
+
+
+def batch_members():
+    lens = S.batch_lengths(256, 50, 1000, seed=7)
+    # member i: protein of length lens[i] from seed 7000 + i, lambda 0 for i < 128 else 4
+    return [(A, 7000 + i, 0.0 if i < 128 else 4.0) for i, A in enumerate(lens)]
+
+
+def run(name, members, nthreads):
+    params = S.default_params_path()
+    P = O.Params(params)
+    w = S.codon_weights(2026)
+    path = os.path.join(HERE, f"{name}.json")
+    out = {"params_sha256": S.sha256_file(params), "codon_seed": 2026, "designs": []}
+    if os.path.exists(path):
+        with open(path) as fh:
+            old = json.load(fh)
+        if old.get("params_sha256") == out["params_sha256"]:
+            out = old
+    done = {(d["A"], d["seed"], d["lambda"]) for d in out["designs"]}
+    for (A, seed, lam) in members:
+        if (A, seed, lam) in done:
+            continue
+        prot = S.protein(A, seed)
+        t = time.time()
+        d = O.design(prot, w, P, lam, nthreads=nthreads)
+        dt = time.time() - t
+        assert d.selfcheck_ok
+        out["designs"].append({
+            "A": A, "seed": seed, "lambda": lam, "protein": prot, "mrna": d.mrna,
+            "structure": d.structure, "energy": d.energy, "objective_fixed": d.objective_fixed,
+            "fixed_shift": d.fixed_shift, "codon_cost": d.codon_cost,
+            "objective_kcal": d.objective_kcal, "n_states": d.n_states, "n_cells": d.n_cells,
+            "n_feasible_direct": d.n_feasible_direct, "n_candidates": d.n_candidates,
+            "visits_sparse": d.visits_sparse, "visits_dense": d.visits_dense,
+            "oracle_seconds": round(dt, 3), "oracle_threads": nthreads,
+        })
+        with open(path + ".tmp", "w") as fh:
+            json.dump(out, fh, indent=1)
+        os.replace(path + ".tmp", path)
+        print(name, A, seed, lam, round(dt, 1), flush=True)
+
+
+if __name__ == "__main__":
+    nthreads = int(os.environ.get("ORACLE_THREADS", "8"))
+    for name in sys.argv[1:]:
+        members = batch_members() if name == "config4" else WORKLOADS[name]
+        run(name, members, nthreads)
