@@ -235,6 +235,17 @@ size_t layout_instance(const Lattice& L, char* base, Inst& I, bool place) {
     I.X = (int64_t*)take(N * 8);
     I.stats = (unsigned long long*)take(4 * 8);
     I.span_appends = (unsigned long long*)take((n + 1) * 8);
+    I.alphaU = (int64_t*)take(4 * N * 8);
+    I.betaU = (int64_t*)take(4 * N * 8);
+    I.LM = (int64_t*)take((size_t)kLMRing * (n + 1) * 2 * 8);
+    I.IDL = (int64_t*)take((size_t)N * kLMRing * 12 * 8);
+    I.JDL = (int64_t*)take((size_t)N * kLMRing * 12 * 8);
+    I.fwd_off = (int*)take(L.fwd_off.size() * 4);
+    I.fwd_meta = (int*)take(L.fwd_meta.size() * 4);
+    I.fwd_cost = (int64_t*)take(L.fwd_cost.size() * 8);
+    I.bwd_off = (int*)take(L.bwd_off.size() * 4);
+    I.bwd_meta = (int*)take(L.bwd_meta.size() * 4);
+    I.bwd_cost = (int64_t*)take(L.bwd_cost.size() * 8);
     I.V = (int64_t*)take(cells * 6 * 8);
     I.Bt = (int64_t*)take(cells * 8);
     I.S1 = (int64_t*)take(cells * 8);
@@ -272,6 +283,14 @@ hipError_t upload_instance(const Lattice& L, const Inst& I, hipStream_t st) {
         {(void*)I.rowoff, L.rowoff.data(), L.rowoff.size() * 8},
         {(void*)I.coff, L.coff.data(), L.coff.size() * 8},
         {(void*)I.ccap, L.ccap.data(), L.ccap.size() * 4},
+        {(void*)I.alphaU, L.alphaU.data(), L.alphaU.size() * 8},
+        {(void*)I.betaU, L.betaU.data(), L.betaU.size() * 8},
+        {(void*)I.fwd_off, L.fwd_off.data(), L.fwd_off.size() * 4},
+        {(void*)I.fwd_meta, L.fwd_meta.data(), L.fwd_meta.size() * 4},
+        {(void*)I.fwd_cost, L.fwd_cost.data(), L.fwd_cost.size() * 8},
+        {(void*)I.bwd_off, L.bwd_off.data(), L.bwd_off.size() * 4},
+        {(void*)I.bwd_meta, L.bwd_meta.data(), L.bwd_meta.size() * 4},
+        {(void*)I.bwd_cost, L.bwd_cost.data(), L.bwd_cost.size() * 8},
     };
     for (auto& c : cps) {
         if (!c.bytes) continue;

@@ -61,7 +61,19 @@ struct Inst {
     int64_t *X;
     unsigned long long *stats;  // [0] visits [1] appends [2] overflow flag [3] feasible B
     unsigned long long *span_appends;  // per span appended candidates (n+1), may be null
+    // separable interior-loop data (see the two-loop notes in sd_kernels.hip)
+    const int64_t *alphaU;  // [N*4] U(d -x-> d2) + tail(d2), INF if no edge
+    const int64_t *betaU;   // [N*4] min U over in-edges of c labelled x, INF if none
+    int64_t *LM;            // [kLMRing][n+1][2] per layer-pair inner minima, ring over spans
+    int64_t *IDL;           // [N][kLMRing][3][4] inner minima per left inner state, class, x_{k-1}
+    int64_t *JDL;           // [N][kLMRing][3][4] inner minima per right inner state, class, x_{l+1}
+    // label paths of 1..4 edges: forward from a state / backward into a state (CSR by state*4+l-1)
+    // meta = other_end << 4 | first_label << 2 | last_label, cost = sum of edge costs
+    const int *fwd_off, *fwd_meta, *bwd_off, *bwd_meta;
+    const int64_t *fwd_cost, *bwd_cost;
     int retain_all;
 };
+
+constexpr int kLMRing = 64;  // > 32 spans of two-loop reach
 
 }  // namespace sd

@@ -1,13 +1,26 @@
 // gfx950 kernels of the span wavefront (Sec. 5, Algorithm 1, re-designed for the GPU).
 //
-// One launch per span length g.  A wavefront (64 lanes) owns one layer pair (p, q = p + g) and
+// One step per span length g.  A wavefront (64 lanes) owns one layer pair (p, q = p + g) and
 // therefore every cell (a, b) with a in layer p and b in layer q; it is the only writer of the
 // candidate segments C_b of its right endpoints in this step (the endpoint-ownership rule of
 // Sec. 5), so appends need no atomics and land in start-state order.  Inside a cell the lanes
-// split the closed-value enumeration (hairpin paths / two-loop (l1,l2) pairs / multiloop
-// in-edges) and the candidate-prefix scan of eq. (7), then reduce with wavefront min shuffles.
-// An extra workgroup per launch fills the external column one layer behind the wavefront.
+// split the closed-value enumeration and the candidate-prefix scan of eq. (7), then reduce with
+// wavefront min shuffles.  One extra workgroup fills the external column one layer behind.
+//
+// Two-loop closure (stack / bulge / interior, l1 + l2 <= 30).  For a generic interior loop the
+// energy is init(l1+l2) + asymmetry + mm[t][x_{i+1}][x_{j-1}] + mm[t'][x_{l+1}][x_{k-1}]: the
+// outer mismatch couples only the two bases next to the closing pair and the inner mismatch only
+// the two bases next to the inner pair.  When each unpaired segment crosses a codon boundary the
+// trie's minimum segment cost splits the same way (first edge + rest of its codon, whole codons,
+// last edge), so the whole term separates into
+//     OUT(a1, b1, t)  [closing-pair side]  +  IN(c, d)  [inner-pair side]  +  layer constants.
+// IN depends on the inner cell only, so its minimum over the states of a layer pair, LM, is
+// stored once per layer pair (ring over the last 64 spans) when that pair is finished; a later
+// cell then needs one lookup per (l1, l2) instead of an enumeration.  Every other (l1, l2)
+// (bulges, 1xn, 1x1/1x2/2x2 tables, segments inside one codon) is enumerated explicitly.
 #include <hip/hip_runtime.h>
+
+#include <string.h>
 
 #include "sd_internal.h"
 
@@ -15,14 +28,56 @@ namespace sd {
 
 __constant__ int kTX[6] = {0, 1, 2, 2, 3, 3};  // 5' base of AU CG GC GU UA UG
 __constant__ int kTY[6] = {3, 2, 1, 3, 0, 2};  // 3' base
+__constant__ int kRev[6] = {4, 2, 1, 5, 0, 3}; // type of the reversed pair
 __constant__ int kPairType[16] = {-1, -1, -1, 0, -1, -1, 1, -1, -1, 2, -1, 3, 4, -1, 5, -1};
 // (l1, l2) pairs in canonical order: l1 ascending, then l2 ascending, l1 + l2 <= 30
 __constant__ unsigned char kL1[kNumPairs];
 __constant__ unsigned char kL2[kNumPairs];
+// Two-loop (l1, l2) pairs by category for each phase (p mod 3, q mod 3), each list sorted by
+// l1 + l2 so that the pairs allowed at span g (l1 + l2 <= g - 7) form a prefix.  Entries:
+// l1 | l2 << 5 | side << 10 (side 1: left side separable).  Counts: kCnt[list][phase][cap].
+enum { kListBulge = 0, kListOne = 1, kListLab = 2, kListFast = 3 };
+__constant__ unsigned short kPairList[4][9][kNumPairs];
+__constant__ unsigned short kPairCnt[4][9][31];
+
+// Loop tables staged in LDS (the 1x2 and 2x2 full-loop tables stay in global memory; they are
+// read for 3 of the 496 (l1, l2) pairs only).
+struct SmallE {
+    int32_t stack[6][6];
+    int32_t mmH[6][4][4], mmI[6][4][4], mm1n[6][4][4], mm23[6][4][4];
+    int32_t int11[6][6][4][4];
+    int32_t hairpin[31], bulge[31], interior[31];
+    int32_t ml_closing, ml_intern, ml_base, terminal_au, ninio, ninio_max;
+};
+
+__device__ void stage_tables(SmallE& S, const EnergyTables* __restrict__ E) {
+    const int t = threadIdx.x, nt = blockDim.x;
+    for (int i = t; i < 36; i += nt) (&S.stack[0][0])[i] = (&E->stack[0][0])[i];
+    for (int i = t; i < 96; i += nt) {
+        (&S.mmH[0][0][0])[i] = (&E->mmH[0][0][0])[i];
+        (&S.mmI[0][0][0])[i] = (&E->mmI[0][0][0])[i];
+        (&S.mm1n[0][0][0])[i] = (&E->mm1n[0][0][0])[i];
+        (&S.mm23[0][0][0])[i] = (&E->mm23[0][0][0])[i];
+    }
+    for (int i = t; i < 576; i += nt) (&S.int11[0][0][0][0])[i] = (&E->int11[0][0][0][0])[i];
+    for (int i = t; i < 31; i += nt) {
+        S.hairpin[i] = E->hairpin[i];
+        S.bulge[i] = E->bulge[i];
+        S.interior[i] = E->interior[i];
+    }
+    if (t == 0) {
+        S.ml_closing = E->ml_closing;
+        S.ml_intern = E->ml_intern;
+        S.ml_base = E->ml_base;
+        S.terminal_au = E->terminal_au;
+        S.ninio = E->ninio;
+        S.ninio_max = E->ninio_max;
+    }
+}
 
 __device__ __forceinline__ int ptype(int x, int y) { return kPairType[x * 4 + y]; }
-__device__ __forceinline__ int32_t au_pen(const EnergyTables* E, int t) {
-    return (t == 1 || t == 2) ? 0 : E->terminal_au;
+__device__ __forceinline__ int32_t au_pen(const SmallE& S, int t) {
+    return (t == 1 || t == 2) ? 0 : S.terminal_au;
 }
 __device__ __forceinline__ int64_t mn(int64_t a, int64_t b) { return a < b ? a : b; }
 __device__ __forceinline__ int64_t fx(int32_t e, int s) { return (int64_t)e * ((int64_t)1 << s); }
@@ -55,218 +110,439 @@ __device__ __forceinline__ int64_t gap(const Inst& I, int a, int b) {
     return I.tail[a] + I.P[kb] - I.P[ka + 1];
 }
 
-__device__ int32_t two_loop_e(const EnergyTables* __restrict__ E, int t, int tr, int l1, int l2,
-                              int xi1, int xk1, int xl1, int xj1) {
-    if (l1 == 0 && l2 == 0) return E->stack[t][tr];
-    if (l1 == 0 || l2 == 0) {
-        int l = l1 + l2;
-        if (l == 1) return E->bulge[1] + E->stack[t][tr];
-        return E->bulge[l] + au_pen(E, t) + au_pen(E, tr);
-    }
-    if (l1 == 1 && l2 == 1) return E->int11[t][tr][xi1][xj1];
+__device__ __forceinline__ int32_t bulge_e(const SmallE& S, int t, int tr, int l) {
+    return l == 1 ? S.bulge[1] + S.stack[t][tr] : S.bulge[l] + au_pen(S, t) + au_pen(S, tr);
+}
+
+__device__ __forceinline__ int32_t interior_base(const SmallE& S, int l1, int l2) {
+    int d = l1 > l2 ? l1 - l2 : l2 - l1;
+    int32_t asym = S.ninio * d;
+    return S.interior[l1 + l2] + (asym < S.ninio_max ? asym : S.ninio_max);
+}
+
+// interior loop with l1, l2 >= 1
+__device__ int32_t interior_e(const SmallE& S, const EnergyTables* __restrict__ E, int t, int tr,
+                              int l1, int l2, int xi1, int xk1, int xl1, int xj1) {
+    if (l1 == 1 && l2 == 1) return S.int11[t][tr][xi1][xj1];
     if (l1 == 1 && l2 == 2) return E->int21[t][tr][xi1][xl1][xj1];
     if (l1 == 2 && l2 == 1) return E->int21[tr][t][xl1][xi1][xk1];
     if (l1 == 2 && l2 == 2) return E->int22[t][tr][xi1][xk1][xl1][xj1];
-    int d = l1 > l2 ? l1 - l2 : l2 - l1;
-    int32_t asym = E->ninio * d;
-    asym = asym < E->ninio_max ? asym : E->ninio_max;
-    int32_t e = E->interior[l1 + l2] + asym;
-    if (l1 == 1 || l2 == 1) return e + E->mm1n[t][xi1][xj1] + E->mm1n[tr][xl1][xk1];
-    if (l1 + l2 == 5 && (l1 == 2 || l1 == 3)) return e + E->mm23[t][xi1][xj1] + E->mm23[tr][xl1][xk1];
-    return e + E->mmI[t][xi1][xj1] + E->mmI[tr][xl1][xk1];
+    int32_t e = interior_base(S, l1, l2);
+    if (l1 == 1 || l2 == 1) return e + S.mm1n[t][xi1][xj1] + S.mm1n[tr][xl1][xk1];
+    if (l1 + l2 == 5 && (l1 == 2 || l1 == 3)) return e + S.mm23[t][xi1][xj1] + S.mm23[tr][xl1][xk1];
+    return e + S.mmI[t][xi1][xj1] + S.mmI[tr][xl1][xk1];
+}
+
+// (l1, l2) handled by the separable layer-pair tables: both segments of length >= 2 crossing a
+// codon boundary, generic or 2x3 interior class.
+__device__ __forceinline__ bool fast_pair(int p, int q, int l1, int l2) {
+    if (l1 < 2 || l2 < 2 || (l1 == 2 && l2 == 2)) return false;
+    if ((q - 1 - l2) - (p + 1 + l1) < 5) return false;
+    return (p + 2) / 3 != (p + l1) / 3 && (q - l2) / 3 != (q - 2) / 3;
+}
+__device__ __forceinline__ int pair_class(int l1, int l2) {  // 1: 2x3 mismatch table, 0: generic
+    return (l1 + l2 == 5 && (l1 == 2 || l1 == 3)) ? 1 : 0;
 }
 
 // ---- hairpin closure ------------------------------------------------------------------------
-// Sizes 3, 4, 6 may match a listed special loop, so each lane walks the paths whose bases at
-// positions 1..3 equal its lane id in base 4; other sizes decompose into the two outer edges on
-// each side plus a minimum-cost unpaired interior.
-__device__ int64_t hairpin_lane(const Inst& I, const EnergyTables* __restrict__ E,
-                                const int32_t* __restrict__ spec, int a, int b, int t, int a1,
-                                int64_t Ua, int lane) {
+__device__ int64_t hairpin_lane(const Inst& I, const SmallE& S, const int32_t* __restrict__ spec,
+                                int a, int b, int t, int a1, int64_t Ua, int lane) {
     const int la = I.layer[a], g = I.layer[b] - la, m = g - 2, s = I.shift;
     const int x = kTX[t], y = kTY[t];
     int64_t best = kINF;
     if (m == 3 || m == 4 || m == 6) {
-        int l1 = (lane >> 4) & 3, l2 = (lane >> 2) & 3, l3 = lane & 3;
-        int st = a1;
+        // each lane walks the paths whose bases at positions 1..3 spell its lane id in base 4
+        const int l1 = (lane >> 4) & 3, l2 = (lane >> 2) & 3, l3 = lane & 3;
+        int st = a1, key = x;
         int64_t cost = Ua;
-        int key = x;
-        int labs[3] = {l1, l2, l3};
+        const int labs[3] = {l1, l2, l3};
         for (int i = 0; i < 3; i++) {
-            int e = st * 4 + labs[i];
-            int d = I.out_dst[e];
+            const int e = st * 4 + labs[i], d = I.out_dst[e];
             if (d < 0) return kINF;
             cost += I.out_U[e];
             key = key * 4 + labs[i];
             st = d;
         }
-        // remaining free positions: g - 5 (0, 1 or 3), then the last base y into b
-        const int nfree = g - 5;
+        const int nfree = g - 5;  // 0, 1 or 3 free positions before the final base y
         const int combos = 1 << (2 * nfree);
         for (int k = 0; k < combos; k++) {
-            int st2 = st, key2 = key, ok = 1, lastfree = l3;
+            int st2 = st, key2 = key, ok = 1, last = l3;
             int64_t c2 = cost;
             for (int i = nfree - 1; i >= 0; i--) {
-                int lab = (k >> (2 * i)) & 3;
-                int e = st2 * 4 + lab;
-                int d = I.out_dst[e];
+                const int lab = (k >> (2 * i)) & 3, e = st2 * 4 + lab, d = I.out_dst[e];
                 if (d < 0) { ok = 0; break; }
                 c2 += I.out_U[e];
                 key2 = key2 * 4 + lab;
                 st2 = d;
-                lastfree = lab;
+                last = lab;
             }
-            if (!ok) {
-                // skip the whole subtree below the failing position would be faster; sizes are tiny
-                continue;
-            }
-            int e = st2 * 4 + y;
+            if (!ok) continue;
+            const int e = st2 * 4 + y;
             if (I.out_dst[e] != b) continue;
             c2 += I.out_U[e];
             key2 = key2 * 4 + y;
-            int off = m == 3 ? kSpecOff5 : m == 4 ? kSpecOff6 : kSpecOff8;
+            const int off = m == 3 ? kSpecOff5 : m == 4 ? kSpecOff6 : kSpecOff8;
             int32_t en = spec[off + key2];
-            if (en == kNoSpecial) {
-                en = I.hp_init[m] + (m == 3 ? au_pen(E, t) : E->mmH[t][l1][lastfree]);
-            }
+            if (en == kNoSpecial) en = I.hp_init[m] + (m == 3 ? au_pen(S, t) : S.mmH[t][l1][last]);
             best = mn(best, c2 + fx(en, s));
         }
         return best;
     }
-    // generic: a -x-> a1 -x2-> a2 ~~> b2 -z-> b1 -y-> b
-    const int ib0 = I.in_start[b], ib1 = I.in_start[b + 1];
-    const int nb = ib1 - ib0;
+    // generic size: a -x-> a1 -x2-> a2 ~~> b2 -z-> b1 -y-> b
+    const int ib0 = I.in_start[b], nb = I.in_start[b + 1] - ib0;
     for (int k = lane; k < 4 * 8 * 8; k += 64) {
-        int x2 = k & 3, i1 = (k >> 2) & 7, i2 = k >> 5;
+        const int x2 = k & 3, i1 = (k >> 2) & 7, i2 = k >> 5;
         if (i1 >= nb) continue;
-        int eb = ib0 + i1;
+        const int eb = ib0 + i1;
         if (I.in_lab[eb] != y) continue;
-        int b1 = I.in_src[eb];
-        int j0 = I.in_start[b1];
+        const int b1 = I.in_src[eb], j0 = I.in_start[b1];
         if (i2 >= I.in_start[b1 + 1] - j0) continue;
-        int eb2 = j0 + i2;
-        int e1 = a1 * 4 + x2;
-        int a2 = I.out_dst[e1];
+        const int eb2 = j0 + i2, e1 = a1 * 4 + x2, a2 = I.out_dst[e1];
         if (a2 < 0) continue;
-        int b2 = I.in_src[eb2];
-        int64_t gg = gap(I, a2, b2);
+        const int64_t gg = gap(I, a2, I.in_src[eb2]);
         if (gg >= kINF) continue;
-        int32_t en = I.hp_init[m] + E->mmH[t][x2][I.in_lab[eb2]];
+        const int32_t en = I.hp_init[m] + S.mmH[t][x2][I.in_lab[eb2]];
         best = mn(best, Ua + I.out_U[e1] + gg + I.in_U[eb2] + I.in_U[eb] + fx(en, s));
     }
     return best;
 }
 
-// ---- two-loop closure: stack, bulge, interior with l1 + l2 <= 30 -------------------------------
-struct Seg {
-    int xa, xb;
-    int64_t cost;
-};
-constexpr int kMaxSegs = 24;  // 4 first bases x at most 6 in-edges (codon family size)
-
-// unpaired segment u ~> v with l bases (l >= 1); boundary labels (first, last)
-__device__ __forceinline__ int segs(const Inst& I, int u, int v, int l, Seg* out) {
-    int k = 0;
-    if (l == 1) {
-        for (int x = 0; x < 4; x++) {
-            int e = u * 4 + x;
-            if (I.out_dst[e] == v && k < kMaxSegs) out[k++] = Seg{x, x, I.out_U[e]};
-        }
-        return k;
-    }
-    const int j0 = I.in_start[v], j1 = I.in_start[v + 1];
-    for (int x = 0; x < 4; x++) {
-        int e = u * 4 + x;
-        int u2 = I.out_dst[e];
-        if (u2 < 0) continue;
-        for (int j = j0; j < j1; j++) {
-            int64_t gg = gap(I, u2, I.in_src[j]);
-            if (gg >= kINF || k >= kMaxSegs) continue;
-            out[k++] = Seg{x, I.in_lab[j], I.out_U[e] + gg + I.in_U[j]};
-        }
-    }
-    return k;
-}
-
-__device__ int64_t twoloop_lane(const Inst& I, const EnergyTables* __restrict__ E, int a, int b,
-                                int t, int a1, int64_t Ua, int lane) {
-    const int la = I.layer[a], lb = I.layer[b], s = I.shift, y = kTY[t];
-    const int ib0 = I.in_start[b], ib1 = I.in_start[b + 1];
+// ---- two-loop closure: bulges and stacks ----------------------------------------------------------
+// No boundary bases enter a bulge or stack energy, so each unpaired side costs its minimum
+// (the gap) and the loop is evaluated per inner cell and inner type.
+__device__ int64_t bulge_pair(const Inst& I, const SmallE& S, int t, int a1, int b1, int64_t Uab,
+                              int l1, int l2, int cl, int dl) {
+    const int s = I.shift, l = l1 + l2;
     int64_t best = kINF;
-    Seg L[kMaxSegs], R[kMaxSegs];
-    for (int pi = lane; pi < kNumPairs; pi += 64) {
-        const int l1 = kL1[pi], l2 = kL2[pi];
-        const int cl = la + 1 + l1, dl = lb - 1 - l2;
-        if (dl - cl < 5) continue;
-        for (int eb = ib0; eb < ib1; eb++) {
-            if (I.in_lab[eb] != y) continue;
-            const int b1 = I.in_src[eb];
-            const int64_t Uab = Ua + I.in_U[eb];
-            for (int c = I.off[cl]; c < I.off[cl + 1]; c++) {
-                int nl;
-                if (l1 == 0) {
-                    if (c != a1) continue;
-                    nl = 1;
-                    L[0] = Seg{0, 0, 0};
-                } else {
-                    nl = segs(I, a1, c, l1, L);
-                    if (!nl) continue;
-                }
-                const int64_t crow = I.rowoff[c] - I.off[cl + 1];
-                for (int d = I.off[dl]; d < I.off[dl + 1]; d++) {
-                    const int64_t* vcd = I.V + (crow + d) * 6;
-                    int nr = -1;
-                    for (int tp = 0; tp < 6; tp++) {
-                        const int64_t vin = vcd[tp];
-                        if (vin >= kINF) continue;
-                        if (nr < 0) {
-                            if (l2 == 0) {
-                                nr = d == b1 ? 1 : 0;
-                                R[0] = Seg{0, 0, 0};
-                            } else {
-                                nr = segs(I, d, b1, l2, R);
-                            }
-                        }
-                        if (!nr) break;
-                        const int tr = ptype(kTY[tp], kTX[tp]);
-                        for (int i = 0; i < nl; i++)
-                            for (int j = 0; j < nr; j++) {
-                                int32_t e2 = two_loop_e(E, t, tr, l1, l2, L[i].xa, L[i].xb, R[j].xa, R[j].xb);
-                                best = mn(best, Uab + L[i].cost + vin + R[j].cost + fx(e2, s));
-                            }
-                    }
-                }
+    for (int c = (l1 == 0 ? a1 : I.off[cl]); c < (l1 == 0 ? a1 + 1 : I.off[cl + 1]); c++) {
+        const int64_t gl = l1 == 0 ? 0 : gap(I, a1, c);
+        if (gl >= kINF) continue;
+        const int64_t crow = I.rowoff[c] - I.off[cl + 1];
+        for (int d = (l2 == 0 ? b1 : I.off[dl]); d < (l2 == 0 ? b1 + 1 : I.off[dl + 1]); d++) {
+            const int64_t gr = l2 == 0 ? 0 : gap(I, d, b1);
+            if (gr >= kINF) continue;
+            const int64_t* v = I.V + (crow + d) * 6;
+            for (int tp = 0; tp < 6; tp++) {
+                const int64_t vin = v[tp];
+                if (vin >= kINF) continue;
+                const int32_t e2 = l == 0 ? S.stack[t][kRev[tp]] : bulge_e(S, t, kRev[tp], l);
+                best = mn(best, Uab + gl + vin + gr + fx(e2, s));
             }
         }
     }
     return best;
 }
 
-// ---- multiloop closure ------------------------------------------------------------------------
-__device__ int64_t multiloop_lane(const Inst& I, const EnergyTables* __restrict__ E, int a, int b,
-                                  int t, int a1, int64_t Ua, int lane) {
-    const int y = kTY[t];
-    const int ib0 = I.in_start[b], ib1 = I.in_start[b + 1];
-    const int32_t mlc = E->ml_closing + E->ml_intern + au_pen(E, t);
+// ---- two-loop closure: both segments explicit (each has 1..4 bases inside one codon) -------------
+// Left segments are the label paths of l1 edges out of a1, right segments the paths of l2 edges
+// into b1; lanes split the (left path, right path) combinations.
+__device__ int64_t labelled_pairs(const Inst& I, const SmallE& S, const EnergyTables* __restrict__ E,
+                                  int t, int a1, int b1, int64_t Uab, int ph, int cap, int lane) {
+    const int s = I.shift;
     int64_t best = kINF;
-    for (int eb = ib0 + lane; eb < ib1; eb += 64) {
-        if (I.in_lab[eb] != y) continue;
-        int b1 = I.in_src[eb];
-        if (I.layer[b1] - I.layer[a1] < 10) continue;
-        int64_t s2 = I.S2[cell_of(I, a1, b1)];
-        best = mn(best, s2 + Ua + I.in_U[eb] + fx(mlc, I.shift));  // s2 may be INF: normalised later
+    const int npairs = kPairCnt[kListLab][ph][cap];
+    for (int k = 0; k < npairs; k++) {
+        const int code = kPairList[kListLab][ph][k], l1 = code & 31, l2 = (code >> 5) & 31;
+        const int f0 = I.fwd_off[a1 * 4 + l1 - 1], nl = I.fwd_off[a1 * 4 + l1] - f0;
+        const int r0 = I.bwd_off[b1 * 4 + l2 - 1], nr = I.bwd_off[b1 * 4 + l2] - r0;
+        for (int idx = lane; idx < nl * nr; idx += 64) {
+            const int i = idx / nr, j = idx - i * nr;
+            const int fm = I.fwd_meta[f0 + i], bm = I.bwd_meta[r0 + j];
+            const int c = fm >> 4, xi = (fm >> 2) & 3, xk = fm & 3;
+            const int d = bm >> 4, xl = (bm >> 2) & 3, xj = bm & 3;
+            const int64_t base = Uab + I.fwd_cost[f0 + i] + I.bwd_cost[r0 + j];
+            const int64_t* v = I.V + (I.rowoff[c] + (d - I.off[I.layer[c] + 1])) * 6;
+            for (int tp = 0; tp < 6; tp++) {
+                const int64_t vin = v[tp];
+                if (vin >= kINF) continue;
+                const int32_t e2 = interior_e(S, E, t, kRev[tp], l1, l2, xi, xk, xl, xj);
+                best = mn(best, base + vin + fx(e2, s));
+            }
+        }
     }
     return best;
 }
 
+// ---- one-sided separable two-loops --------------------------------------------------------------
+// A side is separable when its segment has >= 2 bases and its two end edges lie in different
+// codons (then its minimum cost is first-edge part + last-edge part + whole codons).  With the
+// right side separable and the left side explicit (one edge, or both ends inside one codon):
+//   value = U_ab + base + PR + left cost + OB_X(b1, t, x_{i+1}) + IDL_X(c, span, x_{k-1})
+// and symmetrically with the left side separable:
+//   value = U_ab + base + PL + right cost + OA_X(a1, t, x_{j-1}) + JDL_X(d, span, x_{l+1}).
+__device__ __forceinline__ bool sep_left(int p, int l1) { return l1 >= 2 && (p + 2) / 3 != (p + l1) / 3; }
+__device__ __forceinline__ bool sep_right(int q, int l2) { return l2 >= 2 && (q - l2) / 3 != (q - 2) / 3; }
+// mismatch class of an interior loop: 0 generic, 1 2x3, 2 1xn
+__device__ __forceinline__ int mm_class(int l1, int l2) {
+    return (l1 == 1 || l2 == 1) ? 2 : pair_class(l1, l2);
+}
+__device__ __forceinline__ int32_t mmx(const SmallE& S, int X, int t, int i, int j) {
+    return X == 0 ? S.mmI[t][i][j] : X == 1 ? S.mm23[t][i][j] : S.mm1n[t][i][j];
+}
+__device__ __forceinline__ int64_t ring_idx(int state, int span, int X, int lab) {
+    return (((int64_t)state * kLMRing + (span & (kLMRing - 1))) * 3 + X) * 4 + lab;
+}
+__device__ __forceinline__ int64_t PLt(const Inst& I, int p, int l1) { return I.P[(p + l1) / 3] - I.P[(p + 2) / 3 + 1]; }
+__device__ __forceinline__ int64_t PRt(const Inst& I, int q, int l2) { return I.P[(q - 2) / 3] - I.P[(q - l2) / 3 + 1]; }
+
+// Outer minima for one closing edge, computed once into LDS (ob: 12 values, oa: 12 values):
+//   ob[X][x_{i+1}] = min_{x_{j-1}} beta(b1, x_{j-1}) + mm_X[t][x_{i+1}][x_{j-1}]
+//   oa[X][x_{j-1}] = min_{x_{i+1}} alpha(a1, x_{i+1}) + mm_X[t][x_{i+1}][x_{j-1}]
+__device__ __forceinline__ void outer_minima(const Inst& I, const SmallE& S, int a1, int b1, int t,
+                                             int lane, int64_t* obuf) {
+    if (lane < 24) {
+        const int X = (lane >> 2) % 3, x = lane & 3;
+        int64_t r = kINF;
+        for (int o = 0; o < 4; o++) {
+            if (lane < 12) {
+                const int64_t be = I.betaU[b1 * 4 + o];
+                if (be < kINF) r = mn(r, be + fx(mmx(S, X, t, x, o), I.shift));
+            } else {
+                const int64_t al = I.alphaU[a1 * 4 + o];
+                if (al < kINF) r = mn(r, al + fx(mmx(S, X, t, o, x), I.shift));
+            }
+        }
+        obuf[lane] = r;
+    }
+    __builtin_amdgcn_wave_barrier();
+    __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
+}
+
+// left segment explicit (paths of l1 edges out of a1), right segment separable
+__device__ int64_t rsep_pair(const Inst& I, const SmallE& S, int a1, int64_t Uab, int l1, int l2,
+                             int cl, int dl, int q, const int64_t* obuf) {
+    const int X = mm_class(l1, l2), g2 = dl - cl;
+    const int64_t base = Uab + fx(interior_base(S, l1, l2), I.shift) + PRt(I, q, l2);
+    const int f0 = I.fwd_off[a1 * 4 + l1 - 1], f1 = I.fwd_off[a1 * 4 + l1];
+    int64_t best = kINF;
+    for (int i = f0; i < f1; i++) {
+        const int fm = I.fwd_meta[i], c = fm >> 4, xi = (fm >> 2) & 3, xk = fm & 3;
+        const int64_t ob = obuf[X * 4 + xi], idl = I.IDL[ring_idx(c, g2, X, xk)];
+        if (ob < kINF && idl < kINF) best = mn(best, base + I.fwd_cost[i] + ob + idl);
+    }
+    return best;
+}
+
+// left segment separable, right segment explicit (paths of l2 edges into b1)
+__device__ int64_t lsep_pair(const Inst& I, const SmallE& S, int b1, int64_t Uab, int l1, int l2,
+                             int cl, int dl, int p, const int64_t* obuf) {
+    const int X = mm_class(l1, l2), g2 = dl - cl;
+    const int64_t base = Uab + fx(interior_base(S, l1, l2), I.shift) + PLt(I, p, l1);
+    const int r0 = I.bwd_off[b1 * 4 + l2 - 1], r1 = I.bwd_off[b1 * 4 + l2];
+    int64_t best = kINF;
+    for (int j = r0; j < r1; j++) {
+        const int bm = I.bwd_meta[j], d = bm >> 4, xl = (bm >> 2) & 3, xj = bm & 3;
+        const int64_t oa = obuf[12 + X * 4 + xj], jdl = I.JDL[ring_idx(d, g2, X, xl)];
+        if (oa < kINF && jdl < kINF) best = mn(best, base + I.bwd_cost[j] + oa + jdl);
+    }
+    return best;
+}
+
+// ---- the work of one layer pair (p, q) in span step g ----------------------------------------
+struct GroupCounters {
+    unsigned long long visits, appends, feasible;
+};
+
+constexpr int kMaxWidth = 4;  // states per layer supported by the per-wave cell buffer
+
+__device__ GroupCounters span_group(const Inst& I, const SmallE& S, const EnergyTables* __restrict__ E,
+                                    const int32_t* __restrict__ spec, int p, int q, int lane,
+                                    int64_t (*vbuf)[6], int64_t* obuf) {
+    const int g = q - p, s = I.shift, n = I.n;
+    GroupCounters ctr{0, 0, 0};
+    // separable interior minima of this layer pair (both segments separable), per class
+    int64_t mini0 = kINF, mini1 = kINF;
+    if (g >= 12) {
+        const int ph = (p % 3) * 3 + (q % 3), cap = min(g - 7, kMaxLoop);
+        for (int k = lane; k < kPairCnt[kListFast][ph][cap]; k += 64) {
+            const int code = kPairList[kListFast][ph][k], l1 = code & 31, l2 = (code >> 5) & 31;
+            const int cl = p + 1 + l1, dl = q - 1 - l2, X = pair_class(l1, l2);
+            const int64_t lm = I.LM[((size_t)((dl - cl) & (kLMRing - 1)) * (n + 1) + cl) * 2 + X];
+            if (lm >= kINF) continue;
+            const int64_t v = lm + fx(interior_base(S, l1, l2), s) + PLt(I, p, l1) + PRt(I, q, l2);
+            if (X) mini1 = mn(mini1, v);
+            else mini0 = mn(mini0, v);
+        }
+        mini0 = wave_min(mini0);
+        mini1 = wave_min(mini1);
+    }
+    const int a_lo = I.off[p], a_hi = I.off[p + 1], b_lo = I.off[q], b_hi = I.off[q + 1];
+    for (int b = b_lo; b < b_hi; b++) {
+        const int committed = I.ccnt[b];  // entries of spans < g only (this wave owns C_b now)
+        const int64_t cbase = I.coff[b];
+        const int ib0 = I.in_start[b], ib1 = I.in_start[b + 1];
+        int added = 0;
+        for (int a = a_lo; a < a_hi; a++) {
+            const int64_t cell = I.rowoff[a] + (b - I.off[p + 1]);
+            // phase 1: typed closed values and the scalar branch (eq. 2)
+            int64_t Bv = kINF;
+#pragma nounroll
+            for (int t = 0; t < 6; t++) {
+                int64_t v = kINF;
+                const int a1 = g >= 5 ? I.out_dst[a * 4 + kTX[t]] : -1;
+                if (a1 >= 0) {
+                    const int64_t Ua = I.out_U[a * 4 + kTX[t]];
+                    const int y = kTY[t];
+                    v = hairpin_lane(I, S, spec, a, b, t, a1, Ua, lane);
+                    if (g >= 7) {
+                        const int ph = (p % 3) * 3 + (q % 3), cap = min(g - 7, kMaxLoop);
+                        for (int eb = ib0; eb < ib1; eb++) {
+                            if (I.in_lab[eb] != y) continue;
+                            const int b1 = I.in_src[eb];
+                            const int64_t Uab = Ua + I.in_U[eb];
+                            outer_minima(I, S, a1, b1, t, lane, obuf);
+                            for (int k = lane; k < kPairCnt[kListBulge][0][cap]; k += 64) {
+                                const int code = kPairList[kListBulge][0][k], l1 = code & 31, l2 = (code >> 5) & 31;
+                                v = mn(v, bulge_pair(I, S, t, a1, b1, Uab, l1, l2, p + 1 + l1, q - 1 - l2));
+                            }
+                            for (int k = lane; k < kPairCnt[kListOne][ph][cap]; k += 64) {
+                                const int code = kPairList[kListOne][ph][k], l1 = code & 31, l2 = (code >> 5) & 31;
+                                const int cl = p + 1 + l1, dl = q - 1 - l2;
+                                v = mn(v, (code >> 10) ? lsep_pair(I, S, b1, Uab, l1, l2, cl, dl, p, obuf)
+                                                       : rsep_pair(I, S, a1, Uab, l1, l2, cl, dl, q, obuf));
+                            }
+                            v = mn(v, labelled_pairs(I, S, E, t, a1, b1, Uab, ph, cap, lane));
+                        }
+                    }
+                    if (g >= 12) {
+                        // both segments separable: OUT(a1, b1, t) + layer-pair minimum
+                        const int nbx = (ib1 - ib0) * 32;
+                        for (int k = lane; k < nbx; k += 64) {
+                            const int eb = ib0 + (k >> 5), X = (k >> 4) & 1, xi = (k >> 2) & 3, xj = k & 3;
+                            if (I.in_lab[eb] != y) continue;
+                            const int64_t mini = X ? mini1 : mini0;
+                            const int64_t al = I.alphaU[a1 * 4 + xi], be = I.betaU[I.in_src[eb] * 4 + xj];
+                            if (mini >= kINF || al >= kINF || be >= kINF) continue;
+                            v = mn(v, Ua + I.in_U[eb] + al + be + fx(mmx(S, X, t, xi, xj), s) + mini);
+                        }
+                        // multiloop closure (ML_closing + ML_intern + AU) + S2 of the interior
+                        const int32_t mlc = S.ml_closing + S.ml_intern + au_pen(S, t);
+                        for (int eb = ib0 + lane; eb < ib1; eb += 64) {
+                            if (I.in_lab[eb] != y) continue;
+                            const int b1 = I.in_src[eb];
+                            if (I.layer[b1] - I.layer[a1] < 10) continue;
+                            v = mn(v, I.S2[cell_of(I, a1, b1)] + Ua + I.in_U[eb] + fx(mlc, s));
+                        }
+                    }
+                    v = norm_inf(wave_min(v));
+                }
+                if (lane == 0) {
+                    I.V[cell * 6 + t] = v;
+                    vbuf[(a - a_lo) * kMaxWidth + (b - b_lo)][t] = v;
+                }
+                if (v < kINF) Bv = mn(Bv, v + fx(S.ml_intern + au_pen(S, t), s));
+            }
+            // phase 2: S2 (eq. 7), P_S, S1 and the strict retention test (eq. 6)
+            int64_t s2 = kINF;
+            for (int eb = ib0 + lane; eb < ib1; eb += 64) {
+                const int bp = I.in_src[eb];
+                if (I.layer[bp] > p) s2 = mn(s2, I.S2[cell_of(I, a, bp)] + I.in_U[eb] + I.mlbase_fx);
+            }
+            const int64_t arow = I.rowoff[a] - I.off[p + 1];
+            for (int k = lane; k < committed; k += 64) {
+                const int c = I.cc[cbase + k] & 0x7fffffff;
+                s2 = mn(s2, I.S1[arow + c] + I.cB[cbase + k]);
+            }
+            s2 = norm_inf(wave_min(s2));
+            int64_t ps = s2;
+            if (lane < 4) {
+                const int ap = I.out_dst[a * 4 + lane];
+                if (ap >= 0 && I.layer[ap] < q)
+                    ps = mn(ps, I.S1[cell_of(I, ap, b)] + I.out_U[a * 4 + lane] + I.mlbase_fx);
+            }
+            for (int eb = ib0 + lane; eb < ib1; eb += 64) {
+                const int bp = I.in_src[eb];
+                if (I.layer[bp] > p) ps = mn(ps, I.S1[cell_of(I, a, bp)] + I.in_U[eb] + I.mlbase_fx);
+            }
+            ps = norm_inf(wave_min(ps));
+            ctr.visits += (unsigned long long)committed;
+            if (lane == 0) {
+                I.Bt[cell] = Bv;
+                I.S2[cell] = s2;
+                I.S1[cell] = mn(Bv, ps);
+            }
+            const bool strict = Bv < ps;
+            const bool keep = I.retain_all ? (Bv < kINF) : strict;
+            ctr.feasible += Bv < kINF;
+            if (keep) {
+                const int slot = committed + added;
+                if (slot < I.ccap[b]) {
+                    if (lane == 0) {
+                        I.cc[cbase + slot] = a | (strict ? 0 : (int)0x80000000);
+                        I.cB[cbase + slot] = Bv;
+                    }
+                } else if (lane == 0) {
+                    atomicMin(&I.stats[2], (unsigned long long)g);
+                }
+                added++;
+                ctr.appends++;
+            }
+        }
+        if (lane == 0 && added) I.ccnt[b] = min(committed + added, I.ccap[b]);
+    }
+    // producers for later two-loops: IDL (per left inner state), JDL (per right inner state),
+    // LM (layer-pair minimum of the both-separable form)
+    if (g >= 5) {
+        __builtin_amdgcn_wave_barrier();
+        __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
+        const int wa = a_hi - a_lo, wb = b_hi - b_lo;
+        int64_t lm0 = kINF, lm1 = kINF;
+        for (int k = lane; k < wa * 12; k += 64) {
+            const int ia = k / 12, X = (k >> 2) % 3, xk = k & 3, c = a_lo + ia;
+            int64_t acc = kINF;
+            for (int ib = 0; ib < wb; ib++) {
+                const int d = b_lo + ib;
+                for (int tp = 0; tp < 6; tp++) {
+                    const int64_t vin = vbuf[ia * kMaxWidth + ib][tp];
+                    if (vin >= kINF) continue;
+                    for (int xl = 0; xl < 4; xl++) {
+                        const int64_t al = I.alphaU[d * 4 + xl];
+                        if (al < kINF) acc = mn(acc, vin + al + fx(mmx(S, X, kRev[tp], xl, xk), s));
+                    }
+                }
+            }
+            acc = norm_inf(acc);
+            I.IDL[ring_idx(c, g, X, xk)] = acc;
+            const int64_t be = I.betaU[c * 4 + xk];
+            if (acc < kINF && be < kINF) {
+                if (X == 0) lm0 = mn(lm0, acc + be);
+                if (X == 1) lm1 = mn(lm1, acc + be);
+            }
+        }
+        for (int k = lane; k < wb * 12; k += 64) {
+            const int ib = k / 12, X = (k >> 2) % 3, xl = k & 3, d = b_lo + ib;
+            int64_t acc = kINF;
+            for (int ia = 0; ia < wa; ia++) {
+                const int c = a_lo + ia;
+                for (int tp = 0; tp < 6; tp++) {
+                    const int64_t vin = vbuf[ia * kMaxWidth + ib][tp];
+                    if (vin >= kINF) continue;
+                    for (int xk = 0; xk < 4; xk++) {
+                        const int64_t be = I.betaU[c * 4 + xk];
+                        if (be < kINF) acc = mn(acc, vin + be + fx(mmx(S, X, kRev[tp], xl, xk), s));
+                    }
+                }
+            }
+            I.JDL[ring_idx(d, g, X, xl)] = norm_inf(acc);
+        }
+        lm0 = wave_min(lm0);
+        lm1 = wave_min(lm1);
+        if (lane == 0) {
+            int64_t* dst = I.LM + ((size_t)(g & (kLMRing - 1)) * (n + 1) + p) * 2;
+            dst[0] = norm_inf(lm0);
+            dst[1] = norm_inf(lm1);
+        }
+    }
+    return ctr;
+}
+
 // ---- external column: X(a) for every a of layer L (one workgroup) ------------------------------
-__device__ void ext_column(const Inst& I, const EnergyTables* __restrict__ E, int L) {
-    __shared__ int64_t red[256];
+__device__ void ext_column(const Inst& I, const SmallE& S, int L, int64_t* red) {
     const int tid = threadIdx.x;
     for (int a = I.off[L]; a < I.off[L + 1]; a++) {
         int64_t v = kINF;
         if (tid < 4) {
-            int d = I.out_dst[a * 4 + tid];
+            const int d = I.out_dst[a * 4 + tid];
             if (d >= 0) v = I.out_U[a * 4 + tid] + I.X[d];
         }
         if (L + 5 <= I.n) {
@@ -277,8 +553,8 @@ __device__ void ext_column(const Inst& I, const EnergyTables* __restrict__ E, in
                 const int64_t xb = I.X[bb];
 #pragma unroll
                 for (int t = 0; t < 6; t++) {
-                    int64_t vt = vr[t];
-                    if (vt < kINF) v = mn(v, vt + fx(au_pen(E, t), I.shift) + xb);
+                    const int64_t vt = vr[t];
+                    if (vt < kINF) v = mn(v, vt + fx(au_pen(S, t), I.shift) + xb);
                 }
             }
         }
@@ -293,118 +569,64 @@ __device__ void ext_column(const Inst& I, const EnergyTables* __restrict__ E, in
     }
 }
 
-// ---- the span step ---------------------------------------------------------------------------
+__device__ __forceinline__ void flush_counters(const Inst& I, const GroupCounters& c, int g, int lane) {
+    if (lane != 0) return;
+    if (c.visits) atomicAdd(&I.stats[0], c.visits);
+    if (c.appends) {
+        atomicAdd(&I.stats[1], c.appends);
+        if (I.span_appends) atomicAdd(&I.span_appends[g], c.appends);
+    }
+    if (c.feasible) atomicAdd(&I.stats[3], c.feasible);
+}
+
+// ---- the span step (plain mode) ---------------------------------------------------------------
 __global__ __launch_bounds__(256) void k_span(Inst I, const EnergyTables* __restrict__ E,
                                               const int32_t* __restrict__ spec, int g,
                                               int ext_layer, int nblk_cells) {
+    __shared__ SmallE S;
+    __shared__ int64_t red[256];
+    __shared__ int64_t vbuf[4][kMaxWidth * kMaxWidth][6];
+    __shared__ int64_t obuf[4][24];
+    stage_tables(S, E);
+    __syncthreads();
     if ((int)blockIdx.x >= nblk_cells) {
-        if (ext_layer >= 0) ext_column(I, E, ext_layer);
+        if (ext_layer >= 0) ext_column(I, S, ext_layer, red);
         return;
     }
     const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
     const int p = blockIdx.x * 4 + wave, q = p + g;
     if (q > I.n) return;
-    const int s = I.shift;
-    const int a_lo = I.off[p], a_hi = I.off[p + 1], b_lo = I.off[q], b_hi = I.off[q + 1];
-    unsigned long long visits = 0, appends = 0, feasible = 0;
-    for (int b = b_lo; b < b_hi; b++) {
-        const int committed = I.ccnt[b];  // entries of spans < g only (this wave owns C_b now)
-        const int64_t cbase = I.coff[b];
-        int added = 0;
-        for (int a = a_lo; a < a_hi; a++) {
-            const int64_t cell = I.rowoff[a] + (b - I.off[p + 1]);
-            // phase 1: typed closed values and the scalar branch (eq. 2)
-            int64_t Bv = kINF;
-            for (int t = 0; t < 6; t++) {
-                int64_t v = kINF;
-                if (g >= 5) {
-                    const int ea = a * 4 + kTX[t];
-                    const int a1 = I.out_dst[ea];
-                    if (a1 >= 0) {
-                        const int64_t Ua = I.out_U[ea];
-                        v = hairpin_lane(I, E, spec, a, b, t, a1, Ua, lane);
-                        v = mn(v, twoloop_lane(I, E, a, b, t, a1, Ua, lane));
-                        if (g >= 12) v = mn(v, multiloop_lane(I, E, a, b, t, a1, Ua, lane));
-                        v = norm_inf(wave_min(v));
-                    }
-                }
-                if (lane == 0) I.V[cell * 6 + t] = v;
-                if (v < kINF) Bv = mn(Bv, v + fx(E->ml_intern + au_pen(E, t), s));
-            }
-            // phase 2: S2 (eq. 7), P_S, S1 and the strict retention test (eq. 6)
-            int64_t s2 = kINF;
-            const int ib0 = I.in_start[b], ib1 = I.in_start[b + 1];
-            for (int eb = ib0 + lane; eb < ib1; eb += 64) {
-                int bp = I.in_src[eb];
-                if (I.layer[bp] > p) s2 = mn(s2, I.S2[cell_of(I, a, bp)] + I.in_U[eb] + I.mlbase_fx);
-            }
-            const int64_t arow = I.rowoff[a] - I.off[p + 1];
-            for (int k = lane; k < committed; k += 64) {
-                const int c = I.cc[cbase + k] & 0x7fffffff;
-                s2 = mn(s2, I.S1[arow + c] + I.cB[cbase + k]);
-            }
-            s2 = norm_inf(wave_min(s2));
-            int64_t ps = s2;
-            if (lane < 4) {
-                int ap = I.out_dst[a * 4 + lane];
-                if (ap >= 0 && I.layer[ap] < q) ps = mn(ps, I.S1[cell_of(I, ap, b)] + I.out_U[a * 4 + lane] + I.mlbase_fx);
-            }
-            for (int eb = ib0 + lane; eb < ib1; eb += 64) {
-                int bp = I.in_src[eb];
-                if (I.layer[bp] > p) ps = mn(ps, I.S1[cell_of(I, a, bp)] + I.in_U[eb] + I.mlbase_fx);
-            }
-            ps = norm_inf(wave_min(ps));
-            visits += (unsigned long long)committed;
-            if (lane == 0) {
-                I.Bt[cell] = Bv;
-                I.S2[cell] = s2;
-                I.S1[cell] = mn(Bv, ps);
-            }
-            const bool strict = Bv < ps;
-            const bool keep = I.retain_all ? (Bv < kINF) : strict;
-            feasible += Bv < kINF;
-            if (keep) {
-                const int slot = committed + added;
-                if (slot < I.ccap[b]) {
-                    if (lane == 0) {
-                        I.cc[cbase + slot] = a | (strict ? 0 : (int)0x80000000);
-                        I.cB[cbase + slot] = Bv;
-                    }
-                } else if (lane == 0) {
-                    atomicMin((unsigned long long*)&I.stats[2], (unsigned long long)g);
-                }
-                added++;
-                appends++;
-            }
-        }
-        if (lane == 0 && added) I.ccnt[b] = min(committed + added, I.ccap[b]);
-    }
-    if (lane == 0) {
-        if (visits) atomicAdd(&I.stats[0], visits);
-        if (appends) {
-            atomicAdd(&I.stats[1], appends);
-            if (I.span_appends) atomicAdd(&I.span_appends[g], appends);
-        }
-        if (feasible) atomicAdd(&I.stats[3], feasible);
-    }
+    GroupCounters c = span_group(I, S, E, spec, p, q, lane, vbuf[wave], obuf[wave]);
+    flush_counters(I, c, g, lane);
 }
 
-__global__ void k_ext(Inst I, const EnergyTables* __restrict__ E, int L) { ext_column(I, E, L); }
+__global__ __launch_bounds__(256) void k_ext(Inst I, const EnergyTables* __restrict__ E, int L) {
+    __shared__ SmallE S;
+    __shared__ int64_t red[256];
+    stage_tables(S, E);
+    __syncthreads();
+    ext_column(I, S, L, red);
+}
 
 __global__ void k_init(Inst I) {
-    const int tid = blockIdx.x * blockDim.x + threadIdx.x;
-    for (int i = tid; i < I.N; i += gridDim.x * blockDim.x) {
+    const int tid = blockIdx.x * blockDim.x + threadIdx.x, nt = gridDim.x * blockDim.x;
+    for (int i = tid; i < I.N; i += nt) {
         I.ccnt[i] = 0;
         I.X[i] = (i == I.N - 1) ? 0 : kINF;
     }
+    for (size_t i = tid; i < (size_t)kLMRing * (I.n + 1) * 2; i += nt) I.LM[i] = kINF;
+    for (size_t i = tid; i < (size_t)I.N * kLMRing * 12; i += nt) {
+        I.IDL[i] = kINF;
+        I.JDL[i] = kINF;
+    }
     if (tid < 4) I.stats[tid] = tid == 2 ? ~0ull : 0ull;
     if (I.span_appends)
-        for (int i = tid; i <= I.n; i += gridDim.x * blockDim.x) I.span_appends[i] = 0;
+        for (int i = tid; i <= I.n; i += nt) I.span_appends[i] = 0;
 }
 
 }  // namespace sd
 
-// ---- host launch wrappers (C++ linkage, used by the library host code) --------------------------
+// ---- host launch wrappers ----------------------------------------------------------------------
 namespace sd {
 
 hipError_t upload_pair_order() {
@@ -418,7 +640,39 @@ hipError_t upload_pair_order() {
         }
     hipError_t e = hipMemcpyToSymbol(HIP_SYMBOL(kL1), l1, sizeof(l1));
     if (e != hipSuccess) return e;
-    return hipMemcpyToSymbol(HIP_SYMBOL(kL2), l2, sizeof(l2));
+    e = hipMemcpyToSymbol(HIP_SYMBOL(kL2), l2, sizeof(l2));
+    if (e != hipSuccess) return e;
+    // categorised pair lists per phase (p mod 3, q mod 3)
+    static unsigned short list[4][9][kNumPairs];
+    static unsigned short cnt[4][9][31];
+    memset(list, 0, sizeof(list));
+    memset(cnt, 0, sizeof(cnt));
+    for (int pm = 0; pm < 3; pm++)
+        for (int qm = 0; qm < 3; qm++) {
+            const int ph = pm * 3 + qm, p = 3 + pm, q = 300 + qm;  // representatives of the phases
+            int len[4] = {0, 0, 0, 0};
+            for (int sum = 0; sum <= kMaxLoop; sum++) {
+                for (int a = 0; a <= sum; a++) {
+                    const int b = sum - a;
+                    const bool sl = a >= 2 && (p + 2) / 3 != (p + a) / 3;
+                    const bool sr = b >= 2 && (q - b) / 3 != (q - 2) / 3;
+                    int lst;
+                    unsigned short code = (unsigned short)(a | b << 5);
+                    if (a == 0 || b == 0) lst = kListBulge;
+                    else if (sl && sr) lst = kListFast;
+                    else if (!sl && !sr) lst = kListLab;
+                    else {
+                        lst = kListOne;
+                        if (sl) code |= 1 << 10;
+                    }
+                    list[lst][ph][len[lst]++] = code;
+                }
+                for (int l = 0; l < 4; l++) cnt[l][ph][sum] = (unsigned short)len[l];
+            }
+        }
+    e = hipMemcpyToSymbol(HIP_SYMBOL(kPairList), list, sizeof(list));
+    if (e != hipSuccess) return e;
+    return hipMemcpyToSymbol(HIP_SYMBOL(kPairCnt), cnt, sizeof(cnt));
 }
 
 hipError_t launch_init(const Inst& I, hipStream_t st) {

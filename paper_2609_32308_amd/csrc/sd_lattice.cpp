@@ -294,6 +294,11 @@ int build_lattice(const char* protein, const CodonTable& T, const Params& P, dou
     }
     L.off[n + 1] = (int)L.layer.size();
     const int N = L.N = (int)L.layer.size();
+    for (int p = 0; p <= n; p++)
+        if (L.off[p + 1] - L.off[p] > 4) {  // kernels buffer at most 4 x 4 cells per layer pair
+            err = "automaton layer wider than 4 states";
+            return SD_E_INTERNAL;
+        }
     L.out_dst.assign((size_t)4 * N, -1);
     L.out_cod.assign((size_t)4 * N, -1);
     L.out_q.assign((size_t)4 * N, 0.0);
@@ -376,6 +381,62 @@ int build_lattice(const char* protein, const CodonTable& T, const Params& P, dou
             }
     L.tail[beta[A]] = 0;
     for (int k = 0; k < A; k++) L.P[k + 1] = L.P[k] + cmin[k];
+    // segment ends: alpha(d,x) = U(d -x-> d2) + tail(d2); beta(c,x) = min U over in-edges labelled x
+    L.alphaU.assign((size_t)4 * N, kINF);
+    L.betaU.assign((size_t)4 * N, kINF);
+    for (int v = 0; v < N; v++)
+        for (int x = 0; x < 4; x++) {
+            int d = L.out_dst[4 * v + x];
+            if (d >= 0) L.alphaU[4 * v + x] = L.out_U[4 * v + x] + L.tail[d];
+        }
+    for (int v = 0; v < N; v++)
+        for (int j = L.in_start[v]; j < L.in_start[v + 1]; j++)
+            L.betaU[4 * v + L.in_lab[j]] = std::min(L.betaU[4 * v + L.in_lab[j]], L.in_U[j]);
+    // label paths of 1..4 edges out of / into every state (explicit short loop segments)
+    L.fwd_off.assign((size_t)4 * N + 1, 0);
+    L.bwd_off.assign((size_t)4 * N + 1, 0);
+    L.fwd_meta.clear(); L.fwd_cost.clear(); L.bwd_meta.clear(); L.bwd_cost.clear();
+    for (int u = 0; u < N; u++)
+        for (int len = 1; len <= 4; len++) {
+            L.fwd_off[4 * u + len - 1] = (int)L.fwd_meta.size();
+            struct Fr { int state, first_lab, last_lab; int64_t cost; int depth; };
+            std::vector<Fr> stack{{u, -1, -1, 0, 0}};
+            while (!stack.empty()) {
+                Fr f = stack.back();
+                stack.pop_back();
+                if (f.depth == len) {
+                    L.fwd_meta.push_back(f.state << 4 | f.first_lab << 2 | f.last_lab);
+                    L.fwd_cost.push_back(f.cost);
+                    continue;
+                }
+                for (int x = 0; x < 4; x++) {
+                    int e = 4 * f.state + x, d = L.out_dst[e];
+                    if (d < 0) continue;
+                    stack.push_back({d, f.depth == 0 ? x : f.first_lab, x, f.cost + L.out_U[e], f.depth + 1});
+                }
+            }
+        }
+    L.fwd_off[4 * N] = (int)L.fwd_meta.size();
+    for (int v = 0; v < N; v++)
+        for (int len = 1; len <= 4; len++) {
+            L.bwd_off[4 * v + len - 1] = (int)L.bwd_meta.size();
+            // backward walk over in-edge sequences; record (start, first label, last label)
+            struct Fr { int state, first_lab, last_lab; int64_t cost; int depth; };
+            std::vector<Fr> stack{{v, -1, -1, 0, 0}};
+            while (!stack.empty()) {
+                Fr f = stack.back();
+                stack.pop_back();
+                if (f.depth == len) {
+                    L.bwd_meta.push_back(f.state << 4 | f.first_lab << 2 | f.last_lab);
+                    L.bwd_cost.push_back(f.cost);
+                    continue;
+                }
+                for (int j = L.in_start[f.state]; j < L.in_start[f.state + 1]; j++)
+                    stack.push_back({L.in_src[j], L.in_lab[j], f.depth == 0 ? L.in_lab[j] : f.last_lab,
+                                     f.cost + L.in_U[j], f.depth + 1});
+            }
+        }
+    L.bwd_off[4 * N] = (int)L.bwd_meta.size();
     // hairpin initiation per size, extrapolated above 30 (rounded half away from zero)
     L.hp_init.assign(n + 1, kNoSpecial);
     for (int m = 3; m <= n; m++)

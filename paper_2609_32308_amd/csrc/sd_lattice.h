@@ -35,6 +35,9 @@ struct Lattice {
     std::vector<int> in_start, in_src, in_lab, in_cod;
     std::vector<int64_t> in_U;
     std::vector<int64_t> tail, P;
+    std::vector<int64_t> alphaU, betaU;  // [N*4] separable segment ends (see sd_kernels.hip)
+    std::vector<int> fwd_off, fwd_meta, bwd_off, bwd_meta;  // label paths of 1..4 edges
+    std::vector<int64_t> fwd_cost, bwd_cost;
     std::vector<int> pfx, hp_init;
     std::vector<int64_t> rowoff, coff;
     std::vector<int> ccap;
