@@ -61,7 +61,9 @@ typedef struct sd_options {
                               instead of the strict test B < P_S (Sec. 8.1); same optimum     */
     int capacity_override; /* >0: candidate slots per right endpoint (forces the overflow
                               fallback when small; results are unchanged); 0: worst case      */
-    int reserved[6];
+    int kernel_timing;     /* 1: bracket every span-step launch with HIP events on the
+                              context's stream and report the summed kernel time            */
+    int reserved[5];
 } sd_options;
 
 typedef struct sd_result {
@@ -80,6 +82,8 @@ typedef struct sd_result {
     int64_t n_feasible;      /* cells with finite direct branch cost B                        */
     double t_fill_s;         /* cost-only time: allocation + forward fill (Sec. 6)             */
     double t_total_s;        /* complete time: input -> strings                                */
+    double t_span_kernels_s; /* with kernel_timing: summed duration of the span-step kernels  */
+    int64_t n_span_launches; /* span-step kernel launches of the forward fill                  */
 } sd_result;
 
 /* Parameter file (project text format "SPARSEDESIGN-PARAMS 1"; Turner-2004 d0 array shapes,

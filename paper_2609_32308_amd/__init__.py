@@ -36,7 +36,8 @@ class SDError(RuntimeError):
 
 
 class Options(C.Structure):
-    _fields_ = [("retain_all", C.c_int), ("capacity_override", C.c_int), ("reserved", C.c_int * 6)]
+    _fields_ = [("retain_all", C.c_int), ("capacity_override", C.c_int), ("kernel_timing", C.c_int),
+                ("reserved", C.c_int * 5)]
 
 
 class _Result(C.Structure):
@@ -46,6 +47,7 @@ class _Result(C.Structure):
         ("fixed_shift", C.c_int32), ("cai", C.c_double), ("n_states", C.c_int64),
         ("n_cells", C.c_int64), ("n_candidates", C.c_int64), ("n_visits", C.c_int64),
         ("n_feasible", C.c_int64), ("t_fill_s", C.c_double), ("t_total_s", C.c_double),
+        ("t_span_kernels_s", C.c_double), ("n_span_launches", C.c_int64),
     ]
 
 
@@ -143,19 +145,23 @@ class Result:
     n_feasible: int
     t_fill_s: float
     t_total_s: float
+    t_span_kernels_s: float
+    n_span_launches: int
 
 
 def _convert(r: _Result) -> Result:
     out = Result(C.string_at(r.mrna).decode(), C.string_at(r.structure).decode(), r.energy_centi,
                  r.codon_cost, r.objective_kcal, r.objective_fixed, r.fixed_shift, r.cai, r.n_states,
-                 r.n_cells, r.n_candidates, r.n_visits, r.n_feasible, r.t_fill_s, r.t_total_s)
+                 r.n_cells, r.n_candidates, r.n_visits, r.n_feasible, r.t_fill_s, r.t_total_s,
+                 r.t_span_kernels_s, r.n_span_launches)
     lib().sd_result_free(C.byref(r))
     return out
 
 
 class Context:
-    def __init__(self, device: int = 0, retain_all: bool = False, capacity_override: int = 0):
-        opt = Options(int(retain_all), int(capacity_override))
+    def __init__(self, device: int = 0, retain_all: bool = False, capacity_override: int = 0,
+                 kernel_timing: bool = False):
+        opt = Options(int(retain_all), int(capacity_override), int(kernel_timing))
         h = C.c_void_p()
         _check(lib().sd_context_create(device, C.byref(opt), C.byref(h)), "sd_context_create")
         self.h = h

@@ -169,6 +169,7 @@ extern "C" void sd_context_destroy(sd_context* c) {
     if (c->spec_dev) hipFree(c->spec_dev);
     if (c->ev0) hipEventDestroy(c->ev0);
     if (c->ev1) hipEventDestroy(c->ev1);
+    for (hipEvent_t ev : c->tev) hipEventDestroy(ev);
     if (c->stream) hipStreamDestroy(c->stream);
     delete c;
 }
@@ -304,15 +305,36 @@ hipError_t upload_instance(const Lattice& L, const Inst& I, hipStream_t st) {
 sd_status run_plain(sd_context* c, const Lattice& L, Inst& I, int64_t* overflow_span) {
     hipStream_t st = c->stream;
     hipError_t e = launch_init(I, st);
-    for (int g = 1; g <= L.n && e == hipSuccess; g++)
-        e = launch_span(I, (const EnergyTables*)c->E_dev, (const int32_t*)c->spec_dev, g,
-                        g >= 2 ? L.n - g + 1 : -1, st);
+    const bool timing = c->opt.kernel_timing != 0;
+    if (timing && (int)c->tev.size() < 2 * L.n) {
+        while ((int)c->tev.size() < 2 * L.n && e == hipSuccess) {
+            hipEvent_t ev;
+            e = hipEventCreate(&ev);
+            if (e == hipSuccess) c->tev.push_back(ev);
+        }
+    }
+    for (int g = 1; g <= L.n && e == hipSuccess; g++) {
+        if (timing) e = hipEventRecord(c->tev[2 * (g - 1)], st);
+        if (e == hipSuccess)
+            e = launch_span(I, (const EnergyTables*)c->E_dev, (const int32_t*)c->spec_dev, g,
+                            g >= 2 ? L.n - g + 1 : -1, st);
+        if (timing && e == hipSuccess) e = hipEventRecord(c->tev[2 * (g - 1) + 1], st);
+    }
     if (e == hipSuccess) e = launch_ext(I, (const EnergyTables*)c->E_dev, 0, st);
     unsigned long long stats[4];
     if (e == hipSuccess) e = hipMemcpyAsync(stats, I.stats, sizeof(stats), hipMemcpyDeviceToHost, st);
     if (e == hipSuccess) e = hipStreamSynchronize(st);
     if (e != hipSuccess) return hip_fail(e, "span wavefront");
     *overflow_span = stats[2] == ~0ull ? 0 : (int64_t)stats[2];
+    c->last_kernel_ms = 0.0;
+    c->last_launches = L.n;
+    if (timing)
+        for (int g = 1; g <= L.n; g++) {
+            float ms = 0.f;
+            e = hipEventElapsedTime(&ms, c->tev[2 * (g - 1)], c->tev[2 * (g - 1) + 1]);
+            if (e != hipSuccess) return hip_fail(e, "kernel timing");
+            c->last_kernel_ms += ms;
+        }
     c->last_visits = (int64_t)stats[0];
     c->last_appends = (int64_t)stats[1];
     c->last_feasible = (int64_t)stats[3];
@@ -428,6 +450,8 @@ sd_status design_plain(sd_context* c, const char* protein, const sd_codon_table*
     }
     out->t_fill_s = tf1 - tf0;
     out->t_total_s = now_s() - t0;
+    out->t_span_kernels_s = c->last_kernel_ms * 1e-3;
+    out->n_span_launches = c->last_launches;
     if (keep) *keep = std::move(T);
     if (keepL) *keepL = std::move(L);
     return SD_OK;

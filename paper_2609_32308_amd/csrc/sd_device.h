@@ -3,6 +3,7 @@
 #include <hip/hip_runtime.h>
 
 #include <string>
+#include <vector>
 
 #include "../../include/sparsedesign.h"
 #include "sd_internal.h"
@@ -20,6 +21,8 @@ struct sd_context {
     uint64_t params_uid = 0;
     int64_t last_visits = 0, last_appends = 0, last_feasible = 0, last_overflow_span = 0;
     double last_kernel_ms = 0.0;
+    int64_t last_launches = 0;
+    std::vector<hipEvent_t> tev;  // kernel_timing: event pairs around span launches
 };
 
 namespace sd {
