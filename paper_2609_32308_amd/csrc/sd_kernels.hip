@@ -235,31 +235,60 @@ __device__ int64_t bulge_pair(const Inst& I, const SmallE& S, int t, int a1, int
 
 // ---- two-loop closure: both segments explicit (each has 1..4 bases inside one codon) -------------
 // Left segments are the label paths of l1 edges out of a1, right segments the paths of l2 edges
-// into b1; lanes split the (left path, right path) combinations.
+// into b1.  The (pair, left path, right path) combinations of all such pairs are flattened over
+// the lanes: lane k < #pairs publishes its pair's combination count, a wave prefix sum gives
+// the offsets, and every lane decodes its own combinations.
+struct LabPair {
+    int f0, nl, r0, nr, l1, l2, start;
+};
+
 __device__ int64_t labelled_pairs(const Inst& I, const SmallE& S, const EnergyTables* __restrict__ E,
-                                  int t, int a1, int b1, int64_t Uab, int ph, int cap, int lane) {
+                                  int t, int a1, int b1, int64_t Uab, int ph, int cap, int lane,
+                                  LabPair* lp) {
     const int s = I.shift;
+    const int npairs = kPairCnt[kListLab][ph][cap];  // <= 16
+    int cnt = 0;
+    if (lane < npairs) {
+        const int code = kPairList[kListLab][ph][lane], l1 = code & 31, l2 = (code >> 5) & 31;
+        LabPair x;
+        x.f0 = I.fwd_off[a1 * 4 + l1 - 1];
+        x.nl = I.fwd_off[a1 * 4 + l1] - x.f0;
+        x.r0 = I.bwd_off[b1 * 4 + l2 - 1];
+        x.nr = I.bwd_off[b1 * 4 + l2] - x.r0;
+        x.l1 = l1;
+        x.l2 = l2;
+        cnt = x.nl * x.nr;
+        lp[lane] = x;
+    }
+    int incl = cnt;  // inclusive prefix over lanes 0..15
+#pragma unroll
+    for (int o = 1; o < 16; o <<= 1) {
+        const int v = __shfl_up(incl, o, 64);
+        if ((lane & 15) >= o) incl += v;
+    }
+    if (lane < npairs) lp[lane].start = incl - cnt;
+    const int total = __shfl(incl, 15, 64);
+    __builtin_amdgcn_wave_barrier();
+    __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
     int64_t best = kINF;
-    const int npairs = kPairCnt[kListLab][ph][cap];
-    for (int k = 0; k < npairs; k++) {
-        const int code = kPairList[kListLab][ph][k], l1 = code & 31, l2 = (code >> 5) & 31;
-        const int f0 = I.fwd_off[a1 * 4 + l1 - 1], nl = I.fwd_off[a1 * 4 + l1] - f0;
-        const int r0 = I.bwd_off[b1 * 4 + l2 - 1], nr = I.bwd_off[b1 * 4 + l2] - r0;
-        for (int idx = lane; idx < nl * nr; idx += 64) {
-            const int i = idx / nr, j = idx - i * nr;
-            const int fm = I.fwd_meta[f0 + i], bm = I.bwd_meta[r0 + j];
-            const int c = fm >> 4, xi = (fm >> 2) & 3, xk = fm & 3;
-            const int d = bm >> 4, xl = (bm >> 2) & 3, xj = bm & 3;
-            const int64_t base = Uab + I.fwd_cost[f0 + i] + I.bwd_cost[r0 + j];
-            const int64_t* v = I.V + (I.rowoff[c] + (d - I.off[I.layer[c] + 1])) * 6;
-            for (int tp = 0; tp < 6; tp++) {
-                const int64_t vin = v[tp];
-                if (vin >= kINF) continue;
-                const int32_t e2 = interior_e(S, E, t, kRev[tp], l1, l2, xi, xk, xl, xj);
-                best = mn(best, base + vin + fx(e2, s));
-            }
+    for (int idx = lane; idx < total; idx += 64) {
+        int k = 0;
+        while (k + 1 < npairs && lp[k + 1].start <= idx) k++;
+        const LabPair x = lp[k];
+        const int r = idx - x.start, i = r / x.nr, j = r - i * x.nr;
+        const int fm = I.fwd_meta[x.f0 + i], bm = I.bwd_meta[x.r0 + j];
+        const int c = fm >> 4, xi = (fm >> 2) & 3, xk = fm & 3;
+        const int d = bm >> 4, xl = (bm >> 2) & 3, xj = bm & 3;
+        const int64_t base = Uab + I.fwd_cost[x.f0 + i] + I.bwd_cost[x.r0 + j];
+        const int64_t* v = I.V + (I.rowoff[c] + (d - I.off[I.layer[c] + 1])) * 6;
+        for (int tp = 0; tp < 6; tp++) {
+            const int64_t vin = v[tp];
+            if (vin >= kINF) continue;
+            const int32_t e2 = interior_e(S, E, t, kRev[tp], x.l1, x.l2, xi, xk, xl, xj);
+            best = mn(best, base + vin + fx(e2, s));
         }
     }
+    __builtin_amdgcn_wave_barrier();
     return best;
 }
 
@@ -279,8 +308,13 @@ __device__ __forceinline__ int mm_class(int l1, int l2) {
 __device__ __forceinline__ int32_t mmx(const SmallE& S, int X, int t, int i, int j) {
     return X == 0 ? S.mmI[t][i][j] : X == 1 ? S.mm23[t][i][j] : S.mm1n[t][i][j];
 }
+// per-state rings [state][class][label][span mod 64]: a consumer walks consecutive spans
 __device__ __forceinline__ int64_t ring_idx(int state, int span, int X, int lab) {
-    return (((int64_t)state * kLMRing + (span & (kLMRing - 1))) * 3 + X) * 4 + lab;
+    return (((int64_t)state * 3 + X) * 4 + lab) * kLMRing + (span & (kLMRing - 1));
+}
+// per-layer-pair ring [left layer][class][span mod 64]
+__device__ __forceinline__ int64_t lm_idx(int layer, int span, int X) {
+    return ((int64_t)layer * 2 + X) * kLMRing + (span & (kLMRing - 1));
 }
 __device__ __forceinline__ int64_t PLt(const Inst& I, int p, int l1) { return I.P[(p + l1) / 3] - I.P[(p + 2) / 3 + 1]; }
 __device__ __forceinline__ int64_t PRt(const Inst& I, int q, int l2) { return I.P[(q - 2) / 3] - I.P[(q - l2) / 3 + 1]; }
@@ -338,26 +372,92 @@ __device__ int64_t lsep_pair(const Inst& I, const SmallE& S, int b1, int64_t Uab
     return best;
 }
 
-// ---- the work of one layer pair (p, q) in span step g ----------------------------------------
+// ---- the work of one layer pair (p, q) in span step g: one workgroup of 4 waves -------------------
 struct GroupCounters {
     unsigned long long visits, appends, feasible;
 };
 
-constexpr int kMaxWidth = 4;  // states per layer supported by the per-wave cell buffer
+constexpr int kMaxWidth = 4;  // states per layer supported by the per-group cell buffers
+
+struct GroupShared {
+    int64_t vbuf[kMaxWidth * kMaxWidth][6];  // typed closed values of this layer pair's cells
+    int64_t cellB[kMaxWidth * kMaxWidth];
+    int keep[kMaxWidth * kMaxWidth];          // 0 none, 1 strict, 2 retained non-strict
+    int combo[kMaxWidth * kMaxWidth * 6];     // (cell, type) jobs with an out-edge of label x
+    int ncombo;
+    int64_t red[4][2];
+    int64_t obuf[4][24];
+    LabPair lab[4][16];
+};
+
+// typed closed value V_t(a, b) with the lanes of one wave
+__device__ int64_t closed_value(const Inst& I, const SmallE& S, const EnergyTables* __restrict__ E,
+                                const int32_t* __restrict__ spec, int a, int b, int t, int p, int q,
+                                int64_t mini0, int64_t mini1, int lane, int64_t* obuf, LabPair* lab) {
+    const int g = q - p, s = I.shift;
+    const int a1 = I.out_dst[a * 4 + kTX[t]];
+    const int64_t Ua = I.out_U[a * 4 + kTX[t]];
+    const int y = kTY[t];
+    const int ib0 = I.in_start[b], ib1 = I.in_start[b + 1];
+    int64_t v = hairpin_lane(I, S, spec, a, b, t, a1, Ua, lane);
+    if (g >= 7) {
+        const int ph = (p % 3) * 3 + (q % 3), cap = min(g - 7, kMaxLoop);
+        for (int eb = ib0; eb < ib1; eb++) {
+            if (I.in_lab[eb] != y) continue;
+            const int b1 = I.in_src[eb];
+            const int64_t Uab = Ua + I.in_U[eb];
+            outer_minima(I, S, a1, b1, t, lane, obuf);
+            for (int k = lane; k < kPairCnt[kListBulge][0][cap]; k += 64) {
+                const int code = kPairList[kListBulge][0][k], l1 = code & 31, l2 = (code >> 5) & 31;
+                v = mn(v, bulge_pair(I, S, t, a1, b1, Uab, l1, l2, p + 1 + l1, q - 1 - l2));
+            }
+            for (int k = lane; k < kPairCnt[kListOne][ph][cap]; k += 64) {
+                const int code = kPairList[kListOne][ph][k], l1 = code & 31, l2 = (code >> 5) & 31;
+                const int cl = p + 1 + l1, dl = q - 1 - l2;
+                v = mn(v, (code >> 10) ? lsep_pair(I, S, b1, Uab, l1, l2, cl, dl, p, obuf)
+                                       : rsep_pair(I, S, a1, Uab, l1, l2, cl, dl, q, obuf));
+            }
+            v = mn(v, labelled_pairs(I, S, E, t, a1, b1, Uab, ph, cap, lane, lab));
+        }
+    }
+    if (g >= 12) {
+        // both segments separable: OUT(a1, b1, t) + layer-pair minimum
+        const int nbx = (ib1 - ib0) * 32;
+        for (int k = lane; k < nbx; k += 64) {
+            const int eb = ib0 + (k >> 5), X = (k >> 4) & 1, xi = (k >> 2) & 3, xj = k & 3;
+            if (I.in_lab[eb] != y) continue;
+            const int64_t mini = X ? mini1 : mini0;
+            const int64_t al = I.alphaU[a1 * 4 + xi], be = I.betaU[I.in_src[eb] * 4 + xj];
+            if (mini >= kINF || al >= kINF || be >= kINF) continue;
+            v = mn(v, Ua + I.in_U[eb] + al + be + fx(mmx(S, X, t, xi, xj), s) + mini);
+        }
+        // multiloop closure (ML_closing + ML_intern + AU) + S2 of the interior
+        const int32_t mlc = S.ml_closing + S.ml_intern + au_pen(S, t);
+        for (int eb = ib0 + lane; eb < ib1; eb += 64) {
+            if (I.in_lab[eb] != y) continue;
+            const int b1 = I.in_src[eb];
+            if (I.layer[b1] - I.layer[a1] < 10) continue;
+            v = mn(v, I.S2[cell_of(I, a1, b1)] + Ua + I.in_U[eb] + fx(mlc, s));
+        }
+    }
+    return norm_inf(wave_min(v));
+}
 
 __device__ GroupCounters span_group(const Inst& I, const SmallE& S, const EnergyTables* __restrict__ E,
-                                    const int32_t* __restrict__ spec, int p, int q, int lane,
-                                    int64_t (*vbuf)[6], int64_t* obuf) {
-    const int g = q - p, s = I.shift, n = I.n;
+                                    const int32_t* __restrict__ spec, int p, int q, GroupShared& G) {
+    const int g = q - p, s = I.shift;
+    const int tid = threadIdx.x, wave = tid >> 6, lane = tid & 63;
     GroupCounters ctr{0, 0, 0};
+    const int a_lo = I.off[p], a_hi = I.off[p + 1], b_lo = I.off[q], b_hi = I.off[q + 1];
+    const int wa = a_hi - a_lo, wb = b_hi - b_lo, ncell = wa * wb;
     // separable interior minima of this layer pair (both segments separable), per class
     int64_t mini0 = kINF, mini1 = kINF;
     if (g >= 12) {
         const int ph = (p % 3) * 3 + (q % 3), cap = min(g - 7, kMaxLoop);
-        for (int k = lane; k < kPairCnt[kListFast][ph][cap]; k += 64) {
+        for (int k = tid; k < kPairCnt[kListFast][ph][cap]; k += blockDim.x) {
             const int code = kPairList[kListFast][ph][k], l1 = code & 31, l2 = (code >> 5) & 31;
             const int cl = p + 1 + l1, dl = q - 1 - l2, X = pair_class(l1, l2);
-            const int64_t lm = I.LM[((size_t)((dl - cl) & (kLMRing - 1)) * (n + 1) + cl) * 2 + X];
+            const int64_t lm = I.LM[lm_idx(cl, dl - cl, X)];
             if (lm >= kINF) continue;
             const int64_t v = lm + fx(interior_base(S, l1, l2), s) + PLt(I, p, l1) + PRt(I, q, l2);
             if (X) mini1 = mn(mini1, v);
@@ -365,172 +465,153 @@ __device__ GroupCounters span_group(const Inst& I, const SmallE& S, const Energy
         }
         mini0 = wave_min(mini0);
         mini1 = wave_min(mini1);
+        if (lane == 0) {
+            G.red[wave][0] = mini0;
+            G.red[wave][1] = mini1;
+        }
     }
-    const int a_lo = I.off[p], a_hi = I.off[p + 1], b_lo = I.off[q], b_hi = I.off[q + 1];
-    for (int b = b_lo; b < b_hi; b++) {
-        const int committed = I.ccnt[b];  // entries of spans < g only (this wave owns C_b now)
+    if (tid == 0) {
+        int k = 0;
+        for (int ci = 0; ci < ncell; ci++) {
+            const int a = a_lo + ci / wb;
+            for (int t = 0; t < 6; t++) {
+                G.vbuf[ci][t] = kINF;
+                if (g >= 5 && I.out_dst[a * 4 + kTX[t]] >= 0) G.combo[k++] = ci * 6 + t;
+            }
+        }
+        G.ncombo = k;
+    }
+    __syncthreads();
+    if (g >= 12) {
+        mini0 = mn(mn(G.red[0][0], G.red[1][0]), mn(G.red[2][0], G.red[3][0]));
+        mini1 = mn(mn(G.red[0][1], G.red[1][1]), mn(G.red[2][1], G.red[3][1]));
+    }
+    // phase 1: typed closed values, (cell, type) jobs spread over the waves
+    for (int k = wave; k < G.ncombo; k += 4) {
+        const int ci = G.combo[k] / 6, t = G.combo[k] % 6;
+        const int a = a_lo + ci / wb, b = b_lo + ci % wb;
+        const int64_t v = closed_value(I, S, E, spec, a, b, t, p, q, mini0, mini1, lane, G.obuf[wave], G.lab[wave]);
+        if (lane == 0) G.vbuf[ci][t] = v;
+    }
+    __syncthreads();
+    // phase 2: branch value (eq. 2), S2 (eq. 7), P_S, S1 and the retention test (eq. 6); one
+    // cell per wave.  Every scan reads only entries committed by earlier spans.
+    for (int ci = wave; ci < ncell; ci += 4) {
+        const int a = a_lo + ci / wb, b = b_lo + ci % wb;
+        const int64_t cell = I.rowoff[a] + (b - I.off[p + 1]);
+        int64_t Bv = kINF;
+        for (int t = 0; t < 6; t++) {
+            const int64_t v = G.vbuf[ci][t];
+            if (lane == t) I.V[cell * 6 + t] = v;
+            if (v < kINF) Bv = mn(Bv, v + fx(S.ml_intern + au_pen(S, t), s));
+        }
+        const int committed = I.ccnt[b];
         const int64_t cbase = I.coff[b];
         const int ib0 = I.in_start[b], ib1 = I.in_start[b + 1];
-        int added = 0;
-        for (int a = a_lo; a < a_hi; a++) {
-            const int64_t cell = I.rowoff[a] + (b - I.off[p + 1]);
-            // phase 1: typed closed values and the scalar branch (eq. 2)
-            int64_t Bv = kINF;
-#pragma nounroll
-            for (int t = 0; t < 6; t++) {
-                int64_t v = kINF;
-                const int a1 = g >= 5 ? I.out_dst[a * 4 + kTX[t]] : -1;
-                if (a1 >= 0) {
-                    const int64_t Ua = I.out_U[a * 4 + kTX[t]];
-                    const int y = kTY[t];
-                    v = hairpin_lane(I, S, spec, a, b, t, a1, Ua, lane);
-                    if (g >= 7) {
-                        const int ph = (p % 3) * 3 + (q % 3), cap = min(g - 7, kMaxLoop);
-                        for (int eb = ib0; eb < ib1; eb++) {
-                            if (I.in_lab[eb] != y) continue;
-                            const int b1 = I.in_src[eb];
-                            const int64_t Uab = Ua + I.in_U[eb];
-                            outer_minima(I, S, a1, b1, t, lane, obuf);
-                            for (int k = lane; k < kPairCnt[kListBulge][0][cap]; k += 64) {
-                                const int code = kPairList[kListBulge][0][k], l1 = code & 31, l2 = (code >> 5) & 31;
-                                v = mn(v, bulge_pair(I, S, t, a1, b1, Uab, l1, l2, p + 1 + l1, q - 1 - l2));
-                            }
-                            for (int k = lane; k < kPairCnt[kListOne][ph][cap]; k += 64) {
-                                const int code = kPairList[kListOne][ph][k], l1 = code & 31, l2 = (code >> 5) & 31;
-                                const int cl = p + 1 + l1, dl = q - 1 - l2;
-                                v = mn(v, (code >> 10) ? lsep_pair(I, S, b1, Uab, l1, l2, cl, dl, p, obuf)
-                                                       : rsep_pair(I, S, a1, Uab, l1, l2, cl, dl, q, obuf));
-                            }
-                            v = mn(v, labelled_pairs(I, S, E, t, a1, b1, Uab, ph, cap, lane));
-                        }
-                    }
-                    if (g >= 12) {
-                        // both segments separable: OUT(a1, b1, t) + layer-pair minimum
-                        const int nbx = (ib1 - ib0) * 32;
-                        for (int k = lane; k < nbx; k += 64) {
-                            const int eb = ib0 + (k >> 5), X = (k >> 4) & 1, xi = (k >> 2) & 3, xj = k & 3;
-                            if (I.in_lab[eb] != y) continue;
-                            const int64_t mini = X ? mini1 : mini0;
-                            const int64_t al = I.alphaU[a1 * 4 + xi], be = I.betaU[I.in_src[eb] * 4 + xj];
-                            if (mini >= kINF || al >= kINF || be >= kINF) continue;
-                            v = mn(v, Ua + I.in_U[eb] + al + be + fx(mmx(S, X, t, xi, xj), s) + mini);
-                        }
-                        // multiloop closure (ML_closing + ML_intern + AU) + S2 of the interior
-                        const int32_t mlc = S.ml_closing + S.ml_intern + au_pen(S, t);
-                        for (int eb = ib0 + lane; eb < ib1; eb += 64) {
-                            if (I.in_lab[eb] != y) continue;
-                            const int b1 = I.in_src[eb];
-                            if (I.layer[b1] - I.layer[a1] < 10) continue;
-                            v = mn(v, I.S2[cell_of(I, a1, b1)] + Ua + I.in_U[eb] + fx(mlc, s));
-                        }
-                    }
-                    v = norm_inf(wave_min(v));
-                }
-                if (lane == 0) {
-                    I.V[cell * 6 + t] = v;
-                    vbuf[(a - a_lo) * kMaxWidth + (b - b_lo)][t] = v;
-                }
-                if (v < kINF) Bv = mn(Bv, v + fx(S.ml_intern + au_pen(S, t), s));
-            }
-            // phase 2: S2 (eq. 7), P_S, S1 and the strict retention test (eq. 6)
-            int64_t s2 = kINF;
-            for (int eb = ib0 + lane; eb < ib1; eb += 64) {
-                const int bp = I.in_src[eb];
-                if (I.layer[bp] > p) s2 = mn(s2, I.S2[cell_of(I, a, bp)] + I.in_U[eb] + I.mlbase_fx);
-            }
-            const int64_t arow = I.rowoff[a] - I.off[p + 1];
-            for (int k = lane; k < committed; k += 64) {
-                const int c = I.cc[cbase + k] & 0x7fffffff;
-                s2 = mn(s2, I.S1[arow + c] + I.cB[cbase + k]);
-            }
-            s2 = norm_inf(wave_min(s2));
-            int64_t ps = s2;
-            if (lane < 4) {
-                const int ap = I.out_dst[a * 4 + lane];
-                if (ap >= 0 && I.layer[ap] < q)
-                    ps = mn(ps, I.S1[cell_of(I, ap, b)] + I.out_U[a * 4 + lane] + I.mlbase_fx);
-            }
-            for (int eb = ib0 + lane; eb < ib1; eb += 64) {
-                const int bp = I.in_src[eb];
-                if (I.layer[bp] > p) ps = mn(ps, I.S1[cell_of(I, a, bp)] + I.in_U[eb] + I.mlbase_fx);
-            }
-            ps = norm_inf(wave_min(ps));
-            ctr.visits += (unsigned long long)committed;
-            if (lane == 0) {
-                I.Bt[cell] = Bv;
-                I.S2[cell] = s2;
-                I.S1[cell] = mn(Bv, ps);
-            }
+        int64_t s2 = kINF;
+        for (int eb = ib0 + lane; eb < ib1; eb += 64) {
+            const int bp = I.in_src[eb];
+            if (I.layer[bp] > p) s2 = mn(s2, I.S2[cell_of(I, a, bp)] + I.in_U[eb] + I.mlbase_fx);
+        }
+        const int64_t arow = I.rowoff[a] - I.off[p + 1];
+        for (int k = lane; k < committed; k += 64) {
+            const int c = I.cc[cbase + k] & 0x7fffffff;
+            s2 = mn(s2, I.S1[arow + c] + I.cB[cbase + k]);
+        }
+        s2 = norm_inf(wave_min(s2));
+        int64_t ps = s2;
+        if (lane < 4) {
+            const int ap = I.out_dst[a * 4 + lane];
+            if (ap >= 0 && I.layer[ap] < q)
+                ps = mn(ps, I.S1[cell_of(I, ap, b)] + I.out_U[a * 4 + lane] + I.mlbase_fx);
+        }
+        for (int eb = ib0 + lane; eb < ib1; eb += 64) {
+            const int bp = I.in_src[eb];
+            if (I.layer[bp] > p) ps = mn(ps, I.S1[cell_of(I, a, bp)] + I.in_U[eb] + I.mlbase_fx);
+        }
+        ps = norm_inf(wave_min(ps));
+        if (lane == 0) {
+            I.Bt[cell] = Bv;
+            I.S2[cell] = s2;
+            I.S1[cell] = mn(Bv, ps);
             const bool strict = Bv < ps;
-            const bool keep = I.retain_all ? (Bv < kINF) : strict;
-            ctr.feasible += Bv < kINF;
-            if (keep) {
+            G.keep[ci] = I.retain_all ? (Bv < kINF ? (strict ? 1 : 2) : 0) : (strict ? 1 : 0);
+            G.cellB[ci] = Bv;
+        }
+        ctr.visits += (unsigned long long)committed;
+        ctr.feasible += Bv < kINF;
+    }
+    __syncthreads();
+    // appends in start-state order per right endpoint (this group owns C_b in this step)
+    if (tid == 0) {
+        for (int ib = 0; ib < wb; ib++) {
+            const int b = b_lo + ib;
+            const int committed = I.ccnt[b];
+            int added = 0;
+            for (int ia = 0; ia < wa; ia++) {
+                const int ci = ia * wb + ib;
+                if (!G.keep[ci]) continue;
                 const int slot = committed + added;
                 if (slot < I.ccap[b]) {
-                    if (lane == 0) {
-                        I.cc[cbase + slot] = a | (strict ? 0 : (int)0x80000000);
-                        I.cB[cbase + slot] = Bv;
-                    }
-                } else if (lane == 0) {
+                    I.cc[I.coff[b] + slot] = (a_lo + ia) | (G.keep[ci] == 1 ? 0 : (int)0x80000000);
+                    I.cB[I.coff[b] + slot] = G.cellB[ci];
+                } else {
                     atomicMin(&I.stats[2], (unsigned long long)g);
                 }
                 added++;
-                ctr.appends++;
             }
+            if (added) I.ccnt[b] = min(committed + added, I.ccap[b]);
+            ctr.appends += added;
         }
-        if (lane == 0 && added) I.ccnt[b] = min(committed + added, I.ccap[b]);
     }
     // producers for later two-loops: IDL (per left inner state), JDL (per right inner state),
     // LM (layer-pair minimum of the both-separable form)
     if (g >= 5) {
-        __builtin_amdgcn_wave_barrier();
-        __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
-        const int wa = a_hi - a_lo, wb = b_hi - b_lo;
         int64_t lm0 = kINF, lm1 = kINF;
-        for (int k = lane; k < wa * 12; k += 64) {
-            const int ia = k / 12, X = (k >> 2) % 3, xk = k & 3, c = a_lo + ia;
+        for (int k = tid; k < wa * 12 + wb * 12; k += blockDim.x) {
+            const bool left = k < wa * 12;
+            const int kk = left ? k : k - wa * 12;
+            const int i = kk / 12, X = (kk >> 2) % 3, xx = kk & 3;
             int64_t acc = kINF;
-            for (int ib = 0; ib < wb; ib++) {
-                const int d = b_lo + ib;
+            const int nother = left ? wb : wa;
+            for (int o = 0; o < nother; o++) {
+                const int ci = left ? i * wb + o : o * wb + i;
+                const int other = left ? b_lo + o : a_lo + o;
                 for (int tp = 0; tp < 6; tp++) {
-                    const int64_t vin = vbuf[ia * kMaxWidth + ib][tp];
+                    const int64_t vin = G.vbuf[ci][tp];
                     if (vin >= kINF) continue;
-                    for (int xl = 0; xl < 4; xl++) {
-                        const int64_t al = I.alphaU[d * 4 + xl];
-                        if (al < kINF) acc = mn(acc, vin + al + fx(mmx(S, X, kRev[tp], xl, xk), s));
+                    for (int z = 0; z < 4; z++) {
+                        // left: vary x_{l+1} = z with alpha(d); right: vary x_{k-1} = z with beta(c)
+                        const int64_t w = left ? I.alphaU[other * 4 + z] : I.betaU[other * 4 + z];
+                        if (w < kINF)
+                            acc = mn(acc, vin + w + fx(left ? mmx(S, X, kRev[tp], z, xx) : mmx(S, X, kRev[tp], xx, z), s));
                     }
                 }
             }
             acc = norm_inf(acc);
-            I.IDL[ring_idx(c, g, X, xk)] = acc;
-            const int64_t be = I.betaU[c * 4 + xk];
-            if (acc < kINF && be < kINF) {
-                if (X == 0) lm0 = mn(lm0, acc + be);
-                if (X == 1) lm1 = mn(lm1, acc + be);
-            }
-        }
-        for (int k = lane; k < wb * 12; k += 64) {
-            const int ib = k / 12, X = (k >> 2) % 3, xl = k & 3, d = b_lo + ib;
-            int64_t acc = kINF;
-            for (int ia = 0; ia < wa; ia++) {
-                const int c = a_lo + ia;
-                for (int tp = 0; tp < 6; tp++) {
-                    const int64_t vin = vbuf[ia * kMaxWidth + ib][tp];
-                    if (vin >= kINF) continue;
-                    for (int xk = 0; xk < 4; xk++) {
-                        const int64_t be = I.betaU[c * 4 + xk];
-                        if (be < kINF) acc = mn(acc, vin + be + fx(mmx(S, X, kRev[tp], xl, xk), s));
-                    }
+            if (left) {
+                const int c = a_lo + i;
+                I.IDL[ring_idx(c, g, X, xx)] = acc;
+                const int64_t be = I.betaU[c * 4 + xx];
+                if (acc < kINF && be < kINF) {
+                    if (X == 0) lm0 = mn(lm0, acc + be);
+                    if (X == 1) lm1 = mn(lm1, acc + be);
                 }
+            } else {
+                I.JDL[ring_idx(b_lo + i, g, X, xx)] = acc;
             }
-            I.JDL[ring_idx(d, g, X, xl)] = norm_inf(acc);
         }
         lm0 = wave_min(lm0);
         lm1 = wave_min(lm1);
+        __syncthreads();
         if (lane == 0) {
-            int64_t* dst = I.LM + ((size_t)(g & (kLMRing - 1)) * (n + 1) + p) * 2;
-            dst[0] = norm_inf(lm0);
-            dst[1] = norm_inf(lm1);
+            G.red[wave][0] = lm0;
+            G.red[wave][1] = lm1;
+        }
+        __syncthreads();
+        if (tid == 0) {
+            I.LM[lm_idx(p, g, 0)] = norm_inf(mn(mn(G.red[0][0], G.red[1][0]), mn(G.red[2][0], G.red[3][0])));
+            I.LM[lm_idx(p, g, 1)] = norm_inf(mn(mn(G.red[0][1], G.red[1][1]), mn(G.red[2][1], G.red[3][1])));
         }
     }
     return ctr;
@@ -579,24 +660,23 @@ __device__ __forceinline__ void flush_counters(const Inst& I, const GroupCounter
     if (c.feasible) atomicAdd(&I.stats[3], c.feasible);
 }
 
-// ---- the span step (plain mode) ---------------------------------------------------------------
+// ---- the span step (plain mode): block x < layer pairs handles layer pair (x, x + g) -------------
 __global__ __launch_bounds__(256) void k_span(Inst I, const EnergyTables* __restrict__ E,
                                               const int32_t* __restrict__ spec, int g,
                                               int ext_layer, int nblk_cells) {
     __shared__ SmallE S;
     __shared__ int64_t red[256];
-    __shared__ int64_t vbuf[4][kMaxWidth * kMaxWidth][6];
-    __shared__ int64_t obuf[4][24];
+    __shared__ GroupShared G;
     stage_tables(S, E);
     __syncthreads();
     if ((int)blockIdx.x >= nblk_cells) {
         if (ext_layer >= 0) ext_column(I, S, ext_layer, red);
         return;
     }
-    const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
-    const int p = blockIdx.x * 4 + wave, q = p + g;
-    if (q > I.n) return;
-    GroupCounters c = span_group(I, S, E, spec, p, q, lane, vbuf[wave], obuf[wave]);
+    const int p = blockIdx.x, q = p + g;
+    GroupCounters c = span_group(I, S, E, spec, p, q, G);
+    // block-sum the counters (each wave counted its own cells; thread 0 counted appends)
+    const int lane = threadIdx.x & 63;
     flush_counters(I, c, g, lane);
 }
 
@@ -614,7 +694,7 @@ __global__ void k_init(Inst I) {
         I.ccnt[i] = 0;
         I.X[i] = (i == I.N - 1) ? 0 : kINF;
     }
-    for (size_t i = tid; i < (size_t)kLMRing * (I.n + 1) * 2; i += nt) I.LM[i] = kINF;
+    for (size_t i = tid; i < (size_t)(I.n + 1) * 2 * kLMRing; i += nt) I.LM[i] = kINF;
     for (size_t i = tid; i < (size_t)I.N * kLMRing * 12; i += nt) {
         I.IDL[i] = kINF;
         I.JDL[i] = kINF;
@@ -684,7 +764,7 @@ hipError_t launch_init(const Inst& I, hipStream_t st) {
 hipError_t launch_span(const Inst& I, const EnergyTables* E, const int32_t* spec, int g,
                        int ext_layer, hipStream_t st) {
     const int layers = I.n - g + 1;
-    const int nblk = layers > 0 ? (layers + 3) / 4 : 0;
+    const int nblk = layers > 0 ? layers : 0;
     const int total = nblk + (ext_layer >= 0 ? 1 : 0);
     if (total == 0) return hipSuccess;
     hipLaunchKernelGGL(k_span, dim3(total), dim3(256), 0, st, I, E, spec, g, ext_layer, nblk);
