@@ -165,6 +165,7 @@ extern "C" void sd_context_destroy(sd_context* c) {
     hipSetDevice(c->device);
     if (c->stream) hipStreamSynchronize(c->stream);
     if (c->arena) hipFree(c->arena);
+    if (c->staging) hipHostFree(c->staging);
     if (c->E_dev) hipFree(c->E_dev);
     if (c->spec_dev) hipFree(c->spec_dev);
     if (c->ev0) hipEventDestroy(c->ev0);
@@ -207,98 +208,137 @@ sd_status ensure_arena(sd_context* c, size_t bytes) {
     return SD_OK;
 }
 
-// Lay out one instance's device arrays in [base, base + size) and fill the pointers of I.
-size_t layout_instance(const Lattice& L, char* base, Inst& I, bool place) {
-    size_t off = 0;
-    auto take = [&](size_t bytes) -> char* {
-        off = (off + 255) & ~(size_t)255;
-        char* p = base ? base + off : nullptr;
-        off += bytes;
+// Device layout of one instance: region A holds the read-only inputs and the small mutable
+// arrays (uploaded from one staged host image), region B the O(N^2) tables and the rings.
+// With null bases only the sizes are computed.
+InstLayout layout_instance(const Lattice& L, char* A, char* B, Inst& I) {
+    uintptr_t oa = 0, ob = 0;
+    auto ta = [&](size_t bytes) -> char* {
+        oa = (oa + 255) & ~(uintptr_t)255;
+        char* p = (char*)((uintptr_t)A + oa);
+        oa += bytes;
+        return p;
+    };
+    auto tb = [&](size_t bytes) -> char* {
+        ob = (ob + 255) & ~(uintptr_t)255;
+        char* p = (char*)((uintptr_t)B + ob);
+        ob += bytes;
         return p;
     };
     const size_t N = L.N, n = L.n, nE = L.in_src.size(), cells = L.cells, slots = L.cand_slots;
-    I.layer = (int*)take(N * 4);
-    I.off = (int*)take((n + 2) * 4);
-    I.out_dst = (int*)take(4 * N * 4);
-    I.out_U = (int64_t*)take(4 * N * 8);
-    I.in_start = (int*)take((N + 1) * 4);
-    I.in_src = (int*)take(nE * 4);
-    I.in_lab = (int*)take(nE * 4);
-    I.in_U = (int64_t*)take(nE * 8);
-    I.tail = (int64_t*)take(N * 8);
-    I.pfx = (int*)take(N * 4);
-    I.P = (int64_t*)take((L.A + 1) * 8);
-    I.hp_init = (int*)take((n + 1) * 4);
-    I.rowoff = (int64_t*)take(N * 8);
-    I.coff = (int64_t*)take(N * 8);
-    I.ccap = (int*)take(N * 4);
-    I.ccnt = (int*)take(N * 4);
-    I.X = (int64_t*)take(N * 8);
-    I.stats = (unsigned long long*)take(4 * 8);
-    I.span_appends = (unsigned long long*)take((n + 1) * 8);
-    I.alphaU = (int64_t*)take(4 * N * 8);
-    I.betaU = (int64_t*)take(4 * N * 8);
-    I.LM = (int64_t*)take((size_t)kLMRing * (n + 1) * 2 * 8);
-    I.IDL = (int64_t*)take((size_t)N * kLMRing * 12 * 8);
-    I.JDL = (int64_t*)take((size_t)N * kLMRing * 12 * 8);
-    I.fwd_off = (int*)take(L.fwd_off.size() * 4);
-    I.fwd_meta = (int*)take(L.fwd_meta.size() * 4);
-    I.fwd_cost = (int64_t*)take(L.fwd_cost.size() * 8);
-    I.bwd_off = (int*)take(L.bwd_off.size() * 4);
-    I.bwd_meta = (int*)take(L.bwd_meta.size() * 4);
-    I.bwd_cost = (int64_t*)take(L.bwd_cost.size() * 8);
-    I.V = (int64_t*)take(cells * 6 * 8);
-    I.Bt = (int64_t*)take(cells * 8);
-    I.S1 = (int64_t*)take(cells * 8);
-    I.S2 = (int64_t*)take(cells * 8);
-    I.cc = (int*)take(slots * 4);
-    I.cB = (int64_t*)take(slots * 8);
-    off = (off + 255) & ~(size_t)255;
-    (void)place;
+    I.layer = (int*)ta(N * 4);
+    I.off = (int*)ta((n + 2) * 4);
+    I.out_dst = (int*)ta(4 * N * 4);
+    I.out_U = (int64_t*)ta(4 * N * 8);
+    I.in_start = (int*)ta((N + 1) * 4);
+    I.in_src = (int*)ta(nE * 4);
+    I.in_lab = (int*)ta(nE * 4);
+    I.in_U = (int64_t*)ta(nE * 8);
+    I.tail = (int64_t*)ta(N * 8);
+    I.pfx = (int*)ta(N * 4);
+    I.P = (int64_t*)ta((L.A + 1) * 8);
+    I.hp_init = (int*)ta((n + 1) * 4);
+    I.rowoff = (int64_t*)ta(N * 8);
+    I.coff = (int64_t*)ta(N * 8);
+    I.ccap = (int*)ta(N * 4);
+    I.alphaU = (int64_t*)ta(4 * N * 8);
+    I.betaU = (int64_t*)ta(4 * N * 8);
+    I.fwd_off = (int*)ta(L.fwd_off.size() * 4);
+    I.fwd_meta = (int*)ta(L.fwd_meta.size() * 4);
+    I.fwd_cost = (int64_t*)ta(L.fwd_cost.size() * 8);
+    I.bwd_off = (int*)ta(L.bwd_off.size() * 4);
+    I.bwd_meta = (int*)ta(L.bwd_meta.size() * 4);
+    I.bwd_cost = (int64_t*)ta(L.bwd_cost.size() * 8);
+    I.hpB = (int64_t*)ta(L.hpB.size() * 8);
+    I.ccnt = (int*)ta(N * 4);
+    I.X = (int64_t*)ta(N * 8);
+    I.stats = (unsigned long long*)ta(4 * 8);
+    I.span_appends = (unsigned long long*)ta((n + 1) * 8);
+    I.LM = (int64_t*)tb((size_t)kLMRing * (n + 1) * 2 * 8);
+    I.IDL = (int64_t*)tb((size_t)N * kLMRing * 12 * 8);
+    I.JDL = (int64_t*)tb((size_t)N * kLMRing * 12 * 8);
+    I.BI = (int64_t*)tb((size_t)N * kLMRing * 8);
+    I.BJ = (int64_t*)tb((size_t)N * kLMRing * 8);
+    I.V = (int64_t*)tb(cells * 6 * 8);
+    I.Bt = (int64_t*)tb(cells * 8);
+    I.S1 = (int64_t*)tb(cells * 8);
+    I.S2 = (int64_t*)tb(cells * 8);
+    I.cc = (int*)tb(slots * 4);
+    I.cB = (int64_t*)tb(slots * 8);
     I.n = L.n;
     I.N = L.N;
     I.A = L.A;
     I.shift = L.shift;
     I.mlbase_fx = L.mlbase_fx;
-    return off;
+    I.retain_all = 0;
+    I.g0 = 1;
+    InstLayout r;
+    r.a_bytes = (oa + 255) & ~(uintptr_t)255;
+    r.b_bytes = (ob + 255) & ~(uintptr_t)255;
+    return r;
 }
 
-hipError_t upload_instance(const Lattice& L, const Inst& I, hipStream_t st) {
-    struct Cp {
-        void* d;
-        const void* h;
-        size_t bytes;
-    } cps[] = {
-        {(void*)I.layer, L.layer.data(), L.layer.size() * 4},
-        {(void*)I.off, L.off.data(), L.off.size() * 4},
-        {(void*)I.out_dst, L.out_dst.data(), L.out_dst.size() * 4},
-        {(void*)I.out_U, L.out_U.data(), L.out_U.size() * 8},
-        {(void*)I.in_start, L.in_start.data(), L.in_start.size() * 4},
-        {(void*)I.in_src, L.in_src.data(), L.in_src.size() * 4},
-        {(void*)I.in_lab, L.in_lab.data(), L.in_lab.size() * 4},
-        {(void*)I.in_U, L.in_U.data(), L.in_U.size() * 8},
-        {(void*)I.tail, L.tail.data(), L.tail.size() * 8},
-        {(void*)I.pfx, L.pfx.data(), L.pfx.size() * 4},
-        {(void*)I.P, L.P.data(), L.P.size() * 8},
-        {(void*)I.hp_init, L.hp_init.data(), L.hp_init.size() * 4},
-        {(void*)I.rowoff, L.rowoff.data(), L.rowoff.size() * 8},
-        {(void*)I.coff, L.coff.data(), L.coff.size() * 8},
-        {(void*)I.ccap, L.ccap.data(), L.ccap.size() * 4},
-        {(void*)I.alphaU, L.alphaU.data(), L.alphaU.size() * 8},
-        {(void*)I.betaU, L.betaU.data(), L.betaU.size() * 8},
-        {(void*)I.fwd_off, L.fwd_off.data(), L.fwd_off.size() * 4},
-        {(void*)I.fwd_meta, L.fwd_meta.data(), L.fwd_meta.size() * 4},
-        {(void*)I.fwd_cost, L.fwd_cost.data(), L.fwd_cost.size() * 8},
-        {(void*)I.bwd_off, L.bwd_off.data(), L.bwd_off.size() * 4},
-        {(void*)I.bwd_meta, L.bwd_meta.data(), L.bwd_meta.size() * 4},
-        {(void*)I.bwd_cost, L.bwd_cost.data(), L.bwd_cost.size() * 8},
+// Copy the inputs of one instance into the host image of region A (image base = device A base).
+void stage_inputs(const Lattice& L, const Inst& I, const char* devA, char* image) {
+    auto put = [&](const void* dptr, const void* h, size_t bytes) {
+        if (bytes) memcpy(image + ((const char*)dptr - devA), h, bytes);
     };
-    for (auto& c : cps) {
-        if (!c.bytes) continue;
-        hipError_t e = hipMemcpyAsync(c.d, c.h, c.bytes, hipMemcpyHostToDevice, st);
-        if (e != hipSuccess) return e;
+    put(I.layer, L.layer.data(), L.layer.size() * 4);
+    put(I.off, L.off.data(), L.off.size() * 4);
+    put(I.out_dst, L.out_dst.data(), L.out_dst.size() * 4);
+    put(I.out_U, L.out_U.data(), L.out_U.size() * 8);
+    put(I.in_start, L.in_start.data(), L.in_start.size() * 4);
+    put(I.in_src, L.in_src.data(), L.in_src.size() * 4);
+    put(I.in_lab, L.in_lab.data(), L.in_lab.size() * 4);
+    put(I.in_U, L.in_U.data(), L.in_U.size() * 8);
+    put(I.tail, L.tail.data(), L.tail.size() * 8);
+    put(I.pfx, L.pfx.data(), L.pfx.size() * 4);
+    put(I.P, L.P.data(), L.P.size() * 8);
+    put(I.hp_init, L.hp_init.data(), L.hp_init.size() * 4);
+    put(I.rowoff, L.rowoff.data(), L.rowoff.size() * 8);
+    put(I.coff, L.coff.data(), L.coff.size() * 8);
+    put(I.ccap, L.ccap.data(), L.ccap.size() * 4);
+    put(I.alphaU, L.alphaU.data(), L.alphaU.size() * 8);
+    put(I.betaU, L.betaU.data(), L.betaU.size() * 8);
+    put(I.fwd_off, L.fwd_off.data(), L.fwd_off.size() * 4);
+    put(I.fwd_meta, L.fwd_meta.data(), L.fwd_meta.size() * 4);
+    put(I.fwd_cost, L.fwd_cost.data(), L.fwd_cost.size() * 8);
+    put(I.bwd_off, L.bwd_off.data(), L.bwd_off.size() * 4);
+    put(I.bwd_meta, L.bwd_meta.data(), L.bwd_meta.size() * 4);
+    put(I.bwd_cost, L.bwd_cost.data(), L.bwd_cost.size() * 8);
+    put(I.hpB, L.hpB.data(), L.hpB.size() * 8);
+}
+
+sd_status ensure_staging(sd_context* c, size_t bytes) {
+    if (bytes <= c->staging_bytes) return SD_OK;
+    if (c->staging) hipHostFree(c->staging);
+    c->staging = nullptr;
+    c->staging_bytes = 0;
+    size_t want = bytes + bytes / 4;
+    hipError_t e = hipHostMalloc(&c->staging, want, hipHostMallocDefault);
+    if (e != hipSuccess) {
+        hipGetLastError();
+        return fail(SD_E_NOMEM, "pinned host allocation failed");
     }
-    return hipSuccess;
+    c->staging_bytes = want;
+    return SD_OK;
+}
+
+// Place one instance at the start of the arena and upload its inputs with one copy.
+sd_status place_and_upload(sd_context* c, const Lattice& L, Inst& I) {
+    InstLayout sz = layout_instance(L, nullptr, nullptr, I);
+    sd_status s = ensure_arena(c, sz.a_bytes + sz.b_bytes);
+    if (s) return s;
+    s = ensure_staging(c, sz.a_bytes);
+    if (s) return s;
+    char* A = (char*)c->arena;
+    layout_instance(L, A, A + sz.a_bytes, I);
+    hipError_t e = hipStreamSynchronize(c->stream);  // staging buffer may still feed a copy
+    if (e != hipSuccess) return hip_fail(e, "stream sync");
+    stage_inputs(L, I, A, (char*)c->staging);
+    e = hipMemcpyAsync(A, c->staging, sz.a_bytes, hipMemcpyHostToDevice, c->stream);
+    if (e != hipSuccess) return hip_fail(e, "input upload");
+    return SD_OK;
 }
 
 // Plain mode: one span-step launch per span length.  Returns the overflow span (0 if none).
@@ -340,6 +380,10 @@ sd_status run_plain(sd_context* c, const Lattice& L, Inst& I, int64_t* overflow_
     c->last_feasible = (int64_t)stats[3];
     return SD_OK;
 }
+
+sd_status design_plain(sd_context* c, const char* protein, const sd_codon_table* table,
+                       const sd_params* params, double lambda, sd_result* out, TraceTables* keep,
+                       Lattice* keepL);
 
 sd_status fetch_tables(sd_context* c, const Lattice& L, const Inst& I, TraceTables& T) {
     hipStream_t st = c->stream;
@@ -414,13 +458,9 @@ sd_status design_plain(sd_context* c, const char* protein, const sd_codon_table*
     Inst I;
     memset(&I, 0, sizeof(I));
     for (int attempt = 0; attempt < 2; attempt++) {
-        size_t bytes = layout_instance(L, nullptr, I, false);
-        s = ensure_arena(c, bytes);
+        s = place_and_upload(c, L, I);
         if (s) return s;
-        layout_instance(L, (char*)c->arena, I, true);
         I.retain_all = c->opt.retain_all;
-        he = upload_instance(L, I, c->stream);
-        if (he != hipSuccess) return hip_fail(he, "upload");
         int64_t ovf = 0;
         s = run_plain(c, L, I, &ovf);
         if (s) return s;
@@ -526,8 +566,222 @@ extern "C" void sd_result_free(sd_result* r) {
     r->structure = nullptr;
 }
 
+namespace sd {
+
+// Runs the batched persistent launch for lattices Ls (already validated) and returns the device
+// instance descriptors (in the arena) through Is.  *barrier_ok is false when the grid barrier
+// reported a wait beyond its spin limit (the caller then recomputes in plain mode).
+sd_status run_batch(sd_context* c, std::vector<Lattice>& Ls, std::vector<Inst>& Is, int grid,
+                    int threads, bool* barrier_ok, double* kernel_s) {
+    const int n = (int)Ls.size();
+    Is.assign(n, Inst{});
+    std::vector<InstLayout> lay(n);
+    size_t totA = 0, totB = 0;
+    for (int i = 0; i < n; i++) {
+        lay[i] = layout_instance(Ls[i], nullptr, nullptr, Is[i]);
+        totA += lay[i].a_bytes;
+        totB += lay[i].b_bytes;
+    }
+    const size_t inst_bytes = ((sizeof(Inst) * n + 255) / 256) * 256;
+    sd_status s = ensure_arena(c, totA + totB + inst_bytes + 256);
+    if (s) return s;
+    s = ensure_staging(c, totA);
+    if (s) return s;
+    hipError_t e = hipStreamSynchronize(c->stream);
+    if (e != hipSuccess) return hip_fail(e, "stream sync");
+    char* A = (char*)c->arena;
+    char* B = A + totA;
+    Inst* insts_dev = (Inst*)(B + totB);
+    BatchCtl* ctl = (BatchCtl*)((char*)insts_dev + inst_bytes);
+    size_t oa = 0, ob = 0;
+    for (int i = 0; i < n; i++) {
+        layout_instance(Ls[i], A + oa, B + ob, Is[i]);
+        Is[i].retain_all = c->opt.retain_all;
+        Is[i].g0 = 1;
+        stage_inputs(Ls[i], Is[i], A, (char*)c->staging);
+        oa += lay[i].a_bytes;
+        ob += lay[i].b_bytes;
+    }
+    e = hipMemcpyAsync(A, c->staging, totA, hipMemcpyHostToDevice, c->stream);
+    if (e == hipSuccess) e = hipMemcpyAsync(insts_dev, Is.data(), sizeof(Inst) * n, hipMemcpyHostToDevice, c->stream);
+    if (e != hipSuccess) return hip_fail(e, "batch upload");
+    int maxn = 0;
+    for (auto& L : Ls) maxn = std::max(maxn, L.n);
+    const unsigned spin_cap = 1u << 22;  // a few seconds of polling before the barrier gives up
+    // one captured graph: per-instance initialisation, then the persistent span wavefront
+    hipGraph_t graph = nullptr;
+    hipGraphExec_t exec = nullptr;
+    bool captured = false;
+    if (hipStreamBeginCapture(c->stream, hipStreamCaptureModeThreadLocal) == hipSuccess) {
+        hipError_t e1 = launch_batch_init(insts_dev, n, ctl, c->stream);
+        hipError_t e2 = e1 == hipSuccess ? launch_persistent(insts_dev, n, maxn + 1, (const EnergyTables*)c->E_dev,
+                                                             (const int32_t*)c->spec_dev, ctl, grid, threads, spin_cap, c->stream)
+                                         : e1;
+        hipError_t e3 = hipStreamEndCapture(c->stream, &graph);
+        if (e2 == hipSuccess && e3 == hipSuccess && graph &&
+            hipGraphInstantiate(&exec, graph, nullptr, nullptr, 0) == hipSuccess)
+            captured = true;
+    }
+    hipGetLastError();
+    e = hipEventRecord(c->ev0, c->stream);
+    if (captured) {
+        if (e == hipSuccess) e = hipGraphLaunch(exec, c->stream);
+    } else {
+        if (e == hipSuccess) e = launch_batch_init(insts_dev, n, ctl, c->stream);
+        if (e == hipSuccess)
+            e = launch_persistent(insts_dev, n, maxn + 1, (const EnergyTables*)c->E_dev, (const int32_t*)c->spec_dev,
+                                  ctl, grid, threads, spin_cap, c->stream);
+    }
+    if (e == hipSuccess) e = hipEventRecord(c->ev1, c->stream);
+    BatchCtl hctl;
+    if (e == hipSuccess) e = hipMemcpyAsync(&hctl, ctl, sizeof(hctl), hipMemcpyDeviceToHost, c->stream);
+    if (e == hipSuccess) e = hipStreamSynchronize(c->stream);
+    float ms = 0.f;
+    if (e == hipSuccess) e = hipEventElapsedTime(&ms, c->ev0, c->ev1);
+    if (exec) hipGraphExecDestroy(exec);
+    if (graph) hipGraphDestroy(graph);
+    if (e != hipSuccess) return hip_fail(e, "batched wavefront");
+    c->last_graph = captured;
+    *kernel_s = ms * 1e-3;
+    *barrier_ok = hctl.err == 0 && hctl.steps_done == maxn + 1;  // nsteps = maxn + 1
+    return SD_OK;
+}
+
+// Schedule of the persistent launch: threads per block (one wave per layer-pair item, or four
+// waves sharing an item) and resident blocks per CU.  The first batched call on a context times a
+// probe batch with each candidate and keeps the fastest (the probe's results are discarded).
+sd_status tuned_schedule(sd_context* c, const sd_codon_table* table, const sd_params* params, int* grid,
+                         int* threads) {
+    if (c->batch_grid > 0) {
+        *grid = c->batch_grid;
+        *threads = c->batch_threads;
+        return SD_OK;
+    }
+    static const char* aa = "ACDEFGHIKLMNPQRSTVWY";
+    uint64_t st = 0x9E3779B97F4A7C15ull;
+    std::vector<Lattice> Ls(24);
+    std::string err;
+    for (int i = 0; i < 24; i++) {
+        st = st * 6364136223846793005ull + 1442695040888963407ull;
+        int len = 60 + (int)((st >> 33) % 91);
+        std::string p = "M";
+        for (int k = 1; k < len - 1; k++) {
+            st = st * 6364136223846793005ull + 1442695040888963407ull;
+            p += aa[(st >> 33) % 20];
+        }
+        p += "*";
+        int rc = build_lattice(p.c_str(), table->t, params->p, (i & 1) ? 4.0 : 0.0, 0, Ls[i], err);
+        if (rc) return fail((sd_status)rc, err);
+    }
+    double best_t = 1e30;
+    for (int threads_c : {256, 64}) {
+        int per_cu = 0;
+        hipError_t e = persistent_occupancy(threads_c, &per_cu);
+        if (e != hipSuccess || per_cu <= 0) return hip_fail(e, "occupancy query");
+        std::vector<int> cands = {per_cu};
+        if (per_cu > 1) cands.push_back(per_cu / 2);
+        for (int k : cands) {
+            const int gr = k * c->num_cu;
+            std::vector<Inst> Is;
+            bool ok = false;
+            double ks = 0;
+            sd_status s = run_batch(c, Ls, Is, gr, threads_c, &ok, &ks);
+            if (s) return s;
+            if (ok && ks < best_t) {
+                best_t = ks;
+                c->batch_grid = gr;
+                c->batch_threads = threads_c;
+            }
+        }
+    }
+    if (c->batch_grid <= 0) return fail(SD_E_DEVICE, "no persistent schedule completed its grid barriers");
+    *grid = c->batch_grid;
+    *threads = c->batch_threads;
+    return SD_OK;
+}
+
+}  // namespace sd
+
 extern "C" sd_status sd_design_batch(sd_context* ctx, int n, const char* const* proteins,
                                      const double* lambdas, const sd_codon_table* table,
                                      const sd_params* params, sd_result* outs) {
-    return design_batch_impl(ctx, n, proteins, lambdas, table, params, outs);
+    try {
+        if (!ctx || !table || !params || n < 0 || (n > 0 && (!proteins || !lambdas || !outs)))
+            return fail(SD_E_ARG, "null argument");
+        hipError_t he = hipSetDevice(ctx->device);
+        if (he != hipSuccess) return hip_fail(he, "hipSetDevice");
+        int done = 0;
+        while (done < n) {
+            const int m = std::min(n - done, kMaxBatch);
+            const double t0 = now_s();
+            std::vector<Lattice> Ls(m);
+            std::string err;
+            for (int i = 0; i < m; i++) {
+                int rc = build_lattice(proteins[done + i], table->t, params->p, lambdas[done + i],
+                                       ctx->opt.capacity_override, Ls[i], err);
+                if (rc) {
+                    for (int j = 0; j < done; j++) sd_result_free(&outs[j]);
+                    return fail((sd_status)rc, "batch member " + std::to_string(done + i) + ": " + err);
+                }
+            }
+            sd_status s = ensure_params(ctx, params);
+            int grid = 0, threads = 256;
+            if (!s) s = tuned_schedule(ctx, table, params, &grid, &threads);
+            const double tf0 = now_s();
+            std::vector<Inst> Is;
+            bool ok = false;
+            double ks = 0;
+            if (!s) s = run_batch(ctx, Ls, Is, grid, threads, &ok, &ks);
+            const double tf1 = now_s();
+            if (s) {
+                for (int j = 0; j < done; j++) sd_result_free(&outs[j]);
+                return s;
+            }
+            ctx->last_batch_kernel_s = ks;
+            ctx->last_batch_fill_s = tf1 - tf0;
+            for (int i = 0; i < m && s == SD_OK; i++) {
+                const int gi = done + i;
+                unsigned long long st[4];
+                hipError_t e = hipMemcpy(st, Is[i].stats, sizeof(st), hipMemcpyDeviceToHost);
+                if (e != hipSuccess) {
+                    s = hip_fail(e, "batch stats");
+                    break;
+                }
+                if (!ok || st[2] != ~0ull) {
+                    // barrier failure or candidate overflow: exact recomputation in plain mode
+                    s = design_plain(ctx, proteins[gi], table, params, lambdas[gi], &outs[gi], nullptr, nullptr);
+                    ctx->last_batch_fallbacks++;
+                    continue;
+                }
+                TraceTables T;
+                s = fetch_tables(ctx, Ls[i], Is[i], T);
+                if (s) break;
+                TraceResult R;
+                int rc = trace_design(Ls[i], params->p, T, R);
+                if (rc) {
+                    s = fail((sd_status)rc, "traceback self-check failed");
+                    break;
+                }
+                int64_t Z = 0;
+                for (int v = 0; v < Ls[i].N; v++)
+                    for (int k = 0; k < T.ccnt[v]; k++) Z += T.cc[Ls[i].coff[v] + k] >= 0;
+                s = fill_result(Ls[i], R, T.X[0], Z, (int64_t)st[0], (int64_t)st[3], &outs[gi]);
+                if (s) break;
+                outs[gi].t_fill_s = (tf1 - tf0) / m;
+                outs[gi].t_total_s = now_s() - t0;
+                outs[gi].t_span_kernels_s = ks / m;
+                outs[gi].n_span_launches = 0;
+            }
+            if (s) {
+                for (int j = 0; j < done + m; j++) sd_result_free(&outs[j]);
+                return s;
+            }
+            done += m;
+        }
+        return SD_OK;
+    } catch (const std::bad_alloc&) {
+        return fail(SD_E_NOMEM, "host allocation");
+    } catch (...) {
+        return fail(SD_E_INTERNAL, "unexpected exception");
+    }
 }

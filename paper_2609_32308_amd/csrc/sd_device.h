@@ -16,6 +16,13 @@ struct sd_context {
     hipEvent_t ev0 = nullptr, ev1 = nullptr;
     void* arena = nullptr;
     size_t arena_bytes = 0;
+    void* staging = nullptr;  // pinned host image of the input region
+    size_t staging_bytes = 0;
+    int batch_grid = 0;       // autotuned persistent grid size (0: not tuned yet)
+    int batch_threads = 256;  // autotuned threads per block of the persistent launch
+    bool last_graph = false;  // last batch ran as a captured graph
+    double last_batch_kernel_s = 0.0, last_batch_fill_s = 0.0;
+    int64_t last_batch_fallbacks = 0;
     void* E_dev = nullptr;     // EnergyTables
     void* spec_dev = nullptr;  // special hairpin table
     uint64_t params_uid = 0;
@@ -26,13 +33,23 @@ struct sd_context {
 };
 
 namespace sd {
+struct InstLayout {
+    size_t a_bytes, b_bytes;
+};
+struct Lattice;
+struct Params;
+InstLayout layout_instance(const Lattice& L, char* A, char* B, Inst& I);
+void stage_inputs(const Lattice& L, const Inst& I, const char* devA, char* image);
 hipError_t upload_pair_order();
 hipError_t launch_init(const Inst& I, hipStream_t st);
 hipError_t launch_span(const Inst& I, const EnergyTables* E, const int32_t* spec, int g,
                        int ext_layer, hipStream_t st);
 hipError_t launch_ext(const Inst& I, const EnergyTables* E, int L, hipStream_t st);
+hipError_t launch_batch_init(const Inst* insts_dev, int ninst, BatchCtl* ctl, hipStream_t st);
+hipError_t persistent_occupancy(int threads, int* blocks_per_cu);
+hipError_t launch_persistent(const Inst* insts_dev, int ninst, int nsteps, const EnergyTables* E,
+                             const int32_t* spec, BatchCtl* ctl, int grid, int threads, unsigned spin_cap,
+                             hipStream_t st);
 }  // namespace sd
 
-sd_status design_batch_impl(sd_context* ctx, int n, const char* const* proteins,
-                            const double* lambdas, const sd_codon_table* table,
-                            const sd_params* params, sd_result* outs);
+

@@ -71,9 +71,26 @@ struct Inst {
     // meta = other_end << 4 | first_label << 2 | last_label, cost = sum of edge costs
     const int *fwd_off, *fwd_meta, *bwd_off, *bwd_meta;
     const int64_t *fwd_cost, *bwd_cost;
+    // generic hairpins: HB[b*16 + y*4 + z] = min over b2 -z-> b1 -y-> b of U(b2->b1) + U(b1->b)
+    const int64_t *hpB;
+    // bulges of >= 3 bases, per state and span (span innermost):
+    //   BI[c][g] = min over d at layer(c)+g, type t' of V_t'(c,d) + tail(d) + AU(t')
+    //   BJ[d][g] = min over c at layer(d)-g, type t' of V_t'(c,d) + AU(t')
+    int64_t *BI, *BJ;
     int retain_all;
+    int g0;  // persistent launches: first span this launch processes for the instance
 };
 
 constexpr int kLMRing = 64;  // > 32 spans of two-loop reach
+static_assert(sizeof(Inst) % 8 == 0, "instance descriptors are copied as 8-byte words");
+
+// Batched persistent launch: barrier state shared by all workgroups.
+struct BatchCtl {
+    unsigned int count;  // arrivals at the current barrier
+    unsigned int gen;    // barrier generation
+    int err;             // set when a barrier wait exceeds its spin limit (every group then exits)
+    int steps_done;      // spans completed (diagnostics)
+};
+constexpr int kMaxBatch = 1024;  // instances per persistent launch
 
 }  // namespace sd

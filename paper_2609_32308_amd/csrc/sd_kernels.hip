@@ -36,9 +36,9 @@ __constant__ unsigned char kL2[kNumPairs];
 // Two-loop (l1, l2) pairs by category for each phase (p mod 3, q mod 3), each list sorted by
 // l1 + l2 so that the pairs allowed at span g (l1 + l2 <= g - 7) form a prefix.  Entries:
 // l1 | l2 << 5 | side << 10 (side 1: left side separable).  Counts: kCnt[list][phase][cap].
-enum { kListBulge = 0, kListOne = 1, kListLab = 2, kListFast = 3 };
-__constant__ unsigned short kPairList[4][9][kNumPairs];
-__constant__ unsigned short kPairCnt[4][9][31];
+enum { kListBulge = 0, kListOne = 1, kListLab = 2, kListFast = 3, kListBulgeSep = 4 };
+__constant__ unsigned short kPairList[5][9][kNumPairs];
+__constant__ unsigned short kPairCnt[5][9][31];
 
 // Loop tables staged in LDS (the 1x2 and 2x2 full-loop tables stay in global memory; they are
 // read for 3 of the 496 (l1, l2) pairs only).
@@ -188,21 +188,15 @@ __device__ int64_t hairpin_lane(const Inst& I, const SmallE& S, const int32_t* _
         }
         return best;
     }
-    // generic size: a -x-> a1 -x2-> a2 ~~> b2 -z-> b1 -y-> b
-    const int ib0 = I.in_start[b], nb = I.in_start[b + 1] - ib0;
-    for (int k = lane; k < 4 * 8 * 8; k += 64) {
-        const int x2 = k & 3, i1 = (k >> 2) & 7, i2 = k >> 5;
-        if (i1 >= nb) continue;
-        const int eb = ib0 + i1;
-        if (I.in_lab[eb] != y) continue;
-        const int b1 = I.in_src[eb], j0 = I.in_start[b1];
-        if (i2 >= I.in_start[b1 + 1] - j0) continue;
-        const int eb2 = j0 + i2, e1 = a1 * 4 + x2, a2 = I.out_dst[e1];
-        if (a2 < 0) continue;
-        const int64_t gg = gap(I, a2, I.in_src[eb2]);
-        if (gg >= kINF) continue;
-        const int32_t en = I.hp_init[m] + S.mmH[t][x2][I.in_lab[eb2]];
-        best = mn(best, Ua + I.out_U[e1] + gg + I.in_U[eb2] + I.in_U[eb] + fx(en, s));
+    // generic size m >= 5: a -x-> a1 -x2-> a2 ~~> b2 -z-> b1 -y-> b.  a2 and b2 are >= 3 layers
+    // apart, so the gap is tail(a2) + whole codons and the minimum separates into
+    // alpha(a1, x2) + mmH[t][x2][z] + HB(b, y, z) plus layer constants.
+    if (lane < 16) {
+        const int x2 = lane >> 2, z = lane & 3;
+        const int64_t al = I.alphaU[a1 * 4 + x2], hb = I.hpB[b * 16 + y * 4 + z];
+        if (al < kINF && hb < kINF)
+            best = Ua + al + hb + I.P[(la + g - 2) / 3] - I.P[(la + 2) / 3 + 1] +
+                   fx(I.hp_init[m] + S.mmH[t][x2][z], s);
     }
     return best;
 }
@@ -411,6 +405,20 @@ __device__ int64_t closed_value(const Inst& I, const SmallE& S, const EnergyTabl
                 const int code = kPairList[kListBulge][0][k], l1 = code & 31, l2 = (code >> 5) & 31;
                 v = mn(v, bulge_pair(I, S, t, a1, b1, Uab, l1, l2, p + 1 + l1, q - 1 - l2));
             }
+            // bulges of >= 3 bases: the unpaired side costs its gap (tail + whole codons)
+            for (int k = lane; k < kPairCnt[kListBulgeSep][0][cap]; k += 64) {
+                const int code = kPairList[kListBulgeSep][0][k], l1 = code & 31, l2 = (code >> 5) & 31;
+                const int l = l1 + l2, cl = p + 1 + l1, dl = q - 1 - l2;
+                int64_t w;
+                if (l1 == 0) {
+                    const int64_t bi = I.BI[(int64_t)a1 * kLMRing + ((dl - cl) & (kLMRing - 1))];
+                    w = bi >= kINF ? kINF : Uab + bi + I.P[(q - 1) / 3] - I.P[dl / 3 + 1];
+                } else {
+                    const int64_t bj = I.BJ[(int64_t)b1 * kLMRing + ((dl - cl) & (kLMRing - 1))];
+                    w = bj >= kINF ? kINF : Uab + bj + I.tail[a1] + I.P[cl / 3] - I.P[(p + 1) / 3 + 1];
+                }
+                if (w < kINF) v = mn(v, w + fx(S.bulge[l] + au_pen(S, t), s));
+            }
             for (int k = lane; k < kPairCnt[kListOne][ph][cap]; k += 64) {
                 const int code = kPairList[kListOne][ph][k], l1 = code & 31, l2 = (code >> 5) & 31;
                 const int cl = p + 1 + l1, dl = q - 1 - l2;
@@ -446,7 +454,7 @@ __device__ int64_t closed_value(const Inst& I, const SmallE& S, const EnergyTabl
 __device__ GroupCounters span_group(const Inst& I, const SmallE& S, const EnergyTables* __restrict__ E,
                                     const int32_t* __restrict__ spec, int p, int q, GroupShared& G) {
     const int g = q - p, s = I.shift;
-    const int tid = threadIdx.x, wave = tid >> 6, lane = tid & 63;
+    const int tid = threadIdx.x, wave = tid >> 6, lane = tid & 63, nw = blockDim.x >> 6;
     GroupCounters ctr{0, 0, 0};
     const int a_lo = I.off[p], a_hi = I.off[p + 1], b_lo = I.off[q], b_hi = I.off[q + 1];
     const int wa = a_hi - a_lo, wb = b_hi - b_lo, ncell = wa * wb;
@@ -483,11 +491,14 @@ __device__ GroupCounters span_group(const Inst& I, const SmallE& S, const Energy
     }
     __syncthreads();
     if (g >= 12) {
-        mini0 = mn(mn(G.red[0][0], G.red[1][0]), mn(G.red[2][0], G.red[3][0]));
-        mini1 = mn(mn(G.red[0][1], G.red[1][1]), mn(G.red[2][1], G.red[3][1]));
+        mini0 = mini1 = kINF;
+        for (int w = 0; w < nw; w++) {
+            mini0 = mn(mini0, G.red[w][0]);
+            mini1 = mn(mini1, G.red[w][1]);
+        }
     }
     // phase 1: typed closed values, (cell, type) jobs spread over the waves
-    for (int k = wave; k < G.ncombo; k += 4) {
+    for (int k = wave; k < G.ncombo; k += nw) {
         const int ci = G.combo[k] / 6, t = G.combo[k] % 6;
         const int a = a_lo + ci / wb, b = b_lo + ci % wb;
         const int64_t v = closed_value(I, S, E, spec, a, b, t, p, q, mini0, mini1, lane, G.obuf[wave], G.lab[wave]);
@@ -496,7 +507,7 @@ __device__ GroupCounters span_group(const Inst& I, const SmallE& S, const Energy
     __syncthreads();
     // phase 2: branch value (eq. 2), S2 (eq. 7), P_S, S1 and the retention test (eq. 6); one
     // cell per wave.  Every scan reads only entries committed by earlier spans.
-    for (int ci = wave; ci < ncell; ci += 4) {
+    for (int ci = wave; ci < ncell; ci += nw) {
         const int a = a_lo + ci / wb, b = b_lo + ci % wb;
         const int64_t cell = I.rowoff[a] + (b - I.off[p + 1]);
         int64_t Bv = kINF;
@@ -567,6 +578,28 @@ __device__ GroupCounters span_group(const Inst& I, const SmallE& S, const Energy
     // producers for later two-loops: IDL (per left inner state), JDL (per right inner state),
     // LM (layer-pair minimum of the both-separable form)
     if (g >= 5) {
+        // bulge rings
+        for (int k = tid; k < wa + wb; k += blockDim.x) {
+            int64_t acc = kINF;
+            if (k < wa) {
+                for (int ib = 0; ib < wb; ib++) {
+                    const int64_t td = I.tail[b_lo + ib];
+                    for (int tp = 0; tp < 6; tp++) {
+                        const int64_t vin = G.vbuf[k * wb + ib][tp];
+                        if (vin < kINF) acc = mn(acc, vin + td + fx(au_pen(S, tp), s));
+                    }
+                }
+                I.BI[(int64_t)(a_lo + k) * kLMRing + (g & (kLMRing - 1))] = norm_inf(acc);
+            } else {
+                const int ib = k - wa;
+                for (int ia = 0; ia < wa; ia++)
+                    for (int tp = 0; tp < 6; tp++) {
+                        const int64_t vin = G.vbuf[ia * wb + ib][tp];
+                        if (vin < kINF) acc = mn(acc, vin + fx(au_pen(S, tp), s));
+                    }
+                I.BJ[(int64_t)(b_lo + ib) * kLMRing + (g & (kLMRing - 1))] = norm_inf(acc);
+            }
+        }
         int64_t lm0 = kINF, lm1 = kINF;
         for (int k = tid; k < wa * 12 + wb * 12; k += blockDim.x) {
             const bool left = k < wa * 12;
@@ -610,8 +643,13 @@ __device__ GroupCounters span_group(const Inst& I, const SmallE& S, const Energy
         }
         __syncthreads();
         if (tid == 0) {
-            I.LM[lm_idx(p, g, 0)] = norm_inf(mn(mn(G.red[0][0], G.red[1][0]), mn(G.red[2][0], G.red[3][0])));
-            I.LM[lm_idx(p, g, 1)] = norm_inf(mn(mn(G.red[0][1], G.red[1][1]), mn(G.red[2][1], G.red[3][1])));
+            int64_t r0 = kINF, r1 = kINF;
+            for (int w = 0; w < nw; w++) {
+                r0 = mn(r0, G.red[w][0]);
+                r1 = mn(r1, G.red[w][1]);
+            }
+            I.LM[lm_idx(p, g, 0)] = norm_inf(r0);
+            I.LM[lm_idx(p, g, 1)] = norm_inf(r1);
         }
     }
     return ctr;
@@ -699,6 +737,131 @@ __global__ void k_init(Inst I) {
         I.IDL[i] = kINF;
         I.JDL[i] = kINF;
     }
+    for (size_t i = tid; i < (size_t)I.N * kLMRing; i += nt) {
+        I.BI[i] = kINF;
+        I.BJ[i] = kINF;
+    }
+    if (tid < 4) I.stats[tid] = tid == 2 ? ~0ull : 0ull;
+    if (I.span_appends)
+        for (int i = tid; i <= I.n; i += nt) I.span_appends[i] = 0;
+}
+
+// ---- batched persistent kernel ------------------------------------------------------------------
+// All instances advance one global span per grid barrier.  At step g the work items are the layer
+// pairs of span g of every instance with n >= g, followed (per instance) by the external column
+// of layer n - g + 1 (one layer behind).  Items are spread over the resident workgroups; the
+// barrier is an arrival counter plus a generation word with agent-scope release/acquire fences.
+__device__ bool grid_barrier(BatchCtl* ctl, unsigned nblocks, unsigned spin_cap, int* s_flag) {
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        __threadfence();
+        const unsigned g0 = __hip_atomic_load(&ctl->gen, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        const unsigned arrived =
+            __hip_atomic_fetch_add(&ctl->count, 1u, __ATOMIC_ACQ_REL, __HIP_MEMORY_SCOPE_AGENT) + 1u;
+        int err = 0;
+        if (arrived == nblocks) {
+            __hip_atomic_store(&ctl->count, 0u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+            __hip_atomic_fetch_add(&ctl->gen, 1u, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_AGENT);
+        } else {
+            unsigned spins = 0;
+            while (__hip_atomic_load(&ctl->gen, __ATOMIC_ACQUIRE, __HIP_MEMORY_SCOPE_AGENT) == g0) {
+                if (__hip_atomic_load(&ctl->err, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) || ++spins > spin_cap) {
+                    __hip_atomic_store(&ctl->err, 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+                    err = 1;
+                    break;
+                }
+                __builtin_amdgcn_s_sleep(2);
+            }
+        }
+        __threadfence();
+        *s_flag = err;
+    }
+    __syncthreads();
+    return *s_flag == 0;
+}
+
+template <int NT>
+__global__ __launch_bounds__(NT) void k_persistent(const Inst* __restrict__ insts, int ninst, int nsteps,
+                                                    const EnergyTables* __restrict__ E,
+                                                    const int32_t* __restrict__ spec, BatchCtl* ctl,
+                                                    unsigned spin_cap) {
+    __shared__ SmallE S;
+    __shared__ int64_t red[NT];
+    __shared__ GroupShared G;
+    __shared__ int pref[kMaxBatch + 1];
+    __shared__ int nl[kMaxBatch];
+    __shared__ int g0s[kMaxBatch];
+    __shared__ Inst sI;
+    __shared__ int s_flag;
+    stage_tables(S, E);
+    for (int i = threadIdx.x; i < ninst; i += blockDim.x) {
+        nl[i] = insts[i].n;
+        g0s[i] = insts[i].g0;
+    }
+    __syncthreads();
+    for (int step = 0; step < nsteps; step++) {
+        // work items per instance at its span g = g0 + step: layer pairs of span g, then one
+        // external column (layer n - g + 1, one layer behind)
+        if (threadIdx.x == 0) {
+            int acc = 0;
+            for (int i = 0; i < ninst; i++) {
+                pref[i] = acc;
+                const int n = nl[i], g = g0s[i] + step;
+                acc += (g <= n ? n - g + 1 : 0) + ((g >= 2 && g <= n + 1) ? 1 : 0);
+            }
+            pref[ninst] = acc;
+        }
+        __syncthreads();
+        const int total = pref[ninst];
+        for (int item = blockIdx.x; item < total; item += gridDim.x) {
+            int lo = 0, hi = ninst - 1;  // last instance whose prefix <= item
+            while (lo < hi) {
+                const int mid = (lo + hi + 1) >> 1;
+                if (pref[mid] <= item) lo = mid;
+                else hi = mid - 1;
+            }
+            const int inst = lo, local = item - pref[inst], g = g0s[inst] + step;
+            for (int k = threadIdx.x; k < (int)(sizeof(Inst) / 8); k += blockDim.x)
+                reinterpret_cast<uint64_t*>(&sI)[k] = reinterpret_cast<const uint64_t*>(&insts[inst])[k];
+            __syncthreads();
+            const int n = sI.n, ncell_items = g <= n ? n - g + 1 : 0;
+            if (local < ncell_items) {
+                GroupCounters c = span_group(sI, S, E, spec, local, local + g, G);
+                flush_counters(sI, c, g, threadIdx.x & 63);
+            } else {
+                ext_column(sI, S, n - g + 1, red);
+            }
+            __syncthreads();
+        }
+        if (!grid_barrier(ctl, gridDim.x, spin_cap, &s_flag)) return;
+        if (blockIdx.x == 0 && threadIdx.x == 0) ctl->steps_done = step + 1;
+    }
+}
+
+// Resets the barrier state and initialises every instance whose g0 is 1 (new instances).
+__global__ void k_batch_init(const Inst* __restrict__ insts, int ninst, BatchCtl* ctl) {
+    const Inst& I = insts[blockIdx.x];
+    const int tid = threadIdx.x, nt = blockDim.x;
+    if (blockIdx.x == 0 && tid == 0) {
+        ctl->count = 0;
+        ctl->gen = 0;
+        ctl->err = 0;
+        ctl->steps_done = 0;
+    }
+    if (I.g0 != 1) return;
+    for (int i = tid; i < I.N; i += nt) {
+        I.ccnt[i] = 0;
+        I.X[i] = (i == I.N - 1) ? 0 : kINF;
+    }
+    for (size_t i = tid; i < (size_t)(I.n + 1) * 2 * kLMRing; i += nt) I.LM[i] = kINF;
+    for (size_t i = tid; i < (size_t)I.N * kLMRing * 12; i += nt) {
+        I.IDL[i] = kINF;
+        I.JDL[i] = kINF;
+    }
+    for (size_t i = tid; i < (size_t)I.N * kLMRing; i += nt) {
+        I.BI[i] = kINF;
+        I.BJ[i] = kINF;
+    }
     if (tid < 4) I.stats[tid] = tid == 2 ? ~0ull : 0ull;
     if (I.span_appends)
         for (int i = tid; i <= I.n; i += nt) I.span_appends[i] = 0;
@@ -723,14 +886,14 @@ hipError_t upload_pair_order() {
     e = hipMemcpyToSymbol(HIP_SYMBOL(kL2), l2, sizeof(l2));
     if (e != hipSuccess) return e;
     // categorised pair lists per phase (p mod 3, q mod 3)
-    static unsigned short list[4][9][kNumPairs];
-    static unsigned short cnt[4][9][31];
+    static unsigned short list[5][9][kNumPairs];
+    static unsigned short cnt[5][9][31];
     memset(list, 0, sizeof(list));
     memset(cnt, 0, sizeof(cnt));
     for (int pm = 0; pm < 3; pm++)
         for (int qm = 0; qm < 3; qm++) {
             const int ph = pm * 3 + qm, p = 3 + pm, q = 300 + qm;  // representatives of the phases
-            int len[4] = {0, 0, 0, 0};
+            int len[5] = {0, 0, 0, 0, 0};
             for (int sum = 0; sum <= kMaxLoop; sum++) {
                 for (int a = 0; a <= sum; a++) {
                     const int b = sum - a;
@@ -738,7 +901,8 @@ hipError_t upload_pair_order() {
                     const bool sr = b >= 2 && (q - b) / 3 != (q - 2) / 3;
                     int lst;
                     unsigned short code = (unsigned short)(a | b << 5);
-                    if (a == 0 || b == 0) lst = kListBulge;
+                    if ((a == 0 || b == 0) && a + b >= 3) lst = kListBulgeSep;
+                    else if (a == 0 || b == 0) lst = kListBulge;
                     else if (sl && sr) lst = kListFast;
                     else if (!sl && !sr) lst = kListLab;
                     else {
@@ -747,7 +911,7 @@ hipError_t upload_pair_order() {
                     }
                     list[lst][ph][len[lst]++] = code;
                 }
-                for (int l = 0; l < 4; l++) cnt[l][ph][sum] = (unsigned short)len[l];
+                for (int l = 0; l < 5; l++) cnt[l][ph][sum] = (unsigned short)len[l];
             }
         }
     e = hipMemcpyToSymbol(HIP_SYMBOL(kPairList), list, sizeof(list));
@@ -768,6 +932,28 @@ hipError_t launch_span(const Inst& I, const EnergyTables* E, const int32_t* spec
     const int total = nblk + (ext_layer >= 0 ? 1 : 0);
     if (total == 0) return hipSuccess;
     hipLaunchKernelGGL(k_span, dim3(total), dim3(256), 0, st, I, E, spec, g, ext_layer, nblk);
+    return hipGetLastError();
+}
+
+hipError_t launch_batch_init(const Inst* insts_dev, int ninst, BatchCtl* ctl, hipStream_t st) {
+    if (ninst <= 0) return hipSuccess;
+    hipLaunchKernelGGL(k_batch_init, dim3(ninst), dim3(256), 0, st, insts_dev, ninst, ctl);
+    return hipGetLastError();
+}
+
+// threads per block: 64 (one wave per layer-pair item) or 256 (four waves share an item)
+hipError_t persistent_occupancy(int threads, int* blocks_per_cu) {
+    if (threads == 64) return hipOccupancyMaxActiveBlocksPerMultiprocessor(blocks_per_cu, k_persistent<64>, 64, 0);
+    return hipOccupancyMaxActiveBlocksPerMultiprocessor(blocks_per_cu, k_persistent<256>, 256, 0);
+}
+
+hipError_t launch_persistent(const Inst* insts_dev, int ninst, int nsteps, const EnergyTables* E,
+                             const int32_t* spec, BatchCtl* ctl, int grid, int threads, unsigned spin_cap,
+                             hipStream_t st) {
+    if (threads == 64)
+        hipLaunchKernelGGL(k_persistent<64>, dim3(grid), dim3(64), 0, st, insts_dev, ninst, nsteps, E, spec, ctl, spin_cap);
+    else
+        hipLaunchKernelGGL(k_persistent<256>, dim3(grid), dim3(256), 0, st, insts_dev, ninst, nsteps, E, spec, ctl, spin_cap);
     return hipGetLastError();
 }
 

@@ -392,6 +392,17 @@ int build_lattice(const char* protein, const CodonTable& T, const Params& P, dou
     for (int v = 0; v < N; v++)
         for (int j = L.in_start[v]; j < L.in_start[v + 1]; j++)
             L.betaU[4 * v + L.in_lab[j]] = std::min(L.betaU[4 * v + L.in_lab[j]], L.in_U[j]);
+    // hairpin closing side: min over b2 -z-> b1 -y-> b of the two edge costs
+    L.hpB.assign((size_t)16 * N, kINF);
+    for (int v = 0; v < N; v++)
+        for (int j = L.in_start[v]; j < L.in_start[v + 1]; j++) {
+            const int b1 = L.in_src[j], y = L.in_lab[j];
+            for (int j2 = L.in_start[b1]; j2 < L.in_start[b1 + 1]; j2++) {
+                const int z = L.in_lab[j2];
+                int64_t& h = L.hpB[16 * v + 4 * y + z];
+                h = std::min(h, L.in_U[j] + L.in_U[j2]);
+            }
+        }
     // label paths of 1..4 edges out of / into every state (explicit short loop segments)
     L.fwd_off.assign((size_t)4 * N + 1, 0);
     L.bwd_off.assign((size_t)4 * N + 1, 0);
