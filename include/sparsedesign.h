@@ -84,6 +84,10 @@ typedef struct sd_result {
     double t_total_s;        /* complete time: input -> strings                                */
     double t_span_kernels_s; /* with kernel_timing: summed duration of the span-step kernels  */
     int64_t n_span_launches; /* span-step kernel launches of the forward fill                  */
+    int64_t cand_slots;      /* candidate slots reserved for the fill that produced the result */
+    int64_t cand_slots_first;/* slots reserved by the first attempt (before any fallback)      */
+    int32_t cand_overflow;   /* 1 if the first attempt's reservation overflowed (then exact
+                                worst-case segments were used; the result is unchanged)       */
 } sd_result;
 
 /* Parameter file (project text format "SPARSEDESIGN-PARAMS 1"; Turner-2004 d0 array shapes,
@@ -124,6 +128,67 @@ sd_status sd_design_tables(sd_context *ctx, const char *protein, const sd_codon_
 
 /* Number of automaton states of a protein (to size the sd_design_tables buffers). */
 sd_status sd_lattice_size(const char *protein, int64_t *n_states, int64_t *n_cells);
+
+/* ---- learned candidate-buffer sizing ------------------------------------------------------
+ * A small FP32 MLP (22 -> hidden -> hidden -> K, ReLU, sigmoid outputs) trained on the GPU by the
+ * library's own kernels.  Input features of a request (sd_sizer_features): log(A)/log(2000),
+ * the 20 amino-acid fractions, lambda/4.  Output k: the fraction of the worst-case candidate
+ * slots that the exact DP retains for right endpoints b in position bin k (layer(b)/n in
+ * [k/K, (k+1)/K)), as logged by sd_occupancy.  Sizing only changes how much memory is reserved:
+ * an overflowing reservation falls back to exact worst-case segments, results are unchanged. */
+typedef struct sd_sizer sd_sizer;
+sd_status sd_sizer_create(sd_context *ctx, int hidden, int n_out, uint64_t seed, sd_sizer **out);
+void sd_sizer_free(sd_sizer *z);
+int64_t sd_sizer_num_params(const sd_sizer *z);
+/* parameters as one flat FP32 array: W1[hidden][22], b1, W2[hidden][hidden], b2, W3[K][hidden], b3 */
+sd_status sd_sizer_get_params(const sd_sizer *z, float *flat);
+sd_status sd_sizer_set_params(sd_sizer *z, const float *flat);
+/* MSE loss and its gradient (flat layout above) on n samples X[n][22], Y[n][K] */
+sd_status sd_sizer_gradient(sd_sizer *z, int n, const float *X, const float *Y, float *loss, float *grad);
+/* full-batch Adam on the device; final_loss (may be NULL) = loss before the last update */
+sd_status sd_sizer_train(sd_sizer *z, int n, const float *X, const float *Y, int steps, float lr,
+                         float *final_loss);
+sd_status sd_sizer_predict(sd_sizer *z, int n, const float *X, float *Yhat);
+sd_status sd_sizer_features(const char *protein, double lambda_kcal, float out[22]);
+/* Sizing policy of a context: NULL restores worst-case segments.  A right endpoint in bin k gets
+ * min(worst, ceil(worst * min(1, yhat_k * (1 + margin))) + slack) slots.  The sizer must outlive
+ * the context's use of it. */
+sd_status sd_context_set_sizer(sd_context *ctx, const sd_sizer *z, float margin, int slack);
+/* Exact occupancy log: designs n requests (batched, worst-case segments) and writes Y[n][K], the
+ * per-bin retained fraction of the worst-case slots, plus the results (may be NULL). */
+sd_status sd_occupancy(sd_context *ctx, int n, const char *const *proteins, const double *lambdas,
+                       const sd_codon_table *table, const sd_params *params, int K, float *Y,
+                       sd_result *outs);
+
+/* ---- design server (continuous batching) ---------------------------------------------------
+ * A server thread admits queued requests FIFO while a slot is free and the request's device
+ * state fits the pool (tables sized exactly from the automaton, candidate segments from the
+ * context's sizing policy), runs one persistent launch of steps_per_round span steps over all
+ * active requests (each at its own span), and retires finished ones (traceback on host worker
+ * threads), freeing their memory for the next admissions.  While a server runs, its context must
+ * not be used by other calls.  Results are identical to sd_design; t_total_s is the latency from
+ * submission to completion. */
+typedef struct sd_server sd_server;
+typedef struct sd_server_cfg {
+    size_t pool_bytes;   /* device memory for the DP state of admitted requests (>= 1 MiB)  */
+    int max_active;      /* concurrent requests on the device (1..1024)                     */
+    int steps_per_round; /* span steps per persistent launch between admission points (>0) */
+    int reserved[6];
+} sd_server_cfg;
+typedef struct sd_server_stats {
+    int64_t submitted, admitted, completed, fallbacks, rounds, peak_active, active, queued;
+    int64_t pool_in_use, pool_high_water, reserved_bytes, reserved_cand_bytes;
+    double gpu_seconds;
+} sd_server_stats;
+sd_status sd_server_start(sd_context *ctx, const sd_codon_table *table, const sd_params *params,
+                          const sd_server_cfg *cfg, sd_server **out);
+sd_status sd_server_submit(sd_server *s, const char *protein, double lambda_kcal, uint64_t *ticket);
+/* SD_E_BUSY while pending; on completion *out owns its strings (sd_result_free) */
+sd_status sd_server_poll(sd_server *s, uint64_t ticket, sd_result *out);
+sd_status sd_server_wait(sd_server *s, uint64_t ticket, sd_result *out);
+sd_status sd_server_get_stats(sd_server *s, sd_server_stats *out);
+/* cancels queued requests (SD_E_CANCELLED), finishes active ones, frees the server */
+sd_status sd_server_stop(sd_server *s);
 
 void sd_result_free(sd_result *r);
 const char *sd_status_str(sd_status s);

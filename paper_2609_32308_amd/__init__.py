@@ -25,7 +25,11 @@ EXPORTS = [
     "sd_params_load", "sd_params_sha256", "sd_params_free", "sd_codon_table_from_weights",
     "sd_codon_table_from_freqs", "sd_codon_table_free", "sd_context_create", "sd_context_destroy",
     "sd_design", "sd_design_batch", "sd_design_tables", "sd_lattice_size", "sd_result_free",
-    "sd_status_str", "sd_last_error",
+    "sd_status_str", "sd_last_error", "sd_sizer_create", "sd_sizer_free", "sd_sizer_num_params",
+    "sd_sizer_get_params", "sd_sizer_set_params", "sd_sizer_gradient", "sd_sizer_train",
+    "sd_sizer_predict", "sd_sizer_features", "sd_context_set_sizer", "sd_occupancy",
+    "sd_server_start", "sd_server_submit", "sd_server_poll", "sd_server_wait", "sd_server_get_stats",
+    "sd_server_stop",
 ]
 
 
@@ -40,6 +44,18 @@ class Options(C.Structure):
                 ("reserved", C.c_int * 5)]
 
 
+class ServerCfg(C.Structure):
+    _fields_ = [("pool_bytes", C.c_size_t), ("max_active", C.c_int), ("steps_per_round", C.c_int),
+                ("reserved", C.c_int * 6)]
+
+
+class ServerStats(C.Structure):
+    _fields_ = [(k, C.c_int64) for k in ("submitted", "admitted", "completed", "fallbacks", "rounds",
+                                          "peak_active", "active", "queued", "pool_in_use",
+                                          "pool_high_water", "reserved_bytes", "reserved_cand_bytes")] + \
+               [("gpu_seconds", C.c_double)]
+
+
 class _Result(C.Structure):
     _fields_ = [
         ("mrna", C.c_void_p), ("structure", C.c_void_p), ("energy_centi", C.c_int32),
@@ -48,6 +64,7 @@ class _Result(C.Structure):
         ("n_cells", C.c_int64), ("n_candidates", C.c_int64), ("n_visits", C.c_int64),
         ("n_feasible", C.c_int64), ("t_fill_s", C.c_double), ("t_total_s", C.c_double),
         ("t_span_kernels_s", C.c_double), ("n_span_launches", C.c_int64),
+        ("cand_slots", C.c_int64), ("cand_slots_first", C.c_int64), ("cand_overflow", C.c_int32),
     ]
 
 
@@ -81,6 +98,26 @@ def lib():
         L.sd_status_str.restype = C.c_char_p
         L.sd_last_error.argtypes = []
         L.sd_last_error.restype = C.c_char_p
+        PF = C.POINTER(C.c_float)
+        L.sd_sizer_create.argtypes = [vp, C.c_int, C.c_int, C.c_uint64, C.POINTER(vp)]
+        L.sd_sizer_free.argtypes = [vp]
+        L.sd_sizer_num_params.argtypes = [vp]
+        L.sd_sizer_num_params.restype = C.c_int64
+        L.sd_sizer_get_params.argtypes = [vp, PF]
+        L.sd_sizer_set_params.argtypes = [vp, PF]
+        L.sd_sizer_gradient.argtypes = [vp, C.c_int, PF, PF, PF, PF]
+        L.sd_sizer_train.argtypes = [vp, C.c_int, PF, PF, C.c_int, C.c_float, PF]
+        L.sd_sizer_predict.argtypes = [vp, C.c_int, PF, PF]
+        L.sd_sizer_features.argtypes = [C.c_char_p, C.c_double, PF]
+        L.sd_context_set_sizer.argtypes = [vp, vp, C.c_float, C.c_int]
+        L.sd_occupancy.argtypes = [vp, C.c_int, C.POINTER(C.c_char_p), C.POINTER(C.c_double), vp, vp,
+                                   C.c_int, PF, C.POINTER(_Result)]
+        L.sd_server_start.argtypes = [vp, vp, vp, C.POINTER(ServerCfg), C.POINTER(vp)]
+        L.sd_server_submit.argtypes = [vp, C.c_char_p, C.c_double, C.POINTER(C.c_uint64)]
+        L.sd_server_poll.argtypes = [vp, C.c_uint64, C.POINTER(_Result)]
+        L.sd_server_wait.argtypes = [vp, C.c_uint64, C.POINTER(_Result)]
+        L.sd_server_get_stats.argtypes = [vp, C.POINTER(ServerStats)]
+        L.sd_server_stop.argtypes = [vp]
         _lib = L
     return _lib
 
@@ -147,13 +184,17 @@ class Result:
     t_total_s: float
     t_span_kernels_s: float
     n_span_launches: int
+    cand_slots: int
+    cand_slots_first: int
+    cand_overflow: int
 
 
 def _convert(r: _Result) -> Result:
     out = Result(C.string_at(r.mrna).decode(), C.string_at(r.structure).decode(), r.energy_centi,
                  r.codon_cost, r.objective_kcal, r.objective_fixed, r.fixed_shift, r.cai, r.n_states,
                  r.n_cells, r.n_candidates, r.n_visits, r.n_feasible, r.t_fill_s, r.t_total_s,
-                 r.t_span_kernels_s, r.n_span_launches)
+                 r.t_span_kernels_s, r.n_span_launches, r.cand_slots, r.cand_slots_first,
+                 r.cand_overflow)
     lib().sd_result_free(C.byref(r))
     return out
 
@@ -186,6 +227,22 @@ class Context:
         _check(lib().sd_design_batch(self.h, n, arr, lam, table.h, params.h, res), "sd_design_batch")
         return [_convert(res[i]) for i in range(n)]
 
+    def set_sizer(self, sizer, margin: float = 0.5, slack: int = 8):
+        _check(lib().sd_context_set_sizer(self.h, sizer.h if sizer else None, float(margin), int(slack)),
+               "sd_context_set_sizer")
+        self._sizer = sizer  # keep alive
+
+    def occupancy(self, proteins, lambdas, table: CodonTable, params: Params, K: int):
+        """Exact per-bin candidate occupancy fractions (n, K) plus the designs."""
+        n = len(proteins)
+        arr = (C.c_char_p * n)(*[p.encode() for p in proteins])
+        lam = (C.c_double * n)(*[float(x) for x in lambdas])
+        Y = np.zeros((n, K), np.float32)
+        res = (_Result * n)()
+        _check(lib().sd_occupancy(self.h, n, arr, lam, table.h, params.h, K,
+                                  Y.ctypes.data_as(C.POINTER(C.c_float)), res), "sd_occupancy")
+        return Y, [_convert(res[i]) for i in range(n)]
+
     def design_tables(self, protein: str, table: CodonTable, params: Params, lam: float):
         N, _ = lattice_size(protein)
         V = np.empty((6, N, N), np.int64)
@@ -202,3 +259,102 @@ def lattice_size(protein: str):
     n, c = C.c_int64(), C.c_int64()
     _check(lib().sd_lattice_size(protein.encode(), C.byref(n), C.byref(c)), "sd_lattice_size")
     return n.value, c.value
+
+
+def _fp(a):
+    return a.ctypes.data_as(C.POINTER(C.c_float))
+
+
+def features(protein: str, lam: float) -> np.ndarray:
+    out = np.zeros(22, np.float32)
+    _check(lib().sd_sizer_features(protein.encode(), float(lam), _fp(out)), "sd_sizer_features")
+    return out
+
+
+class Sizer:
+    """FP32 MLP 22 -> hidden -> hidden -> K trained on the device (learned candidate sizing)."""
+
+    def __init__(self, ctx: Context, hidden: int = 64, n_out: int = 8, seed: int = 1):
+        h = C.c_void_p()
+        _check(lib().sd_sizer_create(ctx.h, hidden, n_out, seed, C.byref(h)), "sd_sizer_create")
+        self.h, self.hidden, self.K, self.ctx = h, hidden, n_out, ctx
+
+    def __del__(self):
+        if getattr(self, "h", None) and _lib is not None:
+            _lib.sd_sizer_free(self.h)
+            self.h = None
+
+    @property
+    def n_params(self) -> int:
+        return lib().sd_sizer_num_params(self.h)
+
+    def get_params(self) -> np.ndarray:
+        out = np.zeros(self.n_params, np.float32)
+        _check(lib().sd_sizer_get_params(self.h, _fp(out)), "sd_sizer_get_params")
+        return out
+
+    def set_params(self, flat):
+        a = np.ascontiguousarray(flat, dtype=np.float32)
+        _check(lib().sd_sizer_set_params(self.h, _fp(a)), "sd_sizer_set_params")
+
+    def gradient(self, X, Y):
+        X = np.ascontiguousarray(X, np.float32)
+        Y = np.ascontiguousarray(Y, np.float32)
+        loss = np.zeros(1, np.float32)
+        g = np.zeros(self.n_params, np.float32)
+        _check(lib().sd_sizer_gradient(self.h, len(X), _fp(X), _fp(Y), _fp(loss), _fp(g)), "sd_sizer_gradient")
+        return float(loss[0]), g
+
+    def train(self, X, Y, steps: int = 2000, lr: float = 3e-3) -> float:
+        X = np.ascontiguousarray(X, np.float32)
+        Y = np.ascontiguousarray(Y, np.float32)
+        loss = np.zeros(1, np.float32)
+        _check(lib().sd_sizer_train(self.h, len(X), _fp(X), _fp(Y), steps, lr, _fp(loss)), "sd_sizer_train")
+        return float(loss[0])
+
+    def predict(self, X) -> np.ndarray:
+        X = np.ascontiguousarray(X, np.float32)
+        Y = np.zeros((len(X), self.K), np.float32)
+        _check(lib().sd_sizer_predict(self.h, len(X), _fp(X), _fp(Y)), "sd_sizer_predict")
+        return Y
+
+
+class Server:
+    """Continuous-batching design server on one context (the context is reserved while it runs)."""
+
+    def __init__(self, ctx: Context, table: CodonTable, params: Params, pool_bytes: int = 8 << 30,
+                 max_active: int = 256, steps_per_round: int = 64):
+        cfg = ServerCfg(int(pool_bytes), int(max_active), int(steps_per_round))
+        h = C.c_void_p()
+        _check(lib().sd_server_start(ctx.h, table.h, params.h, C.byref(cfg), C.byref(h)), "sd_server_start")
+        self.h, self._keep = h, (ctx, table, params)
+
+    def submit(self, protein: str, lam: float) -> int:
+        t = C.c_uint64()
+        _check(lib().sd_server_submit(self.h, protein.encode(), float(lam), C.byref(t)), "sd_server_submit")
+        return t.value
+
+    def poll(self, ticket: int):
+        r = _Result()
+        rc = lib().sd_server_poll(self.h, ticket, C.byref(r))
+        if rc == -9:
+            return None
+        _check(rc, "sd_server_poll")
+        return _convert(r)
+
+    def wait(self, ticket: int) -> Result:
+        r = _Result()
+        _check(lib().sd_server_wait(self.h, ticket, C.byref(r)), "sd_server_wait")
+        return _convert(r)
+
+    def stats(self) -> dict:
+        st = ServerStats()
+        _check(lib().sd_server_get_stats(self.h, C.byref(st)), "sd_server_get_stats")
+        return {k: getattr(st, k) for k, _ in ServerStats._fields_}
+
+    def stop(self):
+        if getattr(self, "h", None):
+            _check(lib().sd_server_stop(self.h), "sd_server_stop")
+            self.h = None
+
+    __del__ = stop

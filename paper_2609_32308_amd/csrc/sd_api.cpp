@@ -16,22 +16,19 @@
 #include "sd_device.h"
 #include "sd_lattice.h"
 #include "sd_traceback.h"
+#include "sd_host.h"
 
 using namespace sd;
 
-struct sd_params {
-    Params p;
-    uint64_t uid;
-};
-struct sd_codon_table {
-    CodonTable t;
-};
 
 namespace {
 thread_local std::string g_err;
 uint64_t g_uid = 1;
 std::mutex g_uid_mu;
+const char kCode64[65] = "KNKNTTTTRSRSIIMIQHQHPPPPRRRRLLLLEDEDAAAAGGGGVVVV*Y*YSSSS*CWCLFLF";
+}  // namespace
 
+namespace sd {
 sd_status fail(sd_status s, const std::string& msg) {
     g_err = msg;
     return s;
@@ -42,8 +39,7 @@ sd_status hip_fail(hipError_t e, const char* where) {
 double now_s() {
     return std::chrono::duration<double>(std::chrono::steady_clock::now().time_since_epoch()).count();
 }
-const char kCode64[65] = "KNKNTTTTRSRSIIMIQHQHPPPPRRRRLLLLEDEDAAAAGGGGVVVV*Y*YSSSS*CWCLFLF";
-}  // namespace
+}  // namespace sd
 
 // ------------------------------------------------------------------------------------------------
 extern "C" const char* sd_status_str(sd_status s) {
@@ -439,6 +435,45 @@ sd_status fill_result(const Lattice& L, const TraceResult& R, int64_t xs, int64_
     return SD_OK;
 }
 
+void sizer_predict_host(const sd_sizer* z, const float* x, float* y);
+int sizer_bins(const sd_sizer* z);
+
+// Candidate capacity policy of a context for one request (frac must outlive the policy).
+CapPolicy policy_for(const sd_context* c, const char* protein, double lambda, std::vector<float>& frac) {
+    CapPolicy cp;
+    if (c->force_worst) return cp;
+    if (c->opt.capacity_override > 0) {
+        cp.override_slots = c->opt.capacity_override;
+        return cp;
+    }
+    if (c->sizer) {
+        float x[22];
+        if (sd_sizer_features(protein, lambda, x) == SD_OK) {
+            frac.assign(sizer_bins(c->sizer), 0.f);
+            sizer_predict_host(c->sizer, x, frac.data());
+            cp.frac = frac.data();
+            cp.K = (int)frac.size();
+            cp.margin = c->sz_margin;
+            cp.slack = c->sz_slack;
+        }
+    }
+    return cp;
+}
+
+// Exact occupancy of one finished design: per position bin, retained strict candidates over the
+// worst-case slots of the bin's right endpoints.
+void occupancy_bins(const Lattice& L, const TraceTables& T, int K, float* y) {
+    std::vector<double> num(K, 0.0), den(K, 0.0);
+    for (int b = 0; b < L.N; b++) {
+        const int lb = L.layer[b], k = position_bin(lb, L.n, K);
+        den[k] += lb >= 5 ? L.off[lb - 4] : 0;
+        int cnt = 0;
+        for (int j = 0; j < T.ccnt[b]; j++) cnt += T.cc[L.coff[b] + j] >= 0;
+        num[k] += cnt;
+    }
+    for (int k = 0; k < K; k++) y[k] = den[k] > 0 ? (float)(num[k] / den[k]) : 0.f;
+}
+
 // One plain design; optionally keeps the downloaded tables.
 sd_status design_plain(sd_context* c, const char* protein, const sd_codon_table* table,
                        const sd_params* params, double lambda, sd_result* out, TraceTables* keep,
@@ -449,12 +484,14 @@ sd_status design_plain(sd_context* c, const char* protein, const sd_codon_table*
     if (he != hipSuccess) return hip_fail(he, "hipSetDevice");
     Lattice L;
     std::string err;
-    int cap = c->opt.capacity_override;
-    int rc = build_lattice(protein, table->t, params->p, lambda, cap, L, err);
+    std::vector<float> frac;
+    int rc = build_lattice(protein, table->t, params->p, lambda, policy_for(c, protein, lambda, frac), L, err);
     if (rc) return fail((sd_status)rc, err);
     sd_status s = ensure_params(c, params);
     if (s) return s;
     const double tf0 = now_s();
+    const int64_t slots_first = L.cand_slots;
+    int overflowed = 0;
     Inst I;
     memset(&I, 0, sizeof(I));
     for (int attempt = 0; attempt < 2; attempt++) {
@@ -468,7 +505,8 @@ sd_status design_plain(sd_context* c, const char* protein, const sd_codon_table*
         // overflow of a predicted / overridden capacity: fall back to exact worst-case segments
         if (attempt == 1) return fail(SD_E_INTERNAL, "candidate overflow with worst-case capacity");
         c->last_overflow_span = ovf;
-        rc = build_lattice(protein, table->t, params->p, lambda, 0, L, err);
+        overflowed = 1;
+        rc = build_lattice(protein, table->t, params->p, lambda, CapPolicy(), L, err);
         if (rc) return fail((sd_status)rc, err);
     }
     const double tf1 = now_s();
@@ -492,6 +530,9 @@ sd_status design_plain(sd_context* c, const char* protein, const sd_codon_table*
     out->t_total_s = now_s() - t0;
     out->t_span_kernels_s = c->last_kernel_ms * 1e-3;
     out->n_span_launches = c->last_launches;
+    out->cand_slots = L.cand_slots;
+    out->cand_slots_first = slots_first;
+    out->cand_overflow = overflowed;
     if (keep) *keep = std::move(T);
     if (keepL) *keepL = std::move(L);
     return SD_OK;
@@ -520,7 +561,7 @@ extern "C" sd_status sd_lattice_size(const char* protein, int64_t* n_states, int
     memset(&P.E, 0, sizeof(P.E));
     Lattice L;
     std::string err;
-    rc = build_lattice(protein, T, P, 0.0, 0, L, err);
+    rc = build_lattice(protein, T, P, 0.0, CapPolicy(), L, err);
     if (rc) return fail((sd_status)rc, err);
     *n_states = L.N;
     *n_cells = L.cells;
@@ -670,7 +711,7 @@ sd_status tuned_schedule(sd_context* c, const sd_codon_table* table, const sd_pa
             p += aa[(st >> 33) % 20];
         }
         p += "*";
-        int rc = build_lattice(p.c_str(), table->t, params->p, (i & 1) ? 4.0 : 0.0, 0, Ls[i], err);
+        int rc = build_lattice(p.c_str(), table->t, params->p, (i & 1) ? 4.0 : 0.0, CapPolicy(), Ls[i], err);
         if (rc) return fail((sd_status)rc, err);
     }
     double best_t = 1e30;
@@ -717,8 +758,9 @@ extern "C" sd_status sd_design_batch(sd_context* ctx, int n, const char* const* 
             std::vector<Lattice> Ls(m);
             std::string err;
             for (int i = 0; i < m; i++) {
+                std::vector<float> frac;
                 int rc = build_lattice(proteins[done + i], table->t, params->p, lambdas[done + i],
-                                       ctx->opt.capacity_override, Ls[i], err);
+                                       policy_for(ctx, proteins[done + i], lambdas[done + i], frac), Ls[i], err);
                 if (rc) {
                     for (int j = 0; j < done; j++) sd_result_free(&outs[j]);
                     return fail((sd_status)rc, "batch member " + std::to_string(done + i) + ": " + err);
@@ -749,8 +791,19 @@ extern "C" sd_status sd_design_batch(sd_context* ctx, int n, const char* const* 
                 }
                 if (!ok || st[2] != ~0ull) {
                     // barrier failure or candidate overflow: exact recomputation in plain mode
-                    s = design_plain(ctx, proteins[gi], table, params, lambdas[gi], &outs[gi], nullptr, nullptr);
+                    // with worst-case segments
+                    TraceTables T2;
+                    Lattice L2;
+                    const int fw = ctx->force_worst;
+                    ctx->force_worst = 1;
+                    s = design_plain(ctx, proteins[gi], table, params, lambdas[gi], &outs[gi], &T2, &L2);
+                    ctx->force_worst = fw;
                     ctx->last_batch_fallbacks++;
+                    if (!s) {
+                        outs[gi].cand_slots_first = Ls[i].cand_slots;
+                        outs[gi].cand_overflow = st[2] != ~0ull;
+                        if (ctx->occ_K > 0) occupancy_bins(L2, T2, ctx->occ_K, &ctx->occ[(size_t)gi * ctx->occ_K]);
+                    }
                     continue;
                 }
                 TraceTables T;
@@ -771,6 +824,10 @@ extern "C" sd_status sd_design_batch(sd_context* ctx, int n, const char* const* 
                 outs[gi].t_total_s = now_s() - t0;
                 outs[gi].t_span_kernels_s = ks / m;
                 outs[gi].n_span_launches = 0;
+                outs[gi].cand_slots = Ls[i].cand_slots;
+                outs[gi].cand_slots_first = Ls[i].cand_slots;
+                outs[gi].cand_overflow = 0;
+                if (ctx->occ_K > 0) occupancy_bins(Ls[i], T, ctx->occ_K, &ctx->occ[(size_t)gi * ctx->occ_K]);
             }
             if (s) {
                 for (int j = 0; j < done + m; j++) sd_result_free(&outs[j]);
@@ -784,4 +841,36 @@ extern "C" sd_status sd_design_batch(sd_context* ctx, int n, const char* const* 
     } catch (...) {
         return fail(SD_E_INTERNAL, "unexpected exception");
     }
+}
+
+extern "C" sd_status sd_context_set_sizer(sd_context* ctx, const sd_sizer* z, float margin, int slack) {
+    if (!ctx || margin < 0.f || slack < 0) return fail(SD_E_ARG, "bad sizing policy");
+    ctx->sizer = z;
+    ctx->sz_margin = margin;
+    ctx->sz_slack = slack;
+    return SD_OK;
+}
+
+extern "C" sd_status sd_occupancy(sd_context* ctx, int n, const char* const* proteins, const double* lambdas,
+                                  const sd_codon_table* table, const sd_params* params, int K, float* Y,
+                                  sd_result* outs) {
+    if (!ctx || !Y || K <= 0 || K > 64 || n < 0) return fail(SD_E_ARG, "bad occupancy arguments");
+    std::vector<sd_result> tmp;
+    sd_result* res = outs;
+    if (!res) {
+        tmp.resize(n);
+        res = tmp.data();
+    }
+    ctx->occ.assign((size_t)n * K, 0.f);
+    ctx->occ_K = K;
+    const int fw = ctx->force_worst;
+    ctx->force_worst = 1;
+    sd_status s = sd_design_batch(ctx, n, proteins, lambdas, table, params, res);
+    ctx->force_worst = fw;
+    ctx->occ_K = 0;
+    if (s) return s;
+    memcpy(Y, ctx->occ.data(), sizeof(float) * (size_t)n * K);
+    if (!outs)
+        for (auto& r : tmp) sd_result_free(&r);
+    return SD_OK;
 }

@@ -23,6 +23,13 @@ struct sd_context {
     bool last_graph = false;  // last batch ran as a captured graph
     double last_batch_kernel_s = 0.0, last_batch_fill_s = 0.0;
     int64_t last_batch_fallbacks = 0;
+    // learned sizing policy (sd_context_set_sizer) and exact occupancy capture (sd_occupancy)
+    const sd_sizer* sizer = nullptr;
+    float sz_margin = 0.f;
+    int sz_slack = 0;
+    int force_worst = 0;
+    int occ_K = 0;
+    std::vector<float> occ;
     void* E_dev = nullptr;     // EnergyTables
     void* spec_dev = nullptr;  // special hairpin table
     uint64_t params_uid = 0;

@@ -1,0 +1,33 @@
+// Host-side helpers shared by the plain/batched driver and the design server.
+#pragma once
+#include <hip/hip_runtime.h>
+
+#include <string>
+#include <vector>
+
+#include "../../include/sparsedesign.h"
+#include "sd_device.h"
+#include "sd_lattice.h"
+#include "sd_traceback.h"
+
+struct sd_params {
+    sd::Params p;
+    uint64_t uid;
+};
+struct sd_codon_table {
+    sd::CodonTable t;
+};
+
+namespace sd {
+sd_status fail(sd_status s, const std::string& msg);
+sd_status hip_fail(hipError_t e, const char* where);
+double now_s();
+sd_status ensure_params(sd_context* c, const sd_params* p);
+sd_status fetch_tables(sd_context* c, const Lattice& L, const Inst& I, TraceTables& T);
+sd_status fill_result(const Lattice& L, const TraceResult& R, int64_t xs, int64_t Z, int64_t visits,
+                      int64_t feasible, sd_result* out);
+sd_status design_plain(sd_context* c, const char* protein, const sd_codon_table* table,
+                       const sd_params* params, double lambda, sd_result* out, TraceTables* keep,
+                       Lattice* keepL);
+CapPolicy policy_for(const sd_context* c, const char* protein, double lambda, std::vector<float>& frac);
+}  // namespace sd

@@ -238,8 +238,13 @@ int64_t host_gap(const Lattice& L, int a, int b) {
     return L.tail[a] + L.P[kb] - L.P[ka + 1];
 }
 
+int position_bin(int layer, int n, int K) {
+    const int k = n > 0 ? (int)(((int64_t)layer * K) / (n + 1)) : 0;
+    return k < K ? k : K - 1;
+}
+
 int build_lattice(const char* protein, const CodonTable& T, const Params& P, double lambda,
-                  int capacity_override, Lattice& L, std::string& err) {
+                  const CapPolicy& cp, Lattice& L, std::string& err) {
     int rc = check_protein(protein);
     if (rc) {
         err = "protein must use ACDEFGHIKLMNPQRSTVWY with an optional final '*'";
@@ -467,7 +472,13 @@ int build_lattice(const char* protein, const CodonTable& T, const Params& P, dou
     for (int b = 0; b < N; b++) {
         int lb = L.layer[b];
         int worst = lb >= 5 ? L.off[lb - 4] : 0;
-        int cap = capacity_override > 0 ? std::min(worst, capacity_override) : worst;
+        int cap = worst;
+        if (cp.override_slots > 0) {
+            cap = std::min(worst, cp.override_slots);
+        } else if (cp.frac && cp.K > 0) {
+            const double f = std::min(1.0, (double)cp.frac[position_bin(lb, n, cp.K)] * (1.0 + cp.margin));
+            cap = std::min<int64_t>(worst, (int64_t)ceil(worst * f) + cp.slack);
+        }
         L.coff[b] = acc;
         L.ccap[b] = cap;
         acc += cap;

@@ -48,8 +48,18 @@ struct Lattice {
 
 // validation and construction; return sd_status values
 int check_protein(const char* p);
+// Candidate capacity per right endpoint: override > 0 wins; else with K bin fractions each b
+// gets min(worst, ceil(worst * min(1, frac[bin] * (1 + margin))) + slack); else worst case.
+struct CapPolicy {
+    int override_slots = 0;
+    const float* frac = nullptr;
+    int K = 0;
+    float margin = 0.f;
+    int slack = 0;
+};
+int position_bin(int layer, int n, int K);
 int build_lattice(const char* protein, const CodonTable& T, const Params& P, double lambda,
-                  int capacity_override, Lattice& L, std::string& err);
+                  const CapPolicy& cap, Lattice& L, std::string& err);
 
 // closed-form gap on the host (same definition as the kernels)
 int64_t host_gap(const Lattice& L, int a, int b);

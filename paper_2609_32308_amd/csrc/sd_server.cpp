@@ -1,0 +1,452 @@
+// Design server: continuous batching of design requests at span-step boundaries.
+//
+// A server thread repeats rounds.  Each round it
+//   1. admits queued requests (FIFO) while a slot is free and the request's device state fits
+//      the remaining pool: the O(N^2) tables are known exactly from the automaton, the candidate
+//      segments come from the context's sizing policy (learned sizer or worst case);
+//   2. runs one persistent launch of `steps_per_round` span steps over every active instance,
+//      each at its own span (new instances start at span 1 and are initialised by the launch);
+//   3. retires instances that passed their last span: their tables are copied out, their pool
+//      memory is released at once, and the canonical traceback runs on host worker threads.
+// An instance whose candidate reservation overflowed is recomputed exactly in plain mode with
+// worst-case segments, so every result equals the standalone design.
+#include <hip/hip_runtime.h>
+#include <string.h>
+
+#include <algorithm>
+#include <condition_variable>
+#include <deque>
+#include <map>
+#include <mutex>
+#include <thread>
+#include <vector>
+
+#include <atomic>
+
+#include "sd_host.h"
+
+using namespace sd;
+
+namespace {
+
+// first-fit allocator over one device buffer (offsets, 256-byte granularity)
+struct Pool {
+    size_t size = 0;
+    std::map<size_t, size_t> free_;  // offset -> length
+    size_t used = 0, high = 0;
+    void init(size_t n) {
+        size = n;
+        free_.clear();
+        free_[0] = n;
+        used = high = 0;
+    }
+    bool alloc(size_t n, size_t* off) {
+        n = (n + 255) & ~(size_t)255;
+        for (auto it = free_.begin(); it != free_.end(); ++it)
+            if (it->second >= n) {
+                *off = it->first;
+                const size_t rest = it->second - n, at = it->first + n;
+                free_.erase(it);
+                if (rest) free_[at] = rest;
+                used += n;
+                high = std::max(high, used);
+                return true;
+            }
+        return false;
+    }
+    void release(size_t off, size_t n) {
+        n = (n + 255) & ~(size_t)255;
+        used -= n;
+        auto it = free_.emplace(off, n).first;
+        auto nx = std::next(it);
+        if (nx != free_.end() && it->first + it->second == nx->first) {
+            it->second += nx->second;
+            free_.erase(nx);
+        }
+        if (it != free_.begin()) {
+            auto pv = std::prev(it);
+            if (pv->first + pv->second == it->first) {
+                pv->second += it->second;
+                free_.erase(it);
+            }
+        }
+    }
+};
+
+struct Request {
+    uint64_t ticket;
+    std::string protein;
+    double lambda;
+    double t_submit, t_admit = 0;
+};
+
+struct Active {
+    Request rq;
+    Lattice L;
+    Inst I;
+    size_t off = 0, bytes = 0;
+    int g = 1;  // next span to process
+};
+
+struct Done {
+    sd_status status;
+    sd_result res;
+};
+
+}  // namespace
+
+struct sd_server {
+    sd_context* ctx;
+    const sd_codon_table* table;
+    const sd_params* params;
+    sd_server_cfg cfg;
+    Pool pool;
+    char* pool_dev = nullptr;
+    char* aux_dev = nullptr;  // instance descriptors + barrier state
+    void* staging = nullptr;
+    size_t staging_bytes = 0;
+    int grid = 0, threads = 256;
+
+    std::mutex mu;
+    std::condition_variable cv, cv_done;
+    std::deque<Request> queue;
+    std::map<uint64_t, Done> done;
+    std::vector<Active> active;
+    uint64_t next_ticket = 1;
+    std::atomic<bool> stop{false};
+    std::thread loop;
+    // traceback workers
+    std::mutex tmu;
+    std::condition_variable tcv;
+    struct Job {
+        Active a;
+        TraceTables T;
+        int64_t visits, feasible;
+        double t_fill;
+    };
+    std::deque<Job> jobs;
+    std::vector<std::thread> workers;
+    int jobs_running = 0;
+    sd_server_stats st{};
+};
+
+namespace {
+
+void finish(sd_server* S, uint64_t ticket, sd_status status, const sd_result& r) {
+    std::lock_guard<std::mutex> lk(S->mu);
+    S->done[ticket] = Done{status, r};
+    S->st.completed++;
+    S->cv_done.notify_all();
+}
+
+void worker_main(sd_server* S) {
+    for (;;) {
+        sd_server::Job job;
+        {
+            std::unique_lock<std::mutex> lk(S->tmu);
+            S->tcv.wait(lk, [&] { return S->stop || !S->jobs.empty(); });
+            if (S->jobs.empty()) return;
+            job = std::move(S->jobs.front());
+            S->jobs.pop_front();
+            S->jobs_running++;
+        }
+        TraceResult R;
+        sd_result r;
+        memset(&r, 0, sizeof(r));
+        sd_status s = (sd_status)trace_design(job.a.L, S->params->p, job.T, R);
+        if (!s) {
+            int64_t Z = 0;
+            for (int v = 0; v < job.a.L.N; v++)
+                for (int k = 0; k < job.T.ccnt[v]; k++) Z += job.T.cc[job.a.L.coff[v] + k] >= 0;
+            s = fill_result(job.a.L, R, job.T.X[0], Z, job.visits, job.feasible, &r);
+            r.t_fill_s = job.t_fill;
+            r.t_total_s = now_s() - job.a.rq.t_submit;
+            r.cand_slots = r.cand_slots_first = job.a.L.cand_slots;
+        }
+        finish(S, job.a.rq.ticket, s, r);
+        std::lock_guard<std::mutex> lk(S->tmu);
+        S->jobs_running--;
+    }
+}
+
+sd_status ensure_srv_staging(sd_server* S, size_t bytes) {
+    if (bytes <= S->staging_bytes) return SD_OK;
+    if (S->staging) hipHostFree(S->staging);
+    S->staging = nullptr;
+    S->staging_bytes = 0;
+    if (hipHostMalloc(&S->staging, bytes * 2, hipHostMallocDefault) != hipSuccess) return SD_E_NOMEM;
+    S->staging_bytes = bytes * 2;
+    return SD_OK;
+}
+
+// Admit queued requests that fit; returns after uploading their inputs.
+sd_status admit(sd_server* S) {
+    for (;;) {
+        Request rq;
+        {
+            std::lock_guard<std::mutex> lk(S->mu);
+            if (S->queue.empty() || (int)S->active.size() >= S->cfg.max_active) return SD_OK;
+            rq = S->queue.front();
+        }
+        Active a;
+        a.rq = rq;
+        std::string err;
+        std::vector<float> frac;
+        int rc = build_lattice(rq.protein.c_str(), S->table->t, S->params->p, rq.lambda,
+                               policy_for(S->ctx, rq.protein.c_str(), rq.lambda, frac), a.L, err);
+        if (rc) {  // invalid request: answer it right away
+            {
+                std::lock_guard<std::mutex> lk(S->mu);
+                S->queue.pop_front();
+            }
+            sd_result r;
+            memset(&r, 0, sizeof(r));
+            finish(S, rq.ticket, (sd_status)rc, r);
+            continue;
+        }
+        memset(&a.I, 0, sizeof(a.I));
+        InstLayout lay = layout_instance(a.L, nullptr, nullptr, a.I);
+        a.bytes = lay.a_bytes + lay.b_bytes;
+        if (a.bytes > S->pool.size) {  // can never fit: recompute in plain mode outside the pool
+            {
+                std::lock_guard<std::mutex> lk(S->mu);
+                S->queue.pop_front();
+            }
+            sd_result r;
+            sd_status s = design_plain(S->ctx, rq.protein.c_str(), S->table, S->params, rq.lambda, &r, nullptr, nullptr);
+            if (!s) r.t_total_s = now_s() - rq.t_submit;
+            finish(S, rq.ticket, s, r);
+            continue;
+        }
+        size_t off;
+        if (!S->pool.alloc(a.bytes, &off)) return SD_OK;  // wait for memory to free up
+        {
+            std::lock_guard<std::mutex> lk(S->mu);
+            S->queue.pop_front();
+        }
+        a.off = off;
+        char* A = S->pool_dev + off;
+        layout_instance(a.L, A, A + lay.a_bytes, a.I);
+        a.I.retain_all = S->ctx->opt.retain_all;
+        a.I.g0 = 1;
+        sd_status s = ensure_srv_staging(S, lay.a_bytes);
+        if (s) return s;
+        hipError_t e = hipStreamSynchronize(S->ctx->stream);
+        if (e != hipSuccess) return hip_fail(e, "server staging");
+        stage_inputs(a.L, a.I, A, (char*)S->staging);
+        e = hipMemcpyAsync(A, S->staging, lay.a_bytes, hipMemcpyHostToDevice, S->ctx->stream);
+        if (e == hipSuccess) e = hipStreamSynchronize(S->ctx->stream);
+        if (e != hipSuccess) return hip_fail(e, "server upload");
+        a.rq.t_admit = now_s();
+        S->st.admitted++;
+        S->st.reserved_bytes += a.bytes;
+        S->st.reserved_cand_bytes += a.L.cand_slots * 12;
+        S->active.push_back(std::move(a));
+        S->st.peak_active = std::max<int64_t>(S->st.peak_active, (int64_t)S->active.size());
+        S->st.pool_high_water = std::max<int64_t>(S->st.pool_high_water, (int64_t)S->pool.high);
+    }
+}
+
+sd_status round_once(sd_server* S) {
+    const int n = (int)S->active.size();
+    std::vector<Inst> Is(n);
+    for (int i = 0; i < n; i++) {
+        Is[i] = S->active[i].I;
+        Is[i].g0 = S->active[i].g;
+    }
+    Inst* insts = (Inst*)S->aux_dev;
+    BatchCtl* ctl = (BatchCtl*)(S->aux_dev + sizeof(Inst) * kMaxBatch);
+    hipStream_t st = S->ctx->stream;
+    const double t0 = now_s();
+    hipError_t e = hipMemcpyAsync(insts, Is.data(), sizeof(Inst) * n, hipMemcpyHostToDevice, st);
+    if (e == hipSuccess) e = launch_batch_init(insts, n, ctl, st);
+    if (e == hipSuccess)
+        e = launch_persistent(insts, n, S->cfg.steps_per_round, (const EnergyTables*)S->ctx->E_dev,
+                              (const int32_t*)S->ctx->spec_dev, ctl, S->grid, S->threads, 1u << 22, st);
+    BatchCtl h;
+    if (e == hipSuccess) e = hipMemcpyAsync(&h, ctl, sizeof(h), hipMemcpyDeviceToHost, st);
+    if (e == hipSuccess) e = hipStreamSynchronize(st);
+    if (e != hipSuccess) return hip_fail(e, "server round");
+    const double dt = now_s() - t0;
+    S->st.rounds++;
+    S->st.gpu_seconds += dt;
+    const bool ok = h.err == 0 && h.steps_done == S->cfg.steps_per_round;
+    // advance and retire
+    std::vector<Active> keep;
+    for (int i = 0; i < n; i++) {
+        Active& a = S->active[i];
+        a.g += S->cfg.steps_per_round;
+        if (ok && a.g <= a.L.n + 1) {
+            keep.push_back(std::move(a));
+            continue;
+        }
+        unsigned long long stats[4];
+        e = hipMemcpy(stats, a.I.stats, sizeof(stats), hipMemcpyDeviceToHost);
+        if (e != hipSuccess) return hip_fail(e, "server stats");
+        if (!ok || stats[2] != ~0ull) {
+            // barrier failure or candidate overflow: exact recomputation in plain mode
+            S->pool.release(a.off, a.bytes);
+            sd_result r;
+            const int fw = S->ctx->force_worst;
+            S->ctx->force_worst = 1;
+            sd_status s = design_plain(S->ctx, a.rq.protein.c_str(), S->table, S->params, a.rq.lambda, &r, nullptr, nullptr);
+            S->ctx->force_worst = fw;
+            if (!s) {
+                r.t_total_s = now_s() - a.rq.t_submit;
+                r.cand_overflow = stats[2] != ~0ull;
+                r.cand_slots_first = a.L.cand_slots;
+            }
+            S->st.fallbacks++;
+            finish(S, a.rq.ticket, s, r);
+            continue;
+        }
+        sd_server::Job job;
+        sd_status s = fetch_tables(S->ctx, a.L, a.I, job.T);
+        S->pool.release(a.off, a.bytes);
+        if (s) return s;
+        job.visits = (int64_t)stats[0];
+        job.feasible = (int64_t)stats[3];
+        job.t_fill = a.rq.t_admit > 0 ? now_s() - a.rq.t_admit : 0.0;
+        job.a = std::move(a);
+        {
+            std::lock_guard<std::mutex> lk(S->tmu);
+            S->jobs.push_back(std::move(job));
+        }
+        S->tcv.notify_one();
+    }
+    S->active = std::move(keep);
+    return SD_OK;
+}
+
+void server_main(sd_server* S) {
+    hipSetDevice(S->ctx->device);
+    for (;;) {
+        {
+            std::unique_lock<std::mutex> lk(S->mu);
+            S->cv.wait_for(lk, std::chrono::milliseconds(5),
+                           [&] { return S->stop || !S->queue.empty() || !S->active.empty(); });
+            if (S->stop && S->active.empty()) break;
+        }
+        sd_status s = admit(S);
+        if (!s && !S->active.empty()) s = round_once(S);
+        if (s) {  // device failure: fail everything that is in flight or queued
+            std::lock_guard<std::mutex> lk(S->mu);
+            for (auto& a : S->active) S->done[a.rq.ticket] = Done{s, sd_result{}};
+            for (auto& q : S->queue) S->done[q.ticket] = Done{s, sd_result{}};
+            S->active.clear();
+            S->queue.clear();
+            S->cv_done.notify_all();
+        }
+    }
+}
+
+}  // namespace
+
+extern "C" sd_status sd_server_start(sd_context* ctx, const sd_codon_table* table, const sd_params* params,
+                                     const sd_server_cfg* cfg, sd_server** out) {
+    if (!ctx || !table || !params || !cfg || !out) return fail(SD_E_ARG, "null argument");
+    if (cfg->pool_bytes < (1u << 20) || cfg->max_active <= 0 || cfg->max_active > kMaxBatch ||
+        cfg->steps_per_round <= 0)
+        return fail(SD_E_ARG, "bad server configuration");
+    *out = nullptr;
+    sd_status s = ensure_params(ctx, params);
+    if (s) return s;
+    sd_server* S = new (std::nothrow) sd_server();
+    if (!S) return fail(SD_E_NOMEM, "host allocation");
+    S->ctx = ctx;
+    S->table = table;
+    S->params = params;
+    S->cfg = *cfg;
+    hipError_t e = hipSetDevice(ctx->device);
+    if (e == hipSuccess) e = hipMalloc((void**)&S->pool_dev, cfg->pool_bytes);
+    if (e == hipSuccess) e = hipMalloc((void**)&S->aux_dev, sizeof(Inst) * kMaxBatch + 256);
+    if (e != hipSuccess) {
+        if (S->pool_dev) hipFree(S->pool_dev);
+        delete S;
+        hipGetLastError();
+        return fail(SD_E_NOMEM, "server pool allocation");
+    }
+    S->pool.init(cfg->pool_bytes);
+    int per_cu = 0;
+    e = persistent_occupancy(256, &per_cu);
+    if (e != hipSuccess || per_cu <= 0) {
+        hipFree(S->pool_dev);
+        hipFree(S->aux_dev);
+        delete S;
+        return hip_fail(e, "occupancy query");
+    }
+    S->threads = ctx->batch_grid > 0 ? ctx->batch_threads : 256;
+    S->grid = ctx->batch_grid > 0 ? ctx->batch_grid : per_cu * ctx->num_cu;
+    for (int i = 0; i < 4; i++) S->workers.emplace_back(worker_main, S);
+    S->loop = std::thread(server_main, S);
+    *out = S;
+    return SD_OK;
+}
+
+extern "C" sd_status sd_server_submit(sd_server* S, const char* protein, double lambda, uint64_t* ticket) {
+    if (!S || !protein || !ticket) return fail(SD_E_ARG, "null argument");
+    std::lock_guard<std::mutex> lk(S->mu);
+    if (S->stop) return fail(SD_E_CANCELLED, "server stopped");
+    Request r{S->next_ticket++, protein, lambda, now_s()};
+    S->queue.push_back(r);
+    S->st.submitted++;
+    *ticket = r.ticket;
+    S->cv.notify_one();
+    return SD_OK;
+}
+
+extern "C" sd_status sd_server_poll(sd_server* S, uint64_t ticket, sd_result* out) {
+    if (!S || !out) return fail(SD_E_ARG, "null argument");
+    std::lock_guard<std::mutex> lk(S->mu);
+    auto it = S->done.find(ticket);
+    if (it == S->done.end()) return SD_E_BUSY;
+    sd_status s = it->second.status;
+    *out = it->second.res;
+    S->done.erase(it);
+    return s;
+}
+
+extern "C" sd_status sd_server_wait(sd_server* S, uint64_t ticket, sd_result* out) {
+    if (!S || !out) return fail(SD_E_ARG, "null argument");
+    std::unique_lock<std::mutex> lk(S->mu);
+    S->cv_done.wait(lk, [&] { return S->done.count(ticket) > 0; });
+    auto it = S->done.find(ticket);
+    sd_status s = it->second.status;
+    *out = it->second.res;
+    S->done.erase(it);
+    return s;
+}
+
+extern "C" sd_status sd_server_get_stats(sd_server* S, sd_server_stats* out) {
+    if (!S || !out) return fail(SD_E_ARG, "null argument");
+    std::lock_guard<std::mutex> lk(S->mu);
+    *out = S->st;
+    out->pool_in_use = (int64_t)S->pool.used;
+    out->active = (int64_t)S->active.size();
+    out->queued = (int64_t)S->queue.size();
+    return SD_OK;
+}
+
+extern "C" sd_status sd_server_stop(sd_server* S) {
+    if (!S) return fail(SD_E_ARG, "null argument");
+    {
+        std::lock_guard<std::mutex> lk(S->mu);
+        S->stop = true;
+        for (auto& q : S->queue) S->done[q.ticket] = Done{SD_E_CANCELLED, sd_result{}};
+        S->queue.clear();
+        S->cv.notify_all();
+        S->cv_done.notify_all();
+    }
+    if (S->loop.joinable()) S->loop.join();
+    {
+        std::lock_guard<std::mutex> lk(S->tmu);
+        S->tcv.notify_all();
+    }
+    for (auto& w : S->workers) w.join();
+    for (auto& kv : S->done) sd_result_free(&kv.second.res);
+    hipFree(S->pool_dev);
+    hipFree(S->aux_dev);
+    if (S->staging) hipHostFree(S->staging);
+    delete S;
+    return SD_OK;
+}
