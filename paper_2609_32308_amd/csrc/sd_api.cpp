@@ -255,6 +255,8 @@ InstLayout layout_instance(const Lattice& L, char* A, char* B, Inst& I) {
     I.JDL = (int64_t*)tb((size_t)N * kLMRing * 12 * 8);
     I.BI = (int64_t*)tb((size_t)N * kLMRing * 8);
     I.BJ = (int64_t*)tb((size_t)N * kLMRing * 8);
+    I.RS = (int64_t*)tb((size_t)N * kLMRing * 16 * 8);
+    I.LS = (int64_t*)tb((size_t)N * kLMRing * 16 * 8);
     I.V = (int64_t*)tb(cells * 6 * 8);
     I.Bt = (int64_t*)tb(cells * 8);
     I.S1 = (int64_t*)tb(cells * 8);

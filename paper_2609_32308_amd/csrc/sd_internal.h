@@ -77,6 +77,12 @@ struct Inst {
     //   BI[c][g] = min over d at layer(c)+g, type t' of V_t'(c,d) + tail(d) + AU(t')
     //   BJ[d][g] = min over c at layer(d)-g, type t' of V_t'(c,d) + AU(t')
     int64_t *BI, *BJ;
+    // one-sided interior loops, minimised over the separable side's length, per state and span:
+    //   RS[c][s][l1-1][x_{k-1}]: explicit left segment of l1 <= 4 bases ending in c, right side
+    //                            separable, s = layer(b1) - layer(c)
+    //   LS[d][s][l2-1][x_{l+1}]: explicit right segment of l2 <= 4 bases starting at d, left side
+    //                            separable, s = layer(d) - layer(a1)
+    int64_t *RS, *LS;
     int retain_all;
     int g0;  // persistent launches: first span this launch processes for the instance
 };

@@ -366,6 +366,55 @@ __device__ int64_t lsep_pair(const Inst& I, const SmallE& S, int b1, int64_t Uab
     return best;
 }
 
+// ---- one-sided pairs through the per-state tables RS / LS ---------------------------------------
+// The explicit side's short label paths are enumerated once; the separable side's length was
+// minimised by the producer.  The 2x3 and 3x2 pairs (whose mismatch class differs from the rest
+// of their row) are evaluated per pair.
+__device__ __forceinline__ int64_t rs_idx(int state, int span, int l, int lab) {
+    return ((int64_t)state * kLMRing + (span & (kLMRing - 1))) * 16 + (l - 1) * 4 + lab;
+}
+
+__device__ int64_t one_sided(const Inst& I, const SmallE& S, int a1, int b1, int64_t Uab, int p, int q,
+                             int cap, int lane, const int64_t* obuf) {
+    const int g = q - p;
+    int start[9];
+    int tot = 0;
+    for (int l = 1; l <= 4; l++) {  // left explicit (right separable) path lists
+        start[l - 1] = tot;
+        const bool ok = !sep_left(p, l) && g - 2 - l >= 8;
+        tot += ok ? I.fwd_off[a1 * 4 + l] - I.fwd_off[a1 * 4 + l - 1] : 0;
+    }
+    for (int l = 1; l <= 4; l++) {  // right explicit (left separable) path lists
+        start[3 + l] = tot;
+        const bool ok = !sep_right(q, l) && g - 2 - l >= 8;
+        tot += ok ? I.bwd_off[b1 * 4 + l] - I.bwd_off[b1 * 4 + l - 1] : 0;
+    }
+    start[8] = tot;
+    int64_t best = kINF;
+    for (int idx = lane; idx < tot; idx += 64) {
+        int k = 0;
+        while (k < 7 && start[k + 1] <= idx) k++;
+        const int i = idx - start[k];
+        if (k < 4) {
+            const int l1 = k + 1, X = l1 == 1 ? 2 : 0, e = I.fwd_off[a1 * 4 + l1 - 1] + i;
+            const int fm = I.fwd_meta[e], c = fm >> 4, xi = (fm >> 2) & 3, xk = fm & 3;
+            const int64_t rs = I.RS[rs_idx(c, g - 2 - l1, l1, xk)], ob = obuf[X * 4 + xi];
+            if (rs < kINF && ob < kINF) best = mn(best, Uab + I.fwd_cost[e] + ob + rs);
+        } else {
+            const int l2 = k - 3, X = l2 == 1 ? 2 : 0, e = I.bwd_off[b1 * 4 + l2 - 1] + i;
+            const int bm = I.bwd_meta[e], d = bm >> 4, xl = (bm >> 2) & 3, xj = bm & 3;
+            const int64_t ls = I.LS[rs_idx(d, g - 2 - l2, l2, xl)], oa = obuf[12 + X * 4 + xj];
+            if (ls < kINF && oa < kINF) best = mn(best, Uab + I.bwd_cost[e] + oa + ls);
+        }
+    }
+    // 2x3 with the left side explicit, 3x2 with the right side explicit
+    if (lane == 0 && cap >= 5 && !sep_left(p, 2) && sep_right(q, 3))
+        best = mn(best, rsep_pair(I, S, a1, Uab, 2, 3, p + 3, q - 4, q, obuf));
+    if (lane == 1 && cap >= 5 && sep_left(p, 3) && !sep_right(q, 2))
+        best = mn(best, lsep_pair(I, S, b1, Uab, 3, 2, p + 4, q - 3, p, obuf));
+    return best;
+}
+
 // ---- the work of one layer pair (p, q) in span step g: one workgroup of 4 waves -------------------
 struct GroupCounters {
     unsigned long long visits, appends, feasible;
@@ -419,12 +468,7 @@ __device__ int64_t closed_value(const Inst& I, const SmallE& S, const EnergyTabl
                 }
                 if (w < kINF) v = mn(v, w + fx(S.bulge[l] + au_pen(S, t), s));
             }
-            for (int k = lane; k < kPairCnt[kListOne][ph][cap]; k += 64) {
-                const int code = kPairList[kListOne][ph][k], l1 = code & 31, l2 = (code >> 5) & 31;
-                const int cl = p + 1 + l1, dl = q - 1 - l2;
-                v = mn(v, (code >> 10) ? lsep_pair(I, S, b1, Uab, l1, l2, cl, dl, p, obuf)
-                                       : rsep_pair(I, S, a1, Uab, l1, l2, cl, dl, q, obuf));
-            }
+            v = mn(v, one_sided(I, S, a1, b1, Uab, p, q, cap, lane, obuf));
             v = mn(v, labelled_pairs(I, S, E, t, a1, b1, Uab, ph, cap, lane, lab));
         }
     }
@@ -578,6 +622,53 @@ __device__ GroupCounters span_group(const Inst& I, const SmallE& S, const Energy
     // producers for later two-loops: IDL (per left inner state), JDL (per right inner state),
     // LM (layer-pair minimum of the both-separable form)
     if (g >= 5) {
+        // one-sided tables (inputs from spans <= g - 3): one wave per state; lanes 0..26 take the
+        // separable length 3 + lane in class 0 (explicit side 2..4 bases), lanes 32..58 the same
+        // lengths in the 1xn class (explicit side of one base); then min-reductions per half-wave.
+        for (int k = wave; k < wa + wb; k += nw) {
+            const bool left = k < wa;
+            const int st = left ? a_lo + k : b_lo + (k - wa);
+            const int h = lane >> 5, ls = 3 + (lane & 31), g2 = g - ls;
+            // left: consumer closing layers (p - 1 - l1, p + g + 1) with c = st in layer p;
+            // right: consumer closing layers (p - 1, q + l2 + 1) with d = st in layer q
+            const int qc = p + g + 1, pc = p - 1;
+            const bool sep = left ? sep_right(qc, ls) : (pc >= 0 && sep_left(pc, ls));
+            const bool ok = (lane & 31) < 27 && g2 >= 5 && sep;
+            const int64_t ptail = !ok ? 0 : left ? PRt(I, qc, ls) : PLt(I, pc, ls);
+            int64_t r[12];
+#pragma unroll
+            for (int j = 0; j < 12; j++) r[j] = kINF;
+            if (ok) {
+                const int X = h ? 2 : 0;
+#pragma unroll
+                for (int lab = 0; lab < 4; lab++) {
+                    const int64_t in = left ? I.IDL[ring_idx(st, g2, X, lab)] : I.JDL[ring_idx(st, g2, X, lab)];
+                    if (in >= kINF) continue;
+#pragma unroll
+                    for (int l = 1; l <= 3; l++) {  // explicit length: h ? 1 : l + 1
+                        const int le = h ? 1 : l + 1;
+                        if (h && l > 1) continue;
+                        if (le + ls > kMaxLoop) continue;
+                        if (le == 2 && ls == 3) continue;  // 2x3 / 3x2: evaluated per pair
+                        const int32_t eb = left ? interior_base(S, le, ls) : interior_base(S, ls, le);
+                        r[(l - 1) * 4 + lab] = in + fx(eb, s) + ptail;
+                    }
+                }
+            }
+#pragma unroll
+            for (int j = 0; j < 12; j++) {
+                int64_t v = r[j];
+#pragma unroll
+                for (int o = 1; o < 32; o <<= 1) v = mn(v, __shfl_xor(v, o, 64));
+                r[j] = v;
+            }
+            int64_t* T = left ? I.RS : I.LS;
+            // lane 0 writes explicit lengths 2..4, lane 32 explicit length 1
+            if (lane == 0)
+                for (int j = 0; j < 12; j++) T[rs_idx(st, g, 2 + j / 4, j & 3)] = norm_inf(r[j]);
+            if (lane == 32)
+                for (int j = 0; j < 4; j++) T[rs_idx(st, g, 1, j)] = norm_inf(r[j]);
+        }
         // bulge rings
         for (int k = tid; k < wa + wb; k += blockDim.x) {
             int64_t acc = kINF;
@@ -741,6 +832,10 @@ __global__ void k_init(Inst I) {
         I.BI[i] = kINF;
         I.BJ[i] = kINF;
     }
+    for (size_t i = tid; i < (size_t)I.N * kLMRing * 16; i += nt) {
+        I.RS[i] = kINF;
+        I.LS[i] = kINF;
+    }
     if (tid < 4) I.stats[tid] = tid == 2 ? ~0ull : 0ull;
     if (I.span_appends)
         for (int i = tid; i <= I.n; i += nt) I.span_appends[i] = 0;
@@ -791,7 +886,6 @@ __global__ __launch_bounds__(NT) void k_persistent(const Inst* __restrict__ inst
     __shared__ int pref[kMaxBatch + 1];
     __shared__ int nl[kMaxBatch];
     __shared__ int g0s[kMaxBatch];
-    __shared__ Inst sI;
     __shared__ int s_flag;
     stage_tables(S, E);
     for (int i = threadIdx.x; i < ninst; i += blockDim.x) {
@@ -820,16 +914,16 @@ __global__ __launch_bounds__(NT) void k_persistent(const Inst* __restrict__ inst
                 if (pref[mid] <= item) lo = mid;
                 else hi = mid - 1;
             }
-            const int inst = lo, local = item - pref[inst], g = g0s[inst] + step;
-            for (int k = threadIdx.x; k < (int)(sizeof(Inst) / 8); k += blockDim.x)
-                reinterpret_cast<uint64_t*>(&sI)[k] = reinterpret_cast<const uint64_t*>(&insts[inst])[k];
-            __syncthreads();
-            const int n = sI.n, ncell_items = g <= n ? n - g + 1 : 0;
+            // the instance index is block-uniform: its descriptor is read with scalar loads
+            const int inst = __builtin_amdgcn_readfirstlane(lo);
+            const int local = item - pref[inst], g = g0s[inst] + step;
+            const Inst& I = insts[inst];
+            const int n = I.n, ncell_items = g <= n ? n - g + 1 : 0;
             if (local < ncell_items) {
-                GroupCounters c = span_group(sI, S, E, spec, local, local + g, G);
-                flush_counters(sI, c, g, threadIdx.x & 63);
+                GroupCounters c = span_group(I, S, E, spec, local, local + g, G);
+                flush_counters(I, c, g, threadIdx.x & 63);
             } else {
-                ext_column(sI, S, n - g + 1, red);
+                ext_column(I, S, n - g + 1, red);
             }
             __syncthreads();
         }
@@ -861,6 +955,10 @@ __global__ void k_batch_init(const Inst* __restrict__ insts, int ninst, BatchCtl
     for (size_t i = tid; i < (size_t)I.N * kLMRing; i += nt) {
         I.BI[i] = kINF;
         I.BJ[i] = kINF;
+    }
+    for (size_t i = tid; i < (size_t)I.N * kLMRing * 16; i += nt) {
+        I.RS[i] = kINF;
+        I.LS[i] = kINF;
     }
     if (tid < 4) I.stats[tid] = tid == 2 ? ~0ull : 0ull;
     if (I.span_appends)
