@@ -41,7 +41,7 @@ class SDError(RuntimeError):
 
 class Options(C.Structure):
     _fields_ = [("retain_all", C.c_int), ("capacity_override", C.c_int), ("kernel_timing", C.c_int),
-                ("reserved", C.c_int * 5)]
+                ("span_threads", C.c_int), ("reserved", C.c_int * 4)]
 
 
 class ServerCfg(C.Structure):
@@ -201,8 +201,8 @@ def _convert(r: _Result) -> Result:
 
 class Context:
     def __init__(self, device: int = 0, retain_all: bool = False, capacity_override: int = 0,
-                 kernel_timing: bool = False):
-        opt = Options(int(retain_all), int(capacity_override), int(kernel_timing))
+                 kernel_timing: bool = False, span_threads: int = 0):
+        opt = Options(int(retain_all), int(capacity_override), int(kernel_timing), int(span_threads))
         h = C.c_void_p()
         _check(lib().sd_context_create(device, C.byref(opt), C.byref(h)), "sd_context_create")
         self.h = h

@@ -143,6 +143,11 @@ extern "C" sd_status sd_context_create(int device, const sd_options* opt, sd_con
     c->device = device;
     c->num_cu = prop.multiProcessorCount;
     if (opt) c->opt = *opt;
+    if (c->opt.span_threads == 0) c->opt.span_threads = 256;
+    if (c->opt.span_threads != 256 && c->opt.span_threads != 512 && c->opt.span_threads != 1024) {
+        delete c;
+        return fail(SD_E_ARG, "span_threads must be 0, 256, 512 or 1024");
+    }
     e = hipSetDevice(device);
     if (e == hipSuccess) e = hipStreamCreateWithFlags(&c->stream, hipStreamNonBlocking);
     if (e == hipSuccess) e = upload_pair_order();
@@ -246,6 +251,8 @@ InstLayout layout_instance(const Lattice& L, char* A, char* B, Inst& I) {
     I.bwd_meta = (int*)ta(L.bwd_meta.size() * 4);
     I.bwd_cost = (int64_t*)ta(L.bwd_cost.size() * 8);
     I.hpB = (int64_t*)ta(L.hpB.size() * 8);
+    I.OB = (int64_t*)ta(L.OB.size() * 8);
+    I.OA = (int64_t*)ta(L.OA.size() * 8);
     I.ccnt = (int*)ta(N * 4);
     I.X = (int64_t*)ta(N * 8);
     I.stats = (unsigned long long*)ta(4 * 8);
@@ -305,6 +312,8 @@ void stage_inputs(const Lattice& L, const Inst& I, const char* devA, char* image
     put(I.bwd_meta, L.bwd_meta.data(), L.bwd_meta.size() * 4);
     put(I.bwd_cost, L.bwd_cost.data(), L.bwd_cost.size() * 8);
     put(I.hpB, L.hpB.data(), L.hpB.size() * 8);
+    put(I.OB, L.OB.data(), L.OB.size() * 8);
+    put(I.OA, L.OA.data(), L.OA.size() * 8);
 }
 
 sd_status ensure_staging(sd_context* c, size_t bytes) {
@@ -355,7 +364,7 @@ sd_status run_plain(sd_context* c, const Lattice& L, Inst& I, int64_t* overflow_
         if (timing) e = hipEventRecord(c->tev[2 * (g - 1)], st);
         if (e == hipSuccess)
             e = launch_span(I, (const EnergyTables*)c->E_dev, (const int32_t*)c->spec_dev, g,
-                            g >= 2 ? L.n - g + 1 : -1, st);
+                            g >= 2 ? L.n - g + 1 : -1, c->opt.span_threads, st);
         if (timing && e == hipSuccess) e = hipEventRecord(c->tev[2 * (g - 1) + 1], st);
     }
     if (e == hipSuccess) e = launch_ext(I, (const EnergyTables*)c->E_dev, 0, st);

@@ -73,6 +73,7 @@ struct Inst {
     const int64_t *fwd_cost, *bwd_cost;
     // generic hairpins: HB[b*16 + y*4 + z] = min over b2 -z-> b1 -y-> b of U(b2->b1) + U(b1->b)
     const int64_t *hpB;
+    const int64_t *OB, *OA;  // [state][t][X][label] outer minima of one-sided interior loops
     // bulges of >= 3 bases, per state and span (span innermost):
     //   BI[c][g] = min over d at layer(c)+g, type t' of V_t'(c,d) + tail(d) + AU(t')
     //   BJ[d][g] = min over c at layer(d)-g, type t' of V_t'(c,d) + AU(t')
@@ -87,7 +88,8 @@ struct Inst {
     int g0;  // persistent launches: first span this launch processes for the instance
 };
 
-constexpr int kLMRing = 64;  // > 32 spans of two-loop reach
+constexpr int kLMRing = 64;
+constexpr int kMaxWaves = 16;  // waves per workgroup of the span-step kernels (1024 threads)  // > 32 spans of two-loop reach
 static_assert(sizeof(Inst) % 8 == 0, "instance descriptors are copied as 8-byte words");
 
 // Batched persistent launch: barrier state shared by all workgroups.

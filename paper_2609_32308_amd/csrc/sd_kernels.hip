@@ -146,8 +146,8 @@ __device__ __forceinline__ int pair_class(int l1, int l2) {  // 1: 2x3 mismatch 
 
 // ---- hairpin closure ------------------------------------------------------------------------
 __device__ int64_t hairpin_lane(const Inst& I, const SmallE& S, const int32_t* __restrict__ spec,
-                                int a, int b, int t, int a1, int64_t Ua, int lane) {
-    const int la = I.layer[a], g = I.layer[b] - la, m = g - 2, s = I.shift;
+                                int a, int b, int t, int a1, int64_t Ua, int la, int g, int lane) {
+    const int m = g - 2, s = I.shift;
     const int x = kTX[t], y = kTY[t];
     int64_t best = kINF;
     if (m == 3 || m == 4 || m == 6) {
@@ -313,55 +313,36 @@ __device__ __forceinline__ int64_t lm_idx(int layer, int span, int X) {
 __device__ __forceinline__ int64_t PLt(const Inst& I, int p, int l1) { return I.P[(p + l1) / 3] - I.P[(p + 2) / 3 + 1]; }
 __device__ __forceinline__ int64_t PRt(const Inst& I, int q, int l2) { return I.P[(q - 2) / 3] - I.P[(q - l2) / 3 + 1]; }
 
-// Outer minima for one closing edge, computed once into LDS (ob: 12 values, oa: 12 values):
-//   ob[X][x_{i+1}] = min_{x_{j-1}} beta(b1, x_{j-1}) + mm_X[t][x_{i+1}][x_{j-1}]
-//   oa[X][x_{j-1}] = min_{x_{i+1}} alpha(a1, x_{i+1}) + mm_X[t][x_{i+1}][x_{j-1}]
-__device__ __forceinline__ void outer_minima(const Inst& I, const SmallE& S, int a1, int b1, int t,
-                                             int lane, int64_t* obuf) {
-    if (lane < 24) {
-        const int X = (lane >> 2) % 3, x = lane & 3;
-        int64_t r = kINF;
-        for (int o = 0; o < 4; o++) {
-            if (lane < 12) {
-                const int64_t be = I.betaU[b1 * 4 + o];
-                if (be < kINF) r = mn(r, be + fx(mmx(S, X, t, x, o), I.shift));
-            } else {
-                const int64_t al = I.alphaU[a1 * 4 + o];
-                if (al < kINF) r = mn(r, al + fx(mmx(S, X, t, o, x), I.shift));
-            }
-        }
-        obuf[lane] = r;
-    }
-    __builtin_amdgcn_wave_barrier();
-    __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
-}
+// Outer minima of one-sided loops come from per-state tables built with the automaton:
+//   OB(b1, t)[X][x_{i+1}] = min_{x_{j-1}} beta(b1, x_{j-1}) + mm_X[t][x_{i+1}][x_{j-1}]
+//   OA(a1, t)[X][x_{j-1}] = min_{x_{i+1}} alpha(a1, x_{i+1}) + mm_X[t][x_{i+1}][x_{j-1}]
 
 // left segment explicit (paths of l1 edges out of a1), right segment separable
 __device__ int64_t rsep_pair(const Inst& I, const SmallE& S, int a1, int64_t Uab, int l1, int l2,
-                             int cl, int dl, int q, const int64_t* obuf) {
+                             int cl, int dl, int q, const int64_t* __restrict__ ob) {
     const int X = mm_class(l1, l2), g2 = dl - cl;
     const int64_t base = Uab + fx(interior_base(S, l1, l2), I.shift) + PRt(I, q, l2);
     const int f0 = I.fwd_off[a1 * 4 + l1 - 1], f1 = I.fwd_off[a1 * 4 + l1];
     int64_t best = kINF;
     for (int i = f0; i < f1; i++) {
         const int fm = I.fwd_meta[i], c = fm >> 4, xi = (fm >> 2) & 3, xk = fm & 3;
-        const int64_t ob = obuf[X * 4 + xi], idl = I.IDL[ring_idx(c, g2, X, xk)];
-        if (ob < kINF && idl < kINF) best = mn(best, base + I.fwd_cost[i] + ob + idl);
+        const int64_t o = ob[X * 4 + xi], idl = I.IDL[ring_idx(c, g2, X, xk)];
+        if (o < kINF && idl < kINF) best = mn(best, base + I.fwd_cost[i] + o + idl);
     }
     return best;
 }
 
 // left segment separable, right segment explicit (paths of l2 edges into b1)
 __device__ int64_t lsep_pair(const Inst& I, const SmallE& S, int b1, int64_t Uab, int l1, int l2,
-                             int cl, int dl, int p, const int64_t* obuf) {
+                             int cl, int dl, int p, const int64_t* __restrict__ oa) {
     const int X = mm_class(l1, l2), g2 = dl - cl;
     const int64_t base = Uab + fx(interior_base(S, l1, l2), I.shift) + PLt(I, p, l1);
     const int r0 = I.bwd_off[b1 * 4 + l2 - 1], r1 = I.bwd_off[b1 * 4 + l2];
     int64_t best = kINF;
     for (int j = r0; j < r1; j++) {
         const int bm = I.bwd_meta[j], d = bm >> 4, xl = (bm >> 2) & 3, xj = bm & 3;
-        const int64_t oa = obuf[12 + X * 4 + xj], jdl = I.JDL[ring_idx(d, g2, X, xl)];
-        if (oa < kINF && jdl < kINF) best = mn(best, base + I.bwd_cost[j] + oa + jdl);
+        const int64_t o = oa[X * 4 + xj], jdl = I.JDL[ring_idx(d, g2, X, xl)];
+        if (o < kINF && jdl < kINF) best = mn(best, base + I.bwd_cost[j] + o + jdl);
     }
     return best;
 }
@@ -375,7 +356,8 @@ __device__ __forceinline__ int64_t rs_idx(int state, int span, int l, int lab) {
 }
 
 __device__ int64_t one_sided(const Inst& I, const SmallE& S, int a1, int b1, int64_t Uab, int p, int q,
-                             int cap, int lane, const int64_t* obuf) {
+                             int cap, int lane, const int64_t* __restrict__ ob,
+                             const int64_t* __restrict__ oa) {
     const int g = q - p;
     int start[9];
     int tot = 0;
@@ -398,24 +380,24 @@ __device__ int64_t one_sided(const Inst& I, const SmallE& S, int a1, int b1, int
         if (k < 4) {
             const int l1 = k + 1, X = l1 == 1 ? 2 : 0, e = I.fwd_off[a1 * 4 + l1 - 1] + i;
             const int fm = I.fwd_meta[e], c = fm >> 4, xi = (fm >> 2) & 3, xk = fm & 3;
-            const int64_t rs = I.RS[rs_idx(c, g - 2 - l1, l1, xk)], ob = obuf[X * 4 + xi];
-            if (rs < kINF && ob < kINF) best = mn(best, Uab + I.fwd_cost[e] + ob + rs);
+            const int64_t rs = I.RS[rs_idx(c, g - 2 - l1, l1, xk)], o = ob[X * 4 + xi];
+            if (rs < kINF && o < kINF) best = mn(best, Uab + I.fwd_cost[e] + o + rs);
         } else {
             const int l2 = k - 3, X = l2 == 1 ? 2 : 0, e = I.bwd_off[b1 * 4 + l2 - 1] + i;
             const int bm = I.bwd_meta[e], d = bm >> 4, xl = (bm >> 2) & 3, xj = bm & 3;
-            const int64_t ls = I.LS[rs_idx(d, g - 2 - l2, l2, xl)], oa = obuf[12 + X * 4 + xj];
-            if (ls < kINF && oa < kINF) best = mn(best, Uab + I.bwd_cost[e] + oa + ls);
+            const int64_t ls = I.LS[rs_idx(d, g - 2 - l2, l2, xl)], o = oa[X * 4 + xj];
+            if (ls < kINF && o < kINF) best = mn(best, Uab + I.bwd_cost[e] + o + ls);
         }
     }
     // 2x3 with the left side explicit, 3x2 with the right side explicit
     if (lane == 0 && cap >= 5 && !sep_left(p, 2) && sep_right(q, 3))
-        best = mn(best, rsep_pair(I, S, a1, Uab, 2, 3, p + 3, q - 4, q, obuf));
+        best = mn(best, rsep_pair(I, S, a1, Uab, 2, 3, p + 3, q - 4, q, ob));
     if (lane == 1 && cap >= 5 && sep_left(p, 3) && !sep_right(q, 2))
-        best = mn(best, lsep_pair(I, S, b1, Uab, 3, 2, p + 4, q - 3, p, obuf));
+        best = mn(best, lsep_pair(I, S, b1, Uab, 3, 2, p + 4, q - 3, p, oa));
     return best;
 }
 
-// ---- the work of one layer pair (p, q) in span step g: one workgroup of 4 waves -------------------
+// ---- the work of one layer pair (p, q) in span step g: one workgroup of several waves ----------
 struct GroupCounters {
     unsigned long long visits, appends, feasible;
 };
@@ -428,71 +410,179 @@ struct GroupShared {
     int keep[kMaxWidth * kMaxWidth];          // 0 none, 1 strict, 2 retained non-strict
     int combo[kMaxWidth * kMaxWidth * 6];     // (cell, type) jobs with an out-edge of label x
     int ncombo;
-    int64_t red[4][2];
-    int64_t obuf[4][24];
-    LabPair lab[4][16];
+    int64_t red[kMaxWaves][2];
+    LabPair lab[kMaxWaves][16];
 };
 
-// typed closed value V_t(a, b) with the lanes of one wave
-__device__ int64_t closed_value(const Inst& I, const SmallE& S, const EnergyTables* __restrict__ E,
-                                const int32_t* __restrict__ spec, int a, int b, int t, int p, int q,
-                                int64_t mini0, int64_t mini1, int lane, int64_t* obuf, LabPair* lab) {
+// One of two parts of the typed closed value V_t(a, b), with the lanes of one wave:
+//   part 0: hairpin, stacks and bulges, multiloop closure;
+//   part 1: interior loops (one-sided, both explicit, both separable).
+// The parts of one (cell, type) run on different waves and meet in an LDS minimum.
+__device__ int64_t closed_part(const Inst& I, const SmallE& S, const EnergyTables* __restrict__ E,
+                               const int32_t* __restrict__ spec, int a, int b, int t, int p, int q,
+                               int part, int64_t mini0, int64_t mini1, int lane, LabPair* lab) {
     const int g = q - p, s = I.shift;
     const int a1 = I.out_dst[a * 4 + kTX[t]];
     const int64_t Ua = I.out_U[a * 4 + kTX[t]];
     const int y = kTY[t];
     const int ib0 = I.in_start[b], ib1 = I.in_start[b + 1];
-    int64_t v = hairpin_lane(I, S, spec, a, b, t, a1, Ua, lane);
-    if (g >= 7) {
-        const int ph = (p % 3) * 3 + (q % 3), cap = min(g - 7, kMaxLoop);
-        for (int eb = ib0; eb < ib1; eb++) {
-            if (I.in_lab[eb] != y) continue;
-            const int b1 = I.in_src[eb];
-            const int64_t Uab = Ua + I.in_U[eb];
-            outer_minima(I, S, a1, b1, t, lane, obuf);
-            for (int k = lane; k < kPairCnt[kListBulge][0][cap]; k += 64) {
-                const int code = kPairList[kListBulge][0][k], l1 = code & 31, l2 = (code >> 5) & 31;
-                v = mn(v, bulge_pair(I, S, t, a1, b1, Uab, l1, l2, p + 1 + l1, q - 1 - l2));
-            }
-            // bulges of >= 3 bases: the unpaired side costs its gap (tail + whole codons)
-            for (int k = lane; k < kPairCnt[kListBulgeSep][0][cap]; k += 64) {
-                const int code = kPairList[kListBulgeSep][0][k], l1 = code & 31, l2 = (code >> 5) & 31;
-                const int l = l1 + l2, cl = p + 1 + l1, dl = q - 1 - l2;
-                int64_t w;
-                if (l1 == 0) {
-                    const int64_t bi = I.BI[(int64_t)a1 * kLMRing + ((dl - cl) & (kLMRing - 1))];
-                    w = bi >= kINF ? kINF : Uab + bi + I.P[(q - 1) / 3] - I.P[dl / 3 + 1];
-                } else {
-                    const int64_t bj = I.BJ[(int64_t)b1 * kLMRing + ((dl - cl) & (kLMRing - 1))];
-                    w = bj >= kINF ? kINF : Uab + bj + I.tail[a1] + I.P[cl / 3] - I.P[(p + 1) / 3 + 1];
+    const int ph = (p % 3) * 3 + (q % 3), cap = min(g - 7, kMaxLoop);
+    int64_t v = kINF;
+    if (part == 0) {
+        v = hairpin_lane(I, S, spec, a, b, t, a1, Ua, p, g, lane);
+        if (g >= 7) {
+            for (int eb = ib0; eb < ib1; eb++) {
+                if (I.in_lab[eb] != y) continue;
+                const int b1 = I.in_src[eb];
+                const int64_t Uab = Ua + I.in_U[eb];
+                for (int k = lane; k < kPairCnt[kListBulge][0][cap]; k += 64) {
+                    const int code = kPairList[kListBulge][0][k], l1 = code & 31, l2 = (code >> 5) & 31;
+                    v = mn(v, bulge_pair(I, S, t, a1, b1, Uab, l1, l2, p + 1 + l1, q - 1 - l2));
                 }
-                if (w < kINF) v = mn(v, w + fx(S.bulge[l] + au_pen(S, t), s));
+                // bulges of >= 3 bases: the unpaired side costs its gap (tail + whole codons)
+                for (int k = lane; k < kPairCnt[kListBulgeSep][0][cap]; k += 64) {
+                    const int code = kPairList[kListBulgeSep][0][k], l1 = code & 31, l2 = (code >> 5) & 31;
+                    const int l = l1 + l2, cl = p + 1 + l1, dl = q - 1 - l2;
+                    int64_t w;
+                    if (l1 == 0) {
+                        const int64_t bi = I.BI[(int64_t)a1 * kLMRing + ((dl - cl) & (kLMRing - 1))];
+                        w = bi >= kINF ? kINF : Uab + bi + I.P[(q - 1) / 3] - I.P[dl / 3 + 1];
+                    } else {
+                        const int64_t bj = I.BJ[(int64_t)b1 * kLMRing + ((dl - cl) & (kLMRing - 1))];
+                        w = bj >= kINF ? kINF : Uab + bj + I.tail[a1] + I.P[cl / 3] - I.P[(p + 1) / 3 + 1];
+                    }
+                    if (w < kINF) v = mn(v, w + fx(S.bulge[l] + au_pen(S, t), s));
+                }
             }
-            v = mn(v, one_sided(I, S, a1, b1, Uab, p, q, cap, lane, obuf));
-            v = mn(v, labelled_pairs(I, S, E, t, a1, b1, Uab, ph, cap, lane, lab));
         }
-    }
-    if (g >= 12) {
-        // both segments separable: OUT(a1, b1, t) + layer-pair minimum
-        const int nbx = (ib1 - ib0) * 32;
-        for (int k = lane; k < nbx; k += 64) {
-            const int eb = ib0 + (k >> 5), X = (k >> 4) & 1, xi = (k >> 2) & 3, xj = k & 3;
-            if (I.in_lab[eb] != y) continue;
-            const int64_t mini = X ? mini1 : mini0;
-            const int64_t al = I.alphaU[a1 * 4 + xi], be = I.betaU[I.in_src[eb] * 4 + xj];
-            if (mini >= kINF || al >= kINF || be >= kINF) continue;
-            v = mn(v, Ua + I.in_U[eb] + al + be + fx(mmx(S, X, t, xi, xj), s) + mini);
+        if (g >= 12) {
+            // multiloop closure (ML_closing + ML_intern + AU) + S2 of the interior
+            const int32_t mlc = S.ml_closing + S.ml_intern + au_pen(S, t);
+            for (int eb = ib0 + lane; eb < ib1; eb += 64) {
+                if (I.in_lab[eb] != y) continue;
+                const int b1 = I.in_src[eb];
+                if (I.layer[b1] - (p + 1) < 10) continue;
+                v = mn(v, I.S2[cell_of(I, a1, b1)] + Ua + I.in_U[eb] + fx(mlc, s));
+            }
         }
-        // multiloop closure (ML_closing + ML_intern + AU) + S2 of the interior
-        const int32_t mlc = S.ml_closing + S.ml_intern + au_pen(S, t);
-        for (int eb = ib0 + lane; eb < ib1; eb += 64) {
-            if (I.in_lab[eb] != y) continue;
-            const int b1 = I.in_src[eb];
-            if (I.layer[b1] - I.layer[a1] < 10) continue;
-            v = mn(v, I.S2[cell_of(I, a1, b1)] + Ua + I.in_U[eb] + fx(mlc, s));
+    } else {
+        if (g >= 7) {
+            const int64_t* oa = I.OA + (int64_t)(a1 * 6 + t) * 12;
+            for (int eb = ib0; eb < ib1; eb++) {
+                if (I.in_lab[eb] != y) continue;
+                const int b1 = I.in_src[eb];
+                const int64_t Uab = Ua + I.in_U[eb];
+                v = mn(v, one_sided(I, S, a1, b1, Uab, p, q, cap, lane, I.OB + (int64_t)(b1 * 6 + t) * 12, oa));
+                v = mn(v, labelled_pairs(I, S, E, t, a1, b1, Uab, ph, cap, lane, lab));
+            }
+        }
+        if (g >= 12) {
+            // both segments separable: OUT(a1, b1, t) + layer-pair minimum
+            const int nbx = (ib1 - ib0) * 32;
+            for (int k = lane; k < nbx; k += 64) {
+                const int eb = ib0 + (k >> 5), X = (k >> 4) & 1, xi = (k >> 2) & 3, xj = k & 3;
+                if (I.in_lab[eb] != y) continue;
+                const int64_t mini = X ? mini1 : mini0;
+                const int64_t al = I.alphaU[a1 * 4 + xi], be = I.betaU[I.in_src[eb] * 4 + xj];
+                if (mini >= kINF || al >= kINF || be >= kINF) continue;
+                v = mn(v, Ua + I.in_U[eb] + al + be + fx(mmx(S, X, t, xi, xj), s) + mini);
+            }
         }
     }
     return norm_inf(wave_min(v));
+}
+
+// Per-state tables of span g for later two-loops, one state per wave (lanes as noted):
+//   left state c (layer p):  RS(c, g), IDL(c, g), BI(c, g) and its LM contribution;
+//   right state d (layer q): LS(d, g), JDL(d, g), BJ(d, g).
+// RS / LS read IDL / JDL of spans <= g - 3 only; the rest reads this group's typed values.
+__device__ void produce_state(const Inst& I, const SmallE& S, const GroupShared& G, int p, int g,
+                              int k, int a_lo, int b_lo, int wa, int wb, int lane,
+                              int64_t& lm0, int64_t& lm1) {
+    const int s = I.shift;
+    const bool left = k < wa;
+    const int i = left ? k : k - wa, st = left ? a_lo + i : b_lo + i;
+    // one-sided tables: lane = 4 * grp + lab covers separable lengths 3 + grp and 19 + grp;
+    // outputs per explicit length 1..4, minimised over the 16 lane groups
+    {
+        const int lab = lane & 3, grp = lane >> 2;
+        const int qc = p + g + 1, pc = p - 1;  // consumer closing layers (left / right state)
+        int64_t o[4] = {kINF, kINF, kINF, kINF};
+#pragma unroll
+        for (int h = 0; h < 2; h++) {
+            const int ls = 3 + grp + 16 * h, g2 = g - ls;
+            if (ls > 29 || g2 < 5) continue;
+            if (left ? !sep_right(qc, ls) : (pc < 0 || !sep_left(pc, ls))) continue;
+            const int64_t ptail = left ? PRt(I, qc, ls) : PLt(I, pc, ls);
+            const int64_t in0 = left ? I.IDL[ring_idx(st, g2, 0, lab)] : I.JDL[ring_idx(st, g2, 0, lab)];
+            const int64_t in2 = left ? I.IDL[ring_idx(st, g2, 2, lab)] : I.JDL[ring_idx(st, g2, 2, lab)];
+#pragma unroll
+            for (int le = 1; le <= 4; le++) {
+                if (le + ls > kMaxLoop || (le == 2 && ls == 3)) continue;
+                const int64_t in = le == 1 ? in2 : in0;
+                if (in >= kINF) continue;
+                const int32_t eb = left ? interior_base(S, le, ls) : interior_base(S, ls, le);
+                o[le - 1] = mn(o[le - 1], in + fx(eb, s) + ptail);
+            }
+        }
+#pragma unroll
+        for (int j = 0; j < 4; j++)
+#pragma unroll
+            for (int m = 4; m < 64; m <<= 1) o[j] = mn(o[j], shfl_xor64(o[j], m));
+        if (grp == 0) {
+            int64_t* T = left ? I.RS : I.LS;
+#pragma unroll
+            for (int j = 0; j < 4; j++) T[rs_idx(st, g, j + 1, lab)] = norm_inf(o[j]);
+        }
+    }
+    // inner minima: lane = 16 * X + 4 * xx + z (48 lanes), minimised over z
+    {
+        const int X = lane >> 4, xx = (lane >> 2) & 3, z = lane & 3;
+        int64_t acc = kINF;
+        if (X < 3) {
+            const int nother = left ? wb : wa;
+            for (int o = 0; o < nother; o++) {
+                const int ci = left ? i * wb + o : o * wb + i;
+                // left: vary x_{l+1} = z with alpha(d); right: vary x_{k-1} = z with beta(c)
+                const int64_t w = left ? I.alphaU[(b_lo + o) * 4 + z] : I.betaU[(a_lo + o) * 4 + z];
+                if (w >= kINF) continue;
+                for (int tp = 0; tp < 6; tp++) {
+                    const int64_t vin = G.vbuf[ci][tp];
+                    if (vin < kINF)
+                        acc = mn(acc, vin + w + fx(left ? mmx(S, X, kRev[tp], z, xx) : mmx(S, X, kRev[tp], xx, z), s));
+                }
+            }
+        }
+        acc = mn(acc, shfl_xor64(acc, 1));
+        acc = mn(acc, shfl_xor64(acc, 2));
+        acc = norm_inf(acc);
+        if (X < 3 && z == 0) {
+            if (left) {
+                I.IDL[ring_idx(st, g, X, xx)] = acc;
+                const int64_t be = I.betaU[st * 4 + xx];
+                if (acc < kINF && be < kINF) {
+                    if (X == 0) lm0 = mn(lm0, acc + be);
+                    if (X == 1) lm1 = mn(lm1, acc + be);
+                }
+            } else {
+                I.JDL[ring_idx(st, g, X, xx)] = acc;
+            }
+        }
+    }
+    // bulge rings: lane = 6 * other + type (24 lanes)
+    {
+        const int o = lane / 6, tp = lane - 6 * o;
+        int64_t acc = kINF;
+        if (lane < 24 && o < (left ? wb : wa)) {
+            const int64_t vin = G.vbuf[left ? i * wb + o : o * wb + i][tp];
+            if (vin < kINF) acc = vin + (left ? I.tail[b_lo + o] : 0) + fx(au_pen(S, tp), s);
+        }
+        acc = norm_inf(wave_min(acc));
+        if (lane == 0) {
+            if (left) I.BI[(int64_t)st * kLMRing + (g & (kLMRing - 1))] = acc;
+            else I.BJ[(int64_t)st * kLMRing + (g & (kLMRing - 1))] = acc;
+        }
+    }
 }
 
 __device__ GroupCounters span_group(const Inst& I, const SmallE& S, const EnergyTables* __restrict__ E,
@@ -522,16 +612,22 @@ __device__ GroupCounters span_group(const Inst& I, const SmallE& S, const Energy
             G.red[wave][1] = mini1;
         }
     }
-    if (tid == 0) {
-        int k = 0;
-        for (int ci = 0; ci < ncell; ci++) {
-            const int a = a_lo + ci / wb;
-            for (int t = 0; t < 6; t++) {
+    // (cell, type) jobs whose type's first label leaves a; typed values cleared
+    if (wave == 0) {
+        int base = 0;
+        for (int k0 = 0; k0 < ncell * 6; k0 += 64) {
+            const int k = k0 + lane;
+            bool job = false;
+            if (k < ncell * 6) {
+                const int ci = k / 6, t = k - 6 * ci;
                 G.vbuf[ci][t] = kINF;
-                if (g >= 5 && I.out_dst[a * 4 + kTX[t]] >= 0) G.combo[k++] = ci * 6 + t;
+                job = g >= 5 && I.out_dst[(a_lo + ci / wb) * 4 + kTX[t]] >= 0;
             }
+            const unsigned long long m = __ballot(job);
+            if (job) G.combo[base + __popcll(m & ((1ull << lane) - 1ull))] = k;
+            base += __popcll(m);
         }
-        G.ncombo = k;
+        if (lane == 0) G.ncombo = base;
     }
     __syncthreads();
     if (g >= 12) {
@@ -541,16 +637,19 @@ __device__ GroupCounters span_group(const Inst& I, const SmallE& S, const Energy
             mini1 = mn(mini1, G.red[w][1]);
         }
     }
-    // phase 1: typed closed values, (cell, type) jobs spread over the waves
-    for (int k = wave; k < G.ncombo; k += nw) {
-        const int ci = G.combo[k] / 6, t = G.combo[k] % 6;
+    // phase 1: typed closed values; the two parts of every (cell, type) job on separate waves
+    const int njobs = 2 * G.ncombo;
+    for (int k = wave; k < njobs; k += nw) {
+        const int cmb = G.combo[k >> 1], ci = cmb / 6, t = cmb - 6 * ci;
         const int a = a_lo + ci / wb, b = b_lo + ci % wb;
-        const int64_t v = closed_value(I, S, E, spec, a, b, t, p, q, mini0, mini1, lane, G.obuf[wave], G.lab[wave]);
-        if (lane == 0) G.vbuf[ci][t] = v;
+        const int64_t v = closed_part(I, S, E, spec, a, b, t, p, q, k & 1, mini0, mini1, lane, G.lab[wave]);
+        if (lane == 0 && v < kINF)
+            __hip_atomic_fetch_min(&G.vbuf[ci][t], v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
     }
     __syncthreads();
     // phase 2: branch value (eq. 2), S2 (eq. 7), P_S, S1 and the retention test (eq. 6); one
-    // cell per wave.  Every scan reads only entries committed by earlier spans.
+    // cell per wave from the first wave on.  Every scan reads only entries committed by earlier
+    // spans.
     for (int ci = wave; ci < ncell; ci += nw) {
         const int a = a_lo + ci / wb, b = b_lo + ci % wb;
         const int64_t cell = I.rowoff[a] + (b - I.off[p + 1]);
@@ -596,15 +695,38 @@ __device__ GroupCounters span_group(const Inst& I, const SmallE& S, const Energy
         ctr.visits += (unsigned long long)committed;
         ctr.feasible += Bv < kINF;
     }
+    // producers for later two-loops, one state per wave from the last wave down, so that they
+    // overlap phase 2 (they read typed values and earlier spans only)
+    int64_t lm0 = kINF, lm1 = kINF;
+    if (g >= 5)
+        for (int k = nw - 1 - wave; k < wa + wb; k += nw)
+            produce_state(I, S, G, p, g, k, a_lo, b_lo, wa, wb, lane, lm0, lm1);
+    lm0 = wave_min(lm0);
+    lm1 = wave_min(lm1);
+    if (lane == 0) {
+        G.red[wave][0] = lm0;
+        G.red[wave][1] = lm1;
+    }
     __syncthreads();
-    // appends in start-state order per right endpoint (this group owns C_b in this step)
-    if (tid == 0) {
-        for (int ib = 0; ib < wb; ib++) {
-            const int b = b_lo + ib;
+    if (wave == 0) {
+        // LM: layer-pair minimum of the both-separable form
+        if (lane == 0 && g >= 5) {
+            int64_t r0 = kINF, r1 = kINF;
+            for (int w = 0; w < nw; w++) {
+                r0 = mn(r0, G.red[w][0]);
+                r1 = mn(r1, G.red[w][1]);
+            }
+            I.LM[lm_idx(p, g, 0)] = norm_inf(r0);
+            I.LM[lm_idx(p, g, 1)] = norm_inf(r1);
+        }
+        // appends in start-state order, one lane per right endpoint (this group owns C_b in
+        // this step)
+        int added = 0;
+        if (lane < wb) {
+            const int b = b_lo + lane;
             const int committed = I.ccnt[b];
-            int added = 0;
             for (int ia = 0; ia < wa; ia++) {
-                const int ci = ia * wb + ib;
+                const int ci = ia * wb + lane;
                 if (!G.keep[ci]) continue;
                 const int slot = committed + added;
                 if (slot < I.ccap[b]) {
@@ -616,132 +738,10 @@ __device__ GroupCounters span_group(const Inst& I, const SmallE& S, const Energy
                 added++;
             }
             if (added) I.ccnt[b] = min(committed + added, I.ccap[b]);
-            ctr.appends += added;
         }
-    }
-    // producers for later two-loops: IDL (per left inner state), JDL (per right inner state),
-    // LM (layer-pair minimum of the both-separable form)
-    if (g >= 5) {
-        // one-sided tables (inputs from spans <= g - 3): one wave per state; lanes 0..26 take the
-        // separable length 3 + lane in class 0 (explicit side 2..4 bases), lanes 32..58 the same
-        // lengths in the 1xn class (explicit side of one base); then min-reductions per half-wave.
-        for (int k = wave; k < wa + wb; k += nw) {
-            const bool left = k < wa;
-            const int st = left ? a_lo + k : b_lo + (k - wa);
-            const int h = lane >> 5, ls = 3 + (lane & 31), g2 = g - ls;
-            // left: consumer closing layers (p - 1 - l1, p + g + 1) with c = st in layer p;
-            // right: consumer closing layers (p - 1, q + l2 + 1) with d = st in layer q
-            const int qc = p + g + 1, pc = p - 1;
-            const bool sep = left ? sep_right(qc, ls) : (pc >= 0 && sep_left(pc, ls));
-            const bool ok = (lane & 31) < 27 && g2 >= 5 && sep;
-            const int64_t ptail = !ok ? 0 : left ? PRt(I, qc, ls) : PLt(I, pc, ls);
-            int64_t r[12];
-#pragma unroll
-            for (int j = 0; j < 12; j++) r[j] = kINF;
-            if (ok) {
-                const int X = h ? 2 : 0;
-#pragma unroll
-                for (int lab = 0; lab < 4; lab++) {
-                    const int64_t in = left ? I.IDL[ring_idx(st, g2, X, lab)] : I.JDL[ring_idx(st, g2, X, lab)];
-                    if (in >= kINF) continue;
-#pragma unroll
-                    for (int l = 1; l <= 3; l++) {  // explicit length: h ? 1 : l + 1
-                        const int le = h ? 1 : l + 1;
-                        if (h && l > 1) continue;
-                        if (le + ls > kMaxLoop) continue;
-                        if (le == 2 && ls == 3) continue;  // 2x3 / 3x2: evaluated per pair
-                        const int32_t eb = left ? interior_base(S, le, ls) : interior_base(S, ls, le);
-                        r[(l - 1) * 4 + lab] = in + fx(eb, s) + ptail;
-                    }
-                }
-            }
-#pragma unroll
-            for (int j = 0; j < 12; j++) {
-                int64_t v = r[j];
-#pragma unroll
-                for (int o = 1; o < 32; o <<= 1) v = mn(v, __shfl_xor(v, o, 64));
-                r[j] = v;
-            }
-            int64_t* T = left ? I.RS : I.LS;
-            // lane 0 writes explicit lengths 2..4, lane 32 explicit length 1
-            if (lane == 0)
-                for (int j = 0; j < 12; j++) T[rs_idx(st, g, 2 + j / 4, j & 3)] = norm_inf(r[j]);
-            if (lane == 32)
-                for (int j = 0; j < 4; j++) T[rs_idx(st, g, 1, j)] = norm_inf(r[j]);
-        }
-        // bulge rings
-        for (int k = tid; k < wa + wb; k += blockDim.x) {
-            int64_t acc = kINF;
-            if (k < wa) {
-                for (int ib = 0; ib < wb; ib++) {
-                    const int64_t td = I.tail[b_lo + ib];
-                    for (int tp = 0; tp < 6; tp++) {
-                        const int64_t vin = G.vbuf[k * wb + ib][tp];
-                        if (vin < kINF) acc = mn(acc, vin + td + fx(au_pen(S, tp), s));
-                    }
-                }
-                I.BI[(int64_t)(a_lo + k) * kLMRing + (g & (kLMRing - 1))] = norm_inf(acc);
-            } else {
-                const int ib = k - wa;
-                for (int ia = 0; ia < wa; ia++)
-                    for (int tp = 0; tp < 6; tp++) {
-                        const int64_t vin = G.vbuf[ia * wb + ib][tp];
-                        if (vin < kINF) acc = mn(acc, vin + fx(au_pen(S, tp), s));
-                    }
-                I.BJ[(int64_t)(b_lo + ib) * kLMRing + (g & (kLMRing - 1))] = norm_inf(acc);
-            }
-        }
-        int64_t lm0 = kINF, lm1 = kINF;
-        for (int k = tid; k < wa * 12 + wb * 12; k += blockDim.x) {
-            const bool left = k < wa * 12;
-            const int kk = left ? k : k - wa * 12;
-            const int i = kk / 12, X = (kk >> 2) % 3, xx = kk & 3;
-            int64_t acc = kINF;
-            const int nother = left ? wb : wa;
-            for (int o = 0; o < nother; o++) {
-                const int ci = left ? i * wb + o : o * wb + i;
-                const int other = left ? b_lo + o : a_lo + o;
-                for (int tp = 0; tp < 6; tp++) {
-                    const int64_t vin = G.vbuf[ci][tp];
-                    if (vin >= kINF) continue;
-                    for (int z = 0; z < 4; z++) {
-                        // left: vary x_{l+1} = z with alpha(d); right: vary x_{k-1} = z with beta(c)
-                        const int64_t w = left ? I.alphaU[other * 4 + z] : I.betaU[other * 4 + z];
-                        if (w < kINF)
-                            acc = mn(acc, vin + w + fx(left ? mmx(S, X, kRev[tp], z, xx) : mmx(S, X, kRev[tp], xx, z), s));
-                    }
-                }
-            }
-            acc = norm_inf(acc);
-            if (left) {
-                const int c = a_lo + i;
-                I.IDL[ring_idx(c, g, X, xx)] = acc;
-                const int64_t be = I.betaU[c * 4 + xx];
-                if (acc < kINF && be < kINF) {
-                    if (X == 0) lm0 = mn(lm0, acc + be);
-                    if (X == 1) lm1 = mn(lm1, acc + be);
-                }
-            } else {
-                I.JDL[ring_idx(b_lo + i, g, X, xx)] = acc;
-            }
-        }
-        lm0 = wave_min(lm0);
-        lm1 = wave_min(lm1);
-        __syncthreads();
-        if (lane == 0) {
-            G.red[wave][0] = lm0;
-            G.red[wave][1] = lm1;
-        }
-        __syncthreads();
-        if (tid == 0) {
-            int64_t r0 = kINF, r1 = kINF;
-            for (int w = 0; w < nw; w++) {
-                r0 = mn(r0, G.red[w][0]);
-                r1 = mn(r1, G.red[w][1]);
-            }
-            I.LM[lm_idx(p, g, 0)] = norm_inf(r0);
-            I.LM[lm_idx(p, g, 1)] = norm_inf(r1);
-        }
+        added += __shfl_xor(added, 1, 64);
+        added += __shfl_xor(added, 2, 64);
+        ctr.appends += (unsigned long long)added;
     }
     return ctr;
 }
@@ -790,11 +790,12 @@ __device__ __forceinline__ void flush_counters(const Inst& I, const GroupCounter
 }
 
 // ---- the span step (plain mode): block x < layer pairs handles layer pair (x, x + g) -------------
-__global__ __launch_bounds__(256) void k_span(Inst I, const EnergyTables* __restrict__ E,
-                                              const int32_t* __restrict__ spec, int g,
-                                              int ext_layer, int nblk_cells) {
+template <int NT>
+__global__ __launch_bounds__(NT) void k_span(Inst I, const EnergyTables* __restrict__ E,
+                                             const int32_t* __restrict__ spec, int g,
+                                             int ext_layer, int nblk_cells) {
     __shared__ SmallE S;
-    __shared__ int64_t red[256];
+    __shared__ int64_t red[NT];
     __shared__ GroupShared G;
     stage_tables(S, E);
     __syncthreads();
@@ -914,10 +915,10 @@ __global__ __launch_bounds__(NT) void k_persistent(const Inst* __restrict__ inst
                 if (pref[mid] <= item) lo = mid;
                 else hi = mid - 1;
             }
-            // the instance index is block-uniform: its descriptor is read with scalar loads
+            // the instance index is block-uniform: its descriptor is copied with scalar loads
             const int inst = __builtin_amdgcn_readfirstlane(lo);
             const int local = item - pref[inst], g = g0s[inst] + step;
-            const Inst& I = insts[inst];
+            const Inst I = insts[inst];
             const int n = I.n, ncell_items = g <= n ? n - g + 1 : 0;
             if (local < ncell_items) {
                 GroupCounters c = span_group(I, S, E, spec, local, local + g, G);
@@ -1024,12 +1025,17 @@ hipError_t launch_init(const Inst& I, hipStream_t st) {
 
 // one span step: cells of span g plus the external column of layer ext_layer (or -1)
 hipError_t launch_span(const Inst& I, const EnergyTables* E, const int32_t* spec, int g,
-                       int ext_layer, hipStream_t st) {
+                       int ext_layer, int threads, hipStream_t st) {
     const int layers = I.n - g + 1;
     const int nblk = layers > 0 ? layers : 0;
     const int total = nblk + (ext_layer >= 0 ? 1 : 0);
     if (total == 0) return hipSuccess;
-    hipLaunchKernelGGL(k_span, dim3(total), dim3(256), 0, st, I, E, spec, g, ext_layer, nblk);
+    switch (threads) {
+    case 256: hipLaunchKernelGGL(k_span<256>, dim3(total), dim3(256), 0, st, I, E, spec, g, ext_layer, nblk); break;
+    case 512: hipLaunchKernelGGL(k_span<512>, dim3(total), dim3(512), 0, st, I, E, spec, g, ext_layer, nblk); break;
+    case 1024: hipLaunchKernelGGL(k_span<1024>, dim3(total), dim3(1024), 0, st, I, E, spec, g, ext_layer, nblk); break;
+    default: return hipErrorInvalidValue;
+    }
     return hipGetLastError();
 }
 

@@ -408,6 +408,29 @@ int build_lattice(const char* protein, const CodonTable& T, const Params& P, dou
                 h = std::min(h, L.in_U[j] + L.in_U[j2]);
             }
         }
+    // outer minima of one-sided interior loops, per state, closing type t, mismatch class X
+    // (0 generic, 1 2x3, 2 1xn) and boundary label x:
+    //   OB(b1, t, X, x) = min_o beta(b1, o) + mm_X[t][x][o]    (x = x_{i+1}, o = x_{j-1})
+    //   OA(a1, t, X, x) = min_o alpha(a1, o) + mm_X[t][o][x]   (o = x_{i+1}, x = x_{j-1})
+    L.OB.assign((size_t)72 * N, kINF);
+    L.OA.assign((size_t)72 * N, kINF);
+    {
+        const int32_t(*mm[3])[4][4] = {P.E.mmI, P.E.mm23, P.E.mm1n};
+        const int64_t unit = (int64_t)1 << shift;
+        for (int v = 0; v < N; v++)
+            for (int t = 0; t < 6; t++)
+                for (int X = 0; X < 3; X++)
+                    for (int x = 0; x < 4; x++) {
+                        int64_t rb = kINF, ra = kINF;
+                        for (int o = 0; o < 4; o++) {
+                            const int64_t be = L.betaU[4 * v + o], al = L.alphaU[4 * v + o];
+                            if (be < kINF) rb = std::min(rb, be + (int64_t)mm[X][t][x][o] * unit);
+                            if (al < kINF) ra = std::min(ra, al + (int64_t)mm[X][t][o][x] * unit);
+                        }
+                        L.OB[(size_t)72 * v + (t * 3 + X) * 4 + x] = rb;
+                        L.OA[(size_t)72 * v + (t * 3 + X) * 4 + x] = ra;
+                    }
+    }
     // label paths of 1..4 edges out of / into every state (explicit short loop segments)
     L.fwd_off.assign((size_t)4 * N + 1, 0);
     L.bwd_off.assign((size_t)4 * N + 1, 0);
