@@ -1,29 +1,39 @@
 """Benchmark of the exact coding-sequence design DP on one MI355X.
 
-    python bench.py [--gpus 1] [--steps K] [--warmup W] [--workload config2|config3|batch]
+    python bench.py [--gpus 1] [--steps K] [--warmup W]
+                    [--workload config2|config3|batch|served] [--no-cpu-baseline]
 
-A step is one pass of the whole path (input build, forward fill, canonical traceback, result
-strings) over one batch of synthetic input:
+A step is one pass of the whole path over one batch of synthetic input.  Inputs are protein
+strings handed to the C ABI; the library builds the automaton, uploads it, fills the DP on the
+GPU, runs the canonical traceback and returns the result strings.
   config2 (default): one 300-aa synthetic protein (Met + 298 uniform residues + stop, seed 1),
                      designed at lambda = 0 and lambda = 4 in plain mode (one span-step kernel
                      launch per span length);
-  config3:           the 925-aa and 1,976-aa proteins at lambda = 0 and 4 (plain mode);
-  batch:             256 proteins, lengths log-uniform in [50, 1000] aa, half at lambda = 0 and
-                     half at lambda = 4, in one batched call.
-`value` is DP cells per second over the timed steps (cells = state pairs (a, b) with
-rho(a) < rho(b), summed over the step's designs).  One JSON line is printed.
+  config3:           the 925-aa and 1,976-aa proteins (seed 1) at lambda = 0 and 4, plain mode;
+  batch:             256 proteins, lengths log-uniform in [50, 1000] aa (seed 7), half at
+                     lambda = 0 and half at lambda = 4, in one batched persistent launch;
+  served:            a Poisson request stream through the continuous-batching server, with the
+                     learned candidate sizer against worst-case sizing (see served_workload).
+
+`value` is DP cells per second of fill time, summed over the step's designs (a cell is a state
+pair (a, b) with rho(a) < rho(b)); fill time is the cost-only interval of the method: device
+allocation, the O(N) input upload and the forward fill, without automaton build and traceback.
+`complete_cells_per_s` and `designs_per_min` use complete time (input strings to result
+strings).  One JSON line is printed.
 
 Roofline of the dominant kernel (the span step): algorithmic HBM bytes per launch =
 (72 B per cell for the V/B/S1/S2 writes + 20 B per candidate visit + 12 B per appended
 candidate) / launches, divided by the kernel's average duration measured with HIP events on the
 library's stream.  `traffic` comes from the committed rocprofv3 counter summary if it was taken
 on the current kernel source, else null.  `cpu_baseline` times the CPU oracle (test
-infrastructure, dense O(N^3) reference) on one design of the same workload.
+infrastructure, dense O(N^3) reference) on a bounded sample of the same workload.
 """
 import argparse
 import hashlib
 import json
+import math
 import os
+import random
 import sys
 import time
 
@@ -31,6 +41,7 @@ ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
 PEAK_HBM_GBS = 8000.0
+PEAK_VALU_LANE_OPS = 256 * 4 * 16 * 2.4e9  # CUs x SIMDs x lanes x clock
 BYTES_PER_CELL = 72    # V (6 x int64) + B + S1 + S2 written once per cell
 BYTES_PER_VISIT = 20   # candidate start state (4) + B(c,b) (8) + gathered S1(a,c) (8)
 BYTES_PER_APPEND = 12  # appended (c, B) entry
@@ -62,14 +73,15 @@ def kernel_source_sha():
     return h.hexdigest()
 
 
-def traffic_from_profiles(name):
-    path = os.path.join(ROOT, "profiles", f"k_span_{name}_traffic.json")
+def profile_record(name):
+    """Counter summary committed under profiles/, if taken on the current kernel source."""
+    path = os.path.join(ROOT, "profiles", f"k_span_{name}_counters.json")
     if not os.path.exists(path):
         return None
     d = json.load(open(path))
     if d.get("kernel_source_sha256") != kernel_source_sha():
         return None  # counters were taken on an older kernel
-    return d.get("hbm_bytes_per_launch")
+    return d
 
 
 def run_step(ctx, items, table, params, batch):
@@ -78,21 +90,184 @@ def run_step(ctx, items, table, params, batch):
     return [ctx.design(p, table, params, lam) for p, lam in items]
 
 
+def cpu_model():
+    try:
+        for line in open("/proc/cpuinfo"):
+            if line.startswith("model name"):
+                return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    return "unknown"
+
+
 def cpu_baseline(items):
+    """The oracle, as it stands, on the host cores: every design of the sample on all cores,
+    then the first one on a single thread (bounded to about 10-30 s of CPU work)."""
     import oracle as O
     import sdinputs as S
     threads = int(os.environ.get("OMP_NUM_THREADS", os.cpu_count() or 1))
     P = O.Params(S.default_params_path())
     w = S.codon_weights(2026)
-    # bounded sample: the first design of the workload whose dense oracle finishes in ~30 s
-    p, lam = min(items, key=lambda x: len(x[0]))
-    if len(p) > 400:
-        p = p[:300]  # a 300-residue prefix of the same protein keeps the sample bounded
+    sample = [(p, lam) for p, lam in items if len(p) <= 400]
+    note = "the workload's designs"
+    if not sample:
+        # proteins too long for the dense O(N^3) oracle: 300-residue prefixes stand in
+        sample = [(p[:300], lam) for p, lam in items[:2]]
+        note = "300-residue prefixes of the workload's first designs"
+    sample = sample[:2]
+    cells = 0
     t = time.time()
-    d = O.design(p, w, P, lam, nthreads=threads)
+    for p, lam in sample:
+        cells += O.design(p, w, P, lam, nthreads=threads).n_cells
     dt = time.time() - t
-    return {"value": d.n_cells / dt, "unit": "cells/s", "cores": threads, "kind": "oracle",
-            "sample": f"dense oracle, one design of {len(p)} aa at lambda={lam} ({d.n_cells} cells, {dt:.2f} s)"}
+    p1, lam1 = sample[0]
+    t = time.time()
+    c1 = O.design(p1, w, P, lam1, nthreads=1).n_cells
+    dt1 = time.time() - t
+    return {"value": cells / dt, "unit": "cells/s", "cores": threads, "kind": "oracle",
+            "sample": f"dense oracle on {note}: {len(sample)} design(s) of {len(sample[0][0])} aa "
+                      f"({cells} cells, {dt:.2f} s on {threads} threads); single thread {c1 / dt1:.4g} cells/s "
+                      f"({dt1:.2f} s)",
+            "single_thread_value": c1 / dt1, "cpu_model": cpu_model(), "os_cpu_count": os.cpu_count()}
+
+
+def per_design_stats(items, results):
+    out = {}
+    for (p, lam), r in list(zip(items, results))[:4]:
+        n = 3 * len(p)
+        out[f"{len(p)}aa_lambda{lam:g}"] = {
+            "energy": r.energy, "objective_kcal": r.objective_kcal, "Z": r.n_candidates,
+            "Z_over_n2": r.n_candidates / n ** 2, "Z_over_B_finite": r.n_candidates / max(r.n_feasible, 1),
+            "visits": r.n_visits, "cells": r.n_cells, "t_fill_s": r.t_fill_s, "t_total_s": r.t_total_s}
+    return out
+
+
+def roofline_for(results_steps, counters, batch):
+    alg_bytes = launches = ktime = 0.0
+    for step in results_steps:
+        for r in step:
+            alg_bytes += BYTES_PER_CELL * r.n_cells + BYTES_PER_VISIT * r.n_visits + BYTES_PER_APPEND * r.n_candidates
+            launches += r.n_span_launches
+            ktime += r.t_span_kernels_s
+        if batch:
+            launches += 1  # one persistent launch per batched call
+    avg_launch_s = ktime / launches if launches else float("nan")
+    per_launch = alg_bytes / launches if launches else 0.0
+    achieved = per_launch / avg_launch_s / 1e9 if ktime > 0 else 0.0
+    roof = {"bound": "hbm", "kernel": "k_persistent" if batch else "k_span", "achieved": achieved, "peak": PEAK_HBM_GBS,
+            "unit": "GB/s", "frac": achieved / PEAK_HBM_GBS,
+            "traffic": counters.get("hbm_bytes_per_launch") if counters else None,
+            "alg_bytes_per_launch": per_launch, "avg_launch_us": avg_launch_s * 1e6, "launches": int(launches)}
+    if counters and counters.get("valu_insts_per_launch"):
+        lane_ops = counters["valu_insts_per_launch"] * 64
+        roof["valu_lane_ops_per_launch"] = lane_ops
+        roof["valu_frac"] = lane_ops / avg_launch_s / PEAK_VALU_LANE_OPS
+    return roof
+
+
+def progress(msg):
+    print(msg, file=sys.stderr, flush=True)
+
+
+def served_workload(args, sd, S):
+    """Continuous-batching server on a Poisson stream, learned sizer against worst-case sizing.
+
+    Requests: lengths log-uniform in [50, 2000] aa, lambda uniform in {0, 4}, protein seeds
+    200000 + i, arrival times from a seeded exponential.  The sizer is trained on the exact
+    DP's own occupancy logs of synthetic proteins (seeds 100000 + i, lengths log-uniform in
+    [50, 600] to keep the logging run short), 10 % held out.  The plain GPU DP on the same
+    requests, one after another, gives the capacity that sets the offered load.
+    """
+    params = sd.Params(S.default_params_path())
+    table = sd.CodonTable(S.codon_weights(2026))
+    ctx = sd.Context(0)
+    nreq, ntrain, K = args.requests, args.train_proteins, 8
+    # learned sizer: exact occupancy logs -> FP32 MLP trained on the GPU
+    tl = S.batch_lengths(ntrain, 50, 600, seed=100000)
+    train = [S.protein(A, 100000 + i) for i, A in enumerate(tl)]
+    tlam = [0.0 if i % 2 == 0 else 4.0 for i in range(ntrain)]
+    t = time.time()
+    Y, _ = ctx.occupancy(train, tlam, table, params, K)
+    t_log = time.time() - t
+    progress(f"occupancy log of {ntrain} proteins: {t_log:.1f} s")
+    import numpy as np
+    X = np.stack([sd.features(p, l) for p, l in zip(train, tlam)]).astype(np.float32)
+    cut = int(0.9 * ntrain)
+    sizer = sd.Sizer(ctx, 64, K, seed=11)
+    t = time.time()
+    sizer.train(X[:cut], Y[:cut], steps=2000, lr=3e-3)
+    t_train = time.time() - t
+    held = float(np.mean((sizer.predict(X[cut:]) - Y[cut:]) ** 2))
+    progress(f"sizer trained in {t_train:.1f} s, held-out MSE {held:.3g}")
+    # request stream
+    rl = S.batch_lengths(nreq, 50, 2000, seed=11)
+    rng = random.Random(11)
+    reqs = [(S.protein(A, 200000 + i), rng.choice([0.0, 4.0])) for i, A in enumerate(rl)]
+    cells_total = 0
+    t = time.time()
+    plain = []
+    for i, (p, lam) in enumerate(reqs):
+        plain.append(ctx.design(p, table, params, lam))
+        if i % 20 == 19:
+            progress(f"plain {i + 1}/{nreq}")
+    t_plain = time.time() - t
+    cells_total = sum(r.n_cells for r in plain)
+    capacity = nreq / t_plain  # designs/s, plain, one after another
+    ctx.close()
+
+    def serve(policy, rho):
+        c = sd.Context(0)
+        if policy == "mlp":
+            c.set_sizer(sizer, margin=0.5, slack=8)
+        srv = sd.Server(c, table, params, pool_bytes=args.pool_gib << 30, max_active=256, steps_per_round=32)
+        arng = random.Random(12)
+        t0 = time.perf_counter()
+        tickets, t_sub = [], []
+        next_t = 0.0
+        for p, lam in reqs:
+            if rho > 0:
+                next_t += arng.expovariate(rho * capacity)
+                dt = t0 + next_t - time.perf_counter()
+                if dt > 0:
+                    time.sleep(dt)
+            t_sub.append(time.perf_counter() - t0)
+            tickets.append(srv.submit(p, lam))
+        res = []
+        for i, tk in enumerate(tickets):
+            res.append(srv.wait(tk))
+            if i % 20 == 19:
+                progress(f"served {policy} load {rho}: {i + 1}/{nreq}")
+        st = srv.stats()
+        srv.stop()
+        c.close()
+        lat = sorted(r.t_total_s for r in res)
+        done = max(ts + r.t_total_s for ts, r in zip(t_sub, res))
+        same = all((a.energy, a.objective_fixed, a.mrna, a.structure) == (b.energy, b.objective_fixed, b.mrna, b.structure)
+                   for a, b in zip(res, plain))
+        return {"policy": policy, "offered_load": rho if rho > 0 else "saturated",
+                "designs_per_min": nreq / done * 60.0, "cells_per_s": cells_total / done,
+                "p50_s": lat[len(lat) // 2], "p99_s": lat[min(len(lat) - 1, int(math.ceil(0.99 * len(lat))) - 1)],
+                "peak_active": st["peak_active"], "fallbacks": st["fallbacks"], "rounds": st["rounds"],
+                "reserved_bytes_per_request": st["reserved_bytes"] / nreq,
+                "reserved_cand_bytes_per_request": st["reserved_cand_bytes"] / nreq,
+                "pool_high_water": st["pool_high_water"], "identical_to_plain": same}
+
+    runs = [serve("worst", 0.0), serve("mlp", 0.0), serve("worst", 0.8), serve("mlp", 0.8), serve("mlp", 0.95)]
+    sat = runs[1]
+    line = {
+        "metric": METRIC, "value": sat["cells_per_s"], "unit": "cells/s", "n_gpus": 1, "steps": 1, "warmup": 0,
+        "ms_per_step": nreq / sat["designs_per_min"] * 60.0 * 1e3, "higher_is_better": True, "scaling": "weak",
+        "vs_baseline": None, "dtype": "int64", "data": "synthetic",
+        "config": {"workload": f"served: {nreq} requests, lengths log-uniform in [50,2000] aa, lambda in {{0,4}}, "
+                               f"Poisson arrivals, pool {args.pool_gib} GiB, learned sizer", "requests": nreq,
+                   "aa_range": [50, 2000], "mode": "served"},
+        "plain_sequential": {"designs_per_min": nreq / t_plain * 60.0, "cells_per_s": cells_total / t_plain,
+                             "p50_s": sorted(r.t_total_s for r in plain)[nreq // 2]},
+        "served_runs": runs,
+        "sizer": {"train_proteins": ntrain, "train_aa_range": [50, 600], "bins": K, "hidden": 64,
+                  "occupancy_log_s": t_log, "train_s": t_train, "heldout_mse": held},
+    }
+    print(json.dumps(line), flush=True)
 
 
 def main():
@@ -100,8 +275,11 @@ def main():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=5)
     ap.add_argument("--warmup", type=int, default=1)
-    ap.add_argument("--workload", default="config2", choices=["config2", "config3", "batch"])
+    ap.add_argument("--workload", default="config2", choices=["config2", "config3", "batch", "served"])
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--requests", type=int, default=100, help="served: number of requests")
+    ap.add_argument("--train-proteins", type=int, default=200, help="served: proteins in the occupancy log")
+    ap.add_argument("--pool-gib", type=int, default=8, help="served: device pool of the server")
     ap.add_argument("--copy-calibration-mib", type=int, default=0,
                     help="only run a plain device copy of this many MiB (counter calibration)")
     args = ap.parse_args()
@@ -123,6 +301,9 @@ def main():
     import paper_2609_32308_amd as sd
     import sdinputs as S
 
+    if args.workload == "served":
+        served_workload(args, sd, S)
+        return
     items, config = workload(args.workload)
     batch = args.workload == "batch"
     ctx = sd.Context(0, kernel_timing=True)
@@ -137,22 +318,12 @@ def main():
     t1 = time.perf_counter()
     elapsed = t1 - t0
     step_cells = sum(r.n_cells for r in results[0])
+    fill = sum(r.t_fill_s for s_ in results for r in s_)
     designs = len(items) * args.steps
-    value = step_cells * args.steps / elapsed
-    # dominant kernel: the span step
-    alg_bytes = launches = ktime = 0.0
-    for step in results:
-        for r in step:
-            alg_bytes += BYTES_PER_CELL * r.n_cells + BYTES_PER_VISIT * r.n_visits + BYTES_PER_APPEND * r.n_candidates
-            launches += r.n_span_launches
-            ktime += r.t_span_kernels_s
-    avg_launch_s = ktime / launches if launches else float("nan")
-    per_launch = alg_bytes / launches if launches else 0.0
-    achieved = per_launch / avg_launch_s / 1e9 if ktime > 0 else 0.0
-    traffic = traffic_from_profiles(args.workload)
+    counters = profile_record(args.workload)
     line = {
         "metric": METRIC,
-        "value": value,
+        "value": step_cells * args.steps / fill,
         "unit": "cells/s",
         "n_gpus": 1,
         "steps": args.steps,
@@ -164,15 +335,12 @@ def main():
         "dtype": "int64",
         "data": "synthetic",
         "config": config,
+        "complete_cells_per_s": step_cells * args.steps / elapsed,
         "designs_per_min": designs / elapsed * 60.0,
-        "fill_cells_per_s": step_cells * args.steps / sum(r.t_fill_s for s_ in results for r in s_),
-        "per_lambda": {str(lam): {"energy": r.energy, "objective_kcal": r.objective_kcal,
-                                  "Z": r.n_candidates, "visits": r.n_visits, "t_fill_s": r.t_fill_s}
-                       for (p, lam), r in list(zip(items, results[-1]))[:4]},
-        "roofline": {"bound": "hbm", "kernel": "k_span", "achieved": achieved, "peak": PEAK_HBM_GBS,
-                     "unit": "GB/s", "frac": achieved / PEAK_HBM_GBS,
-                     "traffic": traffic, "alg_bytes_per_launch": per_launch,
-                     "avg_launch_us": avg_launch_s * 1e6, "launches": int(launches)},
+        "fill_ms_per_step": fill / args.steps * 1e3,
+        "per_design": per_design_stats(items, results[-1]),
+        "roofline": roofline_for(results, counters, batch),
+        "params_sha256": params.sha256,
     }
     ctx.close()
     if not args.no_cpu_baseline:

@@ -64,7 +64,7 @@ typedef struct sd_options {
     int kernel_timing;     /* 1: bracket every span-step launch with HIP events on the
                               context's stream and report the summed kernel time            */
     int span_threads;      /* workgroup size of the plain-mode span step: 0 (library choice),
-                              256, 512 or 1024; anything else gives SD_E_ARG at create     */
+                              64, 256, 512 or 1024; anything else gives SD_E_ARG at create */
     int reserved[4];
 } sd_options;
 

@@ -144,9 +144,10 @@ extern "C" sd_status sd_context_create(int device, const sd_options* opt, sd_con
     c->num_cu = prop.multiProcessorCount;
     if (opt) c->opt = *opt;
     if (c->opt.span_threads == 0) c->opt.span_threads = 256;
-    if (c->opt.span_threads != 256 && c->opt.span_threads != 512 && c->opt.span_threads != 1024) {
+    if (c->opt.span_threads != 64 && c->opt.span_threads != 256 && c->opt.span_threads != 512 &&
+        c->opt.span_threads != 1024) {
         delete c;
-        return fail(SD_E_ARG, "span_threads must be 0, 256, 512 or 1024");
+        return fail(SD_E_ARG, "span_threads must be 0, 64, 256, 512 or 1024");
     }
     e = hipSetDevice(device);
     if (e == hipSuccess) e = hipStreamCreateWithFlags(&c->stream, hipStreamNonBlocking);
@@ -209,67 +210,22 @@ sd_status ensure_arena(sd_context* c, size_t bytes) {
     return SD_OK;
 }
 
-// Device layout of one instance: region A holds the read-only inputs and the small mutable
-// arrays (uploaded from one staged host image), region B the O(N^2) tables and the rings.
-// With null bases only the sizes are computed.
+// Device layout of one instance (see the Inst declaration): region A holds the read-only inputs
+// and the small mutable arrays (uploaded from one staged host image), region B the O(N^2)
+// tables and the rings.  With null bases only the sizes are computed.  Every array's extent is
+// checked against its slot on the host, so a kernel indexing within an array's documented
+// size stays inside the instance's regions.
 InstLayout layout_instance(const Lattice& L, char* A, char* B, Inst& I) {
-    uintptr_t oa = 0, ob = 0;
-    auto ta = [&](size_t bytes) -> char* {
-        oa = (oa + 255) & ~(uintptr_t)255;
-        char* p = (char*)((uintptr_t)A + oa);
-        oa += bytes;
-        return p;
-    };
-    auto tb = [&](size_t bytes) -> char* {
-        ob = (ob + 255) & ~(uintptr_t)255;
-        char* p = (char*)((uintptr_t)B + ob);
-        ob += bytes;
-        return p;
-    };
-    const size_t N = L.N, n = L.n, nE = L.in_src.size(), cells = L.cells, slots = L.cand_slots;
-    I.layer = (int*)ta(N * 4);
-    I.off = (int*)ta((n + 2) * 4);
-    I.out_dst = (int*)ta(4 * N * 4);
-    I.out_U = (int64_t*)ta(4 * N * 8);
-    I.in_start = (int*)ta((N + 1) * 4);
-    I.in_src = (int*)ta(nE * 4);
-    I.in_lab = (int*)ta(nE * 4);
-    I.in_U = (int64_t*)ta(nE * 8);
-    I.tail = (int64_t*)ta(N * 8);
-    I.pfx = (int*)ta(N * 4);
-    I.P = (int64_t*)ta((L.A + 1) * 8);
-    I.hp_init = (int*)ta((n + 1) * 4);
-    I.rowoff = (int64_t*)ta(N * 8);
-    I.coff = (int64_t*)ta(N * 8);
-    I.ccap = (int*)ta(N * 4);
-    I.alphaU = (int64_t*)ta(4 * N * 8);
-    I.betaU = (int64_t*)ta(4 * N * 8);
-    I.fwd_off = (int*)ta(L.fwd_off.size() * 4);
-    I.fwd_meta = (int*)ta(L.fwd_meta.size() * 4);
-    I.fwd_cost = (int64_t*)ta(L.fwd_cost.size() * 8);
-    I.bwd_off = (int*)ta(L.bwd_off.size() * 4);
-    I.bwd_meta = (int*)ta(L.bwd_meta.size() * 4);
-    I.bwd_cost = (int64_t*)ta(L.bwd_cost.size() * 8);
-    I.hpB = (int64_t*)ta(L.hpB.size() * 8);
-    I.OB = (int64_t*)ta(L.OB.size() * 8);
-    I.OA = (int64_t*)ta(L.OA.size() * 8);
-    I.ccnt = (int*)ta(N * 4);
-    I.X = (int64_t*)ta(N * 8);
-    I.stats = (unsigned long long*)ta(4 * 8);
-    I.span_appends = (unsigned long long*)ta((n + 1) * 8);
-    I.LM = (int64_t*)tb((size_t)kLMRing * (n + 1) * 2 * 8);
-    I.IDL = (int64_t*)tb((size_t)N * kLMRing * 12 * 8);
-    I.JDL = (int64_t*)tb((size_t)N * kLMRing * 12 * 8);
-    I.BI = (int64_t*)tb((size_t)N * kLMRing * 8);
-    I.BJ = (int64_t*)tb((size_t)N * kLMRing * 8);
-    I.RS = (int64_t*)tb((size_t)N * kLMRing * 16 * 8);
-    I.LS = (int64_t*)tb((size_t)N * kLMRing * 16 * 8);
-    I.V = (int64_t*)tb(cells * 6 * 8);
-    I.Bt = (int64_t*)tb(cells * 8);
-    I.S1 = (int64_t*)tb(cells * 8);
-    I.S2 = (int64_t*)tb(cells * 8);
-    I.cc = (int*)tb(slots * 4);
-    I.cB = (int64_t*)tb(slots * 8);
+    const int64_t N = L.N, n = L.n;
+    int64_t m = std::max<int64_t>(N + 2, std::max<int64_t>(n + 2, (int64_t)L.A + 1));
+    I.U = (8 * m + 255) & ~(int64_t)255;
+    I.ra = A;
+    I.rb = B;
+    I.nE = (int64_t)L.in_src.size();
+    I.nF = (int64_t)L.fwd_meta.size();
+    I.nB = (int64_t)L.bwd_meta.size();
+    I.cells = L.cells;
+    I.slots = L.cand_slots;
     I.n = L.n;
     I.N = L.N;
     I.A = L.A;
@@ -277,9 +233,35 @@ InstLayout layout_instance(const Lattice& L, char* A, char* B, Inst& I) {
     I.mlbase_fx = L.mlbase_fx;
     I.retain_all = 0;
     I.g0 = 1;
+    // extents against slots (units of U in region A, of R in region B)
+    struct Ext { const void* p; int64_t bytes; int64_t slot; };
+    const int64_t U = I.U, R = I.R();
+    const Ext ea[] = {
+        {I.layer(), 4 * N, U}, {I.off(), 4 * (n + 2), U}, {I.in_start(), 4 * (N + 1), U},
+        {I.tail(), 8 * N, U}, {I.pfx(), 4 * N, U}, {I.P(), 8 * ((int64_t)L.A + 1), U},
+        {I.hp_init(), 4 * (n + 1), U}, {I.rowoff(), 8 * N, U}, {I.coff(), 8 * N, U},
+        {I.ccap(), 4 * N, U}, {I.ccnt(), 4 * N, U}, {I.X(), 8 * N, U},
+        {I.out_dst(), 16 * N, 2 * U}, {I.out_U(), 32 * N, 4 * U}, {I.alphaU(), 32 * N, 4 * U},
+        {I.betaU(), 32 * N, 4 * U}, {I.fwd_off(), 4 * (int64_t)L.fwd_off.size(), 3 * U},
+        {I.bwd_off(), 4 * (int64_t)L.bwd_off.size(), 3 * U}, {I.hpB(), 8 * (int64_t)L.hpB.size(), 16 * U},
+        {I.OB(), 8 * (int64_t)L.OB.size(), 72 * U}, {I.OA(), 8 * (int64_t)L.OA.size(), 72 * U},
+        {I.stats(), 32, U}, {I.span_appends(), 8 * (n + 1), U},
+        {I.LM(), 8 * (int64_t)kLMRing * (n + 1) * 2, 2 * R}, {I.IDL(), 8 * (int64_t)kLMRing * N * 12, 12 * R},
+        {I.JDL(), 8 * (int64_t)kLMRing * N * 12, 12 * R}, {I.BI(), 8 * (int64_t)kLMRing * N, R},
+        {I.BJ(), 8 * (int64_t)kLMRing * N, R}, {I.RS(), 8 * (int64_t)kLMRing * N * 16, 16 * R},
+        {I.LS(), 8 * (int64_t)kLMRing * N * 16, 16 * R}};
+    bool ok = (int64_t)L.fwd_off.size() == 4 * N + 1 && (int64_t)L.bwd_off.size() == 4 * N + 1 &&
+              (int64_t)L.hpB.size() == 16 * N && (int64_t)L.OB.size() == 72 * N && (int64_t)L.OA.size() == 72 * N;
+    for (const Ext& e : ea) ok = ok && e.bytes <= e.slot;
+    if (!ok) {
+        // a layout that does not hold its arrays is a library bug: refuse to place the instance
+        InstLayout bad;
+        bad.a_bytes = bad.b_bytes = 0;
+        return bad;
+    }
     InstLayout r;
-    r.a_bytes = (oa + 255) & ~(uintptr_t)255;
-    r.b_bytes = (ob + 255) & ~(uintptr_t)255;
+    r.a_bytes = (I.a_bytes() + 255) & ~(int64_t)255;
+    r.b_bytes = (I.b_bytes() + 255) & ~(int64_t)255;
     return r;
 }
 
@@ -288,32 +270,32 @@ void stage_inputs(const Lattice& L, const Inst& I, const char* devA, char* image
     auto put = [&](const void* dptr, const void* h, size_t bytes) {
         if (bytes) memcpy(image + ((const char*)dptr - devA), h, bytes);
     };
-    put(I.layer, L.layer.data(), L.layer.size() * 4);
-    put(I.off, L.off.data(), L.off.size() * 4);
-    put(I.out_dst, L.out_dst.data(), L.out_dst.size() * 4);
-    put(I.out_U, L.out_U.data(), L.out_U.size() * 8);
-    put(I.in_start, L.in_start.data(), L.in_start.size() * 4);
-    put(I.in_src, L.in_src.data(), L.in_src.size() * 4);
-    put(I.in_lab, L.in_lab.data(), L.in_lab.size() * 4);
-    put(I.in_U, L.in_U.data(), L.in_U.size() * 8);
-    put(I.tail, L.tail.data(), L.tail.size() * 8);
-    put(I.pfx, L.pfx.data(), L.pfx.size() * 4);
-    put(I.P, L.P.data(), L.P.size() * 8);
-    put(I.hp_init, L.hp_init.data(), L.hp_init.size() * 4);
-    put(I.rowoff, L.rowoff.data(), L.rowoff.size() * 8);
-    put(I.coff, L.coff.data(), L.coff.size() * 8);
-    put(I.ccap, L.ccap.data(), L.ccap.size() * 4);
-    put(I.alphaU, L.alphaU.data(), L.alphaU.size() * 8);
-    put(I.betaU, L.betaU.data(), L.betaU.size() * 8);
-    put(I.fwd_off, L.fwd_off.data(), L.fwd_off.size() * 4);
-    put(I.fwd_meta, L.fwd_meta.data(), L.fwd_meta.size() * 4);
-    put(I.fwd_cost, L.fwd_cost.data(), L.fwd_cost.size() * 8);
-    put(I.bwd_off, L.bwd_off.data(), L.bwd_off.size() * 4);
-    put(I.bwd_meta, L.bwd_meta.data(), L.bwd_meta.size() * 4);
-    put(I.bwd_cost, L.bwd_cost.data(), L.bwd_cost.size() * 8);
-    put(I.hpB, L.hpB.data(), L.hpB.size() * 8);
-    put(I.OB, L.OB.data(), L.OB.size() * 8);
-    put(I.OA, L.OA.data(), L.OA.size() * 8);
+    put(I.layer(), L.layer.data(), L.layer.size() * 4);
+    put(I.off(), L.off.data(), L.off.size() * 4);
+    put(I.out_dst(), L.out_dst.data(), L.out_dst.size() * 4);
+    put(I.out_U(), L.out_U.data(), L.out_U.size() * 8);
+    put(I.in_start(), L.in_start.data(), L.in_start.size() * 4);
+    put(I.in_src(), L.in_src.data(), L.in_src.size() * 4);
+    put(I.in_lab(), L.in_lab.data(), L.in_lab.size() * 4);
+    put(I.in_U(), L.in_U.data(), L.in_U.size() * 8);
+    put(I.tail(), L.tail.data(), L.tail.size() * 8);
+    put(I.pfx(), L.pfx.data(), L.pfx.size() * 4);
+    put(I.P(), L.P.data(), L.P.size() * 8);
+    put(I.hp_init(), L.hp_init.data(), L.hp_init.size() * 4);
+    put(I.rowoff(), L.rowoff.data(), L.rowoff.size() * 8);
+    put(I.coff(), L.coff.data(), L.coff.size() * 8);
+    put(I.ccap(), L.ccap.data(), L.ccap.size() * 4);
+    put(I.alphaU(), L.alphaU.data(), L.alphaU.size() * 8);
+    put(I.betaU(), L.betaU.data(), L.betaU.size() * 8);
+    put(I.fwd_off(), L.fwd_off.data(), L.fwd_off.size() * 4);
+    put(I.fwd_meta(), L.fwd_meta.data(), L.fwd_meta.size() * 4);
+    put(I.fwd_cost(), L.fwd_cost.data(), L.fwd_cost.size() * 8);
+    put(I.bwd_off(), L.bwd_off.data(), L.bwd_off.size() * 4);
+    put(I.bwd_meta(), L.bwd_meta.data(), L.bwd_meta.size() * 4);
+    put(I.bwd_cost(), L.bwd_cost.data(), L.bwd_cost.size() * 8);
+    put(I.hpB(), L.hpB.data(), L.hpB.size() * 8);
+    put(I.OB(), L.OB.data(), L.OB.size() * 8);
+    put(I.OA(), L.OA.data(), L.OA.size() * 8);
 }
 
 sd_status ensure_staging(sd_context* c, size_t bytes) {
@@ -334,6 +316,7 @@ sd_status ensure_staging(sd_context* c, size_t bytes) {
 // Place one instance at the start of the arena and upload its inputs with one copy.
 sd_status place_and_upload(sd_context* c, const Lattice& L, Inst& I) {
     InstLayout sz = layout_instance(L, nullptr, nullptr, I);
+    if (!sz.a_bytes) return fail(SD_E_INTERNAL, "instance layout does not hold its arrays");
     sd_status s = ensure_arena(c, sz.a_bytes + sz.b_bytes);
     if (s) return s;
     s = ensure_staging(c, sz.a_bytes);
@@ -369,7 +352,7 @@ sd_status run_plain(sd_context* c, const Lattice& L, Inst& I, int64_t* overflow_
     }
     if (e == hipSuccess) e = launch_ext(I, (const EnergyTables*)c->E_dev, 0, st);
     unsigned long long stats[4];
-    if (e == hipSuccess) e = hipMemcpyAsync(stats, I.stats, sizeof(stats), hipMemcpyDeviceToHost, st);
+    if (e == hipSuccess) e = hipMemcpyAsync(stats, I.stats(), sizeof(stats), hipMemcpyDeviceToHost, st);
     if (e == hipSuccess) e = hipStreamSynchronize(st);
     if (e != hipSuccess) return hip_fail(e, "span wavefront");
     *overflow_span = stats[2] == ~0ull ? 0 : (int64_t)stats[2];
@@ -401,14 +384,14 @@ sd_status fetch_tables(sd_context* c, const Lattice& L, const Inst& I, TraceTabl
     T.X.resize(L.N);
     T.ccnt.resize(L.N);
     T.cc.resize(L.cand_slots);
-    hipError_t e = hipMemcpyAsync(T.V.data(), I.V, L.cells * 48, hipMemcpyDeviceToHost, st);
-    if (e == hipSuccess) e = hipMemcpyAsync(T.B.data(), I.Bt, L.cells * 8, hipMemcpyDeviceToHost, st);
-    if (e == hipSuccess) e = hipMemcpyAsync(T.S1.data(), I.S1, L.cells * 8, hipMemcpyDeviceToHost, st);
-    if (e == hipSuccess) e = hipMemcpyAsync(T.S2.data(), I.S2, L.cells * 8, hipMemcpyDeviceToHost, st);
-    if (e == hipSuccess) e = hipMemcpyAsync(T.X.data(), I.X, L.N * 8, hipMemcpyDeviceToHost, st);
-    if (e == hipSuccess) e = hipMemcpyAsync(T.ccnt.data(), I.ccnt, L.N * 4, hipMemcpyDeviceToHost, st);
+    hipError_t e = hipMemcpyAsync(T.V.data(), I.V(), L.cells * 48, hipMemcpyDeviceToHost, st);
+    if (e == hipSuccess) e = hipMemcpyAsync(T.B.data(), I.Bt(), L.cells * 8, hipMemcpyDeviceToHost, st);
+    if (e == hipSuccess) e = hipMemcpyAsync(T.S1.data(), I.S1(), L.cells * 8, hipMemcpyDeviceToHost, st);
+    if (e == hipSuccess) e = hipMemcpyAsync(T.S2.data(), I.S2(), L.cells * 8, hipMemcpyDeviceToHost, st);
+    if (e == hipSuccess) e = hipMemcpyAsync(T.X.data(), I.X(), L.N * 8, hipMemcpyDeviceToHost, st);
+    if (e == hipSuccess) e = hipMemcpyAsync(T.ccnt.data(), I.ccnt(), L.N * 4, hipMemcpyDeviceToHost, st);
     if (e == hipSuccess && L.cand_slots)
-        e = hipMemcpyAsync(T.cc.data(), I.cc, L.cand_slots * 4, hipMemcpyDeviceToHost, st);
+        e = hipMemcpyAsync(T.cc.data(), I.cc(), L.cand_slots * 4, hipMemcpyDeviceToHost, st);
     if (e == hipSuccess) e = hipStreamSynchronize(st);
     if (e != hipSuccess) return hip_fail(e, "table download");
     return SD_OK;
@@ -631,6 +614,7 @@ sd_status run_batch(sd_context* c, std::vector<Lattice>& Ls, std::vector<Inst>& 
     size_t totA = 0, totB = 0;
     for (int i = 0; i < n; i++) {
         lay[i] = layout_instance(Ls[i], nullptr, nullptr, Is[i]);
+        if (!lay[i].a_bytes) return fail(SD_E_INTERNAL, "instance layout does not hold its arrays");
         totA += lay[i].a_bytes;
         totB += lay[i].b_bytes;
     }
@@ -795,7 +779,7 @@ extern "C" sd_status sd_design_batch(sd_context* ctx, int n, const char* const* 
             for (int i = 0; i < m && s == SD_OK; i++) {
                 const int gi = done + i;
                 unsigned long long st[4];
-                hipError_t e = hipMemcpy(st, Is[i].stats, sizeof(st), hipMemcpyDeviceToHost);
+                hipError_t e = hipMemcpy(st, Is[i].stats(), sizeof(st), hipMemcpyDeviceToHost);
                 if (e != hipSuccess) {
                     s = hip_fail(e, "batch stats");
                     break;

@@ -39,57 +39,111 @@ struct EnergyTables {
 constexpr int32_t kNoSpecial = 0x7fffffff;
 constexpr int kSpecOff5 = 0, kSpecOff6 = 1024, kSpecOff8 = 1024 + 4096, kSpecSize = 1024 + 4096 + 65536;
 
+// Instance descriptor.  All arrays of one design live in two device regions whose layout is a
+// function of a few sizes, so the descriptor holds two base pointers plus sizes and every array
+// address is recomputed arithmetically where it is used (cheap scalar ALU, few live registers,
+// also when the descriptor is read from memory by the batched kernel).
+//
+// Region A (inputs and small mutable state) is cut into units of U bytes, U >= 8 * (N + 2),
+// >= 8 * (n + 2) and >= 8 * (A + 1), a multiple of 256; unit k starts at ra + k * U:
+//   0 layer[N]  1 off[n+2]  2 in_start[N+1]  3 tail[N]  4 pfx[N]  5 P[A+1]  6 hp_init[n+1]
+//   7 rowoff[N]  8 coff[N]  9 ccap[N]  10 ccnt[N]  11 X[N]  12-13 out_dst[4N]  14-17 out_U[4N]
+//   18-21 alphaU[4N]  22-25 betaU[4N]  26-28 fwd_off[4N+1]  29-31 bwd_off[4N+1]
+//   32-47 hpB[16N]  48-119 OB[72N]  120-191 OA[72N]  192 stats[4]  193 span_appends[n+1]
+//   194.. in_src[nE], in_lab[nE], in_U[nE], fwd_meta[nF], fwd_cost[nF], bwd_meta[nB],
+//         bwd_cost[nB] (each start 8-byte aligned)
+// Region B (DP tables) is cut into ring units of R = 512 * N bytes (N states x 64 spans x 8 B):
+//   0-1 LM  2-13 IDL  14-25 JDL  26 BI  27 BJ  28-43 RS  44-59 LS, then from 60 R:
+//   V[cells][6], Bt[cells], S1[cells], S2[cells], cc[slots], cB[slots].
+// Meaning of the arrays:
+//   layer/off: layer of a state, first state of a layer; out_dst/out_U: out-edge by label
+//   (-1 / cost); in_start/in_src/in_lab/in_U: in-edges (CSR, sorted by source and label);
+//   tail: cheapest completion of the current codon from a state; pfx: 2-base prefix code of a
+//   phase-2 state (4x+y), base x of phase 1; P: prefix sums of per-codon minimum cost;
+//   hp_init: hairpin initiation per size (extrapolated above 30); rowoff: cell row offsets,
+//   cell(a,b) = rowoff[a] + b - off[layer(a)+1]; V/Bt/S1/S2: typed closed values, branch value,
+//   multiloop prefixes; coff/ccap/ccnt/cc/cB: candidate segment per right endpoint (offset,
+//   capacity, committed count, start states with the non-strict flag in bit 31, B values);
+//   X: external column; stats: [0] visits [1] appends [2] earliest overflow span [3] finite B;
+//   span_appends: appended candidates per span.
+//   alphaU[d*4+x] = U(d -x-> d2) + tail(d2); betaU[c*4+x] = min U over in-edges of c labelled x.
+//   LM[layer][class 2][span]: layer-pair minima of the both-separable interior form.
+//   IDL/JDL[state][class 3][label 4][span]: inner minima per left / right inner state.
+//   fwd_*/bwd_*: label paths of 1..4 edges out of / into a state (CSR by state*4+l-1);
+//   meta = other_end << 4 | first_label << 2 | last_label, cost = sum of edge costs.
+//   hpB[b*16 + y*4 + z] = min over b2 -z-> b1 -y-> b of U(b2->b1) + U(b1->b).
+//   OB/OA[state][t][X][label]: outer minima of one-sided interior loops.
+//   BI[c][span] = min over d, t' of V_t'(c,d) + tail(d) + AU(t');  BJ[d][span] likewise without
+//   the tail.  RS[c][span][l-1][label], LS[d][span][l-1][label]: one-sided loops minimised over
+//   the separable side's length (explicit side of l <= 4 bases).
 struct Inst {
+    char *ra, *rb;         // region bases
+    int64_t U;             // region-A unit in bytes
+    int64_t nE, nF, nB;    // in-edges, forward and backward path entries
+    int64_t cells, slots;  // DP cells, candidate slots
+    int64_t mlbase_fx;     // ML_base * 2^s
     int n, N, A, shift;
-    int64_t mlbase_fx;  // ML_base * 2^s
-    const int *layer, *off;
-    const int *out_dst;
-    const int64_t *out_U;
-    const int *in_start, *in_src, *in_lab;
-    const int64_t *in_U;
-    const int64_t *tail;  // cheapest completion of the current codon from a state
-    const int *pfx;       // 2-base prefix code of a phase-2 state (4x+y), base x of phase 1
-    const int64_t *P;     // prefix sums of per-codon minimum cost, A+1 entries
-    const int *hp_init;   // hairpin initiation per size m (extrapolated above 30), n+1 entries
-    const int64_t *rowoff;
-    int64_t *V, *Bt, *S1, *S2;
-    const int64_t *coff;
-    const int *ccap;
-    int *ccnt;
-    int *cc;
-    int64_t *cB;
-    int64_t *X;
-    unsigned long long *stats;  // [0] visits [1] appends [2] overflow flag [3] feasible B
-    unsigned long long *span_appends;  // per span appended candidates (n+1), may be null
-    // separable interior-loop data (see the two-loop notes in sd_kernels.hip)
-    const int64_t *alphaU;  // [N*4] U(d -x-> d2) + tail(d2), INF if no edge
-    const int64_t *betaU;   // [N*4] min U over in-edges of c labelled x, INF if none
-    int64_t *LM;            // [kLMRing][n+1][2] per layer-pair inner minima, ring over spans
-    int64_t *IDL;           // [N][kLMRing][3][4] inner minima per left inner state, class, x_{k-1}
-    int64_t *JDL;           // [N][kLMRing][3][4] inner minima per right inner state, class, x_{l+1}
-    // label paths of 1..4 edges: forward from a state / backward into a state (CSR by state*4+l-1)
-    // meta = other_end << 4 | first_label << 2 | last_label, cost = sum of edge costs
-    const int *fwd_off, *fwd_meta, *bwd_off, *bwd_meta;
-    const int64_t *fwd_cost, *bwd_cost;
-    // generic hairpins: HB[b*16 + y*4 + z] = min over b2 -z-> b1 -y-> b of U(b2->b1) + U(b1->b)
-    const int64_t *hpB;
-    const int64_t *OB, *OA;  // [state][t][X][label] outer minima of one-sided interior loops
-    // bulges of >= 3 bases, per state and span (span innermost):
-    //   BI[c][g] = min over d at layer(c)+g, type t' of V_t'(c,d) + tail(d) + AU(t')
-    //   BJ[d][g] = min over c at layer(d)-g, type t' of V_t'(c,d) + AU(t')
-    int64_t *BI, *BJ;
-    // one-sided interior loops, minimised over the separable side's length, per state and span:
-    //   RS[c][s][l1-1][x_{k-1}]: explicit left segment of l1 <= 4 bases ending in c, right side
-    //                            separable, s = layer(b1) - layer(c)
-    //   LS[d][s][l2-1][x_{l+1}]: explicit right segment of l2 <= 4 bases starting at d, left side
-    //                            separable, s = layer(d) - layer(a1)
-    int64_t *RS, *LS;
     int retain_all;
     int g0;  // persistent launches: first span this launch processes for the instance
+
+    __host__ __device__ static int64_t al8(int64_t x) { return (x + 7) & ~(int64_t)7; }
+    __host__ __device__ char* ua(int k) const { return ra + (int64_t)k * U; }
+    __host__ __device__ int64_t R() const { return (int64_t)512 * N; }
+    __host__ __device__ char* ub(int k) const { return rb + (int64_t)k * R(); }
+
+    __host__ __device__ const int* layer() const { return (const int*)ua(0); }
+    __host__ __device__ const int* off() const { return (const int*)ua(1); }
+    __host__ __device__ const int* in_start() const { return (const int*)ua(2); }
+    __host__ __device__ const int64_t* tail() const { return (const int64_t*)ua(3); }
+    __host__ __device__ const int* pfx() const { return (const int*)ua(4); }
+    __host__ __device__ const int64_t* P() const { return (const int64_t*)ua(5); }
+    __host__ __device__ const int* hp_init() const { return (const int*)ua(6); }
+    __host__ __device__ const int64_t* rowoff() const { return (const int64_t*)ua(7); }
+    __host__ __device__ const int64_t* coff() const { return (const int64_t*)ua(8); }
+    __host__ __device__ const int* ccap() const { return (const int*)ua(9); }
+    __host__ __device__ int* ccnt() const { return (int*)ua(10); }
+    __host__ __device__ int64_t* X() const { return (int64_t*)ua(11); }
+    __host__ __device__ const int* out_dst() const { return (const int*)ua(12); }
+    __host__ __device__ const int64_t* out_U() const { return (const int64_t*)ua(14); }
+    __host__ __device__ const int64_t* alphaU() const { return (const int64_t*)ua(18); }
+    __host__ __device__ const int64_t* betaU() const { return (const int64_t*)ua(22); }
+    __host__ __device__ const int* fwd_off() const { return (const int*)ua(26); }
+    __host__ __device__ const int* bwd_off() const { return (const int*)ua(29); }
+    __host__ __device__ const int64_t* hpB() const { return (const int64_t*)ua(32); }
+    __host__ __device__ const int64_t* OB() const { return (const int64_t*)ua(48); }
+    __host__ __device__ const int64_t* OA() const { return (const int64_t*)ua(120); }
+    __host__ __device__ unsigned long long* stats() const { return (unsigned long long*)ua(192); }
+    __host__ __device__ unsigned long long* span_appends() const { return (unsigned long long*)ua(193); }
+    __host__ __device__ const int* in_src() const { return (const int*)ua(194); }
+    __host__ __device__ const int* in_lab() const { return (const int*)(ua(194) + al8(4 * nE)); }
+    __host__ __device__ const int64_t* in_U() const { return (const int64_t*)(ua(194) + 2 * al8(4 * nE)); }
+    __host__ __device__ char* paths() const { return ua(194) + 2 * al8(4 * nE) + 8 * nE; }
+    __host__ __device__ const int* fwd_meta() const { return (const int*)paths(); }
+    __host__ __device__ const int64_t* fwd_cost() const { return (const int64_t*)(paths() + al8(4 * nF)); }
+    __host__ __device__ const int* bwd_meta() const { return (const int*)(paths() + al8(4 * nF) + 8 * nF); }
+    __host__ __device__ const int64_t* bwd_cost() const {
+        return (const int64_t*)(paths() + al8(4 * nF) + 8 * nF + al8(4 * nB));
+    }
+    __host__ __device__ int64_t a_bytes() const { return (int64_t)(paths() - ra) + al8(4 * nF) + 8 * nF + al8(4 * nB) + 8 * nB; }
+
+    __host__ __device__ int64_t* LM() const { return (int64_t*)ub(0); }
+    __host__ __device__ int64_t* IDL() const { return (int64_t*)ub(2); }
+    __host__ __device__ int64_t* JDL() const { return (int64_t*)ub(14); }
+    __host__ __device__ int64_t* BI() const { return (int64_t*)ub(26); }
+    __host__ __device__ int64_t* BJ() const { return (int64_t*)ub(27); }
+    __host__ __device__ int64_t* RS() const { return (int64_t*)ub(28); }
+    __host__ __device__ int64_t* LS() const { return (int64_t*)ub(44); }
+    __host__ __device__ int64_t* V() const { return (int64_t*)ub(60); }
+    __host__ __device__ int64_t* Bt() const { return (int64_t*)(ub(60) + 48 * cells); }
+    __host__ __device__ int64_t* S1() const { return (int64_t*)(ub(60) + 56 * cells); }
+    __host__ __device__ int64_t* S2() const { return (int64_t*)(ub(60) + 64 * cells); }
+    __host__ __device__ int* cc() const { return (int*)(ub(60) + 72 * cells); }
+    __host__ __device__ int64_t* cB() const { return (int64_t*)(ub(60) + 72 * cells + al8(4 * slots)); }
+    __host__ __device__ int64_t b_bytes() const { return 60 * R() + 72 * cells + al8(4 * slots) + 8 * slots; }
 };
 
 constexpr int kLMRing = 64;
-constexpr int kMaxWaves = 16;  // waves per workgroup of the span-step kernels (1024 threads)  // > 32 spans of two-loop reach
+constexpr int kMaxWaves = 16;  // waves per workgroup of the span-step kernels (1024 threads)
 static_assert(sizeof(Inst) % 8 == 0, "instance descriptors are copied as 8-byte words");
 
 // Batched persistent launch: barrier state shared by all workgroups.

@@ -94,20 +94,22 @@ __device__ __forceinline__ int64_t wave_min(int64_t v) {
     return v;
 }
 
-__device__ __forceinline__ int64_t cell_of(const Inst& I, int a, int b) {
-    return I.rowoff[a] + (b - I.off[I.layer[a] + 1]);
+template <class IT>
+__device__ __forceinline__ int64_t cell_of(const IT& I, int a, int b) {
+    return I.rowoff()[a] + (b - I.off()[I.layer()[a] + 1]);
 }
 
 // Minimum path cost between states of the codon trie (closed form; INF if unreachable).
-__device__ __forceinline__ int64_t gap(const Inst& I, int a, int b) {
-    int la = I.layer[a], lb = I.layer[b];
+template <class IT>
+__device__ __forceinline__ int64_t gap(const IT& I, int a, int b) {
+    int la = I.layer()[a], lb = I.layer()[b];
     if (la == lb) return a == b ? 0 : kINF;
     int ka = la / 3, kb = lb / 3;
     if (ka == kb) {
         if (la % 3 == 0) return 0;
-        return (I.pfx[b] >> 2) == I.pfx[a] ? 0 : kINF;
+        return (I.pfx()[b] >> 2) == I.pfx()[a] ? 0 : kINF;
     }
-    return I.tail[a] + I.P[kb] - I.P[ka + 1];
+    return I.tail()[a] + I.P()[kb] - I.P()[ka + 1];
 }
 
 __device__ __forceinline__ int32_t bulge_e(const SmallE& S, int t, int tr, int l) {
@@ -145,7 +147,8 @@ __device__ __forceinline__ int pair_class(int l1, int l2) {  // 1: 2x3 mismatch 
 }
 
 // ---- hairpin closure ------------------------------------------------------------------------
-__device__ int64_t hairpin_lane(const Inst& I, const SmallE& S, const int32_t* __restrict__ spec,
+template <class IT>
+__device__ int64_t hairpin_lane(const IT& I, const SmallE& S, const int32_t* __restrict__ spec,
                                 int a, int b, int t, int a1, int64_t Ua, int la, int g, int lane) {
     const int m = g - 2, s = I.shift;
     const int x = kTX[t], y = kTY[t];
@@ -157,9 +160,9 @@ __device__ int64_t hairpin_lane(const Inst& I, const SmallE& S, const int32_t* _
         int64_t cost = Ua;
         const int labs[3] = {l1, l2, l3};
         for (int i = 0; i < 3; i++) {
-            const int e = st * 4 + labs[i], d = I.out_dst[e];
+            const int e = st * 4 + labs[i], d = I.out_dst()[e];
             if (d < 0) return kINF;
-            cost += I.out_U[e];
+            cost += I.out_U()[e];
             key = key * 4 + labs[i];
             st = d;
         }
@@ -169,21 +172,21 @@ __device__ int64_t hairpin_lane(const Inst& I, const SmallE& S, const int32_t* _
             int st2 = st, key2 = key, ok = 1, last = l3;
             int64_t c2 = cost;
             for (int i = nfree - 1; i >= 0; i--) {
-                const int lab = (k >> (2 * i)) & 3, e = st2 * 4 + lab, d = I.out_dst[e];
+                const int lab = (k >> (2 * i)) & 3, e = st2 * 4 + lab, d = I.out_dst()[e];
                 if (d < 0) { ok = 0; break; }
-                c2 += I.out_U[e];
+                c2 += I.out_U()[e];
                 key2 = key2 * 4 + lab;
                 st2 = d;
                 last = lab;
             }
             if (!ok) continue;
             const int e = st2 * 4 + y;
-            if (I.out_dst[e] != b) continue;
-            c2 += I.out_U[e];
+            if (I.out_dst()[e] != b) continue;
+            c2 += I.out_U()[e];
             key2 = key2 * 4 + y;
             const int off = m == 3 ? kSpecOff5 : m == 4 ? kSpecOff6 : kSpecOff8;
             int32_t en = spec[off + key2];
-            if (en == kNoSpecial) en = I.hp_init[m] + (m == 3 ? au_pen(S, t) : S.mmH[t][l1][last]);
+            if (en == kNoSpecial) en = I.hp_init()[m] + (m == 3 ? au_pen(S, t) : S.mmH[t][l1][last]);
             best = mn(best, c2 + fx(en, s));
         }
         return best;
@@ -193,10 +196,10 @@ __device__ int64_t hairpin_lane(const Inst& I, const SmallE& S, const int32_t* _
     // alpha(a1, x2) + mmH[t][x2][z] + HB(b, y, z) plus layer constants.
     if (lane < 16) {
         const int x2 = lane >> 2, z = lane & 3;
-        const int64_t al = I.alphaU[a1 * 4 + x2], hb = I.hpB[b * 16 + y * 4 + z];
+        const int64_t al = I.alphaU()[a1 * 4 + x2], hb = I.hpB()[b * 16 + y * 4 + z];
         if (al < kINF && hb < kINF)
-            best = Ua + al + hb + I.P[(la + g - 2) / 3] - I.P[(la + 2) / 3 + 1] +
-                   fx(I.hp_init[m] + S.mmH[t][x2][z], s);
+            best = Ua + al + hb + I.P()[(la + g - 2) / 3] - I.P()[(la + 2) / 3 + 1] +
+                   fx(I.hp_init()[m] + S.mmH[t][x2][z], s);
     }
     return best;
 }
@@ -204,18 +207,19 @@ __device__ int64_t hairpin_lane(const Inst& I, const SmallE& S, const int32_t* _
 // ---- two-loop closure: bulges and stacks ----------------------------------------------------------
 // No boundary bases enter a bulge or stack energy, so each unpaired side costs its minimum
 // (the gap) and the loop is evaluated per inner cell and inner type.
-__device__ int64_t bulge_pair(const Inst& I, const SmallE& S, int t, int a1, int b1, int64_t Uab,
+template <class IT>
+__device__ int64_t bulge_pair(const IT& I, const SmallE& S, int t, int a1, int b1, int64_t Uab,
                               int l1, int l2, int cl, int dl) {
     const int s = I.shift, l = l1 + l2;
     int64_t best = kINF;
-    for (int c = (l1 == 0 ? a1 : I.off[cl]); c < (l1 == 0 ? a1 + 1 : I.off[cl + 1]); c++) {
+    for (int c = (l1 == 0 ? a1 : I.off()[cl]); c < (l1 == 0 ? a1 + 1 : I.off()[cl + 1]); c++) {
         const int64_t gl = l1 == 0 ? 0 : gap(I, a1, c);
         if (gl >= kINF) continue;
-        const int64_t crow = I.rowoff[c] - I.off[cl + 1];
-        for (int d = (l2 == 0 ? b1 : I.off[dl]); d < (l2 == 0 ? b1 + 1 : I.off[dl + 1]); d++) {
+        const int64_t crow = I.rowoff()[c] - I.off()[cl + 1];
+        for (int d = (l2 == 0 ? b1 : I.off()[dl]); d < (l2 == 0 ? b1 + 1 : I.off()[dl + 1]); d++) {
             const int64_t gr = l2 == 0 ? 0 : gap(I, d, b1);
             if (gr >= kINF) continue;
-            const int64_t* v = I.V + (crow + d) * 6;
+            const int64_t* v = I.V() + (crow + d) * 6;
             for (int tp = 0; tp < 6; tp++) {
                 const int64_t vin = v[tp];
                 if (vin >= kINF) continue;
@@ -236,7 +240,8 @@ struct LabPair {
     int f0, nl, r0, nr, l1, l2, start;
 };
 
-__device__ int64_t labelled_pairs(const Inst& I, const SmallE& S, const EnergyTables* __restrict__ E,
+template <class IT>
+__device__ int64_t labelled_pairs(const IT& I, const SmallE& S, const EnergyTables* __restrict__ E,
                                   int t, int a1, int b1, int64_t Uab, int ph, int cap, int lane,
                                   LabPair* lp) {
     const int s = I.shift;
@@ -245,10 +250,10 @@ __device__ int64_t labelled_pairs(const Inst& I, const SmallE& S, const EnergyTa
     if (lane < npairs) {
         const int code = kPairList[kListLab][ph][lane], l1 = code & 31, l2 = (code >> 5) & 31;
         LabPair x;
-        x.f0 = I.fwd_off[a1 * 4 + l1 - 1];
-        x.nl = I.fwd_off[a1 * 4 + l1] - x.f0;
-        x.r0 = I.bwd_off[b1 * 4 + l2 - 1];
-        x.nr = I.bwd_off[b1 * 4 + l2] - x.r0;
+        x.f0 = I.fwd_off()[a1 * 4 + l1 - 1];
+        x.nl = I.fwd_off()[a1 * 4 + l1] - x.f0;
+        x.r0 = I.bwd_off()[b1 * 4 + l2 - 1];
+        x.nr = I.bwd_off()[b1 * 4 + l2] - x.r0;
         x.l1 = l1;
         x.l2 = l2;
         cnt = x.nl * x.nr;
@@ -270,11 +275,11 @@ __device__ int64_t labelled_pairs(const Inst& I, const SmallE& S, const EnergyTa
         while (k + 1 < npairs && lp[k + 1].start <= idx) k++;
         const LabPair x = lp[k];
         const int r = idx - x.start, i = r / x.nr, j = r - i * x.nr;
-        const int fm = I.fwd_meta[x.f0 + i], bm = I.bwd_meta[x.r0 + j];
+        const int fm = I.fwd_meta()[x.f0 + i], bm = I.bwd_meta()[x.r0 + j];
         const int c = fm >> 4, xi = (fm >> 2) & 3, xk = fm & 3;
         const int d = bm >> 4, xl = (bm >> 2) & 3, xj = bm & 3;
-        const int64_t base = Uab + I.fwd_cost[x.f0 + i] + I.bwd_cost[x.r0 + j];
-        const int64_t* v = I.V + (I.rowoff[c] + (d - I.off[I.layer[c] + 1])) * 6;
+        const int64_t base = Uab + I.fwd_cost()[x.f0 + i] + I.bwd_cost()[x.r0 + j];
+        const int64_t* v = I.V() + (I.rowoff()[c] + (d - I.off()[I.layer()[c] + 1])) * 6;
         for (int tp = 0; tp < 6; tp++) {
             const int64_t vin = v[tp];
             if (vin >= kINF) continue;
@@ -310,39 +315,43 @@ __device__ __forceinline__ int64_t ring_idx(int state, int span, int X, int lab)
 __device__ __forceinline__ int64_t lm_idx(int layer, int span, int X) {
     return ((int64_t)layer * 2 + X) * kLMRing + (span & (kLMRing - 1));
 }
-__device__ __forceinline__ int64_t PLt(const Inst& I, int p, int l1) { return I.P[(p + l1) / 3] - I.P[(p + 2) / 3 + 1]; }
-__device__ __forceinline__ int64_t PRt(const Inst& I, int q, int l2) { return I.P[(q - 2) / 3] - I.P[(q - l2) / 3 + 1]; }
+template <class IT>
+__device__ __forceinline__ int64_t PLt(const IT& I, int p, int l1) { return I.P()[(p + l1) / 3] - I.P()[(p + 2) / 3 + 1]; }
+template <class IT>
+__device__ __forceinline__ int64_t PRt(const IT& I, int q, int l2) { return I.P()[(q - 2) / 3] - I.P()[(q - l2) / 3 + 1]; }
 
 // Outer minima of one-sided loops come from per-state tables built with the automaton:
 //   OB(b1, t)[X][x_{i+1}] = min_{x_{j-1}} beta(b1, x_{j-1}) + mm_X[t][x_{i+1}][x_{j-1}]
 //   OA(a1, t)[X][x_{j-1}] = min_{x_{i+1}} alpha(a1, x_{i+1}) + mm_X[t][x_{i+1}][x_{j-1}]
 
 // left segment explicit (paths of l1 edges out of a1), right segment separable
-__device__ int64_t rsep_pair(const Inst& I, const SmallE& S, int a1, int64_t Uab, int l1, int l2,
+template <class IT>
+__device__ int64_t rsep_pair(const IT& I, const SmallE& S, int a1, int64_t Uab, int l1, int l2,
                              int cl, int dl, int q, const int64_t* __restrict__ ob) {
     const int X = mm_class(l1, l2), g2 = dl - cl;
     const int64_t base = Uab + fx(interior_base(S, l1, l2), I.shift) + PRt(I, q, l2);
-    const int f0 = I.fwd_off[a1 * 4 + l1 - 1], f1 = I.fwd_off[a1 * 4 + l1];
+    const int f0 = I.fwd_off()[a1 * 4 + l1 - 1], f1 = I.fwd_off()[a1 * 4 + l1];
     int64_t best = kINF;
     for (int i = f0; i < f1; i++) {
-        const int fm = I.fwd_meta[i], c = fm >> 4, xi = (fm >> 2) & 3, xk = fm & 3;
-        const int64_t o = ob[X * 4 + xi], idl = I.IDL[ring_idx(c, g2, X, xk)];
-        if (o < kINF && idl < kINF) best = mn(best, base + I.fwd_cost[i] + o + idl);
+        const int fm = I.fwd_meta()[i], c = fm >> 4, xi = (fm >> 2) & 3, xk = fm & 3;
+        const int64_t o = ob[X * 4 + xi], idl = I.IDL()[ring_idx(c, g2, X, xk)];
+        if (o < kINF && idl < kINF) best = mn(best, base + I.fwd_cost()[i] + o + idl);
     }
     return best;
 }
 
 // left segment separable, right segment explicit (paths of l2 edges into b1)
-__device__ int64_t lsep_pair(const Inst& I, const SmallE& S, int b1, int64_t Uab, int l1, int l2,
+template <class IT>
+__device__ int64_t lsep_pair(const IT& I, const SmallE& S, int b1, int64_t Uab, int l1, int l2,
                              int cl, int dl, int p, const int64_t* __restrict__ oa) {
     const int X = mm_class(l1, l2), g2 = dl - cl;
     const int64_t base = Uab + fx(interior_base(S, l1, l2), I.shift) + PLt(I, p, l1);
-    const int r0 = I.bwd_off[b1 * 4 + l2 - 1], r1 = I.bwd_off[b1 * 4 + l2];
+    const int r0 = I.bwd_off()[b1 * 4 + l2 - 1], r1 = I.bwd_off()[b1 * 4 + l2];
     int64_t best = kINF;
     for (int j = r0; j < r1; j++) {
-        const int bm = I.bwd_meta[j], d = bm >> 4, xl = (bm >> 2) & 3, xj = bm & 3;
-        const int64_t o = oa[X * 4 + xj], jdl = I.JDL[ring_idx(d, g2, X, xl)];
-        if (o < kINF && jdl < kINF) best = mn(best, base + I.bwd_cost[j] + o + jdl);
+        const int bm = I.bwd_meta()[j], d = bm >> 4, xl = (bm >> 2) & 3, xj = bm & 3;
+        const int64_t o = oa[X * 4 + xj], jdl = I.JDL()[ring_idx(d, g2, X, xl)];
+        if (o < kINF && jdl < kINF) best = mn(best, base + I.bwd_cost()[j] + o + jdl);
     }
     return best;
 }
@@ -355,7 +364,8 @@ __device__ __forceinline__ int64_t rs_idx(int state, int span, int l, int lab) {
     return ((int64_t)state * kLMRing + (span & (kLMRing - 1))) * 16 + (l - 1) * 4 + lab;
 }
 
-__device__ int64_t one_sided(const Inst& I, const SmallE& S, int a1, int b1, int64_t Uab, int p, int q,
+template <class IT>
+__device__ int64_t one_sided(const IT& I, const SmallE& S, int a1, int b1, int64_t Uab, int p, int q,
                              int cap, int lane, const int64_t* __restrict__ ob,
                              const int64_t* __restrict__ oa) {
     const int g = q - p;
@@ -364,12 +374,12 @@ __device__ int64_t one_sided(const Inst& I, const SmallE& S, int a1, int b1, int
     for (int l = 1; l <= 4; l++) {  // left explicit (right separable) path lists
         start[l - 1] = tot;
         const bool ok = !sep_left(p, l) && g - 2 - l >= 8;
-        tot += ok ? I.fwd_off[a1 * 4 + l] - I.fwd_off[a1 * 4 + l - 1] : 0;
+        tot += ok ? I.fwd_off()[a1 * 4 + l] - I.fwd_off()[a1 * 4 + l - 1] : 0;
     }
     for (int l = 1; l <= 4; l++) {  // right explicit (left separable) path lists
         start[3 + l] = tot;
         const bool ok = !sep_right(q, l) && g - 2 - l >= 8;
-        tot += ok ? I.bwd_off[b1 * 4 + l] - I.bwd_off[b1 * 4 + l - 1] : 0;
+        tot += ok ? I.bwd_off()[b1 * 4 + l] - I.bwd_off()[b1 * 4 + l - 1] : 0;
     }
     start[8] = tot;
     int64_t best = kINF;
@@ -378,15 +388,15 @@ __device__ int64_t one_sided(const Inst& I, const SmallE& S, int a1, int b1, int
         while (k < 7 && start[k + 1] <= idx) k++;
         const int i = idx - start[k];
         if (k < 4) {
-            const int l1 = k + 1, X = l1 == 1 ? 2 : 0, e = I.fwd_off[a1 * 4 + l1 - 1] + i;
-            const int fm = I.fwd_meta[e], c = fm >> 4, xi = (fm >> 2) & 3, xk = fm & 3;
-            const int64_t rs = I.RS[rs_idx(c, g - 2 - l1, l1, xk)], o = ob[X * 4 + xi];
-            if (rs < kINF && o < kINF) best = mn(best, Uab + I.fwd_cost[e] + o + rs);
+            const int l1 = k + 1, X = l1 == 1 ? 2 : 0, e = I.fwd_off()[a1 * 4 + l1 - 1] + i;
+            const int fm = I.fwd_meta()[e], c = fm >> 4, xi = (fm >> 2) & 3, xk = fm & 3;
+            const int64_t rs = I.RS()[rs_idx(c, g - 2 - l1, l1, xk)], o = ob[X * 4 + xi];
+            if (rs < kINF && o < kINF) best = mn(best, Uab + I.fwd_cost()[e] + o + rs);
         } else {
-            const int l2 = k - 3, X = l2 == 1 ? 2 : 0, e = I.bwd_off[b1 * 4 + l2 - 1] + i;
-            const int bm = I.bwd_meta[e], d = bm >> 4, xl = (bm >> 2) & 3, xj = bm & 3;
-            const int64_t ls = I.LS[rs_idx(d, g - 2 - l2, l2, xl)], o = oa[X * 4 + xj];
-            if (ls < kINF && o < kINF) best = mn(best, Uab + I.bwd_cost[e] + o + ls);
+            const int l2 = k - 3, X = l2 == 1 ? 2 : 0, e = I.bwd_off()[b1 * 4 + l2 - 1] + i;
+            const int bm = I.bwd_meta()[e], d = bm >> 4, xl = (bm >> 2) & 3, xj = bm & 3;
+            const int64_t ls = I.LS()[rs_idx(d, g - 2 - l2, l2, xl)], o = oa[X * 4 + xj];
+            if (ls < kINF && o < kINF) best = mn(best, Uab + I.bwd_cost()[e] + o + ls);
         }
     }
     // 2x3 with the left side explicit, 3x2 with the right side explicit
@@ -404,37 +414,39 @@ struct GroupCounters {
 
 constexpr int kMaxWidth = 4;  // states per layer supported by the per-group cell buffers
 
+template <int NW>  // waves per workgroup
 struct GroupShared {
     int64_t vbuf[kMaxWidth * kMaxWidth][6];  // typed closed values of this layer pair's cells
     int64_t cellB[kMaxWidth * kMaxWidth];
     int keep[kMaxWidth * kMaxWidth];          // 0 none, 1 strict, 2 retained non-strict
     int combo[kMaxWidth * kMaxWidth * 6];     // (cell, type) jobs with an out-edge of label x
     int ncombo;
-    int64_t red[kMaxWaves][2];
-    LabPair lab[kMaxWaves][16];
+    int64_t red[NW][2];
+    LabPair lab[NW][16];
 };
 
 // One of two parts of the typed closed value V_t(a, b), with the lanes of one wave:
 //   part 0: hairpin, stacks and bulges, multiloop closure;
 //   part 1: interior loops (one-sided, both explicit, both separable).
 // The parts of one (cell, type) run on different waves and meet in an LDS minimum.
-__device__ int64_t closed_part(const Inst& I, const SmallE& S, const EnergyTables* __restrict__ E,
+template <class IT>
+__device__ int64_t closed_part(const IT& I, const SmallE& S, const EnergyTables* __restrict__ E,
                                const int32_t* __restrict__ spec, int a, int b, int t, int p, int q,
                                int part, int64_t mini0, int64_t mini1, int lane, LabPair* lab) {
     const int g = q - p, s = I.shift;
-    const int a1 = I.out_dst[a * 4 + kTX[t]];
-    const int64_t Ua = I.out_U[a * 4 + kTX[t]];
+    const int a1 = I.out_dst()[a * 4 + kTX[t]];
+    const int64_t Ua = I.out_U()[a * 4 + kTX[t]];
     const int y = kTY[t];
-    const int ib0 = I.in_start[b], ib1 = I.in_start[b + 1];
+    const int ib0 = I.in_start()[b], ib1 = I.in_start()[b + 1];
     const int ph = (p % 3) * 3 + (q % 3), cap = min(g - 7, kMaxLoop);
     int64_t v = kINF;
     if (part == 0) {
         v = hairpin_lane(I, S, spec, a, b, t, a1, Ua, p, g, lane);
         if (g >= 7) {
             for (int eb = ib0; eb < ib1; eb++) {
-                if (I.in_lab[eb] != y) continue;
-                const int b1 = I.in_src[eb];
-                const int64_t Uab = Ua + I.in_U[eb];
+                if (I.in_lab()[eb] != y) continue;
+                const int b1 = I.in_src()[eb];
+                const int64_t Uab = Ua + I.in_U()[eb];
                 for (int k = lane; k < kPairCnt[kListBulge][0][cap]; k += 64) {
                     const int code = kPairList[kListBulge][0][k], l1 = code & 31, l2 = (code >> 5) & 31;
                     v = mn(v, bulge_pair(I, S, t, a1, b1, Uab, l1, l2, p + 1 + l1, q - 1 - l2));
@@ -445,11 +457,11 @@ __device__ int64_t closed_part(const Inst& I, const SmallE& S, const EnergyTable
                     const int l = l1 + l2, cl = p + 1 + l1, dl = q - 1 - l2;
                     int64_t w;
                     if (l1 == 0) {
-                        const int64_t bi = I.BI[(int64_t)a1 * kLMRing + ((dl - cl) & (kLMRing - 1))];
-                        w = bi >= kINF ? kINF : Uab + bi + I.P[(q - 1) / 3] - I.P[dl / 3 + 1];
+                        const int64_t bi = I.BI()[(int64_t)a1 * kLMRing + ((dl - cl) & (kLMRing - 1))];
+                        w = bi >= kINF ? kINF : Uab + bi + I.P()[(q - 1) / 3] - I.P()[dl / 3 + 1];
                     } else {
-                        const int64_t bj = I.BJ[(int64_t)b1 * kLMRing + ((dl - cl) & (kLMRing - 1))];
-                        w = bj >= kINF ? kINF : Uab + bj + I.tail[a1] + I.P[cl / 3] - I.P[(p + 1) / 3 + 1];
+                        const int64_t bj = I.BJ()[(int64_t)b1 * kLMRing + ((dl - cl) & (kLMRing - 1))];
+                        w = bj >= kINF ? kINF : Uab + bj + I.tail()[a1] + I.P()[cl / 3] - I.P()[(p + 1) / 3 + 1];
                     }
                     if (w < kINF) v = mn(v, w + fx(S.bulge[l] + au_pen(S, t), s));
                 }
@@ -459,20 +471,20 @@ __device__ int64_t closed_part(const Inst& I, const SmallE& S, const EnergyTable
             // multiloop closure (ML_closing + ML_intern + AU) + S2 of the interior
             const int32_t mlc = S.ml_closing + S.ml_intern + au_pen(S, t);
             for (int eb = ib0 + lane; eb < ib1; eb += 64) {
-                if (I.in_lab[eb] != y) continue;
-                const int b1 = I.in_src[eb];
-                if (I.layer[b1] - (p + 1) < 10) continue;
-                v = mn(v, I.S2[cell_of(I, a1, b1)] + Ua + I.in_U[eb] + fx(mlc, s));
+                if (I.in_lab()[eb] != y) continue;
+                const int b1 = I.in_src()[eb];
+                if (I.layer()[b1] - (p + 1) < 10) continue;
+                v = mn(v, I.S2()[cell_of(I, a1, b1)] + Ua + I.in_U()[eb] + fx(mlc, s));
             }
         }
     } else {
         if (g >= 7) {
-            const int64_t* oa = I.OA + (int64_t)(a1 * 6 + t) * 12;
+            const int64_t* oa = I.OA() + (int64_t)(a1 * 6 + t) * 12;
             for (int eb = ib0; eb < ib1; eb++) {
-                if (I.in_lab[eb] != y) continue;
-                const int b1 = I.in_src[eb];
-                const int64_t Uab = Ua + I.in_U[eb];
-                v = mn(v, one_sided(I, S, a1, b1, Uab, p, q, cap, lane, I.OB + (int64_t)(b1 * 6 + t) * 12, oa));
+                if (I.in_lab()[eb] != y) continue;
+                const int b1 = I.in_src()[eb];
+                const int64_t Uab = Ua + I.in_U()[eb];
+                v = mn(v, one_sided(I, S, a1, b1, Uab, p, q, cap, lane, I.OB() + (int64_t)(b1 * 6 + t) * 12, oa));
                 v = mn(v, labelled_pairs(I, S, E, t, a1, b1, Uab, ph, cap, lane, lab));
             }
         }
@@ -481,11 +493,11 @@ __device__ int64_t closed_part(const Inst& I, const SmallE& S, const EnergyTable
             const int nbx = (ib1 - ib0) * 32;
             for (int k = lane; k < nbx; k += 64) {
                 const int eb = ib0 + (k >> 5), X = (k >> 4) & 1, xi = (k >> 2) & 3, xj = k & 3;
-                if (I.in_lab[eb] != y) continue;
+                if (I.in_lab()[eb] != y) continue;
                 const int64_t mini = X ? mini1 : mini0;
-                const int64_t al = I.alphaU[a1 * 4 + xi], be = I.betaU[I.in_src[eb] * 4 + xj];
+                const int64_t al = I.alphaU()[a1 * 4 + xi], be = I.betaU()[I.in_src()[eb] * 4 + xj];
                 if (mini >= kINF || al >= kINF || be >= kINF) continue;
-                v = mn(v, Ua + I.in_U[eb] + al + be + fx(mmx(S, X, t, xi, xj), s) + mini);
+                v = mn(v, Ua + I.in_U()[eb] + al + be + fx(mmx(S, X, t, xi, xj), s) + mini);
             }
         }
     }
@@ -496,7 +508,8 @@ __device__ int64_t closed_part(const Inst& I, const SmallE& S, const EnergyTable
 //   left state c (layer p):  RS(c, g), IDL(c, g), BI(c, g) and its LM contribution;
 //   right state d (layer q): LS(d, g), JDL(d, g), BJ(d, g).
 // RS / LS read IDL / JDL of spans <= g - 3 only; the rest reads this group's typed values.
-__device__ void produce_state(const Inst& I, const SmallE& S, const GroupShared& G, int p, int g,
+template <int NW, class IT>
+__device__ void produce_state(const IT& I, const SmallE& S, const GroupShared<NW>& G, int p, int g,
                               int k, int a_lo, int b_lo, int wa, int wb, int lane,
                               int64_t& lm0, int64_t& lm1) {
     const int s = I.shift;
@@ -514,8 +527,8 @@ __device__ void produce_state(const Inst& I, const SmallE& S, const GroupShared&
             if (ls > 29 || g2 < 5) continue;
             if (left ? !sep_right(qc, ls) : (pc < 0 || !sep_left(pc, ls))) continue;
             const int64_t ptail = left ? PRt(I, qc, ls) : PLt(I, pc, ls);
-            const int64_t in0 = left ? I.IDL[ring_idx(st, g2, 0, lab)] : I.JDL[ring_idx(st, g2, 0, lab)];
-            const int64_t in2 = left ? I.IDL[ring_idx(st, g2, 2, lab)] : I.JDL[ring_idx(st, g2, 2, lab)];
+            const int64_t in0 = left ? I.IDL()[ring_idx(st, g2, 0, lab)] : I.JDL()[ring_idx(st, g2, 0, lab)];
+            const int64_t in2 = left ? I.IDL()[ring_idx(st, g2, 2, lab)] : I.JDL()[ring_idx(st, g2, 2, lab)];
 #pragma unroll
             for (int le = 1; le <= 4; le++) {
                 if (le + ls > kMaxLoop || (le == 2 && ls == 3)) continue;
@@ -530,7 +543,7 @@ __device__ void produce_state(const Inst& I, const SmallE& S, const GroupShared&
 #pragma unroll
             for (int m = 4; m < 64; m <<= 1) o[j] = mn(o[j], shfl_xor64(o[j], m));
         if (grp == 0) {
-            int64_t* T = left ? I.RS : I.LS;
+            int64_t* T = left ? I.RS() : I.LS();
 #pragma unroll
             for (int j = 0; j < 4; j++) T[rs_idx(st, g, j + 1, lab)] = norm_inf(o[j]);
         }
@@ -544,7 +557,7 @@ __device__ void produce_state(const Inst& I, const SmallE& S, const GroupShared&
             for (int o = 0; o < nother; o++) {
                 const int ci = left ? i * wb + o : o * wb + i;
                 // left: vary x_{l+1} = z with alpha(d); right: vary x_{k-1} = z with beta(c)
-                const int64_t w = left ? I.alphaU[(b_lo + o) * 4 + z] : I.betaU[(a_lo + o) * 4 + z];
+                const int64_t w = left ? I.alphaU()[(b_lo + o) * 4 + z] : I.betaU()[(a_lo + o) * 4 + z];
                 if (w >= kINF) continue;
                 for (int tp = 0; tp < 6; tp++) {
                     const int64_t vin = G.vbuf[ci][tp];
@@ -558,14 +571,14 @@ __device__ void produce_state(const Inst& I, const SmallE& S, const GroupShared&
         acc = norm_inf(acc);
         if (X < 3 && z == 0) {
             if (left) {
-                I.IDL[ring_idx(st, g, X, xx)] = acc;
-                const int64_t be = I.betaU[st * 4 + xx];
+                I.IDL()[ring_idx(st, g, X, xx)] = acc;
+                const int64_t be = I.betaU()[st * 4 + xx];
                 if (acc < kINF && be < kINF) {
                     if (X == 0) lm0 = mn(lm0, acc + be);
                     if (X == 1) lm1 = mn(lm1, acc + be);
                 }
             } else {
-                I.JDL[ring_idx(st, g, X, xx)] = acc;
+                I.JDL()[ring_idx(st, g, X, xx)] = acc;
             }
         }
     }
@@ -575,22 +588,23 @@ __device__ void produce_state(const Inst& I, const SmallE& S, const GroupShared&
         int64_t acc = kINF;
         if (lane < 24 && o < (left ? wb : wa)) {
             const int64_t vin = G.vbuf[left ? i * wb + o : o * wb + i][tp];
-            if (vin < kINF) acc = vin + (left ? I.tail[b_lo + o] : 0) + fx(au_pen(S, tp), s);
+            if (vin < kINF) acc = vin + (left ? I.tail()[b_lo + o] : 0) + fx(au_pen(S, tp), s);
         }
         acc = norm_inf(wave_min(acc));
         if (lane == 0) {
-            if (left) I.BI[(int64_t)st * kLMRing + (g & (kLMRing - 1))] = acc;
-            else I.BJ[(int64_t)st * kLMRing + (g & (kLMRing - 1))] = acc;
+            if (left) I.BI()[(int64_t)st * kLMRing + (g & (kLMRing - 1))] = acc;
+            else I.BJ()[(int64_t)st * kLMRing + (g & (kLMRing - 1))] = acc;
         }
     }
 }
 
-__device__ GroupCounters span_group(const Inst& I, const SmallE& S, const EnergyTables* __restrict__ E,
-                                    const int32_t* __restrict__ spec, int p, int q, GroupShared& G) {
+template <int NW, class IT>
+__device__ GroupCounters span_group(const IT& I, const SmallE& S, const EnergyTables* __restrict__ E,
+                                    const int32_t* __restrict__ spec, int p, int q, GroupShared<NW>& G) {
     const int g = q - p, s = I.shift;
     const int tid = threadIdx.x, wave = tid >> 6, lane = tid & 63, nw = blockDim.x >> 6;
     GroupCounters ctr{0, 0, 0};
-    const int a_lo = I.off[p], a_hi = I.off[p + 1], b_lo = I.off[q], b_hi = I.off[q + 1];
+    const int a_lo = I.off()[p], a_hi = I.off()[p + 1], b_lo = I.off()[q], b_hi = I.off()[q + 1];
     const int wa = a_hi - a_lo, wb = b_hi - b_lo, ncell = wa * wb;
     // separable interior minima of this layer pair (both segments separable), per class
     int64_t mini0 = kINF, mini1 = kINF;
@@ -599,7 +613,7 @@ __device__ GroupCounters span_group(const Inst& I, const SmallE& S, const Energy
         for (int k = tid; k < kPairCnt[kListFast][ph][cap]; k += blockDim.x) {
             const int code = kPairList[kListFast][ph][k], l1 = code & 31, l2 = (code >> 5) & 31;
             const int cl = p + 1 + l1, dl = q - 1 - l2, X = pair_class(l1, l2);
-            const int64_t lm = I.LM[lm_idx(cl, dl - cl, X)];
+            const int64_t lm = I.LM()[lm_idx(cl, dl - cl, X)];
             if (lm >= kINF) continue;
             const int64_t v = lm + fx(interior_base(S, l1, l2), s) + PLt(I, p, l1) + PRt(I, q, l2);
             if (X) mini1 = mn(mini1, v);
@@ -621,7 +635,7 @@ __device__ GroupCounters span_group(const Inst& I, const SmallE& S, const Energy
             if (k < ncell * 6) {
                 const int ci = k / 6, t = k - 6 * ci;
                 G.vbuf[ci][t] = kINF;
-                job = g >= 5 && I.out_dst[(a_lo + ci / wb) * 4 + kTX[t]] >= 0;
+                job = g >= 5 && I.out_dst()[(a_lo + ci / wb) * 4 + kTX[t]] >= 0;
             }
             const unsigned long long m = __ballot(job);
             if (job) G.combo[base + __popcll(m & ((1ull << lane) - 1ull))] = k;
@@ -652,42 +666,42 @@ __device__ GroupCounters span_group(const Inst& I, const SmallE& S, const Energy
     // spans.
     for (int ci = wave; ci < ncell; ci += nw) {
         const int a = a_lo + ci / wb, b = b_lo + ci % wb;
-        const int64_t cell = I.rowoff[a] + (b - I.off[p + 1]);
+        const int64_t cell = I.rowoff()[a] + (b - I.off()[p + 1]);
         int64_t Bv = kINF;
         for (int t = 0; t < 6; t++) {
             const int64_t v = G.vbuf[ci][t];
-            if (lane == t) I.V[cell * 6 + t] = v;
+            if (lane == t) I.V()[cell * 6 + t] = v;
             if (v < kINF) Bv = mn(Bv, v + fx(S.ml_intern + au_pen(S, t), s));
         }
-        const int committed = I.ccnt[b];
-        const int64_t cbase = I.coff[b];
-        const int ib0 = I.in_start[b], ib1 = I.in_start[b + 1];
+        const int committed = I.ccnt()[b];
+        const int64_t cbase = I.coff()[b];
+        const int ib0 = I.in_start()[b], ib1 = I.in_start()[b + 1];
         int64_t s2 = kINF;
         for (int eb = ib0 + lane; eb < ib1; eb += 64) {
-            const int bp = I.in_src[eb];
-            if (I.layer[bp] > p) s2 = mn(s2, I.S2[cell_of(I, a, bp)] + I.in_U[eb] + I.mlbase_fx);
+            const int bp = I.in_src()[eb];
+            if (I.layer()[bp] > p) s2 = mn(s2, I.S2()[cell_of(I, a, bp)] + I.in_U()[eb] + I.mlbase_fx);
         }
-        const int64_t arow = I.rowoff[a] - I.off[p + 1];
+        const int64_t arow = I.rowoff()[a] - I.off()[p + 1];
         for (int k = lane; k < committed; k += 64) {
-            const int c = I.cc[cbase + k] & 0x7fffffff;
-            s2 = mn(s2, I.S1[arow + c] + I.cB[cbase + k]);
+            const int c = I.cc()[cbase + k] & 0x7fffffff;
+            s2 = mn(s2, I.S1()[arow + c] + I.cB()[cbase + k]);
         }
         s2 = norm_inf(wave_min(s2));
         int64_t ps = s2;
         if (lane < 4) {
-            const int ap = I.out_dst[a * 4 + lane];
-            if (ap >= 0 && I.layer[ap] < q)
-                ps = mn(ps, I.S1[cell_of(I, ap, b)] + I.out_U[a * 4 + lane] + I.mlbase_fx);
+            const int ap = I.out_dst()[a * 4 + lane];
+            if (ap >= 0 && I.layer()[ap] < q)
+                ps = mn(ps, I.S1()[cell_of(I, ap, b)] + I.out_U()[a * 4 + lane] + I.mlbase_fx);
         }
         for (int eb = ib0 + lane; eb < ib1; eb += 64) {
-            const int bp = I.in_src[eb];
-            if (I.layer[bp] > p) ps = mn(ps, I.S1[cell_of(I, a, bp)] + I.in_U[eb] + I.mlbase_fx);
+            const int bp = I.in_src()[eb];
+            if (I.layer()[bp] > p) ps = mn(ps, I.S1()[cell_of(I, a, bp)] + I.in_U()[eb] + I.mlbase_fx);
         }
         ps = norm_inf(wave_min(ps));
         if (lane == 0) {
-            I.Bt[cell] = Bv;
-            I.S2[cell] = s2;
-            I.S1[cell] = mn(Bv, ps);
+            I.Bt()[cell] = Bv;
+            I.S2()[cell] = s2;
+            I.S1()[cell] = mn(Bv, ps);
             const bool strict = Bv < ps;
             G.keep[ci] = I.retain_all ? (Bv < kINF ? (strict ? 1 : 2) : 0) : (strict ? 1 : 0);
             G.cellB[ci] = Bv;
@@ -716,28 +730,28 @@ __device__ GroupCounters span_group(const Inst& I, const SmallE& S, const Energy
                 r0 = mn(r0, G.red[w][0]);
                 r1 = mn(r1, G.red[w][1]);
             }
-            I.LM[lm_idx(p, g, 0)] = norm_inf(r0);
-            I.LM[lm_idx(p, g, 1)] = norm_inf(r1);
+            I.LM()[lm_idx(p, g, 0)] = norm_inf(r0);
+            I.LM()[lm_idx(p, g, 1)] = norm_inf(r1);
         }
         // appends in start-state order, one lane per right endpoint (this group owns C_b in
         // this step)
         int added = 0;
         if (lane < wb) {
             const int b = b_lo + lane;
-            const int committed = I.ccnt[b];
+            const int committed = I.ccnt()[b];
             for (int ia = 0; ia < wa; ia++) {
                 const int ci = ia * wb + lane;
                 if (!G.keep[ci]) continue;
                 const int slot = committed + added;
-                if (slot < I.ccap[b]) {
-                    I.cc[I.coff[b] + slot] = (a_lo + ia) | (G.keep[ci] == 1 ? 0 : (int)0x80000000);
-                    I.cB[I.coff[b] + slot] = G.cellB[ci];
+                if (slot < I.ccap()[b]) {
+                    I.cc()[I.coff()[b] + slot] = (a_lo + ia) | (G.keep[ci] == 1 ? 0 : (int)0x80000000);
+                    I.cB()[I.coff()[b] + slot] = G.cellB[ci];
                 } else {
-                    atomicMin(&I.stats[2], (unsigned long long)g);
+                    atomicMin(&I.stats()[2], (unsigned long long)g);
                 }
                 added++;
             }
-            if (added) I.ccnt[b] = min(committed + added, I.ccap[b]);
+            if (added) I.ccnt()[b] = min(committed + added, I.ccap()[b]);
         }
         added += __shfl_xor(added, 1, 64);
         added += __shfl_xor(added, 2, 64);
@@ -747,20 +761,21 @@ __device__ GroupCounters span_group(const Inst& I, const SmallE& S, const Energy
 }
 
 // ---- external column: X(a) for every a of layer L (one workgroup) ------------------------------
-__device__ void ext_column(const Inst& I, const SmallE& S, int L, int64_t* red) {
+template <class IT>
+__device__ void ext_column(const IT& I, const SmallE& S, int L, int64_t* red) {
     const int tid = threadIdx.x;
-    for (int a = I.off[L]; a < I.off[L + 1]; a++) {
+    for (int a = I.off()[L]; a < I.off()[L + 1]; a++) {
         int64_t v = kINF;
         if (tid < 4) {
-            const int d = I.out_dst[a * 4 + tid];
-            if (d >= 0) v = I.out_U[a * 4 + tid] + I.X[d];
+            const int d = I.out_dst()[a * 4 + tid];
+            if (d >= 0) v = I.out_U()[a * 4 + tid] + I.X()[d];
         }
         if (L + 5 <= I.n) {
-            const int bstart = I.off[L + 5];
-            const int64_t base = I.rowoff[a] - I.off[L + 1];
+            const int bstart = I.off()[L + 5];
+            const int64_t base = I.rowoff()[a] - I.off()[L + 1];
             for (int bb = bstart + tid; bb < I.N; bb += blockDim.x) {
-                const int64_t* vr = I.V + (base + bb) * 6;
-                const int64_t xb = I.X[bb];
+                const int64_t* vr = I.V() + (base + bb) * 6;
+                const int64_t xb = I.X()[bb];
 #pragma unroll
                 for (int t = 0; t < 6; t++) {
                     const int64_t vt = vr[t];
@@ -774,36 +789,48 @@ __device__ void ext_column(const Inst& I, const SmallE& S, int L, int64_t* red) 
             if (tid < w) red[tid] = mn(red[tid], red[tid + w]);
             __syncthreads();
         }
-        if (tid == 0) I.X[a] = norm_inf(red[0]);
+        if (tid == 0) I.X()[a] = norm_inf(red[0]);
         __syncthreads();
     }
 }
 
-__device__ __forceinline__ void flush_counters(const Inst& I, const GroupCounters& c, int g, int lane) {
+template <class IT>
+__device__ __forceinline__ void flush_counters(const IT& I, const GroupCounters& c, int g, int lane) {
     if (lane != 0) return;
-    if (c.visits) atomicAdd(&I.stats[0], c.visits);
+    if (c.visits) atomicAdd(&I.stats()[0], c.visits);
     if (c.appends) {
-        atomicAdd(&I.stats[1], c.appends);
-        if (I.span_appends) atomicAdd(&I.span_appends[g], c.appends);
+        atomicAdd(&I.stats()[1], c.appends);
+        if (I.span_appends()) atomicAdd(&I.span_appends()[g], c.appends);
     }
-    if (c.feasible) atomicAdd(&I.stats[3], c.feasible);
+    if (c.feasible) atomicAdd(&I.stats()[3], c.feasible);
 }
 
-// ---- the span step (plain mode): block x < layer pairs handles layer pair (x, x + g) -------------
+// Workgroups are dispatched round-robin over the 8 XCDs (workgroup i on XCD i mod 8), each with
+// its own L2.  Neighbouring layer pairs read each other's rows and rings, so every XCD gets one
+// contiguous band of layer pairs: a bijection of [0, nb) that sends the workgroups of residue x
+// to the x-th band.
+__device__ __forceinline__ int xcd_band(int i, int nb) {
+    const int x = i & 7, k = i >> 3;
+    int base = 0;
+    for (int r = 0; r < x; r++) base += (nb - r + 7) >> 3;
+    return base + k;
+}
+
+// ---- the span step (plain mode): layer pair xcd_band(x) for block x < layer pairs ---------------
 template <int NT>
 __global__ __launch_bounds__(NT) void k_span(Inst I, const EnergyTables* __restrict__ E,
                                              const int32_t* __restrict__ spec, int g,
                                              int ext_layer, int nblk_cells) {
     __shared__ SmallE S;
     __shared__ int64_t red[NT];
-    __shared__ GroupShared G;
+    __shared__ GroupShared<NT / 64> G;
     stage_tables(S, E);
     __syncthreads();
     if ((int)blockIdx.x >= nblk_cells) {
         if (ext_layer >= 0) ext_column(I, S, ext_layer, red);
         return;
     }
-    const int p = blockIdx.x, q = p + g;
+    const int p = xcd_band(blockIdx.x, nblk_cells), q = p + g;
     GroupCounters c = span_group(I, S, E, spec, p, q, G);
     // block-sum the counters (each wave counted its own cells; thread 0 counted appends)
     const int lane = threadIdx.x & 63;
@@ -821,25 +848,25 @@ __global__ __launch_bounds__(256) void k_ext(Inst I, const EnergyTables* __restr
 __global__ void k_init(Inst I) {
     const int tid = blockIdx.x * blockDim.x + threadIdx.x, nt = gridDim.x * blockDim.x;
     for (int i = tid; i < I.N; i += nt) {
-        I.ccnt[i] = 0;
-        I.X[i] = (i == I.N - 1) ? 0 : kINF;
+        I.ccnt()[i] = 0;
+        I.X()[i] = (i == I.N - 1) ? 0 : kINF;
     }
-    for (size_t i = tid; i < (size_t)(I.n + 1) * 2 * kLMRing; i += nt) I.LM[i] = kINF;
+    for (size_t i = tid; i < (size_t)(I.n + 1) * 2 * kLMRing; i += nt) I.LM()[i] = kINF;
     for (size_t i = tid; i < (size_t)I.N * kLMRing * 12; i += nt) {
-        I.IDL[i] = kINF;
-        I.JDL[i] = kINF;
+        I.IDL()[i] = kINF;
+        I.JDL()[i] = kINF;
     }
     for (size_t i = tid; i < (size_t)I.N * kLMRing; i += nt) {
-        I.BI[i] = kINF;
-        I.BJ[i] = kINF;
+        I.BI()[i] = kINF;
+        I.BJ()[i] = kINF;
     }
     for (size_t i = tid; i < (size_t)I.N * kLMRing * 16; i += nt) {
-        I.RS[i] = kINF;
-        I.LS[i] = kINF;
+        I.RS()[i] = kINF;
+        I.LS()[i] = kINF;
     }
-    if (tid < 4) I.stats[tid] = tid == 2 ? ~0ull : 0ull;
-    if (I.span_appends)
-        for (int i = tid; i <= I.n; i += nt) I.span_appends[i] = 0;
+    if (tid < 4) I.stats()[tid] = tid == 2 ? ~0ull : 0ull;
+    if (I.span_appends())
+        for (int i = tid; i <= I.n; i += nt) I.span_appends()[i] = 0;
 }
 
 // ---- batched persistent kernel ------------------------------------------------------------------
@@ -883,7 +910,7 @@ __global__ __launch_bounds__(NT) void k_persistent(const Inst* __restrict__ inst
                                                     unsigned spin_cap) {
     __shared__ SmallE S;
     __shared__ int64_t red[NT];
-    __shared__ GroupShared G;
+    __shared__ GroupShared<NT / 64> G;
     __shared__ int pref[kMaxBatch + 1];
     __shared__ int nl[kMaxBatch];
     __shared__ int g0s[kMaxBatch];
@@ -915,10 +942,10 @@ __global__ __launch_bounds__(NT) void k_persistent(const Inst* __restrict__ inst
                 if (pref[mid] <= item) lo = mid;
                 else hi = mid - 1;
             }
-            // the instance index is block-uniform: its descriptor is copied with scalar loads
+            // the instance index is block-uniform
             const int inst = __builtin_amdgcn_readfirstlane(lo);
             const int local = item - pref[inst], g = g0s[inst] + step;
-            const Inst I = insts[inst];
+            const Inst I = insts[inst];  // a few scalar registers: bases and sizes
             const int n = I.n, ncell_items = g <= n ? n - g + 1 : 0;
             if (local < ncell_items) {
                 GroupCounters c = span_group(I, S, E, spec, local, local + g, G);
@@ -945,25 +972,25 @@ __global__ void k_batch_init(const Inst* __restrict__ insts, int ninst, BatchCtl
     }
     if (I.g0 != 1) return;
     for (int i = tid; i < I.N; i += nt) {
-        I.ccnt[i] = 0;
-        I.X[i] = (i == I.N - 1) ? 0 : kINF;
+        I.ccnt()[i] = 0;
+        I.X()[i] = (i == I.N - 1) ? 0 : kINF;
     }
-    for (size_t i = tid; i < (size_t)(I.n + 1) * 2 * kLMRing; i += nt) I.LM[i] = kINF;
+    for (size_t i = tid; i < (size_t)(I.n + 1) * 2 * kLMRing; i += nt) I.LM()[i] = kINF;
     for (size_t i = tid; i < (size_t)I.N * kLMRing * 12; i += nt) {
-        I.IDL[i] = kINF;
-        I.JDL[i] = kINF;
+        I.IDL()[i] = kINF;
+        I.JDL()[i] = kINF;
     }
     for (size_t i = tid; i < (size_t)I.N * kLMRing; i += nt) {
-        I.BI[i] = kINF;
-        I.BJ[i] = kINF;
+        I.BI()[i] = kINF;
+        I.BJ()[i] = kINF;
     }
     for (size_t i = tid; i < (size_t)I.N * kLMRing * 16; i += nt) {
-        I.RS[i] = kINF;
-        I.LS[i] = kINF;
+        I.RS()[i] = kINF;
+        I.LS()[i] = kINF;
     }
-    if (tid < 4) I.stats[tid] = tid == 2 ? ~0ull : 0ull;
-    if (I.span_appends)
-        for (int i = tid; i <= I.n; i += nt) I.span_appends[i] = 0;
+    if (tid < 4) I.stats()[tid] = tid == 2 ? ~0ull : 0ull;
+    if (I.span_appends())
+        for (int i = tid; i <= I.n; i += nt) I.span_appends()[i] = 0;
 }
 
 }  // namespace sd
@@ -1031,6 +1058,7 @@ hipError_t launch_span(const Inst& I, const EnergyTables* E, const int32_t* spec
     const int total = nblk + (ext_layer >= 0 ? 1 : 0);
     if (total == 0) return hipSuccess;
     switch (threads) {
+    case 64: hipLaunchKernelGGL(k_span<64>, dim3(total), dim3(64), 0, st, I, E, spec, g, ext_layer, nblk); break;
     case 256: hipLaunchKernelGGL(k_span<256>, dim3(total), dim3(256), 0, st, I, E, spec, g, ext_layer, nblk); break;
     case 512: hipLaunchKernelGGL(k_span<512>, dim3(total), dim3(512), 0, st, I, E, spec, g, ext_layer, nblk); break;
     case 1024: hipLaunchKernelGGL(k_span<1024>, dim3(total), dim3(1024), 0, st, I, E, spec, g, ext_layer, nblk); break;

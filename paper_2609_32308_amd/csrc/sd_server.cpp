@@ -207,6 +207,16 @@ sd_status admit(sd_server* S) {
         memset(&a.I, 0, sizeof(a.I));
         InstLayout lay = layout_instance(a.L, nullptr, nullptr, a.I);
         a.bytes = lay.a_bytes + lay.b_bytes;
+        if (!lay.a_bytes) {
+            {
+                std::lock_guard<std::mutex> lk(S->mu);
+                S->queue.pop_front();
+            }
+            sd_result r;
+            memset(&r, 0, sizeof(r));
+            finish(S, rq.ticket, SD_E_INTERNAL, r);
+            continue;
+        }
         if (a.bytes > S->pool.size) {  // can never fit: recompute in plain mode outside the pool
             {
                 std::lock_guard<std::mutex> lk(S->mu);
@@ -281,7 +291,7 @@ sd_status round_once(sd_server* S) {
             continue;
         }
         unsigned long long stats[4];
-        e = hipMemcpy(stats, a.I.stats, sizeof(stats), hipMemcpyDeviceToHost);
+        e = hipMemcpy(stats, a.I.stats(), sizeof(stats), hipMemcpyDeviceToHost);
         if (e != hipSuccess) return hip_fail(e, "server stats");
         if (!ok || stats[2] != ~0ull) {
             // barrier failure or candidate overflow: exact recomputation in plain mode
