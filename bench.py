@@ -174,8 +174,8 @@ def served_workload(args, sd, S):
 
     Requests: lengths log-uniform in [50, 2000] aa, lambda uniform in {0, 4}, protein seeds
     200000 + i, arrival times from a seeded exponential.  The sizer is trained on the exact
-    DP's own occupancy logs of synthetic proteins (seeds 100000 + i, lengths log-uniform in
-    [50, 600] to keep the logging run short), 10 % held out.  The plain GPU DP on the same
+    DP's own occupancy logs of synthetic proteins (seeds 100000 + i, same length law, both
+    lambdas), 10 % held out.  The plain GPU DP on the same
     requests, one after another, gives the capacity that sets the offered load.
     """
     params = sd.Params(S.default_params_path())
@@ -183,7 +183,7 @@ def served_workload(args, sd, S):
     ctx = sd.Context(0)
     nreq, ntrain, K = args.requests, args.train_proteins, 8
     # learned sizer: exact occupancy logs -> FP32 MLP trained on the GPU
-    tl = S.batch_lengths(ntrain, 50, 600, seed=100000)
+    tl = S.batch_lengths(ntrain, 50, 2000, seed=100000)
     train = [S.protein(A, 100000 + i) for i, A in enumerate(tl)]
     tlam = [0.0 if i % 2 == 0 else 4.0 for i in range(ntrain)]
     t = time.time()
@@ -219,7 +219,7 @@ def served_workload(args, sd, S):
         c = sd.Context(0)
         if policy == "mlp":
             c.set_sizer(sizer, margin=0.5, slack=8)
-        srv = sd.Server(c, table, params, pool_bytes=args.pool_gib << 30, max_active=256, steps_per_round=32)
+        srv = sd.Server(c, table, params, pool_bytes=args.pool_gib << 30, max_active=256, steps_per_round=64)
         arng = random.Random(12)
         t0 = time.perf_counter()
         tickets, t_sub = [], []
@@ -264,7 +264,7 @@ def served_workload(args, sd, S):
         "plain_sequential": {"designs_per_min": nreq / t_plain * 60.0, "cells_per_s": cells_total / t_plain,
                              "p50_s": sorted(r.t_total_s for r in plain)[nreq // 2]},
         "served_runs": runs,
-        "sizer": {"train_proteins": ntrain, "train_aa_range": [50, 600], "bins": K, "hidden": 64,
+        "sizer": {"train_proteins": ntrain, "train_aa_range": [50, 2000], "bins": K, "hidden": 64,
                   "occupancy_log_s": t_log, "train_s": t_train, "heldout_mse": held},
     }
     print(json.dumps(line), flush=True)
@@ -278,7 +278,7 @@ def main():
     ap.add_argument("--workload", default="config2", choices=["config2", "config3", "batch", "served"])
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--requests", type=int, default=100, help="served: number of requests")
-    ap.add_argument("--train-proteins", type=int, default=200, help="served: proteins in the occupancy log")
+    ap.add_argument("--train-proteins", type=int, default=120, help="served: proteins in the occupancy log")
     ap.add_argument("--pool-gib", type=int, default=8, help="served: device pool of the server")
     ap.add_argument("--copy-calibration-mib", type=int, default=0,
                     help="only run a plain device copy of this many MiB (counter calibration)")

@@ -65,7 +65,10 @@ typedef struct sd_options {
                               context's stream and report the summed kernel time            */
     int span_threads;      /* workgroup size of the plain-mode span step: 0 (library choice),
                               64, 256, 512 or 1024; anything else gives SD_E_ARG at create */
-    int reserved[4];
+    int batch_threads;     /* persistent (batched / served) launch: threads per workgroup, 64 or
+                              256, with batch_per_cu workgroups per CU; both 0: autotuned     */
+    int batch_per_cu;
+    int reserved[2];
 } sd_options;
 
 typedef struct sd_result {
@@ -134,10 +137,11 @@ sd_status sd_lattice_size(const char *protein, int64_t *n_states, int64_t *n_cel
 /* ---- learned candidate-buffer sizing ------------------------------------------------------
  * A small FP32 MLP (22 -> hidden -> hidden -> K, ReLU, sigmoid outputs) trained on the GPU by the
  * library's own kernels.  Input features of a request (sd_sizer_features): log(A)/log(2000),
- * the 20 amino-acid fractions, lambda/4.  Output k: the fraction of the worst-case candidate
- * slots that the exact DP retains for right endpoints b in position bin k (layer(b)/n in
- * [k/K, (k+1)/K)), as logged by sd_occupancy.  Sizing only changes how much memory is reserved:
- * an overflowing reservation falls back to exact worst-case segments, results are unchanged. */
+ * the 20 amino-acid fractions, lambda/4.  Output k: the largest fraction of its worst-case
+ * candidate slots that the exact DP retains for any right endpoint b in position bin k
+ * (layer(b)/n in [k/K, (k+1)/K); endpoints with fewer than 64 worst-case slots excluded), as
+ * logged by sd_occupancy.  Sizing only changes how much memory is reserved: an overflowing
+ * reservation falls back to exact worst-case segments, results are unchanged. */
 typedef struct sd_sizer sd_sizer;
 sd_status sd_sizer_create(sd_context *ctx, int hidden, int n_out, uint64_t seed, sd_sizer **out);
 void sd_sizer_free(sd_sizer *z);
@@ -157,7 +161,8 @@ sd_status sd_sizer_features(const char *protein, double lambda_kcal, float out[2
  * the context's use of it. */
 sd_status sd_context_set_sizer(sd_context *ctx, const sd_sizer *z, float margin, int slack);
 /* Exact occupancy log: designs n requests (batched, worst-case segments) and writes Y[n][K], the
- * per-bin retained fraction of the worst-case slots, plus the results (may be NULL). */
+ * per-bin largest retained fraction of the worst-case slots (see above), plus the results (may
+ * be NULL). */
 sd_status sd_occupancy(sd_context *ctx, int n, const char *const *proteins, const double *lambdas,
                        const sd_codon_table *table, const sd_params *params, int K, float *Y,
                        sd_result *outs);

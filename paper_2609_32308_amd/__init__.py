@@ -41,7 +41,8 @@ class SDError(RuntimeError):
 
 class Options(C.Structure):
     _fields_ = [("retain_all", C.c_int), ("capacity_override", C.c_int), ("kernel_timing", C.c_int),
-                ("span_threads", C.c_int), ("reserved", C.c_int * 4)]
+                ("span_threads", C.c_int), ("batch_threads", C.c_int), ("batch_per_cu", C.c_int),
+                ("reserved", C.c_int * 2)]
 
 
 class ServerCfg(C.Structure):
@@ -201,8 +202,10 @@ def _convert(r: _Result) -> Result:
 
 class Context:
     def __init__(self, device: int = 0, retain_all: bool = False, capacity_override: int = 0,
-                 kernel_timing: bool = False, span_threads: int = 0):
-        opt = Options(int(retain_all), int(capacity_override), int(kernel_timing), int(span_threads))
+                 kernel_timing: bool = False, span_threads: int = 0, batch_threads: int = 0,
+                 batch_per_cu: int = 0):
+        opt = Options(int(retain_all), int(capacity_override), int(kernel_timing), int(span_threads),
+                      int(batch_threads), int(batch_per_cu))
         h = C.c_void_p()
         _check(lib().sd_context_create(device, C.byref(opt), C.byref(h)), "sd_context_create")
         self.h = h

@@ -149,7 +149,19 @@ extern "C" sd_status sd_context_create(int device, const sd_options* opt, sd_con
         delete c;
         return fail(SD_E_ARG, "span_threads must be 0, 64, 256, 512 or 1024");
     }
+    if ((c->opt.batch_threads != 0 && c->opt.batch_threads != 64 && c->opt.batch_threads != 256) ||
+        (c->opt.batch_threads != 0) != (c->opt.batch_per_cu > 0) || c->opt.batch_per_cu < 0) {
+        delete c;
+        return fail(SD_E_ARG, "batch_threads must be 0, 64 or 256, with batch_per_cu > 0 exactly when it is set");
+    }
     e = hipSetDevice(device);
+    if (e == hipSuccess && c->opt.batch_threads) {
+        int per_cu = 0;
+        if (persistent_occupancy(c->opt.batch_threads, &per_cu) != hipSuccess || c->opt.batch_per_cu > per_cu) {
+            delete c;
+            return fail(SD_E_ARG, "batch_per_cu exceeds the co-resident workgroups per CU");
+        }
+    }
     if (e == hipSuccess) e = hipStreamCreateWithFlags(&c->stream, hipStreamNonBlocking);
     if (e == hipSuccess) e = upload_pair_order();
     if (e == hipSuccess) e = hipEventCreate(&c->ev0);
@@ -245,7 +257,7 @@ InstLayout layout_instance(const Lattice& L, char* A, char* B, Inst& I) {
         {I.betaU(), 32 * N, 4 * U}, {I.fwd_off(), 4 * (int64_t)L.fwd_off.size(), 3 * U},
         {I.bwd_off(), 4 * (int64_t)L.bwd_off.size(), 3 * U}, {I.hpB(), 8 * (int64_t)L.hpB.size(), 16 * U},
         {I.OB(), 8 * (int64_t)L.OB.size(), 72 * U}, {I.OA(), 8 * (int64_t)L.OA.size(), 72 * U},
-        {I.stats(), 32, U}, {I.span_appends(), 8 * (n + 1), U},
+        {I.stats(), 32, U}, {I.visits(), 8 * (n + 1), U}, {I.feasible(), 8 * (n + 1), U},
         {I.LM(), 8 * (int64_t)kLMRing * (n + 1) * 2, 2 * R}, {I.IDL(), 8 * (int64_t)kLMRing * N * 12, 12 * R},
         {I.JDL(), 8 * (int64_t)kLMRing * N * 12, 12 * R}, {I.BI(), 8 * (int64_t)kLMRing * N, R},
         {I.BJ(), 8 * (int64_t)kLMRing * N, R}, {I.RS(), 8 * (int64_t)kLMRing * N * 16, 16 * R},
@@ -331,6 +343,23 @@ sd_status place_and_upload(sd_context* c, const Lattice& L, Inst& I) {
     return SD_OK;
 }
 
+// Counters of a finished instance: out[0] candidate visits, out[2] earliest overflow span (all
+// ones if none), out[3] cells with finite B; out[1] is unused.  Synchronises the stream.
+hipError_t read_stats(const Inst& I, hipStream_t st, unsigned long long out[4]) {
+    std::vector<unsigned long long> v(I.n + 1), f(I.n + 1);
+    hipError_t e = hipMemcpyAsync(out, I.stats(), 4 * sizeof(unsigned long long), hipMemcpyDeviceToHost, st);
+    if (e == hipSuccess) e = hipMemcpyAsync(v.data(), I.visits(), v.size() * 8, hipMemcpyDeviceToHost, st);
+    if (e == hipSuccess) e = hipMemcpyAsync(f.data(), I.feasible(), f.size() * 8, hipMemcpyDeviceToHost, st);
+    if (e == hipSuccess) e = hipStreamSynchronize(st);
+    if (e != hipSuccess) return e;
+    out[0] = out[1] = out[3] = 0;
+    for (size_t i = 0; i < v.size(); i++) {
+        out[0] += v[i];
+        out[3] += f[i];
+    }
+    return hipSuccess;
+}
+
 // Plain mode: one span-step launch per span length.  Returns the overflow span (0 if none).
 sd_status run_plain(sd_context* c, const Lattice& L, Inst& I, int64_t* overflow_span) {
     hipStream_t st = c->stream;
@@ -352,8 +381,7 @@ sd_status run_plain(sd_context* c, const Lattice& L, Inst& I, int64_t* overflow_
     }
     if (e == hipSuccess) e = launch_ext(I, (const EnergyTables*)c->E_dev, 0, st);
     unsigned long long stats[4];
-    if (e == hipSuccess) e = hipMemcpyAsync(stats, I.stats(), sizeof(stats), hipMemcpyDeviceToHost, st);
-    if (e == hipSuccess) e = hipStreamSynchronize(st);
+    if (e == hipSuccess) e = read_stats(I, st, stats);
     if (e != hipSuccess) return hip_fail(e, "span wavefront");
     *overflow_span = stats[2] == ~0ull ? 0 : (int64_t)stats[2];
     c->last_kernel_ms = 0.0;
@@ -366,7 +394,6 @@ sd_status run_plain(sd_context* c, const Lattice& L, Inst& I, int64_t* overflow_
             c->last_kernel_ms += ms;
         }
     c->last_visits = (int64_t)stats[0];
-    c->last_appends = (int64_t)stats[1];
     c->last_feasible = (int64_t)stats[3];
     return SD_OK;
 }
@@ -454,18 +481,21 @@ CapPolicy policy_for(const sd_context* c, const char* protein, double lambda, st
     return cp;
 }
 
-// Exact occupancy of one finished design: per position bin, retained strict candidates over the
-// worst-case slots of the bin's right endpoints.
+// Exact occupancy of one finished design: per position bin, the largest fraction of its
+// worst-case slots that any right endpoint of the bin filled with retained strict candidates
+// (endpoints with fewer than 64 worst-case slots are left to the sizing slack).  A reservation
+// of this fraction covers every endpoint of the bin, which is what an overflow-free size needs.
 void occupancy_bins(const Lattice& L, const TraceTables& T, int K, float* y) {
-    std::vector<double> num(K, 0.0), den(K, 0.0);
+    std::vector<double> mx(K, 0.0);
     for (int b = 0; b < L.N; b++) {
         const int lb = L.layer[b], k = position_bin(lb, L.n, K);
-        den[k] += lb >= 5 ? L.off[lb - 4] : 0;
+        const int worst = lb >= 5 ? L.off[lb - 4] : 0;
+        if (worst < 64) continue;
         int cnt = 0;
         for (int j = 0; j < T.ccnt[b]; j++) cnt += T.cc[L.coff[b] + j] >= 0;
-        num[k] += cnt;
+        mx[k] = std::max(mx[k], (double)cnt / worst);
     }
-    for (int k = 0; k < K; k++) y[k] = den[k] > 0 ? (float)(num[k] / den[k]) : 0.f;
+    for (int k = 0; k < K; k++) y[k] = (float)mx[k];
 }
 
 // One plain design; optionally keeps the downloaded tables.
@@ -686,36 +716,53 @@ sd_status run_batch(sd_context* c, std::vector<Lattice>& Ls, std::vector<Inst>& 
 // Schedule of the persistent launch: threads per block (one wave per layer-pair item, or four
 // waves sharing an item) and resident blocks per CU.  The first batched call on a context times a
 // probe batch with each candidate and keeps the fastest (the probe's results are discarded).
-sd_status tuned_schedule(sd_context* c, const sd_codon_table* table, const sd_params* params, int* grid,
-                         int* threads) {
-    if (c->batch_grid > 0) {
-        *grid = c->batch_grid;
-        *threads = c->batch_threads;
+// Autotuned persistent schedule (threads per workgroup, workgroups per CU).  The probe is a
+// sample of the batch itself: up to 12 members spread over its sorted lengths, designed with
+// worst-case segments under every candidate schedule; the fastest is kept per size class
+// (log2 of the mean length of the batch), so later batches of similar sizes reuse it.
+sd_status tuned_schedule(sd_context* c, const std::vector<Lattice>& batch, int* grid, int* threads) {
+    if (c->opt.batch_threads > 0) {  // fixed by the caller
+        *threads = c->opt.batch_threads;
+        *grid = c->opt.batch_per_cu * c->num_cu;
         return SD_OK;
     }
-    static const char* aa = "ACDEFGHIKLMNPQRSTVWY";
-    uint64_t st = 0x9E3779B97F4A7C15ull;
-    std::vector<Lattice> Ls(24);
-    std::string err;
-    for (int i = 0; i < 24; i++) {
-        st = st * 6364136223846793005ull + 1442695040888963407ull;
-        int len = 60 + (int)((st >> 33) % 91);
-        std::string p = "M";
-        for (int k = 1; k < len - 1; k++) {
-            st = st * 6364136223846793005ull + 1442695040888963407ull;
-            p += aa[(st >> 33) % 20];
+    double mean_n = 0;
+    for (const Lattice& L : batch) mean_n += L.n;
+    mean_n /= std::max<size_t>(1, batch.size());
+    const int cls = (int)std::floor(std::log2(std::max(1.0, mean_n)));
+    auto hit = c->sched.find(cls);
+    if (hit != c->sched.end()) {
+        *grid = hit->second.first;
+        *threads = hit->second.second;
+        return SD_OK;
+    }
+    std::vector<int> order(batch.size());
+    for (size_t i = 0; i < order.size(); i++) order[i] = (int)i;
+    std::sort(order.begin(), order.end(), [&](int x, int y) { return batch[x].n < batch[y].n; });
+    const int m = (int)std::min<size_t>(12, batch.size());
+    std::vector<Lattice> Ls;
+    for (int i = 0; i < m; i++) {
+        Lattice L = batch[order[(size_t)i * batch.size() / m]];
+        L.ccap.assign(L.N, 0);  // worst-case segments for the probe
+        int64_t acc = 0;
+        for (int b = 0; b < L.N; b++) {
+            const int lb = L.layer[b];
+            L.coff[b] = acc;
+            L.ccap[b] = lb >= 5 ? L.off[lb - 4] : 0;
+            acc += L.ccap[b];
         }
-        p += "*";
-        int rc = build_lattice(p.c_str(), table->t, params->p, (i & 1) ? 4.0 : 0.0, CapPolicy(), Ls[i], err);
-        if (rc) return fail((sd_status)rc, err);
+        L.cand_slots = acc;
+        Ls.push_back(std::move(L));
     }
     double best_t = 1e30;
+    int best_grid = 0, best_threads = 256;
     for (int threads_c : {256, 64}) {
         int per_cu = 0;
         hipError_t e = persistent_occupancy(threads_c, &per_cu);
         if (e != hipSuccess || per_cu <= 0) return hip_fail(e, "occupancy query");
         std::vector<int> cands = {per_cu};
-        if (per_cu > 1) cands.push_back(per_cu / 2);
+        if (per_cu > 2) cands.push_back((per_cu + 1) / 2);
+        if (per_cu > 1) cands.push_back(1);
         for (int k : cands) {
             const int gr = k * c->num_cu;
             std::vector<Inst> Is;
@@ -725,14 +772,17 @@ sd_status tuned_schedule(sd_context* c, const sd_codon_table* table, const sd_pa
             if (s) return s;
             if (ok && ks < best_t) {
                 best_t = ks;
-                c->batch_grid = gr;
-                c->batch_threads = threads_c;
+                best_grid = gr;
+                best_threads = threads_c;
             }
         }
     }
-    if (c->batch_grid <= 0) return fail(SD_E_DEVICE, "no persistent schedule completed its grid barriers");
-    *grid = c->batch_grid;
-    *threads = c->batch_threads;
+    if (best_grid <= 0) return fail(SD_E_DEVICE, "no persistent schedule completed its grid barriers");
+    c->sched[cls] = {best_grid, best_threads};
+    c->batch_grid = best_grid;
+    c->batch_threads = best_threads;
+    *grid = best_grid;
+    *threads = best_threads;
     return SD_OK;
 }
 
@@ -763,7 +813,7 @@ extern "C" sd_status sd_design_batch(sd_context* ctx, int n, const char* const* 
             }
             sd_status s = ensure_params(ctx, params);
             int grid = 0, threads = 256;
-            if (!s) s = tuned_schedule(ctx, table, params, &grid, &threads);
+            if (!s) s = tuned_schedule(ctx, Ls, &grid, &threads);
             const double tf0 = now_s();
             std::vector<Inst> Is;
             bool ok = false;
@@ -779,7 +829,7 @@ extern "C" sd_status sd_design_batch(sd_context* ctx, int n, const char* const* 
             for (int i = 0; i < m && s == SD_OK; i++) {
                 const int gi = done + i;
                 unsigned long long st[4];
-                hipError_t e = hipMemcpy(st, Is[i].stats(), sizeof(st), hipMemcpyDeviceToHost);
+                hipError_t e = read_stats(Is[i], ctx->stream, st);
                 if (e != hipSuccess) {
                     s = hip_fail(e, "batch stats");
                     break;

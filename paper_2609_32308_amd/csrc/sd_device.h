@@ -3,6 +3,7 @@
 #include <hip/hip_runtime.h>
 
 #include <string>
+#include <map>
 #include <vector>
 
 #include "../../include/sparsedesign.h"
@@ -20,6 +21,7 @@ struct sd_context {
     size_t staging_bytes = 0;
     int batch_grid = 0;       // autotuned persistent grid size (0: not tuned yet)
     int batch_threads = 256;  // autotuned threads per block of the persistent launch
+    std::map<int, std::pair<int, int>> sched;  // size class -> (grid, threads) from the tuner
     bool last_graph = false;  // last batch ran as a captured graph
     double last_batch_kernel_s = 0.0, last_batch_fill_s = 0.0;
     int64_t last_batch_fallbacks = 0;
@@ -46,6 +48,7 @@ struct InstLayout {
 struct Lattice;
 struct Params;
 InstLayout layout_instance(const Lattice& L, char* A, char* B, Inst& I);
+hipError_t read_stats(const Inst& I, hipStream_t st, unsigned long long out[4]);
 void stage_inputs(const Lattice& L, const Inst& I, const char* devA, char* image);
 hipError_t upload_pair_order();
 hipError_t launch_init(const Inst& I, hipStream_t st);

@@ -49,8 +49,8 @@ constexpr int kSpecOff5 = 0, kSpecOff6 = 1024, kSpecOff8 = 1024 + 4096, kSpecSiz
 //   0 layer[N]  1 off[n+2]  2 in_start[N+1]  3 tail[N]  4 pfx[N]  5 P[A+1]  6 hp_init[n+1]
 //   7 rowoff[N]  8 coff[N]  9 ccap[N]  10 ccnt[N]  11 X[N]  12-13 out_dst[4N]  14-17 out_U[4N]
 //   18-21 alphaU[4N]  22-25 betaU[4N]  26-28 fwd_off[4N+1]  29-31 bwd_off[4N+1]
-//   32-47 hpB[16N]  48-119 OB[72N]  120-191 OA[72N]  192 stats[4]  193 span_appends[n+1]
-//   194.. in_src[nE], in_lab[nE], in_U[nE], fwd_meta[nF], fwd_cost[nF], bwd_meta[nB],
+//   32-47 hpB[16N]  48-119 OB[72N]  120-191 OA[72N]  192 stats[4]  193 visits[n+1]
+//   194 feasible[n+1]  195.. in_src[nE], in_lab[nE], in_U[nE], fwd_meta[nF], fwd_cost[nF], bwd_meta[nB],
 //         bwd_cost[nB] (each start 8-byte aligned)
 // Region B (DP tables) is cut into ring units of R = 512 * N bytes (N states x 64 spans x 8 B):
 //   0-1 LM  2-13 IDL  14-25 JDL  26 BI  27 BJ  28-43 RS  44-59 LS, then from 60 R:
@@ -64,8 +64,9 @@ constexpr int kSpecOff5 = 0, kSpecOff6 = 1024, kSpecOff8 = 1024 + 4096, kSpecSiz
 //   cell(a,b) = rowoff[a] + b - off[layer(a)+1]; V/Bt/S1/S2: typed closed values, branch value,
 //   multiloop prefixes; coff/ccap/ccnt/cc/cB: candidate segment per right endpoint (offset,
 //   capacity, committed count, start states with the non-strict flag in bit 31, B values);
-//   X: external column; stats: [0] visits [1] appends [2] earliest overflow span [3] finite B;
-//   span_appends: appended candidates per span.
+//   X: external column; stats: [2] earliest overflow span (others unused); visits / feasible:
+//   candidate visits and cells with finite B, summed per left layer (one adder per layer pair
+//   and step, so the counters see no contention).
 //   alphaU[d*4+x] = U(d -x-> d2) + tail(d2); betaU[c*4+x] = min U over in-edges of c labelled x.
 //   LM[layer][class 2][span]: layer-pair minima of the both-separable interior form.
 //   IDL/JDL[state][class 3][label 4][span]: inner minima per left / right inner state.
@@ -113,11 +114,12 @@ struct Inst {
     __host__ __device__ const int64_t* OB() const { return (const int64_t*)ua(48); }
     __host__ __device__ const int64_t* OA() const { return (const int64_t*)ua(120); }
     __host__ __device__ unsigned long long* stats() const { return (unsigned long long*)ua(192); }
-    __host__ __device__ unsigned long long* span_appends() const { return (unsigned long long*)ua(193); }
-    __host__ __device__ const int* in_src() const { return (const int*)ua(194); }
-    __host__ __device__ const int* in_lab() const { return (const int*)(ua(194) + al8(4 * nE)); }
-    __host__ __device__ const int64_t* in_U() const { return (const int64_t*)(ua(194) + 2 * al8(4 * nE)); }
-    __host__ __device__ char* paths() const { return ua(194) + 2 * al8(4 * nE) + 8 * nE; }
+    __host__ __device__ unsigned long long* visits() const { return (unsigned long long*)ua(193); }
+    __host__ __device__ unsigned long long* feasible() const { return (unsigned long long*)ua(194); }
+    __host__ __device__ const int* in_src() const { return (const int*)ua(195); }
+    __host__ __device__ const int* in_lab() const { return (const int*)(ua(195) + al8(4 * nE)); }
+    __host__ __device__ const int64_t* in_U() const { return (const int64_t*)(ua(195) + 2 * al8(4 * nE)); }
+    __host__ __device__ char* paths() const { return ua(195) + 2 * al8(4 * nE) + 8 * nE; }
     __host__ __device__ const int* fwd_meta() const { return (const int*)paths(); }
     __host__ __device__ const int64_t* fwd_cost() const { return (const int64_t*)(paths() + al8(4 * nF)); }
     __host__ __device__ const int* bwd_meta() const { return (const int*)(paths() + al8(4 * nF) + 8 * nF); }
@@ -152,6 +154,8 @@ struct BatchCtl {
     unsigned int gen;    // barrier generation
     int err;             // set when a barrier wait exceeds its spin limit (every group then exits)
     int steps_done;      // spans completed (diagnostics)
+    unsigned int next;   // work tickets handed out so far (items of all steps, in step order)
+    unsigned int pad[3];
 };
 constexpr int kMaxBatch = 1024;  // instances per persistent launch
 

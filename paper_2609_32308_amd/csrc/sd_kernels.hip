@@ -795,14 +795,10 @@ __device__ void ext_column(const IT& I, const SmallE& S, int L, int64_t* red) {
 }
 
 template <class IT>
-__device__ __forceinline__ void flush_counters(const IT& I, const GroupCounters& c, int g, int lane) {
+__device__ __forceinline__ void flush_counters(const IT& I, const GroupCounters& c, int p, int lane) {
     if (lane != 0) return;
-    if (c.visits) atomicAdd(&I.stats()[0], c.visits);
-    if (c.appends) {
-        atomicAdd(&I.stats()[1], c.appends);
-        if (I.span_appends()) atomicAdd(&I.span_appends()[g], c.appends);
-    }
-    if (c.feasible) atomicAdd(&I.stats()[3], c.feasible);
+    if (c.visits) atomicAdd(&I.visits()[p], c.visits);
+    if (c.feasible) atomicAdd(&I.feasible()[p], c.feasible);
 }
 
 // Workgroups are dispatched round-robin over the 8 XCDs (workgroup i on XCD i mod 8), each with
@@ -834,7 +830,7 @@ __global__ __launch_bounds__(NT) void k_span(Inst I, const EnergyTables* __restr
     GroupCounters c = span_group(I, S, E, spec, p, q, G);
     // block-sum the counters (each wave counted its own cells; thread 0 counted appends)
     const int lane = threadIdx.x & 63;
-    flush_counters(I, c, g, lane);
+    flush_counters(I, c, p, lane);
 }
 
 __global__ __launch_bounds__(256) void k_ext(Inst I, const EnergyTables* __restrict__ E, int L) {
@@ -865,8 +861,10 @@ __global__ void k_init(Inst I) {
         I.LS()[i] = kINF;
     }
     if (tid < 4) I.stats()[tid] = tid == 2 ? ~0ull : 0ull;
-    if (I.span_appends())
-        for (int i = tid; i <= I.n; i += nt) I.span_appends()[i] = 0;
+    for (int i = tid; i <= I.n; i += nt) {
+        I.visits()[i] = 0;
+        I.feasible()[i] = 0;
+    }
 }
 
 // ---- batched persistent kernel ------------------------------------------------------------------
@@ -886,14 +884,19 @@ __device__ bool grid_barrier(BatchCtl* ctl, unsigned nblocks, unsigned spin_cap,
             __hip_atomic_store(&ctl->count, 0u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
             __hip_atomic_fetch_add(&ctl->gen, 1u, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_AGENT);
         } else {
+            // poll with relaxed loads: an acquire per poll would invalidate this XCD's caches
+            // over and over under the feet of the workgroups still working; one acquire fence
+            // follows the wait.  The pause between polls grows to about 1.7 us.
             unsigned spins = 0;
-            while (__hip_atomic_load(&ctl->gen, __ATOMIC_ACQUIRE, __HIP_MEMORY_SCOPE_AGENT) == g0) {
+            int pause = 1;
+            while (__hip_atomic_load(&ctl->gen, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) == g0) {
                 if (__hip_atomic_load(&ctl->err, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) || ++spins > spin_cap) {
                     __hip_atomic_store(&ctl->err, 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
                     err = 1;
                     break;
                 }
-                __builtin_amdgcn_s_sleep(2);
+                for (int k = 0; k < pause; k++) __builtin_amdgcn_s_sleep(4);
+                if (pause < 16) pause <<= 1;
             }
         }
         __threadfence();
@@ -904,7 +907,7 @@ __device__ bool grid_barrier(BatchCtl* ctl, unsigned nblocks, unsigned spin_cap,
 }
 
 template <int NT>
-__global__ __launch_bounds__(NT) void k_persistent(const Inst* __restrict__ insts, int ninst, int nsteps,
+__global__ __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(4))) void k_persistent(const Inst* __restrict__ insts, int ninst, int nsteps,
                                                     const EnergyTables* __restrict__ E,
                                                     const int32_t* __restrict__ spec, BatchCtl* ctl,
                                                     unsigned spin_cap) {
@@ -915,12 +918,18 @@ __global__ __launch_bounds__(NT) void k_persistent(const Inst* __restrict__ inst
     __shared__ int nl[kMaxBatch];
     __shared__ int g0s[kMaxBatch];
     __shared__ int s_flag;
+    __shared__ unsigned s_ticket;
     stage_tables(S, E);
     for (int i = threadIdx.x; i < ninst; i += blockDim.x) {
         nl[i] = insts[i].n;
         g0s[i] = insts[i].g0;
     }
+    // Work tickets: the items of step 0, then those of step 1, ... are numbered consecutively and
+    // handed out by one counter, so workgroups balance uneven items dynamically.  A workgroup
+    // that draws a ticket beyond the current step keeps it for the step it belongs to.
+    if (threadIdx.x == 0) s_ticket = atomicAdd(&ctl->next, 1u);
     __syncthreads();
+    unsigned ticket = s_ticket, base = 0;
     for (int step = 0; step < nsteps; step++) {
         // work items per instance at its span g = g0 + step: layer pairs of span g, then one
         // external column (layer n - g + 1, one layer behind)
@@ -934,8 +943,9 @@ __global__ __launch_bounds__(NT) void k_persistent(const Inst* __restrict__ inst
             pref[ninst] = acc;
         }
         __syncthreads();
-        const int total = pref[ninst];
-        for (int item = blockIdx.x; item < total; item += gridDim.x) {
+        const unsigned total = (unsigned)pref[ninst];
+        while (ticket < base + total) {
+            const int item = (int)(ticket - base);
             int lo = 0, hi = ninst - 1;  // last instance whose prefix <= item
             while (lo < hi) {
                 const int mid = (lo + hi + 1) >> 1;
@@ -949,12 +959,16 @@ __global__ __launch_bounds__(NT) void k_persistent(const Inst* __restrict__ inst
             const int n = I.n, ncell_items = g <= n ? n - g + 1 : 0;
             if (local < ncell_items) {
                 GroupCounters c = span_group(I, S, E, spec, local, local + g, G);
-                flush_counters(I, c, g, threadIdx.x & 63);
+                flush_counters(I, c, local, threadIdx.x & 63);
             } else {
                 ext_column(I, S, n - g + 1, red);
             }
+            __syncthreads();  // the item is done and every thread has read the last ticket
+            if (threadIdx.x == 0) s_ticket = atomicAdd(&ctl->next, 1u);
             __syncthreads();
+            ticket = s_ticket;
         }
+        base += total;
         if (!grid_barrier(ctl, gridDim.x, spin_cap, &s_flag)) return;
         if (blockIdx.x == 0 && threadIdx.x == 0) ctl->steps_done = step + 1;
     }
@@ -969,6 +983,7 @@ __global__ void k_batch_init(const Inst* __restrict__ insts, int ninst, BatchCtl
         ctl->gen = 0;
         ctl->err = 0;
         ctl->steps_done = 0;
+        ctl->next = 0;
     }
     if (I.g0 != 1) return;
     for (int i = tid; i < I.N; i += nt) {
@@ -989,8 +1004,10 @@ __global__ void k_batch_init(const Inst* __restrict__ insts, int ninst, BatchCtl
         I.LS()[i] = kINF;
     }
     if (tid < 4) I.stats()[tid] = tid == 2 ? ~0ull : 0ull;
-    if (I.span_appends())
-        for (int i = tid; i <= I.n; i += nt) I.span_appends()[i] = 0;
+    for (int i = tid; i <= I.n; i += nt) {
+        I.visits()[i] = 0;
+        I.feasible()[i] = 0;
+    }
 }
 
 }  // namespace sd

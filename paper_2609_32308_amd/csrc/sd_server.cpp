@@ -78,6 +78,8 @@ struct Request {
     std::string protein;
     double lambda;
     double t_submit, t_admit = 0;
+    bool worst = false;  // re-admitted after a candidate overflow: worst-case segments
+    int64_t first_slots = 0;
 };
 
 struct Active {
@@ -161,7 +163,9 @@ void worker_main(sd_server* S) {
             s = fill_result(job.a.L, R, job.T.X[0], Z, job.visits, job.feasible, &r);
             r.t_fill_s = job.t_fill;
             r.t_total_s = now_s() - job.a.rq.t_submit;
-            r.cand_slots = r.cand_slots_first = job.a.L.cand_slots;
+            r.cand_slots = job.a.L.cand_slots;
+            r.cand_slots_first = job.a.rq.worst ? job.a.rq.first_slots : job.a.L.cand_slots;
+            r.cand_overflow = job.a.rq.worst ? 1 : 0;
         }
         finish(S, job.a.rq.ticket, s, r);
         std::lock_guard<std::mutex> lk(S->tmu);
@@ -193,7 +197,8 @@ sd_status admit(sd_server* S) {
         std::string err;
         std::vector<float> frac;
         int rc = build_lattice(rq.protein.c_str(), S->table->t, S->params->p, rq.lambda,
-                               policy_for(S->ctx, rq.protein.c_str(), rq.lambda, frac), a.L, err);
+                               rq.worst ? CapPolicy() : policy_for(S->ctx, rq.protein.c_str(), rq.lambda, frac),
+                               a.L, err);
         if (rc) {  // invalid request: answer it right away
             {
                 std::lock_guard<std::mutex> lk(S->mu);
@@ -291,10 +296,24 @@ sd_status round_once(sd_server* S) {
             continue;
         }
         unsigned long long stats[4];
-        e = hipMemcpy(stats, a.I.stats(), sizeof(stats), hipMemcpyDeviceToHost);
+        e = read_stats(a.I, st, stats);
         if (e != hipSuccess) return hip_fail(e, "server stats");
-        if (!ok || stats[2] != ~0ull) {
-            // barrier failure or candidate overflow: exact recomputation in plain mode
+        if (ok && stats[2] != ~0ull) {
+            // candidate overflow of a predicted reservation: the request goes back to the head
+            // of the queue and is redone with worst-case segments (exact; the mix keeps running)
+            S->pool.release(a.off, a.bytes);
+            Request rq = a.rq;
+            rq.worst = true;
+            rq.first_slots = a.L.cand_slots;
+            {
+                std::lock_guard<std::mutex> lk(S->mu);
+                S->queue.push_front(rq);
+            }
+            S->st.fallbacks++;
+            continue;
+        }
+        if (!ok) {
+            // barrier failure: exact recomputation in plain mode
             S->pool.release(a.off, a.bytes);
             sd_result r;
             const int fw = S->ctx->force_worst;
@@ -385,8 +404,13 @@ extern "C" sd_status sd_server_start(sd_context* ctx, const sd_codon_table* tabl
         delete S;
         return hip_fail(e, "occupancy query");
     }
-    S->threads = ctx->batch_grid > 0 ? ctx->batch_threads : 256;
-    S->grid = ctx->batch_grid > 0 ? ctx->batch_grid : per_cu * ctx->num_cu;
+    if (ctx->opt.batch_threads > 0) {  // fixed by the caller (validated at context creation)
+        S->threads = ctx->opt.batch_threads;
+        S->grid = ctx->opt.batch_per_cu * ctx->num_cu;
+    } else {
+        S->threads = ctx->batch_grid > 0 ? ctx->batch_threads : 256;
+        S->grid = ctx->batch_grid > 0 ? ctx->batch_grid : per_cu * ctx->num_cu;
+    }
     for (int i = 0; i < 4; i++) S->workers.emplace_back(worker_main, S);
     S->loop = std::thread(server_main, S);
     *out = S;
