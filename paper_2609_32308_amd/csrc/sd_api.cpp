@@ -649,7 +649,7 @@ sd_status run_batch(sd_context* c, std::vector<Lattice>& Ls, std::vector<Inst>& 
         totB += lay[i].b_bytes;
     }
     const size_t inst_bytes = ((sizeof(Inst) * n + 255) / 256) * 256;
-    sd_status s = ensure_arena(c, totA + totB + inst_bytes + 256);
+    sd_status s = ensure_arena(c, totA + totB + inst_bytes + sizeof(BatchCtl) + 256);
     if (s) return s;
     s = ensure_staging(c, totA);
     if (s) return s;
@@ -709,7 +709,7 @@ sd_status run_batch(sd_context* c, std::vector<Lattice>& Ls, std::vector<Inst>& 
     if (e != hipSuccess) return hip_fail(e, "batched wavefront");
     c->last_graph = captured;
     *kernel_s = ms * 1e-3;
-    *barrier_ok = hctl.err == 0 && hctl.steps_done == maxn + 1;  // nsteps = maxn + 1
+    *barrier_ok = hctl.err.v == 0 && hctl.steps_done.v == (unsigned)(maxn + 1);  // nsteps = maxn + 1
     return SD_OK;
 }
 

@@ -148,14 +148,20 @@ constexpr int kLMRing = 64;
 constexpr int kMaxWaves = 16;  // waves per workgroup of the span-step kernels (1024 threads)
 static_assert(sizeof(Inst) % 8 == 0, "instance descriptors are copied as 8-byte words");
 
-// Batched persistent launch: barrier state shared by all workgroups.
+// Batched persistent launch: barrier and work-ticket state shared by all workgroups.  Workgroup
+// i belongs to group i mod 8 (the XCD it is dispatched to); every contended word sits on its own
+// 128-byte line.
+struct alignas(128) CtlWord {
+    unsigned int v;
+    unsigned int pad[31];
+};
 struct BatchCtl {
-    unsigned int count;  // arrivals at the current barrier
-    unsigned int gen;    // barrier generation
-    int err;             // set when a barrier wait exceeds its spin limit (every group then exits)
-    int steps_done;      // spans completed (diagnostics)
-    unsigned int next;   // work tickets handed out so far (items of all steps, in step order)
-    unsigned int pad[3];
+    CtlWord arrive[8];  // arrivals of each group at the current barrier
+    CtlWord top;        // groups complete at the current barrier
+    CtlWord gen;        // barrier generation
+    CtlWord next[8];    // work tickets handed out per group (its band of every step, in order)
+    CtlWord err;        // set when a barrier wait exceeds its spin limit (every group then exits)
+    CtlWord steps_done; // spans completed (diagnostics)
 };
 constexpr int kMaxBatch = 1024;  // instances per persistent launch
 

@@ -870,28 +870,38 @@ __global__ void k_init(Inst I) {
 // ---- batched persistent kernel ------------------------------------------------------------------
 // All instances advance one global span per grid barrier.  At step g the work items are the layer
 // pairs of span g of every instance with n >= g, followed (per instance) by the external column
-// of layer n - g + 1 (one layer behind).  Items are spread over the resident workgroups; the
-// barrier is an arrival counter plus a generation word with agent-scope release/acquire fences.
-__device__ bool grid_barrier(BatchCtl* ctl, unsigned nblocks, unsigned spin_cap, int* s_flag) {
+// of layer n - g + 1 (one layer behind).  The items of a step are cut into 8 contiguous bands, one
+// per workgroup group (XCD); a group's workgroups draw its band's items from the group's ticket
+// counter.  The barrier is two-level: the last arrival of a group counts the group at the top
+// word, the last group bumps the generation (agent-scope release / acquire).
+__device__ bool grid_barrier(BatchCtl* ctl, unsigned spin_cap, int* s_flag) {
     __syncthreads();
     if (threadIdx.x == 0) {
         __threadfence();
-        const unsigned g0 = __hip_atomic_load(&ctl->gen, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-        const unsigned arrived =
-            __hip_atomic_fetch_add(&ctl->count, 1u, __ATOMIC_ACQ_REL, __HIP_MEMORY_SCOPE_AGENT) + 1u;
+        const unsigned grp = blockIdx.x & 7, ngrp = gridDim.x < 8 ? gridDim.x : 8;
+        const unsigned members = (gridDim.x - grp + 7) >> 3;
+        const unsigned g0 = __hip_atomic_load(&ctl->gen.v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
         int err = 0;
-        if (arrived == nblocks) {
-            __hip_atomic_store(&ctl->count, 0u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-            __hip_atomic_fetch_add(&ctl->gen, 1u, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_AGENT);
-        } else {
+        bool last = false;
+        const unsigned a = __hip_atomic_fetch_add(&ctl->arrive[grp].v, 1u, __ATOMIC_ACQ_REL, __HIP_MEMORY_SCOPE_AGENT) + 1u;
+        if (a == members) {
+            __hip_atomic_store(&ctl->arrive[grp].v, 0u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+            const unsigned t = __hip_atomic_fetch_add(&ctl->top.v, 1u, __ATOMIC_ACQ_REL, __HIP_MEMORY_SCOPE_AGENT) + 1u;
+            if (t == ngrp) {
+                __hip_atomic_store(&ctl->top.v, 0u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+                __hip_atomic_fetch_add(&ctl->gen.v, 1u, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_AGENT);
+                last = true;
+            }
+        }
+        if (!last) {
             // poll with relaxed loads: an acquire per poll would invalidate this XCD's caches
             // over and over under the feet of the workgroups still working; one acquire fence
             // follows the wait.  The pause between polls grows to about 1.7 us.
             unsigned spins = 0;
             int pause = 1;
-            while (__hip_atomic_load(&ctl->gen, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) == g0) {
-                if (__hip_atomic_load(&ctl->err, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) || ++spins > spin_cap) {
-                    __hip_atomic_store(&ctl->err, 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+            while (__hip_atomic_load(&ctl->gen.v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) == g0) {
+                if (__hip_atomic_load(&ctl->err.v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) || ++spins > spin_cap) {
+                    __hip_atomic_store(&ctl->err.v, 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
                     err = 1;
                     break;
                 }
@@ -907,10 +917,9 @@ __device__ bool grid_barrier(BatchCtl* ctl, unsigned nblocks, unsigned spin_cap,
 }
 
 template <int NT>
-__global__ __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(4))) void k_persistent(const Inst* __restrict__ insts, int ninst, int nsteps,
-                                                    const EnergyTables* __restrict__ E,
-                                                    const int32_t* __restrict__ spec, BatchCtl* ctl,
-                                                    unsigned spin_cap) {
+__global__ __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(4))) void k_persistent(
+    const Inst* __restrict__ insts, int ninst, int nsteps, const EnergyTables* __restrict__ E,
+    const int32_t* __restrict__ spec, BatchCtl* ctl, unsigned spin_cap) {
     __shared__ SmallE S;
     __shared__ int64_t red[NT];
     __shared__ GroupShared<NT / 64> G;
@@ -924,10 +933,10 @@ __global__ __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(4))) void k_
         nl[i] = insts[i].n;
         g0s[i] = insts[i].g0;
     }
-    // Work tickets: the items of step 0, then those of step 1, ... are numbered consecutively and
-    // handed out by one counter, so workgroups balance uneven items dynamically.  A workgroup
-    // that draws a ticket beyond the current step keeps it for the step it belongs to.
-    if (threadIdx.x == 0) s_ticket = atomicAdd(&ctl->next, 1u);
+    // Work tickets of group grp number the items of its band of step 0, then of step 1, ...  A
+    // workgroup that draws a ticket beyond the current step keeps it for the step it belongs to.
+    const unsigned grp = blockIdx.x & 7, ngrp = gridDim.x < 8 ? gridDim.x : 8;
+    if (threadIdx.x == 0) s_ticket = atomicAdd(&ctl->next[grp].v, 1u);
     __syncthreads();
     unsigned ticket = s_ticket, base = 0;
     for (int step = 0; step < nsteps; step++) {
@@ -944,8 +953,10 @@ __global__ __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(4))) void k_
         }
         __syncthreads();
         const unsigned total = (unsigned)pref[ninst];
-        while (ticket < base + total) {
-            const int item = (int)(ticket - base);
+        const unsigned lo_item = (unsigned)((uint64_t)total * grp / ngrp);
+        const unsigned band = (unsigned)((uint64_t)total * (grp + 1) / ngrp) - lo_item;
+        while (ticket < base + band) {
+            const int item = (int)(lo_item + (ticket - base));
             int lo = 0, hi = ninst - 1;  // last instance whose prefix <= item
             while (lo < hi) {
                 const int mid = (lo + hi + 1) >> 1;
@@ -964,13 +975,13 @@ __global__ __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(4))) void k_
                 ext_column(I, S, n - g + 1, red);
             }
             __syncthreads();  // the item is done and every thread has read the last ticket
-            if (threadIdx.x == 0) s_ticket = atomicAdd(&ctl->next, 1u);
+            if (threadIdx.x == 0) s_ticket = atomicAdd(&ctl->next[grp].v, 1u);
             __syncthreads();
             ticket = s_ticket;
         }
-        base += total;
-        if (!grid_barrier(ctl, gridDim.x, spin_cap, &s_flag)) return;
-        if (blockIdx.x == 0 && threadIdx.x == 0) ctl->steps_done = step + 1;
+        base += band;
+        if (!grid_barrier(ctl, spin_cap, &s_flag)) return;
+        if (blockIdx.x == 0 && threadIdx.x == 0) ctl->steps_done.v = step + 1;
     }
 }
 
@@ -978,12 +989,15 @@ __global__ __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(4))) void k_
 __global__ void k_batch_init(const Inst* __restrict__ insts, int ninst, BatchCtl* ctl) {
     const Inst& I = insts[blockIdx.x];
     const int tid = threadIdx.x, nt = blockDim.x;
-    if (blockIdx.x == 0 && tid == 0) {
-        ctl->count = 0;
-        ctl->gen = 0;
-        ctl->err = 0;
-        ctl->steps_done = 0;
-        ctl->next = 0;
+    if (blockIdx.x == 0 && tid < 8) {
+        ctl->arrive[tid].v = 0;
+        ctl->next[tid].v = 0;
+        if (tid == 0) {
+            ctl->top.v = 0;
+            ctl->gen.v = 0;
+            ctl->err.v = 0;
+            ctl->steps_done.v = 0;
+        }
     }
     if (I.g0 != 1) return;
     for (int i = tid; i < I.N; i += nt) {

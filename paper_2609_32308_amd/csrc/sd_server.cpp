@@ -285,7 +285,7 @@ sd_status round_once(sd_server* S) {
     const double dt = now_s() - t0;
     S->st.rounds++;
     S->st.gpu_seconds += dt;
-    const bool ok = h.err == 0 && h.steps_done == S->cfg.steps_per_round;
+    const bool ok = h.err.v == 0 && h.steps_done.v == (unsigned)S->cfg.steps_per_round;
     // advance and retire
     std::vector<Active> keep;
     for (int i = 0; i < n; i++) {
@@ -388,7 +388,7 @@ extern "C" sd_status sd_server_start(sd_context* ctx, const sd_codon_table* tabl
     S->cfg = *cfg;
     hipError_t e = hipSetDevice(ctx->device);
     if (e == hipSuccess) e = hipMalloc((void**)&S->pool_dev, cfg->pool_bytes);
-    if (e == hipSuccess) e = hipMalloc((void**)&S->aux_dev, sizeof(Inst) * kMaxBatch + 256);
+    if (e == hipSuccess) e = hipMalloc((void**)&S->aux_dev, sizeof(Inst) * kMaxBatch + sizeof(BatchCtl) + 256);
     if (e != hipSuccess) {
         if (S->pool_dev) hipFree(S->pool_dev);
         delete S;
