@@ -258,11 +258,12 @@ InstLayout layout_instance(const Lattice& L, char* A, char* B, Inst& I) {
         {I.bwd_off(), 4 * (int64_t)L.bwd_off.size(), 3 * U}, {I.hpB(), 8 * (int64_t)L.hpB.size(), 16 * U},
         {I.OB(), 8 * (int64_t)L.OB.size(), 72 * U}, {I.OA(), 8 * (int64_t)L.OA.size(), 72 * U},
         {I.stats(), 32, U}, {I.visits(), 8 * (n + 1), U}, {I.feasible(), 8 * (n + 1), U},
+        {I.inmask(), 4 * N, U},
         {I.LM(), 8 * (int64_t)kLMRing * (n + 1) * 2, 2 * R}, {I.IDL(), 8 * (int64_t)kLMRing * N * 12, 12 * R},
         {I.JDL(), 8 * (int64_t)kLMRing * N * 12, 12 * R}, {I.BI(), 8 * (int64_t)kLMRing * N, R},
         {I.BJ(), 8 * (int64_t)kLMRing * N, R}, {I.RS(), 8 * (int64_t)kLMRing * N * 16, 16 * R},
         {I.LS(), 8 * (int64_t)kLMRing * N * 16, 16 * R}};
-    bool ok = (int64_t)L.fwd_off.size() == 4 * N + 1 && (int64_t)L.bwd_off.size() == 4 * N + 1 &&
+    bool ok = (int64_t)L.inmask.size() == N && (int64_t)L.fwd_off.size() == 4 * N + 1 && (int64_t)L.bwd_off.size() == 4 * N + 1 &&
               (int64_t)L.hpB.size() == 16 * N && (int64_t)L.OB.size() == 72 * N && (int64_t)L.OA.size() == 72 * N;
     for (const Ext& e : ea) ok = ok && e.bytes <= e.slot;
     if (!ok) {
@@ -291,6 +292,7 @@ void stage_inputs(const Lattice& L, const Inst& I, const char* devA, char* image
     put(I.in_lab(), L.in_lab.data(), L.in_lab.size() * 4);
     put(I.in_U(), L.in_U.data(), L.in_U.size() * 8);
     put(I.tail(), L.tail.data(), L.tail.size() * 8);
+    put(I.inmask(), L.inmask.data(), L.inmask.size() * 4);
     put(I.pfx(), L.pfx.data(), L.pfx.size() * 4);
     put(I.P(), L.P.data(), L.P.size() * 8);
     put(I.hp_init(), L.hp_init.data(), L.hp_init.size() * 4);

@@ -50,7 +50,7 @@ constexpr int kSpecOff5 = 0, kSpecOff6 = 1024, kSpecOff8 = 1024 + 4096, kSpecSiz
 //   7 rowoff[N]  8 coff[N]  9 ccap[N]  10 ccnt[N]  11 X[N]  12-13 out_dst[4N]  14-17 out_U[4N]
 //   18-21 alphaU[4N]  22-25 betaU[4N]  26-28 fwd_off[4N+1]  29-31 bwd_off[4N+1]
 //   32-47 hpB[16N]  48-119 OB[72N]  120-191 OA[72N]  192 stats[4]  193 visits[n+1]
-//   194 feasible[n+1]  195.. in_src[nE], in_lab[nE], in_U[nE], fwd_meta[nF], fwd_cost[nF], bwd_meta[nB],
+//   194 feasible[n+1]  195 inmask[N]  196.. in_src[nE], in_lab[nE], in_U[nE], fwd_meta[nF], fwd_cost[nF], bwd_meta[nB],
 //         bwd_cost[nB] (each start 8-byte aligned)
 // Region B (DP tables) is cut into ring units of R = 512 * N bytes (N states x 64 spans x 8 B):
 //   0-1 LM  2-13 IDL  14-25 JDL  26 BI  27 BJ  28-43 RS  44-59 LS, then from 60 R:
@@ -58,7 +58,8 @@ constexpr int kSpecOff5 = 0, kSpecOff6 = 1024, kSpecOff8 = 1024 + 4096, kSpecSiz
 // Meaning of the arrays:
 //   layer/off: layer of a state, first state of a layer; out_dst/out_U: out-edge by label
 //   (-1 / cost); in_start/in_src/in_lab/in_U: in-edges (CSR, sorted by source and label);
-//   tail: cheapest completion of the current codon from a state; pfx: 2-base prefix code of a
+//   inmask: bit y set if the state has an in-edge labelled y; tail: cheapest completion of the
+//   current codon from a state; pfx: 2-base prefix code of a
 //   phase-2 state (4x+y), base x of phase 1; P: prefix sums of per-codon minimum cost;
 //   hp_init: hairpin initiation per size (extrapolated above 30); rowoff: cell row offsets,
 //   cell(a,b) = rowoff[a] + b - off[layer(a)+1]; V/Bt/S1/S2: typed closed values, branch value,
@@ -116,10 +117,11 @@ struct Inst {
     __host__ __device__ unsigned long long* stats() const { return (unsigned long long*)ua(192); }
     __host__ __device__ unsigned long long* visits() const { return (unsigned long long*)ua(193); }
     __host__ __device__ unsigned long long* feasible() const { return (unsigned long long*)ua(194); }
-    __host__ __device__ const int* in_src() const { return (const int*)ua(195); }
-    __host__ __device__ const int* in_lab() const { return (const int*)(ua(195) + al8(4 * nE)); }
-    __host__ __device__ const int64_t* in_U() const { return (const int64_t*)(ua(195) + 2 * al8(4 * nE)); }
-    __host__ __device__ char* paths() const { return ua(195) + 2 * al8(4 * nE) + 8 * nE; }
+    __host__ __device__ const int* inmask() const { return (const int*)ua(195); }
+    __host__ __device__ const int* in_src() const { return (const int*)ua(196); }
+    __host__ __device__ const int* in_lab() const { return (const int*)(ua(196) + al8(4 * nE)); }
+    __host__ __device__ const int64_t* in_U() const { return (const int64_t*)(ua(196) + 2 * al8(4 * nE)); }
+    __host__ __device__ char* paths() const { return ua(196) + 2 * al8(4 * nE) + 8 * nE; }
     __host__ __device__ const int* fwd_meta() const { return (const int*)paths(); }
     __host__ __device__ const int64_t* fwd_cost() const { return (const int64_t*)(paths() + al8(4 * nF)); }
     __host__ __device__ const int* bwd_meta() const { return (const int*)(paths() + al8(4 * nF) + 8 * nF); }

@@ -626,7 +626,8 @@ __device__ GroupCounters span_group(const IT& I, const SmallE& S, const EnergyTa
             G.red[wave][1] = mini1;
         }
     }
-    // (cell, type) jobs whose type's first label leaves a; typed values cleared
+    // (cell, type) jobs: the type's first label leaves a and its last label enters b (any other
+    // type is infeasible for the cell); typed values cleared
     if (wave == 0) {
         int base = 0;
         for (int k0 = 0; k0 < ncell * 6; k0 += 64) {
@@ -635,7 +636,8 @@ __device__ GroupCounters span_group(const IT& I, const SmallE& S, const EnergyTa
             if (k < ncell * 6) {
                 const int ci = k / 6, t = k - 6 * ci;
                 G.vbuf[ci][t] = kINF;
-                job = g >= 5 && I.out_dst()[(a_lo + ci / wb) * 4 + kTX[t]] >= 0;
+                job = g >= 5 && I.out_dst()[(a_lo + ci / wb) * 4 + kTX[t]] >= 0 &&
+                      ((I.inmask()[b_lo + ci % wb] >> kTY[t]) & 1);
             }
             const unsigned long long m = __ballot(job);
             if (job) G.combo[base + __popcll(m & ((1ull << lane) - 1ull))] = k;

@@ -397,6 +397,9 @@ int build_lattice(const char* protein, const CodonTable& T, const Params& P, dou
     for (int v = 0; v < N; v++)
         for (int j = L.in_start[v]; j < L.in_start[v + 1]; j++)
             L.betaU[4 * v + L.in_lab[j]] = std::min(L.betaU[4 * v + L.in_lab[j]], L.in_U[j]);
+    L.inmask.assign(N, 0);
+    for (int v = 0; v < N; v++)
+        for (int j = L.in_start[v]; j < L.in_start[v + 1]; j++) L.inmask[v] |= 1 << L.in_lab[j];
     // hairpin closing side: min over b2 -z-> b1 -y-> b of the two edge costs
     L.hpB.assign((size_t)16 * N, kINF);
     for (int v = 0; v < N; v++)

@@ -41,6 +41,7 @@ struct Lattice {
     std::vector<int64_t> hpB;  // [N*16] hairpin closing-side minima (see sd_internal.h)
     std::vector<int64_t> OB, OA;  // [N*72] one-sided loop outer minima, [state][t][X][label]
     std::vector<int> pfx, hp_init;
+    std::vector<int> inmask;  // [N] bit y: the state has an in-edge labelled y
     std::vector<int64_t> rowoff, coff;
     std::vector<int> ccap;
     int64_t cells = 0, cand_slots = 0;
