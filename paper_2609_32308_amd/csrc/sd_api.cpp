@@ -262,7 +262,7 @@ InstLayout layout_instance(const Lattice& L, char* A, char* B, Inst& I) {
         {I.LM(), 8 * (int64_t)kLMRing * (n + 1) * 2, 2 * R}, {I.IDL(), 8 * (int64_t)kLMRing * N * 12, 12 * R},
         {I.JDL(), 8 * (int64_t)kLMRing * N * 12, 12 * R}, {I.BI(), 8 * (int64_t)kLMRing * N, R},
         {I.BJ(), 8 * (int64_t)kLMRing * N, R}, {I.RS(), 8 * (int64_t)kLMRing * N * 16, 16 * R},
-        {I.LS(), 8 * (int64_t)kLMRing * N * 16, 16 * R}};
+        {I.LS(), 8 * (int64_t)kLMRing * N * 16, 16 * R}, {I.MINI(), 8 * (int64_t)kLMRing * (n + 1) * 2, 2 * R}};
     bool ok = (int64_t)L.inmask.size() == N && (int64_t)L.fwd_off.size() == 4 * N + 1 && (int64_t)L.bwd_off.size() == 4 * N + 1 &&
               (int64_t)L.hpB.size() == 16 * N && (int64_t)L.OB.size() == 72 * N && (int64_t)L.OA.size() == 72 * N;
     for (const Ext& e : ea) ok = ok && e.bytes <= e.slot;

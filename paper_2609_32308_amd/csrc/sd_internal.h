@@ -53,7 +53,7 @@ constexpr int kSpecOff5 = 0, kSpecOff6 = 1024, kSpecOff8 = 1024 + 4096, kSpecSiz
 //   194 feasible[n+1]  195 inmask[N]  196.. in_src[nE], in_lab[nE], in_U[nE], fwd_meta[nF], fwd_cost[nF], bwd_meta[nB],
 //         bwd_cost[nB] (each start 8-byte aligned)
 // Region B (DP tables) is cut into ring units of R = 512 * N bytes (N states x 64 spans x 8 B):
-//   0-1 LM  2-13 IDL  14-25 JDL  26 BI  27 BJ  28-43 RS  44-59 LS, then from 60 R:
+//   0-1 LM  2-13 IDL  14-25 JDL  26 BI  27 BJ  28-43 RS  44-59 LS  60-61 MINI, then from 62 R:
 //   V[cells][6], Bt[cells], S1[cells], S2[cells], cc[slots], cB[slots].
 // Meaning of the arrays:
 //   layer/off: layer of a state, first state of a layer; out_dst/out_U: out-edge by label
@@ -70,6 +70,8 @@ constexpr int kSpecOff5 = 0, kSpecOff6 = 1024, kSpecOff8 = 1024 + 4096, kSpecSiz
 //   and step, so the counters see no contention).
 //   alphaU[d*4+x] = U(d -x-> d2) + tail(d2); betaU[c*4+x] = min U over in-edges of c labelled x.
 //   LM[layer][class 2][span]: layer-pair minima of the both-separable interior form.
+//   MINI[layer p][span][class 2]: both-separable interior minimum of layer pair (p, p + span),
+//   prepared one step ahead.
 //   IDL/JDL[state][class 3][label 4][span]: inner minima per left / right inner state.
 //   fwd_*/bwd_*: label paths of 1..4 edges out of / into a state (CSR by state*4+l-1);
 //   meta = other_end << 4 | first_label << 2 | last_label, cost = sum of edge costs.
@@ -137,13 +139,14 @@ struct Inst {
     __host__ __device__ int64_t* BJ() const { return (int64_t*)ub(27); }
     __host__ __device__ int64_t* RS() const { return (int64_t*)ub(28); }
     __host__ __device__ int64_t* LS() const { return (int64_t*)ub(44); }
-    __host__ __device__ int64_t* V() const { return (int64_t*)ub(60); }
-    __host__ __device__ int64_t* Bt() const { return (int64_t*)(ub(60) + 48 * cells); }
-    __host__ __device__ int64_t* S1() const { return (int64_t*)(ub(60) + 56 * cells); }
-    __host__ __device__ int64_t* S2() const { return (int64_t*)(ub(60) + 64 * cells); }
-    __host__ __device__ int* cc() const { return (int*)(ub(60) + 72 * cells); }
-    __host__ __device__ int64_t* cB() const { return (int64_t*)(ub(60) + 72 * cells + al8(4 * slots)); }
-    __host__ __device__ int64_t b_bytes() const { return 60 * R() + 72 * cells + al8(4 * slots) + 8 * slots; }
+    __host__ __device__ int64_t* MINI() const { return (int64_t*)ub(60); }
+    __host__ __device__ int64_t* V() const { return (int64_t*)ub(62); }
+    __host__ __device__ int64_t* Bt() const { return (int64_t*)(ub(62) + 48 * cells); }
+    __host__ __device__ int64_t* S1() const { return (int64_t*)(ub(62) + 56 * cells); }
+    __host__ __device__ int64_t* S2() const { return (int64_t*)(ub(62) + 64 * cells); }
+    __host__ __device__ int* cc() const { return (int*)(ub(62) + 72 * cells); }
+    __host__ __device__ int64_t* cB() const { return (int64_t*)(ub(62) + 72 * cells + al8(4 * slots)); }
+    __host__ __device__ int64_t b_bytes() const { return 62 * R() + 72 * cells + al8(4 * slots) + 8 * slots; }
 };
 
 constexpr int kLMRing = 64;

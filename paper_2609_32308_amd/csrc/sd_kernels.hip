@@ -315,6 +315,10 @@ __device__ __forceinline__ int64_t ring_idx(int state, int span, int X, int lab)
 __device__ __forceinline__ int64_t lm_idx(int layer, int span, int X) {
     return ((int64_t)layer * 2 + X) * kLMRing + (span & (kLMRing - 1));
 }
+// ring of prepared both-separable minima [layer p][span mod 64][class]
+__device__ __forceinline__ int64_t mini_idx(int p, int span, int X) {
+    return ((int64_t)p * kLMRing + (span & (kLMRing - 1))) * 2 + X;
+}
 template <class IT>
 __device__ __forceinline__ int64_t PLt(const IT& I, int p, int l1) { return I.P()[(p + l1) / 3] - I.P()[(p + 2) / 3 + 1]; }
 template <class IT>
@@ -422,6 +426,7 @@ struct GroupShared {
     int combo[kMaxWidth * kMaxWidth * 6];     // (cell, type) jobs with an out-edge of label x
     int ncombo;
     int64_t red[NW][2];
+    int64_t red2[NW][2];
     LabPair lab[NW][16];
 };
 
@@ -606,25 +611,11 @@ __device__ GroupCounters span_group(const IT& I, const SmallE& S, const EnergyTa
     GroupCounters ctr{0, 0, 0};
     const int a_lo = I.off()[p], a_hi = I.off()[p + 1], b_lo = I.off()[q], b_hi = I.off()[q + 1];
     const int wa = a_hi - a_lo, wb = b_hi - b_lo, ncell = wa * wb;
-    // separable interior minima of this layer pair (both segments separable), per class
+    // both-separable interior minima of this layer pair, per class (prepared one step ahead)
     int64_t mini0 = kINF, mini1 = kINF;
     if (g >= 12) {
-        const int ph = (p % 3) * 3 + (q % 3), cap = min(g - 7, kMaxLoop);
-        for (int k = tid; k < kPairCnt[kListFast][ph][cap]; k += blockDim.x) {
-            const int code = kPairList[kListFast][ph][k], l1 = code & 31, l2 = (code >> 5) & 31;
-            const int cl = p + 1 + l1, dl = q - 1 - l2, X = pair_class(l1, l2);
-            const int64_t lm = I.LM()[lm_idx(cl, dl - cl, X)];
-            if (lm >= kINF) continue;
-            const int64_t v = lm + fx(interior_base(S, l1, l2), s) + PLt(I, p, l1) + PRt(I, q, l2);
-            if (X) mini1 = mn(mini1, v);
-            else mini0 = mn(mini0, v);
-        }
-        mini0 = wave_min(mini0);
-        mini1 = wave_min(mini1);
-        if (lane == 0) {
-            G.red[wave][0] = mini0;
-            G.red[wave][1] = mini1;
-        }
+        mini0 = I.MINI()[mini_idx(p, g, 0)];
+        mini1 = I.MINI()[mini_idx(p, g, 1)];
     }
     // (cell, type) jobs: the type's first label leaves a and its last label enters b (any other
     // type is infeasible for the cell); typed values cleared
@@ -646,13 +637,6 @@ __device__ GroupCounters span_group(const IT& I, const SmallE& S, const EnergyTa
         if (lane == 0) G.ncombo = base;
     }
     __syncthreads();
-    if (g >= 12) {
-        mini0 = mini1 = kINF;
-        for (int w = 0; w < nw; w++) {
-            mini0 = mn(mini0, G.red[w][0]);
-            mini1 = mn(mini1, G.red[w][1]);
-        }
-    }
     // phase 1: typed closed values; the two parts of every (cell, type) job on separate waves
     const int njobs = 2 * G.ncombo;
     for (int k = wave; k < njobs; k += nw) {
@@ -758,6 +742,40 @@ __device__ GroupCounters span_group(const IT& I, const SmallE& S, const EnergyTa
         added += __shfl_xor(added, 1, 64);
         added += __shfl_xor(added, 2, 64);
         ctr.appends += (unsigned long long)added;
+    }
+    // both-separable minima of the next span's pair (p, q + 1), by the waves other than wave 0
+    // (busy with the appends): they read LM of spans <= g - 7, complete before this step
+    if (g + 1 >= 12 && q + 1 <= I.n) {
+        const int w0 = nw > 1 ? 1 : 0;
+        if (wave >= w0) {
+            int64_t m0 = kINF, m1 = kINF;
+            const int qn = q + 1, ph = (p % 3) * 3 + (qn % 3), cap = min(g + 1 - 7, kMaxLoop);
+            for (int k = tid - 64 * w0; k < kPairCnt[kListFast][ph][cap]; k += blockDim.x - 64 * w0) {
+                const int code = kPairList[kListFast][ph][k], l1 = code & 31, l2 = (code >> 5) & 31;
+                const int cl = p + 1 + l1, dl = qn - 1 - l2, X = pair_class(l1, l2);
+                const int64_t lm = I.LM()[lm_idx(cl, dl - cl, X)];
+                if (lm >= kINF) continue;
+                const int64_t v = lm + fx(interior_base(S, l1, l2), s) + PLt(I, p, l1) + PRt(I, qn, l2);
+                if (X) m1 = mn(m1, v);
+                else m0 = mn(m0, v);
+            }
+            m0 = wave_min(m0);
+            m1 = wave_min(m1);
+            if (lane == 0) {
+                G.red2[wave][0] = m0;
+                G.red2[wave][1] = m1;
+            }
+        }
+        __syncthreads();
+        if (tid == 64 * w0) {
+            int64_t r0 = kINF, r1 = kINF;
+            for (int w = w0; w < nw; w++) {
+                r0 = mn(r0, G.red2[w][0]);
+                r1 = mn(r1, G.red2[w][1]);
+            }
+            I.MINI()[mini_idx(p, g + 1, 0)] = norm_inf(r0);
+            I.MINI()[mini_idx(p, g + 1, 1)] = norm_inf(r1);
+        }
     }
     return ctr;
 }
