@@ -113,13 +113,24 @@ void sd_codon_table_free(sd_codon_table *t);
 sd_status sd_context_create(int device, const sd_options *opt, sd_context **out);
 void sd_context_destroy(sd_context *ctx);
 
-/* One design, plain mode: one span-step kernel launch per span length (Algorithm 1 order),
- * canonical traceback on the device.  On success *out owns two strings. */
+/* One design, plain mode (Sec. 4.1 recurrences in the span order of Sec. 5, Algorithm 1): the
+ * automaton of `protein` (NUL-terminated one-letter string, optional final '*') is built on the
+ * host and uploaded, the forward fill runs as one span-step kernel launch per span length on
+ * the context's stream, the tables are copied back and the canonical first-match traceback runs
+ * on the host (deferred traceback, Sec. 5) with an exact self-check.  lambda_kcal >= 0 weights
+ * the codon cost (eq. 1).  On success *out is filled and owns two strings (sd_result_free); on
+ * error *out is untouched: SD_E_PROTEIN / SD_E_CODON_TABLE / SD_E_LAMBDA / SD_E_RANGE for bad
+ * inputs (no kernel launched), SD_E_NOMEM / SD_E_DEVICE for allocation or HIP failures,
+ * SD_E_INTERNAL if the self-check fails. */
 sd_status sd_design(sd_context *ctx, const char *protein, const sd_codon_table *table,
                     const sd_params *params, double lambda_kcal, sd_result *out);
 
-/* n designs in one persistent launch (all instances advance one span per grid barrier).
- * proteins[i] with lambdas[i]; outs[i] receives each result.  On error no output owns memory. */
+/* n designs in one persistent, graph-captured launch (all instances advance one span per grid
+ * barrier; the schedule is autotuned on a sample of the batch or fixed by sd_options).
+ * proteins[i] (as for sd_design) with lambdas[i]; outs[i] (array of n) receives each result,
+ * identical to sd_design's.  Members whose learned reservation overflows, or a launch whose
+ * barrier gives up, are recomputed exactly in plain mode.  On error no output owns memory and
+ * the status names the first invalid member (SD_E_PROTEIN, ...) or the failure. */
 sd_status sd_design_batch(sd_context *ctx, int n, const char *const *proteins,
                           const double *lambdas, const sd_codon_table *table,
                           const sd_params *params, sd_result *outs);
