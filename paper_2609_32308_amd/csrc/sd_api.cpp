@@ -180,6 +180,7 @@ extern "C" void sd_context_destroy(sd_context* c) {
     if (c->stream) hipStreamSynchronize(c->stream);
     if (c->arena) hipFree(c->arena);
     if (c->staging) hipHostFree(c->staging);
+    if (c->tbuf) hipHostFree(c->tbuf);
     if (c->E_dev) hipFree(c->E_dev);
     if (c->spec_dev) hipFree(c->spec_dev);
     if (c->ev0) hipEventDestroy(c->ev0);
@@ -404,25 +405,58 @@ sd_status design_plain(sd_context* c, const char* protein, const sd_codon_table*
                        const sd_params* params, double lambda, sd_result* out, TraceTables* keep,
                        Lattice* keepL);
 
-sd_status fetch_tables(sd_context* c, const Lattice& L, const Inst& I, TraceTables& T) {
+// Download the tables the traceback reads.  By default into the context's pinned buffer (grown
+// on demand, no host zeroing, DMA at full link speed; valid until the next download on this
+// context); with own_storage into host memory owned by T (for results traced back later).
+sd_status fetch_tables(sd_context* c, const Lattice& L, const Inst& I, TraceTables& T, bool own_storage) {
     hipStream_t st = c->stream;
-    T.V.resize(L.cells * 6);
-    T.B.resize(L.cells);
-    T.S1.resize(L.cells);
-    T.S2.resize(L.cells);
-    T.X.resize(L.N);
-    T.ccnt.resize(L.N);
-    T.cc.resize(L.cand_slots);
-    hipError_t e = hipMemcpyAsync(T.V.data(), I.V(), L.cells * 48, hipMemcpyDeviceToHost, st);
-    if (e == hipSuccess) e = hipMemcpyAsync(T.B.data(), I.Bt(), L.cells * 8, hipMemcpyDeviceToHost, st);
-    if (e == hipSuccess) e = hipMemcpyAsync(T.S1.data(), I.S1(), L.cells * 8, hipMemcpyDeviceToHost, st);
-    if (e == hipSuccess) e = hipMemcpyAsync(T.S2.data(), I.S2(), L.cells * 8, hipMemcpyDeviceToHost, st);
-    if (e == hipSuccess) e = hipMemcpyAsync(T.X.data(), I.X(), L.N * 8, hipMemcpyDeviceToHost, st);
-    if (e == hipSuccess) e = hipMemcpyAsync(T.ccnt.data(), I.ccnt(), L.N * 4, hipMemcpyDeviceToHost, st);
-    if (e == hipSuccess && L.cand_slots)
-        e = hipMemcpyAsync(T.cc.data(), I.cc(), L.cand_slots * 4, hipMemcpyDeviceToHost, st);
+    const size_t cells = (size_t)L.cells, N = (size_t)L.N, slots = (size_t)L.cand_slots;
+    const size_t bytes = cells * 72 + N * 8 + ((N * 4 + 7) & ~(size_t)7) + slots * 4;
+    char* base;
+    if (own_storage) {
+        T.own.reset(new (std::nothrow) char[bytes]);
+        if (!T.own) return fail(SD_E_NOMEM, "host table buffer");
+        base = T.own.get();
+    } else {
+        if (bytes > c->tbuf_bytes) {
+            hipError_t e = hipStreamSynchronize(st);
+            if (e == hipSuccess && c->tbuf) e = hipHostFree(c->tbuf);
+            c->tbuf = nullptr;
+            c->tbuf_bytes = 0;
+            const size_t want = bytes + bytes / 4;
+            if (e == hipSuccess) e = hipHostMalloc((void**)&c->tbuf, want, hipHostMallocDefault);
+            if (e != hipSuccess) {
+                c->tbuf = nullptr;
+                return hip_fail(e, "pinned table buffer");
+            }
+            c->tbuf_bytes = want;
+        }
+        base = c->tbuf;
+        T.own.reset();
+    }
+    int64_t* V = (int64_t*)base;
+    int64_t* B = V + cells * 6;
+    int64_t* S1 = B + cells;
+    int64_t* S2 = S1 + cells;
+    int64_t* X = S2 + cells;
+    int* ccnt = (int*)(X + N);
+    int* cc = (int*)((char*)ccnt + ((N * 4 + 7) & ~(size_t)7));
+    hipError_t e = hipMemcpyAsync(V, I.V(), cells * 48, hipMemcpyDeviceToHost, st);
+    if (e == hipSuccess) e = hipMemcpyAsync(B, I.Bt(), cells * 8, hipMemcpyDeviceToHost, st);
+    if (e == hipSuccess) e = hipMemcpyAsync(S1, I.S1(), cells * 8, hipMemcpyDeviceToHost, st);
+    if (e == hipSuccess) e = hipMemcpyAsync(S2, I.S2(), cells * 8, hipMemcpyDeviceToHost, st);
+    if (e == hipSuccess) e = hipMemcpyAsync(X, I.X(), N * 8, hipMemcpyDeviceToHost, st);
+    if (e == hipSuccess) e = hipMemcpyAsync(ccnt, I.ccnt(), N * 4, hipMemcpyDeviceToHost, st);
+    if (e == hipSuccess && slots) e = hipMemcpyAsync(cc, I.cc(), slots * 4, hipMemcpyDeviceToHost, st);
     if (e == hipSuccess) e = hipStreamSynchronize(st);
     if (e != hipSuccess) return hip_fail(e, "table download");
+    T.V = V;
+    T.B = B;
+    T.S1 = S1;
+    T.S2 = S2;
+    T.X = X;
+    T.ccnt = ccnt;
+    T.cc = cc;
     return SD_OK;
 }
 
@@ -603,7 +637,7 @@ extern "C" sd_status sd_design_tables(sd_context* ctx, const char* protein, cons
         sd_status s = design_plain(ctx, protein, table, params, lambda_kcal, out, &T, &L);
         if (s) return s;
         const size_t N = L.N;
-        auto dense = [&](int64_t* dst, const std::vector<int64_t>& src, int stride, int t) {
+        auto dense = [&](int64_t* dst, const int64_t* src, int stride, int t) {
             if (!dst) return;
             for (size_t a = 0; a < N; a++)
                 for (size_t b = 0; b < N; b++) {
@@ -616,7 +650,7 @@ extern "C" sd_status sd_design_tables(sd_context* ctx, const char* protein, cons
         dense(B, T.B, 1, 0);
         dense(S1, T.S1, 1, 0);
         dense(S2, T.S2, 1, 0);
-        if (X) memcpy(X, T.X.data(), N * 8);
+        if (X) memcpy(X, T.X, N * 8);
         return SD_OK;
     } catch (const std::bad_alloc&) {
         return fail(SD_E_NOMEM, "host allocation");

@@ -22,6 +22,8 @@ struct sd_context {
     int batch_grid = 0;       // autotuned persistent grid size (0: not tuned yet)
     int batch_threads = 256;  // autotuned threads per block of the persistent launch
     std::map<int, std::pair<int, int>> sched;  // size class -> (grid, threads) from the tuner
+    char* tbuf = nullptr;  // pinned download buffer of the traceback tables
+    size_t tbuf_bytes = 0;
     bool last_graph = false;  // last batch ran as a captured graph
     double last_batch_kernel_s = 0.0, last_batch_fill_s = 0.0;
     int64_t last_batch_fallbacks = 0;

@@ -330,7 +330,7 @@ sd_status round_once(sd_server* S) {
             continue;
         }
         sd_server::Job job;
-        sd_status s = fetch_tables(S->ctx, a.L, a.I, job.T);
+        sd_status s = fetch_tables(S->ctx, a.L, a.I, job.T, true);
         S->pool.release(a.off, a.bytes);
         if (s) return s;
         job.visits = (int64_t)stats[0];

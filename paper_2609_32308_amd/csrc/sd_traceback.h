@@ -3,6 +3,7 @@
 #include <stdint.h>
 
 #include <algorithm>
+#include <memory>
 #include <string>
 #include <vector>
 
@@ -10,9 +11,13 @@
 
 namespace sd {
 
+// Views of the downloaded tables (row layout, V: 6 per cell; candidate segments with cc < 0
+// for non-strict entries).  The memory is either the context's pinned download buffer (valid
+// until the context's next download) or owned by `own`.
 struct TraceTables {
-    std::vector<int64_t> V, B, S1, S2, X;  // row layout (V: 6 per cell)
-    std::vector<int> ccnt, cc;              // candidate segments (cc < 0: non-strict entry)
+    const int64_t *V = nullptr, *B = nullptr, *S1 = nullptr, *S2 = nullptr, *X = nullptr;
+    const int *ccnt = nullptr, *cc = nullptr;
+    std::unique_ptr<char[]> own;
 };
 
 struct TraceResult {
