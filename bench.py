@@ -277,6 +277,9 @@ def main():
     ap.add_argument("--warmup", type=int, default=1)
     ap.add_argument("--workload", default="config2", choices=["config2", "config3", "batch", "served"])
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--retain-all", action="store_true",
+                    help="plain workloads: also time the scalar-dense control (every finite direct "
+                         "interval retained) and report its time and visit ratios to the sparse fill")
     ap.add_argument("--requests", type=int, default=100, help="served: number of requests")
     ap.add_argument("--train-proteins", type=int, default=120, help="served: proteins in the occupancy log")
     ap.add_argument("--pool-gib", type=int, default=8, help="served: device pool of the server")
@@ -343,6 +346,20 @@ def main():
         "params_sha256": params.sha256,
     }
     ctx.close()
+    if args.retain_all and not batch:
+        # scalar-dense control (Sec. 8.1 / Table 3): same designs, every finite B retained
+        dctx = sd.Context(0, retain_all=True)
+        run_step(dctx, items, table, params, False)
+        dense = run_step(dctx, items, table, params, False)
+        dctx.close()
+        sparse = results[-1]
+        fs, fd = sum(r.t_fill_s for r in sparse), sum(r.t_fill_s for r in dense)
+        vs, vd = sum(r.n_visits for r in sparse), sum(r.n_visits for r in dense)
+        assert all((a.mrna, a.structure, a.objective_fixed) == (b.mrna, b.structure, b.objective_fixed)
+                   for a, b in zip(sparse, dense))
+        line["scalar_dense_control"] = {"fill_s_sparse": fs, "fill_s_dense": fd, "time_ratio": fd / fs,
+                                        "visits_sparse": vs, "visits_dense": vd, "visit_ratio": vd / max(vs, 1),
+                                        "identical_designs": True}
     if not args.no_cpu_baseline:
         line["cpu_baseline"] = cpu_baseline(items)
     print(json.dumps(line), flush=True)

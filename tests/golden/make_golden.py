@@ -4,7 +4,10 @@ Calls only oracle/ and sdinputs/ (the seeded generators); nothing here touches t
 The GPU parity tests compare against these files at sizes where running the dense oracle
 inside a test would take minutes.
 
-    python tests/golden/make_golden.py config2 config3 [config4]
+    python tests/golden/make_golden.py config2 config3 [config4] [stress]
+
+The stress families of Sec. 9.2 (poly-S and alternating YI, no Met and no stop) are keyed by
+seed 0 (S) and seed -1 (YI).
 """
 import json
 import os
@@ -30,6 +33,13 @@ def batch_members():
     return [(A, 7000 + i, 0.0 if i < 128 else 4.0) for i, A in enumerate(lens)]
 
 
+def stress_protein(A, seed):
+    return "S" * A if seed == 0 else "YI" * (A // 2)
+
+
+STRESS = [(256, fam, lam) for fam in (0, -1) for lam in (0.0, 4.0)]
+
+
 def run(name, members, nthreads):
     params = S.default_params_path()
     P = O.Params(params)
@@ -45,7 +55,7 @@ def run(name, members, nthreads):
     for (A, seed, lam) in members:
         if (A, seed, lam) in done:
             continue
-        prot = S.protein(A, seed)
+        prot = stress_protein(A, seed) if name == "stress" else S.protein(A, seed)
         t = time.time()
         d = O.design(prot, w, P, lam, nthreads=nthreads)
         dt = time.time() - t
@@ -68,5 +78,5 @@ def run(name, members, nthreads):
 if __name__ == "__main__":
     nthreads = int(os.environ.get("ORACLE_THREADS", "8"))
     for name in sys.argv[1:]:
-        members = batch_members() if name == "config4" else WORKLOADS[name]
+        members = batch_members() if name == "config4" else STRESS if name == "stress" else WORKLOADS[name]
         run(name, members, nthreads)
