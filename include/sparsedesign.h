@@ -135,6 +135,21 @@ sd_status sd_design_batch(sd_context *ctx, int n, const char *const *proteins,
                           const double *lambdas, const sd_codon_table *table,
                           const sd_params *params, sd_result *outs);
 
+/* Supported lambda envelope of one protein on [lambda_lo, lambda_hi] (the supported-envelope /
+ * inverse-lambda tools of Sec. 10; eq. 1 is a lower envelope of lines E/100 + lambda * C).
+ * Exact dichotomic search: the designs optimal at the interval ends, then at every crossing of
+ * two consecutive supported lines the optimum is computed (all crossings of one level in one
+ * batched call) and kept if it lies strictly below both lines (relative tolerance 1e-9).
+ * On success outs[0..*n_out-1] (caller array of max_designs >= 2 entries) hold the supported
+ * designs in increasing lambda (decreasing codon cost), each owning its strings; design i is
+ * optimal for lambda in [breaks[i], breaks[i+1]] (breaks: caller array of max_designs + 1).
+ * If the search would exceed max_designs it stops with the designs found so far (then a
+ * breakpoint interval may hide further supported designs).  Errors as for sd_design_batch, plus
+ * SD_E_LAMBDA unless 0 <= lambda_lo < lambda_hi < inf. */
+sd_status sd_lambda_envelope(sd_context *ctx, const char *protein, double lambda_lo, double lambda_hi,
+                             int max_designs, const sd_codon_table *table, const sd_params *params,
+                             sd_result *outs, double *breaks, int *n_out);
+
 /* Test hook: the plain design plus its tables copied into caller buffers in a dense
  * state-pair layout [a*N + b] (V: [tau][a][b] with tau in AU,CG,GC,GU,UA,UG; entries with
  * rho(a) >= rho(b) are set to 2^62).  Any table pointer may be NULL.  N = out->n_states. */

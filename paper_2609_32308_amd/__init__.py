@@ -29,7 +29,7 @@ EXPORTS = [
     "sd_sizer_get_params", "sd_sizer_set_params", "sd_sizer_gradient", "sd_sizer_train",
     "sd_sizer_predict", "sd_sizer_features", "sd_context_set_sizer", "sd_occupancy",
     "sd_server_start", "sd_server_submit", "sd_server_poll", "sd_server_wait", "sd_server_get_stats",
-    "sd_server_stop",
+    "sd_server_stop", "sd_lambda_envelope",
 ]
 
 
@@ -111,6 +111,8 @@ def lib():
         L.sd_sizer_predict.argtypes = [vp, C.c_int, PF, PF]
         L.sd_sizer_features.argtypes = [C.c_char_p, C.c_double, PF]
         L.sd_context_set_sizer.argtypes = [vp, vp, C.c_float, C.c_int]
+        L.sd_lambda_envelope.argtypes = [vp, C.c_char_p, C.c_double, C.c_double, C.c_int, vp, vp,
+                                         C.POINTER(_Result), C.POINTER(C.c_double), C.POINTER(C.c_int)]
         L.sd_occupancy.argtypes = [vp, C.c_int, C.POINTER(C.c_char_p), C.POINTER(C.c_double), vp, vp,
                                    C.c_int, PF, C.POINTER(_Result)]
         L.sd_server_start.argtypes = [vp, vp, vp, C.POINTER(ServerCfg), C.POINTER(vp)]
@@ -229,6 +231,16 @@ class Context:
         res = (_Result * n)()
         _check(lib().sd_design_batch(self.h, n, arr, lam, table.h, params.h, res), "sd_design_batch")
         return [_convert(res[i]) for i in range(n)]
+
+    def lambda_envelope(self, protein: str, lo: float, hi: float, table: CodonTable, params: Params,
+                        max_designs: int = 64):
+        """Supported designs on [lo, hi] in increasing lambda and their breakpoints."""
+        res = (_Result * max_designs)()
+        br = (C.c_double * (max_designs + 1))()
+        n = C.c_int()
+        _check(lib().sd_lambda_envelope(self.h, protein.encode(), float(lo), float(hi), int(max_designs),
+                                        table.h, params.h, res, br, C.byref(n)), "sd_lambda_envelope")
+        return [_convert(res[i]) for i in range(n.value)], [br[i] for i in range(n.value + 1)]
 
     def set_sizer(self, sizer, margin: float = 0.5, slack: int = 8):
         _check(lib().sd_context_set_sizer(self.h, sizer.h if sizer else None, float(margin), int(slack)),

@@ -1,0 +1,52 @@
+"""Supported lambda envelope (eq. 1 is the lower envelope of the lines E/100 + lambda * C).
+
+The envelope returned by the library must be ordered (codon cost falling, energy rising, lambda
+breakpoints increasing), each supported design must be optimal inside its interval (checked
+against a plain GPU design at the interval midpoint), and at arbitrary lambda the envelope's
+minimum must equal the dense CPU oracle's optimum.
+"""
+import numpy as np
+import pytest
+
+import oracle as O
+import sdinputs as S
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def sd():
+    import paper_2609_32308_amd as m
+    return m
+
+
+def line(r, lam):
+    return r.energy / 100.0 + lam * r.codon_cost
+
+
+@pytest.mark.parametrize("A,seed", [(40, 3), (60, 5)])
+def test_envelope_supported_designs(sd, A, seed, params_path, weights, oparams):
+    ctx = sd.Context(0)
+    gp, gt = sd.Params(params_path), sd.CodonTable(weights)
+    p = S.protein(A, seed)
+    designs, breaks = ctx.lambda_envelope(p, 0.0, 8.0, gt, gp, max_designs=64)
+    print("envelope", A, seed, len(designs), [round(b, 4) for b in breaks], flush=True)
+    assert len(designs) >= 2 and len(breaks) == len(designs) + 1
+    assert breaks[0] == 0.0 and breaks[-1] == 8.0
+    for i in range(len(designs) - 1):
+        a, b = designs[i], designs[i + 1]
+        assert a.codon_cost > b.codon_cost and a.energy < b.energy
+        assert breaks[i] <= breaks[i + 1] <= breaks[i + 2]
+        # consecutive lines cross at the breakpoint
+        assert abs(line(a, breaks[i + 1]) - line(b, breaks[i + 1])) <= 1e-9 * (1 + abs(line(a, breaks[i + 1])))
+    for i, d in enumerate(designs):
+        assert O.evaluate(d.mrna, d.structure, oparams) == d.energy
+        mid = 0.5 * (breaks[i] + breaks[i + 1])
+        r = ctx.design(p, gt, gp, mid)
+        assert abs(r.objective_kcal - line(d, mid)) <= 1e-9 * (1 + abs(r.objective_kcal))
+    rng = np.random.default_rng(seed)
+    for lam in [0.0, 8.0] + list(rng.uniform(0.0, 8.0, 4)):
+        o = O.design(p, weights, oparams, float(lam), nthreads=8)
+        env = min(line(d, lam) for d in designs)
+        assert abs(env - o.objective_kcal) <= 1e-9 * (1 + abs(env))
+    ctx.close()
