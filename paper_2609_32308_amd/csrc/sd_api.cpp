@@ -264,7 +264,7 @@ InstLayout layout_instance(const Lattice& L, char* A, char* B, Inst& I) {
         {I.JDL(), 8 * (int64_t)kLMRing * N * 12, 12 * R}, {I.BI(), 8 * (int64_t)kLMRing * N, R},
         {I.BJ(), 8 * (int64_t)kLMRing * N, R}, {I.RS(), 8 * (int64_t)kLMRing * N * 16, 16 * R},
         {I.LS(), 8 * (int64_t)kLMRing * N * 16, 16 * R}, {I.MINI(), 8 * (int64_t)kLMRing * (n + 1) * 2, 2 * R}};
-    bool ok = (int64_t)L.inmask.size() == N && (int64_t)L.fwd_off.size() == 4 * N + 1 && (int64_t)L.bwd_off.size() == 4 * N + 1 &&
+    bool ok = L.fwd_crow.size() == L.fwd_meta.size() && (int64_t)L.inmask.size() == N && (int64_t)L.fwd_off.size() == 4 * N + 1 && (int64_t)L.bwd_off.size() == 4 * N + 1 &&
               (int64_t)L.hpB.size() == 16 * N && (int64_t)L.OB.size() == 72 * N && (int64_t)L.OA.size() == 72 * N;
     for (const Ext& e : ea) ok = ok && e.bytes <= e.slot;
     if (!ok) {
@@ -305,6 +305,7 @@ void stage_inputs(const Lattice& L, const Inst& I, const char* devA, char* image
     put(I.fwd_off(), L.fwd_off.data(), L.fwd_off.size() * 4);
     put(I.fwd_meta(), L.fwd_meta.data(), L.fwd_meta.size() * 4);
     put(I.fwd_cost(), L.fwd_cost.data(), L.fwd_cost.size() * 8);
+    put(I.fwd_crow(), L.fwd_crow.data(), L.fwd_crow.size() * 8);
     put(I.bwd_off(), L.bwd_off.data(), L.bwd_off.size() * 4);
     put(I.bwd_meta(), L.bwd_meta.data(), L.bwd_meta.size() * 4);
     put(I.bwd_cost(), L.bwd_cost.data(), L.bwd_cost.size() * 8);

@@ -51,7 +51,7 @@ constexpr int kSpecOff5 = 0, kSpecOff6 = 1024, kSpecOff8 = 1024 + 4096, kSpecSiz
 //   18-21 alphaU[4N]  22-25 betaU[4N]  26-28 fwd_off[4N+1]  29-31 bwd_off[4N+1]
 //   32-47 hpB[16N]  48-119 OB[72N]  120-191 OA[72N]  192 stats[4]  193 visits[n+1]
 //   194 feasible[n+1]  195 inmask[N]  196.. in_src[nE], in_lab[nE], in_U[nE], fwd_meta[nF], fwd_cost[nF], bwd_meta[nB],
-//         bwd_cost[nB] (each start 8-byte aligned)
+//         bwd_cost[nB], fwd_crow[nF] (each start 8-byte aligned)
 // Region B (DP tables) is cut into ring units of R = 512 * N bytes (N states x 64 spans x 8 B):
 //   0-1 LM  2-13 IDL  14-25 JDL  26 BI  27 BJ  28-43 RS  44-59 LS  60-61 MINI, then from 62 R:
 //   V[cells][6], Bt[cells], S1[cells], S2[cells], cc[slots], cB[slots].
@@ -74,7 +74,8 @@ constexpr int kSpecOff5 = 0, kSpecOff6 = 1024, kSpecOff8 = 1024 + 4096, kSpecSiz
 //   prepared one step ahead.
 //   IDL/JDL[state][class 3][label 4][span]: inner minima per left / right inner state.
 //   fwd_*/bwd_*: label paths of 1..4 edges out of / into a state (CSR by state*4+l-1);
-//   meta = other_end << 4 | first_label << 2 | last_label, cost = sum of edge costs.
+//   meta = other_end << 4 | first_label << 2 | last_label, cost = sum of edge costs; fwd_crow =
+//   the cell-row base of the path's end state c (cell(c, d) = fwd_crow + d).
 //   hpB[b*16 + y*4 + z] = min over b2 -z-> b1 -y-> b of U(b2->b1) + U(b1->b).
 //   OB/OA[state][t][X][label]: outer minima of one-sided interior loops.
 //   BI[c][span] = min over d, t' of V_t'(c,d) + tail(d) + AU(t');  BJ[d][span] likewise without
@@ -130,7 +131,12 @@ struct Inst {
     __host__ __device__ const int64_t* bwd_cost() const {
         return (const int64_t*)(paths() + al8(4 * nF) + 8 * nF + al8(4 * nB));
     }
-    __host__ __device__ int64_t a_bytes() const { return (int64_t)(paths() - ra) + al8(4 * nF) + 8 * nF + al8(4 * nB) + 8 * nB; }
+    __host__ __device__ const int64_t* fwd_crow() const {
+        return (const int64_t*)(paths() + al8(4 * nF) + 8 * nF + al8(4 * nB) + 8 * nB);
+    }
+    __host__ __device__ int64_t a_bytes() const {
+        return (int64_t)(paths() - ra) + al8(4 * nF) + 8 * nF + al8(4 * nB) + 8 * nB + 8 * nF;
+    }
 
     __host__ __device__ int64_t* LM() const { return (int64_t*)ub(0); }
     __host__ __device__ int64_t* IDL() const { return (int64_t*)ub(2); }
@@ -150,6 +156,7 @@ struct Inst {
 };
 
 constexpr int kLMRing = 64;
+constexpr int kMaxWidth = 4;  // states per layer (the lattice build rejects wider layers)
 constexpr int kMaxWaves = 16;  // waves per workgroup of the span-step kernels (1024 threads)
 static_assert(sizeof(Inst) % 8 == 0, "instance descriptors are copied as 8-byte words");
 

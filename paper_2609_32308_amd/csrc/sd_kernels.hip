@@ -206,26 +206,52 @@ __device__ int64_t hairpin_lane(const IT& I, const SmallE& S, const int32_t* __r
 
 // ---- two-loop closure: bulges and stacks ----------------------------------------------------------
 // No boundary bases enter a bulge or stack energy, so each unpaired side costs its minimum
-// (the gap) and the loop is evaluated per inner cell and inner type.
+// (the gap).  The explicit pairs (stack, bulges of 1 and 2) are flattened over the lanes as
+// (pair, inner left state, inner right state); each lane evaluates the six inner types.
 template <class IT>
-__device__ int64_t bulge_pair(const IT& I, const SmallE& S, int t, int a1, int b1, int64_t Uab,
-                              int l1, int l2, int cl, int dl) {
-    const int s = I.shift, l = l1 + l2;
+__device__ __forceinline__ int64_t gap_l(const IT& I, int a, int la, int b, int lb) {  // gap() with known layers
+    if (la == lb) return a == b ? 0 : kINF;
+    const int ka = la / 3, kb = lb / 3;
+    if (ka == kb) {
+        if (la % 3 == 0) return 0;
+        return (I.pfx()[b] >> 2) == I.pfx()[a] ? 0 : kINF;
+    }
+    return I.tail()[a] + I.P()[kb] - I.P()[ka + 1];
+}
+
+template <class IT>
+__device__ int64_t bulge_lanes(const IT& I, const SmallE& S, int t, int a1, int b1, int64_t Uab, int p,
+                               int q, int cap, int lane) {
+    const int s = I.shift;
     int64_t best = kINF;
-    for (int c = (l1 == 0 ? a1 : I.off()[cl]); c < (l1 == 0 ? a1 + 1 : I.off()[cl + 1]); c++) {
-        const int64_t gl = l1 == 0 ? 0 : gap(I, a1, c);
-        if (gl >= kINF) continue;
-        const int64_t crow = I.rowoff()[c] - I.off()[cl + 1];
-        for (int d = (l2 == 0 ? b1 : I.off()[dl]); d < (l2 == 0 ? b1 + 1 : I.off()[dl + 1]); d++) {
-            const int64_t gr = l2 == 0 ? 0 : gap(I, d, b1);
-            if (gr >= kINF) continue;
-            const int64_t* v = I.V() + (crow + d) * 6;
-            for (int tp = 0; tp < 6; tp++) {
-                const int64_t vin = v[tp];
-                if (vin >= kINF) continue;
-                const int32_t e2 = l == 0 ? S.stack[t][kRev[tp]] : bulge_e(S, t, kRev[tp], l);
-                best = mn(best, Uab + gl + vin + gr + fx(e2, s));
-            }
+    const int npairs = kPairCnt[kListBulge][0][cap];  // <= 5
+    for (int idx = lane; idx < npairs * kMaxWidth * kMaxWidth; idx += 64) {
+        const int k = idx / (kMaxWidth * kMaxWidth), ci = (idx / kMaxWidth) % kMaxWidth, di = idx % kMaxWidth;
+        const int code = kPairList[kListBulge][0][k], l1 = code & 31, l2 = (code >> 5) & 31;
+        const int cl = p + 1 + l1, dl = q - 1 - l2;
+        int c = a1, d = b1;
+        if (l1 == 0) {
+            if (ci) continue;
+        } else {
+            c = I.off()[cl] + ci;
+            if (c >= I.off()[cl + 1]) continue;
+        }
+        if (l2 == 0) {
+            if (di) continue;
+        } else {
+            d = I.off()[dl] + di;
+            if (d >= I.off()[dl + 1]) continue;
+        }
+        const int64_t gl = l1 == 0 ? 0 : gap_l(I, a1, p + 1, c, cl);
+        const int64_t gr = l2 == 0 ? 0 : gap_l(I, d, dl, b1, q - 1);
+        if (gl >= kINF || gr >= kINF) continue;
+        const int64_t* v = I.V() + (I.rowoff()[c] - I.off()[cl + 1] + d) * 6;
+        const int l = l1 + l2;
+#pragma unroll
+        for (int tp = 0; tp < 6; tp++) {
+            const int64_t vin = v[tp];
+            const int32_t e2 = l == 0 ? S.stack[t][kRev[tp]] : bulge_e(S, t, kRev[tp], l);
+            if (vin < kINF) best = mn(best, Uab + gl + vin + gr + fx(e2, s));
         }
     }
     return best;
@@ -279,7 +305,7 @@ __device__ int64_t labelled_pairs(const IT& I, const SmallE& S, const EnergyTabl
         const int c = fm >> 4, xi = (fm >> 2) & 3, xk = fm & 3;
         const int d = bm >> 4, xl = (bm >> 2) & 3, xj = bm & 3;
         const int64_t base = Uab + I.fwd_cost()[x.f0 + i] + I.bwd_cost()[x.r0 + j];
-        const int64_t* v = I.V() + (I.rowoff()[c] + (d - I.off()[I.layer()[c] + 1])) * 6;
+        const int64_t* v = I.V() + (I.fwd_crow()[x.f0 + i] + d) * 6;
         for (int tp = 0; tp < 6; tp++) {
             const int64_t vin = v[tp];
             if (vin >= kINF) continue;
@@ -416,7 +442,6 @@ struct GroupCounters {
     unsigned long long visits, appends, feasible;
 };
 
-constexpr int kMaxWidth = 4;  // states per layer supported by the per-group cell buffers
 
 template <int NW>  // waves per workgroup
 struct GroupShared {
@@ -452,10 +477,7 @@ __device__ int64_t closed_part(const IT& I, const SmallE& S, const EnergyTables*
                 if (I.in_lab()[eb] != y) continue;
                 const int b1 = I.in_src()[eb];
                 const int64_t Uab = Ua + I.in_U()[eb];
-                for (int k = lane; k < kPairCnt[kListBulge][0][cap]; k += 64) {
-                    const int code = kPairList[kListBulge][0][k], l1 = code & 31, l2 = (code >> 5) & 31;
-                    v = mn(v, bulge_pair(I, S, t, a1, b1, Uab, l1, l2, p + 1 + l1, q - 1 - l2));
-                }
+                v = mn(v, bulge_lanes(I, S, t, a1, b1, Uab, p, q, cap, lane));
                 // bulges of >= 3 bases: the unpaired side costs its gap (tail + whole codons)
                 for (int k = lane; k < kPairCnt[kListBulgeSep][0][cap]; k += 64) {
                     const int code = kPairList[kListBulgeSep][0][k], l1 = code & 31, l2 = (code >> 5) & 31;

@@ -492,6 +492,11 @@ int build_lattice(const char* protein, const CodonTable& T, const Params& P, dou
         acc += N - L.off[L.layer[a] + 1];
     }
     L.cells = acc;
+    L.fwd_crow.resize(L.fwd_meta.size());
+    for (size_t e = 0; e < L.fwd_meta.size(); e++) {
+        const int c = L.fwd_meta[e] >> 4;
+        L.fwd_crow[e] = L.rowoff[c] - L.off[L.layer[c] + 1];
+    }
     L.coff.assign(N, 0);
     L.ccap.assign(N, 0);
     acc = 0;

@@ -38,6 +38,7 @@ struct Lattice {
     std::vector<int64_t> alphaU, betaU;  // [N*4] separable segment ends (see sd_kernels.hip)
     std::vector<int> fwd_off, fwd_meta, bwd_off, bwd_meta;  // label paths of 1..4 edges
     std::vector<int64_t> fwd_cost, bwd_cost;
+    std::vector<int64_t> fwd_crow;  // per forward path: rowoff[end] - off[layer(end) + 1]
     std::vector<int64_t> hpB;  // [N*16] hairpin closing-side minima (see sd_internal.h)
     std::vector<int64_t> OB, OA;  // [N*72] one-sided loop outer minima, [state][t][X][label]
     std::vector<int> pfx, hp_init;
