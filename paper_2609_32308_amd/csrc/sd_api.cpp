@@ -143,16 +143,16 @@ extern "C" sd_status sd_context_create(int device, const sd_options* opt, sd_con
     c->device = device;
     c->num_cu = prop.multiProcessorCount;
     if (opt) c->opt = *opt;
-    if (c->opt.span_threads == 0) c->opt.span_threads = 256;
-    if (c->opt.span_threads != 64 && c->opt.span_threads != 256 && c->opt.span_threads != 512 &&
-        c->opt.span_threads != 1024) {
+    if (c->opt.span_threads != 0 && c->opt.span_threads != 64 && c->opt.span_threads != 256 &&
+        c->opt.span_threads != 512 && c->opt.span_threads != 1024) {
         delete c;
         return fail(SD_E_ARG, "span_threads must be 0, 64, 256, 512 or 1024");
     }
-    if ((c->opt.batch_threads != 0 && c->opt.batch_threads != 64 && c->opt.batch_threads != 256) ||
+    if ((c->opt.batch_threads != 0 && c->opt.batch_threads != 64 && c->opt.batch_threads != 256 &&
+         c->opt.batch_threads != 512) ||
         (c->opt.batch_threads != 0) != (c->opt.batch_per_cu > 0) || c->opt.batch_per_cu < 0) {
         delete c;
-        return fail(SD_E_ARG, "batch_threads must be 0, 64 or 256, with batch_per_cu > 0 exactly when it is set");
+        return fail(SD_E_ARG, "batch_threads must be 0, 64, 256 or 512, with batch_per_cu > 0 exactly when it is set");
     }
     e = hipSetDevice(device);
     if (e == hipSuccess && c->opt.batch_threads) {
@@ -364,6 +364,18 @@ hipError_t read_stats(const Inst& I, hipStream_t st, unsigned long long out[4]) 
     return hipSuccess;
 }
 
+// Workgroup size of the span step for a span with `pairs` layer pairs.  Eight waves per pair
+// shorten each pair's critical path (more of its typed-value jobs run at once) but halve the
+// workgroups resident per CU, so they pay only while every pair of the span still fits in about
+// SPAN_WIDE_PER_CU workgroups per CU.
+#ifndef SPAN_WIDE_PER_CU
+#define SPAN_WIDE_PER_CU 4
+#endif
+int span_threads_for(const sd_context* c, int pairs) {
+    if (c->opt.span_threads) return c->opt.span_threads;
+    return pairs <= SPAN_WIDE_PER_CU * c->num_cu ? 512 : 256;
+}
+
 // Plain mode: one span-step launch per span length.  Returns the overflow span (0 if none).
 sd_status run_plain(sd_context* c, const Lattice& L, Inst& I, int64_t* overflow_span) {
     hipStream_t st = c->stream;
@@ -380,7 +392,7 @@ sd_status run_plain(sd_context* c, const Lattice& L, Inst& I, int64_t* overflow_
         if (timing) e = hipEventRecord(c->tev[2 * (g - 1)], st);
         if (e == hipSuccess)
             e = launch_span(I, (const EnergyTables*)c->E_dev, (const int32_t*)c->spec_dev, g,
-                            g >= 2 ? L.n - g + 1 : -1, c->opt.span_threads, st);
+                            g >= 2 ? L.n - g + 1 : -1, span_threads_for(c, L.n - g + 1), st);
         if (timing && e == hipSuccess) e = hipEventRecord(c->tev[2 * (g - 1) + 1], st);
     }
     if (e == hipSuccess) e = launch_ext(I, (const EnergyTables*)c->E_dev, 0, st);
@@ -793,7 +805,7 @@ sd_status tuned_schedule(sd_context* c, const std::vector<Lattice>& batch, int* 
     }
     double best_t = 1e30;
     int best_grid = 0, best_threads = 256;
-    for (int threads_c : {256, 64}) {
+    for (int threads_c : {256, 512, 64}) {
         int per_cu = 0;
         hipError_t e = persistent_occupancy(threads_c, &per_cu);
         if (e != hipSuccess || per_cu <= 0) return hip_fail(e, "occupancy query");

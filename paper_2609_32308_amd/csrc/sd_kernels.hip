@@ -1146,9 +1146,10 @@ hipError_t launch_batch_init(const Inst* insts_dev, int ninst, BatchCtl* ctl, hi
     return hipGetLastError();
 }
 
-// threads per block: 64 (one wave per layer-pair item) or 256 (four waves share an item)
+// threads per block: 64 (one wave per layer-pair item), 256 or 512 (4 or 8 waves share an item)
 hipError_t persistent_occupancy(int threads, int* blocks_per_cu) {
     if (threads == 64) return hipOccupancyMaxActiveBlocksPerMultiprocessor(blocks_per_cu, k_persistent<64>, 64, 0);
+    if (threads == 512) return hipOccupancyMaxActiveBlocksPerMultiprocessor(blocks_per_cu, k_persistent<512>, 512, 0);
     return hipOccupancyMaxActiveBlocksPerMultiprocessor(blocks_per_cu, k_persistent<256>, 256, 0);
 }
 
@@ -1157,6 +1158,8 @@ hipError_t launch_persistent(const Inst* insts_dev, int ninst, int nsteps, const
                              hipStream_t st) {
     if (threads == 64)
         hipLaunchKernelGGL(k_persistent<64>, dim3(grid), dim3(64), 0, st, insts_dev, ninst, nsteps, E, spec, ctl, spin_cap);
+    else if (threads == 512)
+        hipLaunchKernelGGL(k_persistent<512>, dim3(grid), dim3(512), 0, st, insts_dev, ninst, nsteps, E, spec, ctl, spin_cap);
     else
         hipLaunchKernelGGL(k_persistent<256>, dim3(grid), dim3(256), 0, st, insts_dev, ninst, nsteps, E, spec, ctl, spin_cap);
     return hipGetLastError();
