@@ -10,6 +10,7 @@ GPU, runs the canonical traceback and returns the result strings.
                      designed at lambda = 0 and lambda = 4 in plain mode (one span-step kernel
                      launch per span length);
   config3:           the 925-aa and 1,976-aa proteins (seed 1) at lambda = 0 and 4, plain mode;
+  scale:             one 3,677-aa protein (seed 1) at lambda = 0 and 4, plain mode;
   batch:             256 proteins, lengths log-uniform in [50, 1000] aa (seed 7), half at
                      lambda = 0 and half at lambda = 4, in one batched persistent launch;
   served:            a Poisson request stream through the continuous-batching server, with the
@@ -58,6 +59,10 @@ def workload(name):
         items = [(S.protein(A, 1), lam) for A in (925, 1976) for lam in (0.0, 4.0)]
         return items, {"workload": "plain design, synthetic 925-aa and 1976-aa proteins (seed 1), lambda 0 and 4",
                        "aa": [925, 1976], "lambdas": [0, 4], "mode": "plain"}
+    if name == "scale":
+        p = S.protein(3677, 1)
+        return [(p, 0.0), (p, 4.0)], {"workload": "plain design, one 3677-aa synthetic protein (seed 1; the length of the paper's largest design), lambda 0 and 4",
+                                      "aa": 3677, "lambdas": [0, 4], "mode": "plain"}
     if name == "batch":
         lens = S.batch_lengths(256, 50, 1000, seed=7)
         items = [(S.protein(A, 7000 + i), 0.0 if i < 128 else 4.0) for i, A in enumerate(lens)]
@@ -250,7 +255,8 @@ def served_workload(args, sd, S):
                 "peak_active": st["peak_active"], "fallbacks": st["fallbacks"], "rounds": st["rounds"],
                 "reserved_bytes_per_request": st["reserved_bytes"] / nreq,
                 "reserved_cand_bytes_per_request": st["reserved_cand_bytes"] / nreq,
-                "pool_high_water": st["pool_high_water"], "identical_to_plain": same}
+                "pool_high_water": st["pool_high_water"], "gpu_busy_frac": st["gpu_seconds"] / done,
+                "identical_to_plain": same}
 
     runs = [serve("worst", 0.0), serve("mlp", 0.0), serve("worst", 0.8), serve("mlp", 0.8), serve("mlp", 0.95)]
     sat = runs[1]
@@ -275,7 +281,7 @@ def main():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=5)
     ap.add_argument("--warmup", type=int, default=1)
-    ap.add_argument("--workload", default="config2", choices=["config2", "config3", "batch", "served"])
+    ap.add_argument("--workload", default="config2", choices=["config2", "config3", "scale", "batch", "served"])
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--retain-all", action="store_true",
                     help="plain workloads: also time the scalar-dense control (every finite direct "

@@ -421,12 +421,21 @@ sd_status design_plain(sd_context* c, const char* protein, const sd_codon_table*
 // Download the tables the traceback reads.  By default into the context's pinned buffer (grown
 // on demand, no host zeroing, DMA at full link speed; valid until the next download on this
 // context); with own_storage into host memory owned by T (for results traced back later).
-sd_status fetch_tables(sd_context* c, const Lattice& L, const Inst& I, TraceTables& T, bool own_storage) {
+size_t table_bytes(const Lattice& L) {
+    const size_t cells = (size_t)L.cells, N = (size_t)L.N, slots = (size_t)L.cand_slots;
+    return cells * 72 + N * 8 + ((N * 4 + 7) & ~(size_t)7) + slots * 4;
+}
+
+sd_status fetch_tables(sd_context* c, const Lattice& L, const Inst& I, TraceTables& T, bool own_storage,
+                       char* into) {
     hipStream_t st = c->stream;
     const size_t cells = (size_t)L.cells, N = (size_t)L.N, slots = (size_t)L.cand_slots;
-    const size_t bytes = cells * 72 + N * 8 + ((N * 4 + 7) & ~(size_t)7) + slots * 4;
+    const size_t bytes = table_bytes(L);
     char* base;
-    if (own_storage) {
+    if (into) {
+        base = into;
+        T.own.reset();
+    } else if (own_storage) {
         T.own.reset(new (std::nothrow) char[bytes]);
         if (!T.own) return fail(SD_E_NOMEM, "host table buffer");
         base = T.own.get();
@@ -805,7 +814,7 @@ sd_status tuned_schedule(sd_context* c, const std::vector<Lattice>& batch, int* 
     }
     double best_t = 1e30;
     int best_grid = 0, best_threads = 256;
-    for (int threads_c : {256, 512, 64}) {
+    for (int threads_c : {256, 64}) {  // 512 (caller-selectable) lost every probe on mixed batches
         int per_cu = 0;
         hipError_t e = persistent_occupancy(threads_c, &per_cu);
         if (e != hipSuccess || per_cu <= 0) return hip_fail(e, "occupancy query");

@@ -23,7 +23,11 @@ sd_status fail(sd_status s, const std::string& msg);
 sd_status hip_fail(hipError_t e, const char* where);
 double now_s();
 sd_status ensure_params(sd_context* c, const sd_params* p);
-sd_status fetch_tables(sd_context* c, const Lattice& L, const Inst& I, TraceTables& T, bool own_storage = false);
+// into: caller memory of table_bytes(L) (pinned for full-speed copies); else the context's
+// pinned buffer, or host memory owned by T with own_storage
+size_t table_bytes(const Lattice& L);
+sd_status fetch_tables(sd_context* c, const Lattice& L, const Inst& I, TraceTables& T, bool own_storage = false,
+                       char* into = nullptr);
 sd_status fill_result(const Lattice& L, const TraceResult& R, int64_t xs, int64_t Z, int64_t visits,
                       int64_t feasible, sd_result* out);
 sd_status design_plain(sd_context* c, const char* protein, const sd_codon_table* table,

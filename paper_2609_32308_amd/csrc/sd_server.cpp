@@ -123,9 +123,12 @@ struct sd_server {
     struct Job {
         Active a;
         TraceTables T;
+        char* pinned = nullptr;  // pinned host buffer holding T, returned to the pool after use
+        size_t pinned_bytes = 0;
         int64_t visits, feasible;
         double t_fill;
     };
+    std::vector<std::pair<char*, size_t>> pinned_free;  // reusable pinned table buffers (under tmu)
     std::deque<Job> jobs;
     std::vector<std::thread> workers;
     int jobs_running = 0;
@@ -169,6 +172,7 @@ void worker_main(sd_server* S) {
         }
         finish(S, job.a.rq.ticket, s, r);
         std::lock_guard<std::mutex> lk(S->tmu);
+        if (job.pinned) S->pinned_free.push_back({job.pinned, job.pinned_bytes});
         S->jobs_running--;
     }
 }
@@ -330,7 +334,32 @@ sd_status round_once(sd_server* S) {
             continue;
         }
         sd_server::Job job;
-        sd_status s = fetch_tables(S->ctx, a.L, a.I, job.T, true);
+        // pinned buffer from the pool (smallest that fits), else a new one; host memory as a
+        // last resort
+        const size_t need = table_bytes(a.L);
+        {
+            std::lock_guard<std::mutex> lk(S->tmu);
+            int best = -1;
+            for (int k = 0; k < (int)S->pinned_free.size(); k++)
+                if (S->pinned_free[k].second >= need &&
+                    (best < 0 || S->pinned_free[k].second < S->pinned_free[best].second))
+                    best = k;
+            if (best >= 0) {
+                job.pinned = S->pinned_free[best].first;
+                job.pinned_bytes = S->pinned_free[best].second;
+                S->pinned_free.erase(S->pinned_free.begin() + best);
+            }
+        }
+        if (!job.pinned) {
+            const size_t want = need + need / 8;
+            if (hipHostMalloc((void**)&job.pinned, want, hipHostMallocDefault) == hipSuccess) {
+                job.pinned_bytes = want;
+            } else {
+                hipGetLastError();
+                job.pinned = nullptr;
+            }
+        }
+        sd_status s = fetch_tables(S->ctx, a.L, a.I, job.T, true, job.pinned);
         S->pool.release(a.off, a.bytes);
         if (s) return s;
         job.visits = (int64_t)stats[0];
@@ -478,6 +507,7 @@ extern "C" sd_status sd_server_stop(sd_server* S) {
     }
     for (auto& w : S->workers) w.join();
     for (auto& kv : S->done) sd_result_free(&kv.second.res);
+    for (auto& b : S->pinned_free) hipHostFree(b.first);  // every job has returned its buffer
     hipFree(S->pool_dev);
     hipFree(S->aux_dev);
     if (S->staging) hipHostFree(S->staging);
