@@ -87,3 +87,36 @@ def test_config4_members_vs_golden(ctx, gt, gp):
     for r, d in zip(rb, ds):
         assert (r.energy, r.objective_fixed, r.mrna, r.structure) == (d["energy"], d["objective_fixed"], d["mrna"], d["structure"])
         assert r.n_candidates == d["n_candidates"] and r.n_visits == d["visits_sparse"]
+
+
+@pytest.mark.parametrize("threads,per_cu", [(64, 2), (256, 1), (512, 1)])
+def test_fixed_schedules_equal_plain(sd, gt, gp, threads, per_cu):
+    # every persistent schedule the caller can fix (workgroup size x workgroups per CU) gives the
+    # plain results, whichever one the autotuner would have picked
+    lens = [8, 33, 57, 21, 70]
+    prots = [S.protein(A, 800 + i) for i, A in enumerate(lens)]
+    lams = [0.0, 4.0, 0.0, 4.0, 2.0]
+    c = sd.Context(0, batch_threads=threads, batch_per_cu=per_cu)
+    say("schedule", threads, per_cu)
+    rb = c.design_batch(prots, lams, gt, gp)
+    for p, lam, r in zip(prots, lams, rb):
+        assert key(r) == key(c.design(p, gt, gp, lam))
+    c.close()
+
+
+def test_invalid_options_rejected(sd):
+    for kw in ({"span_threads": 100}, {"batch_threads": 128, "batch_per_cu": 1},
+               {"batch_threads": 256}, {"batch_per_cu": 2}, {"batch_threads": 256, "batch_per_cu": 1000}):
+        with pytest.raises(sd.SDError) as e:
+            sd.Context(0, **kw)
+        assert e.value.code == -1, kw
+
+
+def test_envelope_invalid_ranges(ctx, sd, gt, gp):
+    for lo, hi, code in ((-1.0, 4.0, -5), (2.0, 2.0, -5), (3.0, 1.0, -5), (0.0, float("inf"), -5)):
+        with pytest.raises(sd.SDError) as e:
+            ctx.lambda_envelope("MKV*", lo, hi, gt, gp)
+        assert e.value.code == code
+    with pytest.raises(sd.SDError) as e:
+        ctx.lambda_envelope("MKV*", 0.0, 1.0, gt, gp, max_designs=1)
+    assert e.value.code == -1
