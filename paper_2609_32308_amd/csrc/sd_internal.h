@@ -32,6 +32,10 @@ struct EnergyTables {
     int32_t hairpin[31], bulge[31], interior[31];
     int32_t ml_closing, ml_intern, ml_base, terminal_au, ninio, ninio_max;
     int32_t pad[2];
+    // 16-bit copies of int21 / int22 (the parser requires entries in [-32768, 32767]) that the
+    // kernels stage into LDS with 16-byte copies
+    alignas(16) int16_t int21h[6][6][4][4][4];
+    alignas(16) int16_t int22h[6][6][4][4][4][4];
 };
 
 // Special hairpin lookup: key = base-4 number of the loop sequence (closing pair included),

@@ -20,6 +20,7 @@
 // (bulges, 1xn, 1x1/1x2/2x2 tables, segments inside one codon) is enumerated explicitly.
 #include <hip/hip_runtime.h>
 
+#include <stddef.h>
 #include <string.h>
 
 #include "sd_internal.h"
@@ -40,9 +41,11 @@ enum { kListBulge = 0, kListOne = 1, kListLab = 2, kListFast = 3, kListBulgeSep 
 __constant__ unsigned short kPairList[5][9][kNumPairs];
 __constant__ unsigned short kPairCnt[5][9][31];
 
-// Loop tables staged in LDS (the 1x2 and 2x2 full-loop tables stay in global memory; they are
-// read for 3 of the 496 (l1, l2) pairs only).
+// Loop tables staged in LDS per workgroup (~27 KB; the 1x2 and 2x2 full-loop tables as 16-bit
+// copies).
 struct SmallE {
+    alignas(16) int16_t int21[6][6][4][4][4];    // 1x2 loops (staged from the 16-bit copies)
+    alignas(16) int16_t int22[6][6][4][4][4][4]; // 2x2 loops
     int32_t stack[6][6];
     int32_t mmH[6][4][4], mmI[6][4][4], mm1n[6][4][4], mm23[6][4][4];
     int32_t int11[6][6][4][4];
@@ -52,6 +55,14 @@ struct SmallE {
 
 __device__ void stage_tables(SmallE& S, const EnergyTables* __restrict__ E) {
     const int t = threadIdx.x, nt = blockDim.x;
+    {
+        static_assert(sizeof(S.int21) + sizeof(S.int22) == 23040, "int21 + int22 copies");
+        static_assert(offsetof(EnergyTables, int22h) == offsetof(EnergyTables, int21h) + sizeof(S.int21),
+                      "adjacent 16-bit tables");
+        const uint4* src = reinterpret_cast<const uint4*>(&E->int21h[0][0][0][0][0]);
+        uint4* dst = reinterpret_cast<uint4*>(&S.int21[0][0][0][0][0]);
+        for (int i = t; i < 23040 / 16; i += nt) dst[i] = src[i];
+    }
     for (int i = t; i < 36; i += nt) (&S.stack[0][0])[i] = (&E->stack[0][0])[i];
     for (int i = t; i < 96; i += nt) {
         (&S.mmH[0][0][0])[i] = (&E->mmH[0][0][0])[i];
@@ -126,9 +137,9 @@ __device__ __forceinline__ int32_t interior_base(const SmallE& S, int l1, int l2
 __device__ int32_t interior_e(const SmallE& S, const EnergyTables* __restrict__ E, int t, int tr,
                               int l1, int l2, int xi1, int xk1, int xl1, int xj1) {
     if (l1 == 1 && l2 == 1) return S.int11[t][tr][xi1][xj1];
-    if (l1 == 1 && l2 == 2) return E->int21[t][tr][xi1][xl1][xj1];
-    if (l1 == 2 && l2 == 1) return E->int21[tr][t][xl1][xi1][xk1];
-    if (l1 == 2 && l2 == 2) return E->int22[t][tr][xi1][xk1][xl1][xj1];
+    if (l1 == 1 && l2 == 2) return S.int21[t][tr][xi1][xl1][xj1];
+    if (l1 == 2 && l2 == 1) return S.int21[tr][t][xl1][xi1][xk1];
+    if (l1 == 2 && l2 == 2) return S.int22[t][tr][xi1][xk1][xl1][xj1];
     int32_t e = interior_base(S, l1, l2);
     if (l1 == 1 || l2 == 1) return e + S.mm1n[t][xi1][xj1] + S.mm1n[tr][xl1][xk1];
     if (l1 + l2 == 5 && (l1 == 2 || l1 == 3)) return e + S.mm23[t][xi1][xj1] + S.mm23[tr][xl1][xk1];
@@ -966,15 +977,10 @@ __global__ __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(4))) void k_
     __shared__ int64_t red[NT];
     __shared__ GroupShared<NT / 64> G;
     __shared__ int pref[kMaxBatch + 1];
-    __shared__ int nl[kMaxBatch];
-    __shared__ int g0s[kMaxBatch];
+    __shared__ int wsum[NT / 64];
     __shared__ int s_flag;
     __shared__ unsigned s_ticket;
     stage_tables(S, E);
-    for (int i = threadIdx.x; i < ninst; i += blockDim.x) {
-        nl[i] = insts[i].n;
-        g0s[i] = insts[i].g0;
-    }
     // Work tickets of group grp number the items of its band of step 0, then of step 1, ...  A
     // workgroup that draws a ticket beyond the current step keeps it for the step it belongs to.
     const unsigned grp = blockIdx.x & 7, ngrp = gridDim.x < 8 ? gridDim.x : 8;
@@ -983,15 +989,37 @@ __global__ __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(4))) void k_
     unsigned ticket = s_ticket, base = 0;
     for (int step = 0; step < nsteps; step++) {
         // work items per instance at its span g = g0 + step: layer pairs of span g, then one
-        // external column (layer n - g + 1, one layer behind)
-        if (threadIdx.x == 0) {
-            int acc = 0;
-            for (int i = 0; i < ninst; i++) {
+        // external column (layer n - g + 1, one layer behind); exclusive prefix over instances,
+        // each thread taking a contiguous run of instances
+        {
+            const int per = (ninst + NT - 1) / NT, lo = threadIdx.x * per, hi = min(lo + per, ninst);
+            int sum = 0;
+            for (int i = lo; i < hi; i++) {
+                const int n = insts[i].n, g = insts[i].g0 + step;
+                sum += (g <= n ? n - g + 1 : 0) + ((g >= 2 && g <= n + 1) ? 1 : 0);
+            }
+            const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+            int incl = sum;
+#pragma unroll
+            for (int o = 1; o < 64; o <<= 1) {
+                const int v = __shfl_up(incl, o, 64);
+                if (lane >= o) incl += v;
+            }
+            if (lane == 63) wsum[w] = incl;
+            __syncthreads();
+            int base_w = 0;
+            for (int k = 0; k < w; k++) base_w += wsum[k];
+            int acc = base_w + incl - sum;
+            for (int i = lo; i < hi; i++) {
                 pref[i] = acc;
-                const int n = nl[i], g = g0s[i] + step;
+                const int n = insts[i].n, g = insts[i].g0 + step;
                 acc += (g <= n ? n - g + 1 : 0) + ((g >= 2 && g <= n + 1) ? 1 : 0);
             }
-            pref[ninst] = acc;
+            if (threadIdx.x == NT - 1) {
+                int tot = 0;
+                for (int k = 0; k < NT / 64; k++) tot += wsum[k];
+                pref[ninst] = tot;
+            }
         }
         __syncthreads();
         const unsigned total = (unsigned)pref[ninst];
@@ -1007,8 +1035,8 @@ __global__ __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(4))) void k_
             }
             // the instance index is block-uniform
             const int inst = __builtin_amdgcn_readfirstlane(lo);
-            const int local = item - pref[inst], g = g0s[inst] + step;
             const Inst I = insts[inst];  // a few scalar registers: bases and sizes
+            const int local = item - pref[inst], g = I.g0 + step;
             const int n = I.n, ncell_items = g <= n ? n - g + 1 : 0;
             if (local < ncell_items) {
                 GroupCounters c = span_group(I, S, E, spec, local, local + g, G);

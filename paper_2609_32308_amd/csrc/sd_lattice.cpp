@@ -199,6 +199,23 @@ int parse_params(const std::string& text, Params& P, std::string& err) {
         for (int32_t e : P.special_e[k]) upd(e);
     for (int32_t v : {P.E.ml_closing, P.E.ml_intern, P.E.ml_base, P.E.terminal_au, P.E.ninio, P.E.ninio_max}) upd(v);
     P.maxabs = mx;
+    // 16-bit copies of the 1x2 and 2x2 tables for the kernels
+    for (int j = 0; j < 2304; j++) {
+        const int32_t v = (&P.E.int21[0][0][0][0][0])[j];
+        if (v < -32768 || v > 32767) {
+            err = "[int21] entry outside the 16-bit range the kernels stage";
+            return SD_E_PARAMS;
+        }
+        (&P.E.int21h[0][0][0][0][0])[j] = (int16_t)v;
+    }
+    for (int j = 0; j < 9216; j++) {
+        const int32_t v = (&P.E.int22[0][0][0][0][0][0])[j];
+        if (v < -32768 || v > 32767) {
+            err = "[int22] entry outside the 16-bit range the kernels stage";
+            return SD_E_PARAMS;
+        }
+        (&P.E.int22h[0][0][0][0][0][0])[j] = (int16_t)v;
+    }
     // special-loop lookup table keyed by the base-4 value of the loop sequence
     P.spec_table.assign(kSpecSize, kNoSpecial);
     const int offs[3] = {kSpecOff5, kSpecOff6, kSpecOff8};
