@@ -46,6 +46,13 @@ def lib():
         L.or_eval.argtypes = [C.c_char_p, C.c_char_p, C.c_void_p, C.POINTER(C.c_int32)]
         L.or_bruteforce.argtypes = [C.c_char_p, C.POINTER(C.c_double), C.c_void_p, C.c_double,
                                     P64, C.POINTER(C.c_double), P64, C.POINTER(C.c_int32)]
+        PC = C.POINTER(C.c_char_p)
+        L.or_design_motifs.argtypes = [C.c_char_p, C.POINTER(C.c_double), C.c_void_p, C.c_double, PC,
+                                       C.c_int, C.c_int, C.c_char_p, C.c_char_p, C.POINTER(_Res)]
+        L.or_motif_lattice.argtypes = [C.c_char_p, PC, C.c_int, P64, P64, P64, P64]
+        L.or_bruteforce_motifs.argtypes = [C.c_char_p, C.POINTER(C.c_double), C.c_void_p, C.c_double,
+                                           PC, C.c_int, P64, C.POINTER(C.c_double), P64,
+                                           C.POINTER(C.c_int32)]
         L.or_multiloop_dense.argtypes = [C.c_int, C.POINTER(C.c_int), C.c_int, C.POINTER(C.c_int),
                                          C.POINTER(C.c_int), P64, P64, P64, P64, P64]
         _lib = L
@@ -124,6 +131,41 @@ def design(protein: str, w, params: Params, lam: float, nthreads: int = 0, table
                   res.visits_sparse, bool(res.selfcheck_ok), arrs)
 
 
+def _motif_array(motifs):
+    arr = (C.c_char_p * max(len(motifs), 1))(*[m.encode() for m in motifs])
+    return arr, len(motifs)
+
+
+INFEASIBLE = -12
+
+
+def design_motifs(protein: str, w, params: Params, lam: float, motifs, nthreads: int = 0) -> Design:
+    """Dense oracle design over the product with the forbidden-motif matcher."""
+    n = 3 * len(protein)
+    mr = C.create_string_buffer(n + 1)
+    st = C.create_string_buffer(n + 1)
+    res = _Res()
+    wa, wp = _w(w)
+    arr, nm = _motif_array(motifs)
+    rc = lib().or_design_motifs(protein.encode(), wp, params.h, lam, arr, nm, nthreads, mr, st,
+                                C.byref(res))
+    if rc:
+        raise OracleError(rc, "or_design_motifs")
+    return Design(mr.value.decode(), st.value.decode(), res.energy, res.objective_fixed, res.path_u,
+                  res.fixed_shift, res.codon_cost, res.objective_kcal, res.n_states, res.n_edges,
+                  res.n_cells, res.n_feasible_direct, res.n_candidates, res.visits_dense,
+                  res.visits_sparse, bool(res.selfcheck_ok), None)
+
+
+def motif_lattice(protein: str, motifs) -> dict:
+    v = [C.c_int64() for _ in range(4)]
+    arr, nm = _motif_array(motifs)
+    rc = lib().or_motif_lattice(protein.encode(), arr, nm, *[C.byref(x) for x in v])
+    if rc:
+        raise OracleError(rc, "or_motif_lattice")
+    return dict(zip(["n_states", "n_edges", "width", "n_paths"], [x.value for x in v]))
+
+
 def design_status(protein: str, w, params: Params, lam: float) -> int:
     n = 3 * max(len(protein), 1)
     mr = C.create_string_buffer(n + 1)
@@ -171,6 +213,17 @@ def bruteforce(protein: str, w, params: Params, lam: float):
                              C.byref(ns), C.byref(sh))
     if rc:
         raise OracleError(rc, "or_bruteforce")
+    return {"best_fixed": bf.value, "best_kcal": bk.value, "n_seqs": ns.value, "shift": sh.value}
+
+
+def bruteforce_motifs(protein: str, w, params: Params, lam: float, motifs):
+    bf, bk, ns, sh = C.c_int64(), C.c_double(), C.c_int64(), C.c_int32()
+    wa, wp = _w(w)
+    arr, nm = _motif_array(motifs)
+    rc = lib().or_bruteforce_motifs(protein.encode(), wp, params.h, lam, arr, nm, C.byref(bf),
+                                    C.byref(bk), C.byref(ns), C.byref(sh))
+    if rc:
+        raise OracleError(rc, "or_bruteforce_motifs")
     return {"best_fixed": bf.value, "best_kcal": bk.value, "n_seqs": ns.value, "shift": sh.value}
 
 

@@ -4,7 +4,8 @@
  * codon costs U(r) and the FP64 codon penalty C(r).  Returns min_r MFE(r)*2^s + U(r) in the
  * fixed point of the lattice DP (same shift rule and rounding), and min_r MFE(r)/100 +
  * lambda*C(r) in FP64 (the objective of eq. 1).  Sec. 7.1 reports the same kind of independent
- * synonymous enumeration as a correctness check.
+ * synonymous enumeration as a correctness check.  With forbidden motifs, mRNAs containing any
+ * motif as a substring are skipped (the constrained language of Sec. 3).
  */
 #include <math.h>
 #include <stdlib.h>
@@ -14,9 +15,11 @@
 
 static const char CODE64[65] = "KNKNTTTTRSRSIIMIQHQHPPPPRRRRLLLLEDEDAAAAGGGGVVVV*Y*YSSSS*CWCLFLF";
 
-int or_bruteforce(const char *protein, const double w[64], const or_params *P, double lambda,
-                  int64_t *best_fixed, double *best_kcal, int64_t *n_seqs, int32_t *shift) {
+int or_bruteforce_motifs(const char *protein, const double w[64], const or_params *P, double lambda,
+                         const char *const *motifs, int nm, int64_t *best_fixed, double *best_kcal,
+                         int64_t *n_seqs, int32_t *shift) {
     if (!protein || !w || !P || !best_fixed || !best_kcal || !n_seqs || !shift) return OR_E_ARG;
+    if (nm < 0 || (nm > 0 && !motifs)) return OR_E_ARG;
     int s = or_fixed_shift(protein, w, P, lambda);
     if (s < 0) return s;
     int A = (int)strlen(protein);
@@ -44,6 +47,14 @@ int or_bruteforce(const char *protein, const double w[64], const or_params *P, d
             Cr += q;
         }
         seq[3 * A] = 0;
+        int banned = 0;
+        for (int i = 0; i < nm && !banned; i++) banned = strstr(seq, motifs[i]) != NULL;
+        if (banned) {
+            int k = A - 1;
+            while (k >= 0 && ++idx[k] == nf[k]) idx[k--] = 0;
+            if (k < 0) break;
+            continue;
+        }
         int32_t e;
         int rc = or_zuker(seq, P, &e, NULL);
         if (rc) {
@@ -65,4 +76,9 @@ int or_bruteforce(const char *protein, const double w[64], const or_params *P, d
     *n_seqs = count;
     *shift = s;
     return OR_OK;
+}
+
+int or_bruteforce(const char *protein, const double w[64], const or_params *P, double lambda,
+                  int64_t *best_fixed, double *best_kcal, int64_t *n_seqs, int32_t *shift) {
+    return or_bruteforce_motifs(protein, w, P, lambda, NULL, 0, best_fixed, best_kcal, n_seqs, shift);
 }

@@ -84,6 +84,8 @@ static int check_codons(const char *p, const double *w) {
     return OR_OK;
 }
 
+static int finish_dfa(dfa_t *D);
+
 /* prefix-trie codon DFA of Sec. 3 (Fig. 1 state-join rule holds by construction) */
 static int build_dfa(const char *prot, const double *w, dfa_t *D) {
     memset(D, 0, sizeof(*D));
@@ -147,6 +149,12 @@ static int build_dfa(const char *prot, const double *w, dfa_t *D) {
     D->off[n + 1] = N;
     D->N = N;
     D->nE = E;
+    return finish_dfa(D);
+}
+
+/* out-edge table by label, in-edges sorted by (source, label), out-edges sorted by label */
+static int finish_dfa(dfa_t *D) {
+    int N = D->N, E = D->nE;
     D->out = malloc(sizeof(int) * 4 * N);
     D->in_start = calloc(N + 1, sizeof(int));
     D->in_e = malloc(sizeof(int) * (E + 1));
@@ -183,6 +191,216 @@ static int build_dfa(const char *prot, const double *w, dfa_t *D) {
     }
     free(fill);
     return OR_OK;
+}
+
+/* --- forbidden motifs (Sec. 3: the codon DFA intersected with a deterministic motif matcher) ---
+ * Matcher states are the distinct prefixes of the motifs (the empty prefix included), ranked by
+ * length and then in A<C<G<U order.  Reading base x in state m leads to the longest suffix of
+ * m.x that is again a prefix; the step is forbidden when some suffix of m.x is a whole motif
+ * (such transitions are removed).  The product keeps the pairs (codon state, matcher state)
+ * reachable from (source, empty prefix) by allowed steps, then drops every pair from which no
+ * path reaches the last layer.  Within a layer, states are ordered by codon state, then by
+ * matcher rank.  An empty language (no synonymous mRNA avoids the motifs) is OR_E_INFEASIBLE. */
+typedef struct {
+    int K;
+    char (*str)[OR_MAX_MOTIF + 1];
+    int *delta; /* [K*4] next matcher state, -1 if the step completes a motif */
+} matcher_t;
+
+static int pref_cmp(const void *x, const void *y) {
+    const char *a = x, *b = y;
+    size_t la = strlen(a), lb = strlen(b);
+    if (la != lb) return la < lb ? -1 : 1;
+    return strcmp(a, b);
+}
+
+static int pref_find(const matcher_t *M, const char *t) {
+    for (int i = 0; i < M->K; i++)
+        if (strcmp(M->str[i], t) == 0) return i;
+    return -1;
+}
+
+static int build_matcher(const char *const *motifs, int nm, matcher_t *M) {
+    memset(M, 0, sizeof(*M));
+    int cap = 1;
+    for (int i = 0; i < nm; i++) {
+        if (!motifs[i]) return OR_E_ARG;
+        size_t L = strlen(motifs[i]);
+        if (L < 1 || L > OR_MAX_MOTIF) return OR_E_ARG;
+        for (size_t k = 0; k < L; k++)
+            if (or_nuc(motifs[i][k]) < 0) return OR_E_ARG;
+        cap += (int)L;
+    }
+    M->str = calloc(cap, sizeof(*M->str));
+    if (!M->str) return OR_E_NOMEM;
+    int K = 0;
+    M->str[K++][0] = 0;
+    for (int i = 0; i < nm; i++) {
+        size_t L = strlen(motifs[i]);
+        for (size_t l = 1; l <= L; l++) {
+            memcpy(M->str[K], motifs[i], l);
+            M->str[K][l] = 0;
+            K++;
+        }
+    }
+    qsort(M->str, K, sizeof(*M->str), pref_cmp);
+    int u = 0;
+    for (int i = 0; i < K; i++)
+        if (u == 0 || strcmp(M->str[u - 1], M->str[i]) != 0) memcpy(M->str[u++], M->str[i], sizeof(*M->str));
+    M->K = K = u;
+    M->delta = malloc(sizeof(int) * 4 * K);
+    if (!M->delta) return OR_E_NOMEM;
+    char t[OR_MAX_MOTIF + 2];
+    for (int m = 0; m < K; m++)
+        for (int x = 0; x < 4; x++) {
+            size_t L = strlen(M->str[m]);
+            memcpy(t, M->str[m], L);
+            t[L] = "ACGU"[x];
+            t[L + 1] = 0;
+            int forbidden = 0, next = -1;
+            for (size_t k = 0; k <= L + 1; k++) { /* suffixes, longest first */
+                for (int i = 0; i < nm && !forbidden; i++)
+                    if (strcmp(t + k, motifs[i]) == 0) forbidden = 1;
+                if (next < 0 && k <= L + 1 && (L + 1 - k) <= OR_MAX_MOTIF) next = pref_find(M, t + k);
+            }
+            M->delta[m * 4 + x] = forbidden ? -1 : next;
+        }
+    return OR_OK;
+}
+
+static void matcher_free(matcher_t *M) {
+    free(M->str);
+    free(M->delta);
+    memset(M, 0, sizeof(*M));
+}
+
+typedef struct {
+    int q, m;
+} pq_t;
+
+static int pq_cmp(const void *x, const void *y) {
+    const pq_t *a = x, *b = y;
+    if (a->q != b->q) return a->q < b->q ? -1 : 1;
+    return (a->m > b->m) - (a->m < b->m);
+}
+
+/* product of the codon DFA T with the matcher of the motifs; T's costs are copied per edge */
+static int build_product(const dfa_t *T, const char *const *motifs, int nm, dfa_t *D) {
+    memset(D, 0, sizeof(*D));
+    matcher_t M;
+    int rc = build_matcher(motifs, nm, &M);
+    if (rc) {
+        matcher_free(&M);
+        return rc;
+    }
+    const int n = T->n, K = M.K;
+    /* forward pass, layer by layer: states as (codon state, matcher state) pairs */
+    int cap = 64, S = 0;
+    pq_t *st = malloc(sizeof(pq_t) * cap);
+    int *loff = malloc(sizeof(int) * (n + 2));
+    if (!st || !loff) {
+        free(st); free(loff); matcher_free(&M);
+        return OR_E_NOMEM;
+    }
+    loff[0] = 0;
+    st[S++] = (pq_t){0, 0};
+    for (int p = 0; p < n; p++) {
+        loff[p + 1] = S;
+        for (int i = loff[p]; i < loff[p + 1]; i++)
+            for (int x = 0; x < 4; x++) {
+                int e = T->out[st[i].q * 4 + x];
+                if (e < 0) continue;
+                int m2 = M.delta[st[i].m * 4 + x];
+                if (m2 < 0) continue;
+                if (S == cap) {
+                    cap *= 2;
+                    pq_t *ns = realloc(st, sizeof(pq_t) * cap);
+                    if (!ns) { free(st); free(loff); matcher_free(&M); return OR_E_NOMEM; }
+                    st = ns;
+                }
+                st[S++] = (pq_t){T->edst[e], m2};
+            }
+        /* sort and deduplicate the new layer */
+        qsort(st + loff[p + 1], S - loff[p + 1], sizeof(pq_t), pq_cmp);
+        int u = loff[p + 1];
+        for (int i = loff[p + 1]; i < S; i++)
+            if (u == loff[p + 1] || pq_cmp(&st[u - 1], &st[i]) != 0) st[u++] = st[i];
+        S = u;
+    }
+    loff[n + 1] = S;
+    /* backward pass: live = some path reaches the last layer */
+    char *live = calloc(S, 1);
+    int *id = malloc(sizeof(int) * S);
+    if (!live || !id) { free(st); free(loff); free(live); free(id); matcher_free(&M); return OR_E_NOMEM; }
+    for (int i = loff[n]; i < S; i++) live[i] = 1;
+    for (int p = n - 1; p >= 0; p--)
+        for (int i = loff[p]; i < loff[p + 1]; i++)
+            for (int x = 0; x < 4 && !live[i]; x++) {
+                int e = T->out[st[i].q * 4 + x];
+                if (e < 0) continue;
+                int m2 = M.delta[st[i].m * 4 + x];
+                if (m2 < 0) continue;
+                pq_t key = {T->edst[e], m2};
+                pq_t *hit = bsearch(&key, st + loff[p + 1], loff[p + 2] - loff[p + 1], sizeof(pq_t), pq_cmp);
+                if (hit && live[hit - st]) live[i] = 1;
+            }
+    if (!live[0]) {
+        free(st); free(loff); free(live); free(id); matcher_free(&M);
+        return OR_E_INFEASIBLE;
+    }
+    int N = 0;
+    for (int i = 0; i < S; i++) id[i] = live[i] ? N++ : -1;
+    D->A = T->A;
+    D->n = n;
+    D->N = N;
+    D->layer = malloc(sizeof(int) * N);
+    D->off = malloc(sizeof(int) * (n + 2));
+    int maxE = 4 * N;
+    D->esrc = malloc(sizeof(int) * maxE);
+    D->edst = malloc(sizeof(int) * maxE);
+    D->elab = malloc(sizeof(int) * maxE);
+    D->ecod = malloc(sizeof(int) * maxE);
+    D->eq = malloc(sizeof(double) * maxE);
+    if (!D->layer || !D->off || !D->esrc || !D->edst || !D->elab || !D->ecod || !D->eq) {
+        free(st); free(loff); free(live); free(id); matcher_free(&M);
+        return OR_E_NOMEM;
+    }
+    int E = 0;
+    for (int p = 0; p <= n; p++) {
+        D->off[p] = N;
+        for (int i = loff[p]; i < loff[p + 1]; i++)
+            if (live[i]) {
+                if (D->off[p] == N) D->off[p] = id[i];
+                D->layer[id[i]] = p;
+            }
+    }
+    D->off[n + 1] = N;
+    for (int p = n; p >= 0; p--) /* empty layers cannot occur, but keep off monotone anyway */
+        if (D->off[p] > D->off[p + 1]) D->off[p] = D->off[p + 1];
+    for (int p = 0; p < n; p++)
+        for (int i = loff[p]; i < loff[p + 1]; i++) {
+            if (!live[i]) continue;
+            for (int x = 0; x < 4; x++) {
+                int e = T->out[st[i].q * 4 + x];
+                if (e < 0) continue;
+                int m2 = M.delta[st[i].m * 4 + x];
+                if (m2 < 0) continue;
+                pq_t key = {T->edst[e], m2};
+                pq_t *hit = bsearch(&key, st + loff[p + 1], loff[p + 2] - loff[p + 1], sizeof(pq_t), pq_cmp);
+                if (!hit || !live[hit - st]) continue;
+                D->esrc[E] = id[i];
+                D->edst[E] = id[hit - st];
+                D->elab[E] = x;
+                D->ecod[E] = T->ecod[e];
+                D->eq[E] = T->eq[e];
+                E++;
+            }
+        }
+    D->nE = E;
+    (void)K;
+    free(st); free(loff); free(live); free(id);
+    matcher_free(&M);
+    return finish_dfa(D);
 }
 
 /* Range rule for the fixed-point shift: the largest s in [16,40] with
@@ -308,6 +526,8 @@ typedef struct {
     int64_t *B, *D1, *D2, *PD; /* N*N */
     int64_t *X;                /* N */
     mlg_t mg;
+    int wmax;                  /* widest layer */
+    int segmax;                /* bound on the loop segments between two states (4 x in-degree) */
 } dp_t;
 
 #define IDX(a, b) ((size_t)(a) * C->N + (size_t)(b))
@@ -525,7 +745,7 @@ static int64_t twoloop_scan(const dp_t *C, int a, int b, int t, int64_t target, 
     if (ea < 0) return OR_INF;
     int a1 = D->edst[ea];
     int64_t best = OR_INF;
-    seg_t Ls[64], Rs[64];
+    seg_t Ls[C->segmax], Rs[C->segmax];
     for (int l1 = 0; l1 <= 30; l1++)
         for (int l2 = 0; l1 + l2 <= 30; l2++) {
             int lc = la + 1 + l1, ld = lb - 1 - l2;
@@ -640,7 +860,7 @@ static int traceback(dp_t *C, tb_t *T) {
         }
         int a = f.a, b = f.b;
         if (f.kind == F_X) {
-            if (a == D->N - 1) continue;
+            if (D->layer[a] == D->n) continue;
             int64_t x = C->X[a];
             int done = 0;
             for (int i = D->out_start[a]; i < D->out_start[a + 1] && !done; i++) {
@@ -748,7 +968,8 @@ static int traceback(dp_t *C, tb_t *T) {
     return OR_OK;
 }
 
-static int setup(dp_t *C, const char *protein, const double *w, const or_params *P, double lambda) {
+static int setup(dp_t *C, const char *protein, const double *w, const or_params *P, double lambda,
+                 const char *const *motifs, int nm) {
     memset(C, 0, sizeof(*C));
     int rc = check_protein(protein);
     if (rc) return rc;
@@ -762,7 +983,24 @@ static int setup(dp_t *C, const char *protein, const double *w, const or_params 
     double lam100 = 100.0 * lambda;
     C->s = choose_shift(&C->D, P, lam100);
     if (C->s < 0) return OR_E_RANGE;
+    if (nm > 0) {
+        if (!motifs || nm > OR_MAX_MOTIFS) return OR_E_ARG;
+        dfa_t prod;
+        rc = build_product(&C->D, motifs, nm, &prod);
+        dfa_free(&C->D);
+        C->D = prod;
+        if (rc) return rc;
+    } else if (nm < 0) {
+        return OR_E_ARG;
+    }
     set_costs(&C->D, P, lam100, C->s);
+    C->wmax = 1;
+    for (int p = 0; p <= C->D.n; p++)
+        if (C->D.off[p + 1] - C->D.off[p] > C->wmax) C->wmax = C->D.off[p + 1] - C->D.off[p];
+    int maxin = 1;
+    for (int v = 0; v < C->D.N; v++)
+        if (C->D.in_start[v + 1] - C->D.in_start[v] > maxin) maxin = C->D.in_start[v + 1] - C->D.in_start[v];
+    C->segmax = 4 * maxin + 4;
     C->N = (size_t)C->D.N;
     C->mg = (mlg_t){C->D.N, C->D.layer, C->D.esrc, C->D.edst, C->D.eu_ml,
                     C->D.in_start, C->D.in_e, C->D.out_start, C->D.out_e};
@@ -776,7 +1014,7 @@ static void teardown(dp_t *C) {
 
 int or_fixed_shift(const char *protein, const double w[64], const or_params *P, double lambda) {
     dp_t C;
-    int rc = setup(&C, protein, w, P, lambda);
+    int rc = setup(&C, protein, w, P, lambda, NULL, 0);
     int s = rc ? rc : C.s;
     teardown(&C);
     return s;
@@ -814,13 +1052,14 @@ int or_lattice_stats(const char *protein, int64_t *n_states, int64_t *n_edges, i
     return OR_OK;
 }
 
-int or_design(const char *protein, const double w[64], const or_params *P, double lambda,
-              int nthreads, char *mrna, char *structure, or_result *res,
-              int64_t *dbg_V, int64_t *dbg_B, int64_t *dbg_D1, int64_t *dbg_D2, int64_t *dbg_X) {
+static int design_impl(const char *protein, const double w[64], const or_params *P, double lambda,
+                       const char *const *motifs, int nm, int nthreads, char *mrna, char *structure,
+                       or_result *res, int64_t *dbg_V, int64_t *dbg_B, int64_t *dbg_D1,
+                       int64_t *dbg_D2, int64_t *dbg_X) {
     if (!mrna || !structure || !res) return OR_E_ARG;
     memset(res, 0, sizeof(*res));
     dp_t Cx, *C = &Cx;
-    int rc = setup(C, protein, w, P, lambda);
+    int rc = setup(C, protein, w, P, lambda, motifs, nm);
     if (rc) {
         teardown(C);
         return rc;
@@ -843,7 +1082,7 @@ int or_design(const char *protein, const double w[64], const or_params *P, doubl
     for (size_t i = 0; i < 6 * NN; i++) C->V[i] = OR_INF;
     fill_gap(C);
     /* span wavefront: every cell of span g depends only on smaller spans */
-    int *ca = malloc(sizeof(int) * C->N * 4), *cb = malloc(sizeof(int) * C->N * 4);
+    int *ca = malloc(sizeof(int) * C->N * C->wmax), *cb = malloc(sizeof(int) * C->N * C->wmax);
     for (int g = 1; g <= D->n; g++) {
         int nc = 0;
         for (int p = 0; p + g <= D->n; p++)
@@ -858,8 +1097,7 @@ int or_design(const char *protein, const double w[64], const or_params *P, doubl
     free(ca);
     free(cb);
     /* external column X(a) for fragments a -> t */
-    for (int i = 0; i < D->N; i++) C->X[i] = OR_INF;
-    C->X[D->N - 1] = 0;
+    for (int i = 0; i < D->N; i++) C->X[i] = D->layer[i] == D->n ? 0 : OR_INF;
     for (int p = D->n - 1; p >= 0; p--)
         for (int a = D->off[p]; a < D->off[p + 1]; a++) {
             int64_t x = OR_INF;
@@ -934,7 +1172,7 @@ int or_design(const char *protein, const double w[64], const or_params *P, doubl
         if (D->ecod[e] >= 0) ccost += D->eq[e];
         state = D->edst[e];
     }
-    if (state != D->N - 1) T.ok = 0;
+    if (D->layer[state] != D->n) T.ok = 0;
     if (T.ok && (Uwalk != T.U || EN(T.E) + T.U != C->X[0])) T.ok = 0;
     for (int i = 0; i < D->n; i++) {
         mrna[i] = T.seq[i] >= 0 ? "ACGU"[T.seq[i]] : 'N';
@@ -956,4 +1194,64 @@ int or_design(const char *protein, const double w[64], const or_params *P, doubl
     free(T.pair);
     teardown(C);
     return T.ok ? OR_OK : OR_E_INTERNAL;
+}
+
+int or_design(const char *protein, const double w[64], const or_params *P, double lambda,
+              int nthreads, char *mrna, char *structure, or_result *res,
+              int64_t *dbg_V, int64_t *dbg_B, int64_t *dbg_D1, int64_t *dbg_D2, int64_t *dbg_X) {
+    return design_impl(protein, w, P, lambda, NULL, 0, nthreads, mrna, structure, res, dbg_V, dbg_B,
+                       dbg_D1, dbg_D2, dbg_X);
+}
+
+int or_design_motifs(const char *protein, const double w[64], const or_params *P, double lambda,
+                     const char *const *motifs, int nm, int nthreads, char *mrna, char *structure,
+                     or_result *res) {
+    if (nm < 1) return OR_E_ARG;
+    return design_impl(protein, w, P, lambda, motifs, nm, nthreads, mrna, structure, res, NULL, NULL,
+                       NULL, NULL, NULL);
+}
+
+int or_motif_lattice(const char *protein, const char *const *motifs, int nm, int64_t *n_states,
+                     int64_t *n_edges, int64_t *width, int64_t *n_paths) {
+    int rc = check_protein(protein);
+    if (rc) return rc;
+    if (nm < 1 || nm > OR_MAX_MOTIFS || !motifs) return OR_E_ARG;
+    double w[64];
+    for (int i = 0; i < 64; i++) w[i] = 1.0;
+    dfa_t T, D;
+    rc = build_dfa(protein, w, &T);
+    if (rc) {
+        dfa_free(&T);
+        return rc;
+    }
+    rc = build_product(&T, motifs, nm, &D);
+    dfa_free(&T);
+    if (rc) {
+        dfa_free(&D);
+        return rc;
+    }
+    /* paths from the source, layer by layer (saturating) */
+    int64_t *cnt = calloc(D.N, sizeof(int64_t));
+    if (!cnt) {
+        dfa_free(&D);
+        return OR_E_NOMEM;
+    }
+    cnt[0] = 1;
+    int64_t wmax = 0, total = 0;
+    for (int p = 0; p <= D.n; p++) {
+        if (D.off[p + 1] - D.off[p] > wmax) wmax = D.off[p + 1] - D.off[p];
+        for (int u = D.off[p]; u < D.off[p + 1]; u++)
+            for (int i = D.out_start[u]; i < D.out_start[u + 1]; i++) {
+                int v = D.edst[D.out_e[i]];
+                cnt[v] = cnt[v] > INT64_MAX - cnt[u] ? INT64_MAX : cnt[v] + cnt[u];
+            }
+    }
+    for (int u = D.off[D.n]; u < D.N; u++) total = total > INT64_MAX - cnt[u] ? INT64_MAX : total + cnt[u];
+    if (n_states) *n_states = D.N;
+    if (n_edges) *n_edges = D.nE;
+    if (width) *width = wmax;
+    if (n_paths) *n_paths = total;
+    free(cnt);
+    dfa_free(&D);
+    return OR_OK;
 }

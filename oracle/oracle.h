@@ -25,6 +25,8 @@
 #define OR_INF ((int64_t)1 << 62)   /* fixed-point infeasibility sentinel */
 #define OR_EINF 1000000000          /* integer energy of an infeasible / unlisted loop size */
 #define OR_MAX_SPECIAL 256
+#define OR_MAX_MOTIF 32            /* longest forbidden motif */
+#define OR_MAX_MOTIFS 256          /* motifs per design */
 
 /* Energy parameters in 0.01 kcal/mol (Turner-2004 d0 array shapes, Sec. 3). */
 typedef struct or_params {
@@ -56,7 +58,8 @@ typedef struct or_result {
 
 /* status codes shared by the oracle entry points (same meaning as the library's, own copy) */
 enum { OR_OK = 0, OR_E_ARG = -1, OR_E_PROTEIN = -2, OR_E_CODON = -3, OR_E_PARAMS = -4,
-       OR_E_LAMBDA = -5, OR_E_RANGE = -6, OR_E_NOMEM = -7, OR_E_INTERNAL = -11 };
+       OR_E_LAMBDA = -5, OR_E_RANGE = -6, OR_E_NOMEM = -7, OR_E_INTERNAL = -11,
+       OR_E_INFEASIBLE = -12 };
 
 int or_params_load(const char *path, or_params **out);
 void or_params_free(or_params *p);
@@ -66,6 +69,18 @@ void or_params_free(or_params *p);
 int or_design(const char *protein, const double w[64], const or_params *P, double lambda,
               int nthreads, char *mrna, char *structure, or_result *res,
               int64_t *dbg_V, int64_t *dbg_B, int64_t *dbg_D1, int64_t *dbg_D2, int64_t *dbg_X);
+/* Design under forbidden motifs: the same DP over the product of the codon DFA with the motif
+ * matcher (Sec. 3).  motifs: nm strings over ACGU (1..OR_MAX_MOTIF bases, nm <= OR_MAX_MOTIFS);
+ * the returned mRNA contains none of them.  The fixed-point shift is the one of the
+ * unconstrained design (range rule over the codon families).  OR_E_INFEASIBLE if no
+ * synonymous mRNA avoids every motif. */
+int or_design_motifs(const char *protein, const double w[64], const or_params *P, double lambda,
+                     const char *const *motifs, int nm, int nthreads, char *mrna, char *structure,
+                     or_result *res);
+/* Product automaton statistics: states, edges, widest layer and the number of source-to-sink
+ * paths (saturating at INT64_MAX); every state lies on such a path (dead states are removed). */
+int or_motif_lattice(const char *protein, const char *const *motifs, int nm, int64_t *n_states,
+                     int64_t *n_edges, int64_t *width, int64_t *n_paths);
 /* Lattice statistics only (no DP): states, edges, cells, feasible direct intervals. */
 int or_lattice_stats(const char *protein, int64_t *n_states, int64_t *n_edges, int64_t *n_cells,
                      int64_t *n_feasible);
@@ -80,6 +95,11 @@ int or_eval(const char *seq, const char *structure, const or_params *P, int32_t 
  * min of the FP64 objective E/100 + lambda*C(r). */
 int or_bruteforce(const char *protein, const double w[64], const or_params *P, double lambda,
                   int64_t *best_fixed, double *best_kcal, int64_t *n_seqs, int32_t *shift);
+/* The same over the synonymous mRNAs that contain none of the motifs (n_seqs counts those;
+ * best_fixed is OR_INF and best_kcal +inf if there is none). */
+int or_bruteforce_motifs(const char *protein, const double w[64], const or_params *P, double lambda,
+                         const char *const *motifs, int nm, int64_t *best_fixed, double *best_kcal,
+                         int64_t *n_seqs, int32_t *shift);
 
 /* Abstract multiloop recurrences (eqs. 3-5) on a layered DAG with given direct costs B
  * (N*N, OR_INF = absent) and unpaired-edge costs u; fills D1, D2, PD (N*N). */

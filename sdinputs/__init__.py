@@ -9,6 +9,9 @@ formats the two independent implementations parse.
   added implicitly (Section 3, problem definition).
 * Codon weights are relative adaptiveness values w(c) = f(c) / max over synonymous f, so every
   family has maximum exactly 1 (Section 3).
+* Forbidden motifs: uniform random 6-mers (16 of them widen the 64- and 105-aa automata by about
+  2.7x, to width 10, as the paper's motif inventories do), or substrings of random coding
+  sequences of a protein for small cases where the constraint must bind.
 * Energy parameters: the genuine Turner-2004 tables are not available, so ``synthetic_params``
   draws a table set with the same array shapes and plausible signs and magnitudes. It is a
   stand-in, never the real model.
@@ -85,6 +88,39 @@ def codon_weights(seed: int = 2026, floor: float = 0.05) -> np.ndarray:
         for i in idx:
             w[i] = f[i] / mx
     return w
+
+
+def motifs(count: int, seed: int, lo: int = 6, hi: int = 6) -> list[str]:
+    """Forbidden-motif inventory: `count` distinct uniform random strings over ACGU with lengths
+    uniform in [lo, hi] (a stand-in for restriction sites and similar short sequence signals)."""
+    rng = np.random.default_rng(seed)
+    out: list[str] = []
+    while len(out) < count:
+        L = int(rng.integers(lo, hi + 1))
+        m = "".join(NUC[i] for i in rng.integers(0, 4, L))
+        if m not in out:
+            out.append(m)
+    return out
+
+
+def motifs_in(protein_: str, count: int, seed: int, lo: int = 3, hi: int = 4) -> list[str]:
+    """Motifs cut from random synonymous mRNAs of the protein (so that they do occur): each is a
+    substring of length uniform in [lo, hi] at a uniform position of a fresh random coding
+    sequence."""
+    rng = np.random.default_rng(seed)
+    out: list[str] = []
+    tries = 0
+    while len(out) < count and tries < 1000:
+        tries += 1
+        rna = "".join(GENETIC_CODE[aa][int(rng.integers(0, len(GENETIC_CODE[aa])))] for aa in protein_)
+        L = int(rng.integers(lo, hi + 1))
+        if L > len(rna):
+            continue
+        i = int(rng.integers(0, len(rna) - L + 1))
+        m = rna[i:i + L]
+        if m not in out:
+            out.append(m)
+    return out
 
 
 def batch_lengths(count: int, lo: int, hi: int, seed: int) -> list[int]:
