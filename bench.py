@@ -68,6 +68,10 @@ def workload(name):
         items = [(S.protein(A, 7000 + i), 0.0 if i < 128 else 4.0) for i, A in enumerate(lens)]
         return items, {"workload": "batched design, 256 synthetic proteins log-uniform in [50,1000] aa, half lambda 0 / half lambda 4",
                        "proteins": 256, "aa_range": [50, 1000], "mode": "batch"}
+    if name == "motifs":
+        p = S.protein(105, 1)
+        return [(p, 0.0), (p, 4.0)], {"workload": "forbidden-motif design, one 105-aa synthetic protein (seed 1) avoiding 16 random 6-mers (seed 7), lambda 0 and 4",
+                                      "aa": 105, "motifs": S.motifs(16, 7), "lambdas": [0, 4], "mode": "plain, generic lattice"}
     raise SystemExit(f"unknown workload {name}")
 
 
@@ -89,7 +93,9 @@ def profile_record(name):
     return d
 
 
-def run_step(ctx, items, table, params, batch):
+def run_step(ctx, items, table, params, batch, motifs=None):
+    if motifs:
+        return [ctx.design_motifs(p, motifs, table, params, lam) for p, lam in items]
     if batch:
         return ctx.design_batch([p for p, _ in items], [l for _, l in items], table, params)
     return [ctx.design(p, table, params, lam) for p, lam in items]
@@ -105,7 +111,7 @@ def cpu_model():
     return "unknown"
 
 
-def cpu_baseline(items):
+def cpu_baseline(items, motifs=None):
     """The oracle, as it stands, on the host cores: every design of the sample on all cores,
     then the first one on a single thread (bounded to about 10-30 s of CPU work)."""
     import oracle as O
@@ -122,17 +128,23 @@ def cpu_baseline(items):
     sample = sample[:2]
     cells = 0
     t = time.time()
+    def run(p, lam, nt):
+        if motifs:
+            return O.design_motifs(p, w, P, lam, motifs, nthreads=nt).n_cells
+        return O.design(p, w, P, lam, nthreads=nt).n_cells
     for p, lam in sample:
-        cells += O.design(p, w, P, lam, nthreads=threads).n_cells
+        cells += run(p, lam, threads)
     dt = time.time() - t
     p1, lam1 = sample[0]
+    if motifs:
+        p1 = p1[:60]  # the single-thread leg on a 60-residue prefix keeps it to about 10 s
     t = time.time()
-    c1 = O.design(p1, w, P, lam1, nthreads=1).n_cells
+    c1 = run(p1, lam1, 1)
     dt1 = time.time() - t
     return {"value": cells / dt, "unit": "cells/s", "cores": threads, "kind": "oracle",
-            "sample": f"dense oracle on {note}: {len(sample)} design(s) of {len(sample[0][0])} aa "
+            "sample": f"dense oracle{' (motif product lattice)' if motifs else ''} on {note}: {len(sample)} design(s) of {len(sample[0][0])} aa "
                       f"({cells} cells, {dt:.2f} s on {threads} threads); single thread {c1 / dt1:.4g} cells/s "
-                      f"({dt1:.2f} s)",
+                      f"({dt1:.2f} s{', 60-residue prefix' if motifs else ''})",
             "single_thread_value": c1 / dt1, "cpu_model": cpu_model(), "os_cpu_count": os.cpu_count()}
 
 
@@ -147,7 +159,7 @@ def per_design_stats(items, results):
     return out
 
 
-def roofline_for(results_steps, counters, batch):
+def roofline_for(results_steps, counters, batch, kernel=None):
     alg_bytes = launches = ktime = 0.0
     for step in results_steps:
         for r in step:
@@ -159,7 +171,7 @@ def roofline_for(results_steps, counters, batch):
     avg_launch_s = ktime / launches if launches else float("nan")
     per_launch = alg_bytes / launches if launches else 0.0
     achieved = per_launch / avg_launch_s / 1e9 if ktime > 0 else 0.0
-    roof = {"bound": "hbm", "kernel": "k_persistent" if batch else "k_span", "achieved": achieved, "peak": PEAK_HBM_GBS,
+    roof = {"bound": "hbm", "kernel": kernel or ("k_persistent" if batch else "k_span"), "achieved": achieved, "peak": PEAK_HBM_GBS,
             "unit": "GB/s", "frac": achieved / PEAK_HBM_GBS,
             "traffic": counters.get("hbm_bytes_per_launch") if counters else None,
             "alg_bytes_per_launch": per_launch, "avg_launch_us": avg_launch_s * 1e6, "launches": int(launches)}
@@ -281,7 +293,7 @@ def main():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=5)
     ap.add_argument("--warmup", type=int, default=1)
-    ap.add_argument("--workload", default="config2", choices=["config2", "config3", "scale", "batch", "served"])
+    ap.add_argument("--workload", default="config2", choices=["config2", "config3", "scale", "batch", "served", "motifs"])
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--retain-all", action="store_true",
                     help="plain workloads: also time the scalar-dense control (every finite direct "
@@ -315,15 +327,16 @@ def main():
         return
     items, config = workload(args.workload)
     batch = args.workload == "batch"
+    motifs = config.get("motifs")
     ctx = sd.Context(0, kernel_timing=True)
     params = sd.Params(S.default_params_path())
     table = sd.CodonTable(S.codon_weights(2026))
     for _ in range(args.warmup):
-        run_step(ctx, items, table, params, batch)
+        run_step(ctx, items, table, params, batch, motifs)
     t0 = time.perf_counter()
     results = []
     for _ in range(args.steps):
-        results.append(run_step(ctx, items, table, params, batch))
+        results.append(run_step(ctx, items, table, params, batch, motifs))
     t1 = time.perf_counter()
     elapsed = t1 - t0
     step_cells = sum(r.n_cells for r in results[0])
@@ -348,11 +361,13 @@ def main():
         "designs_per_min": designs / elapsed * 60.0,
         "fill_ms_per_step": fill / args.steps * 1e3,
         "per_design": per_design_stats(items, results[-1]),
-        "roofline": roofline_for(results, counters, batch),
+        "roofline": roofline_for(results, counters, batch, "k_span_gen" if motifs else None),
         "params_sha256": params.sha256,
     }
     ctx.close()
-    if args.retain_all and not batch:
+    if motifs:
+        line["per_design"] = {k: dict(v, n_states=r.n_states) for (k, v), r in zip(line["per_design"].items(), results[-1])}
+    if args.retain_all and not batch and not motifs:
         # scalar-dense control (Sec. 8.1 / Table 3): same designs, every finite B retained
         dctx = sd.Context(0, retain_all=True)
         run_step(dctx, items, table, params, False)
@@ -367,7 +382,7 @@ def main():
                                         "visits_sparse": vs, "visits_dense": vd, "visit_ratio": vd / max(vs, 1),
                                         "identical_designs": True}
     if not args.no_cpu_baseline:
-        line["cpu_baseline"] = cpu_baseline(items)
+        line["cpu_baseline"] = cpu_baseline(items, motifs)
     print(json.dumps(line), flush=True)
 
 

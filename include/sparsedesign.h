@@ -49,7 +49,8 @@ typedef enum sd_status {
     SD_E_DEVICE = -8,       /* HIP error or no gfx950 device                             */
     SD_E_BUSY = -9,         /* server: request still running                             */
     SD_E_CANCELLED = -10,   /* server: request cancelled or server stopped               */
-    SD_E_INTERNAL = -11     /* self-check failed (should never happen)                   */
+    SD_E_INTERNAL = -11,    /* self-check failed (should never happen)                   */
+    SD_E_INFEASIBLE = -12   /* no coding sequence meets the constraints (forbidden motifs) */
 } sd_status;
 
 typedef struct sd_params sd_params;           /* opaque int32 energy tables (0.01 kcal/mol) */
@@ -150,6 +151,24 @@ sd_status sd_design_batch(sd_context *ctx, int n, const char *const *proteins,
 sd_status sd_lambda_envelope(sd_context *ctx, const char *protein, double lambda_lo, double lambda_hi,
                              int max_designs, const sd_codon_table *table, const sd_params *params,
                              sd_result *outs, double *breaks, int *n_out);
+
+/* One design under forbidden-motif constraints (Sec. 3: the codon automaton intersected with a
+ * deterministic matcher of the motifs keeps the layered path model; transitions that complete a
+ * motif are removed; the finite-state constraint experiments report the state growth).
+ * motifs: n_motifs (1..256) NUL-terminated strings of 1..32 bases over A, C, G, U; the returned
+ * mRNA contains none of them as a substring, in any frame and across codon boundaries.
+ * The product automaton keeps the pairs (codon state, matcher state) that lie on a path from
+ * the source to the last layer; layers may hold up to 16 states.  The fill runs in plain mode
+ * with a generic span kernel that reads minimum path costs from gap tables built on the device
+ * (the codon trie's closed form does not hold on the product).  The fixed-point shift is the
+ * unconstrained design's, so objectives of constrained and unconstrained designs compare
+ * exactly.  Errors as for sd_design, plus SD_E_ARG for a malformed motif list,
+ * SD_E_INFEASIBLE if every synonymous mRNA contains a motif, SD_E_RANGE if a layer of the
+ * product is wider than 16 states.  Candidate segments are sized for the worst case (the
+ * learned sizer is trained on unconstrained designs); sd_options.capacity_override applies. */
+sd_status sd_design_motifs(sd_context *ctx, const char *protein, const char *const *motifs,
+                           int n_motifs, const sd_codon_table *table, const sd_params *params,
+                           double lambda_kcal, sd_result *out);
 
 /* Test hook: the plain design plus its tables copied into caller buffers in a dense
  * state-pair layout [a*N + b] (V: [tau][a][b] with tau in AU,CG,GC,GU,UA,UG; entries with

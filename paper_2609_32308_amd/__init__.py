@@ -18,7 +18,8 @@ INF = 1 << 62
 
 STATUS = {0: "SD_OK", -1: "SD_E_ARG", -2: "SD_E_PROTEIN", -3: "SD_E_CODON_TABLE",
           -4: "SD_E_PARAMS", -5: "SD_E_LAMBDA", -6: "SD_E_RANGE", -7: "SD_E_NOMEM",
-          -8: "SD_E_DEVICE", -9: "SD_E_BUSY", -10: "SD_E_CANCELLED", -11: "SD_E_INTERNAL"}
+          -8: "SD_E_DEVICE", -9: "SD_E_BUSY", -10: "SD_E_CANCELLED", -11: "SD_E_INTERNAL",
+          -12: "SD_E_INFEASIBLE"}
 
 # every function declared in include/sparsedesign.h
 EXPORTS = [
@@ -29,7 +30,7 @@ EXPORTS = [
     "sd_sizer_get_params", "sd_sizer_set_params", "sd_sizer_gradient", "sd_sizer_train",
     "sd_sizer_predict", "sd_sizer_features", "sd_context_set_sizer", "sd_occupancy",
     "sd_server_start", "sd_server_submit", "sd_server_poll", "sd_server_wait", "sd_server_get_stats",
-    "sd_server_stop", "sd_lambda_envelope",
+    "sd_server_stop", "sd_lambda_envelope", "sd_design_motifs",
 ]
 
 
@@ -89,6 +90,8 @@ def lib():
         L.sd_context_create.argtypes = [C.c_int, C.POINTER(Options), C.POINTER(vp)]
         L.sd_context_destroy.argtypes = [vp]
         L.sd_design.argtypes = [vp, C.c_char_p, vp, vp, C.c_double, C.POINTER(_Result)]
+        L.sd_design_motifs.argtypes = [vp, C.c_char_p, C.POINTER(C.c_char_p), C.c_int, vp, vp, C.c_double,
+                                       C.POINTER(_Result)]
         L.sd_design_batch.argtypes = [vp, C.c_int, C.POINTER(C.c_char_p), C.POINTER(C.c_double),
                                       vp, vp, C.POINTER(_Result)]
         L.sd_design_tables.argtypes = [vp, C.c_char_p, vp, vp, C.c_double, C.POINTER(_Result),
@@ -222,6 +225,15 @@ class Context:
     def design(self, protein: str, table: CodonTable, params: Params, lam: float) -> Result:
         r = _Result()
         _check(lib().sd_design(self.h, protein.encode(), table.h, params.h, float(lam), C.byref(r)), "sd_design")
+        return _convert(r)
+
+    def design_motifs(self, protein: str, motifs, table: CodonTable, params: Params, lam: float) -> Result:
+        """Design whose mRNA contains none of the motifs (strings over ACGU)."""
+        m = list(motifs)
+        arr = (C.c_char_p * max(len(m), 1))(*[x.encode() for x in m])
+        r = _Result()
+        _check(lib().sd_design_motifs(self.h, protein.encode(), arr, len(m), table.h, params.h, float(lam),
+                                      C.byref(r)), "sd_design_motifs")
         return _convert(r)
 
     def design_batch(self, proteins, lambdas, table: CodonTable, params: Params):

@@ -56,6 +56,7 @@ extern "C" const char* sd_status_str(sd_status s) {
         case SD_E_BUSY: return "busy";
         case SD_E_CANCELLED: return "cancelled";
         case SD_E_INTERNAL: return "internal error";
+        case SD_E_INFEASIBLE: return "no coding sequence meets the constraints";
     }
     return "unknown status";
 }
@@ -246,6 +247,8 @@ InstLayout layout_instance(const Lattice& L, char* A, char* B, Inst& I) {
     I.mlbase_fx = L.mlbase_fx;
     I.retain_all = 0;
     I.g0 = 1;
+    I.gwin = L.generic ? L.gwin : 0;
+    I.wmax = L.wmax;
     // extents against slots (units of U in region A, of R in region B)
     struct Ext { const void* p; int64_t bytes; int64_t slot; };
     const int64_t U = I.U, R = I.R();
@@ -390,7 +393,10 @@ sd_status run_plain(sd_context* c, const Lattice& L, Inst& I, int64_t* overflow_
     }
     for (int g = 1; g <= L.n && e == hipSuccess; g++) {
         if (timing) e = hipEventRecord(c->tev[2 * (g - 1)], st);
-        if (e == hipSuccess)
+        if (e == hipSuccess && L.generic)
+            e = launch_span_gen(I, (const EnergyTables*)c->E_dev, (const int32_t*)c->spec_dev, g,
+                                g >= 2 ? L.n - g + 1 : -1, st);
+        else if (e == hipSuccess)
             e = launch_span(I, (const EnergyTables*)c->E_dev, (const int32_t*)c->spec_dev, g,
                             g >= 2 ? L.n - g + 1 : -1, span_threads_for(c, L.n - g + 1), st);
         if (timing && e == hipSuccess) e = hipEventRecord(c->tev[2 * (g - 1) + 1], st);
@@ -416,14 +422,15 @@ sd_status run_plain(sd_context* c, const Lattice& L, Inst& I, int64_t* overflow_
 
 sd_status design_plain(sd_context* c, const char* protein, const sd_codon_table* table,
                        const sd_params* params, double lambda, sd_result* out, TraceTables* keep,
-                       Lattice* keepL);
+                       Lattice* keepL, const std::vector<std::string>* motifs);
 
 // Download the tables the traceback reads.  By default into the context's pinned buffer (grown
 // on demand, no host zeroing, DMA at full link speed; valid until the next download on this
 // context); with own_storage into host memory owned by T (for results traced back later).
 size_t table_bytes(const Lattice& L) {
     const size_t cells = (size_t)L.cells, N = (size_t)L.N, slots = (size_t)L.cand_slots;
-    return cells * 72 + N * 8 + ((N * 4 + 7) & ~(size_t)7) + slots * 4;
+    return cells * 72 + N * 8 + ((N * 4 + 7) & ~(size_t)7) + ((slots * 4 + 7) & ~(size_t)7) +
+           (L.generic ? cells * 8 : 0);
 }
 
 sd_status fetch_tables(sd_context* c, const Lattice& L, const Inst& I, TraceTables& T, bool own_storage,
@@ -463,6 +470,7 @@ sd_status fetch_tables(sd_context* c, const Lattice& L, const Inst& I, TraceTabl
     int64_t* X = S2 + cells;
     int* ccnt = (int*)(X + N);
     int* cc = (int*)((char*)ccnt + ((N * 4 + 7) & ~(size_t)7));
+    int64_t* G = L.generic ? (int64_t*)((char*)cc + ((slots * 4 + 7) & ~(size_t)7)) : nullptr;
     hipError_t e = hipMemcpyAsync(V, I.V(), cells * 48, hipMemcpyDeviceToHost, st);
     if (e == hipSuccess) e = hipMemcpyAsync(B, I.Bt(), cells * 8, hipMemcpyDeviceToHost, st);
     if (e == hipSuccess) e = hipMemcpyAsync(S1, I.S1(), cells * 8, hipMemcpyDeviceToHost, st);
@@ -470,6 +478,7 @@ sd_status fetch_tables(sd_context* c, const Lattice& L, const Inst& I, TraceTabl
     if (e == hipSuccess) e = hipMemcpyAsync(X, I.X(), N * 8, hipMemcpyDeviceToHost, st);
     if (e == hipSuccess) e = hipMemcpyAsync(ccnt, I.ccnt(), N * 4, hipMemcpyDeviceToHost, st);
     if (e == hipSuccess && slots) e = hipMemcpyAsync(cc, I.cc(), slots * 4, hipMemcpyDeviceToHost, st);
+    if (e == hipSuccess && G) e = hipMemcpyAsync(G, I.Gt(), cells * 8, hipMemcpyDeviceToHost, st);
     if (e == hipSuccess) e = hipStreamSynchronize(st);
     if (e != hipSuccess) return hip_fail(e, "table download");
     T.V = V;
@@ -479,6 +488,7 @@ sd_status fetch_tables(sd_context* c, const Lattice& L, const Inst& I, TraceTabl
     T.X = X;
     T.ccnt = ccnt;
     T.cc = cc;
+    T.G = G;
     return SD_OK;
 }
 
@@ -559,7 +569,7 @@ void occupancy_bins(const Lattice& L, const TraceTables& T, int K, float* y) {
 // One plain design; optionally keeps the downloaded tables.
 sd_status design_plain(sd_context* c, const char* protein, const sd_codon_table* table,
                        const sd_params* params, double lambda, sd_result* out, TraceTables* keep,
-                       Lattice* keepL) {
+                       Lattice* keepL, const std::vector<std::string>* motifs) {
     const double t0 = now_s();
     if (!c || !table || !params || !out) return fail(SD_E_ARG, "null argument");
     hipError_t he = hipSetDevice(c->device);
@@ -567,7 +577,17 @@ sd_status design_plain(sd_context* c, const char* protein, const sd_codon_table*
     Lattice L;
     std::string err;
     std::vector<float> frac;
-    int rc = build_lattice(protein, table->t, params->p, lambda, policy_for(c, protein, lambda, frac), L, err);
+    CapPolicy cp0;
+    if (!motifs) {
+        cp0 = policy_for(c, protein, lambda, frac);
+    } else if (c->opt.capacity_override > 0 && !c->force_worst) {
+        cp0.override_slots = c->opt.capacity_override;  // the sizer knows unconstrained lattices only
+    }
+    auto build = [&](const CapPolicy& cp) {
+        return motifs ? build_motif_lattice(protein, table->t, params->p, lambda, cp, *motifs, L, err)
+                      : build_lattice(protein, table->t, params->p, lambda, cp, L, err);
+    };
+    int rc = build(cp0);
     if (rc) return fail((sd_status)rc, err);
     sd_status s = ensure_params(c, params);
     if (s) return s;
@@ -588,13 +608,14 @@ sd_status design_plain(sd_context* c, const char* protein, const sd_codon_table*
         if (attempt == 1) return fail(SD_E_INTERNAL, "candidate overflow with worst-case capacity");
         c->last_overflow_span = ovf;
         overflowed = 1;
-        rc = build_lattice(protein, table->t, params->p, lambda, CapPolicy(), L, err);
+        rc = build(CapPolicy());
         if (rc) return fail((sd_status)rc, err);
     }
     const double tf1 = now_s();
     TraceTables T;
     s = fetch_tables(c, L, I, T);
     if (s) return s;
+    L.gtab = T.G;
     TraceResult R;
     rc = trace_design(L, params->p, T, R);
     if (rc) return fail((sd_status)rc, "traceback self-check failed");
@@ -625,7 +646,25 @@ sd_status design_plain(sd_context* c, const char* protein, const sd_codon_table*
 extern "C" sd_status sd_design(sd_context* ctx, const char* protein, const sd_codon_table* table,
                                const sd_params* params, double lambda_kcal, sd_result* out) {
     try {
-        return design_plain(ctx, protein, table, params, lambda_kcal, out, nullptr, nullptr);
+        return design_plain(ctx, protein, table, params, lambda_kcal, out, nullptr, nullptr, nullptr);
+    } catch (const std::bad_alloc&) {
+        return fail(SD_E_NOMEM, "host allocation");
+    } catch (...) {
+        return fail(SD_E_INTERNAL, "unexpected exception");
+    }
+}
+
+extern "C" sd_status sd_design_motifs(sd_context* ctx, const char* protein, const char* const* motifs,
+                                      int n_motifs, const sd_codon_table* table, const sd_params* params,
+                                      double lambda_kcal, sd_result* out) {
+    try {
+        if (!motifs || n_motifs < 1 || n_motifs > kMaxMotifs) return fail(SD_E_ARG, "need 1 to 256 motifs");
+        std::vector<std::string> ms;
+        for (int i = 0; i < n_motifs; i++) {
+            if (!motifs[i]) return fail(SD_E_ARG, "null motif");
+            ms.push_back(motifs[i]);
+        }
+        return design_plain(ctx, protein, table, params, lambda_kcal, out, nullptr, nullptr, &ms);
     } catch (const std::bad_alloc&) {
         return fail(SD_E_NOMEM, "host allocation");
     } catch (...) {
@@ -656,7 +695,7 @@ extern "C" sd_status sd_design_tables(sd_context* ctx, const char* protein, cons
     try {
         TraceTables T;
         Lattice L;
-        sd_status s = design_plain(ctx, protein, table, params, lambda_kcal, out, &T, &L);
+        sd_status s = design_plain(ctx, protein, table, params, lambda_kcal, out, &T, &L, nullptr);
         if (s) return s;
         const size_t N = L.N;
         auto dense = [&](int64_t* dst, const int64_t* src, int stride, int t) {
@@ -899,7 +938,7 @@ extern "C" sd_status sd_design_batch(sd_context* ctx, int n, const char* const* 
                     Lattice L2;
                     const int fw = ctx->force_worst;
                     ctx->force_worst = 1;
-                    s = design_plain(ctx, proteins[gi], table, params, lambdas[gi], &outs[gi], &T2, &L2);
+                    s = design_plain(ctx, proteins[gi], table, params, lambdas[gi], &outs[gi], &T2, &L2, nullptr);
                     ctx->force_worst = fw;
                     ctx->last_batch_fallbacks++;
                     if (!s) {

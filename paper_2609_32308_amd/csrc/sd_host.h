@@ -32,6 +32,6 @@ sd_status fill_result(const Lattice& L, const TraceResult& R, int64_t xs, int64_
                       int64_t feasible, sd_result* out);
 sd_status design_plain(sd_context* c, const char* protein, const sd_codon_table* table,
                        const sd_params* params, double lambda, sd_result* out, TraceTables* keep,
-                       Lattice* keepL);
+                       Lattice* keepL, const std::vector<std::string>* motifs = nullptr);
 CapPolicy policy_for(const sd_context* c, const char* protein, double lambda, std::vector<float>& frac);
 }  // namespace sd

@@ -58,7 +58,10 @@ constexpr int kSpecOff5 = 0, kSpecOff6 = 1024, kSpecOff8 = 1024 + 4096, kSpecSiz
 //         bwd_cost[nB], fwd_crow[nF] (each start 8-byte aligned)
 // Region B (DP tables) is cut into ring units of R = 512 * N bytes (N states x 64 spans x 8 B):
 //   0-1 LM  2-13 IDL  14-25 JDL  26 BI  27 BJ  28-43 RS  44-59 LS  60-61 MINI, then from 62 R:
-//   V[cells][6], Bt[cells], S1[cells], S2[cells], cc[slots], cB[slots].
+//   V[cells][6], Bt[cells], S1[cells], S2[cells], cc[slots], cB[slots], and for generic lattices
+//   G[cells] (minimum path cost a -> b) and LG[state][gwin][4][4] (minimum cost of a path u -> v
+//   of 1..30 edges with first label x and last label y; v indexed from the first state of the
+//   layer after u's).
 // Meaning of the arrays:
 //   layer/off: layer of a state, first state of a layer; out_dst/out_U: out-edge by label
 //   (-1 / cost); in_start/in_src/in_lab/in_U: in-edges (CSR, sorted by source and label);
@@ -94,6 +97,8 @@ struct Inst {
     int n, N, A, shift;
     int retain_all;
     int g0;  // persistent launches: first span this launch processes for the instance
+    int gwin;  // generic lattices: states in the 30 layers after any layer (0 for the codon trie)
+    int wmax;  // widest layer
 
     __host__ __device__ static int64_t al8(int64_t x) { return (x + 7) & ~(int64_t)7; }
     __host__ __device__ char* ua(int k) const { return ra + (int64_t)k * U; }
@@ -156,11 +161,18 @@ struct Inst {
     __host__ __device__ int64_t* S2() const { return (int64_t*)(ub(62) + 64 * cells); }
     __host__ __device__ int* cc() const { return (int*)(ub(62) + 72 * cells); }
     __host__ __device__ int64_t* cB() const { return (int64_t*)(ub(62) + 72 * cells + al8(4 * slots)); }
-    __host__ __device__ int64_t b_bytes() const { return 62 * R() + 72 * cells + al8(4 * slots) + 8 * slots; }
+    // generic lattices only: gap table G[cells] and labelled gap table LG[N][gwin][16]
+    __host__ __device__ int64_t* Gt() const { return (int64_t*)(ub(62) + 72 * cells + al8(4 * slots) + 8 * slots); }
+    __host__ __device__ int64_t* LG() const { return Gt() + cells; }
+    __host__ __device__ int64_t b_bytes() const {
+        return 62 * R() + 72 * cells + al8(4 * slots) + 8 * slots + (gwin ? 8 * cells + 128 * (int64_t)N * gwin : 0);
+    }
 };
 
 constexpr int kLMRing = 64;
 constexpr int kMaxWidth = 4;  // states per layer (the lattice build rejects wider layers)
+constexpr int kGenMaxWidth = 16;  // states per layer of a generic (motif-constrained) lattice
+constexpr int kGenLoopWin = 30;   // layer distances covered by the labelled gap table
 constexpr int kMaxWaves = 16;  // waves per workgroup of the span-step kernels (1024 threads)
 static_assert(sizeof(Inst) % 8 == 0, "instance descriptors are copied as 8-byte words");
 

@@ -898,7 +898,7 @@ __global__ void k_init(Inst I) {
     const int tid = blockIdx.x * blockDim.x + threadIdx.x, nt = gridDim.x * blockDim.x;
     for (int i = tid; i < I.N; i += nt) {
         I.ccnt()[i] = 0;
-        I.X()[i] = (i == I.N - 1) ? 0 : kINF;
+        I.X()[i] = I.layer()[i] == I.n ? 0 : kINF;  // every state of the last layer is a sink
     }
     for (size_t i = tid; i < (size_t)(I.n + 1) * 2 * kLMRing; i += nt) I.LM()[i] = kINF;
     for (size_t i = tid; i < (size_t)I.N * kLMRing * 12; i += nt) {
@@ -918,6 +918,370 @@ __global__ void k_init(Inst I) {
         I.visits()[i] = 0;
         I.feasible()[i] = 0;
     }
+}
+
+// ---- generic lattice: the codon automaton intersected with a forbidden-motif matcher --------------
+// Nothing below relies on the codon trie.  Minimum path costs come from two tables that the span
+// step fills for its own cells and that later spans read:
+//   G(a, b)        minimum path cost a -> b (cell layout);
+//   LG(u, v, x, y) minimum cost of a path u -> v whose first edge is labelled x and last edge y,
+//                  for layer distances 1..30 (the unpaired segments of a two-loop).
+// A generic interior loop couples its segments only through the four bases next to the two
+// pairs (outer mismatch: x_{i+1}, x_{j-1}; inner mismatch: x_{l+1}, x_{k-1}), so for an inner
+// cell (c, d) the minimum over those bases is a min-plus product over a 4-cycle: eliminate x_{j-1}
+// with the right segment and the outer mismatch, x_{k-1} with the left segment and the inner
+// mismatch, then take the minimum over (x_{i+1}, x_{l+1}).  Loops with both sides of <= 2 bases
+// (the 1x1, 1x2, 2x2 tables) enumerate all boundary bases.
+constexpr int kGenParts = 4;  // per (cell, type): part 0 hairpin, stack, bulges, multiloop; 1..3 interior
+
+template <class IT>
+__device__ __forceinline__ int64_t gen_gap(const IT& I, int a, int la, int b, int lb) {
+    if (la == lb) return a == b ? 0 : kINF;
+    return I.Gt()[I.rowoff()[a] + (b - I.off()[la + 1])];
+}
+template <class IT>
+__device__ __forceinline__ const int64_t* gen_lg(const IT& I, int u, int lu, int v) {
+    return I.LG() + ((int64_t)u * I.gwin + (v - I.off()[lu + 1])) * 16;
+}
+
+struct GenShared {
+    int64_t vbuf[kGenMaxWidth * kGenMaxWidth][6];
+    int64_t cellB[kGenMaxWidth * kGenMaxWidth];
+    int keep[kGenMaxWidth * kGenMaxWidth];
+    int combo[kGenMaxWidth * kGenMaxWidth * 6];
+    int ncombo;
+};
+
+// interior loop (l1, l2 >= 1) closed by type t around inner cell values vin[6], with the left
+// and right segment tables L = LG(a1, c), R = LG(d, b1)
+__device__ int64_t gen_interior(const SmallE& S, const EnergyTables* __restrict__ E, int t, int l1, int l2,
+                                const int64_t* __restrict__ Lp, const int64_t* __restrict__ Rp,
+                                const int64_t vin[6], int s) {
+    int64_t best = kINF;
+    if (l1 <= 2 && l2 <= 2) {
+        for (int i = 0; i < 16; i++) {
+            const int64_t li = Lp[i];
+            if (li >= kINF) continue;
+            for (int j = 0; j < 16; j++) {
+                const int64_t rj = Rp[j];
+                if (rj >= kINF) continue;
+#pragma unroll
+                for (int tp = 0; tp < 6; tp++) {
+                    if (vin[tp] >= kINF) continue;
+                    const int32_t e2 = interior_e(S, E, t, kRev[tp], l1, l2, i >> 2, i & 3, j >> 2, j & 3);
+                    best = mn(best, li + rj + vin[tp] + fx(e2, s));
+                }
+            }
+        }
+        return best;
+    }
+    const int X = mm_class(l1, l2);
+    // T2[xl][xi] = min over xj of R[xl][xj] + mm_X[t][xi][xj]
+    int64_t T2[16];
+#pragma unroll
+    for (int k = 0; k < 16; k++) {
+        const int xl = k >> 2, xi = k & 3;
+        int64_t acc = kINF;
+#pragma unroll
+        for (int xj = 0; xj < 4; xj++) {
+            const int64_t r = Rp[xl * 4 + xj];
+            if (r < kINF) acc = mn(acc, r + fx(mmx(S, X, t, xi, xj), s));
+        }
+        T2[k] = acc;
+    }
+    for (int tp = 0; tp < 6; tp++) {
+        if (vin[tp] >= kINF) continue;
+        const int tr = kRev[tp];
+        for (int xi = 0; xi < 4; xi++)
+            for (int xl = 0; xl < 4; xl++) {
+                const int64_t t2 = T2[xl * 4 + xi];
+                if (t2 >= kINF) continue;
+                int64_t t1 = kINF;  // min over xk of L[xi][xk] + mm_X[tr][xl][xk]
+#pragma unroll
+                for (int xk = 0; xk < 4; xk++) {
+                    const int64_t l = Lp[xi * 4 + xk];
+                    if (l < kINF) t1 = mn(t1, l + fx(mmx(S, X, tr, xl, xk), s));
+                }
+                if (t1 < kINF) best = mn(best, t1 + t2 + vin[tp]);
+            }
+    }
+    return best >= kINF ? kINF : best + fx(interior_base(S, l1, l2), s);
+}
+
+// One part of V_t(a, b) on a generic lattice, with the lanes of one wave (min over lanes).
+template <class IT>
+__device__ int64_t gen_closed_part(const IT& I, const SmallE& S, const EnergyTables* __restrict__ E,
+                                   const int32_t* __restrict__ spec, int a, int b, int t, int p, int q,
+                                   int part, int lane) {
+    const int g = q - p, s = I.shift;
+    const int a1 = I.out_dst()[a * 4 + kTX[t]];
+    const int64_t Ua = I.out_U()[a * 4 + kTX[t]];
+    const int y = kTY[t];
+    const int ib0 = I.in_start()[b], ib1 = I.in_start()[b + 1];
+    int64_t v = kINF;
+    if (part == 0) {
+        const int m = g - 2;
+        if (m == 3 || m == 4 || m == 6) {
+            v = hairpin_lane(I, S, spec, a, b, t, a1, Ua, p, g, lane);  // path enumeration only
+        } else if (m >= 5) {
+            // a -x-> a1 -x2-> a2 ~~> b2 -z-> b1 -y-> b: lanes over (x2, in-edge of b1)
+            for (int eb = ib0; eb < ib1; eb++) {
+                if (I.in_lab()[eb] != y) continue;
+                const int b1 = I.in_src()[eb];
+                const int j0 = I.in_start()[b1], nj = I.in_start()[b1 + 1] - j0;
+                for (int k = lane; k < 4 * nj; k += 64) {
+                    const int x2 = k & 3, j = j0 + (k >> 2);
+                    const int a2 = I.out_dst()[a1 * 4 + x2];
+                    if (a2 < 0) continue;
+                    const int64_t gg = gen_gap(I, a2, p + 2, I.in_src()[j], q - 2);
+                    if (gg >= kINF) continue;
+                    v = mn(v, Ua + I.out_U()[a1 * 4 + x2] + gg + I.in_U()[j] + I.in_U()[eb] +
+                                  fx(I.hp_init()[m] + S.mmH[t][x2][I.in_lab()[j]], s));
+                }
+            }
+        }
+        if (g >= 7) {
+            // stack (item 0), left bulges (inner c of layer p+1+l, d = b1), right bulges (c = a1,
+            // inner d of layer q-1-l); inner span >= 5 and l <= 30
+            const int cl_hi = min(p + 31, q - 6), dl_lo = max(q - 31, p + 6);
+            const int c0 = I.off()[p + 2], c1 = cl_hi >= p + 2 ? I.off()[cl_hi + 1] : c0;
+            const int d1 = I.off()[q - 1], d0 = dl_lo <= q - 2 ? I.off()[dl_lo] : d1;
+            const int nc = c1 - c0, nd = d1 - d0;
+            for (int eb = ib0; eb < ib1; eb++) {
+                if (I.in_lab()[eb] != y) continue;
+                const int b1 = I.in_src()[eb];
+                const int64_t Uab = Ua + I.in_U()[eb];
+                for (int k = lane; k < 1 + nc + nd; k += 64) {
+                    int c = a1, d = b1, lc = p + 1, l = 0;
+                    int64_t gl = 0;
+                    if (k >= 1 && k <= nc) {
+                        c = c0 + k - 1;
+                        lc = I.layer()[c];
+                        l = lc - (p + 1);
+                        gl = gen_gap(I, a1, p + 1, c, lc);
+                    } else if (k > nc) {
+                        d = d0 + k - 1 - nc;
+                        const int ld = I.layer()[d];
+                        l = (q - 1) - ld;
+                        gl = gen_gap(I, d, ld, b1, q - 1);
+                    }
+                    if (gl >= kINF) continue;
+                    const int64_t* vv = I.V() + (I.rowoff()[c] - I.off()[lc + 1] + d) * 6;
+#pragma unroll
+                    for (int tp = 0; tp < 6; tp++) {
+                        const int64_t vin = vv[tp];
+                        if (vin >= kINF) continue;
+                        const int32_t e2 = l == 0 ? S.stack[t][kRev[tp]] : bulge_e(S, t, kRev[tp], l);
+                        v = mn(v, Uab + gl + vin + fx(e2, s));
+                    }
+                }
+            }
+        }
+        if (g >= 12) {
+            // multiloop closure (ML_closing + ML_intern + AU) + S2 of the interior
+            const int32_t mlc = S.ml_closing + S.ml_intern + au_pen(S, t);
+            for (int eb = ib0 + lane; eb < ib1; eb += 64) {
+                if (I.in_lab()[eb] != y) continue;
+                const int b1 = I.in_src()[eb];
+                if (I.layer()[b1] - (p + 1) < 10) continue;
+                v = mn(v, I.S2()[cell_of(I, a1, b1)] + Ua + I.in_U()[eb] + fx(mlc, s));
+            }
+        }
+    } else if (g >= 9) {
+        // interior loops with l1 = part, part + 3, ...: the inner left state c runs over the
+        // layer of l1, the lanes over every inner right state d with 1 <= l2 <= 30 - l1 and
+        // inner span >= 5 (one contiguous state range)
+        for (int eb = ib0; eb < ib1; eb++) {
+            if (I.in_lab()[eb] != y) continue;
+            const int b1 = I.in_src()[eb];
+            const int64_t Uab = Ua + I.in_U()[eb];
+            for (int l1 = part; l1 <= kGenLoopWin - 1; l1 += kGenParts - 1) {
+                const int lc = p + 1 + l1;
+                const int dl_lo = max(q - 1 - (kGenLoopWin - l1), lc + 5), dl_hi = q - 2;
+                if (dl_lo > dl_hi) break;
+                const int d0 = I.off()[dl_lo], d1 = I.off()[dl_hi + 1];
+                for (int c = I.off()[lc]; c < I.off()[lc + 1]; c++) {
+                    const int64_t* lgl = gen_lg(I, a1, p + 1, c);
+                    const int64_t crow = I.rowoff()[c] - I.off()[lc + 1];
+                    for (int d = d0 + lane; d < d1; d += 64) {
+                        const int64_t* vv = I.V() + (crow + d) * 6;
+                        int64_t vin[6];
+                        bool any = false;
+#pragma unroll
+                        for (int tp = 0; tp < 6; tp++) {
+                            vin[tp] = vv[tp];
+                            any = any || vin[tp] < kINF;
+                        }
+                        if (!any) continue;
+                        const int ld = I.layer()[d];
+                        const int64_t w = gen_interior(S, E, t, l1, q - 1 - ld, lgl, gen_lg(I, d, ld, b1), vin, s);
+                        if (w < kINF) v = mn(v, Uab + w);
+                    }
+                }
+            }
+        }
+    }
+    return norm_inf(wave_min(v));
+}
+
+template <int NW, class IT>
+__device__ GroupCounters gen_span_group(const IT& I, const SmallE& S, const EnergyTables* __restrict__ E,
+                                        const int32_t* __restrict__ spec, int p, int q, GenShared& G) {
+    const int g = q - p, s = I.shift;
+    const int tid = threadIdx.x, wave = tid >> 6, lane = tid & 63, nw = blockDim.x >> 6;
+    GroupCounters ctr{0, 0, 0};
+    const int a_lo = I.off()[p], a_hi = I.off()[p + 1], b_lo = I.off()[q], b_hi = I.off()[q + 1];
+    const int wa = a_hi - a_lo, wb = b_hi - b_lo, ncell = wa * wb;
+    // gap tables of this span's cells (only later spans read them)
+    for (int ci = tid; ci < ncell; ci += blockDim.x) {
+        const int a = a_lo + ci / wb, b = b_lo + ci % wb;
+        int64_t gv = kINF;
+        for (int eb = I.in_start()[b]; eb < I.in_start()[b + 1]; eb++) {
+            const int bp = I.in_src()[eb];
+            const int64_t gp = g == 1 ? (bp == a ? 0 : kINF) : I.Gt()[cell_of(I, a, bp)];
+            if (gp < kINF) gv = mn(gv, gp + I.in_U()[eb]);
+        }
+        I.Gt()[cell_of(I, a, b)] = gv;
+    }
+    if (g <= kGenLoopWin) {
+        for (int k = tid; k < ncell * 16; k += blockDim.x) {
+            const int ci = k >> 4, x = (k >> 2) & 3, yy = k & 3;
+            const int a = a_lo + ci / wb, b = b_lo + ci % wb;
+            const int u1 = I.out_dst()[a * 4 + x];
+            int64_t lv = kINF;
+            if (u1 >= 0) {
+                if (g == 1) {
+                    if (u1 == b && x == yy) lv = I.out_U()[a * 4 + x];
+                } else {
+                    for (int eb = I.in_start()[b]; eb < I.in_start()[b + 1]; eb++) {
+                        if (I.in_lab()[eb] != yy) continue;
+                        const int v1 = I.in_src()[eb];
+                        const int64_t gg = g == 2 ? (u1 == v1 ? 0 : kINF) : I.Gt()[cell_of(I, u1, v1)];
+                        if (gg < kINF) lv = mn(lv, I.out_U()[a * 4 + x] + gg + I.in_U()[eb]);
+                    }
+                }
+            }
+            I.LG()[((int64_t)a * I.gwin + (b - I.off()[p + 1])) * 16 + x * 4 + yy] = lv;
+        }
+    }
+    // (cell, type) jobs as in the trie kernel
+    if (wave == 0) {
+        int base = 0;
+        for (int k0 = 0; k0 < ncell * 6; k0 += 64) {
+            const int k = k0 + lane;
+            bool job = false;
+            if (k < ncell * 6) {
+                const int ci = k / 6, t = k - 6 * ci;
+                G.vbuf[ci][t] = kINF;
+                job = g >= 5 && I.out_dst()[(a_lo + ci / wb) * 4 + kTX[t]] >= 0 &&
+                      ((I.inmask()[b_lo + ci % wb] >> kTY[t]) & 1);
+            }
+            const unsigned long long m = __ballot(job);
+            if (job) G.combo[base + __popcll(m & ((1ull << lane) - 1ull))] = k;
+            base += __popcll(m);
+        }
+        if (lane == 0) G.ncombo = base;
+    }
+    __syncthreads();
+    const int njobs = kGenParts * G.ncombo;
+    for (int k = wave; k < njobs; k += nw) {
+        const int cmb = G.combo[k / kGenParts], ci = cmb / 6, t = cmb - 6 * ci;
+        const int a = a_lo + ci / wb, b = b_lo + ci % wb;
+        const int64_t v = gen_closed_part(I, S, E, spec, a, b, t, p, q, k % kGenParts, lane);
+        if (lane == 0 && v < kINF)
+            __hip_atomic_fetch_min(&G.vbuf[ci][t], v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
+    }
+    __syncthreads();
+    // branch value, S2 (eq. 7), P_S, S1 and the retention test, one cell per wave
+    for (int ci = wave; ci < ncell; ci += nw) {
+        const int a = a_lo + ci / wb, b = b_lo + ci % wb;
+        const int64_t cell = I.rowoff()[a] + (b - I.off()[p + 1]);
+        int64_t Bv = kINF;
+        for (int t = 0; t < 6; t++) {
+            const int64_t v = G.vbuf[ci][t];
+            if (lane == t) I.V()[cell * 6 + t] = v;
+            if (v < kINF) Bv = mn(Bv, v + fx(S.ml_intern + au_pen(S, t), s));
+        }
+        const int committed = I.ccnt()[b];
+        const int64_t cbase = I.coff()[b];
+        const int ib0 = I.in_start()[b], ib1 = I.in_start()[b + 1];
+        int64_t s2 = kINF;
+        for (int eb = ib0 + lane; eb < ib1; eb += 64) {
+            const int bp = I.in_src()[eb];
+            if (I.layer()[bp] > p) s2 = mn(s2, I.S2()[cell_of(I, a, bp)] + I.in_U()[eb] + I.mlbase_fx);
+        }
+        const int64_t arow = I.rowoff()[a] - I.off()[p + 1];
+        for (int k = lane; k < committed; k += 64) {
+            const int c = I.cc()[cbase + k] & 0x7fffffff;
+            s2 = mn(s2, I.S1()[arow + c] + I.cB()[cbase + k]);
+        }
+        s2 = norm_inf(wave_min(s2));
+        int64_t ps = s2;
+        if (lane < 4) {
+            const int ap = I.out_dst()[a * 4 + lane];
+            if (ap >= 0 && I.layer()[ap] < q)
+                ps = mn(ps, I.S1()[cell_of(I, ap, b)] + I.out_U()[a * 4 + lane] + I.mlbase_fx);
+        }
+        for (int eb = ib0 + lane; eb < ib1; eb += 64) {
+            const int bp = I.in_src()[eb];
+            if (I.layer()[bp] > p) ps = mn(ps, I.S1()[cell_of(I, a, bp)] + I.in_U()[eb] + I.mlbase_fx);
+        }
+        ps = norm_inf(wave_min(ps));
+        if (lane == 0) {
+            I.Bt()[cell] = Bv;
+            I.S2()[cell] = s2;
+            I.S1()[cell] = mn(Bv, ps);
+            const bool strict = Bv < ps;
+            G.keep[ci] = I.retain_all ? (Bv < kINF ? (strict ? 1 : 2) : 0) : (strict ? 1 : 0);
+            G.cellB[ci] = Bv;
+        }
+        ctr.visits += (unsigned long long)committed;
+        ctr.feasible += Bv < kINF;
+    }
+    __syncthreads();
+    // appends in start-state order, one lane per right endpoint
+    if (wave == 0) {
+        int added = 0;
+        if (lane < wb) {
+            const int b = b_lo + lane;
+            const int committed = I.ccnt()[b];
+            for (int ia = 0; ia < wa; ia++) {
+                const int ci = ia * wb + lane;
+                if (!G.keep[ci]) continue;
+                const int slot = committed + added;
+                if (slot < I.ccap()[b]) {
+                    I.cc()[I.coff()[b] + slot] = (a_lo + ia) | (G.keep[ci] == 1 ? 0 : (int)0x80000000);
+                    I.cB()[I.coff()[b] + slot] = G.cellB[ci];
+                } else {
+                    atomicMin(&I.stats()[2], (unsigned long long)g);
+                }
+                added++;
+            }
+            if (added) I.ccnt()[b] = min(committed + added, I.ccap()[b]);
+        }
+        for (int m = 1; m < 64; m <<= 1) added += __shfl_xor(added, m, 64);
+        ctr.appends += (unsigned long long)added;
+    }
+    return ctr;
+}
+
+// span step on a generic lattice: layer pair xcd_band(x) for block x < layer pairs, then the
+// external column one layer behind
+__global__ __launch_bounds__(256) void k_span_gen(Inst I, const EnergyTables* __restrict__ E,
+                                                  const int32_t* __restrict__ spec, int g,
+                                                  int ext_layer, int nblk_cells) {
+    __shared__ SmallE S;
+    __shared__ int64_t red[256];
+    __shared__ GenShared G;
+    stage_tables(S, E);
+    __syncthreads();
+    if ((int)blockIdx.x >= nblk_cells) {
+        if (ext_layer >= 0) ext_column(I, S, ext_layer, red);
+        return;
+    }
+    const int p = xcd_band(blockIdx.x, nblk_cells), q = p + g;
+    GroupCounters c = gen_span_group<4>(I, S, E, spec, p, q, G);
+    flush_counters(I, c, p, threadIdx.x & 63);
 }
 
 // ---- batched persistent kernel ------------------------------------------------------------------
@@ -1072,7 +1436,7 @@ __global__ void k_batch_init(const Inst* __restrict__ insts, int ninst, BatchCtl
     if (I.g0 != 1) return;
     for (int i = tid; i < I.N; i += nt) {
         I.ccnt()[i] = 0;
-        I.X()[i] = (i == I.N - 1) ? 0 : kINF;
+        I.X()[i] = I.layer()[i] == I.n ? 0 : kINF;  // every state of the last layer is a sink
     }
     for (size_t i = tid; i < (size_t)(I.n + 1) * 2 * kLMRing; i += nt) I.LM()[i] = kINF;
     for (size_t i = tid; i < (size_t)I.N * kLMRing * 12; i += nt) {
@@ -1165,6 +1529,17 @@ hipError_t launch_span(const Inst& I, const EnergyTables* E, const int32_t* spec
     case 1024: hipLaunchKernelGGL(k_span<1024>, dim3(total), dim3(1024), 0, st, I, E, spec, g, ext_layer, nblk); break;
     default: return hipErrorInvalidValue;
     }
+    return hipGetLastError();
+}
+
+// one span step on a generic lattice (same grid as launch_span)
+hipError_t launch_span_gen(const Inst& I, const EnergyTables* E, const int32_t* spec, int g,
+                           int ext_layer, hipStream_t st) {
+    const int layers = I.n - g + 1;
+    const int nblk = layers > 0 ? layers : 0;
+    const int total = nblk + (ext_layer >= 0 ? 1 : 0);
+    if (total == 0) return hipSuccess;
+    hipLaunchKernelGGL(k_span_gen, dim3(total), dim3(256), 0, st, I, E, spec, g, ext_layer, nblk);
     return hipGetLastError();
 }
 

@@ -6,6 +6,7 @@
 #include <string.h>
 
 #include <algorithm>
+#include <map>
 #include <sstream>
 
 #include "../../include/sparsedesign.h"
@@ -247,6 +248,7 @@ int64_t host_gap(const Lattice& L, int a, int b) {
     int la = L.layer[a], lb = L.layer[b];
     if (la == lb) return a == b ? 0 : kINF;
     if (la > lb) return kINF;
+    if (L.generic) return L.gtab ? L.gtab[L.rowoff[a] + (b - L.off[la + 1])] : kINF;
     int ka = la / 3, kb = lb / 3;
     if (ka == kb) {
         if (la % 3 == 0) return 0;
@@ -259,6 +261,75 @@ int position_bin(int layer, int n, int K) {
     const int k = n > 0 ? (int)(((int64_t)layer * K) / (n + 1)) : 0;
     return k < K ? k : K - 1;
 }
+
+namespace {
+// in-edges sorted by (source, label), and the in-label mask of every state
+void index_in_edges(Lattice& L) {
+    const int N = L.N;
+    L.in_start.assign(N + 1, 0);
+    for (int u = 0; u < N; u++)
+        for (int x = 0; x < 4; x++)
+            if (L.out_dst[4 * u + x] >= 0) L.in_start[L.out_dst[4 * u + x] + 1]++;
+    for (int v = 0; v < N; v++) L.in_start[v + 1] += L.in_start[v];
+    const int nE = L.in_start[N];
+    L.in_src.assign(nE, 0);
+    L.in_lab.assign(nE, 0);
+    L.in_cod.assign(nE, -1);
+    L.in_U.assign(nE, 0);
+    std::vector<int> fill(N, 0);
+    for (int u = 0; u < N; u++)
+        for (int x = 0; x < 4; x++) {
+            int v = L.out_dst[4 * u + x];
+            if (v < 0) continue;
+            int j = L.in_start[v] + fill[v]++;
+            L.in_src[j] = u;
+            L.in_lab[j] = x;
+            L.in_cod[j] = L.out_cod[4 * u + x];
+            L.in_U[j] = L.out_U[4 * u + x];
+        }
+    L.inmask.assign(N, 0);
+    for (int v = 0; v < N; v++)
+        for (int j = L.in_start[v]; j < L.in_start[v + 1]; j++) L.inmask[v] |= 1 << L.in_lab[j];
+}
+
+// hairpin initiation per size, extrapolated above 30 (rounded half away from zero)
+void hairpin_init(Lattice& L, const Params& P) {
+    L.hp_init.assign(L.n + 1, kNoSpecial);
+    for (int m = 3; m <= L.n; m++)
+        L.hp_init[m] = m <= 30 ? P.E.hairpin[m]
+                               : P.E.hairpin[30] + (int32_t)lround(P.lxc * log((double)m / 30.0));
+}
+
+// row layout of the cell tables and the candidate segments (capacity per right endpoint)
+void layout_rows(Lattice& L, const CapPolicy& cp) {
+    const int N = L.N, n = L.n;
+    L.rowoff.assign(N, 0);
+    int64_t acc = 0;
+    for (int a = 0; a < N; a++) {
+        L.rowoff[a] = acc;
+        acc += N - L.off[L.layer[a] + 1];
+    }
+    L.cells = acc;
+    L.coff.assign(N, 0);
+    L.ccap.assign(N, 0);
+    acc = 0;
+    for (int b = 0; b < N; b++) {
+        int lb = L.layer[b];
+        int worst = lb >= 5 ? L.off[lb - 4] : 0;
+        int cap = worst;
+        if (cp.override_slots > 0) {
+            cap = std::min(worst, cp.override_slots);
+        } else if (cp.frac && cp.K > 0) {
+            const double f = std::min(1.0, (double)cp.frac[position_bin(lb, n, cp.K)] * (1.0 + cp.margin));
+            cap = std::min<int64_t>(worst, (int64_t)ceil(worst * f) + cp.slack);
+        }
+        L.coff[b] = acc;
+        L.ccap[b] = cap;
+        acc += cap;
+    }
+    L.cand_slots = acc;
+}
+}  // namespace
 
 int build_lattice(const char* protein, const CodonTable& T, const Params& P, double lambda,
                   const CapPolicy& cp, Lattice& L, std::string& err) {
@@ -362,28 +433,7 @@ int build_lattice(const char* protein, const CodonTable& T, const Params& P, dou
     L.out_U.assign((size_t)4 * N, 0);
     for (size_t e = 0; e < L.out_U.size(); e++)
         if (L.out_cod[e] >= 0) L.out_U[e] = llround(ldexp(lam100 * L.out_q[e], shift));
-    // in-edges sorted by (source, label)
-    L.in_start.assign(N + 1, 0);
-    for (int u = 0; u < N; u++)
-        for (int x = 0; x < 4; x++)
-            if (L.out_dst[4 * u + x] >= 0) L.in_start[L.out_dst[4 * u + x] + 1]++;
-    for (int v = 0; v < N; v++) L.in_start[v + 1] += L.in_start[v];
-    const int nE = L.in_start[N];
-    L.in_src.assign(nE, 0);
-    L.in_lab.assign(nE, 0);
-    L.in_cod.assign(nE, -1);
-    L.in_U.assign(nE, 0);
-    std::vector<int> fill(N, 0);
-    for (int u = 0; u < N; u++)
-        for (int x = 0; x < 4; x++) {
-            int v = L.out_dst[4 * u + x];
-            if (v < 0) continue;
-            int j = L.in_start[v] + fill[v]++;
-            L.in_src[j] = u;
-            L.in_lab[j] = x;
-            L.in_cod[j] = L.out_cod[4 * u + x];
-            L.in_U[j] = L.out_U[4 * u + x];
-        }
+    index_in_edges(L);
     // gap closed form: cheapest completion of the current codon, per-codon minima, prefix sums
     L.tail.assign(N, 0);
     L.P.assign(A + 1, 0);
@@ -414,9 +464,6 @@ int build_lattice(const char* protein, const CodonTable& T, const Params& P, dou
     for (int v = 0; v < N; v++)
         for (int j = L.in_start[v]; j < L.in_start[v + 1]; j++)
             L.betaU[4 * v + L.in_lab[j]] = std::min(L.betaU[4 * v + L.in_lab[j]], L.in_U[j]);
-    L.inmask.assign(N, 0);
-    for (int v = 0; v < N; v++)
-        for (int j = L.in_start[v]; j < L.in_start[v + 1]; j++) L.inmask[v] |= 1 << L.in_lab[j];
     // hairpin closing side: min over b2 -z-> b1 -y-> b of the two edge costs
     L.hpB.assign((size_t)16 * N, kINF);
     for (int v = 0; v < N; v++)
@@ -496,42 +543,166 @@ int build_lattice(const char* protein, const CodonTable& T, const Params& P, dou
             }
         }
     L.bwd_off[4 * N] = (int)L.bwd_meta.size();
-    // hairpin initiation per size, extrapolated above 30 (rounded half away from zero)
-    L.hp_init.assign(n + 1, kNoSpecial);
-    for (int m = 3; m <= n; m++)
-        L.hp_init[m] = m <= 30 ? P.E.hairpin[m]
-                               : P.E.hairpin[30] + (int32_t)lround(P.lxc * log((double)m / 30.0));
-    // row layout of cell tables and candidate segments
-    L.rowoff.assign(N, 0);
-    int64_t acc = 0;
-    for (int a = 0; a < N; a++) {
-        L.rowoff[a] = acc;
-        acc += N - L.off[L.layer[a] + 1];
-    }
-    L.cells = acc;
+    hairpin_init(L, P);
+    layout_rows(L, cp);
     L.fwd_crow.resize(L.fwd_meta.size());
     for (size_t e = 0; e < L.fwd_meta.size(); e++) {
         const int c = L.fwd_meta[e] >> 4;
         L.fwd_crow[e] = L.rowoff[c] - L.off[L.layer[c] + 1];
     }
-    L.coff.assign(N, 0);
-    L.ccap.assign(N, 0);
-    acc = 0;
-    for (int b = 0; b < N; b++) {
-        int lb = L.layer[b];
-        int worst = lb >= 5 ? L.off[lb - 4] : 0;
-        int cap = worst;
-        if (cp.override_slots > 0) {
-            cap = std::min(worst, cp.override_slots);
-        } else if (cp.frac && cp.K > 0) {
-            const double f = std::min(1.0, (double)cp.frac[position_bin(lb, n, cp.K)] * (1.0 + cp.margin));
-            cap = std::min<int64_t>(worst, (int64_t)ceil(worst * f) + cp.slack);
-        }
-        L.coff[b] = acc;
-        L.ccap[b] = cap;
-        acc += cap;
+    return SD_OK;
+}
+
+// ------------------------------------------------------------------------------------------------
+// Forbidden motifs (Sec. 3): the codon trie intersected with a deterministic motif matcher.
+// Matcher states are the distinct motif prefixes (the empty one included), ranked by length and
+// then lexicographically in A<C<G<U order; reading base x in prefix m goes to the longest suffix
+// of m.x that is a prefix, and is not allowed when a suffix of m.x is a whole motif.  Product
+// states are the (trie state, matcher state) pairs reachable from (source, empty prefix) that can
+// still reach the last layer, ordered by layer, then trie state, then matcher rank.
+// ------------------------------------------------------------------------------------------------
+int build_motif_lattice(const char* protein, const CodonTable& T, const Params& P, double lambda,
+                        const CapPolicy& cp, const std::vector<std::string>& motifs, Lattice& L,
+                        std::string& err) {
+    if (motifs.empty() || (int)motifs.size() > kMaxMotifs) {
+        err = "need 1 to 256 motifs";
+        return SD_E_ARG;
     }
-    L.cand_slots = acc;
+    for (const std::string& m : motifs) {
+        if (m.empty() || (int)m.size() > kMaxMotifLen || m.find_first_not_of("ACGU") != std::string::npos) {
+            err = "motifs are 1 to 32 bases over A, C, G, U";
+            return SD_E_ARG;
+        }
+    }
+    Lattice Tr;
+    int rc = build_lattice(protein, T, P, lambda, CapPolicy(), Tr, err);
+    if (rc) return rc;
+    // matcher
+    std::vector<std::string> pre{std::string()};
+    for (const std::string& m : motifs)
+        for (size_t l = 1; l <= m.size(); l++) pre.push_back(m.substr(0, l));
+    std::sort(pre.begin(), pre.end(), [](const std::string& a, const std::string& b) {
+        return a.size() != b.size() ? a.size() < b.size() : a < b;
+    });
+    pre.erase(std::unique(pre.begin(), pre.end()), pre.end());
+    const int K = (int)pre.size();
+    std::map<std::string, int> rank;
+    for (int i = 0; i < K; i++) rank[pre[i]] = i;
+    std::vector<int> step((size_t)4 * K, -1);
+    for (int m = 0; m < K; m++)
+        for (int x = 0; x < 4; x++) {
+            const std::string t = pre[m] + "ACGU"[x];
+            bool banned = false;
+            for (const std::string& w : motifs)
+                if (w.size() <= t.size() && t.compare(t.size() - w.size(), w.size(), w) == 0) banned = true;
+            if (banned) continue;
+            for (size_t k = 0; k <= t.size(); k++) {  // longest suffix first
+                auto it = rank.find(t.substr(k));
+                if (it != rank.end()) {
+                    step[(size_t)4 * m + x] = it->second;
+                    break;
+                }
+            }
+        }
+    // forward: reachable pairs per layer, sorted by (trie state, matcher rank)
+    const int n = Tr.n;
+    typedef std::pair<int, int> QM;
+    std::vector<std::vector<QM>> lay(n + 1);
+    lay[0].push_back(QM(0, 0));
+    for (int p = 0; p < n; p++) {
+        std::vector<QM>& nx = lay[p + 1];
+        for (const QM& s : lay[p])
+            for (int x = 0; x < 4; x++) {
+                const int d = Tr.out_dst[(size_t)4 * s.first + x], m2 = step[(size_t)4 * s.second + x];
+                if (d >= 0 && m2 >= 0) nx.push_back(QM(d, m2));
+            }
+        std::sort(nx.begin(), nx.end());
+        nx.erase(std::unique(nx.begin(), nx.end()), nx.end());
+    }
+    // backward: keep the pairs with a path to the last layer
+    auto succ = [&](int p, const QM& s, int x) -> int {  // index in lay[p+1] or -1
+        const int d = Tr.out_dst[(size_t)4 * s.first + x], m2 = step[(size_t)4 * s.second + x];
+        if (d < 0 || m2 < 0) return -1;
+        auto it = std::lower_bound(lay[p + 1].begin(), lay[p + 1].end(), QM(d, m2));
+        return (it != lay[p + 1].end() && *it == QM(d, m2)) ? (int)(it - lay[p + 1].begin()) : -1;
+    };
+    std::vector<std::vector<char>> live(n + 1);
+    live[n].assign(lay[n].size(), 1);
+    for (int p = n - 1; p >= 0; p--) {
+        live[p].assign(lay[p].size(), 0);
+        for (size_t i = 0; i < lay[p].size(); i++)
+            for (int x = 0; x < 4 && !live[p][i]; x++) {
+                const int j = succ(p, lay[p][i], x);
+                if (j >= 0 && live[p + 1][j]) live[p][i] = 1;
+            }
+    }
+    if (!live[0][0]) {
+        err = "no synonymous mRNA avoids every motif";
+        return SD_E_INFEASIBLE;
+    }
+    std::vector<std::vector<int>> id(n + 1);
+    L = Lattice();
+    L.protein = protein;
+    L.lambda = lambda;
+    L.A = Tr.A;
+    L.n = n;
+    L.shift = Tr.shift;
+    L.mlbase_fx = Tr.mlbase_fx;
+    L.off.assign(n + 2, 0);
+    int N = 0;
+    for (int p = 0; p <= n; p++) {
+        L.off[p] = N;
+        id[p].assign(lay[p].size(), -1);
+        for (size_t i = 0; i < lay[p].size(); i++)
+            if (live[p][i]) {
+                id[p][i] = N++;
+                L.layer.push_back(p);
+            }
+        if (N - L.off[p] > kGenMaxWidth) {
+            err = "motif automaton layer wider than 16 states";
+            return SD_E_RANGE;
+        }
+        L.wmax = std::max(L.wmax, N - L.off[p]);
+    }
+    L.off[n + 1] = N;
+    L.N = N;
+    L.out_dst.assign((size_t)4 * N, -1);
+    L.out_cod.assign((size_t)4 * N, -1);
+    L.out_q.assign((size_t)4 * N, 0.0);
+    L.out_U.assign((size_t)4 * N, 0);
+    for (int p = 0; p < n; p++)
+        for (size_t i = 0; i < lay[p].size(); i++) {
+            if (id[p][i] < 0) continue;
+            const int u = id[p][i], q = lay[p][i].first;
+            for (int x = 0; x < 4; x++) {
+                const int j = succ(p, lay[p][i], x);
+                if (j < 0 || id[p + 1][j] < 0) continue;
+                L.out_dst[(size_t)4 * u + x] = id[p + 1][j];
+                L.out_cod[(size_t)4 * u + x] = Tr.out_cod[(size_t)4 * q + x];
+                L.out_q[(size_t)4 * u + x] = Tr.out_q[(size_t)4 * q + x];
+                L.out_U[(size_t)4 * u + x] = Tr.out_U[(size_t)4 * q + x];
+            }
+        }
+    index_in_edges(L);
+    hairpin_init(L, P);
+    layout_rows(L, cp);
+    // the trie's closed-form arrays are not used on a generic lattice: neutral fillers that keep
+    // the device layout's extents
+    L.tail.assign(N, 0);
+    L.pfx.assign(N, 0);
+    L.P.assign(L.A + 1, 0);
+    L.alphaU.assign((size_t)4 * N, kINF);
+    L.betaU.assign((size_t)4 * N, kINF);
+    L.hpB.assign((size_t)16 * N, kINF);
+    L.OB.assign((size_t)72 * N, kINF);
+    L.OA.assign((size_t)72 * N, kINF);
+    L.fwd_off.assign((size_t)4 * N + 1, 0);
+    L.bwd_off.assign((size_t)4 * N + 1, 0);
+    L.generic = true;
+    L.motifs = motifs;
+    for (int p = 0; p <= n; p++)
+        L.gwin = std::max(L.gwin, L.off[std::min(p + 1 + kGenLoopWin, n + 1)] - L.off[std::min(p + 1, n + 1)]);
+    L.gwin = std::max(L.gwin, 1);
     return SD_OK;
 }
 

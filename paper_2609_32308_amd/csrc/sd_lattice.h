@@ -47,6 +47,13 @@ struct Lattice {
     std::vector<int> ccap;
     int64_t cells = 0, cand_slots = 0;
     int64_t mlbase_fx = 0;
+    // generic lattice (codon automaton x forbidden-motif matcher): the kernels use gap tables
+    // instead of the trie's closed form; gtab is the downloaded gap table (cell layout) that
+    // host_gap reads during the traceback
+    bool generic = false;
+    int gwin = 0, wmax = 0;
+    std::vector<std::string> motifs;
+    const int64_t* gtab = nullptr;
 };
 
 // validation and construction; return sd_status values
@@ -64,7 +71,17 @@ int position_bin(int layer, int n, int K);
 int build_lattice(const char* protein, const CodonTable& T, const Params& P, double lambda,
                   const CapPolicy& cap, Lattice& L, std::string& err);
 
-// closed-form gap on the host (same definition as the kernels)
+// Design under forbidden motifs: the codon trie of `protein` intersected with a deterministic
+// matcher of the motifs (1..kMaxMotifLen bases over ACGU, at most kMaxMotifs of them).  The
+// fixed-point shift is the unconstrained design's.  SD_E_INFEASIBLE if no coding sequence avoids
+// every motif, SD_E_RANGE if a layer is wider than kGenMaxWidth states.
+constexpr int kMaxMotifLen = 32;
+constexpr int kMaxMotifs = 256;
+int build_motif_lattice(const char* protein, const CodonTable& T, const Params& P, double lambda,
+                        const CapPolicy& cap, const std::vector<std::string>& motifs, Lattice& L,
+                        std::string& err);
+
+// minimum path cost between two states (closed form on the trie, the gap table otherwise)
 int64_t host_gap(const Lattice& L, int a, int b);
 
 std::string sha256_hex(const std::string& data);

@@ -67,9 +67,13 @@ struct Tracer {
     int64_t E = 0, U = 0;
     bool ok = true;
 
+    int segmax = 8;  // loop segments between two states: a segment of >= 2 bases is a first edge
+                     // and an in-edge of its end state, so at most 4 x the largest in-degree
+
     Tracer(const Lattice& l, const Params& p, const TraceTables& t) : L(l), P(p), T(t) {
         seq.assign(L.n, -1);
         pr.assign(L.n, -1);
+        for (int v = 0; v < L.N; v++) segmax = std::max(segmax, 4 * (L.in_start[v + 1] - L.in_start[v]) + 4);
     }
     int64_t fx(int64_t e) const { return e * ((int64_t)1 << L.shift); }
     int64_t cell(int a, int b) const { return L.rowoff[a] + (b - L.off[L.layer[a] + 1]); }
@@ -211,7 +215,8 @@ struct Tracer {
         int la = L.layer[a], lb = L.layer[b];
         int ea = a * 4 + TX[t], a1 = L.out_dst[ea];
         if (a1 < 0) return false;
-        Seg Ls[32], Rs[32];
+        std::vector<Seg> Lv(segmax), Rv(segmax);
+        Seg *Ls = Lv.data(), *Rs = Rv.data();
         for (int l1 = 0; l1 <= kMaxLoop; l1++)
             for (int l2 = 0; l1 + l2 <= kMaxLoop; l2++) {
                 int cl = la + 1 + l1, dl = lb - 1 - l2;
@@ -286,7 +291,7 @@ struct Tracer {
             st.pop_back();
             const int a = f.a, b = f.b;
             if (f.kind == KX) {
-                if (a == L.N - 1) continue;
+                if (L.layer[a] == L.n) continue;
                 int64_t x = T.X[a];
                 bool done = false;
                 for (int y = 0; y < 4 && !done; y++) {
@@ -425,7 +430,7 @@ int trace_design(const Lattice& L, const Params& P, const TraceTables& T, TraceR
         if (L.out_cod[e] >= 0) C += L.out_q[e];
         st = L.out_dst[e];
     }
-    if (st != L.N - 1) ok = false;
+    if (L.layer[st] != L.n) ok = false;
     if (ok && (Uw != tr.U || tr.fx(tr.E) + tr.U != T.X[0])) ok = false;
     R.mrna.assign(L.n, 'N');
     R.structure.assign(L.n, '.');

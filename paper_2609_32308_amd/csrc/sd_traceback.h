@@ -16,6 +16,7 @@ namespace sd {
 // until the context's next download) or owned by `own`.
 struct TraceTables {
     const int64_t *V = nullptr, *B = nullptr, *S1 = nullptr, *S2 = nullptr, *X = nullptr;
+    const int64_t* G = nullptr;  // gap table (generic lattices only)
     const int *ccnt = nullptr, *cc = nullptr;
     std::unique_ptr<char[]> own;
 };

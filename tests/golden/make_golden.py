@@ -4,7 +4,7 @@ Calls only oracle/ and sdinputs/ (the seeded generators); nothing here touches t
 The GPU parity tests compare against these files at sizes where running the dense oracle
 inside a test would take minutes.
 
-    python tests/golden/make_golden.py config2 config3 [config4] [stress]
+    python tests/golden/make_golden.py config2 config3 [config4] [stress] [motifs] [motifs_wide]
 
 The stress families of Sec. 9.2 (poly-S and alternating YI, no Met and no stop) are keyed by
 seed 0 (S) and seed -1 (YI).
@@ -39,6 +39,14 @@ def stress_protein(A, seed):
 
 STRESS = [(256, fam, lam) for fam in (0, -1) for lam in (0.0, 4.0)]
 
+# forbidden motifs: the 64- and 105-aa sizes of the finite-state constraint experiments, with an
+# inventory of 16 random 6-mers (seed 7), and 300 aa as a larger case; "motifs_wide": 96 random
+# 6- and 7-mers (seed 3) that widen a layer of the 60-aa automaton to 16 states, the kernel limit
+MOTIF_SETS = {
+    "motifs": (lambda: S.motifs(16, 7), [(A, 1, lam) for A in (64, 105, 300) for lam in (0.0, 4.0)]),
+    "motifs_wide": (lambda: S.motifs(96, 3, 6, 7), [(60, 1, 0.0), (60, 1, 4.0)]),
+}
+
 
 def run(name, members, nthreads):
     params = S.default_params_path()
@@ -57,7 +65,11 @@ def run(name, members, nthreads):
             continue
         prot = stress_protein(A, seed) if name == "stress" else S.protein(A, seed)
         t = time.time()
-        d = O.design(prot, w, P, lam, nthreads=nthreads)
+        if name in MOTIF_SETS:
+            out["motifs"] = MOTIF_SETS[name][0]()
+            d = O.design_motifs(prot, w, P, lam, out["motifs"], nthreads=nthreads)
+        else:
+            d = O.design(prot, w, P, lam, nthreads=nthreads)
         dt = time.time() - t
         assert d.selfcheck_ok
         out["designs"].append({
@@ -78,5 +90,6 @@ def run(name, members, nthreads):
 if __name__ == "__main__":
     nthreads = int(os.environ.get("ORACLE_THREADS", "8"))
     for name in sys.argv[1:]:
-        members = batch_members() if name == "config4" else STRESS if name == "stress" else WORKLOADS[name]
+        members = (batch_members() if name == "config4" else STRESS if name == "stress"
+                   else MOTIF_SETS[name][1] if name in MOTIF_SETS else WORKLOADS[name])
         run(name, members, nthreads)
