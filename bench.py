@@ -361,7 +361,7 @@ def main():
         "designs_per_min": designs / elapsed * 60.0,
         "fill_ms_per_step": fill / args.steps * 1e3,
         "per_design": per_design_stats(items, results[-1]),
-        "roofline": roofline_for(results, counters, batch, "k_span_gen" if motifs else None),
+        "roofline": roofline_for(results, counters, batch, "k_gen_closed+k_span_gen" if motifs else None),
         "params_sha256": params.sha256,
     }
     ctx.close()

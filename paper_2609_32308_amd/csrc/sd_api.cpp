@@ -249,6 +249,7 @@ InstLayout layout_instance(const Lattice& L, char* A, char* B, Inst& I) {
     I.g0 = 1;
     I.gwin = L.generic ? L.gwin : 0;
     I.wmax = L.wmax;
+    I.njobs = L.generic ? (int64_t)L.gjobs.size() / 2 : 0;
     // extents against slots (units of U in region A, of R in region B)
     struct Ext { const void* p; int64_t bytes; int64_t slot; };
     const int64_t U = I.U, R = I.R();
@@ -315,6 +316,10 @@ void stage_inputs(const Lattice& L, const Inst& I, const char* devA, char* image
     put(I.hpB(), L.hpB.data(), L.hpB.size() * 8);
     put(I.OB(), L.OB.data(), L.OB.size() * 8);
     put(I.OA(), L.OA.data(), L.OA.size() * 8);
+    if (L.generic) {
+        put(I.gjob_off(), L.gjob_off.data(), L.gjob_off.size() * 8);
+        put(I.gjobs(), L.gjobs.data(), L.gjobs.size() * 4);
+    }
 }
 
 sd_status ensure_staging(sd_context* c, size_t bytes) {

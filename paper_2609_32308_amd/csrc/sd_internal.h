@@ -94,6 +94,7 @@ struct Inst {
     int64_t nE, nF, nB;    // in-edges, forward and backward path entries
     int64_t cells, slots;  // DP cells, candidate slots
     int64_t mlbase_fx;     // ML_base * 2^s
+    int64_t njobs;         // generic lattices: typed-value jobs over all spans
     int n, N, A, shift;
     int retain_all;
     int g0;  // persistent launches: first span this launch processes for the instance
@@ -143,8 +144,15 @@ struct Inst {
     __host__ __device__ const int64_t* fwd_crow() const {
         return (const int64_t*)(paths() + al8(4 * nF) + 8 * nF + al8(4 * nB) + 8 * nB);
     }
+    // generic lattices: per span g the typed-value jobs [gjob_off[g], gjob_off[g+1]) of gjobs
+    // (pairs a, b * 8 + type), and one work-ticket counter per span
+    __host__ __device__ int64_t* gjob_off() const {
+        return (int64_t*)(paths() + al8(4 * nF) + 8 * nF + al8(4 * nB) + 8 * nB + 8 * nF);
+    }
+    __host__ __device__ int* gjobs() const { return (int*)(gjob_off() + (gwin ? n + 2 : 0)); }
+    __host__ __device__ unsigned* gtickets() const { return (unsigned*)(gjobs() + 2 * njobs); }
     __host__ __device__ int64_t a_bytes() const {
-        return (int64_t)(paths() - ra) + al8(4 * nF) + 8 * nF + al8(4 * nB) + 8 * nB + 8 * nF;
+        return (int64_t)((char*)gtickets() - ra) + (gwin ? al8(4 * ((int64_t)n + 1)) : 0);
     }
 
     __host__ __device__ int64_t* LM() const { return (int64_t*)ub(0); }

@@ -918,6 +918,10 @@ __global__ void k_init(Inst I) {
         I.visits()[i] = 0;
         I.feasible()[i] = 0;
     }
+    if (I.gwin) {  // generic lattices: typed values are folded in with atomic minima
+        for (int64_t i = tid; i < I.cells * 6; i += nt) I.V()[i] = kINF;
+        for (int i = tid; i <= I.n; i += nt) I.gtickets()[i] = 0;
+    }
 }
 
 // ---- generic lattice: the codon automaton intersected with a forbidden-motif matcher --------------
@@ -932,7 +936,7 @@ __global__ void k_init(Inst I) {
 // with the right segment and the outer mismatch, x_{k-1} with the left segment and the inner
 // mismatch, then take the minimum over (x_{i+1}, x_{l+1}).  Loops with both sides of <= 2 bases
 // (the 1x1, 1x2, 2x2 tables) enumerate all boundary bases.
-constexpr int kGenParts = 4;  // per (cell, type): part 0 hairpin, stack, bulges, multiloop; 1..3 interior
+constexpr int kGenParts = 8;  // per (cell, type): part 0 hairpin, stack, bulges, multiloop; 1..7 interior
 
 template <class IT>
 __device__ __forceinline__ int64_t gen_gap(const IT& I, int a, int la, int b, int lb) {
@@ -945,11 +949,8 @@ __device__ __forceinline__ const int64_t* gen_lg(const IT& I, int u, int lu, int
 }
 
 struct GenShared {
-    int64_t vbuf[kGenMaxWidth * kGenMaxWidth][6];
     int64_t cellB[kGenMaxWidth * kGenMaxWidth];
     int keep[kGenMaxWidth * kGenMaxWidth];
-    int combo[kGenMaxWidth * kGenMaxWidth * 6];
-    int ncombo;
 };
 
 // interior loop (l1, l2 >= 1) closed by type t around inner cell values vin[6], with the left
@@ -1005,6 +1006,37 @@ __device__ int64_t gen_interior(const SmallE& S, const EnergyTables* __restrict_
                 if (t1 < kINF) best = mn(best, t1 + t2 + vin[tp]);
             }
     }
+    return best >= kINF ? kINF : best + fx(interior_base(S, l1, l2), s);
+}
+
+// Interior loop of mismatch class X with both segment tables known, when the left segment's
+// part is pre-reduced: A[xk][xj] = min over xi of L[xi][xk] + mm_X[t][xi][xj] (per inner left
+// state c).  Then min over (xk, xl) of [min over xj of A[xk][xj] + R[xl][xj]] + IN(xk, xl), with
+// IN(xk, xl) = min over inner types of V + mm_X[reversed type][xl][xk].
+__device__ __forceinline__ int64_t gen_interior_fast(const SmallE& S, int X, const int64_t A[16],
+                                                     const int64_t* __restrict__ Rp, const int64_t vin[6],
+                                                     int l1, int l2, int s) {
+    int64_t R[16];
+#pragma unroll
+    for (int k = 0; k < 16; k++) R[k] = Rp[k];
+    int64_t best = kINF;
+#pragma unroll
+    for (int xk = 0; xk < 4; xk++)
+#pragma unroll
+        for (int xl = 0; xl < 4; xl++) {
+            int64_t out = kINF;
+#pragma unroll
+            for (int xj = 0; xj < 4; xj++) {
+                const int64_t a = A[xk * 4 + xj], r = R[xl * 4 + xj];
+                if (a < kINF && r < kINF) out = mn(out, a + r);
+            }
+            if (out >= kINF) continue;
+            int64_t in = kINF;
+#pragma unroll
+            for (int tp = 0; tp < 6; tp++)
+                if (vin[tp] < kINF) in = mn(in, vin[tp] + fx(mmx(S, X, kRev[tp], xl, xk), s));
+            if (in < kINF) best = mn(best, out + in);
+        }
     return best >= kINF ? kINF : best + fx(interior_base(S, l1, l2), s);
 }
 
@@ -1088,9 +1120,11 @@ __device__ int64_t gen_closed_part(const IT& I, const SmallE& S, const EnergyTab
             }
         }
     } else if (g >= 9) {
-        // interior loops with l1 = part, part + 3, ...: the inner left state c runs over the
+        // interior loops with l1 = part, part + 7, ...: the inner left state c runs over the
         // layer of l1, the lanes over every inner right state d with 1 <= l2 <= 30 - l1 and
-        // inner span >= 5 (one contiguous state range)
+        // inner span >= 5 (one contiguous state range).  Pairs of the class that dominates the
+        // row (1xn for l1 = 1, generic otherwise) take the pre-reduced form; 1x1/1x2/2x2, 2x3
+        // and 1xn with l1 > 1 the full one.
         for (int eb = ib0; eb < ib1; eb++) {
             if (I.in_lab()[eb] != y) continue;
             const int b1 = I.in_src()[eb];
@@ -1100,9 +1134,25 @@ __device__ int64_t gen_closed_part(const IT& I, const SmallE& S, const EnergyTab
                 const int dl_lo = max(q - 1 - (kGenLoopWin - l1), lc + 5), dl_hi = q - 2;
                 if (dl_lo > dl_hi) break;
                 const int d0 = I.off()[dl_lo], d1 = I.off()[dl_hi + 1];
+                const int Xc = l1 == 1 ? 2 : 0;
                 for (int c = I.off()[lc]; c < I.off()[lc + 1]; c++) {
                     const int64_t* lgl = gen_lg(I, a1, p + 1, c);
                     const int64_t crow = I.rowoff()[c] - I.off()[lc + 1];
+                    int64_t A[16];
+                    bool anyA = false;
+#pragma unroll
+                    for (int k = 0; k < 16; k++) {
+                        const int xk = k >> 2, xj = k & 3;
+                        int64_t acc = kINF;
+#pragma unroll
+                        for (int xi = 0; xi < 4; xi++) {
+                            const int64_t l = lgl[xi * 4 + xk];
+                            if (l < kINF) acc = mn(acc, l + fx(mmx(S, Xc, t, xi, xj), s));
+                        }
+                        A[k] = acc;
+                        anyA = anyA || acc < kINF;
+                    }
+                    if (!anyA) continue;  // no path a1 -> c of l1 edges
                     for (int d = d0 + lane; d < d1; d += 64) {
                         const int64_t* vv = I.V() + (crow + d) * 6;
                         int64_t vin[6];
@@ -1113,8 +1163,11 @@ __device__ int64_t gen_closed_part(const IT& I, const SmallE& S, const EnergyTab
                             any = any || vin[tp] < kINF;
                         }
                         if (!any) continue;
-                        const int ld = I.layer()[d];
-                        const int64_t w = gen_interior(S, E, t, l1, q - 1 - ld, lgl, gen_lg(I, d, ld, b1), vin, s);
+                        const int ld = I.layer()[d], l2 = q - 1 - ld;
+                        const int64_t* lgr = gen_lg(I, d, ld, b1);
+                        const bool fast = !(l1 <= 2 && l2 <= 2) && mm_class(l1, l2) == Xc;
+                        const int64_t w = fast ? gen_interior_fast(S, Xc, A, lgr, vin, l1, l2, s)
+                                               : gen_interior(S, E, t, l1, l2, lgl, lgr, vin, s);
                         if (w < kINF) v = mn(v, Uab + w);
                     }
                 }
@@ -1164,43 +1217,16 @@ __device__ GroupCounters gen_span_group(const IT& I, const SmallE& S, const Ener
             I.LG()[((int64_t)a * I.gwin + (b - I.off()[p + 1])) * 16 + x * 4 + yy] = lv;
         }
     }
-    // (cell, type) jobs as in the trie kernel
-    if (wave == 0) {
-        int base = 0;
-        for (int k0 = 0; k0 < ncell * 6; k0 += 64) {
-            const int k = k0 + lane;
-            bool job = false;
-            if (k < ncell * 6) {
-                const int ci = k / 6, t = k - 6 * ci;
-                G.vbuf[ci][t] = kINF;
-                job = g >= 5 && I.out_dst()[(a_lo + ci / wb) * 4 + kTX[t]] >= 0 &&
-                      ((I.inmask()[b_lo + ci % wb] >> kTY[t]) & 1);
-            }
-            const unsigned long long m = __ballot(job);
-            if (job) G.combo[base + __popcll(m & ((1ull << lane) - 1ull))] = k;
-            base += __popcll(m);
-        }
-        if (lane == 0) G.ncombo = base;
-    }
-    __syncthreads();
-    const int njobs = kGenParts * G.ncombo;
-    for (int k = wave; k < njobs; k += nw) {
-        const int cmb = G.combo[k / kGenParts], ci = cmb / 6, t = cmb - 6 * ci;
-        const int a = a_lo + ci / wb, b = b_lo + ci % wb;
-        const int64_t v = gen_closed_part(I, S, E, spec, a, b, t, p, q, k % kGenParts, lane);
-        if (lane == 0 && v < kINF)
-            __hip_atomic_fetch_min(&G.vbuf[ci][t], v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
-    }
-    __syncthreads();
+    // typed values of this span were filled by k_gen_closed
     // branch value, S2 (eq. 7), P_S, S1 and the retention test, one cell per wave
     for (int ci = wave; ci < ncell; ci += nw) {
         const int a = a_lo + ci / wb, b = b_lo + ci % wb;
         const int64_t cell = I.rowoff()[a] + (b - I.off()[p + 1]);
         int64_t Bv = kINF;
-        for (int t = 0; t < 6; t++) {
-            const int64_t v = G.vbuf[ci][t];
-            if (lane == t) I.V()[cell * 6 + t] = v;
-            if (v < kINF) Bv = mn(Bv, v + fx(S.ml_intern + au_pen(S, t), s));
+        {
+            const int64_t v = lane < 6 ? I.V()[cell * 6 + lane] : kINF;
+            if (v < kINF) Bv = v + fx(S.ml_intern + au_pen(S, lane), s);
+            Bv = wave_min(Bv);
         }
         const int committed = I.ccnt()[b];
         const int64_t cbase = I.coff()[b];
@@ -1263,6 +1289,29 @@ __device__ GroupCounters gen_span_group(const IT& I, const SmallE& S, const Ener
         ctr.appends += (unsigned long long)added;
     }
     return ctr;
+}
+
+// typed closed values of span g on a generic lattice: every wave draws (job, part) tickets of the
+// span's job list (host-built: cells and types that can close) and folds its part into V with an
+// atomic minimum (V starts at infinity, set by k_init)
+__global__ __launch_bounds__(256) void k_gen_closed(Inst I, const EnergyTables* __restrict__ E,
+                                                    const int32_t* __restrict__ spec, int g) {
+    __shared__ SmallE S;
+    stage_tables(S, E);
+    __syncthreads();
+    const int lane = threadIdx.x & 63;
+    const int64_t j0 = I.gjob_off()[g], total = (I.gjob_off()[g + 1] - j0) * kGenParts;
+    for (;;) {
+        unsigned k = 0;
+        if (lane == 0) k = atomicAdd(&I.gtickets()[g], 1u);
+        k = __shfl(k, 0, 64);
+        if ((int64_t)k >= total) break;
+        const int64_t j = j0 + k / kGenParts;
+        const int a = I.gjobs()[2 * j], bt = I.gjobs()[2 * j + 1], b = bt >> 3, t = bt & 7;
+        const int64_t v = gen_closed_part(I, S, E, spec, a, b, t, I.layer()[a], I.layer()[b], (int)(k % kGenParts), lane);
+        if (lane == 0 && v < kINF)
+            __hip_atomic_fetch_min(&I.V()[cell_of(I, a, b) * 6 + t], v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    }
 }
 
 // span step on a generic lattice: layer pair xcd_band(x) for block x < layer pairs, then the
@@ -1539,6 +1588,15 @@ hipError_t launch_span_gen(const Inst& I, const EnergyTables* E, const int32_t* 
     const int nblk = layers > 0 ? layers : 0;
     const int total = nblk + (ext_layer >= 0 ? 1 : 0);
     if (total == 0) return hipSuccess;
+    if (g >= 5 && nblk > 0) {
+        int cu = 0, dev = 0;
+        hipError_t e = hipGetDevice(&dev);
+        if (e == hipSuccess) e = hipDeviceGetAttribute(&cu, hipDeviceAttributeMultiprocessorCount, dev);
+        if (e != hipSuccess) return e;
+        hipLaunchKernelGGL(k_gen_closed, dim3(4 * cu), dim3(256), 0, st, I, E, spec, g);
+        e = hipGetLastError();
+        if (e != hipSuccess) return e;
+    }
     hipLaunchKernelGGL(k_span_gen, dim3(total), dim3(256), 0, st, I, E, spec, g, ext_layer, nblk);
     return hipGetLastError();
 }

@@ -703,6 +703,24 @@ int build_motif_lattice(const char* protein, const CodonTable& T, const Params& 
     for (int p = 0; p <= n; p++)
         L.gwin = std::max(L.gwin, L.off[std::min(p + 1 + kGenLoopWin, n + 1)] - L.off[std::min(p + 1, n + 1)]);
     L.gwin = std::max(L.gwin, 1);
+    // typed-value jobs per span: (a, b, t) with an out-edge of a labelled t's 5' base, an in-edge
+    // of b labelled its 3' base and span >= 5 (no other type can close the cell)
+    L.gjob_off.assign(n + 2, 0);
+    L.gjobs.clear();
+    for (int g = 0; g <= n; g++) {
+        L.gjob_off[g] = (int64_t)L.gjobs.size() / 2;
+        if (g < 5) continue;
+        for (int p = 0; p + g <= n; p++)
+            for (int a = L.off[p]; a < L.off[p + 1]; a++)
+                for (int b = L.off[p + g]; b < L.off[p + g + 1]; b++)
+                    for (int t = 0; t < 6; t++) {
+                        static const int tx[6] = {0, 1, 2, 2, 3, 3}, ty[6] = {3, 2, 1, 3, 0, 2};
+                        if (L.out_dst[(size_t)4 * a + tx[t]] < 0 || !((L.inmask[b] >> ty[t]) & 1)) continue;
+                        L.gjobs.push_back(a);
+                        L.gjobs.push_back(b * 8 + t);
+                    }
+    }
+    L.gjob_off[n + 1] = (int64_t)L.gjobs.size() / 2;
     return SD_OK;
 }
 

@@ -53,6 +53,8 @@ struct Lattice {
     bool generic = false;
     int gwin = 0, wmax = 0;
     std::vector<std::string> motifs;
+    std::vector<int64_t> gjob_off;  // [n+2]: jobs of span g are [gjob_off[g], gjob_off[g+1])
+    std::vector<int32_t> gjobs;     // pairs (a, b*8 + type) of typed-value jobs
     const int64_t* gtab = nullptr;
 };
 
