@@ -170,6 +170,18 @@ sd_status sd_design_motifs(sd_context *ctx, const char *protein, const char *con
                            int n_motifs, const sd_codon_table *table, const sd_params *params,
                            double lambda_kcal, sd_result *out);
 
+/* Inverse lambda (the inverse-lambda tool of Sec. 10): the smallest lambda in [0, lambda_hi] at
+ * which a supported design of `protein` has CAI >= target_cai (relative tolerance 1e-12), found
+ * on the supported envelope of [0, lambda_hi] (sd_lambda_envelope with max_designs).  The optimal
+ * CAI is a non-decreasing step function of lambda, so *lambda_out is the left breakpoint of the
+ * first supported line that meets the target (0 if the lambda = 0 optimum already does); *out
+ * receives that design (owning its strings).  SD_E_ARG unless 0 < target_cai <= 1,
+ * SD_E_INFEASIBLE if no supported design on the interval reaches it; otherwise errors as for
+ * sd_lambda_envelope. */
+sd_status sd_inverse_lambda(sd_context *ctx, const char *protein, double target_cai, double lambda_hi,
+                            int max_designs, const sd_codon_table *table, const sd_params *params,
+                            sd_result *out, double *lambda_out);
+
 /* Test hook: the plain design plus its tables copied into caller buffers in a dense
  * state-pair layout [a*N + b] (V: [tau][a][b] with tau in AU,CG,GC,GU,UA,UG; entries with
  * rho(a) >= rho(b) are set to 2^62).  Any table pointer may be NULL.  N = out->n_states. */

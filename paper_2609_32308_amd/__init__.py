@@ -30,7 +30,7 @@ EXPORTS = [
     "sd_sizer_get_params", "sd_sizer_set_params", "sd_sizer_gradient", "sd_sizer_train",
     "sd_sizer_predict", "sd_sizer_features", "sd_context_set_sizer", "sd_occupancy",
     "sd_server_start", "sd_server_submit", "sd_server_poll", "sd_server_wait", "sd_server_get_stats",
-    "sd_server_stop", "sd_lambda_envelope", "sd_design_motifs",
+    "sd_server_stop", "sd_lambda_envelope", "sd_design_motifs", "sd_inverse_lambda",
 ]
 
 
@@ -92,6 +92,8 @@ def lib():
         L.sd_design.argtypes = [vp, C.c_char_p, vp, vp, C.c_double, C.POINTER(_Result)]
         L.sd_design_motifs.argtypes = [vp, C.c_char_p, C.POINTER(C.c_char_p), C.c_int, vp, vp, C.c_double,
                                        C.POINTER(_Result)]
+        L.sd_inverse_lambda.argtypes = [vp, C.c_char_p, C.c_double, C.c_double, C.c_int, vp, vp,
+                                        C.POINTER(_Result), C.POINTER(C.c_double)]
         L.sd_design_batch.argtypes = [vp, C.c_int, C.POINTER(C.c_char_p), C.POINTER(C.c_double),
                                       vp, vp, C.POINTER(_Result)]
         L.sd_design_tables.argtypes = [vp, C.c_char_p, vp, vp, C.c_double, C.POINTER(_Result),
@@ -235,6 +237,16 @@ class Context:
         _check(lib().sd_design_motifs(self.h, protein.encode(), arr, len(m), table.h, params.h, float(lam),
                                       C.byref(r)), "sd_design_motifs")
         return _convert(r)
+
+    def inverse_lambda(self, protein: str, target_cai: float, lambda_hi: float, table: CodonTable,
+                       params: Params, max_designs: int = 64):
+        """(lambda, design): the smallest lambda <= lambda_hi whose supported design has CAI >= target."""
+        r = _Result()
+        lam = C.c_double()
+        _check(lib().sd_inverse_lambda(self.h, protein.encode(), float(target_cai), float(lambda_hi),
+                                       max_designs, table.h, params.h, C.byref(r), C.byref(lam)),
+               "sd_inverse_lambda")
+        return lam.value, _convert(r)
 
     def design_batch(self, proteins, lambdas, table: CodonTable, params: Params):
         n = len(proteins)

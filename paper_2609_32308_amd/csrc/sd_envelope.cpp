@@ -142,3 +142,36 @@ extern "C" sd_status sd_lambda_envelope(sd_context* ctx, const char* protein, do
         return fail(SD_E_INTERNAL, "unexpected exception");
     }
 }
+
+// Inverse lambda: the smallest lambda in [0, lambda_hi] at which a supported design reaches a
+// target CAI.  The optimal codon cost is a non-increasing step function of lambda whose steps are
+// the envelope's breakpoints, so the answer is the left breakpoint of the first supported design
+// (in increasing lambda) whose CAI meets the target.
+extern "C" sd_status sd_inverse_lambda(sd_context* ctx, const char* protein, double target_cai,
+                                       double lambda_hi, int max_designs, const sd_codon_table* table,
+                                       const sd_params* params, sd_result* out, double* lambda_out) {
+    try {
+        if (!ctx || !protein || !table || !params || !out || !lambda_out || max_designs < 2)
+            return fail(SD_E_ARG, "null argument or max_designs < 2");
+        if (!(target_cai > 0.0 && target_cai <= 1.0)) return fail(SD_E_ARG, "target CAI must lie in (0, 1]");
+        std::vector<sd_result> outs(max_designs);
+        std::vector<double> breaks(max_designs + 1);
+        int m = 0;
+        sd_status s = sd_lambda_envelope(ctx, protein, 0.0, lambda_hi, max_designs, table, params, outs.data(),
+                                         breaks.data(), &m);
+        if (s) return s;
+        int pick = -1;
+        for (int i = 0; i < m && pick < 0; i++)
+            if (outs[i].cai >= target_cai * (1.0 - 1e-12)) pick = i;
+        for (int i = 0; i < m; i++)
+            if (i != pick) sd_result_free(&outs[i]);
+        if (pick < 0) return fail(SD_E_INFEASIBLE, "no supported design on [0, lambda_hi] reaches the target CAI");
+        *out = outs[pick];
+        *lambda_out = breaks[pick];
+        return SD_OK;
+    } catch (const std::bad_alloc&) {
+        return fail(SD_E_NOMEM, "host allocation");
+    } catch (...) {
+        return fail(SD_E_INTERNAL, "unexpected exception");
+    }
+}

@@ -50,3 +50,37 @@ def test_envelope_supported_designs(sd, A, seed, params_path, weights, oparams):
         env = min(line(d, lam) for d in designs)
         assert abs(env - o.objective_kcal) <= 1e-9 * (1 + abs(env))
     ctx.close()
+
+
+def test_inverse_lambda(sd, params_path, weights, oparams):
+    # the smallest lambda whose optimum reaches a target CAI is the left breakpoint of the first
+    # supported line that meets it
+    ctx = sd.Context(0)
+    gp, gt = sd.Params(params_path), sd.CodonTable(weights)
+    p = S.protein(40, 3)
+    designs, breaks = ctx.lambda_envelope(p, 0.0, 8.0, gt, gp, max_designs=64)
+    print("inverse lambda", len(designs), flush=True)
+    assert len(designs) >= 3
+    k = len(designs) // 2
+    target = designs[k].cai
+    lam, d = ctx.inverse_lambda(p, target, 8.0, gt, gp)
+    assert lam == breaks[k] and lam > 0.0
+    assert d.mrna == designs[k].mrna and d.cai >= target * (1 - 1e-12)
+    # just below it the optimum misses the target; just above it the optimum is this design's line
+    below = ctx.design(p, gt, gp, lam - 1e-7)
+    assert below.cai < target
+    above = O.design(p, weights, oparams, lam + 1e-7, nthreads=8)
+    assert abs(above.objective_kcal - line(d, lam + 1e-7)) <= 1e-9 * (1 + abs(above.objective_kcal))
+    # a target the lambda = 0 optimum already meets
+    lam0, d0 = ctx.inverse_lambda(p, designs[0].cai, 8.0, gt, gp)
+    assert lam0 == 0.0 and d0.mrna == designs[0].mrna
+    # unreachable on the interval, and invalid targets
+    if designs[-1].cai < 1.0:
+        with pytest.raises(sd.SDError) as e:
+            ctx.inverse_lambda(p, min(1.0, designs[-1].cai * 1.001), 8.0, gt, gp)
+        assert e.value.code == -12
+    for bad in (0.0, -0.5, 1.5):
+        with pytest.raises(sd.SDError) as e:
+            ctx.inverse_lambda(p, bad, 8.0, gt, gp)
+        assert e.value.code == -1
+    ctx.close()
