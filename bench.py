@@ -204,7 +204,12 @@ def served_workload(args, sd, S):
     train = [S.protein(A, 100000 + i) for i, A in enumerate(tl)]
     tlam = [0.0 if i % 2 == 0 else 4.0 for i in range(ntrain)]
     t = time.time()
-    Y, _ = ctx.occupancy(train, tlam, table, params, K)
+    import numpy as np
+    Ys = []
+    for i in range(0, ntrain, 100):  # chunks, so that a long log reports progress
+        Ys.append(ctx.occupancy(train[i:i + 100], tlam[i:i + 100], table, params, K)[0])
+        progress(f"occupancy log {min(ntrain, i + 100)}/{ntrain}")
+    Y = np.concatenate(Ys)
     t_log = time.time() - t
     progress(f"occupancy log of {ntrain} proteins: {t_log:.1f} s")
     import numpy as np
