@@ -466,9 +466,10 @@ struct GroupShared {
     LabPair lab[NW][16];
 };
 
-// One of two parts of the typed closed value V_t(a, b), with the lanes of one wave:
+// One of three parts of the typed closed value V_t(a, b), with the lanes of one wave:
 //   part 0: hairpin, stacks and bulges, multiloop closure;
-//   part 1: interior loops (one-sided, both explicit, both separable).
+//   part 1: interior loops with a separable side (one-sided, both separable);
+//   part 2: interior loops with both sides explicit (labelled short paths).
 // The parts of one (cell, type) run on different waves and meet in an LDS minimum.
 template <class IT>
 __device__ int64_t closed_part(const IT& I, const SmallE& S, const EnergyTables* __restrict__ E,
@@ -515,6 +516,15 @@ __device__ int64_t closed_part(const IT& I, const SmallE& S, const EnergyTables*
                 v = mn(v, I.S2()[cell_of(I, a1, b1)] + Ua + I.in_U()[eb] + fx(mlc, s));
             }
         }
+    } else if (part == 2) {
+        if (g >= 7) {
+            for (int eb = ib0; eb < ib1; eb++) {
+                if (I.in_lab()[eb] != y) continue;
+                const int b1 = I.in_src()[eb];
+                const int64_t Uab = Ua + I.in_U()[eb];
+                v = mn(v, labelled_pairs(I, S, E, t, a1, b1, Uab, ph, cap, lane, lab));
+            }
+        }
     } else {
         if (g >= 7) {
             const int64_t* oa = I.OA() + (int64_t)(a1 * 6 + t) * 12;
@@ -523,7 +533,6 @@ __device__ int64_t closed_part(const IT& I, const SmallE& S, const EnergyTables*
                 const int b1 = I.in_src()[eb];
                 const int64_t Uab = Ua + I.in_U()[eb];
                 v = mn(v, one_sided(I, S, a1, b1, Uab, p, q, cap, lane, I.OB() + (int64_t)(b1 * 6 + t) * 12, oa));
-                v = mn(v, labelled_pairs(I, S, E, t, a1, b1, Uab, ph, cap, lane, lab));
             }
         }
         if (g >= 12) {
@@ -670,12 +679,12 @@ __device__ GroupCounters span_group(const IT& I, const SmallE& S, const EnergyTa
         if (lane == 0) G.ncombo = base;
     }
     __syncthreads();
-    // phase 1: typed closed values; the two parts of every (cell, type) job on separate waves
-    const int njobs = 2 * G.ncombo;
+    // phase 1: typed closed values; the three parts of every (cell, type) job on separate waves
+    const int njobs = 3 * G.ncombo;
     for (int k = wave; k < njobs; k += nw) {
-        const int cmb = G.combo[k >> 1], ci = cmb / 6, t = cmb - 6 * ci;
+        const int cmb = G.combo[k / 3], ci = cmb / 6, t = cmb - 6 * ci;
         const int a = a_lo + ci / wb, b = b_lo + ci % wb;
-        const int64_t v = closed_part(I, S, E, spec, a, b, t, p, q, k & 1, mini0, mini1, lane, G.lab[wave]);
+        const int64_t v = closed_part(I, S, E, spec, a, b, t, p, q, k % 3, mini0, mini1, lane, G.lab[wave]);
         if (lane == 0 && v < kINF)
             __hip_atomic_fetch_min(&G.vbuf[ci][t], v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
     }

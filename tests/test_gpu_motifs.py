@@ -7,7 +7,9 @@ matcher; the finite-state constraint experiments) against the dense CPU oracle.
   * 64, 105 and 300 aa with an inventory of 16 random 6-mers, and a 60-aa case whose automaton
     reaches the 16-state layer limit, against stored oracle goldens (tests/golden/motifs*.json);
   * an infeasible language, malformed motif lists and an over-wide automaton give their errors,
-    and plain designs on the same context are unaffected.
+    and plain designs on the same context are unaffected;
+  * a forced candidate-capacity overflow (recomputed with worst-case segments) and the
+    retain-all control reach the oracle's design.
 """
 import json
 import os
@@ -131,3 +133,24 @@ def test_motif_errors_and_context_reuse(ctx, gtable, gparams, oparams, weights, 
         (before.mrna, before.structure, before.objective_fixed, before.n_candidates)
     d = O.design(p, weights, oparams, 4.0, nthreads=8)
     assert after.objective_fixed == d.objective_fixed and after.mrna == d.mrna
+
+
+def test_motif_overflow_fallback_and_retain_all(sd, gtable, gparams, oparams, weights):
+    # a 2-slot candidate capacity overflows and is recomputed with worst-case segments; the
+    # retain-all control keeps every finite direct interval; both reach the oracle's design
+    p = S.protein(45, 4)
+    motifs = S.motifs(16, 24)
+    d = as_dict(O.design_motifs(p, weights, oparams, 4.0, motifs, nthreads=8))
+    say("motif overflow")
+    c = sd.Context(0, capacity_override=2)
+    r = c.design_motifs(p, motifs, gtable, gparams, 4.0)
+    same(r, d, motifs)
+    assert r.cand_overflow == 1 and r.cand_slots > r.cand_slots_first
+    c.close()
+    say("motif retain-all")
+    c = sd.Context(0, retain_all=True)
+    r = c.design_motifs(p, motifs, gtable, gparams, 4.0)
+    assert (r.energy, r.objective_fixed, r.mrna, r.structure) == \
+        (d["energy"], d["objective_fixed"], d["mrna"], d["structure"])
+    assert r.n_candidates == d["n_candidates"] and r.n_visits >= d["visits_sparse"]
+    c.close()
