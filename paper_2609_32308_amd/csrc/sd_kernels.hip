@@ -280,7 +280,7 @@ struct LabPair {
 template <class IT>
 __device__ int64_t labelled_pairs(const IT& I, const SmallE& S, const EnergyTables* __restrict__ E,
                                   int t, int a1, int b1, int64_t Uab, int ph, int cap, int lane,
-                                  LabPair* lp) {
+                                  LabPair* lp, int h, int nh) {
     const int s = I.shift;
     const int npairs = kPairCnt[kListLab][ph][cap];  // <= 16
     int cnt = 0;
@@ -307,7 +307,7 @@ __device__ int64_t labelled_pairs(const IT& I, const SmallE& S, const EnergyTabl
     __builtin_amdgcn_wave_barrier();
     __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
     int64_t best = kINF;
-    for (int idx = lane; idx < total; idx += 64) {
+    for (int idx = lane + 64 * h; idx < total; idx += 64 * nh) {
         int k = 0;
         while (k + 1 < npairs && lp[k + 1].start <= idx) k++;
         const LabPair x = lp[k];
@@ -466,15 +466,16 @@ struct GroupShared {
     LabPair lab[NW][16];
 };
 
-// One of three parts of the typed closed value V_t(a, b), with the lanes of one wave:
+// One part of the typed closed value V_t(a, b), with the lanes of one wave:
 //   part 0: hairpin, stacks and bulges, multiloop closure;
 //   part 1: interior loops with a separable side (one-sided, both separable);
-//   part 2: interior loops with both sides explicit (labelled short paths).
+//   parts 2 .. nparts-1: interior loops with both sides explicit (labelled short paths), whose
+//   flattened items are dealt to these parts in blocks of 64.
 // The parts of one (cell, type) run on different waves and meet in an LDS minimum.
 template <class IT>
 __device__ int64_t closed_part(const IT& I, const SmallE& S, const EnergyTables* __restrict__ E,
                                const int32_t* __restrict__ spec, int a, int b, int t, int p, int q,
-                               int part, int64_t mini0, int64_t mini1, int lane, LabPair* lab) {
+                               int part, int nparts, int64_t mini0, int64_t mini1, int lane, LabPair* lab) {
     const int g = q - p, s = I.shift;
     const int a1 = I.out_dst()[a * 4 + kTX[t]];
     const int64_t Ua = I.out_U()[a * 4 + kTX[t]];
@@ -516,13 +517,13 @@ __device__ int64_t closed_part(const IT& I, const SmallE& S, const EnergyTables*
                 v = mn(v, I.S2()[cell_of(I, a1, b1)] + Ua + I.in_U()[eb] + fx(mlc, s));
             }
         }
-    } else if (part == 2) {
+    } else if (part >= 2) {
         if (g >= 7) {
             for (int eb = ib0; eb < ib1; eb++) {
                 if (I.in_lab()[eb] != y) continue;
                 const int b1 = I.in_src()[eb];
                 const int64_t Uab = Ua + I.in_U()[eb];
-                v = mn(v, labelled_pairs(I, S, E, t, a1, b1, Uab, ph, cap, lane, lab));
+                v = mn(v, labelled_pairs(I, S, E, t, a1, b1, Uab, ph, cap, lane, lab, part - 2, nparts - 2));
             }
         }
     } else {
@@ -679,12 +680,13 @@ __device__ GroupCounters span_group(const IT& I, const SmallE& S, const EnergyTa
         if (lane == 0) G.ncombo = base;
     }
     __syncthreads();
-    // phase 1: typed closed values; the three parts of every (cell, type) job on separate waves
-    const int njobs = 3 * G.ncombo;
+    // phase 1: typed closed values; the parts of every (cell, type) job on separate waves
+    constexpr int nparts = NW >= 8 ? 4 : 3;  // labelled pairs over two waves in wide workgroups
+    const int njobs = nparts * G.ncombo;
     for (int k = wave; k < njobs; k += nw) {
-        const int cmb = G.combo[k / 3], ci = cmb / 6, t = cmb - 6 * ci;
+        const int cmb = G.combo[k / nparts], ci = cmb / 6, t = cmb - 6 * ci;
         const int a = a_lo + ci / wb, b = b_lo + ci % wb;
-        const int64_t v = closed_part(I, S, E, spec, a, b, t, p, q, k % 3, mini0, mini1, lane, G.lab[wave]);
+        const int64_t v = closed_part(I, S, E, spec, a, b, t, p, q, k % nparts, nparts, mini0, mini1, lane, G.lab[wave]);
         if (lane == 0 && v < kINF)
             __hip_atomic_fetch_min(&G.vbuf[ci][t], v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
     }
