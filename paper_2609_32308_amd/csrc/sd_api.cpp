@@ -372,15 +372,20 @@ hipError_t read_stats(const Inst& I, hipStream_t st, unsigned long long out[4]) 
     return hipSuccess;
 }
 
-// Workgroup size of the span step for a span with `pairs` layer pairs.  Eight waves per pair
-// shorten each pair's critical path (more of its typed-value jobs run at once) but halve the
-// workgroups resident per CU, so they pay only while every pair of the span still fits in about
-// SPAN_WIDE_PER_CU workgroups per CU.
+// Workgroup size of the span step for a span with `pairs` layer pairs.  Eight or sixteen waves
+// per pair shorten each pair's critical path (more of its typed-value job parts run at once) but
+// leave fewer workgroups resident per CU, so eight pay only while every pair of the span still
+// fits in about SPAN_WIDE_PER_CU workgroups per CU, and sixteen while there is at most one pair
+// per CU.
 #ifndef SPAN_WIDE_PER_CU
 #define SPAN_WIDE_PER_CU 4
 #endif
+#ifndef SPAN_XWIDE_PER_CU
+#define SPAN_XWIDE_PER_CU 1
+#endif
 int span_threads_for(const sd_context* c, int pairs) {
     if (c->opt.span_threads) return c->opt.span_threads;
+    if (pairs <= SPAN_XWIDE_PER_CU * c->num_cu) return 1024;
     return pairs <= SPAN_WIDE_PER_CU * c->num_cu ? 512 : 256;
 }
 

@@ -681,7 +681,8 @@ __device__ GroupCounters span_group(const IT& I, const SmallE& S, const EnergyTa
     }
     __syncthreads();
     // phase 1: typed closed values; the parts of every (cell, type) job on separate waves
-    constexpr int nparts = NW >= 8 ? 4 : 3;  // labelled pairs over two waves in wide workgroups
+    // labelled pairs over 1, 2 or 4 waves: wide workgroups run spans with few layer pairs
+    constexpr int nparts = NW >= 16 ? 6 : NW >= 8 ? 4 : 3;
     const int njobs = nparts * G.ncombo;
     for (int k = wave; k < njobs; k += nw) {
         const int cmb = G.combo[k / nparts], ci = cmb / 6, t = cmb - 6 * ci;
