@@ -948,7 +948,9 @@ __global__ void k_init(Inst I) {
 // with the right segment and the outer mismatch, x_{k-1} with the left segment and the inner
 // mismatch, then take the minimum over (x_{i+1}, x_{l+1}).  Loops with both sides of <= 2 bases
 // (the 1x1, 1x2, 2x2 tables) enumerate all boundary bases.
-constexpr int kGenParts = 8;  // per (cell, type): part 0 hairpin, stack, bulges, multiloop; 1..7 interior
+// per (cell, type): part 0 hairpin, stack, bulges, multiloop; part l1 = 1..29 the interior loops
+// whose left segment has l1 bases (one ticket each, so that a span's work balances finely)
+constexpr int kGenParts = 30;
 
 template <class IT>
 __device__ __forceinline__ int64_t gen_gap(const IT& I, int a, int la, int b, int lb) {
@@ -1132,11 +1134,11 @@ __device__ int64_t gen_closed_part(const IT& I, const SmallE& S, const EnergyTab
             }
         }
     } else if (g >= 9) {
-        // interior loops with l1 = part, part + 7, ...: the inner left state c runs over the
-        // layer of l1, the lanes over every inner right state d with 1 <= l2 <= 30 - l1 and
-        // inner span >= 5 (one contiguous state range).  Pairs of the class that dominates the
-        // row (1xn for l1 = 1, generic otherwise) take the pre-reduced form; 1x1/1x2/2x2, 2x3
-        // and 1xn with l1 > 1 the full one.
+        // interior loops with l1 = part (29 parts cover every l1): the inner left state c runs
+        // over the layer of l1, the lanes over every inner right state d with 1 <= l2 <= 30 - l1
+        // and inner span >= 5 (one contiguous state range).  Pairs of the class that dominates
+        // the row (1xn for l1 = 1, generic otherwise) take the pre-reduced form; 1x1/1x2/2x2,
+        // 2x3 and 1xn with l1 > 1 the full one.
         for (int eb = ib0; eb < ib1; eb++) {
             if (I.in_lab()[eb] != y) continue;
             const int b1 = I.in_src()[eb];
