@@ -1,20 +1,22 @@
 """Benchmark of the exact coding-sequence design DP on one MI355X.
 
     python bench.py [--gpus 1] [--steps K] [--warmup W]
-                    [--workload config2|config3|batch|served] [--no-cpu-baseline]
+                    [--workload plain300|plain925_1976|scale|batch|served|motifs] [--no-cpu-baseline]
 
 A step is one pass of the whole path over one batch of synthetic input.  Inputs are protein
 strings handed to the C ABI; the library builds the automaton, uploads it, fills the DP on the
 GPU, runs the canonical traceback and returns the result strings.
-  config2 (default): one 300-aa synthetic protein (Met + 298 uniform residues + stop, seed 1),
+  plain300 (default): one 300-aa synthetic protein (Met + 298 uniform residues + stop, seed 1),
                      designed at lambda = 0 and lambda = 4 in plain mode (one span-step kernel
                      launch per span length);
-  config3:           the 925-aa and 1,976-aa proteins (seed 1) at lambda = 0 and 4, plain mode;
+  plain925_1976:     the 925-aa and 1,976-aa proteins (seed 1) at lambda = 0 and 4, plain mode;
   scale:             one 3,677-aa protein (seed 1) at lambda = 0 and 4, plain mode;
   batch:             256 proteins, lengths log-uniform in [50, 1000] aa (seed 7), half at
                      lambda = 0 and half at lambda = 4, in one batched persistent launch;
   served:            a Poisson request stream through the continuous-batching server, with the
-                     learned candidate sizer against worst-case sizing (see served_workload).
+                     learned candidate sizer against worst-case sizing (see served_workload);
+  motifs:            one 105-aa protein avoiding 16 random 6-mers at lambda = 0 and 4 (the
+                     generic-lattice path).
 
 `value` is DP cells per second of fill time, summed over the step's designs (a cell is a state
 pair (a, b) with rho(a) < rho(b)); fill time is the cost-only interval of the method: device
@@ -51,11 +53,11 @@ METRIC = "DP cells/s + designs/min at lambda in {0,4}, batched/served vs plain, 
 
 def workload(name):
     import sdinputs as S
-    if name == "config2":
+    if name == "plain300":
         p = S.protein(300, 1)
         return [(p, 0.0), (p, 4.0)], {"workload": "plain design, one 300-aa synthetic protein (seed 1), lambda 0 and 4",
                                       "aa": 300, "lambdas": [0, 4], "mode": "plain"}
-    if name == "config3":
+    if name == "plain925_1976":
         items = [(S.protein(A, 1), lam) for A in (925, 1976) for lam in (0.0, 4.0)]
         return items, {"workload": "plain design, synthetic 925-aa and 1976-aa proteins (seed 1), lambda 0 and 4",
                        "aa": [925, 1976], "lambdas": [0, 4], "mode": "plain"}
@@ -298,7 +300,7 @@ def main():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=5)
     ap.add_argument("--warmup", type=int, default=1)
-    ap.add_argument("--workload", default="config2", choices=["config2", "config3", "scale", "batch", "served", "motifs"])
+    ap.add_argument("--workload", default="plain300", choices=["plain300", "plain925_1976", "scale", "batch", "served", "motifs"])
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--retain-all", action="store_true",
                     help="plain workloads: also time the scalar-dense control (every finite direct "

@@ -4,7 +4,7 @@ Calls only oracle/ and sdinputs/ (the seeded generators); nothing here touches t
 The GPU parity tests compare against these files at sizes where running the dense oracle
 inside a test would take minutes.
 
-    python tests/golden/make_golden.py config2 config3 [config4] [stress] [motifs] [motifs_wide]
+    python tests/golden/make_golden.py plain300 plain925_1976 [batch256] [stress] [motifs] [motifs_wide]
 
 The stress families of Sec. 9.2 (poly-S and alternating YI, no Met and no stop) are keyed by
 seed 0 (S) and seed -1 (YI).
@@ -22,8 +22,8 @@ import oracle as O  # noqa: E402
 import sdinputs as S  # noqa: E402
 
 WORKLOADS = {
-    "config2": [(300, seed, lam) for seed in (1, 2, 3, 4) for lam in (0.0, 4.0)],
-    "config3": [(925, 1, 0.0), (925, 1, 4.0), (1976, 1, 0.0), (1976, 1, 4.0)],
+    "plain300": [(300, seed, lam) for seed in (1, 2, 3, 4) for lam in (0.0, 4.0)],
+    "plain925_1976": [(925, 1, 0.0), (925, 1, 4.0), (1976, 1, 0.0), (1976, 1, 4.0)],
 }
 
 
@@ -90,6 +90,6 @@ def run(name, members, nthreads):
 if __name__ == "__main__":
     nthreads = int(os.environ.get("ORACLE_THREADS", "8"))
     for name in sys.argv[1:]:
-        members = (batch_members() if name == "config4" else STRESS if name == "stress"
+        members = (batch_members() if name == "batch256" else STRESS if name == "stress"
                    else MOTIF_SETS[name][1] if name in MOTIF_SETS else WORKLOADS[name])
         run(name, members, nthreads)

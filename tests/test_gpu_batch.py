@@ -73,16 +73,16 @@ def test_batch_rejects_bad_member(sd, ctx, gt, gp):
     assert e.value.code == -2
 
 
-def test_config4_members_vs_golden(ctx, gt, gp):
-    path = os.path.join(HERE, "golden", "config4.json")
+def test_batch256_members_vs_golden(ctx, gt, gp):
+    path = os.path.join(HERE, "golden", "batch256.json")
     if not os.path.exists(path):
-        pytest.skip("config4.json not generated")
+        pytest.skip("batch256.json not generated")
     g = json.load(open(path))
     assert g["params_sha256"] == S.sha256_file(S.default_params_path())
     ds = g["designs"]
     if not ds:
         pytest.skip("no members generated yet")
-    say("config4 golden members", len(ds))
+    say("batch256 golden members", len(ds))
     rb = ctx.design_batch([d["protein"] for d in ds], [d["lambda"] for d in ds], gt, gp)
     for r, d in zip(rb, ds):
         assert (r.energy, r.objective_fixed, r.mrna, r.structure) == (d["energy"], d["objective_fixed"], d["mrna"], d["structure"])

@@ -161,20 +161,20 @@ def _check_golden(r, g):
 
 
 @pytest.mark.parametrize("i", range(8))
-def test_config2_300aa(i, ctx, gtable, gparams):
-    g = _golden("config2")
+def test_plain300_vs_golden(i, ctx, gtable, gparams):
+    g = _golden("plain300")
     if i >= len(g):
         pytest.skip("not generated")
     g = g[i]
-    say("config2", g["seed"], g["lambda"])
+    say("plain300", g["seed"], g["lambda"])
     _check_golden(ctx.design(g["protein"], gtable, gparams, g["lambda"]), g)
 
 
 @pytest.mark.parametrize("i", range(4))
-def test_config3_paper_lengths(i, ctx, gtable, gparams):
-    g = _golden("config3")
+def test_plain925_1976_vs_golden(i, ctx, gtable, gparams):
+    g = _golden("plain925_1976")
     if i >= len(g):
         pytest.skip("not generated")
     g = g[i]
-    say("config3", g["A"], g["lambda"])
+    say("plain925_1976", g["A"], g["lambda"])
     _check_golden(ctx.design(g["protein"], gtable, gparams, g["lambda"]), g)
