@@ -312,7 +312,7 @@ def main():
                     help="only run a plain device copy of this many MiB (counter calibration)")
     args = ap.parse_args()
     if args.gpus != 1:
-        print("bench.py measures one GPU only: this build has no multi-GPU path "
+        print("bench.py measures one GPU only: the library has no multi-GPU path "
               "(independent designs would shard across GPUs without communication)", file=sys.stderr)
         sys.exit(2)
     if args.copy_calibration_mib:
