@@ -387,11 +387,13 @@ int build_lattice(const char* protein, const CodonTable& T, const Params& P, dou
     }
     L.off[n + 1] = (int)L.layer.size();
     const int N = L.N = (int)L.layer.size();
-    for (int p = 0; p <= n; p++)
+    for (int p = 0; p <= n; p++) {
         if (L.off[p + 1] - L.off[p] > 4) {  // kernels buffer at most 4 x 4 cells per layer pair
             err = "automaton layer wider than 4 states";
             return SD_E_INTERNAL;
         }
+        L.wmax = std::max(L.wmax, L.off[p + 1] - L.off[p]);
+    }
     L.out_dst.assign((size_t)4 * N, -1);
     L.out_cod.assign((size_t)4 * N, -1);
     L.out_q.assign((size_t)4 * N, 0.0);
