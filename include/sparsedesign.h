@@ -189,9 +189,21 @@ sd_status sd_inverse_lambda(sd_context *ctx, const char *protein, double target_
 sd_status sd_design_tables(sd_context *ctx, const char *protein, const sd_codon_table *table,
                            const sd_params *params, double lambda_kcal, sd_result *out,
                            int64_t *V, int64_t *B, int64_t *S1, int64_t *S2, int64_t *X);
+/* Test hook: sd_design_motifs plus its tables, in the same dense layout over the product
+ * automaton's states (N = out->n_states; the states are ordered by layer, codon state, matcher
+ * rank). */
+sd_status sd_design_motifs_tables(sd_context *ctx, const char *protein, const char *const *motifs,
+                                  int n_motifs, const sd_codon_table *table, const sd_params *params,
+                                  double lambda_kcal, sd_result *out, int64_t *V, int64_t *B,
+                                  int64_t *S1, int64_t *S2, int64_t *X);
 
 /* Number of automaton states of a protein (to size the sd_design_tables buffers). */
 sd_status sd_lattice_size(const char *protein, int64_t *n_states, int64_t *n_cells);
+/* Size of the product automaton of sd_design_motifs (host only, no device work): states N and
+ * cells.  Errors as for sd_design_motifs' input checks (SD_E_PROTEIN, SD_E_ARG, SD_E_INFEASIBLE,
+ * SD_E_RANGE). */
+sd_status sd_motif_lattice_size(const char *protein, const char *const *motifs, int n_motifs,
+                                int64_t *n_states, int64_t *n_cells);
 
 /* ---- learned candidate-buffer sizing ------------------------------------------------------
  * A small FP32 MLP (22 -> hidden -> hidden -> K, ReLU, sigmoid outputs) trained on the GPU by the

@@ -49,6 +49,9 @@ def lib():
         PC = C.POINTER(C.c_char_p)
         L.or_design_motifs.argtypes = [C.c_char_p, C.POINTER(C.c_double), C.c_void_p, C.c_double, PC,
                                        C.c_int, C.c_int, C.c_char_p, C.c_char_p, C.POINTER(_Res)]
+        L.or_design_motifs_tables.argtypes = [C.c_char_p, C.POINTER(C.c_double), C.c_void_p, C.c_double, PC,
+                                              C.c_int, C.c_int, C.c_char_p, C.c_char_p, C.POINTER(_Res),
+                                              P64, P64, P64, P64, P64]
         L.or_motif_lattice.argtypes = [C.c_char_p, PC, C.c_int, P64, P64, P64, P64]
         L.or_bruteforce_motifs.argtypes = [C.c_char_p, C.POINTER(C.c_double), C.c_void_p, C.c_double,
                                            PC, C.c_int, P64, C.POINTER(C.c_double), P64,
@@ -139,22 +142,34 @@ def _motif_array(motifs):
 INFEASIBLE = -12
 
 
-def design_motifs(protein: str, w, params: Params, lam: float, motifs, nthreads: int = 0) -> Design:
-    """Dense oracle design over the product with the forbidden-motif matcher."""
+def design_motifs(protein: str, w, params: Params, lam: float, motifs, nthreads: int = 0,
+                  tables: bool = False) -> Design:
+    """Dense oracle design over the product with the forbidden-motif matcher; tables=True also
+    returns V (6,N,N), B, D1, D2 (N,N), X (N) over the product's states."""
     n = 3 * len(protein)
     mr = C.create_string_buffer(n + 1)
     st = C.create_string_buffer(n + 1)
     res = _Res()
     wa, wp = _w(w)
     arr, nm = _motif_array(motifs)
-    rc = lib().or_design_motifs(protein.encode(), wp, params.h, lam, arr, nm, nthreads, mr, st,
-                                C.byref(res))
+    arrs = None
+    if tables:
+        N = motif_lattice(protein, motifs)["n_states"]
+        arrs = {"V": np.empty((6, N, N), np.int64), "B": np.empty((N, N), np.int64),
+                "D1": np.empty((N, N), np.int64), "D2": np.empty((N, N), np.int64),
+                "X": np.empty(N, np.int64)}
+        ptrs = [arrs[k].ctypes.data_as(C.POINTER(C.c_int64)) for k in ("V", "B", "D1", "D2", "X")]
+        rc = lib().or_design_motifs_tables(protein.encode(), wp, params.h, lam, arr, nm, nthreads, mr, st,
+                                           C.byref(res), *ptrs)
+    else:
+        rc = lib().or_design_motifs(protein.encode(), wp, params.h, lam, arr, nm, nthreads, mr, st,
+                                    C.byref(res))
     if rc:
         raise OracleError(rc, "or_design_motifs")
     return Design(mr.value.decode(), st.value.decode(), res.energy, res.objective_fixed, res.path_u,
                   res.fixed_shift, res.codon_cost, res.objective_kcal, res.n_states, res.n_edges,
                   res.n_cells, res.n_feasible_direct, res.n_candidates, res.visits_dense,
-                  res.visits_sparse, bool(res.selfcheck_ok), None)
+                  res.visits_sparse, bool(res.selfcheck_ok), arrs)
 
 
 def motif_lattice(protein: str, motifs) -> dict:

@@ -1211,6 +1211,15 @@ int or_design_motifs(const char *protein, const double w[64], const or_params *P
                        NULL, NULL, NULL);
 }
 
+int or_design_motifs_tables(const char *protein, const double w[64], const or_params *P, double lambda,
+                            const char *const *motifs, int nm, int nthreads, char *mrna, char *structure,
+                            or_result *res, int64_t *dbg_V, int64_t *dbg_B, int64_t *dbg_D1,
+                            int64_t *dbg_D2, int64_t *dbg_X) {
+    if (nm < 1) return OR_E_ARG;
+    return design_impl(protein, w, P, lambda, motifs, nm, nthreads, mrna, structure, res, dbg_V, dbg_B,
+                       dbg_D1, dbg_D2, dbg_X);
+}
+
 int or_motif_lattice(const char *protein, const char *const *motifs, int nm, int64_t *n_states,
                      int64_t *n_edges, int64_t *width, int64_t *n_paths) {
     int rc = check_protein(protein);

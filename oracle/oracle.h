@@ -77,6 +77,11 @@ int or_design(const char *protein, const double w[64], const or_params *P, doubl
 int or_design_motifs(const char *protein, const double w[64], const or_params *P, double lambda,
                      const char *const *motifs, int nm, int nthreads, char *mrna, char *structure,
                      or_result *res);
+/* The same with the dense debug tables of or_design (N = states of the product automaton). */
+int or_design_motifs_tables(const char *protein, const double w[64], const or_params *P, double lambda,
+                            const char *const *motifs, int nm, int nthreads, char *mrna, char *structure,
+                            or_result *res, int64_t *dbg_V, int64_t *dbg_B, int64_t *dbg_D1,
+                            int64_t *dbg_D2, int64_t *dbg_X);
 /* Product automaton statistics: states, edges, widest layer and the number of source-to-sink
  * paths (saturating at INT64_MAX); every state lies on such a path (dead states are removed). */
 int or_motif_lattice(const char *protein, const char *const *motifs, int nm, int64_t *n_states,

@@ -31,6 +31,7 @@ EXPORTS = [
     "sd_sizer_predict", "sd_sizer_features", "sd_context_set_sizer", "sd_occupancy",
     "sd_server_start", "sd_server_submit", "sd_server_poll", "sd_server_wait", "sd_server_get_stats",
     "sd_server_stop", "sd_lambda_envelope", "sd_design_motifs", "sd_inverse_lambda",
+    "sd_design_motifs_tables", "sd_motif_lattice_size",
 ]
 
 
@@ -94,6 +95,9 @@ def lib():
                                        C.POINTER(_Result)]
         L.sd_inverse_lambda.argtypes = [vp, C.c_char_p, C.c_double, C.c_double, C.c_int, vp, vp,
                                         C.POINTER(_Result), C.POINTER(C.c_double)]
+        L.sd_design_motifs_tables.argtypes = [vp, C.c_char_p, C.POINTER(C.c_char_p), C.c_int, vp, vp,
+                                              C.c_double, C.POINTER(_Result), P64, P64, P64, P64, P64]
+        L.sd_motif_lattice_size.argtypes = [C.c_char_p, C.POINTER(C.c_char_p), C.c_int, P64, P64]
         L.sd_design_batch.argtypes = [vp, C.c_int, C.POINTER(C.c_char_p), C.POINTER(C.c_double),
                                       vp, vp, C.POINTER(_Result)]
         L.sd_design_tables.argtypes = [vp, C.c_char_p, vp, vp, C.c_double, C.POINTER(_Result),
@@ -292,6 +296,29 @@ class Context:
         _check(lib().sd_design_tables(self.h, protein.encode(), table.h, params.h, float(lam), C.byref(r),
                                       p(V), p(B), p(S1), p(S2), p(X)), "sd_design_tables")
         return _convert(r), {"V": V, "B": B, "S1": S1, "S2": S2, "X": X}
+
+    def design_motifs_tables(self, protein: str, motifs, table: CodonTable, params: Params, lam: float):
+        m = list(motifs)
+        N, _ = motif_lattice_size(protein, m)
+        arr = (C.c_char_p * max(len(m), 1))(*[x.encode() for x in m])
+        V = np.empty((6, N, N), np.int64)
+        B, S1, S2 = (np.empty((N, N), np.int64) for _ in range(3))
+        X = np.empty(N, np.int64)
+        p = lambda a: a.ctypes.data_as(C.POINTER(C.c_int64))
+        r = _Result()
+        _check(lib().sd_design_motifs_tables(self.h, protein.encode(), arr, len(m), table.h, params.h,
+                                             float(lam), C.byref(r), p(V), p(B), p(S1), p(S2), p(X)),
+               "sd_design_motifs_tables")
+        return _convert(r), {"V": V, "B": B, "S1": S1, "S2": S2, "X": X}
+
+
+def motif_lattice_size(protein: str, motifs):
+    m = list(motifs)
+    arr = (C.c_char_p * max(len(m), 1))(*[x.encode() for x in m])
+    n, c = C.c_int64(), C.c_int64()
+    _check(lib().sd_motif_lattice_size(protein.encode(), arr, len(m), C.byref(n), C.byref(c)),
+           "sd_motif_lattice_size")
+    return n.value, c.value
 
 
 def lattice_size(protein: str):

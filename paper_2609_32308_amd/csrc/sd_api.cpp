@@ -699,13 +699,14 @@ extern "C" sd_status sd_lattice_size(const char* protein, int64_t* n_states, int
     return SD_OK;
 }
 
-extern "C" sd_status sd_design_tables(sd_context* ctx, const char* protein, const sd_codon_table* table,
-                                      const sd_params* params, double lambda_kcal, sd_result* out,
-                                      int64_t* V, int64_t* B, int64_t* S1, int64_t* S2, int64_t* X) {
+namespace {
+sd_status design_tables_impl(sd_context* ctx, const char* protein, const std::vector<std::string>* motifs,
+                             const sd_codon_table* table, const sd_params* params, double lambda_kcal,
+                             sd_result* out, int64_t* V, int64_t* B, int64_t* S1, int64_t* S2, int64_t* X) {
     try {
         TraceTables T;
         Lattice L;
-        sd_status s = design_plain(ctx, protein, table, params, lambda_kcal, out, &T, &L, nullptr);
+        sd_status s = design_plain(ctx, protein, table, params, lambda_kcal, out, &T, &L, motifs);
         if (s) return s;
         const size_t N = L.N;
         auto dense = [&](int64_t* dst, const int64_t* src, int stride, int t) {
@@ -727,6 +728,56 @@ extern "C" sd_status sd_design_tables(sd_context* ctx, const char* protein, cons
         return fail(SD_E_NOMEM, "host allocation");
     } catch (...) {
         return fail(SD_E_INTERNAL, "unexpected exception");
+    }
+}
+}  // namespace
+
+extern "C" sd_status sd_motif_lattice_size(const char* protein, const char* const* motifs, int n_motifs,
+                                           int64_t* n_states, int64_t* n_cells) {
+    try {
+        if (!n_states || !n_cells || !motifs || n_motifs < 1 || n_motifs > kMaxMotifs)
+            return fail(SD_E_ARG, "null argument or motif count outside 1..256");
+        std::vector<std::string> ms;
+        for (int i = 0; i < n_motifs; i++) {
+            if (!motifs[i]) return fail(SD_E_ARG, "null motif");
+            ms.push_back(motifs[i]);
+        }
+        CodonTable T;
+        for (int i = 0; i < 64; i++) T.w[i] = 1.0;
+        Params P;
+        memset(&P.E, 0, sizeof(P.E));
+        Lattice L;
+        std::string err;
+        int rc = build_motif_lattice(protein, T, P, 0.0, CapPolicy(), ms, L, err);
+        if (rc) return fail((sd_status)rc, err);
+        *n_states = L.N;
+        *n_cells = L.cells;
+        return SD_OK;
+    } catch (const std::bad_alloc&) {
+        return fail(SD_E_NOMEM, "host allocation");
+    }
+}
+
+extern "C" sd_status sd_design_tables(sd_context* ctx, const char* protein, const sd_codon_table* table,
+                                      const sd_params* params, double lambda_kcal, sd_result* out,
+                                      int64_t* V, int64_t* B, int64_t* S1, int64_t* S2, int64_t* X) {
+    return design_tables_impl(ctx, protein, nullptr, table, params, lambda_kcal, out, V, B, S1, S2, X);
+}
+
+extern "C" sd_status sd_design_motifs_tables(sd_context* ctx, const char* protein, const char* const* motifs,
+                                             int n_motifs, const sd_codon_table* table, const sd_params* params,
+                                             double lambda_kcal, sd_result* out, int64_t* V, int64_t* B,
+                                             int64_t* S1, int64_t* S2, int64_t* X) {
+    try {
+        if (!motifs || n_motifs < 1 || n_motifs > kMaxMotifs) return fail(SD_E_ARG, "need 1 to 256 motifs");
+        std::vector<std::string> ms;
+        for (int i = 0; i < n_motifs; i++) {
+            if (!motifs[i]) return fail(SD_E_ARG, "null motif");
+            ms.push_back(motifs[i]);
+        }
+        return design_tables_impl(ctx, protein, &ms, table, params, lambda_kcal, out, V, B, S1, S2, X);
+    } catch (const std::bad_alloc&) {
+        return fail(SD_E_NOMEM, "host allocation");
     }
 }
 

@@ -9,7 +9,8 @@ matcher; the finite-state constraint experiments) against the dense CPU oracle.
   * an infeasible language, malformed motif lists and an over-wide automaton give their errors,
     and plain designs on the same context are unaffected;
   * a forced candidate-capacity overflow (recomputed with worst-case segments) and the
-    retain-all control reach the oracle's design.
+    retain-all control reach the oracle's design;
+  * the dense cell tables (V, B, S1, S2, X) equal the oracle's at every cell of the product.
 """
 import json
 import os
@@ -154,3 +155,19 @@ def test_motif_overflow_fallback_and_retain_all(sd, gtable, gparams, oparams, we
         (d["energy"], d["objective_fixed"], d["mrna"], d["structure"])
     assert r.n_candidates == d["n_candidates"] and r.n_visits >= d["visits_sparse"]
     c.close()
+
+
+@pytest.mark.parametrize("A,seed,k", [(20, 2, 4), (33, 3, 16), (41, 6, 8)])
+def test_motif_cell_tables(A, seed, k, ctx, gtable, gparams, oparams, weights):
+    # every cell of V_t, B, S1 = D1, S2 = D2 (Theorem 1 on the product automaton) and X equals
+    # the dense oracle's, over the product's states, at sizes that span many layer pairs and spans
+    import numpy as np
+    p = S.protein(A, seed)
+    motifs = S.motifs(k, 30 + seed)
+    for lam in (0.0, 4.0):
+        say("motif tables", A, seed, k, lam)
+        r, T = ctx.design_motifs_tables(p, motifs, gtable, gparams, lam)
+        d = O.design_motifs(p, weights, oparams, lam, motifs, nthreads=8, tables=True)
+        same(r, as_dict(d), motifs)
+        for key, okey in (("V", "V"), ("B", "B"), ("S1", "D1"), ("S2", "D2"), ("X", "X")):
+            assert np.array_equal(T[key], d.tables[okey]), key

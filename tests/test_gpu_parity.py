@@ -88,9 +88,9 @@ def test_cell_tables_equal_dense_oracle(A, seed, lam, ctx, gtable, gparams, opar
 
 @pytest.mark.parametrize("seed", range(1, 9))
 @pytest.mark.parametrize("lam", [0.0, 4.0])
-def test_config1_50aa(seed, lam, ctx, gtable, gparams, oparams, weights):
+def test_plain50(seed, lam, ctx, gtable, gparams, oparams, weights):
     p = S.protein(50, seed)
-    say("config1", seed, lam)
+    say("plain50", seed, lam)
     r = ctx.design(p, gtable, gparams, lam)
     d = O.design(p, weights, oparams, lam, nthreads=8)
     same(r, d)

@@ -177,7 +177,7 @@ def test_lambda_exchange_invariants(seed, oparams, weights):
 
 @pytest.mark.parametrize("seed", range(1, 9))
 @pytest.mark.parametrize("lam", [0.0, 4.0])
-def test_config1_refold_and_evaluate(seed, lam, oparams, weights):
+def test_plain50_refold_and_evaluate(seed, lam, oparams, weights):
     p = S.protein(50, seed)
     d = O.design(p, weights, oparams, lam, nthreads=4)
     assert d.selfcheck_ok
