@@ -405,7 +405,7 @@ sd_status run_plain(sd_context* c, const Lattice& L, Inst& I, int64_t* overflow_
         if (timing) e = hipEventRecord(c->tev[2 * (g - 1)], st);
         if (e == hipSuccess && L.generic)
             e = launch_span_gen(I, (const EnergyTables*)c->E_dev, (const int32_t*)c->spec_dev, g,
-                                g >= 2 ? L.n - g + 1 : -1, st);
+                                g >= 2 ? L.n - g + 1 : -1, c->num_cu, st);
         else if (e == hipSuccess)
             e = launch_span(I, (const EnergyTables*)c->E_dev, (const int32_t*)c->spec_dev, g,
                             g >= 2 ? L.n - g + 1 : -1, span_threads_for(c, L.n - g + 1), st);

@@ -58,7 +58,7 @@ hipError_t launch_span(const Inst& I, const EnergyTables* E, const int32_t* spec
                        int ext_layer, int threads, hipStream_t st);
 hipError_t launch_ext(const Inst& I, const EnergyTables* E, int L, hipStream_t st);
 hipError_t launch_span_gen(const Inst& I, const EnergyTables* E, const int32_t* spec, int g,
-                           int ext_layer, hipStream_t st);
+                           int ext_layer, int num_cu, hipStream_t st);
 hipError_t launch_batch_init(const Inst* insts_dev, int ninst, BatchCtl* ctl, hipStream_t st);
 hipError_t persistent_occupancy(int threads, int* blocks_per_cu);
 hipError_t launch_persistent(const Inst* insts_dev, int ninst, int nsteps, const EnergyTables* E,

@@ -1599,18 +1599,14 @@ hipError_t launch_span(const Inst& I, const EnergyTables* E, const int32_t* spec
 
 // one span step on a generic lattice (same grid as launch_span)
 hipError_t launch_span_gen(const Inst& I, const EnergyTables* E, const int32_t* spec, int g,
-                           int ext_layer, hipStream_t st) {
+                           int ext_layer, int num_cu, hipStream_t st) {
     const int layers = I.n - g + 1;
     const int nblk = layers > 0 ? layers : 0;
     const int total = nblk + (ext_layer >= 0 ? 1 : 0);
     if (total == 0) return hipSuccess;
     if (g >= 5 && nblk > 0) {
-        int cu = 0, dev = 0;
-        hipError_t e = hipGetDevice(&dev);
-        if (e == hipSuccess) e = hipDeviceGetAttribute(&cu, hipDeviceAttributeMultiprocessorCount, dev);
-        if (e != hipSuccess) return e;
-        hipLaunchKernelGGL(k_gen_closed, dim3(4 * cu), dim3(256), 0, st, I, E, spec, g);
-        e = hipGetLastError();
+        hipLaunchKernelGGL(k_gen_closed, dim3(4 * num_cu), dim3(256), 0, st, I, E, spec, g);
+        hipError_t e = hipGetLastError();
         if (e != hipSuccess) return e;
     }
     hipLaunchKernelGGL(k_span_gen, dim3(total), dim3(256), 0, st, I, E, spec, g, ext_layer, nblk);
