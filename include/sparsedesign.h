@@ -114,6 +114,18 @@ void sd_codon_table_free(sd_codon_table *t);
 
 /* Context on HIP device `device` (options may be NULL for defaults). */
 sd_status sd_context_create(int device, const sd_options *opt, sd_context **out);
+/* Context on memory and a stream the caller owns (e.g. a framework's caching allocator and
+ * current stream): every design of the context runs on `hip_stream` (a hipStream_t; NULL is the
+ * device's null stream, on which batched launches run without graph capture) and places its
+ * per-design device tables in [dev_pool, dev_pool + pool_bytes) (device memory, 256-byte aligned,
+ * at least 4 KiB) instead of a library allocation; the device is the pool's.  A design whose
+ * tables do not fit gives SD_E_NOMEM (sd_lattice_size / sd_motif_lattice_size give N and the cell
+ * count; about 72 B per cell plus per-state rings).  The energy tables, pinned host staging
+ * buffers and design servers are still allocated by the library.  sd_context_destroy
+ * synchronises the stream and frees neither the pool nor the stream; both must outlive the
+ * context.  Calls on one context must not overlap, as for sd_context_create. */
+sd_status sd_context_create_external(void *hip_stream, void *dev_pool, size_t pool_bytes,
+                                     const sd_options *opt, sd_context **out);
 void sd_context_destroy(sd_context *ctx);
 
 /* One design, plain mode (Sec. 4.1 recurrences in the span order of Sec. 5, Algorithm 1): the

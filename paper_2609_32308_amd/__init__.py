@@ -31,7 +31,7 @@ EXPORTS = [
     "sd_sizer_predict", "sd_sizer_features", "sd_context_set_sizer", "sd_occupancy",
     "sd_server_start", "sd_server_submit", "sd_server_poll", "sd_server_wait", "sd_server_get_stats",
     "sd_server_stop", "sd_lambda_envelope", "sd_design_motifs", "sd_inverse_lambda",
-    "sd_design_motifs_tables", "sd_motif_lattice_size",
+    "sd_design_motifs_tables", "sd_motif_lattice_size", "sd_context_create_external",
 ]
 
 
@@ -98,6 +98,7 @@ def lib():
         L.sd_design_motifs_tables.argtypes = [vp, C.c_char_p, C.POINTER(C.c_char_p), C.c_int, vp, vp,
                                               C.c_double, C.POINTER(_Result), P64, P64, P64, P64, P64]
         L.sd_motif_lattice_size.argtypes = [C.c_char_p, C.POINTER(C.c_char_p), C.c_int, P64, P64]
+        L.sd_context_create_external.argtypes = [vp, vp, C.c_size_t, C.POINTER(Options), C.POINTER(vp)]
         L.sd_design_batch.argtypes = [vp, C.c_int, C.POINTER(C.c_char_p), C.POINTER(C.c_double),
                                       vp, vp, C.POINTER(_Result)]
         L.sd_design_tables.argtypes = [vp, C.c_char_p, vp, vp, C.c_double, C.POINTER(_Result),
@@ -220,6 +221,19 @@ class Context:
         h = C.c_void_p()
         _check(lib().sd_context_create(device, C.byref(opt), C.byref(h)), "sd_context_create")
         self.h = h
+
+    @classmethod
+    def external(cls, stream: int, pool_ptr: int, pool_bytes: int, retain_all: bool = False,
+                 capacity_override: int = 0, kernel_timing: bool = False):
+        """Context on a caller-owned HIP stream handle and device pool (raw addresses; the caller
+        keeps both alive, e.g. torch.cuda.Stream().cuda_stream and a uint8 CUDA tensor)."""
+        self = cls.__new__(cls)
+        opt = Options(int(retain_all), int(capacity_override), int(kernel_timing), 0, 0, 0)
+        h = C.c_void_p()
+        _check(lib().sd_context_create_external(C.c_void_p(stream), C.c_void_p(pool_ptr), pool_bytes,
+                                                C.byref(opt), C.byref(h)), "sd_context_create_external")
+        self.h = h
+        return self
 
     def close(self):
         if getattr(self, "h", None) and _lib is not None:

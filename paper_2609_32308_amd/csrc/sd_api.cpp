@@ -127,7 +127,10 @@ extern "C" sd_status sd_codon_table_from_freqs(const double f[64], sd_codon_tabl
 extern "C" void sd_codon_table_free(sd_codon_table* t) { delete t; }
 
 // ------------------------------------------------------------------------------------------------
-extern "C" sd_status sd_context_create(int device, const sd_options* opt, sd_context** out) {
+namespace {
+// Context on `device`; with ext_pool the caller's stream and device pool replace the library's own.
+sd_status context_create(int device, const sd_options* opt, bool ext, void* ext_stream, void* ext_pool,
+                         size_t ext_bytes, sd_context** out) {
     if (!out) return fail(SD_E_ARG, "null argument");
     *out = nullptr;
     int ndev = 0;
@@ -163,23 +166,52 @@ extern "C" sd_status sd_context_create(int device, const sd_options* opt, sd_con
             return fail(SD_E_ARG, "batch_per_cu exceeds the co-resident workgroups per CU");
         }
     }
-    if (e == hipSuccess) e = hipStreamCreateWithFlags(&c->stream, hipStreamNonBlocking);
+    if (ext) {
+        c->external = true;
+        c->stream = (hipStream_t)ext_stream;
+        c->arena = ext_pool;
+        c->arena_bytes = ext_bytes;
+    } else if (e == hipSuccess) {
+        e = hipStreamCreateWithFlags(&c->stream, hipStreamNonBlocking);
+    }
     if (e == hipSuccess) e = upload_pair_order();
     if (e == hipSuccess) e = hipEventCreate(&c->ev0);
     if (e == hipSuccess) e = hipEventCreate(&c->ev1);
     if (e != hipSuccess) {
+        if (c->ev0) hipEventDestroy(c->ev0);
+        if (!c->external && c->stream) hipStreamDestroy(c->stream);
         delete c;
         return hip_fail(e, "context setup");
     }
     *out = c;
     return SD_OK;
 }
+}  // namespace
+
+extern "C" sd_status sd_context_create(int device, const sd_options* opt, sd_context** out) {
+    return context_create(device, opt, false, nullptr, nullptr, 0, out);
+}
+
+extern "C" sd_status sd_context_create_external(void* hip_stream, void* dev_pool, size_t pool_bytes,
+                                                const sd_options* opt, sd_context** out) {
+    if (!out) return fail(SD_E_ARG, "null argument");
+    *out = nullptr;
+    if (!dev_pool || pool_bytes < 4096 || ((uintptr_t)dev_pool & 255))
+        return fail(SD_E_ARG, "the device pool must be a 256-byte aligned device allocation of at least 4 KiB");
+    hipPointerAttribute_t at;
+    hipError_t e = hipPointerGetAttributes(&at, dev_pool);
+    if (e != hipSuccess || at.type != hipMemoryTypeDevice) {
+        hipGetLastError();
+        return fail(SD_E_ARG, "the pool is not device memory");
+    }
+    return context_create(at.device, opt, true, hip_stream, dev_pool, pool_bytes, out);
+}
 
 extern "C" void sd_context_destroy(sd_context* c) {
     if (!c) return;
     hipSetDevice(c->device);
-    if (c->stream) hipStreamSynchronize(c->stream);
-    if (c->arena) hipFree(c->arena);
+    hipStreamSynchronize(c->stream);
+    if (c->arena && !c->external) hipFree(c->arena);
     if (c->staging) hipHostFree(c->staging);
     if (c->tbuf) hipHostFree(c->tbuf);
     if (c->E_dev) hipFree(c->E_dev);
@@ -187,7 +219,7 @@ extern "C" void sd_context_destroy(sd_context* c) {
     if (c->ev0) hipEventDestroy(c->ev0);
     if (c->ev1) hipEventDestroy(c->ev1);
     for (hipEvent_t ev : c->tev) hipEventDestroy(ev);
-    if (c->stream) hipStreamDestroy(c->stream);
+    if (c->stream && !c->external) hipStreamDestroy(c->stream);
     delete c;
 }
 
@@ -208,6 +240,9 @@ sd_status ensure_params(sd_context* c, const sd_params* p) {
 
 sd_status ensure_arena(sd_context* c, size_t bytes) {
     if (bytes <= c->arena_bytes) return SD_OK;
+    if (c->external)
+        return fail(SD_E_NOMEM, "the caller's device pool of " + std::to_string(c->arena_bytes) + " bytes cannot hold " +
+                                    std::to_string(bytes) + " bytes");
     if (c->arena) {
         hipStreamSynchronize(c->stream);
         hipFree(c->arena);

@@ -17,6 +17,7 @@ struct sd_context {
     hipEvent_t ev0 = nullptr, ev1 = nullptr;
     void* arena = nullptr;
     size_t arena_bytes = 0;
+    bool external = false;  // arena and stream belong to the caller (sd_context_create_external)
     void* staging = nullptr;  // pinned host image of the input region
     size_t staging_bytes = 0;
     int batch_grid = 0;       // autotuned persistent grid size (0: not tuned yet)

@@ -87,3 +87,32 @@ def test_status_strings():
     L = sd.lib()
     for code in sd.STATUS:
         assert L.sd_status_str(code)
+
+
+@pytest.mark.parametrize("A,seed,k", [(20, 1, 4), (64, 1, 16), (105, 1, 16), (60, 1, 96)])
+def test_motif_lattice_size_matches_oracle(A, seed, k):
+    # the library's product automaton (host only) has the oracle's state count; its cell count is
+    # the row layout's (every state pair with rho(a) < rho(b))
+    import oracle as O
+    p = S.protein(A, seed)
+    motifs = S.motifs(k, 7) if k != 96 else S.motifs(96, 3, 6, 7)
+    N, cells = sd.motif_lattice_size(p, motifs)
+    st = O.motif_lattice(p, motifs)
+    assert N == st["n_states"]
+    assert N * (N - 1) // 2 >= cells > 0
+
+
+def test_motif_lattice_size_errors():
+    with pytest.raises(sd.SDError) as e:
+        sd.motif_lattice_size("KM", ["GA", "AAAA"])
+    assert e.value.code == -12
+    for bad in ([], [""], ["ACGT"], ["A" * 33]):
+        with pytest.raises(sd.SDError) as e:
+            sd.motif_lattice_size("MK*", bad)
+        assert e.value.code == -1
+    with pytest.raises(sd.SDError) as e:
+        sd.motif_lattice_size(S.protein(30, 1), S.motifs(200, 3, 6, 7))
+    assert e.value.code == -6
+    with pytest.raises(sd.SDError) as e:
+        sd.motif_lattice_size("MZ", ["GA"])
+    assert e.value.code == -2
