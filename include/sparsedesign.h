@@ -243,6 +243,14 @@ sd_status sd_sizer_features(const char *protein, double lambda_kcal, float out[2
  * min(worst, ceil(worst * min(1, yhat_k * (1 + margin))) + slack) slots.  The sizer must outlive
  * the context's use of it. */
 sd_status sd_context_set_sizer(sd_context *ctx, const sd_sizer *z, float margin, int slack);
+/* The candidate reservation one request gets under sizer z with (margin, slack) as in
+ * sd_context_set_sizer (host only): *cand_slots slots of 12 bytes (*cand_bytes), beside the
+ * worst case *worst_slots.  This is what a sized context or server reserves for the request
+ * before any overflow (sd_result.cand_slots_first).  SD_E_PROTEIN for a bad protein, SD_E_ARG
+ * for null pointers or negative margin / slack. */
+sd_status sd_sizer_request_bytes(const sd_sizer *z, const char *protein, double lambda_kcal, float margin,
+                                 int slack, int64_t *cand_slots, int64_t *cand_bytes,
+                                 int64_t *worst_slots);
 /* Exact occupancy log: designs n requests (batched, worst-case segments) and writes Y[n][K], the
  * per-bin largest retained fraction of the worst-case slots (see above), plus the results (may
  * be NULL). */

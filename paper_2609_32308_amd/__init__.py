@@ -32,6 +32,7 @@ EXPORTS = [
     "sd_server_start", "sd_server_submit", "sd_server_poll", "sd_server_wait", "sd_server_get_stats",
     "sd_server_stop", "sd_lambda_envelope", "sd_design_motifs", "sd_inverse_lambda",
     "sd_design_motifs_tables", "sd_motif_lattice_size", "sd_context_create_external",
+    "sd_sizer_request_bytes",
 ]
 
 
@@ -99,6 +100,7 @@ def lib():
                                               C.c_double, C.POINTER(_Result), P64, P64, P64, P64, P64]
         L.sd_motif_lattice_size.argtypes = [C.c_char_p, C.POINTER(C.c_char_p), C.c_int, P64, P64]
         L.sd_context_create_external.argtypes = [vp, vp, C.c_size_t, C.POINTER(Options), C.POINTER(vp)]
+        L.sd_sizer_request_bytes.argtypes = [vp, C.c_char_p, C.c_double, C.c_float, C.c_int, P64, P64, P64]
         L.sd_design_batch.argtypes = [vp, C.c_int, C.POINTER(C.c_char_p), C.POINTER(C.c_double),
                                       vp, vp, C.POINTER(_Result)]
         L.sd_design_tables.argtypes = [vp, C.c_char_p, vp, vp, C.c_double, C.POINTER(_Result),
@@ -363,6 +365,13 @@ class Sizer:
         if getattr(self, "h", None) and _lib is not None:
             _lib.sd_sizer_free(self.h)
             self.h = None
+
+    def request_bytes(self, protein: str, lam: float, margin: float = 0.5, slack: int = 8) -> dict:
+        """Candidate slots / bytes this sizer reserves for one request, beside the worst case."""
+        v = [C.c_int64() for _ in range(3)]
+        _check(lib().sd_sizer_request_bytes(self.h, protein.encode(), float(lam), float(margin), int(slack),
+                                            *[C.byref(x) for x in v]), "sd_sizer_request_bytes")
+        return dict(zip(["cand_slots", "cand_bytes", "worst_slots"], [x.value for x in v]))
 
     @property
     def n_params(self) -> int:

@@ -594,6 +594,48 @@ CapPolicy policy_for(const sd_context* c, const char* protein, double lambda, st
     return cp;
 }
 
+}  // namespace sd
+
+// Candidate reservation of one request under a sizer (what a sized context or a server reserves
+// for it before any overflow), beside the worst case; 12 bytes per slot (start state + B).
+extern "C" sd_status sd_sizer_request_bytes(const sd_sizer* z, const char* protein, double lambda_kcal,
+                                            float margin, int slack, int64_t* cand_slots,
+                                            int64_t* cand_bytes, int64_t* worst_slots) {
+    using namespace sd;
+    try {
+        if (!z || !protein || !cand_slots || !cand_bytes || !worst_slots || !(margin >= 0.f) || slack < 0)
+            return fail(SD_E_ARG, "null argument, negative margin or negative slack");
+        float x[22];
+        sd_status s = sd_sizer_features(protein, lambda_kcal, x);
+        if (s) return s;
+        std::vector<float> frac(sizer_bins(z));
+        sizer_predict_host(z, x, frac.data());
+        CodonTable T;
+        for (int i = 0; i < 64; i++) T.w[i] = 1.0;
+        Params P;
+        memset(&P.E, 0, sizeof(P.E));
+        CapPolicy cp;
+        cp.frac = frac.data();
+        cp.K = (int)frac.size();
+        cp.margin = margin;
+        cp.slack = slack;
+        Lattice L;
+        std::string err;
+        int rc = build_lattice(protein, T, P, 0.0, cp, L, err);
+        if (rc) return fail((sd_status)rc, err);
+        *cand_slots = L.cand_slots;
+        *cand_bytes = 12 * L.cand_slots;
+        rc = build_lattice(protein, T, P, 0.0, CapPolicy(), L, err);
+        if (rc) return fail((sd_status)rc, err);
+        *worst_slots = L.cand_slots;
+        return SD_OK;
+    } catch (const std::bad_alloc&) {
+        return fail(SD_E_NOMEM, "host allocation");
+    }
+}
+
+namespace sd {
+
 // Exact occupancy of one finished design: per position bin, the largest fraction of its
 // worst-case slots that any right endpoint of the bin filled with retained strict candidates
 // (endpoints with fewer than 64 worst-case slots are left to the sizing slack).  A reservation

@@ -108,6 +108,11 @@ def test_sizing_policy_keeps_designs_and_saves_memory(sd, params_path, weights):
     for a, b, c in zip(worst, sized, plain):
         assert (a.energy, a.objective_fixed, a.mrna, a.structure) == (b.energy, b.objective_fixed, b.mrna, b.structure)
         assert (b.mrna, b.structure) == (c.mrna, c.structure)
+    # the host-side request estimate is exactly what the sized designs reserved
+    for p, l, a, b, c in zip(test, tl, worst, sized, plain):
+        est = z.request_bytes(p, l, margin=0.5, slack=8)
+        assert est["cand_slots"] == b.cand_slots_first == c.cand_slots_first
+        assert est["worst_slots"] == a.cand_slots_first and est["cand_bytes"] == 12 * est["cand_slots"]
     w = sum(r.cand_slots_first for r in worst)
     m = sum(r.cand_slots_first for r in sized)
     print("reserved slots worst", w, "mlp", m, "overflows", sum(r.cand_overflow for r in sized), flush=True)
