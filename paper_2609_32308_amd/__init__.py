@@ -3,6 +3,11 @@
 Every step of the design DP runs in the library's gfx950 kernels; this module only converts
 arguments and results.  There is no fallback: if the shared library is missing the import of
 `lib()` raises, and without a gfx950 device `Context()` raises SDError(SD_E_DEVICE).
+
+Sharing a process with PyTorch (e.g. `Context.external` on a torch stream and tensor): import
+torch first.  Torch ships its own HIP runtime under the same soname as the system one the
+library links; a process loads only the first, and torch cannot initialise the GPU on a runtime
+the library loaded before it, while the library runs on torch's.
 """
 from __future__ import annotations
 

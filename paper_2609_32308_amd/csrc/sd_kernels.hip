@@ -1,11 +1,14 @@
 // gfx950 kernels of the span wavefront (Sec. 5, Algorithm 1, re-designed for the GPU).
 //
-// One step per span length g.  A wavefront (64 lanes) owns one layer pair (p, q = p + g) and
-// therefore every cell (a, b) with a in layer p and b in layer q; it is the only writer of the
-// candidate segments C_b of its right endpoints in this step (the endpoint-ownership rule of
-// Sec. 5), so appends need no atomics and land in start-state order.  Inside a cell the lanes
-// split the closed-value enumeration and the candidate-prefix scan of eq. (7), then reduce with
+// One step per span length g.  A workgroup (4, 8 or 16 wavefronts) owns one layer pair
+// (p, q = p + g) and therefore every cell (a, b) with a in layer p and b in layer q; it is the
+// only writer of the candidate segments C_b of its right endpoints in this step (the
+// endpoint-ownership rule of Sec. 5), so appends need no atomics and land in start-state order.
+// Its waves split the (cell, type) jobs of the closed values into parts, and inside a part or a
+// cell the lanes split the enumeration and the candidate-prefix scan of eq. (7), then reduce with
 // wavefront min shuffles.  One extra workgroup fills the external column one layer behind.
+// Generic lattices (a forbidden-motif matcher intersected with the codon automaton) have their
+// own span kernels in a section of their own below.
 //
 // Two-loop closure (stack / bulge / interior, l1 + l2 <= 30).  For a generic interior loop the
 // energy is init(l1+l2) + asymmetry + mm[t][x_{i+1}][x_{j-1}] + mm[t'][x_{l+1}][x_{k-1}]: the
@@ -272,7 +275,8 @@ __device__ int64_t bulge_lanes(const IT& I, const SmallE& S, int t, int a1, int 
 // Left segments are the label paths of l1 edges out of a1, right segments the paths of l2 edges
 // into b1.  The (pair, left path, right path) combinations of all such pairs are flattened over
 // the lanes: lane k < #pairs publishes its pair's combination count, a wave prefix sum gives
-// the offsets, and every lane decodes its own combinations.
+// the offsets, and every lane decodes its own combinations.  When nh waves share the list, the
+// wave with index h takes the blocks of 64 combinations h, h + nh, ...
 struct LabPair {
     int f0, nl, r0, nr, l1, l2, start;
 };

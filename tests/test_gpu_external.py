@@ -6,12 +6,23 @@ caller's stream) and forbidden-motif designs must be identical to those of a lib
 context; the library must write into the caller's pool, report SD_E_NOMEM when a design does not
 fit, reject pools that are not aligned device memory, and leave pool and stream alive when the
 context is destroyed.
+
+PyTorch and the library each ship a HIP runtime with the same soname, and a process loads only
+the first: torch works when it is imported before the library (the library then runs on torch's
+runtime), not after.  Earlier tests of this session have loaded the library already, so the
+checks run in a fresh child process that imports torch first.
 """
+import os
+import subprocess
+import sys
+
 import pytest
 
 import sdinputs as S
 
 pytestmark = pytest.mark.gpu
+HERE = os.path.dirname(os.path.abspath(__file__))
+ROOT = os.path.dirname(HERE)
 
 
 def say(*a):
@@ -22,10 +33,21 @@ def key(r):
     return (r.energy, r.objective_fixed, r.mrna, r.structure, r.n_candidates, r.n_visits)
 
 
-def test_external_pool_and_stream(params_path, weights):
-    import torch
+def test_external_pool_and_stream():
+    code = ("import torch, sys; sys.path[:0] = [%r, %r]; import test_gpu_external as t; t.interop()"
+            % (ROOT, HERE))
+    say("external: child process (torch first)")
+    r = subprocess.run([sys.executable, "-u", "-c", code], capture_output=True, text=True, timeout=300)
+    print(r.stdout, r.stderr[-3000:], flush=True)
+    assert r.returncode == 0
+    assert "interop ok" in r.stdout
+
+
+def interop():
+    import torch  # before the library: one HIP runtime for both
     import paper_2609_32308_amd as sd
-    gp, gt = sd.Params(params_path), sd.CodonTable(weights)
+    gp = sd.Params(S.default_params_path())
+    gt = sd.CodonTable(S.codon_weights(2026))
     p = S.protein(120, 4)
     batch = [S.protein(A, 500 + i) for i, A in enumerate((40, 75, 130, 60))]
     lams = [0.0, 4.0, 0.0, 4.0]
@@ -73,3 +95,4 @@ def test_external_pool_and_stream(params_path, weights):
     with pytest.raises(sd.SDError) as e:
         sd.Context.external(stream.cuda_stream, host.data_ptr(), host.numel())
     assert e.value.code == -1
+    say("interop ok")
