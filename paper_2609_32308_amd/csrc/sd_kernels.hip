@@ -221,7 +221,8 @@ __device__ int64_t hairpin_lane(const IT& I, const SmallE& S, const int32_t* __r
 // ---- two-loop closure: bulges and stacks ----------------------------------------------------------
 // No boundary bases enter a bulge or stack energy, so each unpaired side costs its minimum
 // (the gap).  The explicit pairs (stack, bulges of 1 and 2) are flattened over the lanes as
-// (pair, inner left state, inner right state); each lane evaluates the six inner types.
+// (pair, inner left state, inner right state), counting only the states the inner layers hold;
+// each lane evaluates the six inner types.
 template <class IT>
 __device__ __forceinline__ int64_t gap_l(const IT& I, int a, int la, int b, int lb) {  // gap() with known layers
     if (la == lb) return a == b ? 0 : kINF;
@@ -237,25 +238,33 @@ template <class IT>
 __device__ int64_t bulge_lanes(const IT& I, const SmallE& S, int t, int a1, int b1, int64_t Uab, int p,
                                int q, int cap, int lane) {
     const int s = I.shift;
+    // The explicit pairs (l1, l2) are (0,0), (0,1), (1,0), (0,2), (2,0), those with l1 + l2 <= cap.
+    // One side of a bulge is empty, so after the stack each pair's items are the states of its one
+    // inner layer: q-2, p+2, q-3, p+3.
+    const int r1 = cap >= 1 ? I.off()[q - 2] : 0, nr1 = cap >= 1 ? I.off()[q - 1] - r1 : 0;
+    const int l1s = cap >= 1 ? I.off()[p + 2] : 0, nl1 = cap >= 1 ? I.off()[p + 3] - l1s : 0;
+    const int r2 = cap >= 2 ? I.off()[q - 3] : 0, nr2 = cap >= 2 ? r1 - r2 : 0;
+    const int l2s = cap >= 2 ? I.off()[p + 3] : 0, nl2 = cap >= 2 ? I.off()[p + 4] - l2s : 0;
+    const int tot = 1 + nr1 + nl1 + nr2 + nl2;
     int64_t best = kINF;
-    const int npairs = kPairCnt[kListBulge][0][cap];  // <= 5
-    for (int idx = lane; idx < npairs * kMaxWidth * kMaxWidth; idx += 64) {
-        const int k = idx / (kMaxWidth * kMaxWidth), ci = (idx / kMaxWidth) % kMaxWidth, di = idx % kMaxWidth;
-        const int code = kPairList[kListBulge][0][k], l1 = code & 31, l2 = (code >> 5) & 31;
+    for (int idx = lane; idx < tot; idx += 64) {
+        int l1 = 0, l2 = 0, c = a1, d = b1, r = idx - 1;
+        if (idx == 0) {
+        } else if (r < nr1) {
+            l2 = 1;
+            d = r1 + r;
+        } else if ((r -= nr1) < nl1) {
+            l1 = 1;
+            c = l1s + r;
+        } else if ((r -= nl1) < nr2) {
+            l2 = 2;
+            d = r2 + r;
+        } else {
+            r -= nr2;
+            l1 = 2;
+            c = l2s + r;
+        }
         const int cl = p + 1 + l1, dl = q - 1 - l2;
-        int c = a1, d = b1;
-        if (l1 == 0) {
-            if (ci) continue;
-        } else {
-            c = I.off()[cl] + ci;
-            if (c >= I.off()[cl + 1]) continue;
-        }
-        if (l2 == 0) {
-            if (di) continue;
-        } else {
-            d = I.off()[dl] + di;
-            if (d >= I.off()[dl + 1]) continue;
-        }
         const int64_t gl = l1 == 0 ? 0 : gap_l(I, a1, p + 1, c, cl);
         const int64_t gr = l2 == 0 ? 0 : gap_l(I, d, dl, b1, q - 1);
         if (gl >= kINF || gr >= kINF) continue;
@@ -1562,7 +1571,7 @@ hipError_t upload_pair_order() {
                     int lst;
                     unsigned short code = (unsigned short)(a | b << 5);
                     if ((a == 0 || b == 0) && a + b >= 3) lst = kListBulgeSep;
-                    else if (a == 0 || b == 0) lst = kListBulge;
+                    else if (a == 0 || b == 0) lst = kListBulge;  // (0,0) (0,1) (1,0) (0,2) (2,0), enumerated directly by bulge_lanes
                     else if (sl && sr) lst = kListFast;
                     else if (!sl && !sr) lst = kListLab;
                     else {
