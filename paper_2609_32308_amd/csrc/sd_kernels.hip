@@ -102,10 +102,31 @@ __device__ __forceinline__ int64_t shfl_xor64(int64_t v, int m) {
     int hi = __shfl_xor((int)(uint32_t)((uint64_t)v >> 32), m, 64);
     return (int64_t)(((uint64_t)(uint32_t)hi << 32) | (uint64_t)(uint32_t)lo);
 }
+// DPP moves of a 64-bit value within rows of 16 lanes (no LDS traffic).  Callers run with every
+// lane of the wave active.
+template <int CTRL>
+__device__ __forceinline__ int64_t dpp64(int64_t v) {
+    const int lo = (int)(uint32_t)(uint64_t)v, hi = (int)(uint32_t)((uint64_t)v >> 32);
+    const int l2 = __builtin_amdgcn_update_dpp(lo, lo, CTRL, 0xF, 0xF, false);
+    const int h2 = __builtin_amdgcn_update_dpp(hi, hi, CTRL, 0xF, 0xF, false);
+    return (int64_t)(((uint64_t)(uint32_t)h2 << 32) | (uint64_t)(uint32_t)l2);
+}
+constexpr int kDppXor1 = 0xB1, kDppXor2 = 0x4E;               // quad_perm [1,0,3,2], [2,3,0,1]
+constexpr int kDppHalfMirror = 0x141, kDppMirror = 0x140;     // lane i <-> 7-i, 15-i of its row
+constexpr int kDppRor4 = 0x124, kDppRor8 = 0x128;             // rotate the row by 4, 8 lanes
+__device__ __forceinline__ int64_t readlane64(int64_t v, int l) {
+    const int lo = __builtin_amdgcn_readlane((int)(uint32_t)(uint64_t)v, l);
+    const int hi = __builtin_amdgcn_readlane((int)(uint32_t)((uint64_t)v >> 32), l);
+    return (int64_t)(((uint64_t)(uint32_t)hi << 32) | (uint64_t)(uint32_t)lo);
+}
+// minimum over the whole wave (every lane active): DPP within each row of 16 lanes, then the
+// four row minima on the scalar unit
 __device__ __forceinline__ int64_t wave_min(int64_t v) {
-#pragma unroll
-    for (int m = 32; m > 0; m >>= 1) v = mn(v, shfl_xor64(v, m));
-    return v;
+    v = mn(v, dpp64<kDppXor1>(v));
+    v = mn(v, dpp64<kDppXor2>(v));
+    v = mn(v, dpp64<kDppHalfMirror>(v));
+    v = mn(v, dpp64<kDppMirror>(v));
+    return mn(mn(readlane64(v, 0), readlane64(v, 16)), mn(readlane64(v, 32), readlane64(v, 48)));
 }
 
 template <class IT>
@@ -600,9 +621,13 @@ __device__ void produce_state(const IT& I, const SmallE& S, const GroupShared<NW
             }
         }
 #pragma unroll
-        for (int j = 0; j < 4; j++)
-#pragma unroll
-            for (int m = 4; m < 64; m <<= 1) o[j] = mn(o[j], shfl_xor64(o[j], m));
+        for (int j = 0; j < 4; j++) {
+            // over the lanes that share lane & 3: rotations by 4 and 8 within each row, then rows
+            o[j] = mn(o[j], dpp64<kDppRor4>(o[j]));
+            o[j] = mn(o[j], dpp64<kDppRor8>(o[j]));
+            o[j] = mn(o[j], shfl_xor64(o[j], 16));
+            o[j] = mn(o[j], shfl_xor64(o[j], 32));
+        }
         if (grp == 0) {
             int64_t* T = left ? I.RS() : I.LS();
 #pragma unroll
@@ -627,8 +652,8 @@ __device__ void produce_state(const IT& I, const SmallE& S, const GroupShared<NW
                 }
             }
         }
-        acc = mn(acc, shfl_xor64(acc, 1));
-        acc = mn(acc, shfl_xor64(acc, 2));
+        acc = mn(acc, dpp64<kDppXor1>(acc));
+        acc = mn(acc, dpp64<kDppXor2>(acc));
         acc = norm_inf(acc);
         if (X < 3 && z == 0) {
             if (left) {
