@@ -330,20 +330,26 @@ __device__ int64_t labelled_pairs(const IT& I, const SmallE& S, const EnergyTabl
         cnt = x.nl * x.nr;
         lp[lane] = x;
     }
-    int incl = cnt;  // inclusive prefix over lanes 0..15
-#pragma unroll
-    for (int o = 1; o < 16; o <<= 1) {
-        const int v = __shfl_up(incl, o, 64);
-        if ((lane & 15) >= o) incl += v;
-    }
+    // inclusive prefix over lanes 0..15 (the first row) by DPP row shifts; a shifted-in lane
+    // from outside the row reads 0
+    int incl = cnt;
+    incl += __builtin_amdgcn_update_dpp(0, incl, 0x111, 0xF, 0xF, false);  // row_shr:1
+    incl += __builtin_amdgcn_update_dpp(0, incl, 0x112, 0xF, 0xF, false);  // row_shr:2
+    incl += __builtin_amdgcn_update_dpp(0, incl, 0x114, 0xF, 0xF, false);  // row_shr:4
+    incl += __builtin_amdgcn_update_dpp(0, incl, 0x118, 0xF, 0xF, false);  // row_shr:8
     if (lane < npairs) lp[lane].start = incl - cnt;
-    const int total = __shfl(incl, 15, 64);
+    const int total = __builtin_amdgcn_readlane(incl, 15);
+    // pair starts on the scalar unit (a lane at or past npairs starts at total)
+    int pst[16];
+#pragma unroll
+    for (int j = 1; j < 16; j++) pst[j] = __builtin_amdgcn_readlane(incl - cnt, j);
     __builtin_amdgcn_wave_barrier();
     __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
     int64_t best = kINF;
     for (int idx = lane + 64 * h; idx < total; idx += 64 * nh) {
-        int k = 0;
-        while (k + 1 < npairs && lp[k + 1].start <= idx) k++;
+        int k = 0;  // the last pair whose start is <= idx
+#pragma unroll
+        for (int j = 1; j < 16; j++) k += pst[j] <= idx;
         const LabPair x = lp[k];
         const int r = idx - x.start, i = r / x.nr, j = r - i * x.nr;
         const int fm = I.fwd_meta()[x.f0 + i], bm = I.bwd_meta()[x.r0 + j];
