@@ -490,7 +490,7 @@ __device__ int64_t one_sided(const IT& I, const SmallE& S, int a1, int b1, int64
 
 // ---- the work of one layer pair (p, q) in span step g: one workgroup of several waves ----------
 struct GroupCounters {
-    unsigned long long visits, appends, feasible;
+    unsigned long long visits, feasible;
 };
 
 
@@ -506,11 +506,52 @@ struct GroupShared {
     LabPair lab[NW][16];
 };
 
+// Bulges of >= 3 bases through the in-edge b1 -> b: the unpaired side costs its gap (tail +
+// whole codons), read from the BI / BJ rings.
+template <class IT>
+__device__ int64_t long_bulges(const IT& I, const SmallE& S, int t, int a1, int b1, int64_t Uab, int p,
+                               int q, int cap, int lane) {
+    const int s = I.shift;
+    int64_t v = kINF;
+    for (int k = lane; k < kPairCnt[kListBulgeSep][0][cap]; k += 64) {
+        const int code = kPairList[kListBulgeSep][0][k], l1 = code & 31, l2 = (code >> 5) & 31;
+        const int l = l1 + l2, cl = p + 1 + l1, dl = q - 1 - l2;
+        int64_t w;
+        if (l1 == 0) {
+            const int64_t bi = I.BI()[(int64_t)a1 * kLMRing + ((dl - cl) & (kLMRing - 1))];
+            w = bi >= kINF ? kINF : Uab + bi + I.P()[(q - 1) / 3] - I.P()[dl / 3 + 1];
+        } else {
+            const int64_t bj = I.BJ()[(int64_t)b1 * kLMRing + ((dl - cl) & (kLMRing - 1))];
+            w = bj >= kINF ? kINF : Uab + bj + I.tail()[a1] + I.P()[cl / 3] - I.P()[(p + 1) / 3 + 1];
+        }
+        if (w < kINF) v = mn(v, w + fx(S.bulge[l] + au_pen(S, t), s));
+    }
+    return v;
+}
+
+// Multiloop closure (ML_closing + ML_intern + AU) + S2 of the interior, over the in-edges of b
+// labelled y.
+template <class IT>
+__device__ int64_t ml_closure(const IT& I, const SmallE& S, int t, int a1, int64_t Ua, int y, int ib0,
+                              int ib1, int p, int g, int lane) {
+    int64_t v = kINF;
+    if (g < 12) return v;
+    const int32_t mlc = S.ml_closing + S.ml_intern + au_pen(S, t);
+    for (int eb = ib0 + lane; eb < ib1; eb += 64) {
+        if (I.in_lab()[eb] != y) continue;
+        const int b1 = I.in_src()[eb];
+        if (I.layer()[b1] - (p + 1) < 10) continue;
+        v = mn(v, I.S2()[cell_of(I, a1, b1)] + Ua + I.in_U()[eb] + fx(mlc, I.shift));
+    }
+    return v;
+}
+
 // One part of the typed closed value V_t(a, b), with the lanes of one wave:
-//   part 0: hairpin, stacks and bulges, multiloop closure;
+//   part 0: hairpin, stacks and bulges of 1-2 bases;
 //   part 1: interior loops with a separable side (one-sided, both separable);
 //   parts 2 .. nparts-1: interior loops with both sides explicit (labelled short paths), whose
-//   flattened items are dealt to these parts in blocks of 64.
+//   flattened items are dealt to these parts in blocks of 64;
+//   bulges of >= 3 bases and the multiloop closure: the last part when nparts >= 4, else part 0.
 // The parts of one (cell, type) run on different waves and meet in an LDS minimum.
 template <class IT>
 __device__ int64_t closed_part(const IT& I, const SmallE& S, const EnergyTables* __restrict__ E,
@@ -523,6 +564,9 @@ __device__ int64_t closed_part(const IT& I, const SmallE& S, const EnergyTables*
     const int ib0 = I.in_start()[b], ib1 = I.in_start()[b + 1];
     const int ph = (p % 3) * 3 + (q % 3), cap = min(g - 7, kMaxLoop);
     int64_t v = kINF;
+    // bulges of >= 3 bases and the multiloop closure go with the last labelled part when the
+    // labelled list is split, else with part 0
+    const bool long_here = part == (nparts >= 4 ? nparts - 1 : 0);
     if (part == 0) {
         v = hairpin_lane(I, S, spec, a, b, t, a1, Ua, p, g, lane);
         if (g >= 7) {
@@ -531,32 +575,10 @@ __device__ int64_t closed_part(const IT& I, const SmallE& S, const EnergyTables*
                 const int b1 = I.in_src()[eb];
                 const int64_t Uab = Ua + I.in_U()[eb];
                 v = mn(v, bulge_lanes(I, S, t, a1, b1, Uab, p, q, cap, lane));
-                // bulges of >= 3 bases: the unpaired side costs its gap (tail + whole codons)
-                for (int k = lane; k < kPairCnt[kListBulgeSep][0][cap]; k += 64) {
-                    const int code = kPairList[kListBulgeSep][0][k], l1 = code & 31, l2 = (code >> 5) & 31;
-                    const int l = l1 + l2, cl = p + 1 + l1, dl = q - 1 - l2;
-                    int64_t w;
-                    if (l1 == 0) {
-                        const int64_t bi = I.BI()[(int64_t)a1 * kLMRing + ((dl - cl) & (kLMRing - 1))];
-                        w = bi >= kINF ? kINF : Uab + bi + I.P()[(q - 1) / 3] - I.P()[dl / 3 + 1];
-                    } else {
-                        const int64_t bj = I.BJ()[(int64_t)b1 * kLMRing + ((dl - cl) & (kLMRing - 1))];
-                        w = bj >= kINF ? kINF : Uab + bj + I.tail()[a1] + I.P()[cl / 3] - I.P()[(p + 1) / 3 + 1];
-                    }
-                    if (w < kINF) v = mn(v, w + fx(S.bulge[l] + au_pen(S, t), s));
-                }
+                if (long_here) v = mn(v, long_bulges(I, S, t, a1, b1, Uab, p, q, cap, lane));
             }
         }
-        if (g >= 12) {
-            // multiloop closure (ML_closing + ML_intern + AU) + S2 of the interior
-            const int32_t mlc = S.ml_closing + S.ml_intern + au_pen(S, t);
-            for (int eb = ib0 + lane; eb < ib1; eb += 64) {
-                if (I.in_lab()[eb] != y) continue;
-                const int b1 = I.in_src()[eb];
-                if (I.layer()[b1] - (p + 1) < 10) continue;
-                v = mn(v, I.S2()[cell_of(I, a1, b1)] + Ua + I.in_U()[eb] + fx(mlc, s));
-            }
-        }
+        if (long_here) v = mn(v, ml_closure(I, S, t, a1, Ua, y, ib0, ib1, p, g, lane));
     } else if (part >= 2) {
         if (g >= 7) {
             for (int eb = ib0; eb < ib1; eb++) {
@@ -564,8 +586,10 @@ __device__ int64_t closed_part(const IT& I, const SmallE& S, const EnergyTables*
                 const int b1 = I.in_src()[eb];
                 const int64_t Uab = Ua + I.in_U()[eb];
                 v = mn(v, labelled_pairs(I, S, E, t, a1, b1, Uab, ph, cap, lane, lab, part - 2, nparts - 2));
+                if (long_here) v = mn(v, long_bulges(I, S, t, a1, b1, Uab, p, q, cap, lane));
             }
         }
+        if (long_here) v = mn(v, ml_closure(I, S, t, a1, Ua, y, ib0, ib1, p, g, lane));
     } else {
         if (g >= 7) {
             const int64_t* oa = I.OA() + (int64_t)(a1 * 6 + t) * 12;
@@ -695,7 +719,7 @@ __device__ GroupCounters span_group(const IT& I, const SmallE& S, const EnergyTa
                                     const int32_t* __restrict__ spec, int p, int q, GroupShared<NW>& G) {
     const int g = q - p, s = I.shift;
     const int tid = threadIdx.x, wave = tid >> 6, lane = tid & 63, nw = blockDim.x >> 6;
-    GroupCounters ctr{0, 0, 0};
+    GroupCounters ctr{0, 0};
     const int a_lo = I.off()[p], a_hi = I.off()[p + 1], b_lo = I.off()[q], b_hi = I.off()[q + 1];
     const int wa = a_hi - a_lo, wb = b_hi - b_lo, ncell = wa * wb;
     // both-separable interior minima of this layer pair, per class (prepared one step ahead)
@@ -828,9 +852,6 @@ __device__ GroupCounters span_group(const IT& I, const SmallE& S, const EnergyTa
             }
             if (added) I.ccnt()[b] = min(committed + added, I.ccap()[b]);
         }
-        added += __shfl_xor(added, 1, 64);
-        added += __shfl_xor(added, 2, 64);
-        ctr.appends += (unsigned long long)added;
     }
     // both-separable minima of the next span's pair (p, q + 1), by the waves other than wave 0
     // (busy with the appends): they read LM of spans <= g - 7, complete before this step
@@ -937,7 +958,7 @@ __global__ __launch_bounds__(NT) void k_span(Inst I, const EnergyTables* __restr
     }
     const int p = xcd_band(blockIdx.x, nblk_cells), q = p + g;
     GroupCounters c = span_group(I, S, E, spec, p, q, G);
-    // block-sum the counters (each wave counted its own cells; thread 0 counted appends)
+    // each wave counted its own cells
     const int lane = threadIdx.x & 63;
     flush_counters(I, c, p, lane);
 }
@@ -1240,7 +1261,7 @@ __device__ GroupCounters gen_span_group(const IT& I, const SmallE& S, const Ener
                                         const int32_t* __restrict__ spec, int p, int q, GenShared& G) {
     const int g = q - p, s = I.shift;
     const int tid = threadIdx.x, wave = tid >> 6, lane = tid & 63, nw = blockDim.x >> 6;
-    GroupCounters ctr{0, 0, 0};
+    GroupCounters ctr{0, 0};
     const int a_lo = I.off()[p], a_hi = I.off()[p + 1], b_lo = I.off()[q], b_hi = I.off()[q + 1];
     const int wa = a_hi - a_lo, wb = b_hi - b_lo, ncell = wa * wb;
     // gap tables of this span's cells (only later spans read them)
@@ -1343,8 +1364,6 @@ __device__ GroupCounters gen_span_group(const IT& I, const SmallE& S, const Ener
             }
             if (added) I.ccnt()[b] = min(committed + added, I.ccap()[b]);
         }
-        for (int m = 1; m < 64; m <<= 1) added += __shfl_xor(added, m, 64);
-        ctr.appends += (unsigned long long)added;
     }
     return ctr;
 }
