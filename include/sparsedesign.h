@@ -66,7 +66,7 @@ typedef struct sd_options {
                               context's stream and report the summed kernel time            */
     int span_threads;      /* workgroup size of the plain-mode span step: 0 (library choice per
                               span: 1024 while the span has at most one layer pair per CU, 512
-                              while its pairs fit 4 per CU, else 256), 64, 256, 512 or 1024;
+                              up to 12 pairs per CU, else 256), 64, 256, 512 or 1024;
                               anything else gives SD_E_ARG at create */
     int batch_threads;     /* persistent (batched / served) launch: threads per workgroup, 64,
                               256 or 512, with batch_per_cu workgroups per CU; both 0: autotuned */

@@ -409,11 +409,12 @@ hipError_t read_stats(const Inst& I, hipStream_t st, unsigned long long out[4]) 
 
 // Workgroup size of the span step for a span with `pairs` layer pairs.  Eight or sixteen waves
 // per pair shorten each pair's critical path (more of its typed-value job parts run at once) but
-// leave fewer workgroups resident per CU, so eight pay only while every pair of the span still
-// fits in about SPAN_WIDE_PER_CU workgroups per CU, and sixteen while there is at most one pair
-// per CU.
+// leave fewer workgroups resident per CU (three of eight waves, against four of four), so eight
+// pay only up to about SPAN_WIDE_PER_CU pairs per CU (of 2, 3, 4, 6, 12 and 64, 12 was fastest
+// on a 1,976-aa design and 4 to 64 tied on a 300-aa one), and sixteen while there is at most one
+// pair per CU.
 #ifndef SPAN_WIDE_PER_CU
-#define SPAN_WIDE_PER_CU 4
+#define SPAN_WIDE_PER_CU 12
 #endif
 #ifndef SPAN_XWIDE_PER_CU
 #define SPAN_XWIDE_PER_CU 1

@@ -943,10 +943,11 @@ __device__ __forceinline__ int xcd_band(int i, int nb) {
 }
 
 // ---- the span step (plain mode): layer pair xcd_band(x) for block x < layer pairs ---------------
+// The 512-thread instantiation is held to 80 VGPRs so that three of its workgroups fit a CU.
 template <int NT>
-__global__ __launch_bounds__(NT) void k_span(Inst I, const EnergyTables* __restrict__ E,
-                                             const int32_t* __restrict__ spec, int g,
-                                             int ext_layer, int nblk_cells) {
+__global__ __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(NT == 512 ? 6 : 1)))
+void k_span(Inst I, const EnergyTables* __restrict__ E, const int32_t* __restrict__ spec, int g,
+            int ext_layer, int nblk_cells) {
     __shared__ SmallE S;
     __shared__ int64_t red[NT];
     __shared__ GroupShared<NT / 64> G;
