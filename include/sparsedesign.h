@@ -62,8 +62,10 @@ typedef struct sd_options {
                               instead of the strict test B < P_S (Sec. 8.1); same optimum     */
     int capacity_override; /* >0: candidate slots per right endpoint (forces the overflow
                               fallback when small; results are unchanged); 0: worst case      */
-    int kernel_timing;     /* 1: bracket every span-step launch with HIP events on the
-                              context's stream and report the summed kernel time            */
+    int kernel_timing;     /* k > 0: bracket every k-th span-step launch (spans 1, 1+k, ...)
+                              with HIP events on the context's stream and report their summed
+                              duration and count; an event between two launches adds a gap,
+                              so k > 1 keeps the fill close to an untimed one              */
     int span_threads;      /* workgroup size of the plain-mode span step: 0 (library choice per
                               span: 1024 while the span has at most one layer pair per CU, 512
                               up to 12 pairs per CU, else 256), 64, 256, 512 or 1024;
@@ -90,12 +92,14 @@ typedef struct sd_result {
     int64_t n_feasible;      /* cells with finite direct branch cost B                        */
     double t_fill_s;         /* cost-only time: allocation + forward fill (Sec. 6)             */
     double t_total_s;        /* complete time: input -> strings                                */
-    double t_span_kernels_s; /* with kernel_timing: summed duration of the span-step kernels  */
+    double t_span_kernels_s; /* with kernel_timing: summed duration of the timed span-step
+                                launches (batched: this member's share of the persistent one) */
     int64_t n_span_launches; /* span-step kernel launches of the forward fill                  */
     int64_t cand_slots;      /* candidate slots reserved for the fill that produced the result */
     int64_t cand_slots_first;/* slots reserved by the first attempt (before any fallback)      */
     int32_t cand_overflow;   /* 1 if the first attempt's reservation overflowed (then exact
                                 worst-case segments were used; the result is unchanged)       */
+    int64_t n_timed_launches;/* span-step launches timed with kernel_timing (plain mode)       */
 } sd_result;
 
 /* Parameter file (project text format "SPARSEDESIGN-PARAMS 1"; Turner-2004 d0 array shapes,

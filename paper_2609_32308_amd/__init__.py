@@ -74,6 +74,7 @@ class _Result(C.Structure):
         ("n_feasible", C.c_int64), ("t_fill_s", C.c_double), ("t_total_s", C.c_double),
         ("t_span_kernels_s", C.c_double), ("n_span_launches", C.c_int64),
         ("cand_slots", C.c_int64), ("cand_slots_first", C.c_int64), ("cand_overflow", C.c_int32),
+        ("n_timed_launches", C.c_int64),
     ]
 
 
@@ -207,6 +208,7 @@ class Result:
     cand_slots: int
     cand_slots_first: int
     cand_overflow: int
+    n_timed_launches: int
 
 
 def _convert(r: _Result) -> Result:
@@ -214,14 +216,14 @@ def _convert(r: _Result) -> Result:
                  r.codon_cost, r.objective_kcal, r.objective_fixed, r.fixed_shift, r.cai, r.n_states,
                  r.n_cells, r.n_candidates, r.n_visits, r.n_feasible, r.t_fill_s, r.t_total_s,
                  r.t_span_kernels_s, r.n_span_launches, r.cand_slots, r.cand_slots_first,
-                 r.cand_overflow)
+                 r.cand_overflow, r.n_timed_launches)
     lib().sd_result_free(C.byref(r))
     return out
 
 
 class Context:
     def __init__(self, device: int = 0, retain_all: bool = False, capacity_override: int = 0,
-                 kernel_timing: bool = False, span_threads: int = 0, batch_threads: int = 0,
+                 kernel_timing: int = 0, span_threads: int = 0, batch_threads: int = 0,
                  batch_per_cu: int = 0):
         opt = Options(int(retain_all), int(capacity_override), int(kernel_timing), int(span_threads),
                       int(batch_threads), int(batch_per_cu))
@@ -231,7 +233,7 @@ class Context:
 
     @classmethod
     def external(cls, stream: int, pool_ptr: int, pool_bytes: int, retain_all: bool = False,
-                 capacity_override: int = 0, kernel_timing: bool = False):
+                 capacity_override: int = 0, kernel_timing: int = 0):
         """Context on a caller-owned HIP stream handle and device pool (raw addresses; the caller
         keeps both alive, e.g. torch.cuda.Stream().cuda_stream and a uint8 CUDA tensor)."""
         self = cls.__new__(cls)

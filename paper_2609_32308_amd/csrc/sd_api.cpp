@@ -152,6 +152,10 @@ sd_status context_create(int device, const sd_options* opt, bool ext, void* ext_
         delete c;
         return fail(SD_E_ARG, "span_threads must be 0, 64, 256, 512 or 1024");
     }
+    if (c->opt.kernel_timing < 0) {
+        delete c;
+        return fail(SD_E_ARG, "kernel_timing must be >= 0");
+    }
     if ((c->opt.batch_threads != 0 && c->opt.batch_threads != 64 && c->opt.batch_threads != 256 &&
          c->opt.batch_threads != 512) ||
         (c->opt.batch_threads != 0) != (c->opt.batch_per_cu > 0) || c->opt.batch_per_cu < 0) {
@@ -437,15 +441,17 @@ sd_status run_plain(sd_context* c, const Lattice& L, Inst& I, int64_t* overflow_
             if (e == hipSuccess) c->tev.push_back(ev);
         }
     }
+    const int every = timing ? c->opt.kernel_timing : 1;
     for (int g = 1; g <= L.n && e == hipSuccess; g++) {
-        if (timing) e = hipEventRecord(c->tev[2 * (g - 1)], st);
+        const bool timed = timing && (g - 1) % every == 0;
+        if (timed) e = hipEventRecord(c->tev[2 * (g - 1)], st);
         if (e == hipSuccess && L.generic)
             e = launch_span_gen(I, (const EnergyTables*)c->E_dev, (const int32_t*)c->spec_dev, g,
                                 g >= 2 ? L.n - g + 1 : -1, c->num_cu, st);
         else if (e == hipSuccess)
             e = launch_span(I, (const EnergyTables*)c->E_dev, (const int32_t*)c->spec_dev, g,
                             g >= 2 ? L.n - g + 1 : -1, span_threads_for(c, L.n - g + 1), st);
-        if (timing && e == hipSuccess) e = hipEventRecord(c->tev[2 * (g - 1) + 1], st);
+        if (timed && e == hipSuccess) e = hipEventRecord(c->tev[2 * (g - 1) + 1], st);
     }
     if (e == hipSuccess) e = launch_ext(I, (const EnergyTables*)c->E_dev, 0, st);
     unsigned long long stats[4];
@@ -454,12 +460,14 @@ sd_status run_plain(sd_context* c, const Lattice& L, Inst& I, int64_t* overflow_
     *overflow_span = stats[2] == ~0ull ? 0 : (int64_t)stats[2];
     c->last_kernel_ms = 0.0;
     c->last_launches = L.n;
+    c->last_timed = 0;
     if (timing)
-        for (int g = 1; g <= L.n; g++) {
+        for (int g = 1; g <= L.n; g += every) {
             float ms = 0.f;
             e = hipEventElapsedTime(&ms, c->tev[2 * (g - 1)], c->tev[2 * (g - 1) + 1]);
             if (e != hipSuccess) return hip_fail(e, "kernel timing");
             c->last_kernel_ms += ms;
+            c->last_timed++;
         }
     c->last_visits = (int64_t)stats[0];
     c->last_feasible = (int64_t)stats[3];
@@ -721,6 +729,7 @@ sd_status design_plain(sd_context* c, const char* protein, const sd_codon_table*
     out->t_total_s = now_s() - t0;
     out->t_span_kernels_s = c->last_kernel_ms * 1e-3;
     out->n_span_launches = c->last_launches;
+    out->n_timed_launches = c->last_timed;
     out->cand_slots = L.cand_slots;
     out->cand_slots_first = slots_first;
     out->cand_overflow = overflowed;

@@ -41,6 +41,7 @@ struct sd_context {
     int64_t last_visits = 0, last_appends = 0, last_feasible = 0, last_overflow_span = 0;
     double last_kernel_ms = 0.0;
     int64_t last_launches = 0;
+    int64_t last_timed = 0;
     std::vector<hipEvent_t> tev;  // kernel_timing: event pairs around span launches
 };
 
