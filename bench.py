@@ -87,9 +87,14 @@ def kernel_source_sha():
     return h.hexdigest()
 
 
+COUNTER_FILES = {"plain300": "k_span_plain300_counters.json", "batch": "k_persistent_batch256_counters.json"}
+
+
 def profile_record(name):
     """Counter summary committed under profiles/, if taken on the current kernel source."""
-    path = os.path.join(ROOT, "profiles", f"k_span_{name}_counters.json")
+    if name not in COUNTER_FILES:
+        return None
+    path = os.path.join(ROOT, "profiles", COUNTER_FILES[name])
     if not os.path.exists(path):
         return None
     d = json.load(open(path))
