@@ -87,7 +87,8 @@ def kernel_source_sha():
     return h.hexdigest()
 
 
-COUNTER_FILES = {"plain300": "k_span_plain300_counters.json", "batch": "k_persistent_batch256_counters.json"}
+COUNTER_FILES = {"plain300": "k_span_plain300_counters.json", "batch": "k_persistent_batch256_counters.json",
+                 "motifs": "k_gen_closed_motifs_105aa_counters.json"}
 
 
 def profile_record(name):
