@@ -100,7 +100,23 @@ typedef struct sd_result {
     int32_t cand_overflow;   /* 1 if the first attempt's reservation overflowed (then exact
                                 worst-case segments were used; the result is unchanged)       */
     int64_t n_timed_launches;/* span-step launches timed with kernel_timing (plain mode)       */
+    int32_t path;            /* which forward fill produced the result (sd_path below)         */
+    int32_t graph_captured;  /* 1 if that fill was a persistent launch replayed from a captured
+                                hipGraph, else 0                                               */
 } sd_result;
+
+/* sd_result.path: the fill behind a result.  Batched and served results come from the persistent
+ * launch unless its grid barrier gave up (then the member is recomputed in plain mode) or, in a
+ * batch, the member's learned candidate reservation overflowed (recomputed in plain mode with
+ * worst-case segments).  A served request whose reservation overflows is re-run inside the mix
+ * with worst-case segments and stays SD_PATH_PERSISTENT with cand_overflow = 1.  Every path
+ * gives the same design. */
+typedef enum sd_path {
+    SD_PATH_PLAIN = 0,                /* sd_design: one span-step launch per span              */
+    SD_PATH_PERSISTENT = 1,           /* batched or served persistent launch                   */
+    SD_PATH_PLAIN_AFTER_BARRIER = 2,  /* batch or server member redone after a barrier timeout */
+    SD_PATH_PLAIN_AFTER_OVERFLOW = 3  /* batch member redone after a candidate overflow        */
+} sd_path;
 
 /* Parameter file (project text format "SPARSEDESIGN-PARAMS 1"; Turner-2004 d0 array shapes,
  * Sec. 3).  expect_sha256 (64 hex chars) may be NULL; a mismatch gives SD_E_PARAMS. */
@@ -205,6 +221,13 @@ sd_status sd_inverse_lambda(sd_context *ctx, const char *protein, double target_
 sd_status sd_design_tables(sd_context *ctx, const char *protein, const sd_codon_table *table,
                            const sd_params *params, double lambda_kcal, sd_result *out,
                            int64_t *V, int64_t *B, int64_t *S1, int64_t *S2, int64_t *X);
+/* Test hook: sd_design_batch plus the tables of batch member `member` (0 <= member < n) in the
+ * dense layout of sd_design_tables, N = outs[member].n_states.  The tables are the ones that
+ * produced that member's result (the persistent launch's, or the plain fill's when the member
+ * fell back; outs[member].path says which).  SD_E_ARG for a member index outside the batch. */
+sd_status sd_design_batch_tables(sd_context *ctx, int n, const char *const *proteins, const double *lambdas,
+                                 const sd_codon_table *table, const sd_params *params, sd_result *outs,
+                                 int member, int64_t *V, int64_t *B, int64_t *S1, int64_t *S2, int64_t *X);
 /* Test hook: sd_design_motifs plus its tables, in the same dense layout over the product
  * automaton's states (N = out->n_states; the states are ordered by layer, codon state, matcher
  * rank). */
@@ -213,6 +236,20 @@ sd_status sd_design_motifs_tables(sd_context *ctx, const char *protein, const ch
                                   double lambda_kcal, sd_result *out, int64_t *V, int64_t *B,
                                   int64_t *S1, int64_t *S2, int64_t *X);
 
+/* Fixed-point shift s that sd_design uses for these inputs (host only, no device work).  The DP
+ * runs in int64 fixed point: energies times 2^s plus codon costs rounded to the nearest multiple
+ * of 2^-s (the paper's real-valued objective of Sec. 3, eq. 1, read exactly; each codon's
+ * rounding is at most 2^-(s+1) internal units).  s is the largest value in [16, 40] with
+ *     sum over codon positions of the largest rounded cost of a synonymous codon
+ *     + Ebound(n) * 2^s  <  2^60,
+ * where Ebound(n) bounds |energy| of any partial structure on n = 3A nucleotides: at most n/2
+ * pairs, each closing one loop (energy range read off the parameter tables: hairpins of every
+ * size up to n, special loops, stacks, bulges, interior tables and generic interior loops, the
+ * multiloop closing pair) and being at most one branch (ML_intern + AU, or AU), plus ML_base
+ * per unpaired base.  Every finite DP value then lies in (-2^60, 2^60).  SD_E_RANGE if no s in
+ * [16, 40] qualifies (a very large lambda); SD_E_PROTEIN, SD_E_LAMBDA, SD_E_ARG for bad inputs. */
+sd_status sd_fixed_shift(const char *protein, const sd_codon_table *table, const sd_params *params,
+                         double lambda_kcal, int32_t *shift);
 /* Number of automaton states of a protein (to size the sd_design_tables buffers). */
 sd_status sd_lattice_size(const char *protein, int64_t *n_states, int64_t *n_cells);
 /* Size of the product automaton of sd_design_motifs (host only, no device work): states N and
@@ -242,6 +279,9 @@ sd_status sd_sizer_gradient(sd_sizer *z, int n, const float *X, const float *Y, 
 sd_status sd_sizer_train(sd_sizer *z, int n, const float *X, const float *Y, int steps, float lr,
                          float *final_loss);
 sd_status sd_sizer_predict(sd_sizer *z, int n, const float *X, float *Yhat);
+/* The same forward pass on the host (FP32, no device work): the predictor that sizing and server
+ * admission use for each request, from the parameters as of the last train / set_params. */
+sd_status sd_sizer_predict_host(const sd_sizer *z, int n, const float *X, float *Yhat);
 sd_status sd_sizer_features(const char *protein, double lambda_kcal, float out[22]);
 /* Sizing policy of a context: NULL restores worst-case segments.  A right endpoint in bin k gets
  * min(worst, ceil(worst * min(1, yhat_k * (1 + margin))) + slack) slots.  The sizer must outlive

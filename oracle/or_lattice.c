@@ -13,7 +13,7 @@
  *               external values X(a) for fragments a -> t.
  * Fixed point: U(e) = llround(ldexp(100*lambda*q(e), s)), energies enter as E*2^s, the
  * sentinel OR_INF saturates.  The shift s is the largest value in [16,40] for which the range
- * rule holds (see choose_shift).
+ * rule holds (see choose_shift: a bound on every partial value from the parameter tables).
  *
  * DFA: the prefix trie of each codon family; layer 3k holds one state per codon boundary,
  * layer 3k+1 one state per distinct first base, layer 3k+2 one per distinct two-base prefix.
@@ -403,27 +403,111 @@ static int build_product(const dfa_t *T, const char *const *motifs, int nm, dfa_
     return finish_dfa(D);
 }
 
-/* Range rule for the fixed-point shift: the largest s in [16,40] with
- *   sum_k max_c U_k(s) + (n+1) * 8 * (maxabs + ceil(lxc*ln(max(n,30)/30)) + 1) * 2^s < 2^60,
- * so every finite partial value stays far below OR_INF = 2^62. */
+/* Range rule for the fixed-point shift.  Every finite DP value is E*2^s + U for a partial design:
+ * U is the rounded cost of some of the path's codons (0 <= U <= sum_k max_c U_k) and E is the
+ * energy of a partial structure on at most n nucleotides.  Each pair of such a structure closes
+ * exactly one loop (hairpin, stack / bulge / interior loop, or a multiloop with its closing
+ * terms) and is at most one branch (of a multiloop: ML_intern + AU; of the exterior loop: AU);
+ * every other multiloop term is ML_base per unpaired base.  With at most floor(n/2) pairs,
+ *     floor(n/2) * (min(0, Lmin) + Bmin) + n * min(0, ML_base)  <=  E
+ *     E  <=  floor(n/2) * (max(0, Lmax) + Bmax) + n * max(0, ML_base)
+ * where [Lmin, Lmax] bounds the energy of one loop and [Bmin, Bmax] one branch term, both read
+ * off the parameter tables (loop_bounds below).  The shift is the largest s in [16, 40] with
+ *     sum_k max_c U_k(s) + max(|E lower bound|, E upper bound) * 2^s  <  2^60,
+ * so every finite value lies in (-2^60, 2^60), far from OR_INF = 2^62. */
+static int64_t mn64(int64_t a, int64_t b) { return a < b ? a : b; }
+static int64_t mx64(int64_t a, int64_t b) { return a > b ? a : b; }
+
+static void tab_range(const int32_t *t, int cnt, int64_t *lo, int64_t *hi) {
+    for (int i = 0; i < cnt; i++) {
+        *lo = mn64(*lo, t[i]);
+        *hi = mx64(*hi, t[i]);
+    }
+}
+
+/* [Lmin, Lmax]: energy of one loop closed by a pair, on a design of n nucleotides */
+static void loop_bounds(const or_params *P, int n, int64_t *Lmin, int64_t *Lmax) {
+    const int64_t au_lo = mn64(0, P->terminal_au), au_hi = mx64(0, P->terminal_au);
+    int64_t lo = INT64_MAX, hi = INT64_MIN;
+    /* hairpins of every size 3..n: initiation plus a terminal AU (size 3) or a mismatch */
+    int64_t mh_lo = 0, mh_hi = 0, init_lo = INT64_MAX, init_hi = INT64_MIN;
+    tab_range(&P->mmH[0][0][0], 96, &mh_lo, &mh_hi);
+    for (int m = 3; m <= (n > 3 ? n : 3); m++) {
+        int64_t e = or_loop_init(P->hairpin, P->lxc, m);
+        init_lo = mn64(init_lo, e);
+        init_hi = mx64(init_hi, e);
+    }
+    lo = mn64(lo, init_lo + mn64(au_lo, mh_lo));
+    hi = mx64(hi, init_hi + mx64(au_hi, mh_hi));
+    for (int k = 0; k < 3; k++) tab_range(P->spec_e[k], P->nspec[k], &lo, &hi); /* listed totals */
+    /* stacks and bulges */
+    int64_t st_lo = INT64_MAX, st_hi = INT64_MIN;
+    tab_range(&P->stack[0][0], 36, &st_lo, &st_hi);
+    lo = mn64(lo, st_lo);
+    hi = mx64(hi, st_hi);
+    lo = mn64(lo, P->bulge[1] + st_lo);
+    hi = mx64(hi, P->bulge[1] + st_hi);
+    for (int l = 2; l <= 30; l++) {
+        lo = mn64(lo, P->bulge[l] + 2 * au_lo);
+        hi = mx64(hi, P->bulge[l] + 2 * au_hi);
+    }
+    /* interior loops: full tables, and initiation + asymmetry + two mismatches */
+    tab_range(&P->int11[0][0][0][0], 576, &lo, &hi);
+    tab_range(&P->int21[0][0][0][0][0], 2304, &lo, &hi);
+    tab_range(&P->int22[0][0][0][0][0][0], 9216, &lo, &hi);
+    int64_t mi_lo = 0, mi_hi = 0;
+    tab_range(&P->mmI[0][0][0], 96, &mi_lo, &mi_hi);
+    tab_range(&P->mm1n[0][0][0], 96, &mi_lo, &mi_hi);
+    tab_range(&P->mm23[0][0][0], 96, &mi_lo, &mi_hi);
+    const int64_t asym_lo = mn64(0, mn64(P->ninio_max, 28 * (int64_t)P->ninio));
+    const int64_t asym_hi = mx64(0, P->ninio_max);
+    for (int l = 2; l <= 30; l++) {
+        lo = mn64(lo, P->interior[l] + asym_lo + 2 * mi_lo);
+        hi = mx64(hi, P->interior[l] + asym_hi + 2 * mi_hi);
+    }
+    /* multiloop closing pair */
+    lo = mn64(lo, (int64_t)P->ml_closing + P->ml_intern + au_lo);
+    hi = mx64(hi, (int64_t)P->ml_closing + P->ml_intern + au_hi);
+    *Lmin = lo;
+    *Lmax = hi;
+}
+
+/* Energy bound of the range rule: max(|E lower bound|, E upper bound) for n nucleotides. */
+static int64_t energy_bound(const or_params *P, int n) {
+    int64_t Lmin, Lmax;
+    loop_bounds(P, n, &Lmin, &Lmax);
+    const int64_t au_lo = mn64(0, P->terminal_au), au_hi = mx64(0, P->terminal_au);
+    const int64_t br_lo = mn64(0, mn64(P->ml_intern + au_lo, au_lo));
+    const int64_t br_hi = mx64(0, mx64(P->ml_intern + au_hi, au_hi));
+    const int64_t pairs = n / 2;
+    const int64_t e_lo = pairs * (mn64(0, Lmin) + br_lo) + (int64_t)n * mn64(0, P->ml_base);
+    const int64_t e_hi = pairs * (mx64(0, Lmax) + br_hi) + (int64_t)n * mx64(0, P->ml_base);
+    return mx64(-e_lo, e_hi);
+}
+
 static int choose_shift(const dfa_t *D, const or_params *P, double lam100) {
-    double lnf = D->n > 30 ? log((double)D->n / 30.0) : 0.0;
-    int64_t ext = (int64_t)ceil(P->lxc * lnf) + 1;
-    int64_t emax = 8 * ((int64_t)P->maxabs + ext);
+    const int64_t ebound = energy_bound(P, D->n);
     int64_t *mx = calloc(D->A + 1, sizeof(int64_t));
     if (!mx) return OR_E_NOMEM;
     int chosen = OR_E_RANGE;
     for (int s = 40; s >= 16; s--) {
         memset(mx, 0, sizeof(int64_t) * (D->A + 1));
+        int too_big = 0;
         for (int e = 0; e < D->nE; e++) {
             if (D->ecod[e] < 0) continue;
-            int64_t u = llround(ldexp(lam100 * D->eq[e], s));
+            double x = ldexp(lam100 * D->eq[e], s);
+            if (!(x < 0x1p60)) { /* one codon alone breaks the rule (llround would overflow) */
+                too_big = 1;
+                break;
+            }
+            int64_t u = llround(x);
             int k = D->layer[D->esrc[e]] / 3;
             if (u > mx[k]) mx[k] = u;
         }
+        if (too_big) continue;
         __int128 tot = 0;
         for (int k = 0; k < D->A; k++) tot += mx[k];
-        tot += (__int128)(D->n + 1) * emax * ((__int128)1 << s);
+        tot += (__int128)ebound * ((__int128)1 << s);
         if (tot < ((__int128)1 << 60)) {
             chosen = s;
             break;

@@ -20,6 +20,8 @@ import numpy as np
 HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(HERE, "libsparsedesign.so")
 INF = 1 << 62
+# sd_result.path
+PATH_PLAIN, PATH_PERSISTENT, PATH_PLAIN_AFTER_BARRIER, PATH_PLAIN_AFTER_OVERFLOW = 0, 1, 2, 3
 
 STATUS = {0: "SD_OK", -1: "SD_E_ARG", -2: "SD_E_PROTEIN", -3: "SD_E_CODON_TABLE",
           -4: "SD_E_PARAMS", -5: "SD_E_LAMBDA", -6: "SD_E_RANGE", -7: "SD_E_NOMEM",
@@ -37,7 +39,8 @@ EXPORTS = [
     "sd_server_start", "sd_server_submit", "sd_server_poll", "sd_server_wait", "sd_server_get_stats",
     "sd_server_stop", "sd_lambda_envelope", "sd_design_motifs", "sd_inverse_lambda",
     "sd_design_motifs_tables", "sd_motif_lattice_size", "sd_context_create_external",
-    "sd_sizer_request_bytes",
+    "sd_sizer_request_bytes", "sd_fixed_shift", "sd_design_batch_tables",
+    "sd_sizer_predict_host",
 ]
 
 
@@ -74,7 +77,7 @@ class _Result(C.Structure):
         ("n_feasible", C.c_int64), ("t_fill_s", C.c_double), ("t_total_s", C.c_double),
         ("t_span_kernels_s", C.c_double), ("n_span_launches", C.c_int64),
         ("cand_slots", C.c_int64), ("cand_slots_first", C.c_int64), ("cand_overflow", C.c_int32),
-        ("n_timed_launches", C.c_int64),
+        ("n_timed_launches", C.c_int64), ("path", C.c_int32), ("graph_captured", C.c_int32),
     ]
 
 
@@ -111,7 +114,10 @@ def lib():
                                       vp, vp, C.POINTER(_Result)]
         L.sd_design_tables.argtypes = [vp, C.c_char_p, vp, vp, C.c_double, C.POINTER(_Result),
                                        P64, P64, P64, P64, P64]
+        L.sd_design_batch_tables.argtypes = [vp, C.c_int, C.POINTER(C.c_char_p), C.POINTER(C.c_double),
+                                             vp, vp, C.POINTER(_Result), C.c_int, P64, P64, P64, P64, P64]
         L.sd_lattice_size.argtypes = [C.c_char_p, P64, P64]
+        L.sd_fixed_shift.argtypes = [C.c_char_p, vp, vp, C.c_double, C.POINTER(C.c_int32)]
         L.sd_result_free.argtypes = [C.POINTER(_Result)]
         L.sd_status_str.argtypes = [C.c_int]
         L.sd_status_str.restype = C.c_char_p
@@ -127,6 +133,7 @@ def lib():
         L.sd_sizer_gradient.argtypes = [vp, C.c_int, PF, PF, PF, PF]
         L.sd_sizer_train.argtypes = [vp, C.c_int, PF, PF, C.c_int, C.c_float, PF]
         L.sd_sizer_predict.argtypes = [vp, C.c_int, PF, PF]
+        L.sd_sizer_predict_host.argtypes = [vp, C.c_int, PF, PF]
         L.sd_sizer_features.argtypes = [C.c_char_p, C.c_double, PF]
         L.sd_context_set_sizer.argtypes = [vp, vp, C.c_float, C.c_int]
         L.sd_lambda_envelope.argtypes = [vp, C.c_char_p, C.c_double, C.c_double, C.c_int, vp, vp,
@@ -209,6 +216,8 @@ class Result:
     cand_slots_first: int
     cand_overflow: int
     n_timed_launches: int
+    path: int
+    graph_captured: int
 
 
 def _convert(r: _Result) -> Result:
@@ -216,7 +225,7 @@ def _convert(r: _Result) -> Result:
                  r.codon_cost, r.objective_kcal, r.objective_fixed, r.fixed_shift, r.cai, r.n_states,
                  r.n_cells, r.n_candidates, r.n_visits, r.n_feasible, r.t_fill_s, r.t_total_s,
                  r.t_span_kernels_s, r.n_span_launches, r.cand_slots, r.cand_slots_first,
-                 r.cand_overflow, r.n_timed_launches)
+                 r.cand_overflow, r.n_timed_launches, r.path, r.graph_captured)
     lib().sd_result_free(C.byref(r))
     return out
 
@@ -320,6 +329,21 @@ class Context:
                                       p(V), p(B), p(S1), p(S2), p(X)), "sd_design_tables")
         return _convert(r), {"V": V, "B": B, "S1": S1, "S2": S2, "X": X}
 
+    def design_batch_tables(self, proteins, lambdas, table: CodonTable, params: Params, member: int):
+        """design_batch plus the dense tables of one member."""
+        n = len(proteins)
+        N = lattice_size(proteins[member])[0] if 0 <= member < n else 1  # the library rejects the index
+        arr = (C.c_char_p * n)(*[p.encode() for p in proteins])
+        lam = (C.c_double * n)(*[float(x) for x in lambdas])
+        res = (_Result * n)()
+        V = np.empty((6, N, N), np.int64)
+        B, S1, S2 = (np.empty((N, N), np.int64) for _ in range(3))
+        X = np.empty(N, np.int64)
+        p = lambda a: a.ctypes.data_as(C.POINTER(C.c_int64))
+        _check(lib().sd_design_batch_tables(self.h, n, arr, lam, table.h, params.h, res, int(member),
+                                            p(V), p(B), p(S1), p(S2), p(X)), "sd_design_batch_tables")
+        return [_convert(res[i]) for i in range(n)], {"V": V, "B": B, "S1": S1, "S2": S2, "X": X}
+
     def design_motifs_tables(self, protein: str, motifs, table: CodonTable, params: Params, lam: float):
         m = list(motifs)
         N, _ = motif_lattice_size(protein, m)
@@ -342,6 +366,13 @@ def motif_lattice_size(protein: str, motifs):
     _check(lib().sd_motif_lattice_size(protein.encode(), arr, len(m), C.byref(n), C.byref(c)),
            "sd_motif_lattice_size")
     return n.value, c.value
+
+
+def fixed_shift(protein: str, table: CodonTable, params: Params, lam: float) -> int:
+    """The fixed-point shift s a design of these inputs uses (host only)."""
+    s = C.c_int32()
+    _check(lib().sd_fixed_shift(protein.encode(), table.h, params.h, float(lam), C.byref(s)), "sd_fixed_shift")
+    return s.value
 
 
 def lattice_size(protein: str):
@@ -412,6 +443,13 @@ class Sizer:
         X = np.ascontiguousarray(X, np.float32)
         Y = np.zeros((len(X), self.K), np.float32)
         _check(lib().sd_sizer_predict(self.h, len(X), _fp(X), _fp(Y)), "sd_sizer_predict")
+        return Y
+
+    def predict_host(self, X) -> np.ndarray:
+        """The host forward pass that sizing and admission use."""
+        X = np.ascontiguousarray(X, np.float32)
+        Y = np.zeros((len(X), self.K), np.float32)
+        _check(lib().sd_sizer_predict_host(self.h, len(X), _fp(X), _fp(Y)), "sd_sizer_predict_host")
         return Y
 
 

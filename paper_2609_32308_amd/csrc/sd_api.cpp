@@ -786,6 +786,43 @@ extern "C" sd_status sd_lattice_size(const char* protein, int64_t* n_states, int
     return SD_OK;
 }
 
+extern "C" sd_status sd_fixed_shift(const char* protein, const sd_codon_table* table, const sd_params* params,
+                                   double lambda_kcal, int32_t* shift) {
+    try {
+        if (!table || !params || !shift) return fail(SD_E_ARG, "null argument");
+        Lattice L;
+        std::string err;
+        int rc = build_lattice(protein, table->t, params->p, lambda_kcal, CapPolicy(), L, err);
+        if (rc) return fail((sd_status)rc, err);
+        *shift = L.shift;
+        return SD_OK;
+    } catch (const std::bad_alloc&) {
+        return fail(SD_E_NOMEM, "host allocation");
+    }
+}
+
+namespace sd {
+// Copies downloaded tables into the dense test layout [a * N + b] (V: [tau][a][b]); entries with
+// rho(a) >= rho(b) are INF.  Null destinations are skipped.
+void dense_tables(const Lattice& L, const TraceTables& T, const DenseOut& D) {
+    const size_t N = L.N;
+    auto dense = [&](int64_t* dst, const int64_t* src, int stride, int t) {
+        if (!dst) return;
+        for (size_t a = 0; a < N; a++)
+            for (size_t b = 0; b < N; b++) {
+                int64_t v = kINF;
+                if (L.layer[a] < L.layer[b]) v = src[(L.rowoff[a] + (b - L.off[L.layer[a] + 1])) * stride + t];
+                dst[a * N + b] = v;
+            }
+    };
+    for (int t = 0; t < 6 && D.V; t++) dense(D.V + (size_t)t * N * N, T.V, 6, t);
+    dense(D.B, T.B, 1, 0);
+    dense(D.S1, T.S1, 1, 0);
+    dense(D.S2, T.S2, 1, 0);
+    if (D.X) memcpy(D.X, T.X, N * 8);
+}
+}  // namespace sd
+
 namespace {
 sd_status design_tables_impl(sd_context* ctx, const char* protein, const std::vector<std::string>* motifs,
                              const sd_codon_table* table, const sd_params* params, double lambda_kcal,
@@ -795,21 +832,7 @@ sd_status design_tables_impl(sd_context* ctx, const char* protein, const std::ve
         Lattice L;
         sd_status s = design_plain(ctx, protein, table, params, lambda_kcal, out, &T, &L, motifs);
         if (s) return s;
-        const size_t N = L.N;
-        auto dense = [&](int64_t* dst, const int64_t* src, int stride, int t) {
-            if (!dst) return;
-            for (size_t a = 0; a < N; a++)
-                for (size_t b = 0; b < N; b++) {
-                    int64_t v = kINF;
-                    if (L.layer[a] < L.layer[b]) v = src[(L.rowoff[a] + (b - L.off[L.layer[a] + 1])) * stride + t];
-                    dst[a * N + b] = v;
-                }
-        };
-        for (int t = 0; t < 6 && V; t++) dense(V + (size_t)t * N * N, T.V, 6, t);
-        dense(B, T.B, 1, 0);
-        dense(S1, T.S1, 1, 0);
-        dense(S2, T.S2, 1, 0);
-        if (X) memcpy(X, T.X, N * 8);
+        dense_tables(L, T, DenseOut{V, B, S1, S2, X});
         return SD_OK;
     } catch (const std::bad_alloc&) {
         return fail(SD_E_NOMEM, "host allocation");
@@ -1033,12 +1056,17 @@ sd_status tuned_schedule(sd_context* c, const std::vector<Lattice>& batch, int* 
 
 }  // namespace sd
 
-extern "C" sd_status sd_design_batch(sd_context* ctx, int n, const char* const* proteins,
-                                     const double* lambdas, const sd_codon_table* table,
-                                     const sd_params* params, sd_result* outs) {
+namespace {
+// sd_design_batch; with dump_member in [0, n) that member's tables also go to D (dense layout)
+sd_status design_batch_impl(sd_context* ctx, int n, const char* const* proteins, const double* lambdas,
+                            const sd_codon_table* table, const sd_params* params, sd_result* outs,
+                            int dump_member, const DenseOut& D) {
     try {
         if (!ctx || !table || !params || n < 0 || (n > 0 && (!proteins || !lambdas || !outs)))
             return fail(SD_E_ARG, "null argument");
+        // every entry starts empty, so that freeing the outputs on an error path only ever
+        // frees strings this call allocated, whatever the caller's array held
+        memset(outs, 0, sizeof(sd_result) * (size_t)n);
         hipError_t he = hipSetDevice(ctx->device);
         if (he != hipSuccess) return hip_fail(he, "hipSetDevice");
         int done = 0;
@@ -1089,9 +1117,11 @@ extern "C" sd_status sd_design_batch(sd_context* ctx, int n, const char* const* 
                     s = design_plain(ctx, proteins[gi], table, params, lambdas[gi], &outs[gi], &T2, &L2, nullptr);
                     ctx->force_worst = fw;
                     ctx->last_batch_fallbacks++;
+                    if (!s && gi == dump_member) dense_tables(L2, T2, D);
                     if (!s) {
                         outs[gi].cand_slots_first = Ls[i].cand_slots;
                         outs[gi].cand_overflow = st[2] != ~0ull;
+                        outs[gi].path = ok ? SD_PATH_PLAIN_AFTER_OVERFLOW : SD_PATH_PLAIN_AFTER_BARRIER;
                         if (ctx->occ_K > 0) occupancy_bins(L2, T2, ctx->occ_K, &ctx->occ[(size_t)gi * ctx->occ_K]);
                     }
                     continue;
@@ -1099,6 +1129,7 @@ extern "C" sd_status sd_design_batch(sd_context* ctx, int n, const char* const* 
                 TraceTables T;
                 s = fetch_tables(ctx, Ls[i], Is[i], T);
                 if (s) break;
+                if (gi == dump_member) dense_tables(Ls[i], T, D);
                 TraceResult R;
                 int rc = trace_design(Ls[i], params->p, T, R);
                 if (rc) {
@@ -1117,6 +1148,8 @@ extern "C" sd_status sd_design_batch(sd_context* ctx, int n, const char* const* 
                 outs[gi].cand_slots = Ls[i].cand_slots;
                 outs[gi].cand_slots_first = Ls[i].cand_slots;
                 outs[gi].cand_overflow = 0;
+                outs[gi].path = SD_PATH_PERSISTENT;
+                outs[gi].graph_captured = ctx->last_graph ? 1 : 0;
                 if (ctx->occ_K > 0) occupancy_bins(Ls[i], T, ctx->occ_K, &ctx->occ[(size_t)gi * ctx->occ_K]);
             }
             if (s) {
@@ -1131,6 +1164,22 @@ extern "C" sd_status sd_design_batch(sd_context* ctx, int n, const char* const* 
     } catch (...) {
         return fail(SD_E_INTERNAL, "unexpected exception");
     }
+}
+
+}  // namespace
+
+extern "C" sd_status sd_design_batch(sd_context* ctx, int n, const char* const* proteins,
+                                     const double* lambdas, const sd_codon_table* table,
+                                     const sd_params* params, sd_result* outs) {
+    return design_batch_impl(ctx, n, proteins, lambdas, table, params, outs, -1, DenseOut{});
+}
+
+extern "C" sd_status sd_design_batch_tables(sd_context* ctx, int n, const char* const* proteins,
+                                            const double* lambdas, const sd_codon_table* table,
+                                            const sd_params* params, sd_result* outs, int member,
+                                            int64_t* V, int64_t* B, int64_t* S1, int64_t* S2, int64_t* X) {
+    if (member < 0 || member >= n) return fail(SD_E_ARG, "member index outside the batch");
+    return design_batch_impl(ctx, n, proteins, lambdas, table, params, outs, member, DenseOut{V, B, S1, S2, X});
 }
 
 extern "C" sd_status sd_context_set_sizer(sd_context* ctx, const sd_sizer* z, float margin, int slack) {

@@ -34,4 +34,9 @@ sd_status design_plain(sd_context* c, const char* protein, const sd_codon_table*
                        const sd_params* params, double lambda, sd_result* out, TraceTables* keep,
                        Lattice* keepL, const std::vector<std::string>* motifs = nullptr);
 CapPolicy policy_for(const sd_context* c, const char* protein, double lambda, std::vector<float>& frac);
+// destinations of the dense test layout (any may be null)
+struct DenseOut {
+    int64_t *V = nullptr, *B = nullptr, *S1 = nullptr, *S2 = nullptr, *X = nullptr;
+};
+void dense_tables(const Lattice& L, const TraceTables& T, const DenseOut& D);
 }  // namespace sd

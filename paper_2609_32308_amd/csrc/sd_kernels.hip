@@ -1420,7 +1420,16 @@ __global__ __launch_bounds__(256) void k_span_gen(Inst I, const EnergyTables* __
 // per workgroup group (XCD); a group's workgroups draw its band's items from the group's ticket
 // counter.  The barrier is two-level: the last arrival of a group counts the group at the top
 // word, the last group bumps the generation (agent-scope release / acquire).
+//
+// Release: every wave of the workgroup fences at agent scope before the workgroup barrier.  The
+// cell values (S1, S2, B, V) and the candidate appends are stored by many waves, and a
+// workgroup barrier alone neither waits for their stores (no vmcnt wait before s_barrier) nor
+// writes them back from this XCD's L2; thread 0's own fence only covers wave 0's stores.
+// Without the per-wave fence a workgroup on another XCD could read a value of the previous
+// span from memory before it was written back (a stale S1 makes P_S too large and the
+// retention test then keeps extra non-strict candidates).
 __device__ bool grid_barrier(BatchCtl* ctl, unsigned spin_cap, int* s_flag) {
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "agent");
     __syncthreads();
     if (threadIdx.x == 0) {
         __threadfence();

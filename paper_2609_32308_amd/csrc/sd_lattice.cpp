@@ -331,6 +331,60 @@ void layout_rows(Lattice& L, const CapPolicy& cp) {
 }
 }  // namespace
 
+// Bound on |E| of any partial structure on n nucleotides, the energy side of the fixed-point
+// range rule.  A DP value is E * 2^s plus the rounded costs of some codons of the path.  Every
+// pair of the partial structure closes one loop and is at most one branch (multiloop:
+// ML_intern + AU, exterior loop: AU); the other multiloop terms are ML_base per unpaired base.
+// So with at most n/2 pairs and one loop's energy in [lo, hi], one branch term in [blo, bhi]:
+//     n/2 * (min(0, lo) + blo) + n * min(0, ML_base)  <=  E  <=  n/2 * (max(0, hi) + bhi) + n * max(0, ML_base).
+// The loop range covers hairpins of every size up to n (initiation plus a terminal AU or a
+// mismatch, or a listed special loop), stacks, bulges, the interior-loop tables and generic
+// interior loops (initiation, Ninio asymmetry, two mismatches), and the multiloop closing pair.
+static int64_t energy_bound(const Params& P, int n) {
+    const EnergyTables& E = P.E;
+    int64_t lo = INT64_MAX, hi = INT64_MIN;
+    auto cover = [&](int64_t a, int64_t b) { lo = std::min(lo, a); hi = std::max(hi, b); };
+    auto range = [](const int32_t* t, int cnt, int64_t z) {  // [min, max] of t and z
+        int64_t a = z, b = z;
+        for (int i = 0; i < cnt; i++) a = std::min<int64_t>(a, t[i]), b = std::max<int64_t>(b, t[i]);
+        return std::make_pair(a, b);
+    };
+    const int64_t tau = E.terminal_au, au0 = std::min<int64_t>(0, tau), au1 = std::max<int64_t>(0, tau);
+    // hairpins
+    const auto mh = range(&E.mmH[0][0][0], 96, 0);
+    int64_t i0 = INT64_MAX, i1 = INT64_MIN;
+    for (int m = 3; m <= std::max(n, 3); m++) {
+        const int64_t e = m <= 30 ? E.hairpin[m] : E.hairpin[30] + (int64_t)lround(P.lxc * log((double)m / 30.0));
+        i0 = std::min(i0, e);
+        i1 = std::max(i1, e);
+    }
+    cover(i0 + std::min(au0, mh.first), i1 + std::max(au1, mh.second));
+    for (int k = 0; k < 3; k++)
+        for (int32_t e : P.special_e[k]) cover(e, e);
+    // stacks, bulges
+    const auto st = range(&E.stack[0][0], 36, E.stack[0][0]);
+    cover(st.first, st.second);
+    cover(E.bulge[1] + st.first, E.bulge[1] + st.second);
+    for (int l = 2; l <= 30; l++) cover(E.bulge[l] + 2 * au0, E.bulge[l] + 2 * au1);
+    // interior loops
+    for (auto t : {range(&E.int11[0][0][0][0], 576, E.int11[0][0][0][0]),
+                   range(&E.int21[0][0][0][0][0], 2304, E.int21[0][0][0][0][0]),
+                   range(&E.int22[0][0][0][0][0][0], 9216, E.int22[0][0][0][0][0][0])})
+        cover(t.first, t.second);
+    const auto mI = range(&E.mmI[0][0][0], 96, 0), m1 = range(&E.mm1n[0][0][0], 96, 0),
+               m23 = range(&E.mm23[0][0][0], 96, 0);
+    const int64_t mm0 = std::min({mI.first, m1.first, m23.first}), mm1 = std::max({mI.second, m1.second, m23.second});
+    const int64_t as0 = std::min<int64_t>({0, E.ninio_max, 28 * (int64_t)E.ninio}), as1 = std::max<int64_t>(0, E.ninio_max);
+    for (int l = 2; l <= 30; l++) cover(E.interior[l] + as0 + 2 * mm0, E.interior[l] + as1 + 2 * mm1);
+    // multiloop closing pair
+    cover((int64_t)E.ml_closing + E.ml_intern + au0, (int64_t)E.ml_closing + E.ml_intern + au1);
+    const int64_t blo = std::min<int64_t>({0, E.ml_intern + au0, au0}), bhi = std::max<int64_t>({0, E.ml_intern + au1, au1});
+    const int64_t pairs = n / 2;
+    const int64_t elo = pairs * (std::min<int64_t>(0, lo) + blo) + (int64_t)n * std::min<int64_t>(0, E.ml_base);
+    const int64_t ehi = pairs * (std::max<int64_t>(0, hi) + bhi) + (int64_t)n * std::max<int64_t>(0, E.ml_base);
+    return std::max(-elo, ehi);
+}
+
 int build_lattice(const char* protein, const CodonTable& T, const Params& P, double lambda,
                   const CapPolicy& cp, Lattice& L, std::string& err) {
     int rc = check_protein(protein);
@@ -408,22 +462,26 @@ int build_lattice(const char* protein, const CodonTable& T, const Params& P, dou
             L.out_cod[e] = c;
             L.out_q[e] = -log(T.w[c]);
         }
-    // fixed point: largest shift s in [16, 40] meeting the range rule
+    // fixed point: largest shift s in [16, 40] meeting the range rule (energy_bound)
     const double lam100 = 100.0 * lambda;
-    const double lnf = n > 30 ? log((double)n / 30.0) : 0.0;
-    const int64_t ext = (int64_t)ceil(P.lxc * lnf) + 1;
-    const int64_t emax = 8 * ((int64_t)P.maxabs + ext);
+    const __int128 ebound = energy_bound(P, n);
     int shift = -1;
-    std::vector<int64_t> Ucode(64);
     for (int s = 40; s >= 16 && shift < 0; s--) {
         __int128 tot = 0;
-        for (int k = 0; k < A; k++) {
+        for (int k = 0; k < A && tot < ((__int128)1 << 60); k++) {
             int64_t mx = 0;
-            for (int c = 0; c < 64; c++)
-                if (kCode[c] == protein[k]) mx = std::max<int64_t>(mx, llround(ldexp(lam100 * -log(T.w[c]), s)));
+            for (int c = 0; c < 64; c++) {
+                if (kCode[c] != protein[k]) continue;
+                const double x = ldexp(lam100 * -log(T.w[c]), s);
+                if (!(x < 0x1p60)) {  // this codon alone breaks the rule (and would overflow llround)
+                    mx = (int64_t)1 << 60;
+                    break;
+                }
+                mx = std::max<int64_t>(mx, llround(x));
+            }
             tot += mx;
         }
-        tot += (__int128)(n + 1) * emax * ((__int128)1 << s);
+        tot += ebound << s;
         if (tot < ((__int128)1 << 60)) shift = s;
     }
     if (shift < 0) {

@@ -354,3 +354,9 @@ void sizer_predict_host(const sd_sizer* z, const float* x, float* y) {
 }
 int sizer_bins(const sd_sizer* z) { return z->sh.K; }
 }  // namespace sd
+
+extern "C" sd_status sd_sizer_predict_host(const sd_sizer* z, int n, const float* X, float* Yhat) {
+    if (!z || n <= 0 || !X || !Yhat) return mlp_fail(SD_E_ARG, "null argument");
+    for (int i = 0; i < n; i++) sd::sizer_predict_host(z, X + (size_t)i * kFeat, Yhat + (size_t)i * z->sh.K);
+    return SD_OK;
+}

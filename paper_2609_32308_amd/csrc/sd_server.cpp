@@ -137,10 +137,11 @@ struct sd_server {
 
 namespace {
 
-void finish(sd_server* S, uint64_t ticket, sd_status status, const sd_result& r) {
+// Answer a request; `completed` counts it as a finished design (a cancellation is not one).
+void finish(sd_server* S, uint64_t ticket, sd_status status, const sd_result& r, bool completed = true) {
     std::lock_guard<std::mutex> lk(S->mu);
     S->done[ticket] = Done{status, r};
-    S->st.completed++;
+    if (completed) S->st.completed++;
     S->cv_done.notify_all();
 }
 
@@ -164,6 +165,8 @@ void worker_main(sd_server* S) {
             for (int v = 0; v < job.a.L.N; v++)
                 for (int k = 0; k < job.T.ccnt[v]; k++) Z += job.T.cc[job.a.L.coff[v] + k] >= 0;
             s = fill_result(job.a.L, R, job.T.X[0], Z, job.visits, job.feasible, &r);
+            r.path = SD_PATH_PERSISTENT;
+            r.graph_captured = 0;
             r.t_fill_s = job.t_fill;
             r.t_total_s = now_s() - job.a.rq.t_submit;
             r.cand_slots = job.a.L.cand_slots;
@@ -187,7 +190,11 @@ sd_status ensure_srv_staging(sd_server* S, size_t bytes) {
     return SD_OK;
 }
 
-// Admit queued requests that fit; returns after uploading their inputs.
+// Admit queued requests that fit; returns after uploading their inputs.  A request is taken off
+// the queue under the lock that reads it, so sd_server_stop (which answers every queued request
+// SD_E_CANCELLED and clears the queue from the caller's thread) never sees a request that this
+// thread is placing.  A request that has to wait for pool memory goes back to the head of the
+// queue, or is answered SD_E_CANCELLED if the server was stopped meanwhile.
 sd_status admit(sd_server* S) {
     for (;;) {
         Request rq;
@@ -195,6 +202,7 @@ sd_status admit(sd_server* S) {
             std::lock_guard<std::mutex> lk(S->mu);
             if (S->queue.empty() || (int)S->active.size() >= S->cfg.max_active) return SD_OK;
             rq = S->queue.front();
+            S->queue.pop_front();
         }
         Active a;
         a.rq = rq;
@@ -204,10 +212,6 @@ sd_status admit(sd_server* S) {
                                rq.worst ? CapPolicy() : policy_for(S->ctx, rq.protein.c_str(), rq.lambda, frac),
                                a.L, err);
         if (rc) {  // invalid request: answer it right away
-            {
-                std::lock_guard<std::mutex> lk(S->mu);
-                S->queue.pop_front();
-            }
             sd_result r;
             memset(&r, 0, sizeof(r));
             finish(S, rq.ticket, (sd_status)rc, r);
@@ -217,31 +221,33 @@ sd_status admit(sd_server* S) {
         InstLayout lay = layout_instance(a.L, nullptr, nullptr, a.I);
         a.bytes = lay.a_bytes + lay.b_bytes;
         if (!lay.a_bytes) {
-            {
-                std::lock_guard<std::mutex> lk(S->mu);
-                S->queue.pop_front();
-            }
             sd_result r;
             memset(&r, 0, sizeof(r));
             finish(S, rq.ticket, SD_E_INTERNAL, r);
             continue;
         }
         if (a.bytes > S->pool.size) {  // can never fit: recompute in plain mode outside the pool
-            {
-                std::lock_guard<std::mutex> lk(S->mu);
-                S->queue.pop_front();
-            }
             sd_result r;
+            memset(&r, 0, sizeof(r));
             sd_status s = design_plain(S->ctx, rq.protein.c_str(), S->table, S->params, rq.lambda, &r, nullptr, nullptr);
             if (!s) r.t_total_s = now_s() - rq.t_submit;
             finish(S, rq.ticket, s, r);
             continue;
         }
         size_t off;
-        if (!S->pool.alloc(a.bytes, &off)) return SD_OK;  // wait for memory to free up
-        {
-            std::lock_guard<std::mutex> lk(S->mu);
-            S->queue.pop_front();
+        if (!S->pool.alloc(a.bytes, &off)) {  // wait for memory to free up
+            bool cancelled = false;
+            {
+                std::lock_guard<std::mutex> lk(S->mu);
+                if (S->stop) cancelled = true;
+                else S->queue.push_front(rq);
+            }
+            if (cancelled) {
+                sd_result r;
+                memset(&r, 0, sizeof(r));
+                finish(S, rq.ticket, SD_E_CANCELLED, r, false);
+            }
+            return SD_OK;
         }
         a.off = off;
         char* A = S->pool_dev + off;
@@ -249,13 +255,24 @@ sd_status admit(sd_server* S) {
         a.I.retain_all = S->ctx->opt.retain_all;
         a.I.g0 = 1;
         sd_status s = ensure_srv_staging(S, lay.a_bytes);
-        if (s) return s;
+        if (s) {
+            S->pool.release(off, a.bytes);
+            std::lock_guard<std::mutex> lk(S->mu);
+            S->queue.push_front(rq);  // failed with the device failure handling of the caller
+            return s;
+        }
         hipError_t e = hipStreamSynchronize(S->ctx->stream);
-        if (e != hipSuccess) return hip_fail(e, "server staging");
-        stage_inputs(a.L, a.I, A, (char*)S->staging);
-        e = hipMemcpyAsync(A, S->staging, lay.a_bytes, hipMemcpyHostToDevice, S->ctx->stream);
+        if (e == hipSuccess) {
+            stage_inputs(a.L, a.I, A, (char*)S->staging);
+            e = hipMemcpyAsync(A, S->staging, lay.a_bytes, hipMemcpyHostToDevice, S->ctx->stream);
+        }
         if (e == hipSuccess) e = hipStreamSynchronize(S->ctx->stream);
-        if (e != hipSuccess) return hip_fail(e, "server upload");
+        if (e != hipSuccess) {
+            S->pool.release(off, a.bytes);
+            std::lock_guard<std::mutex> lk(S->mu);
+            S->queue.push_front(rq);
+            return hip_fail(e, "server upload");
+        }
         a.rq.t_admit = now_s();
         S->st.admitted++;
         S->st.reserved_bytes += a.bytes;
@@ -328,6 +345,7 @@ sd_status round_once(sd_server* S) {
                 r.t_total_s = now_s() - a.rq.t_submit;
                 r.cand_overflow = stats[2] != ~0ull;
                 r.cand_slots_first = a.L.cand_slots;
+                r.path = SD_PATH_PLAIN_AFTER_BARRIER;
             }
             S->st.fallbacks++;
             finish(S, a.rq.ticket, s, r);

@@ -21,6 +21,10 @@ sys.path.insert(0, ROOT)
 import oracle as O  # noqa: E402
 import sdinputs as S  # noqa: E402
 
+# the fixed-point range rule the stored designs were made under (the shift changes the stored
+# objective_fixed, and designs made under another rule are not reused): per-pair energy bound
+RULE = "pair-bound"
+
 WORKLOADS = {
     "plain300": [(300, seed, lam) for seed in (1, 2, 3, 4) for lam in (0.0, 4.0)],
     "plain925_1976": [(925, 1, 0.0), (925, 1, 4.0), (1976, 1, 0.0), (1976, 1, 4.0)],
@@ -53,11 +57,12 @@ def run(name, members, nthreads):
     P = O.Params(params)
     w = S.codon_weights(2026)
     path = os.path.join(HERE, f"{name}.json")
-    out = {"params_sha256": S.sha256_file(params), "codon_seed": 2026, "designs": []}
+    out = {"params_sha256": S.sha256_file(params), "codon_seed": 2026, "fixed_point_rule": RULE,
+           "designs": []}
     if os.path.exists(path):
         with open(path) as fh:
             old = json.load(fh)
-        if old.get("params_sha256") == out["params_sha256"]:
+        if old.get("params_sha256") == out["params_sha256"] and old.get("fixed_point_rule") == RULE:
             out = old
     done = {(d["A"], d["seed"], d["lambda"]) for d in out["designs"]}
     for (A, seed, lam) in members:

@@ -1,8 +1,13 @@
 """Batched designs: one persistent launch (grid barrier per span, hipGraph-captured) must give
-results identical to the plain per-design path and to the CPU oracle."""
+results identical to the plain per-design path and to the CPU oracle.  Every member must come
+from the persistent launch itself (sd_result.path) replayed from a captured graph, so a silent
+fallback to the plain path turns these tests red; under every persistent schedule the member
+tables must equal the dense oracle's cell by cell."""
+import functools
 import json
 import os
 
+import numpy as np
 import pytest
 
 import oracle as O
@@ -43,12 +48,29 @@ def key(r):
     return (r.energy, r.objective_fixed, r.mrna, r.structure, r.n_candidates, r.n_visits)
 
 
-def test_small_mixed_batch_equals_plain_and_oracle(ctx, gt, gp, oparams, weights):
+def persistent(sd, rs):
+    # the result came from the persistent launch, replayed from a captured graph, with no
+    # candidate overflow
+    for r in rs:
+        assert r.path == sd.PATH_PERSISTENT and r.graph_captured == 1 and r.cand_overflow == 0, \
+            (r.path, r.graph_captured, r.cand_overflow)
+        assert r.n_span_launches == 0
+
+
+@functools.lru_cache(maxsize=None)
+def oracle_tables(p, lam, params_path, wkey):
+    return O.design(p, np.array(wkey), O.Params(params_path), lam, tables=True)
+
+
+def test_small_mixed_batch_equals_plain_and_oracle(sd, ctx, gt, gp, oparams, weights):
+    # 31-60 aa members exercise cross-span visibility through the grid barrier: a stale S1 of
+    # the previous span inflates P_S and retains extra candidates (n_visits, n_candidates)
     lens = [6, 9, 15, 31, 40, 50, 12, 7, 44, 25, 60, 3]
     prots = [S.protein(A, 500 + i) for i, A in enumerate(lens)]
     lams = [0.0 if i % 2 == 0 else 4.0 for i in range(len(prots))]
     say("batch", len(prots))
     rb = ctx.design_batch(prots, lams, gt, gp)
+    persistent(sd, rb)
     for p, lam, r in zip(prots, lams, rb):
         say("member", len(p), lam)
         rp = ctx.design(p, gt, gp, lam)
@@ -56,11 +78,13 @@ def test_small_mixed_batch_equals_plain_and_oracle(ctx, gt, gp, oparams, weights
         d = O.design(p, weights, oparams, lam)
         assert (r.energy, r.objective_fixed, r.mrna, r.structure) == (d.energy, d.objective_fixed, d.mrna, d.structure)
         assert abs(r.objective_kcal - d.objective_kcal) <= 1e-9
+        assert (r.n_candidates, r.n_visits, r.n_feasible) == (d.n_candidates, d.visits_sparse, d.n_feasible_direct)
 
 
-def test_batch_with_duplicates_and_single(ctx, gt, gp):
+def test_batch_with_duplicates_and_single(sd, ctx, gt, gp):
     p = S.protein(35, 9)
     rb = ctx.design_batch([p, p, p], [0.0, 4.0, 0.0], gt, gp)
+    persistent(sd, rb)
     assert key(rb[0]) == key(rb[2])
     assert key(rb[1]) == key(ctx.design(p, gt, gp, 4.0))
     r1 = ctx.design_batch([p], [4.0], gt, gp)
@@ -73,7 +97,7 @@ def test_batch_rejects_bad_member(sd, ctx, gt, gp):
     assert e.value.code == -2
 
 
-def test_batch256_members_vs_golden(ctx, gt, gp):
+def test_batch256_members_vs_golden(sd, ctx, gt, gp):
     path = os.path.join(HERE, "golden", "batch256.json")
     if not os.path.exists(path):
         pytest.skip("batch256.json not generated")
@@ -84,6 +108,7 @@ def test_batch256_members_vs_golden(ctx, gt, gp):
         pytest.skip("no members generated yet")
     say("batch256 golden members", len(ds))
     rb = ctx.design_batch([d["protein"] for d in ds], [d["lambda"] for d in ds], gt, gp)
+    persistent(sd, rb)
     for r, d in zip(rb, ds):
         assert (r.energy, r.objective_fixed, r.mrna, r.structure) == (d["energy"], d["objective_fixed"], d["mrna"], d["structure"])
         assert r.n_candidates == d["n_candidates"] and r.n_visits == d["visits_sparse"]
@@ -99,9 +124,40 @@ def test_fixed_schedules_equal_plain(sd, gt, gp, threads, per_cu):
     c = sd.Context(0, batch_threads=threads, batch_per_cu=per_cu)
     say("schedule", threads, per_cu)
     rb = c.design_batch(prots, lams, gt, gp)
+    persistent(sd, rb)
     for p, lam, r in zip(prots, lams, rb):
         assert key(r) == key(c.design(p, gt, gp, lam))
     c.close()
+
+
+@pytest.mark.parametrize("threads,per_cu", [(0, 0), (64, 1), (64, 2), (256, 1), (256, 2), (512, 1)])
+def test_member_tables_equal_dense_oracle(sd, gt, gp, params_path, weights, threads, per_cu):
+    # every typed value, branch value and multiloop value of each member, filled by the
+    # persistent kernel under this schedule, equals the dense oracle's (Theorem 1); the members
+    # span several layer-pair tiles and a ragged tail, both lambdas, in one launch
+    prots = [S.protein(20, 1), S.protein(33, 2), S.protein(41, 3), S.protein(27, 4)]
+    lams = [0.0, 4.0, 4.0, 0.0]
+    c = sd.Context(0, batch_threads=threads, batch_per_cu=per_cu)
+    for m in range(len(prots)):
+        say("batch tables", threads, per_cu, "member", m)
+        rb, T = c.design_batch_tables(prots, lams, gt, gp, m)
+        persistent(sd, rb)
+        d = oracle_tables(prots[m], lams[m], params_path, tuple(float(x) for x in weights))
+        r = rb[m]
+        assert (r.energy, r.objective_fixed, r.mrna, r.structure) == (d.energy, d.objective_fixed, d.mrna, d.structure)
+        assert np.array_equal(T["V"], d.tables["V"])
+        assert np.array_equal(T["B"], d.tables["B"])
+        assert np.array_equal(T["S1"], d.tables["D1"])
+        assert np.array_equal(T["S2"], d.tables["D2"])
+        assert np.array_equal(T["X"], d.tables["X"])
+        assert (r.n_candidates, r.n_visits, r.n_feasible) == (d.n_candidates, d.visits_sparse, d.n_feasible_direct)
+    c.close()
+
+
+def test_batch_tables_member_out_of_range(sd, ctx, gt, gp):
+    with pytest.raises(sd.SDError) as e:
+        ctx.design_batch_tables(["MKV"], [0.0], gt, gp, 1)
+    assert e.value.code == -1
 
 
 def test_invalid_options_rejected(sd):

@@ -66,16 +66,37 @@ def test_bruteforce_sizes(A, seed, lam, ctx, gtable, gparams, oparams, weights):
     assert r.objective_fixed == O.bruteforce(p, weights, oparams, lam)["best_fixed"]
 
 
+_ORACLE_TABLES = {}
+
+
+def oracle_tables(p, lam, oparams, weights):
+    k = (p, lam)
+    if k not in _ORACLE_TABLES:
+        _ORACLE_TABLES[k] = O.design(p, weights, oparams, lam, tables=True)
+    return _ORACLE_TABLES[k]
+
+
+@pytest.fixture(scope="module", params=[0, 64, 256, 512, 1024])
+def span_ctx(request, sd):
+    # 0: the library's per-span choice; the others force one span-kernel instantiation for every
+    # span (k_span<64>: one wave, three job parts; <256>: three parts; <512>: four parts, 80-VGPR
+    # cap; <1024>: six parts)
+    c = sd.Context(0, span_threads=request.param)
+    yield c
+    c.close()
+
+
 @pytest.mark.parametrize("A,seed", [(20, 1), (33, 2), (41, 3)])
 @pytest.mark.parametrize("lam", [0.0, 4.0])
-def test_cell_tables_equal_dense_oracle(A, seed, lam, ctx, gtable, gparams, oparams, weights):
+def test_cell_tables_equal_dense_oracle(A, seed, lam, span_ctx, gtable, gparams, oparams, weights):
     # every typed closed value, branch value and multiloop value equals the dense oracle's
     # (Theorem 1: sparse S1/S2 = dense D1/D2 at every interval, exactly in fixed point)
     p = S.protein(A, seed)
     say("tables", p, lam)
-    r, T = ctx.design_tables(p, gtable, gparams, lam)
-    d = O.design(p, weights, oparams, lam, tables=True)
+    r, T = span_ctx.design_tables(p, gtable, gparams, lam)
+    d = oracle_tables(p, lam, oparams, weights)
     same(r, d)
+    assert r.path == 0 and r.n_span_launches == 3 * A
     assert np.array_equal(T["V"], d.tables["V"])
     assert np.array_equal(T["B"], d.tables["B"])
     assert np.array_equal(T["S1"], d.tables["D1"])

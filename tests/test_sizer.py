@@ -45,22 +45,98 @@ def sd():
     return m
 
 
+def _magnitudes(flat, X, Y, H, K):
+    """Element-wise magnitude of each forward output and gradient entry: the same chain rule with
+    every factor replaced by its absolute value.  An FP32 evaluation of a sum of such products
+    is off by at most about (terms in the sum) * 2^-24 times this magnitude, so it scales the
+    per-element tolerance (a wrong small entry, such as one bias gradient, still fails)."""
+    W1, b1, W2, b2, W3, b3 = [np.abs(a) for a in R.unpack(flat, H, K)]
+    Wr = R.unpack(flat, H, K)
+    X = np.asarray(X, np.float64)
+    n = X.shape[0]
+    z1 = X @ Wr[0].T + Wr[1]
+    h1 = np.maximum(z1, 0.0)
+    z2 = h1 @ Wr[2].T + Wr[3]
+    h2 = np.maximum(z2, 0.0)
+    z3 = h2 @ Wr[4].T + Wr[5]
+    yh = 1.0 / (1.0 + np.exp(-z3))
+    a1 = np.abs(X) @ W1.T + b1
+    a2 = (a1 * (z1 > 0)) @ W2.T + b2
+    a3 = (a2 * (z2 > 0)) @ W3.T + b3
+    # |yh - Y| is computed from an FP32 yh: its error scales with yh, Y and the logit's magnitude
+    d3 = 2.0 / (n * K) * (np.abs(yh - Y) + yh + np.abs(Y) + yh * (1 - yh) * a3) * yh * (1.0 - yh)
+    gW3 = d3.T @ np.abs(h2)
+    gb3 = d3.sum(0)
+    d2 = (d3 @ W3) * (z2 > 0)
+    gW2 = d2.T @ np.abs(h1)
+    gb2 = d2.sum(0)
+    d1 = (d2 @ W2) * (z1 > 0)
+    gW1 = d1.T @ np.abs(X)
+    gb1 = d1.sum(0)
+    g = np.concatenate([gW1.ravel(), gb1, gW2.ravel(), gb2, gW3.ravel(), gb3])
+    return g, yh * (1 - yh) * a3, min(np.abs(z1).min(), np.abs(z2).min())
+
+
+def _inputs_clear_of_kinks(n, K, flat, H, seed):
+    """Random inputs whose FP64 pre-activations all sit clear of the ReLU kink (a pre-activation
+    within FP32 rounding of 0 could take the other branch on the device)."""
+    for s in range(seed, seed + 50):
+        rng = np.random.default_rng(s)
+        X = rng.random((n, 22)).astype(np.float32)
+        Y = rng.random((n, K)).astype(np.float32)
+        if _magnitudes(flat, X, Y, H, K)[2] > 1e-4:
+            return X, Y
+    raise AssertionError("no input draw clear of the ReLU kinks")
+
+
 @pytest.mark.gpu
-def test_device_gradient_matches_cpu_fp64(sd):
+def test_device_gradient_matches_cpu_fp64_elementwise(sd):
     ctx = sd.Context(0)
     H, K = 64, 8
     z = sd.Sizer(ctx, H, K, seed=3)
-    rng = np.random.default_rng(5)
+    flat = z.get_params()
     for n in (1, 37, 300):
-        X = rng.random((n, 22)).astype(np.float32)
-        Y = rng.random((n, K)).astype(np.float32)
-        flat = z.get_params()
+        X, Y = _inputs_clear_of_kinks(n, K, flat, H, 5 + n)
         loss, g = z.gradient(X, Y)
         rl, rg, _ = R.loss_and_grad(flat, X, Y, H, K)
+        mag, _, _ = _magnitudes(flat, X, Y, H, K)
         assert abs(loss - rl) <= 1e-5 * max(1e-3, abs(rl))
-        err = np.linalg.norm(g - rg) / max(np.linalg.norm(rg), 1e-12)
-        print("n", n, "relative gradient error", err, flush=True)
-        assert err <= 1e-4
+        terms = max(n, H, 22) + 4
+        tol = 4 * terms * 2.0 ** -24 * mag + 1e-4 * np.abs(rg) + 1e-12
+        bad = np.flatnonzero(np.abs(g - rg) > tol)
+        print("n", n, "max |g - g_ref| / tol", float(np.max(np.abs(g - rg) / tol)), flush=True)
+        assert bad.size == 0, (n, bad[:10], g[bad[:10]], rg[bad[:10]])
+        # every block of the flat layout is exercised: no block is identically zero on both sides
+        offs = np.cumsum([0, H * 22, H, H * H, H, K * H, K])
+        for lo, hi in zip(offs[:-1], offs[1:]):
+            assert np.any(rg[lo:hi] != 0.0)
+    ctx.close()
+
+
+@pytest.mark.gpu
+def test_forward_device_and_host_match_cpu_fp64(sd):
+    # the device forward pass (k_dense_fwd, used by training) and the host forward pass (used by
+    # sizing and admission) against the FP64 reference, element by element, on the initial
+    # parameters and after training
+    ctx = sd.Context(0)
+    H, K = 64, 8
+    z = sd.Sizer(ctx, H, K, seed=11)
+    rng = np.random.default_rng(12)
+    Xt = rng.random((400, 22)).astype(np.float32)
+    Yt = (0.1 + 0.5 * Xt[:, :8] * Xt[:, 8:16]).astype(np.float32)
+    for stage in ("initial", "trained"):
+        if stage == "trained":
+            z.train(Xt, Yt, steps=300, lr=3e-3)
+        flat = z.get_params()
+        X, Y = _inputs_clear_of_kinks(64, K, flat, H, 40)
+        _, _, yref = R.loss_and_grad(flat, X, Y, H, K)
+        _, mag, _ = _magnitudes(flat, X, Y, H, K)
+        tol = 4 * (H + 26) * 2.0 ** -24 * mag + 2e-7
+        dev, host = z.predict(X), z.predict_host(X)
+        print(stage, "device", float(np.max(np.abs(dev - yref) / tol)), "host",
+              float(np.max(np.abs(host - yref) / tol)), flush=True)
+        assert np.all(np.abs(dev - yref) <= tol)
+        assert np.all(np.abs(host - yref) <= tol)
     ctx.close()
 
 
@@ -128,3 +204,64 @@ def test_sizing_policy_keeps_designs_and_saves_memory(sd, params_path, weights):
         assert (a.energy, a.objective_fixed, a.mrna, a.structure) == (b.energy, b.objective_fixed, b.mrna, b.structure)
     ctx.set_sizer(None)
     ctx.close()
+
+
+@pytest.mark.gpu
+def test_learned_sizer_raises_admitted_concurrency(sd, params_path, weights, oparams):
+    # What the trained network gains: under one fixed server pool, requests reserve less
+    # candidate memory, so more of them run at once; every result stays the oracle's.
+    import math
+    import oracle as O
+    ctx = sd.Context(0)
+    gp, gt = sd.Params(params_path), sd.CodonTable(weights)
+    K = 8
+    train = [S.protein(A, 9100 + i) for i, A in enumerate(S.batch_lengths(120, 60, 260, seed=23))]
+    lams = [0.0 if i % 2 == 0 else 4.0 for i in range(len(train))]
+    Y, _ = ctx.occupancy(train, lams, gt, gp, K)
+    X = np.stack([sd.features(p, l) for p, l in zip(train, lams)])
+    z = sd.Sizer(ctx, 64, K, seed=7)
+    z.train(X, Y, steps=2000, lr=3e-3)
+    ctx.close()
+    lam, margin = 4.0, 1.0
+
+    def serve(p, sized, pool, copies, max_active):
+        c = sd.Context(0)
+        if sized:
+            c.set_sizer(z, margin=margin, slack=8)
+        srv = sd.Server(c, gt, gp, pool_bytes=pool, max_active=max_active, steps_per_round=64)
+        tickets = [srv.submit(p, lam) for _ in range(copies)]
+        res = [srv.wait(t) for t in tickets]
+        st = srv.stats()
+        srv.stop()
+        c.close()
+        return res, st
+
+    # reservation of one request under each policy, for a 200-aa request whose learned
+    # reservation holds (an overflowing one is re-admitted with worst-case segments and then
+    # reserves both)
+    for seed in range(77, 87):
+        p = S.protein(200, seed)
+        _, st_s = serve(p, True, 1 << 30, 1, 4)
+        if st_s["fallbacks"] == 0:
+            break
+    assert st_s["fallbacks"] == 0
+    _, st_w = serve(p, False, 1 << 30, 1, 4)
+    Ww, Ws = st_w["reserved_bytes"], st_s["reserved_bytes"]
+    print("seed", seed, "reservation per request: worst-case", Ww, "learned", Ws, flush=True)
+    assert Ws < Ww
+    # a pool that holds k worst-case reservations but k + 1 learned ones
+    d = Ww - Ws
+    k = max(2, math.ceil(Ws / d))
+    pool = k * Ww + d // 2
+    assert (k + 1) * Ww > pool and (k + 1) * Ws <= pool
+    res_w, st_w = serve(p, False, pool, k + 4, k + 8)
+    res_s, st_s = serve(p, True, pool, k + 4, k + 8)
+    print("pool", pool, "k", k, "peak worst", st_w["peak_active"], "peak learned", st_s["peak_active"],
+          "overflows", st_s["fallbacks"], flush=True)
+    assert st_w["peak_active"] == k
+    assert st_s["peak_active"] >= k + 1
+    d_or = O.design(p, weights, oparams, lam, nthreads=8)
+    for r in res_w + res_s:
+        assert (r.energy, r.objective_fixed, r.mrna, r.structure) == \
+            (d_or.energy, d_or.objective_fixed, d_or.mrna, d_or.structure)
+        assert r.path == sd.PATH_PERSISTENT
