@@ -301,8 +301,9 @@ InstLayout layout_instance(const Lattice& L, char* A, char* B, Inst& I) {
         {I.betaU(), 32 * N, 4 * U}, {I.fwd_off(), 4 * (int64_t)L.fwd_off.size(), 3 * U},
         {I.bwd_off(), 4 * (int64_t)L.bwd_off.size(), 3 * U}, {I.hpB(), 8 * (int64_t)L.hpB.size(), 16 * U},
         {I.OB(), 8 * (int64_t)L.OB.size(), 72 * U}, {I.OA(), 8 * (int64_t)L.OA.size(), 72 * U},
-        {I.stats(), 32, U}, {I.visits(), 8 * (n + 1), U}, {I.feasible(), 8 * (n + 1), U},
-        {I.inmask(), 4 * N, U},
+        {I.stats(), 96, U}, {I.visits(), 8 * (n + 1), U}, {I.feasible(), 8 * (n + 1), U},
+        {I.inmask(), 4 * N, U}, {I.tr_seq(), 4 * n, U}, {I.tr_pair(), 4 * n, U},
+        {I.tr_stack(), 16 * (n + 2), 2 * U}, {I.cstrict(), 4 * N, U},
         {I.LM(), 8 * (int64_t)kLMRing * (n + 1) * 2, 2 * R}, {I.IDL(), 8 * (int64_t)kLMRing * N * 12, 12 * R},
         {I.JDL(), 8 * (int64_t)kLMRing * N * 12, 12 * R}, {I.BI(), 8 * (int64_t)kLMRing * N, R},
         {I.BJ(), 8 * (int64_t)kLMRing * N, R}, {I.RS(), 8 * (int64_t)kLMRing * N * 16, 16 * R},
@@ -474,11 +475,7 @@ sd_status run_plain(sd_context* c, const Lattice& L, Inst& I, int64_t* overflow_
     return SD_OK;
 }
 
-sd_status design_plain(sd_context* c, const char* protein, const sd_codon_table* table,
-                       const sd_params* params, double lambda, sd_result* out, TraceTables* keep,
-                       Lattice* keepL, const std::vector<std::string>* motifs);
-
-// Download the tables the traceback reads.  By default into the context's pinned buffer (grown
+// Download a design's tables (dense test hooks).  By default into the context's pinned buffer (grown
 // on demand, no host zeroing, DMA at full link speed; valid until the next download on this
 // context); with own_storage into host memory owned by T (for results traced back later).
 size_t table_bytes(const Lattice& L) {
@@ -649,23 +646,59 @@ namespace sd {
 // worst-case slots that any right endpoint of the bin filled with retained strict candidates
 // (endpoints with fewer than 64 worst-case slots are left to the sizing slack).  A reservation
 // of this fraction covers every endpoint of the bin, which is what an overflow-free size needs.
-void occupancy_bins(const Lattice& L, const TraceTables& T, int K, float* y) {
+void occupancy_bins(const Lattice& L, const std::vector<int32_t>& counts, int K, float* y) {
     std::vector<double> mx(K, 0.0);
     for (int b = 0; b < L.N; b++) {
         const int lb = L.layer[b], k = position_bin(lb, L.n, K);
         const int worst = lb >= 5 ? L.off[lb - 4] : 0;
         if (worst < 64) continue;
-        int cnt = 0;
-        for (int j = 0; j < T.ccnt[b]; j++) cnt += T.cc[L.coff[b] + j] >= 0;
-        mx[k] = std::max(mx[k], (double)cnt / worst);
+        mx[k] = std::max(mx[k], (double)counts[b] / worst);
     }
     for (int k = 0; k < K; k++) y[k] = (float)mx[k];
 }
 
-// One plain design; optionally keeps the downloaded tables.
+sd_status fetch_trace(sd_context* c, const Lattice& L, const Inst& I, TraceOut& T) {
+    hipStream_t st = c->stream;
+    T.seq.resize(L.n);
+    T.pair.resize(L.n);
+    T.counts.resize(L.N);
+    long long res[4];
+    hipError_t e = hipSuccess;
+    if (L.n > 0) e = hipMemcpyAsync(T.seq.data(), I.tr_seq(), 4 * (size_t)L.n, hipMemcpyDeviceToHost, st);
+    if (e == hipSuccess && L.n > 0)
+        e = hipMemcpyAsync(T.pair.data(), I.tr_pair(), 4 * (size_t)L.n, hipMemcpyDeviceToHost, st);
+    if (e == hipSuccess) e = hipMemcpyAsync(res, I.tr_res(), sizeof(res), hipMemcpyDeviceToHost, st);
+    if (e == hipSuccess)
+        e = hipMemcpyAsync(T.counts.data(), I.retain_all ? I.cstrict() : I.ccnt(), 4 * (size_t)L.N,
+                           hipMemcpyDeviceToHost, st);
+    if (e == hipSuccess) e = hipStreamSynchronize(st);
+    if (e != hipSuccess) return hip_fail(e, "traceback download");
+    T.energy = res[0];
+    T.path_u = res[1];
+    T.status = res[2];
+    T.xs = res[3];
+    return SD_OK;
+}
+
+sd_status trace_and_finish(sd_context* c, const Lattice& L, const Inst& I, int64_t visits, int64_t feasible,
+                           TraceOut& T, sd_result* out) {
+    hipError_t e = launch_trace(I, (const EnergyTables*)c->E_dev, (const int32_t*)c->spec_dev, c->stream);
+    if (e == hipSuccess && I.retain_all) e = launch_strict_count(I, c->stream);
+    if (e != hipSuccess) return hip_fail(e, "traceback launch");
+    sd_status s = fetch_trace(c, L, I, T);
+    if (s) return s;
+    TraceResult R;
+    if (finish_trace(L, T, R)) return fail(SD_E_INTERNAL, "traceback self-check failed");
+    int64_t Z = 0;
+    for (int v = 0; v < L.N; v++) Z += T.counts[v];
+    return fill_result(L, R, T.xs, Z, visits, feasible, out);
+}
+
+// One plain design; optionally keeps its tables (dense test hooks: downloaded), its lattice and
+// the traceback outputs.
 sd_status design_plain(sd_context* c, const char* protein, const sd_codon_table* table,
                        const sd_params* params, double lambda, sd_result* out, TraceTables* keep,
-                       Lattice* keepL, const std::vector<std::string>* motifs) {
+                       Lattice* keepL, const std::vector<std::string>* motifs, TraceOut* keep_trace) {
     const double t0 = now_s();
     if (!c || !table || !params || !out) return fail(SD_E_ARG, "null argument");
     hipError_t he = hipSetDevice(c->device);
@@ -708,23 +741,9 @@ sd_status design_plain(sd_context* c, const char* protein, const sd_codon_table*
         if (rc) return fail((sd_status)rc, err);
     }
     const double tf1 = now_s();
-    TraceTables T;
-    s = fetch_tables(c, L, I, T);
+    TraceOut T;
+    s = trace_and_finish(c, L, I, c->last_visits, c->last_feasible, T, out);
     if (s) return s;
-    L.gtab = T.G;
-    TraceResult R;
-    rc = trace_design(L, params->p, T, R);
-    if (rc) return fail((sd_status)rc, "traceback self-check failed");
-    int64_t Z = 0;
-    for (int v = 0; v < L.N; v++) Z += T.ccnt[v];
-    s = fill_result(L, R, T.X[0], c->opt.retain_all ? -1 : Z, c->last_visits, c->last_feasible, out);
-    if (s) return s;
-    if (c->opt.retain_all) {
-        int64_t strict = 0;
-        for (int v = 0; v < L.N; v++)
-            for (int k = 0; k < T.ccnt[v]; k++) strict += T.cc[L.coff[v] + k] >= 0;
-        out->n_candidates = strict;
-    }
     out->t_fill_s = tf1 - tf0;
     out->t_total_s = now_s() - t0;
     out->t_span_kernels_s = c->last_kernel_ms * 1e-3;
@@ -733,7 +752,14 @@ sd_status design_plain(sd_context* c, const char* protein, const sd_codon_table*
     out->cand_slots = L.cand_slots;
     out->cand_slots_first = slots_first;
     out->cand_overflow = overflowed;
-    if (keep) *keep = std::move(T);
+    if (keep) {
+        s = fetch_tables(c, L, I, *keep, true);
+        if (s) {
+            sd_result_free(out);
+            return s;
+        }
+    }
+    if (keep_trace) *keep_trace = std::move(T);
     if (keepL) *keepL = std::move(L);
     return SD_OK;
 }
@@ -905,7 +931,7 @@ namespace sd {
 // instance descriptors (in the arena) through Is.  *barrier_ok is false when the grid barrier
 // reported a wait beyond its spin limit (the caller then recomputes in plain mode).
 sd_status run_batch(sd_context* c, std::vector<Lattice>& Ls, std::vector<Inst>& Is, int grid,
-                    int threads, bool* barrier_ok, double* kernel_s) {
+                    int threads, bool* barrier_ok, double* kernel_s, Inst** insts_out) {
     const int n = (int)Ls.size();
     Is.assign(n, Inst{});
     std::vector<InstLayout> lay(n);
@@ -978,6 +1004,7 @@ sd_status run_batch(sd_context* c, std::vector<Lattice>& Ls, std::vector<Inst>& 
     c->last_graph = captured;
     *kernel_s = ms * 1e-3;
     *barrier_ok = hctl.err.v == 0 && hctl.steps_done.v == (unsigned)(maxn + 1);  // nsteps = maxn + 1
+    if (insts_out) *insts_out = insts_dev;
     return SD_OK;
 }
 
@@ -1036,7 +1063,7 @@ sd_status tuned_schedule(sd_context* c, const std::vector<Lattice>& batch, int* 
             std::vector<Inst> Is;
             bool ok = false;
             double ks = 0;
-            sd_status s = run_batch(c, Ls, Is, gr, threads_c, &ok, &ks);
+            sd_status s = run_batch(c, Ls, Is, gr, threads_c, &ok, &ks, nullptr);
             if (s) return s;
             if (ok && ks < best_t) {
                 best_t = ks;
@@ -1091,8 +1118,17 @@ sd_status design_batch_impl(sd_context* ctx, int n, const char* const* proteins,
             std::vector<Inst> Is;
             bool ok = false;
             double ks = 0;
-            if (!s) s = run_batch(ctx, Ls, Is, grid, threads, &ok, &ks);
+            Inst* insts_dev = nullptr;
+            if (!s) s = run_batch(ctx, Ls, Is, grid, threads, &ok, &ks, &insts_dev);
             const double tf1 = now_s();
+            // the canonical traceback of every member in one launch (one wavefront each)
+            if (!s && ok) {
+                hipError_t e = launch_trace_many(insts_dev, m, (const EnergyTables*)ctx->E_dev,
+                                                 (const int32_t*)ctx->spec_dev, ctx->stream);
+                for (int i = 0; i < m && e == hipSuccess; i++)
+                    if (Is[i].retain_all) e = launch_strict_count(Is[i], ctx->stream);
+                if (e != hipSuccess) s = hip_fail(e, "batched traceback launch");
+            }
             if (s) {
                 for (int j = 0; j < done; j++) sd_result_free(&outs[j]);
                 return s;
@@ -1112,9 +1148,11 @@ sd_status design_batch_impl(sd_context* ctx, int n, const char* const* proteins,
                     // with worst-case segments
                     TraceTables T2;
                     Lattice L2;
+                    TraceOut O2;
                     const int fw = ctx->force_worst;
                     ctx->force_worst = 1;
-                    s = design_plain(ctx, proteins[gi], table, params, lambdas[gi], &outs[gi], &T2, &L2, nullptr);
+                    s = design_plain(ctx, proteins[gi], table, params, lambdas[gi], &outs[gi],
+                                     gi == dump_member ? &T2 : nullptr, &L2, nullptr, &O2);
                     ctx->force_worst = fw;
                     ctx->last_batch_fallbacks++;
                     if (!s && gi == dump_member) dense_tables(L2, T2, D);
@@ -1122,24 +1160,27 @@ sd_status design_batch_impl(sd_context* ctx, int n, const char* const* proteins,
                         outs[gi].cand_slots_first = Ls[i].cand_slots;
                         outs[gi].cand_overflow = st[2] != ~0ull;
                         outs[gi].path = ok ? SD_PATH_PLAIN_AFTER_OVERFLOW : SD_PATH_PLAIN_AFTER_BARRIER;
-                        if (ctx->occ_K > 0) occupancy_bins(L2, T2, ctx->occ_K, &ctx->occ[(size_t)gi * ctx->occ_K]);
+                        if (ctx->occ_K > 0) occupancy_bins(L2, O2.counts, ctx->occ_K, &ctx->occ[(size_t)gi * ctx->occ_K]);
                     }
                     continue;
                 }
-                TraceTables T;
-                s = fetch_tables(ctx, Ls[i], Is[i], T);
+                TraceOut T;
+                s = fetch_trace(ctx, Ls[i], Is[i], T);
                 if (s) break;
-                if (gi == dump_member) dense_tables(Ls[i], T, D);
+                if (gi == dump_member) {
+                    TraceTables TT;
+                    s = fetch_tables(ctx, Ls[i], Is[i], TT, true);
+                    if (s) break;
+                    dense_tables(Ls[i], TT, D);
+                }
                 TraceResult R;
-                int rc = trace_design(Ls[i], params->p, T, R);
-                if (rc) {
-                    s = fail((sd_status)rc, "traceback self-check failed");
+                if (finish_trace(Ls[i], T, R)) {
+                    s = fail(SD_E_INTERNAL, "traceback self-check failed");
                     break;
                 }
                 int64_t Z = 0;
-                for (int v = 0; v < Ls[i].N; v++)
-                    for (int k = 0; k < T.ccnt[v]; k++) Z += T.cc[Ls[i].coff[v] + k] >= 0;
-                s = fill_result(Ls[i], R, T.X[0], Z, (int64_t)st[0], (int64_t)st[3], &outs[gi]);
+                for (int v = 0; v < Ls[i].N; v++) Z += T.counts[v];
+                s = fill_result(Ls[i], R, T.xs, Z, (int64_t)st[0], (int64_t)st[3], &outs[gi]);
                 if (s) break;
                 outs[gi].t_fill_s = (tf1 - tf0) / m;
                 outs[gi].t_total_s = now_s() - t0;
@@ -1150,7 +1191,7 @@ sd_status design_batch_impl(sd_context* ctx, int n, const char* const* proteins,
                 outs[gi].cand_overflow = 0;
                 outs[gi].path = SD_PATH_PERSISTENT;
                 outs[gi].graph_captured = ctx->last_graph ? 1 : 0;
-                if (ctx->occ_K > 0) occupancy_bins(Ls[i], T, ctx->occ_K, &ctx->occ[(size_t)gi * ctx->occ_K]);
+                if (ctx->occ_K > 0) occupancy_bins(Ls[i], T.counts, ctx->occ_K, &ctx->occ[(size_t)gi * ctx->occ_K]);
             }
             if (s) {
                 for (int j = 0; j < done + m; j++) sd_result_free(&outs[j]);

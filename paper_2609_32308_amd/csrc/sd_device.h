@@ -23,7 +23,7 @@ struct sd_context {
     int batch_grid = 0;       // autotuned persistent grid size (0: not tuned yet)
     int batch_threads = 256;  // autotuned threads per block of the persistent launch
     std::map<int, std::pair<int, int>> sched;  // size class -> (grid, threads) from the tuner
-    char* tbuf = nullptr;  // pinned download buffer of the traceback tables
+    char* tbuf = nullptr;  // pinned download buffer of the dense-table test hooks
     size_t tbuf_bytes = 0;
     bool last_graph = false;  // last batch ran as a captured graph
     double last_batch_kernel_s = 0.0, last_batch_fill_s = 0.0;
@@ -59,6 +59,12 @@ hipError_t launch_init(const Inst& I, hipStream_t st);
 hipError_t launch_span(const Inst& I, const EnergyTables* E, const int32_t* spec, int g,
                        int ext_layer, int threads, hipStream_t st);
 hipError_t launch_ext(const Inst& I, const EnergyTables* E, int L, hipStream_t st);
+// canonical traceback of one design (one wavefront) / of every design of a device Inst array
+hipError_t launch_trace(const Inst& I, const EnergyTables* E, const int32_t* spec, hipStream_t st);
+hipError_t launch_trace_many(const Inst* insts_dev, int n, const EnergyTables* E, const int32_t* spec,
+                             hipStream_t st);
+// strict candidates per right endpoint into cstrict (retain-all control)
+hipError_t launch_strict_count(const Inst& I, hipStream_t st);
 hipError_t launch_span_gen(const Inst& I, const EnergyTables* E, const int32_t* spec, int g,
                            int ext_layer, int num_cu, hipStream_t st);
 hipError_t launch_batch_init(const Inst* insts_dev, int ninst, BatchCtl* ctl, hipStream_t st);

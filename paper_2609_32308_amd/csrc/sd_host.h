@@ -30,9 +30,18 @@ sd_status fetch_tables(sd_context* c, const Lattice& L, const Inst& I, TraceTabl
                        char* into = nullptr);
 sd_status fill_result(const Lattice& L, const TraceResult& R, int64_t xs, int64_t Z, int64_t visits,
                       int64_t feasible, sd_result* out);
+// Copies the device traceback's O(n + N) outputs of an instance whose k_trace has run on the
+// context's stream (synchronises it); counts are the strict candidates per right endpoint.
+sd_status fetch_trace(sd_context* c, const Lattice& L, const Inst& I, TraceOut& T);
+// Runs the traceback of one placed, filled instance and completes its result on the host.
+sd_status trace_and_finish(sd_context* c, const Lattice& L, const Inst& I, int64_t visits, int64_t feasible,
+                           TraceOut& T, sd_result* out);
+// Largest retained fraction of the worst-case slots per position bin (occupancy logging).
+void occupancy_bins(const Lattice& L, const std::vector<int32_t>& counts, int K, float* y);
 sd_status design_plain(sd_context* c, const char* protein, const sd_codon_table* table,
                        const sd_params* params, double lambda, sd_result* out, TraceTables* keep,
-                       Lattice* keepL, const std::vector<std::string>* motifs = nullptr);
+                       Lattice* keepL, const std::vector<std::string>* motifs = nullptr,
+                       TraceOut* keep_trace = nullptr);
 CapPolicy policy_for(const sd_context* c, const char* protein, double lambda, std::vector<float>& frac);
 // destinations of the dense test layout (any may be null)
 struct DenseOut {

@@ -43,6 +43,12 @@ struct EnergyTables {
 constexpr int32_t kNoSpecial = 0x7fffffff;
 constexpr int kSpecOff5 = 0, kSpecOff6 = 1024, kSpecOff8 = 1024 + 4096, kSpecSize = 1024 + 4096 + 65536;
 
+// A pending decision of the traceback: kind (external column, closed value, S1, S2, branch),
+// the cell (a, b) and, for closed values, the pair type.
+struct TFrame {
+    int kind, a, b, t;
+};
+
 // Instance descriptor.  All arrays of one design live in two device regions whose layout is a
 // function of a few sizes, so the descriptor holds two base pointers plus sizes and every array
 // address is recomputed arithmetically where it is used (cheap scalar ALU, few live registers,
@@ -53,8 +59,10 @@ constexpr int kSpecOff5 = 0, kSpecOff6 = 1024, kSpecOff8 = 1024 + 4096, kSpecSiz
 //   0 layer[N]  1 off[n+2]  2 in_start[N+1]  3 tail[N]  4 pfx[N]  5 P[A+1]  6 hp_init[n+1]
 //   7 rowoff[N]  8 coff[N]  9 ccap[N]  10 ccnt[N]  11 X[N]  12-13 out_dst[4N]  14-17 out_U[4N]
 //   18-21 alphaU[4N]  22-25 betaU[4N]  26-28 fwd_off[4N+1]  29-31 bwd_off[4N+1]
-//   32-47 hpB[16N]  48-119 OB[72N]  120-191 OA[72N]  192 stats[4]  193 visits[n+1]
-//   194 feasible[n+1]  195 inmask[N]  196.. in_src[nE], in_lab[nE], in_U[nE], fwd_meta[nF], fwd_cost[nF], bwd_meta[nB],
+//   32-47 hpB[16N]  48-119 OB[72N]  120-191 OA[72N]  192 stats[4], trace results [8..11]
+//   193 visits[n+1]  194 feasible[n+1]  195 inmask[N]  196 tr_seq[n]  197 tr_pair[n]
+//   198-199 tr_stack[n+2] (16-byte frames)  200 cstrict[N]
+//   201.. in_src[nE], in_lab[nE], in_U[nE], fwd_meta[nF], fwd_cost[nF], bwd_meta[nB],
 //         bwd_cost[nB], fwd_crow[nF] (each start 8-byte aligned)
 // Region B (DP tables) is cut into ring units of R = 512 * N bytes (N states x 64 spans x 8 B):
 //   0-1 LM  2-13 IDL  14-25 JDL  26 BI  27 BJ  28-43 RS  44-59 LS  60-61 MINI, then from 62 R:
@@ -72,7 +80,10 @@ constexpr int kSpecOff5 = 0, kSpecOff6 = 1024, kSpecOff8 = 1024 + 4096, kSpecSiz
 //   cell(a,b) = rowoff[a] + b - off[layer(a)+1]; V/Bt/S1/S2: typed closed values, branch value,
 //   multiloop prefixes; coff/ccap/ccnt/cc/cB: candidate segment per right endpoint (offset,
 //   capacity, committed count, start states with the non-strict flag in bit 31, B values);
-//   X: external column; stats: [2] earliest overflow span (others unused); visits / feasible:
+//   X: external column; stats: [2] earliest overflow span, [8..11] traceback results (energy,
+//   path cost, status, X(s)); tr_seq / tr_pair: the traceback's base label per position and
+//   pairing partner per position (-1 unpaired); tr_stack: its pending decisions; cstrict:
+//   strict candidates per right endpoint (retain-all control only); visits / feasible:
 //   candidate visits and cells with finite B, summed per left layer (one adder per layer pair
 //   and step, so the counters see no contention).
 //   alphaU[d*4+x] = U(d -x-> d2) + tail(d2); betaU[c*4+x] = min U over in-edges of c labelled x.
@@ -131,10 +142,15 @@ struct Inst {
     __host__ __device__ unsigned long long* visits() const { return (unsigned long long*)ua(193); }
     __host__ __device__ unsigned long long* feasible() const { return (unsigned long long*)ua(194); }
     __host__ __device__ const int* inmask() const { return (const int*)ua(195); }
-    __host__ __device__ const int* in_src() const { return (const int*)ua(196); }
-    __host__ __device__ const int* in_lab() const { return (const int*)(ua(196) + al8(4 * nE)); }
-    __host__ __device__ const int64_t* in_U() const { return (const int64_t*)(ua(196) + 2 * al8(4 * nE)); }
-    __host__ __device__ char* paths() const { return ua(196) + 2 * al8(4 * nE) + 8 * nE; }
+    __host__ __device__ int* tr_seq() const { return (int*)ua(196); }
+    __host__ __device__ int* tr_pair() const { return (int*)ua(197); }
+    __host__ __device__ TFrame* tr_stack() const { return (TFrame*)ua(198); }
+    __host__ __device__ int* cstrict() const { return (int*)ua(200); }
+    __host__ __device__ long long* tr_res() const { return (long long*)ua(192) + 8; }
+    __host__ __device__ const int* in_src() const { return (const int*)ua(201); }
+    __host__ __device__ const int* in_lab() const { return (const int*)(ua(201) + al8(4 * nE)); }
+    __host__ __device__ const int64_t* in_U() const { return (const int64_t*)(ua(201) + 2 * al8(4 * nE)); }
+    __host__ __device__ char* paths() const { return ua(201) + 2 * al8(4 * nE) + 8 * nE; }
     __host__ __device__ const int* fwd_meta() const { return (const int*)paths(); }
     __host__ __device__ const int64_t* fwd_cost() const { return (const int64_t*)(paths() + al8(4 * nF)); }
     __host__ __device__ const int* bwd_meta() const { return (const int*)(paths() + al8(4 * nF) + 8 * nF); }

@@ -244,19 +244,6 @@ int check_protein(const char* p) {
     return SD_OK;
 }
 
-int64_t host_gap(const Lattice& L, int a, int b) {
-    int la = L.layer[a], lb = L.layer[b];
-    if (la == lb) return a == b ? 0 : kINF;
-    if (la > lb) return kINF;
-    if (L.generic) return L.gtab ? L.gtab[L.rowoff[a] + (b - L.off[la + 1])] : kINF;
-    int ka = la / 3, kb = lb / 3;
-    if (ka == kb) {
-        if (la % 3 == 0) return 0;
-        return (L.pfx[b] >> 2) == L.pfx[a] ? 0 : kINF;
-    }
-    return L.tail[a] + L.P[kb] - L.P[ka + 1];
-}
-
 int position_bin(int layer, int n, int K) {
     const int k = n > 0 ? (int)(((int64_t)layer * K) / (n + 1)) : 0;
     return k < K ? k : K - 1;

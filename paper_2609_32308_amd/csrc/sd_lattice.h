@@ -48,14 +48,12 @@ struct Lattice {
     int64_t cells = 0, cand_slots = 0;
     int64_t mlbase_fx = 0;
     // generic lattice (codon automaton x forbidden-motif matcher): the kernels use gap tables
-    // instead of the trie's closed form; gtab is the downloaded gap table (cell layout) that
-    // host_gap reads during the traceback
+    // instead of the trie's closed form
     bool generic = false;
     int gwin = 0, wmax = 0;
     std::vector<std::string> motifs;
     std::vector<int64_t> gjob_off;  // [n+2]: jobs of span g are [gjob_off[g], gjob_off[g+1])
     std::vector<int32_t> gjobs;     // pairs (a, b*8 + type) of typed-value jobs
-    const int64_t* gtab = nullptr;
 };
 
 // validation and construction; return sd_status values
@@ -83,8 +81,6 @@ int build_motif_lattice(const char* protein, const CodonTable& T, const Params& 
                         const CapPolicy& cap, const std::vector<std::string>& motifs, Lattice& L,
                         std::string& err);
 
-// minimum path cost between two states (closed form on the trie, the gap table otherwise)
-int64_t host_gap(const Lattice& L, int a, int b);
 
 std::string sha256_hex(const std::string& data);
 int parse_params(const std::string& text, Params& P, std::string& err);

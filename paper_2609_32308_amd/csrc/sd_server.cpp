@@ -6,8 +6,9 @@
 //      segments come from the context's sizing policy (learned sizer or worst case);
 //   2. runs one persistent launch of `steps_per_round` span steps over every active instance,
 //      each at its own span (new instances start at span 1 and are initialised by the launch);
-//   3. retires instances that passed their last span: their tables are copied out, their pool
-//      memory is released at once, and the canonical traceback runs on host worker threads.
+//   3. retires instances that passed their last span: the canonical traceback of all of them
+//      runs on the device in one launch (one wavefront each), only its O(n) outputs are copied
+//      back, and their pool memory is released at once.
 // An instance whose candidate reservation overflowed is recomputed exactly in plain mode with
 // worst-case segments, so every result equals the standalone design.
 #include <hip/hip_runtime.h>
@@ -28,6 +29,10 @@
 using namespace sd;
 
 namespace {
+
+// auxiliary device buffer: the round's instance descriptors, the barrier state, then the
+// descriptors of the instances retiring in the round (traceback launch)
+constexpr size_t kAuxTrace = ((sizeof(Inst) * kMaxBatch + sizeof(BatchCtl) + 255) / 256) * 256;
 
 // first-fit allocator over one device buffer (offsets, 256-byte granularity)
 struct Pool {
@@ -117,21 +122,6 @@ struct sd_server {
     uint64_t next_ticket = 1;
     std::atomic<bool> stop{false};
     std::thread loop;
-    // traceback workers
-    std::mutex tmu;
-    std::condition_variable tcv;
-    struct Job {
-        Active a;
-        TraceTables T;
-        char* pinned = nullptr;  // pinned host buffer holding T, returned to the pool after use
-        size_t pinned_bytes = 0;
-        int64_t visits, feasible;
-        double t_fill;
-    };
-    std::vector<std::pair<char*, size_t>> pinned_free;  // reusable pinned table buffers (under tmu)
-    std::deque<Job> jobs;
-    std::vector<std::thread> workers;
-    int jobs_running = 0;
     sd_server_stats st{};
 };
 
@@ -143,41 +133,6 @@ void finish(sd_server* S, uint64_t ticket, sd_status status, const sd_result& r,
     S->done[ticket] = Done{status, r};
     if (completed) S->st.completed++;
     S->cv_done.notify_all();
-}
-
-void worker_main(sd_server* S) {
-    for (;;) {
-        sd_server::Job job;
-        {
-            std::unique_lock<std::mutex> lk(S->tmu);
-            S->tcv.wait(lk, [&] { return S->stop || !S->jobs.empty(); });
-            if (S->jobs.empty()) return;
-            job = std::move(S->jobs.front());
-            S->jobs.pop_front();
-            S->jobs_running++;
-        }
-        TraceResult R;
-        sd_result r;
-        memset(&r, 0, sizeof(r));
-        sd_status s = (sd_status)trace_design(job.a.L, S->params->p, job.T, R);
-        if (!s) {
-            int64_t Z = 0;
-            for (int v = 0; v < job.a.L.N; v++)
-                for (int k = 0; k < job.T.ccnt[v]; k++) Z += job.T.cc[job.a.L.coff[v] + k] >= 0;
-            s = fill_result(job.a.L, R, job.T.X[0], Z, job.visits, job.feasible, &r);
-            r.path = SD_PATH_PERSISTENT;
-            r.graph_captured = 0;
-            r.t_fill_s = job.t_fill;
-            r.t_total_s = now_s() - job.a.rq.t_submit;
-            r.cand_slots = job.a.L.cand_slots;
-            r.cand_slots_first = job.a.rq.worst ? job.a.rq.first_slots : job.a.L.cand_slots;
-            r.cand_overflow = job.a.rq.worst ? 1 : 0;
-        }
-        finish(S, job.a.rq.ticket, s, r);
-        std::lock_guard<std::mutex> lk(S->tmu);
-        if (job.pinned) S->pinned_free.push_back({job.pinned, job.pinned_bytes});
-        S->jobs_running--;
-    }
 }
 
 sd_status ensure_srv_staging(sd_server* S, size_t bytes) {
@@ -309,6 +264,8 @@ sd_status round_once(sd_server* S) {
     const bool ok = h.err.v == 0 && h.steps_done.v == (unsigned)S->cfg.steps_per_round;
     // advance and retire
     std::vector<Active> keep;
+    std::vector<int> retiring;
+    std::vector<int64_t> visits, feasible;
     for (int i = 0; i < n; i++) {
         Active& a = S->active[i];
         a.g += S->cfg.steps_per_round;
@@ -351,44 +308,48 @@ sd_status round_once(sd_server* S) {
             finish(S, a.rq.ticket, s, r);
             continue;
         }
-        sd_server::Job job;
-        // pinned buffer from the pool (smallest that fits), else a new one; host memory as a
-        // last resort
-        const size_t need = table_bytes(a.L);
-        {
-            std::lock_guard<std::mutex> lk(S->tmu);
-            int best = -1;
-            for (int k = 0; k < (int)S->pinned_free.size(); k++)
-                if (S->pinned_free[k].second >= need &&
-                    (best < 0 || S->pinned_free[k].second < S->pinned_free[best].second))
-                    best = k;
-            if (best >= 0) {
-                job.pinned = S->pinned_free[best].first;
-                job.pinned_bytes = S->pinned_free[best].second;
-                S->pinned_free.erase(S->pinned_free.begin() + best);
+        retiring.push_back(i);
+        visits.push_back((int64_t)stats[0]);
+        feasible.push_back((int64_t)stats[3]);
+    }
+    // canonical traceback of every retiring instance on the device, then O(n) results per request
+    if (!retiring.empty()) {
+        const int nt = (int)retiring.size();
+        std::vector<Inst> Ts(nt);
+        for (int k = 0; k < nt; k++) Ts[k] = S->active[retiring[k]].I;
+        Inst* tdev = (Inst*)(S->aux_dev + kAuxTrace);
+        e = hipMemcpyAsync(tdev, Ts.data(), sizeof(Inst) * nt, hipMemcpyHostToDevice, st);
+        if (e == hipSuccess)
+            e = launch_trace_many(tdev, nt, (const EnergyTables*)S->ctx->E_dev, (const int32_t*)S->ctx->spec_dev, st);
+        for (int k = 0; k < nt && e == hipSuccess; k++)
+            if (Ts[k].retain_all) e = launch_strict_count(Ts[k], st);
+        if (e != hipSuccess) return hip_fail(e, "server traceback");
+        for (int k = 0; k < nt; k++) {
+            Active& a = S->active[retiring[k]];
+            TraceOut T;
+            sd_status s = fetch_trace(S->ctx, a.L, a.I, T);
+            S->pool.release(a.off, a.bytes);
+            if (s) return s;
+            sd_result r;
+            memset(&r, 0, sizeof(r));
+            TraceResult R;
+            s = finish_trace(a.L, T, R) ? fail(SD_E_INTERNAL, "traceback self-check failed") : SD_OK;
+            if (!s) {
+                int64_t Z = 0;
+                for (int v = 0; v < a.L.N; v++) Z += T.counts[v];
+                s = fill_result(a.L, R, T.xs, Z, visits[k], feasible[k], &r);
             }
-        }
-        if (!job.pinned) {
-            const size_t want = need + need / 8;
-            if (hipHostMalloc((void**)&job.pinned, want, hipHostMallocDefault) == hipSuccess) {
-                job.pinned_bytes = want;
-            } else {
-                hipGetLastError();
-                job.pinned = nullptr;
+            if (!s) {
+                r.path = SD_PATH_PERSISTENT;
+                r.graph_captured = 0;
+                r.t_fill_s = a.rq.t_admit > 0 ? now_s() - a.rq.t_admit : 0.0;
+                r.t_total_s = now_s() - a.rq.t_submit;
+                r.cand_slots = a.L.cand_slots;
+                r.cand_slots_first = a.rq.worst ? a.rq.first_slots : a.L.cand_slots;
+                r.cand_overflow = a.rq.worst ? 1 : 0;
             }
+            finish(S, a.rq.ticket, s, r);
         }
-        sd_status s = fetch_tables(S->ctx, a.L, a.I, job.T, true, job.pinned);
-        S->pool.release(a.off, a.bytes);
-        if (s) return s;
-        job.visits = (int64_t)stats[0];
-        job.feasible = (int64_t)stats[3];
-        job.t_fill = a.rq.t_admit > 0 ? now_s() - a.rq.t_admit : 0.0;
-        job.a = std::move(a);
-        {
-            std::lock_guard<std::mutex> lk(S->tmu);
-            S->jobs.push_back(std::move(job));
-        }
-        S->tcv.notify_one();
     }
     S->active = std::move(keep);
     return SD_OK;
@@ -435,7 +396,7 @@ extern "C" sd_status sd_server_start(sd_context* ctx, const sd_codon_table* tabl
     S->cfg = *cfg;
     hipError_t e = hipSetDevice(ctx->device);
     if (e == hipSuccess) e = hipMalloc((void**)&S->pool_dev, cfg->pool_bytes);
-    if (e == hipSuccess) e = hipMalloc((void**)&S->aux_dev, sizeof(Inst) * kMaxBatch + sizeof(BatchCtl) + 256);
+    if (e == hipSuccess) e = hipMalloc((void**)&S->aux_dev, kAuxTrace + sizeof(Inst) * kMaxBatch);
     if (e != hipSuccess) {
         if (S->pool_dev) hipFree(S->pool_dev);
         delete S;
@@ -458,7 +419,6 @@ extern "C" sd_status sd_server_start(sd_context* ctx, const sd_codon_table* tabl
         S->threads = ctx->batch_grid > 0 ? ctx->batch_threads : 256;
         S->grid = ctx->batch_grid > 0 ? ctx->batch_grid : per_cu * ctx->num_cu;
     }
-    for (int i = 0; i < 4; i++) S->workers.emplace_back(worker_main, S);
     S->loop = std::thread(server_main, S);
     *out = S;
     return SD_OK;
@@ -519,13 +479,7 @@ extern "C" sd_status sd_server_stop(sd_server* S) {
         S->cv_done.notify_all();
     }
     if (S->loop.joinable()) S->loop.join();
-    {
-        std::lock_guard<std::mutex> lk(S->tmu);
-        S->tcv.notify_all();
-    }
-    for (auto& w : S->workers) w.join();
     for (auto& kv : S->done) sd_result_free(&kv.second.res);
-    for (auto& b : S->pinned_free) hipHostFree(b.first);  // every job has returned its buffer
     hipFree(S->pool_dev);
     hipFree(S->aux_dev);
     if (S->staging) hipHostFree(S->staging);
