@@ -1,18 +1,20 @@
 """Benchmark of the exact coding-sequence design DP on one MI355X.
 
     python bench.py [--gpus 1] [--steps K] [--warmup W]
-                    [--workload plain300|plain925_1976|scale|batch|served|motifs] [--no-cpu-baseline]
+                    [--workload batch256|plain300|plain925_1976|scale|served|motifs] [--no-cpu-baseline]
 
 A step is one pass of the whole path over one batch of synthetic input.  Inputs are protein
 strings handed to the C ABI; the library builds the automaton, uploads it, fills the DP on the
-GPU, runs the canonical traceback and returns the result strings.
-  plain300 (default): one 300-aa synthetic protein (Met + 298 uniform residues + stop, seed 1),
-                     designed at lambda = 0 and lambda = 4 in plain mode (one span-step kernel
-                     launch per span length);
+GPU, runs the canonical traceback on the GPU and returns the result strings.
+  batch256 (default): 256 proteins, lengths log-uniform in [50, 1000] aa (seed 7), the first 128
+                     at lambda = 0 and the rest at lambda = 4, in one persistent, graph-captured
+                     launch per step.  The same 256 designs are also run once in plain mode (one
+                     span-step launch per span length) and once through the continuous-batching
+                     server at saturation, and reported beside the batched rate;
+  plain300:          one 300-aa synthetic protein (Met + 298 uniform residues + stop, seed 1),
+                     designed at lambda = 0 and lambda = 4 in plain mode;
   plain925_1976:     the 925-aa and 1,976-aa proteins (seed 1) at lambda = 0 and 4, plain mode;
   scale:             one 3,677-aa protein (seed 1) at lambda = 0 and 4, plain mode;
-  batch:             256 proteins, lengths log-uniform in [50, 1000] aa (seed 7), half at
-                     lambda = 0 and half at lambda = 4, in one batched persistent launch;
   served:            a Poisson request stream through the continuous-batching server, with the
                      learned candidate sizer against worst-case sizing (see served_workload);
   motifs:            one 105-aa protein avoiding 16 random 6-mers at lambda = 0 and 4 (the
@@ -24,12 +26,13 @@ allocation, the O(N) input upload and the forward fill, without automaton build 
 `complete_cells_per_s` and `designs_per_min` use complete time (input strings to result
 strings).  One JSON line is printed.
 
-Roofline of the dominant kernel (the span step): algorithmic HBM bytes per launch =
-(72 B per cell for the V/B/S1/S2 writes + 20 B per candidate visit + 12 B per appended
-candidate) / launches, divided by the kernel's average duration measured with HIP events on the
-library's stream.  `traffic` comes from the committed rocprofv3 counter summary if it was taken
-on the current kernel source, else null.  `cpu_baseline` times the CPU oracle (test
-infrastructure, dense O(N^3) reference) on a bounded sample of the same workload.
+Roofline of the dominant kernel (the persistent launch for batch256, the span step for the plain
+workloads): algorithmic HBM bytes per launch = (72 B per cell for the V/B/S1/S2 writes + 20 B
+per candidate visit + 12 B per appended candidate) / launches, divided by the kernel's average
+duration measured with HIP events on the library's stream.  `traffic` comes from the committed
+rocprofv3 counter summary if it was taken on the current kernel source, else null.
+`cpu_baseline` times the CPU oracle (test infrastructure, dense O(N^3) reference) on a bounded
+sample of the same workload.
 """
 import argparse
 import hashlib
@@ -68,11 +71,13 @@ def workload(name):
         p = S.protein(3677, 1)
         return [(p, 0.0), (p, 4.0)], {"workload": "plain design, one 3677-aa synthetic protein (seed 1; the length of the paper's largest design), lambda 0 and 4",
                                       "aa": 3677, "lambdas": [0, 4], "mode": "plain"}
-    if name == "batch":
+    if name == "batch256":
         lens = S.batch_lengths(256, 50, 1000, seed=7)
         items = [(S.protein(A, 7000 + i), 0.0 if i < 128 else 4.0) for i, A in enumerate(lens)]
-        return items, {"workload": "batched design, 256 synthetic proteins log-uniform in [50,1000] aa, half lambda 0 / half lambda 4",
-                       "proteins": 256, "aa_range": [50, 1000], "mode": "batch"}
+        return items, {"workload": "batched design, 256 synthetic proteins log-uniform in [50,1000] aa (seed 7), "
+                                   "128 at lambda 0 and 128 at lambda 4, one persistent graph-captured launch per step; "
+                                   "the same designs in plain mode and served, beside it",
+                       "proteins": 256, "aa_range": [50, 1000], "lambdas": [0, 4], "mode": "batch"}
     if name == "motifs":
         p = S.protein(105, 1)
         return [(p, 0.0), (p, 4.0)], {"workload": "forbidden-motif design, one 105-aa synthetic protein (seed 1) avoiding 16 random 6-mers (seed 7), lambda 0 and 4",
@@ -87,7 +92,7 @@ def kernel_source_sha():
     return h.hexdigest()
 
 
-COUNTER_FILES = {"plain300": "k_span_plain300_counters.json", "batch": "k_persistent_batch256_counters.json",
+COUNTER_FILES = {"plain300": "k_span_plain300_counters.json", "batch256": "k_persistent_batch256_counters.json",
                  "motifs": "k_gen_closed_motifs_105aa_counters.json"}
 
 
@@ -198,6 +203,55 @@ def roofline_for(results_steps, counters, batch, kernel=None):
 
 def progress(msg):
     print(msg, file=sys.stderr, flush=True)
+
+
+def side_legs(sd, items, table, params, batched_results, batched_elapsed_per_step):
+    """The batch's own designs in plain mode (one pass) and through the server at saturation
+    (one pass, worst-case candidate sizing, all requests submitted at once), each checked to give
+    the batched designs, with their rates beside the batched ones."""
+    cells = sum(r.n_cells for r in batched_results)
+    key = lambda r: (r.energy, r.objective_fixed, r.mrna, r.structure)
+    ctx = sd.Context(0)
+    t0 = time.perf_counter()
+    plain = []
+    for i, (p, lam) in enumerate(items):
+        plain.append(ctx.design(p, table, params, lam))
+        if i % 64 == 63:
+            progress(f"plain leg {i + 1}/{len(items)}")
+    t_plain = time.perf_counter() - t0
+    ctx.close()
+    per_lam = {}
+    for lam in sorted({l for _, l in items}):
+        rs = [r for (p, l), r in zip(items, plain) if l == lam]
+        per_lam[f"lambda{lam:g}"] = {"designs": len(rs), "fill_cells_per_s": sum(r.n_cells for r in rs) / sum(r.t_fill_s for r in rs),
+                                     "complete_cells_per_s": sum(r.n_cells for r in rs) / sum(r.t_total_s for r in rs)}
+    plain_fill = sum(r.t_fill_s for r in plain)
+    out = {"plain": {"fill_cells_per_s": cells / plain_fill, "complete_cells_per_s": cells / t_plain,
+                     "designs_per_min": len(items) / t_plain * 60.0, "fill_s": plain_fill, "complete_s": t_plain,
+                     "per_lambda": per_lam,
+                     "identical_to_batched": all(key(a) == key(b) for a, b in zip(plain, batched_results))}}
+    progress("plain leg done")
+    ctx = sd.Context(0)
+    srv = sd.Server(ctx, table, params, pool_bytes=64 << 30, max_active=len(items), steps_per_round=64)
+    t0 = time.perf_counter()
+    tickets = [srv.submit(p, lam) for p, lam in items]
+    served = [srv.wait(t) for t in tickets]
+    t_srv = time.perf_counter() - t0
+    st = srv.stats()
+    srv.stop()
+    ctx.close()
+    lat = sorted(r.t_total_s for r in served)
+    out["served_saturated"] = {
+        "designs_per_min": len(items) / t_srv * 60.0, "complete_cells_per_s": cells / t_srv,
+        "p50_s": lat[len(lat) // 2], "p99_s": lat[min(len(lat) - 1, int(math.ceil(0.99 * len(lat))) - 1)],
+        "rounds": st["rounds"], "peak_active": st["peak_active"], "fallbacks": st["fallbacks"],
+        "pool_gib": 64, "identical_to_batched": all(key(a) == key(b) for a, b in zip(served, batched_results)),
+        "all_persistent": all(r.path == sd.PATH_PERSISTENT for r in served)}
+    progress("served leg done")
+    out["batched_over_plain"] = {"fill": (cells / sum(r.t_fill_s for r in batched_results)) / (cells / plain_fill),
+                                 "complete": t_plain / batched_elapsed_per_step}
+    out["served_over_plain_complete"] = t_plain / t_srv
+    return out
 
 
 def served_workload(args, sd, S):
@@ -312,7 +366,7 @@ def main():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=5)
     ap.add_argument("--warmup", type=int, default=1)
-    ap.add_argument("--workload", default="plain300", choices=["plain300", "plain925_1976", "scale", "batch", "served", "motifs"])
+    ap.add_argument("--workload", default="batch256", choices=["batch256", "plain300", "plain925_1976", "scale", "served", "motifs"])
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--retain-all", action="store_true",
                     help="plain workloads: also time the scalar-dense control (every finite direct "
@@ -345,17 +399,20 @@ def main():
         served_workload(args, sd, S)
         return
     items, config = workload(args.workload)
-    batch = args.workload == "batch"
+    batch = args.workload == "batch256"
     motifs = config.get("motifs")
     ctx = sd.Context(0, kernel_timing=KERNEL_TIMING_EVERY)
     params = sd.Params(S.default_params_path())
     table = sd.CodonTable(S.codon_weights(2026))
-    for _ in range(args.warmup):
+    for i in range(args.warmup):
         run_step(ctx, items, table, params, batch, motifs)
+        progress(f"warmup step {i + 1}/{args.warmup}")
     t0 = time.perf_counter()
     results = []
-    for _ in range(args.steps):
+    for i in range(args.steps):
         results.append(run_step(ctx, items, table, params, batch, motifs))
+        if batch or i % 5 == 4:
+            progress(f"timed step {i + 1}/{args.steps}")
     t1 = time.perf_counter()
     elapsed = t1 - t0
     step_cells = sum(r.n_cells for r in results[0])
@@ -384,6 +441,11 @@ def main():
         "params_sha256": params.sha256,
     }
     ctx.close()
+    if batch:
+        line["batch"] = {"paths": sorted({r.path for r in results[-1]}),
+                         "graph_captured": all(r.graph_captured == 1 for r in results[-1]),
+                         "launch_s": sum(r.t_span_kernels_s for r in results[-1])}
+        line.update(side_legs(sd, items, table, params, results[-1], elapsed / args.steps))
     if motifs:
         line["per_design"] = {k: dict(v, n_states=r.n_states) for (k, v), r in zip(line["per_design"].items(), results[-1])}
     if args.retain_all and not batch and not motifs:

@@ -1282,15 +1282,23 @@ __global__ __launch_bounds__(256) void k_span_gen(Inst I, const EnergyTables* __
 // counter.  The barrier is two-level: the last arrival of a group counts the group at the top
 // word, the last group bumps the generation (agent-scope release / acquire).
 //
-// Release: every wave of the workgroup fences at agent scope before the workgroup barrier.  The
-// cell values (S1, S2, B, V) and the candidate appends are stored by many waves, and a
-// workgroup barrier alone neither waits for their stores (no vmcnt wait before s_barrier) nor
-// writes them back from this XCD's L2; thread 0's own fence only covers wave 0's stores.
-// Without the per-wave fence a workgroup on another XCD could read a value of the previous
-// span from memory before it was written back (a stale S1 makes P_S too large and the
-// retention test then keeps extra non-strict candidates).
+// Release: the cell values (S1, S2, B, V) and the candidate appends are stored by many waves,
+// and a workgroup barrier alone does not wait for their stores (no vmcnt wait before
+// s_barrier), while thread 0's agent-scope fence (L2 write-back, then its own vmcnt wait) only
+// covers the stores that have reached this XCD's L2.  So every wave first waits until its own
+// stores are acknowledged by L2 (vmcnt 0); after the workgroup barrier, thread 0's write-back
+// then carries every wave's stores to memory before the arrival.  Without the per-wave wait a
+// workgroup on another XCD could read a value of the previous span from memory before it was
+// written back (a stale S1 makes P_S too large and the retention test then keeps extra
+// non-strict candidates).  A full agent-scope fence in every wave is also correct but repeats
+// the L2 write-back once per wave (8 s instead of 5 s for the 256-design batch).
+__device__ __forceinline__ void wait_own_stores() {
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "workgroup");  // keeps the compiler from sinking stores
+    __builtin_amdgcn_s_waitcnt(0x0F70);                      // vmcnt(0), expcnt and lgkmcnt untouched
+}
+
 __device__ bool grid_barrier(BatchCtl* ctl, unsigned spin_cap, int* s_flag) {
-    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "agent");
+    wait_own_stores();
     __syncthreads();
     if (threadIdx.x == 0) {
         __threadfence();
