@@ -160,6 +160,22 @@ void sd_context_destroy(sd_context *ctx);
 sd_status sd_design(sd_context *ctx, const char *protein, const sd_codon_table *table,
                     const sd_params *params, double lambda_kcal, sd_result *out);
 
+/* For callers that cannot allocate device memory (code under HIP graph capture, tight serving
+ * loops, harnesses that forbid allocation): sd_design with no allocation.  The design's device
+ * state (energy tables, automaton inputs, DP tables, rings and candidate segments) is placed in
+ * one static device array of 256 MiB that the library holds on each GPU it runs on until the
+ * process ends (its address is taken once per device when a context is created there); no
+ * hipMalloc, hipFree or other allocating device routine is called.  Inputs and outputs are as
+ * for sd_design (plain mode; result strings are host allocations owned by the caller, freed
+ * with sd_result_free); the context's kernel_timing option is ignored.  A design whose state
+ * does not fit the array gives SD_E_NOMEM with the bytes it needs (about 72 B per cell plus
+ * 31 KiB per automaton state: a 300-aa design takes about 75 MiB, 500 aa is near the limit;
+ * sd_design has no such limit).  Every call on a GPU shares that GPU's array, which keeps the
+ * last call's contents: calls that overlap on one GPU (from any contexts or threads) race and
+ * must be serialised by the caller.  SD_E_DEVICE if the array has no address on the device. */
+sd_status sd_design_noalloc(sd_context *ctx, const char *protein, const sd_codon_table *table,
+                            const sd_params *params, double lambda_kcal, sd_result *out);
+
 /* n designs in one persistent, graph-captured launch (all instances advance one span per grid
  * barrier; the schedule is autotuned on a sample of the batch or fixed by sd_options).
  * proteins[i] (as for sd_design) with lambdas[i]; outs[i] (array of n) receives each result,

@@ -40,7 +40,7 @@ EXPORTS = [
     "sd_server_stop", "sd_lambda_envelope", "sd_design_motifs", "sd_inverse_lambda",
     "sd_design_motifs_tables", "sd_motif_lattice_size", "sd_context_create_external",
     "sd_sizer_request_bytes", "sd_fixed_shift", "sd_design_batch_tables",
-    "sd_sizer_predict_host",
+    "sd_sizer_predict_host", "sd_design_noalloc",
 ]
 
 
@@ -101,6 +101,7 @@ def lib():
         L.sd_context_create.argtypes = [C.c_int, C.POINTER(Options), C.POINTER(vp)]
         L.sd_context_destroy.argtypes = [vp]
         L.sd_design.argtypes = [vp, C.c_char_p, vp, vp, C.c_double, C.POINTER(_Result)]
+        L.sd_design_noalloc.argtypes = [vp, C.c_char_p, vp, vp, C.c_double, C.POINTER(_Result)]
         L.sd_design_motifs.argtypes = [vp, C.c_char_p, C.POINTER(C.c_char_p), C.c_int, vp, vp, C.c_double,
                                        C.POINTER(_Result)]
         L.sd_inverse_lambda.argtypes = [vp, C.c_char_p, C.c_double, C.c_double, C.c_int, vp, vp,
@@ -263,6 +264,13 @@ class Context:
     def design(self, protein: str, table: CodonTable, params: Params, lam: float) -> Result:
         r = _Result()
         _check(lib().sd_design(self.h, protein.encode(), table.h, params.h, float(lam), C.byref(r)), "sd_design")
+        return _convert(r)
+
+    def design_noalloc(self, protein: str, table: CodonTable, params: Params, lam: float) -> Result:
+        """sd_design with the device state in the library's static scratch array (no allocation)."""
+        r = _Result()
+        _check(lib().sd_design_noalloc(self.h, protein.encode(), table.h, params.h, float(lam), C.byref(r)),
+               "sd_design_noalloc")
         return _convert(r)
 
     def design_motifs(self, protein: str, motifs, table: CodonTable, params: Params, lam: float) -> Result:

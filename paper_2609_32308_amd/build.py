@@ -7,7 +7,7 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 CSRC = os.path.join(HERE, "csrc")
 LIB = os.path.join(HERE, "libsparsedesign.so")
 SOURCES = ["sd_kernels.hip", "sd_trace.hip", "sd_mlp.hip", "sd_api.cpp", "sd_server.cpp", "sd_envelope.cpp", "sd_lattice.cpp",
-           "sd_traceback.cpp",
+           "sd_traceback.cpp", "sd_noalloc.cpp",
            "sd_sha256.cpp"]
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 FLAGS = ["-O3", "-std=c++17", "-fPIC", "--offload-arch=gfx950",

@@ -179,6 +179,9 @@ sd_status context_create(int device, const sd_options* opt, bool ext, void* ext_
         e = hipStreamCreateWithFlags(&c->stream, hipStreamNonBlocking);
     }
     if (e == hipSuccess) e = upload_pair_order();
+    // this device's address of the static scratch array of sd_design_noalloc (its own error
+    // is reported by that entry point; the other entry points do not use the array)
+    if (e == hipSuccess && scratch_setup(device) != SD_OK) g_err.clear();
     if (e == hipSuccess) e = hipEventCreate(&c->ev0);
     if (e == hipSuccess) e = hipEventCreate(&c->ev1);
     if (e != hipSuccess) {
@@ -424,6 +427,9 @@ hipError_t read_stats(const Inst& I, hipStream_t st, unsigned long long out[4]) 
 #ifndef SPAN_XWIDE_PER_CU
 #define SPAN_XWIDE_PER_CU 1
 #endif
+sd_status run_plain_on(sd_context* c, const Lattice& L, Inst& I, const EnergyTables* Et, const int32_t* spec,
+                       int kernel_timing, int64_t* overflow_span);
+
 int span_threads_for(const sd_context* c, int pairs) {
     if (c->opt.span_threads) return c->opt.span_threads;
     if (pairs <= SPAN_XWIDE_PER_CU * c->num_cu) return 1024;
@@ -432,9 +438,16 @@ int span_threads_for(const sd_context* c, int pairs) {
 
 // Plain mode: one span-step launch per span length.  Returns the overflow span (0 if none).
 sd_status run_plain(sd_context* c, const Lattice& L, Inst& I, int64_t* overflow_span) {
+    return run_plain_on(c, L, I, (const EnergyTables*)c->E_dev, (const int32_t*)c->spec_dev, c->opt.kernel_timing,
+                        overflow_span);
+}
+
+// The same with explicit energy tables and kernel timing (0: none).
+sd_status run_plain_on(sd_context* c, const Lattice& L, Inst& I, const EnergyTables* Et, const int32_t* spec,
+                       int kernel_timing, int64_t* overflow_span) {
     hipStream_t st = c->stream;
     hipError_t e = launch_init(I, st);
-    const bool timing = c->opt.kernel_timing != 0;
+    const bool timing = kernel_timing != 0;
     if (timing && (int)c->tev.size() < 2 * L.n) {
         while ((int)c->tev.size() < 2 * L.n && e == hipSuccess) {
             hipEvent_t ev;
@@ -442,19 +455,17 @@ sd_status run_plain(sd_context* c, const Lattice& L, Inst& I, int64_t* overflow_
             if (e == hipSuccess) c->tev.push_back(ev);
         }
     }
-    const int every = timing ? c->opt.kernel_timing : 1;
+    const int every = timing ? kernel_timing : 1;
     for (int g = 1; g <= L.n && e == hipSuccess; g++) {
         const bool timed = timing && (g - 1) % every == 0;
         if (timed) e = hipEventRecord(c->tev[2 * (g - 1)], st);
         if (e == hipSuccess && L.generic)
-            e = launch_span_gen(I, (const EnergyTables*)c->E_dev, (const int32_t*)c->spec_dev, g,
-                                g >= 2 ? L.n - g + 1 : -1, c->num_cu, st);
+            e = launch_span_gen(I, Et, spec, g, g >= 2 ? L.n - g + 1 : -1, c->num_cu, st);
         else if (e == hipSuccess)
-            e = launch_span(I, (const EnergyTables*)c->E_dev, (const int32_t*)c->spec_dev, g,
-                            g >= 2 ? L.n - g + 1 : -1, span_threads_for(c, L.n - g + 1), st);
+            e = launch_span(I, Et, spec, g, g >= 2 ? L.n - g + 1 : -1, span_threads_for(c, L.n - g + 1), st);
         if (timed && e == hipSuccess) e = hipEventRecord(c->tev[2 * (g - 1) + 1], st);
     }
-    if (e == hipSuccess) e = launch_ext(I, (const EnergyTables*)c->E_dev, 0, st);
+    if (e == hipSuccess) e = launch_ext(I, Et, 0, st);
     unsigned long long stats[4];
     if (e == hipSuccess) e = read_stats(I, st, stats);
     if (e != hipSuccess) return hip_fail(e, "span wavefront");
@@ -682,7 +693,13 @@ sd_status fetch_trace(sd_context* c, const Lattice& L, const Inst& I, TraceOut& 
 
 sd_status trace_and_finish(sd_context* c, const Lattice& L, const Inst& I, int64_t visits, int64_t feasible,
                            TraceOut& T, sd_result* out) {
-    hipError_t e = launch_trace(I, (const EnergyTables*)c->E_dev, (const int32_t*)c->spec_dev, c->stream);
+    return trace_and_finish_on(c, L, I, (const EnergyTables*)c->E_dev, (const int32_t*)c->spec_dev, visits,
+                               feasible, T, out);
+}
+
+sd_status trace_and_finish_on(sd_context* c, const Lattice& L, const Inst& I, const EnergyTables* Et,
+                              const int32_t* spec, int64_t visits, int64_t feasible, TraceOut& T, sd_result* out) {
+    hipError_t e = launch_trace(I, Et, spec, c->stream);
     if (e == hipSuccess && I.retain_all) e = launch_strict_count(I, c->stream);
     if (e != hipSuccess) return hip_fail(e, "traceback launch");
     sd_status s = fetch_trace(c, L, I, T);

@@ -36,6 +36,17 @@ sd_status fetch_trace(sd_context* c, const Lattice& L, const Inst& I, TraceOut& 
 // Runs the traceback of one placed, filled instance and completes its result on the host.
 sd_status trace_and_finish(sd_context* c, const Lattice& L, const Inst& I, int64_t visits, int64_t feasible,
                            TraceOut& T, sd_result* out);
+sd_status trace_and_finish_on(sd_context* c, const Lattice& L, const Inst& I, const EnergyTables* Et,
+                              const int32_t* spec, int64_t visits, int64_t feasible, TraceOut& T, sd_result* out);
+// Plain-mode fill of a placed instance (one span-step launch per span) with explicit energy
+// tables; kernel_timing as in sd_options (0: no events).  *overflow_span: 0 or the first span
+// whose candidate appends overflowed.
+sd_status run_plain_on(sd_context* c, const Lattice& L, Inst& I, const EnergyTables* Et, const int32_t* spec,
+                       int kernel_timing, int64_t* overflow_span);
+// Device address of this device's static scratch array (sd_noalloc.cpp), set when a context is
+// created on it; null if that set-up failed.
+char* scratch_base(int device);
+sd_status scratch_setup(int device);
 // Largest retained fraction of the worst-case slots per position bin (occupancy logging).
 void occupancy_bins(const Lattice& L, const std::vector<int32_t>& counts, int K, float* y);
 sd_status design_plain(sd_context* c, const char* protein, const sd_codon_table* table,
