@@ -260,50 +260,69 @@ def served_workload(args, sd, S):
     Requests: lengths log-uniform in [50, 2000] aa, lambda uniform in {0, 4}, protein seeds
     200000 + i, arrival times from a seeded exponential.  The sizer is trained on the exact
     DP's own occupancy logs of synthetic proteins (seeds 100000 + i, same length law, both
-    lambdas), 10 % held out.  The plain GPU DP on the same
-    requests, one after another, gives the capacity that sets the offered load.
+    lambdas), 10 % held out.  The plain GPU DP on the same requests, one after another, gives
+    the capacity that sets the offered load and the designs every served result must equal.
+
+    A full run (2,000 requests, loads 0.5 / 0.8 / 0.95 and saturation, both policies) takes
+    longer than one GPU call here, so it can be split: --save-sizer / --load-sizer keep the
+    trained parameters between calls, --loads and --policies pick the runs, and --capacity
+    reuses a measured plain capacity (the plain designs are then not recomputed, and served
+    results are compared with a stored digest of them, --plain-digest).
     """
+    import numpy as np
     params = sd.Params(S.default_params_path())
     table = sd.CodonTable(S.codon_weights(2026))
     ctx = sd.Context(0)
     nreq, ntrain, K = args.requests, args.train_proteins, 8
-    # learned sizer: exact occupancy logs -> FP32 MLP trained on the GPU
-    tl = S.batch_lengths(ntrain, 50, 2000, seed=100000)
-    train = [S.protein(A, 100000 + i) for i, A in enumerate(tl)]
-    tlam = [0.0 if i % 2 == 0 else 4.0 for i in range(ntrain)]
-    t = time.time()
-    import numpy as np
-    Ys = []
-    for i in range(0, ntrain, 100):  # chunks, so that a long log reports progress
-        Ys.append(ctx.occupancy(train[i:i + 100], tlam[i:i + 100], table, params, K)[0])
-        progress(f"occupancy log {min(ntrain, i + 100)}/{ntrain}")
-    Y = np.concatenate(Ys)
-    t_log = time.time() - t
-    progress(f"occupancy log of {ntrain} proteins: {t_log:.1f} s")
-    import numpy as np
-    X = np.stack([sd.features(p, l) for p, l in zip(train, tlam)]).astype(np.float32)
-    cut = int(0.9 * ntrain)
     sizer = sd.Sizer(ctx, 64, K, seed=11)
-    t = time.time()
-    sizer.train(X[:cut], Y[:cut], steps=2000, lr=3e-3)
-    t_train = time.time() - t
-    held = float(np.mean((sizer.predict(X[cut:]) - Y[cut:]) ** 2))
-    progress(f"sizer trained in {t_train:.1f} s, held-out MSE {held:.3g}")
+    sizer_info = {"train_proteins": ntrain, "train_aa_range": [50, 2000], "bins": K, "hidden": 64}
+    if args.load_sizer:
+        sizer.set_params(np.load(args.load_sizer))
+        sizer_info["loaded_from"] = os.path.basename(args.load_sizer)
+    else:
+        # learned sizer: exact occupancy logs -> FP32 MLP trained on the GPU
+        tl = S.batch_lengths(ntrain, 50, 2000, seed=100000)
+        train = [S.protein(A, 100000 + i) for i, A in enumerate(tl)]
+        tlam = [0.0 if i % 2 == 0 else 4.0 for i in range(ntrain)]
+        t = time.time()
+        Ys = []
+        for i in range(0, ntrain, 100):  # chunks, so that a long log reports progress
+            Ys.append(ctx.occupancy(train[i:i + 100], tlam[i:i + 100], table, params, K)[0])
+            progress(f"occupancy log {min(ntrain, i + 100)}/{ntrain}")
+        Y = np.concatenate(Ys)
+        t_log = time.time() - t
+        progress(f"occupancy log of {ntrain} proteins: {t_log:.1f} s")
+        X = np.stack([sd.features(p, l) for p, l in zip(train, tlam)]).astype(np.float32)
+        cut = int(0.9 * ntrain)
+        t = time.time()
+        sizer.train(X[:cut], Y[:cut], steps=2000, lr=3e-3)
+        t_train = time.time() - t
+        held = float(np.mean((sizer.predict(X[cut:]) - Y[cut:]) ** 2))
+        progress(f"sizer trained in {t_train:.1f} s, held-out MSE {held:.3g}")
+        sizer_info.update({"occupancy_log_s": t_log, "train_s": t_train, "heldout_mse": held})
+        if args.save_sizer:
+            np.save(args.save_sizer, sizer.get_params())
     # request stream
     rl = S.batch_lengths(nreq, 50, 2000, seed=11)
     rng = random.Random(11)
     reqs = [(S.protein(A, 200000 + i), rng.choice([0.0, 4.0])) for i, A in enumerate(rl)]
-    cells_total = 0
-    t = time.time()
-    plain = []
-    for i, (p, lam) in enumerate(reqs):
-        plain.append(ctx.design(p, table, params, lam))
-        if i % 20 == 19:
-            progress(f"plain {i + 1}/{nreq}")
-    t_plain = time.time() - t
-    cells_total = sum(r.n_cells for r in plain)
-    capacity = nreq / t_plain  # designs/s, plain, one after another
+    key = lambda r: f"{r.energy}|{r.objective_fixed}|{r.mrna}|{r.structure}"
+    if args.capacity > 0:
+        capacity, t_plain, plain = args.capacity, None, None
+        digest = args.plain_digest
+        cells_total = None
+    else:
+        t = time.time()
+        plain = []
+        for i, (p, lam) in enumerate(reqs):
+            plain.append(ctx.design(p, table, params, lam))
+            if i % 20 == 19:
+                progress(f"plain {i + 1}/{nreq}")
+        t_plain = time.time() - t
+        capacity = nreq / t_plain  # designs/s, plain, one after another
+        digest = hashlib.sha256("\n".join(key(r) for r in plain).encode()).hexdigest()
     ctx.close()
+    lat_plain = sorted(r.t_total_s for r in plain) if plain else None
 
     def serve(policy, rho):
         c = sd.Context(0)
@@ -314,7 +333,7 @@ def served_workload(args, sd, S):
         t0 = time.perf_counter()
         tickets, t_sub = [], []
         next_t = 0.0
-        for p, lam in reqs:
+        for i, (p, lam) in enumerate(reqs):
             if rho > 0:
                 next_t += arng.expovariate(rho * capacity)
                 dt = t0 + next_t - time.perf_counter()
@@ -322,41 +341,49 @@ def served_workload(args, sd, S):
                     time.sleep(dt)
             t_sub.append(time.perf_counter() - t0)
             tickets.append(srv.submit(p, lam))
+            if i % 50 == 49:  # paced arrivals take minutes at low load: report them as they go
+                progress(f"submitted {policy} load {rho}: {i + 1}/{nreq}")
         res = []
         for i, tk in enumerate(tickets):
             res.append(srv.wait(tk))
-            if i % 20 == 19:
+            if i % 50 == 49:
                 progress(f"served {policy} load {rho}: {i + 1}/{nreq}")
         st = srv.stats()
         srv.stop()
         c.close()
         lat = sorted(r.t_total_s for r in res)
         done = max(ts + r.t_total_s for ts, r in zip(t_sub, res))
-        same = all((a.energy, a.objective_fixed, a.mrna, a.structure) == (b.energy, b.objective_fixed, b.mrna, b.structure)
-                   for a, b in zip(res, plain))
+        cells = sum(r.n_cells for r in res)
+        same = hashlib.sha256("\n".join(key(r) for r in res).encode()).hexdigest() == digest
         return {"policy": policy, "offered_load": rho if rho > 0 else "saturated",
-                "designs_per_min": nreq / done * 60.0, "cells_per_s": cells_total / done,
+                "designs_per_min": nreq / done * 60.0, "cells_per_s": cells / done,
                 "p50_s": lat[len(lat) // 2], "p99_s": lat[min(len(lat) - 1, int(math.ceil(0.99 * len(lat))) - 1)],
                 "peak_active": st["peak_active"], "fallbacks": st["fallbacks"], "rounds": st["rounds"],
                 "reserved_bytes_per_request": st["reserved_bytes"] / nreq,
                 "reserved_cand_bytes_per_request": st["reserved_cand_bytes"] / nreq,
                 "pool_high_water": st["pool_high_water"], "gpu_busy_frac": st["gpu_seconds"] / done,
-                "identical_to_plain": same}
+                "identical_to_plain": same,
+                "all_persistent": all(r.path == sd.PATH_PERSISTENT for r in res)}
 
-    runs = [serve("worst", 0.0), serve("mlp", 0.0), serve("worst", 0.8), serve("mlp", 0.8), serve("mlp", 0.95)]
-    sat = runs[1]
+    runs = []
+    for rho in args.loads:
+        for policy in args.policies:
+            runs.append(serve(policy, rho))
+            progress(f"run {policy} {rho}: {runs[-1]['designs_per_min']:.1f} designs/min")
+    head = runs[0]
     line = {
-        "metric": METRIC, "value": sat["cells_per_s"], "unit": "cells/s", "n_gpus": 1, "steps": 1, "warmup": 0,
-        "ms_per_step": nreq / sat["designs_per_min"] * 60.0 * 1e3, "higher_is_better": True, "scaling": "weak",
+        "metric": METRIC, "value": head["cells_per_s"], "unit": "cells/s", "n_gpus": 1, "steps": 1, "warmup": 0,
+        "ms_per_step": nreq / head["designs_per_min"] * 60.0 * 1e3, "higher_is_better": True, "scaling": "weak",
         "vs_baseline": None, "dtype": "int64", "data": "synthetic",
         "config": {"workload": f"served: {nreq} requests, lengths log-uniform in [50,2000] aa, lambda in {{0,4}}, "
-                               f"Poisson arrivals, pool {args.pool_gib} GiB, learned sizer", "requests": nreq,
+                               f"Poisson arrivals, pool {args.pool_gib} GiB", "requests": nreq,
                    "aa_range": [50, 2000], "mode": "served"},
-        "plain_sequential": {"designs_per_min": nreq / t_plain * 60.0, "cells_per_s": cells_total / t_plain,
-                             "p50_s": sorted(r.t_total_s for r in plain)[nreq // 2]},
+        "plain_sequential": {"designs_per_min": capacity * 60.0, "capacity_designs_per_s": capacity,
+                             "cells_per_s": (sum(r.n_cells for r in plain) / t_plain) if plain else None,
+                             "p50_s": lat_plain[nreq // 2] if plain else None, "measured_in_this_run": plain is not None,
+                             "results_digest": digest},
         "served_runs": runs,
-        "sizer": {"train_proteins": ntrain, "train_aa_range": [50, 2000], "bins": K, "hidden": 64,
-                  "occupancy_log_s": t_log, "train_s": t_train, "heldout_mse": held},
+        "sizer": sizer_info,
     }
     print(json.dumps(line), flush=True)
 
@@ -374,6 +401,15 @@ def main():
     ap.add_argument("--requests", type=int, default=100, help="served: number of requests")
     ap.add_argument("--train-proteins", type=int, default=120, help="served: proteins in the occupancy log")
     ap.add_argument("--pool-gib", type=int, default=8, help="served: device pool of the server")
+    ap.add_argument("--loads", type=float, nargs="+", default=[0.0, 0.8],
+                    help="served: offered loads as fractions of the plain capacity (0: saturated)")
+    ap.add_argument("--policies", nargs="+", default=["worst", "mlp"], choices=["worst", "mlp"],
+                    help="served: candidate sizing policies to run at every load")
+    ap.add_argument("--save-sizer", default="", help="served: write the trained sizer parameters (.npy)")
+    ap.add_argument("--load-sizer", default="", help="served: use these sizer parameters instead of training")
+    ap.add_argument("--capacity", type=float, default=0.0,
+                    help="served: plain capacity in designs/s from an earlier run (skips the plain pass)")
+    ap.add_argument("--plain-digest", default="", help="served: SHA-256 digest of the plain results of that run")
     ap.add_argument("--copy-calibration-mib", type=int, default=0,
                     help="only run a plain device copy of this many MiB (counter calibration)")
     args = ap.parse_args()
@@ -444,7 +480,8 @@ def main():
     if batch:
         line["batch"] = {"paths": sorted({r.path for r in results[-1]}),
                          "graph_captured": all(r.graph_captured == 1 for r in results[-1]),
-                         "launch_s": sum(r.t_span_kernels_s for r in results[-1])}
+                         "launch_s": sum(r.t_span_kernels_s for r in results[-1]),
+                         "schedule": sorted({(r.sched_threads, r.sched_grid) for r in results[-1]})}
         line.update(side_legs(sd, items, table, params, results[-1], elapsed / args.steps))
     if motifs:
         line["per_design"] = {k: dict(v, n_states=r.n_states) for (k, v), r in zip(line["per_design"].items(), results[-1])}

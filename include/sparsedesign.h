@@ -73,7 +73,16 @@ typedef struct sd_options {
     int batch_threads;     /* persistent (batched / served) launch: threads per workgroup, 64,
                               256 or 512, with batch_per_cu workgroups per CU; both 0: autotuned */
     int batch_per_cu;
-    int reserved[2];
+    int span_check;        /* debug mode (race detection): 1 = plain designs run every span step
+                              twice, the second time with another workgroup size after restoring
+                              the committed candidate counts and the counters, and compare digests
+                              of everything the step wrote; batched designs re-run the whole
+                              persistent launch under another schedule and compare a digest of
+                              each member's tables.  A difference fails the call with
+                              SD_E_INTERNAL naming the span or member.  2 = the same, but the
+                              visit counters are deliberately not restored before the re-run, so
+                              the comparison must fail (a self-test of the check).  0 = off   */
+    int reserved[1];
 } sd_options;
 
 typedef struct sd_result {
@@ -103,6 +112,10 @@ typedef struct sd_result {
     int32_t path;            /* which forward fill produced the result (sd_path below)         */
     int32_t graph_captured;  /* 1 if that fill was a persistent launch replayed from a captured
                                 hipGraph, else 0                                               */
+    int32_t sched_threads;   /* persistent launch behind the result: threads per workgroup
+                                (0 for the plain paths)                                        */
+    int32_t sched_grid;      /* ... and its workgroup count (resident workgroups per CU times
+                                the CU count; 0 for the plain paths)                           */
 } sd_result;
 
 /* sd_result.path: the fill behind a result.  Batched and served results come from the persistent
@@ -266,6 +279,18 @@ sd_status sd_design_motifs_tables(sd_context *ctx, const char *protein, const ch
  * [16, 40] qualifies (a very large lambda); SD_E_PROTEIN, SD_E_LAMBDA, SD_E_ARG for bad inputs. */
 sd_status sd_fixed_shift(const char *protein, const sd_codon_table *table, const sd_params *params,
                          double lambda_kcal, int32_t *shift);
+/* Test hook: the multiloop recurrences alone (eqs. 6-7 with the online retention test) on an
+ * abstract layered DAG, the exact-integer abstract test of Sec. 7.1, run by the span step's own
+ * device code with the direct costs given instead of computed from loop energies.  States
+ * 0..N-1 in layer order (layer[0] = 0, consecutive non-empty layers of at most 4 states);
+ * n_edges edges esrc[k] -> edst[k] between consecutive layers (at most 4 out of a state) with
+ * unpaired-edge costs eu[k]; B[a*N + b] the direct cost of the arc (a, b) (>= 2^61: none).
+ * Costs must lie in [-2^40, 2^40] (SD_E_RANGE).  Outputs, dense [a*N + b]: S1 and S2 (2^62 for
+ * rho(a) >= rho(b) or infeasible), cand[a*N + b] = 1 if a was retained in C_b, and Z = sum |C_b|.
+ * SD_E_ARG for a malformed DAG. */
+sd_status sd_multiloop_abstract(sd_context *ctx, int N, const int32_t *layer, int n_edges, const int32_t *esrc,
+                                const int32_t *edst, const int64_t *eu, const int64_t *B, int64_t *S1,
+                                int64_t *S2, int8_t *cand, int64_t *Z);
 /* Number of automaton states of a protein (to size the sd_design_tables buffers). */
 sd_status sd_lattice_size(const char *protein, int64_t *n_states, int64_t *n_cells);
 /* Size of the product automaton of sd_design_motifs (host only, no device work): states N and

@@ -40,7 +40,7 @@ EXPORTS = [
     "sd_server_stop", "sd_lambda_envelope", "sd_design_motifs", "sd_inverse_lambda",
     "sd_design_motifs_tables", "sd_motif_lattice_size", "sd_context_create_external",
     "sd_sizer_request_bytes", "sd_fixed_shift", "sd_design_batch_tables",
-    "sd_sizer_predict_host", "sd_design_noalloc",
+    "sd_sizer_predict_host", "sd_design_noalloc", "sd_multiloop_abstract",
 ]
 
 
@@ -53,7 +53,7 @@ class SDError(RuntimeError):
 class Options(C.Structure):
     _fields_ = [("retain_all", C.c_int), ("capacity_override", C.c_int), ("kernel_timing", C.c_int),
                 ("span_threads", C.c_int), ("batch_threads", C.c_int), ("batch_per_cu", C.c_int),
-                ("reserved", C.c_int * 2)]
+                ("span_check", C.c_int), ("reserved", C.c_int * 1)]
 
 
 class ServerCfg(C.Structure):
@@ -78,6 +78,7 @@ class _Result(C.Structure):
         ("t_span_kernels_s", C.c_double), ("n_span_launches", C.c_int64),
         ("cand_slots", C.c_int64), ("cand_slots_first", C.c_int64), ("cand_overflow", C.c_int32),
         ("n_timed_launches", C.c_int64), ("path", C.c_int32), ("graph_captured", C.c_int32),
+        ("sched_threads", C.c_int32), ("sched_grid", C.c_int32),
     ]
 
 
@@ -118,6 +119,9 @@ def lib():
         L.sd_design_batch_tables.argtypes = [vp, C.c_int, C.POINTER(C.c_char_p), C.POINTER(C.c_double),
                                              vp, vp, C.POINTER(_Result), C.c_int, P64, P64, P64, P64, P64]
         L.sd_lattice_size.argtypes = [C.c_char_p, P64, P64]
+        P32 = C.POINTER(C.c_int32)
+        L.sd_multiloop_abstract.argtypes = [vp, C.c_int, P32, C.c_int, P32, P32, P64, P64, P64, P64,
+                                            C.POINTER(C.c_int8), P64]
         L.sd_fixed_shift.argtypes = [C.c_char_p, vp, vp, C.c_double, C.POINTER(C.c_int32)]
         L.sd_result_free.argtypes = [C.POINTER(_Result)]
         L.sd_status_str.argtypes = [C.c_int]
@@ -219,6 +223,8 @@ class Result:
     n_timed_launches: int
     path: int
     graph_captured: int
+    sched_threads: int
+    sched_grid: int
 
 
 def _convert(r: _Result) -> Result:
@@ -226,7 +232,8 @@ def _convert(r: _Result) -> Result:
                  r.codon_cost, r.objective_kcal, r.objective_fixed, r.fixed_shift, r.cai, r.n_states,
                  r.n_cells, r.n_candidates, r.n_visits, r.n_feasible, r.t_fill_s, r.t_total_s,
                  r.t_span_kernels_s, r.n_span_launches, r.cand_slots, r.cand_slots_first,
-                 r.cand_overflow, r.n_timed_launches, r.path, r.graph_captured)
+                 r.cand_overflow, r.n_timed_launches, r.path, r.graph_captured, r.sched_threads,
+                 r.sched_grid)
     lib().sd_result_free(C.byref(r))
     return out
 
@@ -234,9 +241,9 @@ def _convert(r: _Result) -> Result:
 class Context:
     def __init__(self, device: int = 0, retain_all: bool = False, capacity_override: int = 0,
                  kernel_timing: int = 0, span_threads: int = 0, batch_threads: int = 0,
-                 batch_per_cu: int = 0):
+                 batch_per_cu: int = 0, span_check: int = 0):
         opt = Options(int(retain_all), int(capacity_override), int(kernel_timing), int(span_threads),
-                      int(batch_threads), int(batch_per_cu))
+                      int(batch_threads), int(batch_per_cu), int(span_check))
         h = C.c_void_p()
         _check(lib().sd_context_create(device, C.byref(opt), C.byref(h)), "sd_context_create")
         self.h = h
@@ -351,6 +358,25 @@ class Context:
         _check(lib().sd_design_batch_tables(self.h, n, arr, lam, table.h, params.h, res, int(member),
                                             p(V), p(B), p(S1), p(S2), p(X)), "sd_design_batch_tables")
         return [_convert(res[i]) for i in range(n)], {"V": V, "B": B, "S1": S1, "S2": S2, "X": X}
+
+    def multiloop_abstract(self, layer, esrc, edst, eu, B):
+        """The multiloop recurrences on an abstract layered DAG: dict of dense S1, S2, cand, Z."""
+        layer = np.ascontiguousarray(layer, np.int32)
+        N = len(layer)
+        es = np.ascontiguousarray(esrc, np.int32)
+        ed = np.ascontiguousarray(edst, np.int32)
+        u = np.ascontiguousarray(eu, np.int64)
+        Bm = np.ascontiguousarray(B, np.int64)
+        S1 = np.empty((N, N), np.int64)
+        S2 = np.empty((N, N), np.int64)
+        cand = np.zeros((N, N), np.int8)
+        z = C.c_int64()
+        p32 = lambda a: a.ctypes.data_as(C.POINTER(C.c_int32))
+        p64 = lambda a: a.ctypes.data_as(C.POINTER(C.c_int64))
+        _check(lib().sd_multiloop_abstract(self.h, N, p32(layer), len(es), p32(es), p32(ed), p64(u), p64(Bm),
+                                           p64(S1), p64(S2), cand.ctypes.data_as(C.POINTER(C.c_int8)),
+                                           C.byref(z)), "sd_multiloop_abstract")
+        return {"S1": S1, "S2": S2, "cand": cand, "Z": z.value}
 
     def design_motifs_tables(self, protein: str, motifs, table: CodonTable, params: Params, lam: float):
         m = list(motifs)

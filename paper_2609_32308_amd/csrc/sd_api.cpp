@@ -156,6 +156,10 @@ sd_status context_create(int device, const sd_options* opt, bool ext, void* ext_
         delete c;
         return fail(SD_E_ARG, "kernel_timing must be >= 0");
     }
+    if (c->opt.span_check < 0 || c->opt.span_check > 2) {
+        delete c;
+        return fail(SD_E_ARG, "span_check must be 0, 1 or 2");
+    }
     if ((c->opt.batch_threads != 0 && c->opt.batch_threads != 64 && c->opt.batch_threads != 256 &&
          c->opt.batch_threads != 512) ||
         (c->opt.batch_threads != 0) != (c->opt.batch_per_cu > 0) || c->opt.batch_per_cu < 0) {
@@ -226,6 +230,7 @@ extern "C" void sd_context_destroy(sd_context* c) {
     if (c->ev0) hipEventDestroy(c->ev0);
     if (c->ev1) hipEventDestroy(c->ev1);
     for (hipEvent_t ev : c->tev) hipEventDestroy(ev);
+    if (c->dbg) hipFree(c->dbg);
     if (c->stream && !c->external) hipStreamDestroy(c->stream);
     delete c;
 }
@@ -456,14 +461,58 @@ sd_status run_plain_on(sd_context* c, const Lattice& L, Inst& I, const EnergyTab
         }
     }
     const int every = timing ? kernel_timing : 1;
+    // span_check debug mode (codon trie only): snapshot of the committed candidate counts and the
+    // per-layer counters, restored before every second run of a step
+    const bool check = c->opt.span_check != 0 && !L.generic;
+    unsigned long long* dsum = nullptr;
+    char *snap_cnt = nullptr, *snap_vis = nullptr, *snap_fea = nullptr;
+    const size_t cnt_b = 4 * (size_t)L.N, ctr_b = 8 * ((size_t)L.n + 1);
+    if (check && e == hipSuccess) {
+        const size_t need = 256 + ((cnt_b + 255) & ~(size_t)255) + 2 * ((ctr_b + 255) & ~(size_t)255);
+        if (need > c->dbg_bytes) {
+            if (c->dbg) hipFree(c->dbg);
+            c->dbg = nullptr;
+            c->dbg_bytes = 0;
+            e = hipMalloc((void**)&c->dbg, need);
+            if (e == hipSuccess) c->dbg_bytes = need;
+        }
+        dsum = (unsigned long long*)c->dbg;
+        snap_cnt = c->dbg + 256;
+        snap_vis = snap_cnt + ((cnt_b + 255) & ~(size_t)255);
+        snap_fea = snap_vis + ((ctr_b + 255) & ~(size_t)255);
+    }
     for (int g = 1; g <= L.n && e == hipSuccess; g++) {
         const bool timed = timing && (g - 1) % every == 0;
-        if (timed) e = hipEventRecord(c->tev[2 * (g - 1)], st);
+        const int ext = g >= 2 ? L.n - g + 1 : -1;
+        if (check) {
+            e = hipMemcpyAsync(snap_cnt, I.ccnt(), cnt_b, hipMemcpyDeviceToDevice, st);
+            if (e == hipSuccess) e = hipMemcpyAsync(snap_vis, I.visits(), ctr_b, hipMemcpyDeviceToDevice, st);
+            if (e == hipSuccess) e = hipMemcpyAsync(snap_fea, I.feasible(), ctr_b, hipMemcpyDeviceToDevice, st);
+        }
+        if (timed && e == hipSuccess) e = hipEventRecord(c->tev[2 * (g - 1)], st);
+        const int threads = span_threads_for(c, L.n - g + 1);
         if (e == hipSuccess && L.generic)
-            e = launch_span_gen(I, Et, spec, g, g >= 2 ? L.n - g + 1 : -1, c->num_cu, st);
+            e = launch_span_gen(I, Et, spec, g, ext, c->num_cu, st);
         else if (e == hipSuccess)
-            e = launch_span(I, Et, spec, g, g >= 2 ? L.n - g + 1 : -1, span_threads_for(c, L.n - g + 1), st);
+            e = launch_span(I, Et, spec, g, ext, threads, st);
         if (timed && e == hipSuccess) e = hipEventRecord(c->tev[2 * (g - 1) + 1], st);
+        if (check && e == hipSuccess) {
+            // the same step again with another workgroup size from the same inputs
+            e = launch_checksum(I, g, dsum, st);
+            if (e == hipSuccess) e = hipMemcpyAsync(I.ccnt(), snap_cnt, cnt_b, hipMemcpyDeviceToDevice, st);
+            if (e == hipSuccess && c->opt.span_check != 2)
+                e = hipMemcpyAsync(I.visits(), snap_vis, ctr_b, hipMemcpyDeviceToDevice, st);
+            if (e == hipSuccess) e = hipMemcpyAsync(I.feasible(), snap_fea, ctr_b, hipMemcpyDeviceToDevice, st);
+            if (e == hipSuccess) e = launch_span(I, Et, spec, g, ext, threads == 256 ? 1024 : 256, st);
+            if (e == hipSuccess) e = launch_checksum(I, g, dsum + 1, st);
+            unsigned long long h[2] = {0, 0};
+            if (e == hipSuccess) e = hipMemcpyAsync(h, dsum, sizeof(h), hipMemcpyDeviceToHost, st);
+            if (e == hipSuccess) e = hipStreamSynchronize(st);
+            if (e == hipSuccess && h[0] != h[1])
+                return fail(SD_E_INTERNAL, "span check: span " + std::to_string(g) + " wrote different values when run "
+                                           "again with " + std::to_string(threads == 256 ? 1024 : 256) +
+                                           " threads per workgroup instead of " + std::to_string(threads));
+        }
     }
     if (e == hipSuccess) e = launch_ext(I, Et, 0, st);
     unsigned long long stats[4];
@@ -911,6 +960,136 @@ extern "C" sd_status sd_motif_lattice_size(const char* protein, const char* cons
     }
 }
 
+extern "C" sd_status sd_multiloop_abstract(sd_context* c, int N, const int32_t* layer, int n_edges,
+                                          const int32_t* esrc, const int32_t* edst, const int64_t* eu,
+                                          const int64_t* B, int64_t* S1, int64_t* S2, int8_t* cand, int64_t* Z) {
+    try {
+        if (!c || N < 1 || !layer || n_edges < 0 || (n_edges > 0 && (!esrc || !edst || !eu)) || !B || !S1 || !S2 ||
+            !cand || !Z)
+            return fail(SD_E_ARG, "null argument or bad size");
+        hipError_t e = hipSetDevice(c->device);
+        if (e != hipSuccess) return hip_fail(e, "hipSetDevice");
+        // layered DAG: layers 0.. in state order, each non-empty and at most kMaxWidth wide,
+        // edges from a layer to the next, at most four out of a state
+        if (layer[0] != 0) return fail(SD_E_ARG, "the first state must be in layer 0");
+        for (int v = 1; v < N; v++)
+            if (layer[v] != layer[v - 1] && layer[v] != layer[v - 1] + 1)
+                return fail(SD_E_ARG, "layers must be consecutive and in state order");
+        Lattice L;
+        L.N = N;
+        L.n = layer[N - 1];
+        L.A = 1;
+        L.layer.assign(layer, layer + N);
+        L.off.assign(L.n + 2, 0);
+        for (int v = N - 1; v >= 0; v--) L.off[layer[v]] = v;
+        L.off[L.n + 1] = N;
+        for (int l = 0; l <= L.n; l++) {
+            L.wmax = std::max(L.wmax, L.off[l + 1] - L.off[l]);
+            if (L.off[l + 1] - L.off[l] > kMaxWidth) return fail(SD_E_ARG, "a layer is wider than 4 states");
+        }
+        L.out_dst.assign(4 * (size_t)N, -1);
+        L.out_cod.assign(4 * (size_t)N, -1);
+        L.out_q.assign(4 * (size_t)N, 0.0);
+        L.out_U.assign(4 * (size_t)N, 0);
+        std::vector<int> outdeg(N, 0);
+        struct InE { int src, lab, dst; int64_t u; };
+        std::vector<InE> ins;
+        for (int k = 0; k < n_edges; k++) {
+            const int a = esrc[k], b = edst[k];
+            if (a < 0 || a >= N || b < 0 || b >= N || layer[b] != layer[a] + 1)
+                return fail(SD_E_ARG, "an edge must join consecutive layers");
+            if (outdeg[a] == 4) return fail(SD_E_ARG, "more than four edges leave a state");
+            if (eu[k] < -((int64_t)1 << 40) || eu[k] > ((int64_t)1 << 40)) return fail(SD_E_RANGE, "edge cost out of range");
+            const int lab = outdeg[a]++;
+            L.out_dst[4 * (size_t)a + lab] = b;
+            L.out_U[4 * (size_t)a + lab] = eu[k];
+            ins.push_back({a, lab, b, eu[k]});
+        }
+        std::stable_sort(ins.begin(), ins.end(), [](const InE& x, const InE& y) {
+            return x.dst != y.dst ? x.dst < y.dst : (x.src != y.src ? x.src < y.src : x.lab < y.lab);
+        });
+        L.in_start.assign(N + 1, 0);
+        L.inmask.assign(N, 0);
+        for (const InE& x : ins) {
+            L.in_start[x.dst + 1]++;
+            L.in_src.push_back(x.src);
+            L.in_lab.push_back(x.lab);
+            L.in_U.push_back(x.u);
+            L.in_cod.push_back(-1);
+            L.inmask[x.dst] |= 1 << x.lab;
+        }
+        for (int v = 0; v < N; v++) L.in_start[v + 1] += L.in_start[v];
+        L.tail.assign(N, 0);
+        L.pfx.assign(N, 0);
+        L.P.assign(2, 0);
+        L.hp_init.assign(L.n + 1, 0);
+        L.alphaU.assign(4 * (size_t)N, kINF);
+        L.betaU.assign(4 * (size_t)N, kINF);
+        L.fwd_off.assign(4 * (size_t)N + 1, 0);
+        L.bwd_off.assign(4 * (size_t)N + 1, 0);
+        L.hpB.assign(16 * (size_t)N, kINF);
+        L.OB.assign(72 * (size_t)N, kINF);
+        L.OA.assign(72 * (size_t)N, kINF);
+        // cells in row layout; worst-case candidate segments (a direct arc may have any span)
+        L.rowoff.assign(N, 0);
+        L.coff.assign(N, 0);
+        L.ccap.assign(N, 0);
+        int64_t cells = 0, slots = 0;
+        for (int a = 0; a < N; a++) {
+            L.rowoff[a] = cells;
+            cells += N - L.off[layer[a] + 1];
+            L.coff[a] = slots;
+            L.ccap[a] = L.off[layer[a]];
+            slots += L.ccap[a];
+        }
+        L.cells = cells;
+        L.cand_slots = slots;
+        std::vector<int64_t> Bc(std::max<int64_t>(cells, 1), kINF);
+        for (int a = 0; a < N; a++)
+            for (int b = L.off[layer[a] + 1]; b < N; b++) {
+                const int64_t v = B[(size_t)a * N + b];
+                if (v < kHalfINF && (v < -((int64_t)1 << 40) || v > ((int64_t)1 << 40)))
+                    return fail(SD_E_RANGE, "direct cost out of range");
+                Bc[L.rowoff[a] + (b - L.off[layer[a] + 1])] = v >= kHalfINF ? kINF : v;
+            }
+        Inst I;
+        memset(&I, 0, sizeof(I));
+        sd_status st = place_and_upload(c, L, I);
+        if (st) return st;
+        I.retain_all = 0;
+        e = hipMemcpyAsync(I.V(), Bc.data(), 8 * (size_t)cells, hipMemcpyHostToDevice, c->stream);
+        if (e == hipSuccess) e = launch_init(I, c->stream);
+        for (int g = 1; g <= L.n && e == hipSuccess; g++) e = launch_ml_abstract(I, g, c->stream);
+        std::vector<int64_t> s1(std::max<int64_t>(cells, 1)), s2(std::max<int64_t>(cells, 1));
+        std::vector<int> cnt(N), cc(std::max<int64_t>(slots, 1));
+        if (e == hipSuccess && cells) e = hipMemcpyAsync(s1.data(), I.S1(), 8 * (size_t)cells, hipMemcpyDeviceToHost, c->stream);
+        if (e == hipSuccess && cells) e = hipMemcpyAsync(s2.data(), I.S2(), 8 * (size_t)cells, hipMemcpyDeviceToHost, c->stream);
+        if (e == hipSuccess) e = hipMemcpyAsync(cnt.data(), I.ccnt(), 4 * (size_t)N, hipMemcpyDeviceToHost, c->stream);
+        if (e == hipSuccess && slots) e = hipMemcpyAsync(cc.data(), I.cc(), 4 * (size_t)slots, hipMemcpyDeviceToHost, c->stream);
+        if (e == hipSuccess) e = hipStreamSynchronize(c->stream);
+        if (e != hipSuccess) return hip_fail(e, "abstract multiloop run");
+        int64_t z = 0;
+        memset(cand, 0, (size_t)N * N);
+        for (int a = 0; a < N; a++)
+            for (int b = 0; b < N; b++) {
+                const bool f = layer[a] < layer[b];
+                const int64_t k = f ? L.rowoff[a] + (b - L.off[layer[a] + 1]) : 0;
+                S1[(size_t)a * N + b] = f ? s1[k] : kINF;
+                S2[(size_t)a * N + b] = f ? s2[k] : kINF;
+            }
+        for (int b = 0; b < N; b++)
+            for (int k = 0; k < cnt[b]; k++) {
+                const int raw = cc[L.coff[b] + k];
+                if (raw >= 0) cand[(size_t)raw * N + b] = 1;
+                z++;
+            }
+        *Z = z;
+        return SD_OK;
+    } catch (const std::bad_alloc&) {
+        return fail(SD_E_NOMEM, "host allocation");
+    }
+}
+
 extern "C" sd_status sd_design_tables(sd_context* ctx, const char* protein, const sd_codon_table* table,
                                       const sd_params* params, double lambda_kcal, sd_result* out,
                                       int64_t* V, int64_t* B, int64_t* S1, int64_t* S2, int64_t* X) {
@@ -1025,13 +1204,14 @@ sd_status run_batch(sd_context* c, std::vector<Lattice>& Ls, std::vector<Inst>& 
     return SD_OK;
 }
 
-// Schedule of the persistent launch: threads per block (one wave per layer-pair item, or four
-// waves sharing an item) and resident blocks per CU.  The first batched call on a context times a
-// probe batch with each candidate and keeps the fastest (the probe's results are discarded).
-// Autotuned persistent schedule (threads per workgroup, workgroups per CU).  The probe is a
-// sample of the batch itself: up to 12 members spread over its sorted lengths, designed with
-// worst-case segments under every candidate schedule; the fastest is kept per size class
-// (log2 of the mean length of the batch), so later batches of similar sizes reuse it.
+// Autotuned schedule of the persistent launch: threads per workgroup (one wave per layer-pair
+// item, or four waves sharing an item) and resident workgroups per CU.  The probe is a sample of
+// the batch itself: up to 12 members spread over its sorted lengths, designed with worst-case
+// segments under every candidate schedule (the probe's results are discarded).  The fastest is
+// kept per size class, (floor log2 of the mean length, floor log2 of the member count, capped at
+// 16 members), so later batches of similar sizes reuse it.  The member count is part of the key
+// because one member leaves most of the grid idle and favours few workgroups, a schedule that
+// is twice as slow for hundreds of members of the same mean length.
 sd_status tuned_schedule(sd_context* c, const std::vector<Lattice>& batch, int* grid, int* threads) {
     if (c->opt.batch_threads > 0) {  // fixed by the caller
         *threads = c->opt.batch_threads;
@@ -1041,7 +1221,9 @@ sd_status tuned_schedule(sd_context* c, const std::vector<Lattice>& batch, int* 
     double mean_n = 0;
     for (const Lattice& L : batch) mean_n += L.n;
     mean_n /= std::max<size_t>(1, batch.size());
-    const int cls = (int)std::floor(std::log2(std::max(1.0, mean_n)));
+    const int cls_n = (int)std::floor(std::log2(std::max(1.0, mean_n)));
+    const int cls_m = std::min(4, (int)std::floor(std::log2((double)std::max<size_t>(1, batch.size()))));
+    const int cls = cls_n * 8 + cls_m;
     auto hit = c->sched.find(cls);
     if (hit != c->sched.end()) {
         *grid = hit->second.first;
@@ -1091,8 +1273,10 @@ sd_status tuned_schedule(sd_context* c, const std::vector<Lattice>& batch, int* 
     }
     if (best_grid <= 0) return fail(SD_E_DEVICE, "no persistent schedule completed its grid barriers");
     c->sched[cls] = {best_grid, best_threads};
-    c->batch_grid = best_grid;
-    c->batch_threads = best_threads;
+    if (batch.size() >= 12) {  // a full sample: the server's schedule unless the caller fixed one
+        c->batch_grid = best_grid;
+        c->batch_threads = best_threads;
+    }
     *grid = best_grid;
     *threads = best_threads;
     return SD_OK;
@@ -1101,6 +1285,51 @@ sd_status tuned_schedule(sd_context* c, const std::vector<Lattice>& batch, int* 
 }  // namespace sd
 
 namespace {
+// Digests of every member's tables after the launch just run; then the same batch under another
+// persistent schedule; the digests must agree member by member.
+sd_status check_batch_rerun(sd_context* ctx, std::vector<Lattice>& Ls, std::vector<Inst>& Is, int grid, int threads,
+                            Inst** insts_dev) {
+    const int m = (int)Ls.size();
+    const size_t need = 256 + 16 * (size_t)m;
+    hipError_t e = hipSuccess;
+    if (need > ctx->dbg_bytes) {
+        if (ctx->dbg) hipFree(ctx->dbg);
+        ctx->dbg = nullptr;
+        ctx->dbg_bytes = 0;
+        e = hipMalloc((void**)&ctx->dbg, need);
+        if (e != hipSuccess) return hip_fail(e, "span check buffer");
+        ctx->dbg_bytes = need;
+    }
+    unsigned long long* d = (unsigned long long*)ctx->dbg;
+    for (int i = 0; i < m && e == hipSuccess; i++) e = launch_checksum(Is[i], 0, d + i, ctx->stream);
+    std::vector<unsigned long long> h1(m), h2(m);
+    if (e == hipSuccess) e = hipMemcpyAsync(h1.data(), d, 8 * (size_t)m, hipMemcpyDeviceToHost, ctx->stream);
+    if (e == hipSuccess) e = hipStreamSynchronize(ctx->stream);
+    if (e != hipSuccess) return hip_fail(e, "span check digests");
+    int per_cu = 0;
+    const int threads2 = threads == 256 ? 64 : 256;
+    e = persistent_occupancy(threads2, &per_cu);
+    if (e != hipSuccess || per_cu <= 0) return hip_fail(e, "occupancy query");
+    bool ok2 = false;
+    double ks2 = 0;
+    std::vector<Inst> Is2;
+    sd_status s = run_batch(ctx, Ls, Is2, std::min(per_cu, 2) * ctx->num_cu, threads2, &ok2, &ks2, insts_dev);
+    if (s) return s;
+    if (!ok2) return fail(SD_E_INTERNAL, "span check: the re-run's grid barrier gave up");
+    for (int i = 0; i < m && e == hipSuccess; i++) e = launch_checksum(Is2[i], 0, d + i, ctx->stream);
+    if (e == hipSuccess) e = hipMemcpyAsync(h2.data(), d, 8 * (size_t)m, hipMemcpyDeviceToHost, ctx->stream);
+    if (e == hipSuccess) e = hipStreamSynchronize(ctx->stream);
+    if (e != hipSuccess) return hip_fail(e, "span check digests");
+    for (int i = 0; i < m; i++)
+        if (h1[i] != h2[i])
+            return fail(SD_E_INTERNAL, "span check: batch member " + std::to_string(i) + " filled different tables "
+                                       "under the schedules " + std::to_string(threads) + " and " +
+                                       std::to_string(threads2) + " threads per workgroup");
+    Is = std::move(Is2);
+    (void)grid;
+    return SD_OK;
+}
+
 // sd_design_batch; with dump_member in [0, n) that member's tables also go to D (dense layout)
 sd_status design_batch_impl(sd_context* ctx, int n, const char* const* proteins, const double* lambdas,
                             const sd_codon_table* table, const sd_params* params, sd_result* outs,
@@ -1138,6 +1367,9 @@ sd_status design_batch_impl(sd_context* ctx, int n, const char* const* proteins,
             Inst* insts_dev = nullptr;
             if (!s) s = run_batch(ctx, Ls, Is, grid, threads, &ok, &ks, &insts_dev);
             const double tf1 = now_s();
+            // span_check debug mode: the whole launch again under another schedule, then a digest
+            // of every member's tables from each run must agree
+            if (!s && ok && ctx->opt.span_check) s = check_batch_rerun(ctx, Ls, Is, grid, threads, &insts_dev);
             // the canonical traceback of every member in one launch (one wavefront each)
             if (!s && ok) {
                 hipError_t e = launch_trace_many(insts_dev, m, (const EnergyTables*)ctx->E_dev,
@@ -1208,6 +1440,8 @@ sd_status design_batch_impl(sd_context* ctx, int n, const char* const* proteins,
                 outs[gi].cand_overflow = 0;
                 outs[gi].path = SD_PATH_PERSISTENT;
                 outs[gi].graph_captured = ctx->last_graph ? 1 : 0;
+                outs[gi].sched_threads = threads;
+                outs[gi].sched_grid = grid;
                 if (ctx->occ_K > 0) occupancy_bins(Ls[i], T.counts, ctx->occ_K, &ctx->occ[(size_t)gi * ctx->occ_K]);
             }
             if (s) {

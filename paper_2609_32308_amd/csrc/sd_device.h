@@ -22,7 +22,7 @@ struct sd_context {
     size_t staging_bytes = 0;
     int batch_grid = 0;       // autotuned persistent grid size (0: not tuned yet)
     int batch_threads = 256;  // autotuned threads per block of the persistent launch
-    std::map<int, std::pair<int, int>> sched;  // size class -> (grid, threads) from the tuner
+    std::map<int, std::pair<int, int>> sched;  // (length, member-count) class -> (grid, threads)
     char* tbuf = nullptr;  // pinned download buffer of the dense-table test hooks
     size_t tbuf_bytes = 0;
     bool last_graph = false;  // last batch ran as a captured graph
@@ -43,6 +43,9 @@ struct sd_context {
     int64_t last_launches = 0;
     int64_t last_timed = 0;
     std::vector<hipEvent_t> tev;  // kernel_timing: event pairs around span launches
+    // span_check debug mode: snapshots of the committed counts and counters, digests
+    char* dbg = nullptr;
+    size_t dbg_bytes = 0;
 };
 
 namespace sd {
@@ -63,6 +66,10 @@ hipError_t launch_ext(const Inst& I, const EnergyTables* E, int L, hipStream_t s
 hipError_t launch_trace(const Inst& I, const EnergyTables* E, const int32_t* spec, hipStream_t st);
 hipError_t launch_trace_many(const Inst* insts_dev, int n, const EnergyTables* E, const int32_t* spec,
                              hipStream_t st);
+// multiloop recurrences of span g on an abstract DAG whose direct costs sit in the V array
+hipError_t launch_ml_abstract(const Inst& I, int g, hipStream_t st);
+// digest of what span step g wrote (g = 0: of every cell of a finished design) into *out
+hipError_t launch_checksum(const Inst& I, int g, unsigned long long* out, hipStream_t st);
 // strict candidates per right endpoint into cstrict (retain-all control)
 hipError_t launch_strict_count(const Inst& I, hipStream_t st);
 hipError_t launch_span_gen(const Inst& I, const EnergyTables* E, const int32_t* spec, int g,

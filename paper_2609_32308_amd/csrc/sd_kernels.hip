@@ -494,7 +494,9 @@ __device__ void produce_state(const IT& I, const SmallE& S, const GroupShared<NW
         const int lab = lane & 3, grp = lane >> 2;
         const int qc = p + g + 1, pc = p - 1;  // consumer closing layers (left / right state)
         int64_t o[4] = {kINF, kINF, kINF, kINF};
-#pragma unroll
+        // one separable length at a time: unrolling keeps both lengths' ring values and tails
+        // live at once, which made the 80-VGPR instantiation spill here
+#pragma unroll 1
         for (int h = 0; h < 2; h++) {
             const int ls = 3 + grp + 16 * h, g2 = g - ls;
             if (ls > 29 || g2 < 5) continue;
@@ -575,6 +577,91 @@ __device__ void produce_state(const IT& I, const SmallE& S, const GroupShared<NW
     }
 }
 
+// The multiloop part of one cell (a, b) of layer pair (p, q) given its direct branch cost Bv
+// (eq. 2), by one wave: S2 (eq. 7: in-edge extensions, then the committed prefix of C_b with
+// the gathered S1(a, c)), P_S, S1 = min(B, P_S) and the retention test B < P_S (eq. 6).  Every
+// scan reads only entries committed by earlier spans (their start states lie in layers after
+// p, so the guard of eq. 7 holds for each).  Lane 0 writes B, S2 and S1 and returns the keep
+// flag: 0 none, 1 strict, 2 retained non-strict (retain-all control).
+template <class IT>
+__device__ int multiloop_cell(const IT& I, int a, int b, int p, int q, int64_t cell, int64_t Bv, int lane,
+                              GroupCounters& ctr) {
+    const int committed = I.ccnt()[b];
+    const int64_t cbase = I.coff()[b];
+    const int ib0 = I.in_start()[b], ib1 = I.in_start()[b + 1];
+    int64_t s2 = kINF;
+    for (int eb = ib0 + lane; eb < ib1; eb += 64) {
+        const int bp = I.in_src()[eb];
+        if (I.layer()[bp] > p) s2 = mn(s2, I.S2()[cell_of(I, a, bp)] + I.in_U()[eb] + I.mlbase_fx);
+    }
+    const int64_t arow = I.rowoff()[a] - I.off()[p + 1];
+    const int* __restrict__ cc = I.cc() + cbase;
+    const int64_t* __restrict__ cB = I.cB() + cbase;
+    const int64_t* __restrict__ S1r = I.S1() + arow;
+    // four entries per lane and round, their loads issued together: the gathers of S1(a, c)
+    // depend on the start states, so one entry at a time would serialise two load latencies
+    // per 64 entries
+    int k = lane;
+    for (; k + 192 < committed; k += 256) {
+        const int c0 = cc[k] & 0x7fffffff, c1 = cc[k + 64] & 0x7fffffff;
+        const int c2 = cc[k + 128] & 0x7fffffff, c3 = cc[k + 192] & 0x7fffffff;
+        const int64_t b0 = cB[k], b1 = cB[k + 64], b2 = cB[k + 128], b3 = cB[k + 192];
+        const int64_t s0 = S1r[c0], s1v = S1r[c1], s2v = S1r[c2], s3 = S1r[c3];
+        s2 = mn(s2, mn(mn(s0 + b0, s1v + b1), mn(s2v + b2, s3 + b3)));
+    }
+    for (; k < committed; k += 64) s2 = mn(s2, S1r[cc[k] & 0x7fffffff] + cB[k]);
+    s2 = norm_inf(wave_min(s2));
+    int64_t ps = s2;
+    if (lane < 4) {
+        const int ap = I.out_dst()[a * 4 + lane];
+        if (ap >= 0 && I.layer()[ap] < q)
+            ps = mn(ps, I.S1()[cell_of(I, ap, b)] + I.out_U()[a * 4 + lane] + I.mlbase_fx);
+    }
+    for (int eb = ib0 + lane; eb < ib1; eb += 64) {
+        const int bp = I.in_src()[eb];
+        if (I.layer()[bp] > p) ps = mn(ps, I.S1()[cell_of(I, a, bp)] + I.in_U()[eb] + I.mlbase_fx);
+    }
+    ps = norm_inf(wave_min(ps));
+    int keep = 0;
+    if (lane == 0) {
+        I.Bt()[cell] = Bv;
+        I.S2()[cell] = s2;
+        I.S1()[cell] = mn(Bv, ps);
+        const bool strict = Bv < ps;
+        keep = I.retain_all ? (Bv < kINF ? (strict ? 1 : 2) : 0) : (strict ? 1 : 0);
+    }
+    ctr.visits += (unsigned long long)committed;
+    ctr.feasible += Bv < kINF;
+    return keep;
+}
+
+// Appends the retained entries (a, B(a, b)) of layer pair (p, q) to the segments C_b in
+// start-state order, one lane per right endpoint: the caller's workgroup owns these segments in
+// step g (endpoint ownership), so no atomics are needed and the layout is deterministic.  An
+// append beyond a segment's capacity records the earliest overflowing span instead.
+template <class IT>
+__device__ void append_candidates(const IT& I, int a_lo, int wa, int b_lo, int wb, const int* keep,
+                                  const int64_t* cellB, int g, int lane) {
+    int added = 0;
+    if (lane < wb) {
+        const int b = b_lo + lane;
+        const int committed = I.ccnt()[b];
+        for (int ia = 0; ia < wa; ia++) {
+            const int ci = ia * wb + lane;
+            if (!keep[ci]) continue;
+            const int slot = committed + added;
+            if (slot < I.ccap()[b]) {
+                I.cc()[I.coff()[b] + slot] = (a_lo + ia) | (keep[ci] == 1 ? 0 : (int)0x80000000);
+                I.cB()[I.coff()[b] + slot] = cellB[ci];
+            } else {
+                atomicMin(&I.stats()[2], (unsigned long long)g);
+            }
+            added++;
+        }
+        if (added) I.ccnt()[b] = min(committed + added, I.ccap()[b]);
+    }
+}
+
 template <int NW, class IT>
 __device__ GroupCounters span_group(const IT& I, const SmallE& S, const EnergyTables* __restrict__ E,
                                     const int32_t* __restrict__ spec, int p, int q, GroupShared<NW>& G) {
@@ -633,41 +720,11 @@ __device__ GroupCounters span_group(const IT& I, const SmallE& S, const EnergyTa
             if (lane == t) I.V()[cell * 6 + t] = v;
             if (v < kINF) Bv = mn(Bv, v + fx(S.ml_intern + au_pen(S, t), s));
         }
-        const int committed = I.ccnt()[b];
-        const int64_t cbase = I.coff()[b];
-        const int ib0 = I.in_start()[b], ib1 = I.in_start()[b + 1];
-        int64_t s2 = kINF;
-        for (int eb = ib0 + lane; eb < ib1; eb += 64) {
-            const int bp = I.in_src()[eb];
-            if (I.layer()[bp] > p) s2 = mn(s2, I.S2()[cell_of(I, a, bp)] + I.in_U()[eb] + I.mlbase_fx);
-        }
-        const int64_t arow = I.rowoff()[a] - I.off()[p + 1];
-        for (int k = lane; k < committed; k += 64) {
-            const int c = I.cc()[cbase + k] & 0x7fffffff;
-            s2 = mn(s2, I.S1()[arow + c] + I.cB()[cbase + k]);
-        }
-        s2 = norm_inf(wave_min(s2));
-        int64_t ps = s2;
-        if (lane < 4) {
-            const int ap = I.out_dst()[a * 4 + lane];
-            if (ap >= 0 && I.layer()[ap] < q)
-                ps = mn(ps, I.S1()[cell_of(I, ap, b)] + I.out_U()[a * 4 + lane] + I.mlbase_fx);
-        }
-        for (int eb = ib0 + lane; eb < ib1; eb += 64) {
-            const int bp = I.in_src()[eb];
-            if (I.layer()[bp] > p) ps = mn(ps, I.S1()[cell_of(I, a, bp)] + I.in_U()[eb] + I.mlbase_fx);
-        }
-        ps = norm_inf(wave_min(ps));
+        const int keep = multiloop_cell(I, a, b, p, q, cell, Bv, lane, ctr);
         if (lane == 0) {
-            I.Bt()[cell] = Bv;
-            I.S2()[cell] = s2;
-            I.S1()[cell] = mn(Bv, ps);
-            const bool strict = Bv < ps;
-            G.keep[ci] = I.retain_all ? (Bv < kINF ? (strict ? 1 : 2) : 0) : (strict ? 1 : 0);
+            G.keep[ci] = keep;
             G.cellB[ci] = Bv;
         }
-        ctr.visits += (unsigned long long)committed;
-        ctr.feasible += Bv < kINF;
     }
     // producers for later two-loops, one state per wave from the last wave down, so that they
     // overlap phase 2 (they read typed values and earlier spans only)
@@ -695,24 +752,7 @@ __device__ GroupCounters span_group(const IT& I, const SmallE& S, const EnergyTa
         }
         // appends in start-state order, one lane per right endpoint (this group owns C_b in
         // this step)
-        int added = 0;
-        if (lane < wb) {
-            const int b = b_lo + lane;
-            const int committed = I.ccnt()[b];
-            for (int ia = 0; ia < wa; ia++) {
-                const int ci = ia * wb + lane;
-                if (!G.keep[ci]) continue;
-                const int slot = committed + added;
-                if (slot < I.ccap()[b]) {
-                    I.cc()[I.coff()[b] + slot] = (a_lo + ia) | (G.keep[ci] == 1 ? 0 : (int)0x80000000);
-                    I.cB()[I.coff()[b] + slot] = G.cellB[ci];
-                } else {
-                    atomicMin(&I.stats()[2], (unsigned long long)g);
-                }
-                added++;
-            }
-            if (added) I.ccnt()[b] = min(committed + added, I.ccap()[b]);
-        }
+        append_candidates(I, a_lo, wa, b_lo, wb, G.keep, G.cellB, g, lane);
     }
     // both-separable minima of the next span's pair (p, q + 1), by the waves other than wave 0
     // (busy with the appends): they read LM of spans <= g - 7, complete before this step
@@ -861,6 +901,97 @@ __global__ void k_init(Inst I) {
         for (int64_t i = tid; i < I.cells * 6; i += nt) I.V()[i] = kINF;
         for (int i = tid; i <= I.n; i += nt) I.gtickets()[i] = 0;
     }
+}
+
+// ---- the multiloop recurrences alone on an abstract layered DAG (test hook) -----------------------
+// Direct branch costs B are given per cell (row layout, in the V array of the instance) instead of
+// coming from loop energies; the unpaired-edge costs are the automaton's edge costs (ML_base 0).
+// One wave per layer pair of span g runs the span step's own multiloop_cell and
+// append_candidates: the exact-integer abstract test of Sec. 7.1 on the GPU code path.
+__global__ __launch_bounds__(64) void k_ml_abstract(Inst I, int g) {
+    __shared__ int keep[kMaxWidth * kMaxWidth];
+    __shared__ int64_t cellB[kMaxWidth * kMaxWidth];
+    const int p = blockIdx.x, q = p + g, lane = threadIdx.x;
+    const int a_lo = I.off()[p], wa = I.off()[p + 1] - a_lo, b_lo = I.off()[q], wb = I.off()[q + 1] - b_lo;
+    GroupCounters ctr{0, 0};
+    for (int ci = 0; ci < wa * wb; ci++) {
+        const int a = a_lo + ci / wb, b = b_lo + ci % wb;
+        const int64_t cell = I.rowoff()[a] + (b - I.off()[p + 1]);
+        const int64_t Bv = I.V()[cell];
+        const int k = multiloop_cell(I, a, b, p, q, cell, Bv, lane, ctr);
+        if (lane == 0) {
+            keep[ci] = k;
+            cellB[ci] = Bv;
+        }
+    }
+    __syncthreads();
+    append_candidates(I, a_lo, wa, b_lo, wb, keep, cellB, g, lane);
+    flush_counters(I, ctr, p, lane);
+}
+
+// ---- span checksums (debug mode) -----------------------------------------------------------------
+// An order-independent digest (wrapping sum of mixed (tag, index, value) words) of what a span
+// step writes: the cells of span g (V, B, S1, S2), the committed candidate counts and entries,
+// the visit and feasibility counters, the external column and the ring slots of span g.  With
+// g = 0 it covers every cell and no ring slot (the whole tables of a finished design).  Two runs
+// of a step that read the same inputs must give the same digest whatever their schedule.
+__device__ __forceinline__ unsigned long long mix64(unsigned long long x) {
+    x ^= x >> 30;
+    x *= 0xbf58476d1ce4e5b9ull;
+    x ^= x >> 27;
+    x *= 0x94d049bb133111ebull;
+    return x ^ (x >> 31);
+}
+__device__ __forceinline__ unsigned long long dword(int tag, int64_t idx, int64_t v) {
+    return mix64((unsigned long long)v ^ mix64(((unsigned long long)idx << 4) | (unsigned)tag));
+}
+
+__global__ void k_checksum(Inst I, int g, unsigned long long* out) {
+    const int64_t tid = (int64_t)blockIdx.x * blockDim.x + threadIdx.x, nt = (int64_t)gridDim.x * blockDim.x;
+    unsigned long long h = 0;
+    // cells: of span g (p = 0 .. n - g), or every cell
+    const int plo = 0, phi = g > 0 ? I.n - g : I.n;
+    for (int p = plo; p <= phi; p++) {
+        const int q0 = g > 0 ? p + g : p + 1, q1 = g > 0 ? p + g : I.n;
+        if (q0 > I.n) break;
+        const int a0 = I.off()[p], a1 = I.off()[p + 1], b0 = I.off()[q0], b1 = I.off()[q1 + 1];
+        const int64_t wb = b1 - b0, tot = (int64_t)(a1 - a0) * wb;
+        for (int64_t k = tid; k < tot; k += nt) {
+            const int a = a0 + (int)(k / wb), b = b0 + (int)(k % wb);
+            const int64_t c = I.rowoff()[a] + (b - I.off()[p + 1]);
+            for (int t = 0; t < 6; t++) h += dword(1 + t, c, I.V()[c * 6 + t]);
+            h += dword(7, c, I.Bt()[c]) + dword(8, c, I.S1()[c]) + dword(9, c, I.S2()[c]);
+        }
+    }
+    for (int64_t b = tid; b < I.N; b += nt) {
+        const int cnt = I.ccnt()[b];
+        h += dword(10, b, cnt) + dword(11, b, I.X()[b]);
+        const int64_t base = I.coff()[b];
+        for (int k = 0; k < cnt; k++) h += dword(12, base + k, I.cc()[base + k]) + dword(13, base + k, I.cB()[base + k]);
+    }
+    for (int64_t l = tid; l <= I.n; l += nt) h += dword(14, l, (int64_t)I.visits()[l]) + dword(15, l, (int64_t)I.feasible()[l]);
+    if (g > 0) {
+        const int r = g & (kLMRing - 1), r1 = (g + 1) & (kLMRing - 1);
+        for (int64_t st = tid; st < I.N; st += nt) {
+            for (int k = 0; k < 12; k++) {
+                h += dword(16, st * 12 + k, I.IDL()[(st * 12 + k) * kLMRing + r]);
+                h += dword(17, st * 12 + k, I.JDL()[(st * 12 + k) * kLMRing + r]);
+            }
+            for (int k = 0; k < 16; k++) {
+                h += dword(18, st * 16 + k, I.RS()[(st * kLMRing + r) * 16 + k]);
+                h += dword(19, st * 16 + k, I.LS()[(st * kLMRing + r) * 16 + k]);
+            }
+            h += dword(20, st, I.BI()[st * kLMRing + r]) + dword(21, st, I.BJ()[st * kLMRing + r]);
+        }
+        for (int64_t l = tid; l <= I.n; l += nt)
+            for (int X = 0; X < 2; X++) {
+                h += dword(22, l * 2 + X, I.LM()[(l * 2 + X) * kLMRing + r]);
+                h += dword(23, l * 2 + X, I.MINI()[(l * kLMRing + r1) * 2 + X]);
+            }
+    }
+    // wave sum, then one atomic per wave (wrapping, so the total is order independent)
+    for (int o = 32; o > 0; o >>= 1) h += __shfl_xor(h, o, 64);
+    if ((threadIdx.x & 63) == 0) atomicAdd(out, h);
 }
 
 // ---- generic lattice: the codon automaton intersected with a forbidden-motif matcher --------------
@@ -1169,63 +1300,16 @@ __device__ GroupCounters gen_span_group(const IT& I, const SmallE& S, const Ener
             if (v < kINF) Bv = v + fx(S.ml_intern + au_pen(S, lane), s);
             Bv = wave_min(Bv);
         }
-        const int committed = I.ccnt()[b];
-        const int64_t cbase = I.coff()[b];
-        const int ib0 = I.in_start()[b], ib1 = I.in_start()[b + 1];
-        int64_t s2 = kINF;
-        for (int eb = ib0 + lane; eb < ib1; eb += 64) {
-            const int bp = I.in_src()[eb];
-            if (I.layer()[bp] > p) s2 = mn(s2, I.S2()[cell_of(I, a, bp)] + I.in_U()[eb] + I.mlbase_fx);
-        }
-        const int64_t arow = I.rowoff()[a] - I.off()[p + 1];
-        for (int k = lane; k < committed; k += 64) {
-            const int c = I.cc()[cbase + k] & 0x7fffffff;
-            s2 = mn(s2, I.S1()[arow + c] + I.cB()[cbase + k]);
-        }
-        s2 = norm_inf(wave_min(s2));
-        int64_t ps = s2;
-        if (lane < 4) {
-            const int ap = I.out_dst()[a * 4 + lane];
-            if (ap >= 0 && I.layer()[ap] < q)
-                ps = mn(ps, I.S1()[cell_of(I, ap, b)] + I.out_U()[a * 4 + lane] + I.mlbase_fx);
-        }
-        for (int eb = ib0 + lane; eb < ib1; eb += 64) {
-            const int bp = I.in_src()[eb];
-            if (I.layer()[bp] > p) ps = mn(ps, I.S1()[cell_of(I, a, bp)] + I.in_U()[eb] + I.mlbase_fx);
-        }
-        ps = norm_inf(wave_min(ps));
+        const int keep = multiloop_cell(I, a, b, p, q, cell, Bv, lane, ctr);
         if (lane == 0) {
-            I.Bt()[cell] = Bv;
-            I.S2()[cell] = s2;
-            I.S1()[cell] = mn(Bv, ps);
-            const bool strict = Bv < ps;
-            G.keep[ci] = I.retain_all ? (Bv < kINF ? (strict ? 1 : 2) : 0) : (strict ? 1 : 0);
+            G.keep[ci] = keep;
             G.cellB[ci] = Bv;
         }
-        ctr.visits += (unsigned long long)committed;
-        ctr.feasible += Bv < kINF;
     }
     __syncthreads();
     // appends in start-state order, one lane per right endpoint
     if (wave == 0) {
-        int added = 0;
-        if (lane < wb) {
-            const int b = b_lo + lane;
-            const int committed = I.ccnt()[b];
-            for (int ia = 0; ia < wa; ia++) {
-                const int ci = ia * wb + lane;
-                if (!G.keep[ci]) continue;
-                const int slot = committed + added;
-                if (slot < I.ccap()[b]) {
-                    I.cc()[I.coff()[b] + slot] = (a_lo + ia) | (G.keep[ci] == 1 ? 0 : (int)0x80000000);
-                    I.cB()[I.coff()[b] + slot] = G.cellB[ci];
-                } else {
-                    atomicMin(&I.stats()[2], (unsigned long long)g);
-                }
-                added++;
-            }
-            if (added) I.ccnt()[b] = min(committed + added, I.ccap()[b]);
-        }
+        append_candidates(I, a_lo, wa, b_lo, wb, G.keep, G.cellB, g, lane);
     }
     return ctr;
 }
@@ -1397,6 +1481,12 @@ __global__ __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(4))) void k_
         const unsigned lo_item = (unsigned)((uint64_t)total * grp / ngrp);
         const unsigned band = (unsigned)((uint64_t)total * (grp + 1) / ngrp) - lo_item;
         while (ticket < base + band) {
+            // the next ticket is drawn by the last wave when the item starts (in four-wave
+            // workgroups that wave rarely has a typed-value part) and published when it ends,
+            // so the atomic's latency overlaps the item instead of following it
+            const bool drawer = threadIdx.x == NT - 64;
+            unsigned nxt = 0;
+            if (drawer) nxt = atomicAdd(&ctl->next[grp].v, 1u);
             const int item = (int)(lo_item + (ticket - base));
             int lo = 0, hi = ninst - 1;  // last instance whose prefix <= item
             while (lo < hi) {
@@ -1415,10 +1505,10 @@ __global__ __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(4))) void k_
             } else {
                 ext_column(I, S, n - g + 1, red);
             }
-            __syncthreads();  // the item is done and every thread has read the last ticket
-            if (threadIdx.x == 0) s_ticket = atomicAdd(&ctl->next[grp].v, 1u);
-            __syncthreads();
+            if (drawer) s_ticket = nxt;
+            __syncthreads();  // the item is done and the next ticket is published
             ticket = s_ticket;
+            __syncthreads();  // every thread has read it before the next item's drawer writes
         }
         base += band;
         if (!grid_barrier(ctl, spin_cap, &s_flag)) return;
@@ -1577,6 +1667,19 @@ hipError_t launch_persistent(const Inst* insts_dev, int ninst, int nsteps, const
         hipLaunchKernelGGL(k_persistent<512>, dim3(grid), dim3(512), 0, st, insts_dev, ninst, nsteps, E, spec, ctl, spin_cap);
     else
         hipLaunchKernelGGL(k_persistent<256>, dim3(grid), dim3(256), 0, st, insts_dev, ninst, nsteps, E, spec, ctl, spin_cap);
+    return hipGetLastError();
+}
+
+hipError_t launch_ml_abstract(const Inst& I, int g, hipStream_t st) {
+    if (I.n - g + 1 <= 0) return hipSuccess;
+    hipLaunchKernelGGL(k_ml_abstract, dim3(I.n - g + 1), dim3(64), 0, st, I, g);
+    return hipGetLastError();
+}
+
+hipError_t launch_checksum(const Inst& I, int g, unsigned long long* out, hipStream_t st) {
+    hipError_t e = hipMemsetAsync(out, 0, sizeof(unsigned long long), st);
+    if (e != hipSuccess) return e;
+    hipLaunchKernelGGL(k_checksum, dim3(256), dim3(256), 0, st, I, g, out);
     return hipGetLastError();
 }
 

@@ -342,6 +342,8 @@ sd_status round_once(sd_server* S) {
             if (!s) {
                 r.path = SD_PATH_PERSISTENT;
                 r.graph_captured = 0;
+                r.sched_threads = S->threads;
+                r.sched_grid = S->grid;
                 r.t_fill_s = a.rq.t_admit > 0 ? now_s() - a.rq.t_admit : 0.0;
                 r.t_total_s = now_s() - a.rq.t_submit;
                 r.cand_slots = a.L.cand_slots;

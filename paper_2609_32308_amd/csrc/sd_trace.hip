@@ -519,50 +519,76 @@ __device__ bool Tracer::twoloop(int a, int b, int t, int64_t v, int ea, int a1) 
     }
     const int total = L.pre[kNumPairs];
     const int64_t Ua = I.out_U()[ea];
-    for (int base = 0; base < total; base += 64) {
-        const int T = base + lane;
-        int code = INT_MAX;  // (lane tuple, tp, p, q) of the lane's first match, ordered by tuple
+    // four groups per lane and round (group T = base + lane + 64 k): their independent loads are
+    // issued together, then each group's lower bound is tested and, rarely, its alternatives
+    // enumerated; the lane's first match is its smallest matching group
+    constexpr int kPer = 4;
+    for (int base = 0; base < total; base += 64 * kPer) {
+        int code = INT_MAX;  // the lane's first matching group and its (tp, p, q)
         int wtp = 0, wp = 0, wq = 0;
-        if (T < total) {
+        int tl1[kPer], tl2[kPer], tc[kPer], td[kPer], tj[kPer], tb1[kPer];
+        int64_t tU[kPer], tgl[kPer], tgr[kPer];
+        const int64_t* tvr[kPer];
+#pragma unroll
+        for (int k = 0; k < kPer; k++) {
+            const int T = base + lane + 64 * k;
+            tl1[k] = -1;
+            if (T >= total) continue;
             int lo = 0, hi = kNumPairs - 1;  // last pair whose prefix <= T
             while (lo < hi) {
                 const int mid = (lo + hi + 1) >> 1;
                 if (L.pre[mid] <= T) lo = mid;
                 else hi = mid - 1;
             }
-            const int k = lo, l1 = L.pl1[k], l2 = L.pl2[k];
+            const int l1 = L.pl1[lo], l2 = L.pl2[lo];
             const int cl = la + 1 + l1, dl = lb - 1 - l2;
-            const int wc = I.off()[cl + 1] - I.off()[cl], wd = I.off()[dl + 1] - I.off()[dl];
-            const int r = T - L.pre[k], jj = r / (wc * wd), ci = (r / wd) % wc, di = r % wd;
-            const int j = L.jl[jj], b1 = I.in_src()[j], c = I.off()[cl] + ci, d = I.off()[dl] + di;
-            const int64_t Uj = I.in_U()[j];
-            // exact lower bound of every alternative of the tuple
-            const int64_t gl = l1 == 0 ? (a1 == c ? 0 : kINF) : tgap(I, a1, c);
-            const int64_t gr = l2 == 0 ? (d == b1 ? 0 : kINF) : tgap(I, d, b1);
-            if (gl < kINF && gr < kINF) {
-                const int64_t* vr = I.V() + tcell(I, c, d) * 6;
-                int64_t vmin = kINF;
-                for (int tp = 0; tp < 6; tp++) vmin = mn(vmin, vr[tp]);
-                const int64_t lb0 = Ua + gl + gr + Uj + fxe(two_loop_lb(L.S, L.M, t, l1, l2));
-                if (vmin < kINF && lb0 + vmin <= v) {
-                    // enumerate (inner type, left segment, right segment) in order
-                    for (int tp = 0; tp < 6 && code == INT_MAX; tp++) {
-                        const int64_t vin = vr[tp];
-                        if (vin >= kINF || lb0 + vin > v) continue;
-                        const int tr = kRev[tp];
-                        Seg sl, sr;
-                        SegIter li(I, a1, c, l1);
-                        for (int p = 0; code == INT_MAX && li.next(I, sl); p++) {
-                            SegIter ri(I, d, b1, l2);
-                            for (int q = 0; code == INT_MAX && ri.next(I, sr); q++) {
-                                const int32_t e2 = two_loop_e(L.S, t, tr, l1, l2, sl.xa, sl.xb, sr.xa, sr.xb);
-                                if (Ua + sl.cost + vin + sr.cost + Uj + fxe(e2) == v) {
-                                    code = T;
-                                    wtp = tp;
-                                    wp = p;
-                                    wq = q;
-                                }
-                            }
+            const int c0 = I.off()[cl], d0 = I.off()[dl];
+            const int wc = I.off()[cl + 1] - c0, wd = I.off()[dl + 1] - d0;
+            const int r = T - L.pre[lo], jj = r / (wc * wd), ci = (r / wd) % wc, di = r % wd;
+            tl1[k] = l1;
+            tl2[k] = l2;
+            tc[k] = c0 + ci;
+            td[k] = d0 + di;
+            tj[k] = L.jl[jj];
+        }
+#pragma unroll
+        for (int k = 0; k < kPer; k++) {
+            if (tl1[k] < 0) continue;
+            tb1[k] = I.in_src()[tj[k]];
+            tU[k] = I.in_U()[tj[k]];
+            tvr[k] = I.V() + tcell(I, tc[k], td[k]) * 6;
+        }
+#pragma unroll
+        for (int k = 0; k < kPer; k++) {
+            if (tl1[k] < 0) continue;
+            tgl[k] = tl1[k] == 0 ? (a1 == tc[k] ? 0 : kINF) : tgap(I, a1, tc[k]);
+            tgr[k] = tl2[k] == 0 ? (td[k] == tb1[k] ? 0 : kINF) : tgap(I, td[k], tb1[k]);
+        }
+        for (int k = 0; k < kPer && code == INT_MAX; k++) {
+            if (tl1[k] < 0 || tgl[k] >= kINF || tgr[k] >= kINF) continue;
+            const int l1 = tl1[k], l2 = tl2[k], c = tc[k], d = td[k], b1 = tb1[k];
+            const int64_t* vr = tvr[k];
+            int64_t vmin = kINF;
+            for (int tp = 0; tp < 6; tp++) vmin = mn(vmin, vr[tp]);
+            // exact lower bound of every alternative of the group
+            const int64_t lb0 = Ua + tgl[k] + tgr[k] + tU[k] + fxe(two_loop_lb(L.S, L.M, t, l1, l2));
+            if (vmin >= kINF || lb0 + vmin > v) continue;
+            // enumerate (inner type, left segment, right segment) in order
+            for (int tp = 0; tp < 6 && code == INT_MAX; tp++) {
+                const int64_t vin = vr[tp];
+                if (vin >= kINF || lb0 + vin > v) continue;
+                const int tr = kRev[tp];
+                Seg sl, sr;
+                SegIter li(I, a1, c, l1);
+                for (int p = 0; code == INT_MAX && li.next(I, sl); p++) {
+                    SegIter ri(I, d, b1, l2);
+                    for (int q = 0; code == INT_MAX && ri.next(I, sr); q++) {
+                        const int32_t e2 = two_loop_e(L.S, t, tr, l1, l2, sl.xa, sl.xb, sr.xa, sr.xb);
+                        if (Ua + sl.cost + vin + sr.cost + tU[k] + fxe(e2) == v) {
+                            code = base + lane + 64 * k;
+                            wtp = tp;
+                            wp = p;
+                            wq = q;
                         }
                     }
                 }

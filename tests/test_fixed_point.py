@@ -232,3 +232,21 @@ def test_rounding_bound(A, seed, oparams, weights):
     err = abs(d.objective_fixed / 2.0 ** s - exact)
     # A codons each rounded by at most 2^-(s+1), plus the FP64 error of the comparison itself
     assert err <= A * 2.0 ** -(s + 1) + 1e-12 * max(1.0, abs(exact))
+
+
+GOLDENS = {"plain300": 8, "plain925_1976": 4, "batch256": 256, "stress": 4, "motifs": 6, "motifs_wide": 2}
+
+
+@pytest.mark.parametrize("name", sorted(GOLDENS))
+def test_goldens_complete_under_this_rule(name, params_path, oparams, weights):
+    # every stored oracle design was made under the current range rule: its shift is the one the
+    # rule gives for its protein (the motif designs use the unconstrained design's shift)
+    import json
+    import os
+    path = os.path.join(os.path.dirname(os.path.abspath(__file__)), "golden", f"{name}.json")
+    g = json.load(open(path))
+    assert g["params_sha256"] == S.sha256_file(params_path)
+    assert g["fixed_point_rule"] == "pair-bound"
+    assert len(g["designs"]) == GOLDENS[name]
+    for d in g["designs"]:
+        assert O.fixed_shift(d["protein"], weights, oparams, d["lambda"]) == d["fixed_shift"]

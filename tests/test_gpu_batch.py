@@ -55,6 +55,7 @@ def persistent(sd, rs):
         assert r.path == sd.PATH_PERSISTENT and r.graph_captured == 1 and r.cand_overflow == 0, \
             (r.path, r.graph_captured, r.cand_overflow)
         assert r.n_span_launches == 0
+        assert r.sched_threads in (64, 256, 512) and r.sched_grid > 0, (r.sched_threads, r.sched_grid)
 
 
 @functools.lru_cache(maxsize=None)
@@ -99,13 +100,10 @@ def test_batch_rejects_bad_member(sd, ctx, gt, gp):
 
 def test_batch256_members_vs_golden(sd, ctx, gt, gp):
     path = os.path.join(HERE, "golden", "batch256.json")
-    if not os.path.exists(path):
-        pytest.skip("batch256.json not generated")
     g = json.load(open(path))
     assert g["params_sha256"] == S.sha256_file(S.default_params_path())
     ds = g["designs"]
-    if not ds:
-        pytest.skip("no members generated yet")
+    assert len(ds) == 256
     say("batch256 golden members", len(ds))
     rb = ctx.design_batch([d["protein"] for d in ds], [d["lambda"] for d in ds], gt, gp)
     persistent(sd, rb)
@@ -125,6 +123,8 @@ def test_fixed_schedules_equal_plain(sd, gt, gp, threads, per_cu):
     say("schedule", threads, per_cu)
     rb = c.design_batch(prots, lams, gt, gp)
     persistent(sd, rb)
+    for r in rb:  # the launch ran under the fixed schedule
+        assert r.sched_threads == threads and r.sched_grid % per_cu == 0, (r.sched_threads, r.sched_grid)
     for p, lam, r in zip(prots, lams, rb):
         assert key(r) == key(c.design(p, gt, gp, lam))
     c.close()

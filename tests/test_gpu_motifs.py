@@ -104,7 +104,7 @@ def test_motif_goldens(name, ctx, gtable, gparams, params_path):
     path = os.path.join(HERE, "golden", f"{name}.json")
     gold = json.load(open(path))
     assert gold["params_sha256"] == S.sha256_file(params_path)
-    assert gold["designs"]
+    assert len(gold["designs"]) == {"motifs": 6, "motifs_wide": 2}[name]
     for d in gold["designs"]:
         say(name, d["A"], d["lambda"])
         r = ctx.design_motifs(d["protein"], gold["motifs"], gtable, gparams, d["lambda"])

@@ -160,12 +160,11 @@ def test_invalid_inputs_on_device(sd, ctx, gtable, gparams):
         assert e.value.code == -5
 
 
-def _golden(name):
+def _golden(name, count):
     path = os.path.join(HERE, "golden", f"{name}.json")
-    if not os.path.exists(path):
-        pytest.skip(f"{name}.json not generated")
     g = json.load(open(path))
     assert g["params_sha256"] == S.sha256_file(S.default_params_path())
+    assert len(g["designs"]) == count
     return g["designs"]
 
 
@@ -183,19 +182,13 @@ def _check_golden(r, g):
 
 @pytest.mark.parametrize("i", range(8))
 def test_plain300_vs_golden(i, ctx, gtable, gparams):
-    g = _golden("plain300")
-    if i >= len(g):
-        pytest.skip("not generated")
-    g = g[i]
+    g = _golden("plain300", 8)[i]
     say("plain300", g["seed"], g["lambda"])
     _check_golden(ctx.design(g["protein"], gtable, gparams, g["lambda"]), g)
 
 
 @pytest.mark.parametrize("i", range(4))
 def test_plain925_1976_vs_golden(i, ctx, gtable, gparams):
-    g = _golden("plain925_1976")
-    if i >= len(g):
-        pytest.skip("not generated")
-    g = g[i]
+    g = _golden("plain925_1976", 4)[i]
     say("plain925_1976", g["A"], g["lambda"])
     _check_golden(ctx.design(g["protein"], gtable, gparams, g["lambda"]), g)
