@@ -395,6 +395,8 @@ def main():
     ap.add_argument("--warmup", type=int, default=1)
     ap.add_argument("--workload", default="batch256", choices=["batch256", "plain300", "plain925_1976", "scale", "served", "motifs"])
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-side-legs", action="store_true",
+                    help="batch256: skip the plain and served passes after the timed steps (profiling runs)")
     ap.add_argument("--retain-all", action="store_true",
                     help="plain workloads: also time the scalar-dense control (every finite direct "
                          "interval retained) and report its time and visit ratios to the sparse fill")
@@ -440,9 +442,17 @@ def main():
     ctx = sd.Context(0, kernel_timing=KERNEL_TIMING_EVERY)
     params = sd.Params(S.default_params_path())
     table = sd.CodonTable(S.codon_weights(2026))
+    last = None
     for i in range(args.warmup):
-        run_step(ctx, items, table, params, batch, motifs)
+        last = run_step(ctx, items, table, params, batch, motifs)
         progress(f"warmup step {i + 1}/{args.warmup}")
+    # the batched schedule's autotuner explores one candidate per call of a new size class: the
+    # timed steps start only once it has settled (untimed extra calls if the warmup was shorter)
+    extra = 0
+    while batch and (last is None or not all(r.sched_tuned for r in last)) and extra < 16:
+        last = run_step(ctx, items, table, params, batch, motifs)
+        extra += 1
+        progress(f"untimed tuning step {extra}")
     t0 = time.perf_counter()
     results = []
     for i in range(args.steps):
@@ -481,8 +491,11 @@ def main():
         line["batch"] = {"paths": sorted({r.path for r in results[-1]}),
                          "graph_captured": all(r.graph_captured == 1 for r in results[-1]),
                          "launch_s": sum(r.t_span_kernels_s for r in results[-1]),
-                         "schedule": sorted({(r.sched_threads, r.sched_grid) for r in results[-1]})}
-        line.update(side_legs(sd, items, table, params, results[-1], elapsed / args.steps))
+                         "schedule": sorted({(r.sched_threads, r.sched_grid, r.sched_item_waves) for r in results[-1]}),
+                         "schedule_settled": all(r.sched_tuned == 1 for s_ in results for r in s_),
+                         "untimed_tuning_steps": extra}
+        if not args.no_side_legs:
+            line.update(side_legs(sd, items, table, params, results[-1], elapsed / args.steps))
     if motifs:
         line["per_design"] = {k: dict(v, n_states=r.n_states) for (k, v), r in zip(line["per_design"].items(), results[-1])}
     if args.retain_all and not batch and not motifs:

@@ -73,6 +73,11 @@ typedef struct sd_options {
     int batch_threads;     /* persistent (batched / served) launch: threads per workgroup, 64,
                               256 or 512, with batch_per_cu workgroups per CU; both 0: autotuned */
     int batch_per_cu;
+    int batch_item_waves;  /* with batch_threads set: waves per work item (layer pair) of the
+                              persistent launch -- 0 or threads / 64 (the workgroup's waves
+                              share each item), or 1 with 64 or 256 threads (every wave works on
+                              its own items); must be 0 when batch_threads is 0; anything else
+                              gives SD_E_ARG at create                                        */
     int span_check;        /* debug mode (race detection): 1 = plain designs run every span step
                               twice, the second time with another workgroup size after restoring
                               the committed candidate counts and the counters, and compare digests
@@ -82,7 +87,6 @@ typedef struct sd_options {
                               SD_E_INTERNAL naming the span or member.  2 = the same, but the
                               visit counters are deliberately not restored before the re-run, so
                               the comparison must fail (a self-test of the check).  0 = off   */
-    int reserved[1];
 } sd_options;
 
 typedef struct sd_result {
@@ -116,6 +120,10 @@ typedef struct sd_result {
                                 (0 for the plain paths)                                        */
     int32_t sched_grid;      /* ... and its workgroup count (resident workgroups per CU times
                                 the CU count; 0 for the plain paths)                           */
+    int32_t sched_item_waves;/* ... and its waves per work item (0 for the plain paths)        */
+    int32_t sched_tuned;     /* 1 if that schedule was fixed by the caller or is the autotuner's
+                                settled choice for the batch's size class; 0 while the tuner
+                                still explores (it runs one candidate per call)                */
 } sd_result;
 
 /* sd_result.path: the fill behind a result.  Batched and served results come from the persistent

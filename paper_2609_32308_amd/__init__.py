@@ -53,7 +53,7 @@ class SDError(RuntimeError):
 class Options(C.Structure):
     _fields_ = [("retain_all", C.c_int), ("capacity_override", C.c_int), ("kernel_timing", C.c_int),
                 ("span_threads", C.c_int), ("batch_threads", C.c_int), ("batch_per_cu", C.c_int),
-                ("span_check", C.c_int), ("reserved", C.c_int * 1)]
+                ("batch_item_waves", C.c_int), ("span_check", C.c_int)]
 
 
 class ServerCfg(C.Structure):
@@ -78,7 +78,8 @@ class _Result(C.Structure):
         ("t_span_kernels_s", C.c_double), ("n_span_launches", C.c_int64),
         ("cand_slots", C.c_int64), ("cand_slots_first", C.c_int64), ("cand_overflow", C.c_int32),
         ("n_timed_launches", C.c_int64), ("path", C.c_int32), ("graph_captured", C.c_int32),
-        ("sched_threads", C.c_int32), ("sched_grid", C.c_int32),
+        ("sched_threads", C.c_int32), ("sched_grid", C.c_int32), ("sched_item_waves", C.c_int32),
+        ("sched_tuned", C.c_int32),
     ]
 
 
@@ -225,6 +226,8 @@ class Result:
     graph_captured: int
     sched_threads: int
     sched_grid: int
+    sched_item_waves: int
+    sched_tuned: int
 
 
 def _convert(r: _Result) -> Result:
@@ -233,7 +236,7 @@ def _convert(r: _Result) -> Result:
                  r.n_cells, r.n_candidates, r.n_visits, r.n_feasible, r.t_fill_s, r.t_total_s,
                  r.t_span_kernels_s, r.n_span_launches, r.cand_slots, r.cand_slots_first,
                  r.cand_overflow, r.n_timed_launches, r.path, r.graph_captured, r.sched_threads,
-                 r.sched_grid)
+                 r.sched_grid, r.sched_item_waves, r.sched_tuned)
     lib().sd_result_free(C.byref(r))
     return out
 
@@ -241,9 +244,9 @@ def _convert(r: _Result) -> Result:
 class Context:
     def __init__(self, device: int = 0, retain_all: bool = False, capacity_override: int = 0,
                  kernel_timing: int = 0, span_threads: int = 0, batch_threads: int = 0,
-                 batch_per_cu: int = 0, span_check: int = 0):
+                 batch_per_cu: int = 0, span_check: int = 0, batch_item_waves: int = 0):
         opt = Options(int(retain_all), int(capacity_override), int(kernel_timing), int(span_threads),
-                      int(batch_threads), int(batch_per_cu), int(span_check))
+                      int(batch_threads), int(batch_per_cu), int(batch_item_waves), int(span_check))
         h = C.c_void_p()
         _check(lib().sd_context_create(device, C.byref(opt), C.byref(h)), "sd_context_create")
         self.h = h

@@ -166,10 +166,17 @@ sd_status context_create(int device, const sd_options* opt, bool ext, void* ext_
         delete c;
         return fail(SD_E_ARG, "batch_threads must be 0, 64, 256 or 512, with batch_per_cu > 0 exactly when it is set");
     }
+    if (c->opt.batch_item_waves != 0 &&
+        (c->opt.batch_threads == 0 || !persistent_schedule_valid(c->opt.batch_threads, c->opt.batch_item_waves))) {
+        delete c;
+        return fail(SD_E_ARG, "batch_item_waves must be 0 or one of (batch_threads, batch_item_waves) = "
+                              "(64, 1), (256, 4), (256, 1), (512, 8)");
+    }
     e = hipSetDevice(device);
     if (e == hipSuccess && c->opt.batch_threads) {
         int per_cu = 0;
-        if (persistent_occupancy(c->opt.batch_threads, &per_cu) != hipSuccess || c->opt.batch_per_cu > per_cu) {
+        const int iw = c->opt.batch_item_waves ? c->opt.batch_item_waves : c->opt.batch_threads / 64;
+        if (persistent_occupancy(c->opt.batch_threads, iw, &per_cu) != hipSuccess || c->opt.batch_per_cu > per_cu) {
             delete c;
             return fail(SD_E_ARG, "batch_per_cu exceeds the co-resident workgroups per CU");
         }
@@ -1126,8 +1133,8 @@ namespace sd {
 // Runs the batched persistent launch for lattices Ls (already validated) and returns the device
 // instance descriptors (in the arena) through Is.  *barrier_ok is false when the grid barrier
 // reported a wait beyond its spin limit (the caller then recomputes in plain mode).
-sd_status run_batch(sd_context* c, std::vector<Lattice>& Ls, std::vector<Inst>& Is, int grid,
-                    int threads, bool* barrier_ok, double* kernel_s, Inst** insts_out) {
+sd_status run_batch(sd_context* c, std::vector<Lattice>& Ls, std::vector<Inst>& Is, const sd_context::Sched& sc,
+                    bool* barrier_ok, double* kernel_s, Inst** insts_out) {
     const int n = (int)Ls.size();
     Is.assign(n, Inst{});
     std::vector<InstLayout> lay(n);
@@ -1171,7 +1178,8 @@ sd_status run_batch(sd_context* c, std::vector<Lattice>& Ls, std::vector<Inst>& 
     if (hipStreamBeginCapture(c->stream, hipStreamCaptureModeThreadLocal) == hipSuccess) {
         hipError_t e1 = launch_batch_init(insts_dev, n, ctl, c->stream);
         hipError_t e2 = e1 == hipSuccess ? launch_persistent(insts_dev, n, maxn + 1, (const EnergyTables*)c->E_dev,
-                                                             (const int32_t*)c->spec_dev, ctl, grid, threads, spin_cap, c->stream)
+                                                             (const int32_t*)c->spec_dev, ctl, sc.grid, sc.threads, sc.item_waves,
+                                                             spin_cap, c->stream)
                                          : e1;
         hipError_t e3 = hipStreamEndCapture(c->stream, &graph);
         if (e2 == hipSuccess && e3 == hipSuccess && graph &&
@@ -1186,7 +1194,7 @@ sd_status run_batch(sd_context* c, std::vector<Lattice>& Ls, std::vector<Inst>& 
         if (e == hipSuccess) e = launch_batch_init(insts_dev, n, ctl, c->stream);
         if (e == hipSuccess)
             e = launch_persistent(insts_dev, n, maxn + 1, (const EnergyTables*)c->E_dev, (const int32_t*)c->spec_dev,
-                                  ctl, grid, threads, spin_cap, c->stream);
+                                  ctl, sc.grid, sc.threads, sc.item_waves, spin_cap, c->stream);
     }
     if (e == hipSuccess) e = hipEventRecord(c->ev1, c->stream);
     BatchCtl hctl;
@@ -1204,82 +1212,91 @@ sd_status run_batch(sd_context* c, std::vector<Lattice>& Ls, std::vector<Inst>& 
     return SD_OK;
 }
 
-// Autotuned schedule of the persistent launch: threads per workgroup (one wave per layer-pair
-// item, or four waves sharing an item) and resident workgroups per CU.  The probe is a sample of
-// the batch itself: up to 12 members spread over its sorted lengths, designed with worst-case
-// segments under every candidate schedule (the probe's results are discarded).  The fastest is
-// kept per size class, (floor log2 of the mean length, floor log2 of the member count, capped at
-// 16 members), so later batches of similar sizes reuse it.  The member count is part of the key
-// because one member leaves most of the grid idle and favours few workgroups, a schedule that
-// is twice as slow for hundreds of members of the same mean length.
-sd_status tuned_schedule(sd_context* c, const std::vector<Lattice>& batch, int* grid, int* threads) {
-    if (c->opt.batch_threads > 0) {  // fixed by the caller
-        *threads = c->opt.batch_threads;
-        *grid = c->opt.batch_per_cu * c->num_cu;
-        return SD_OK;
-    }
+// Autotuned schedule of the persistent launch: threads per workgroup, resident workgroups per CU,
+// and waves per work item (one layer pair): the four waves of a workgroup share each item, or
+// every wave works on its own items.  Every schedule gives bit-identical results, so the tuner
+// explores on the caller's own batches: the first calls of a size class run one candidate each,
+// scored by launch time per DP cell, and later calls of the class run the fastest.  A size class
+// is (floor log2 of the mean length, floor log2 of the member count, capped at 16 members).  A
+// probe on a sample of the batch would misjudge the waves dimension: a dozen members leave the
+// launch latency-bound, where shared items win, while hundreds keep it throughput-bound, where
+// independent waves win.
+namespace {
+int size_class(const std::vector<Lattice>& batch) {
     double mean_n = 0;
     for (const Lattice& L : batch) mean_n += L.n;
     mean_n /= std::max<size_t>(1, batch.size());
     const int cls_n = (int)std::floor(std::log2(std::max(1.0, mean_n)));
     const int cls_m = std::min(4, (int)std::floor(std::log2((double)std::max<size_t>(1, batch.size()))));
-    const int cls = cls_n * 8 + cls_m;
-    auto hit = c->sched.find(cls);
-    if (hit != c->sched.end()) {
-        *grid = hit->second.first;
-        *threads = hit->second.second;
+    return cls_n * 8 + cls_m;
+}
+}  // namespace
+
+// The schedule of the next batched call; *settled is false while the class is still exploring.
+sd_status tuned_schedule(sd_context* c, const std::vector<Lattice>& batch, sd_context::Sched* out, int* cls_out,
+                         bool* settled) {
+    *cls_out = -1;
+    if (c->opt.batch_threads > 0) {  // fixed by the caller
+        out->threads = c->opt.batch_threads;
+        out->grid = c->opt.batch_per_cu * c->num_cu;
+        out->item_waves = c->opt.batch_item_waves ? c->opt.batch_item_waves : c->opt.batch_threads / 64;
+        *settled = true;
         return SD_OK;
     }
-    std::vector<int> order(batch.size());
-    for (size_t i = 0; i < order.size(); i++) order[i] = (int)i;
-    std::sort(order.begin(), order.end(), [&](int x, int y) { return batch[x].n < batch[y].n; });
-    const int m = (int)std::min<size_t>(12, batch.size());
-    std::vector<Lattice> Ls;
-    for (int i = 0; i < m; i++) {
-        Lattice L = batch[order[(size_t)i * batch.size() / m]];
-        L.ccap.assign(L.N, 0);  // worst-case segments for the probe
-        int64_t acc = 0;
-        for (int b = 0; b < L.N; b++) {
-            const int lb = L.layer[b];
-            L.coff[b] = acc;
-            L.ccap[b] = lb >= 5 ? L.off[lb - 4] : 0;
-            acc += L.ccap[b];
+    const int cls = size_class(batch);
+    *cls_out = cls;
+    sd_context::Tune& T = c->tune[cls];
+    if (T.cands.empty()) {
+        // candidates in the order they are tried: independent waves first (the best schedule
+        // for large batches); one workgroup per CU and 64-thread workgroups only for batches of
+        // fewer than 12 members, where the grid barrier's participants weigh more than residency
+        int pc_w = 0, pc_s = 0, pc_64 = 0;
+        hipError_t e = persistent_occupancy(256, 1, &pc_w);
+        if (e == hipSuccess) e = persistent_occupancy(256, 4, &pc_s);
+        if (e == hipSuccess) e = persistent_occupancy(64, 1, &pc_64);
+        if (e != hipSuccess || pc_w <= 0 || pc_s <= 0 || pc_64 <= 0) {
+            c->tune.erase(cls);
+            return hip_fail(e, "occupancy query");
         }
-        L.cand_slots = acc;
-        Ls.push_back(std::move(L));
-    }
-    double best_t = 1e30;
-    int best_grid = 0, best_threads = 256;
-    for (int threads_c : {256, 64}) {  // 512 (caller-selectable) lost every probe on mixed batches
-        int per_cu = 0;
-        hipError_t e = persistent_occupancy(threads_c, &per_cu);
-        if (e != hipSuccess || per_cu <= 0) return hip_fail(e, "occupancy query");
-        std::vector<int> cands = {per_cu};
-        if (per_cu > 2) cands.push_back((per_cu + 1) / 2);
-        if (per_cu > 1) cands.push_back(1);
-        for (int k : cands) {
-            const int gr = k * c->num_cu;
-            std::vector<Inst> Is;
-            bool ok = false;
-            double ks = 0;
-            sd_status s = run_batch(c, Ls, Is, gr, threads_c, &ok, &ks, nullptr);
-            if (s) return s;
-            if (ok && ks < best_t) {
-                best_t = ks;
-                best_grid = gr;
-                best_threads = threads_c;
-            }
+        auto add = [&](int threads, int iw, int per_cu) {
+            sd_context::Sched sc;
+            sc.threads = threads;
+            sc.item_waves = iw;
+            sc.grid = per_cu * c->num_cu;
+            for (const auto& x : T.cands)
+                if (x.threads == sc.threads && x.item_waves == sc.item_waves && x.grid == sc.grid) return;
+            T.cands.push_back(sc);
+        };
+        add(256, 1, pc_w);
+        add(256, 4, pc_s);
+        add(256, 1, std::max(1, pc_w / 2));
+        add(256, 4, std::max(1, pc_s / 2));
+        if (batch.size() < 12) {
+            add(256, 4, 1);
+            add(64, 1, pc_64);
         }
+        T.score.assign(T.cands.size(), 0.0);
     }
-    if (best_grid <= 0) return fail(SD_E_DEVICE, "no persistent schedule completed its grid barriers");
-    c->sched[cls] = {best_grid, best_threads};
-    if (batch.size() >= 12) {  // a full sample: the server's schedule unless the caller fixed one
-        c->batch_grid = best_grid;
-        c->batch_threads = best_threads;
-    }
-    *grid = best_grid;
-    *threads = best_threads;
+    *settled = T.settled;
+    *out = T.settled ? T.best : T.cands[T.next];
     return SD_OK;
+}
+
+// Records the measured launch of an exploring call (ok: the grid barrier completed).
+void tune_record(sd_context* c, int cls, const std::vector<Lattice>& batch, bool ok, double kernel_s) {
+    auto it = c->tune.find(cls);
+    if (it == c->tune.end() || it->second.settled) return;
+    sd_context::Tune& T = it->second;
+    double cells = 0;
+    for (const Lattice& L : batch) cells += (double)L.cells;
+    T.score[T.next] = ok ? kernel_s / std::max(1.0, cells) : HUGE_VAL;
+    if (++T.next < (int)T.cands.size()) return;
+    int b = 0;
+    for (int k = 1; k < (int)T.cands.size(); k++)
+        if (T.score[k] < T.score[b]) b = k;
+    T.best = T.cands[b];
+    T.settled = true;
+    if (batch.size() >= 12) c->batch_sched = T.best;  // the server's schedule unless the caller fixed one
 }
 
 }  // namespace sd
@@ -1287,8 +1304,8 @@ sd_status tuned_schedule(sd_context* c, const std::vector<Lattice>& batch, int* 
 namespace {
 // Digests of every member's tables after the launch just run; then the same batch under another
 // persistent schedule; the digests must agree member by member.
-sd_status check_batch_rerun(sd_context* ctx, std::vector<Lattice>& Ls, std::vector<Inst>& Is, int grid, int threads,
-                            Inst** insts_dev) {
+sd_status check_batch_rerun(sd_context* ctx, std::vector<Lattice>& Ls, std::vector<Inst>& Is,
+                            const sd_context::Sched& sc, Inst** insts_dev) {
     const int m = (int)Ls.size();
     const size_t need = 256 + 16 * (size_t)m;
     hipError_t e = hipSuccess;
@@ -1306,14 +1323,18 @@ sd_status check_batch_rerun(sd_context* ctx, std::vector<Lattice>& Ls, std::vect
     if (e == hipSuccess) e = hipMemcpyAsync(h1.data(), d, 8 * (size_t)m, hipMemcpyDeviceToHost, ctx->stream);
     if (e == hipSuccess) e = hipStreamSynchronize(ctx->stream);
     if (e != hipSuccess) return hip_fail(e, "span check digests");
+    // another schedule: shared items <-> one wave per item
+    sd_context::Sched s2;
+    s2.threads = sc.threads == 256 && sc.item_waves == 4 ? 64 : 256;
+    s2.item_waves = s2.threads == 64 ? 1 : 4;
     int per_cu = 0;
-    const int threads2 = threads == 256 ? 64 : 256;
-    e = persistent_occupancy(threads2, &per_cu);
+    e = persistent_occupancy(s2.threads, s2.item_waves, &per_cu);
     if (e != hipSuccess || per_cu <= 0) return hip_fail(e, "occupancy query");
+    s2.grid = std::min(per_cu, 2) * ctx->num_cu;
     bool ok2 = false;
     double ks2 = 0;
     std::vector<Inst> Is2;
-    sd_status s = run_batch(ctx, Ls, Is2, std::min(per_cu, 2) * ctx->num_cu, threads2, &ok2, &ks2, insts_dev);
+    sd_status s = run_batch(ctx, Ls, Is2, s2, &ok2, &ks2, insts_dev);
     if (s) return s;
     if (!ok2) return fail(SD_E_INTERNAL, "span check: the re-run's grid barrier gave up");
     for (int i = 0; i < m && e == hipSuccess; i++) e = launch_checksum(Is2[i], 0, d + i, ctx->stream);
@@ -1323,10 +1344,10 @@ sd_status check_batch_rerun(sd_context* ctx, std::vector<Lattice>& Ls, std::vect
     for (int i = 0; i < m; i++)
         if (h1[i] != h2[i])
             return fail(SD_E_INTERNAL, "span check: batch member " + std::to_string(i) + " filled different tables "
-                                       "under the schedules " + std::to_string(threads) + " and " +
-                                       std::to_string(threads2) + " threads per workgroup");
+                                       "under the schedules " + std::to_string(sc.threads) + "/" +
+                                       std::to_string(sc.item_waves) + " and " + std::to_string(s2.threads) + "/" +
+                                       std::to_string(s2.item_waves) + " (threads per workgroup / waves per item)");
     Is = std::move(Is2);
-    (void)grid;
     return SD_OK;
 }
 
@@ -1358,18 +1379,21 @@ sd_status design_batch_impl(sd_context* ctx, int n, const char* const* proteins,
                 }
             }
             sd_status s = ensure_params(ctx, params);
-            int grid = 0, threads = 256;
-            if (!s) s = tuned_schedule(ctx, Ls, &grid, &threads);
+            sd_context::Sched sc;
+            int cls = -1;
+            bool settled = true;
+            if (!s) s = tuned_schedule(ctx, Ls, &sc, &cls, &settled);
             const double tf0 = now_s();
             std::vector<Inst> Is;
             bool ok = false;
             double ks = 0;
             Inst* insts_dev = nullptr;
-            if (!s) s = run_batch(ctx, Ls, Is, grid, threads, &ok, &ks, &insts_dev);
+            if (!s) s = run_batch(ctx, Ls, Is, sc, &ok, &ks, &insts_dev);
             const double tf1 = now_s();
+            if (!s && !settled) tune_record(ctx, cls, Ls, ok, ks);
             // span_check debug mode: the whole launch again under another schedule, then a digest
             // of every member's tables from each run must agree
-            if (!s && ok && ctx->opt.span_check) s = check_batch_rerun(ctx, Ls, Is, grid, threads, &insts_dev);
+            if (!s && ok && ctx->opt.span_check) s = check_batch_rerun(ctx, Ls, Is, sc, &insts_dev);
             // the canonical traceback of every member in one launch (one wavefront each)
             if (!s && ok) {
                 hipError_t e = launch_trace_many(insts_dev, m, (const EnergyTables*)ctx->E_dev,
@@ -1440,8 +1464,10 @@ sd_status design_batch_impl(sd_context* ctx, int n, const char* const* proteins,
                 outs[gi].cand_overflow = 0;
                 outs[gi].path = SD_PATH_PERSISTENT;
                 outs[gi].graph_captured = ctx->last_graph ? 1 : 0;
-                outs[gi].sched_threads = threads;
-                outs[gi].sched_grid = grid;
+                outs[gi].sched_threads = sc.threads;
+                outs[gi].sched_grid = sc.grid;
+                outs[gi].sched_item_waves = sc.item_waves;
+                outs[gi].sched_tuned = settled ? 1 : 0;
                 if (ctx->occ_K > 0) occupancy_bins(Ls[i], T.counts, ctx->occ_K, &ctx->occ[(size_t)gi * ctx->occ_K]);
             }
             if (s) {

@@ -20,9 +20,20 @@ struct sd_context {
     bool external = false;  // arena and stream belong to the caller (sd_context_create_external)
     void* staging = nullptr;  // pinned host image of the input region
     size_t staging_bytes = 0;
-    int batch_grid = 0;       // autotuned persistent grid size (0: not tuned yet)
-    int batch_threads = 256;  // autotuned threads per block of the persistent launch
-    std::map<int, std::pair<int, int>> sched;  // (length, member-count) class -> (grid, threads)
+    struct Sched {
+        int grid = 0, threads = 256, item_waves = 4;
+    };
+    Sched batch_sched;  // the server's schedule: tuned on batches of >= 12 members (grid 0: none yet)
+    // Tuner state per (length, member-count) class: the candidate schedules, run one per batched
+    // call until each has been measured, then the fastest for every later call of the class.
+    struct Tune {
+        std::vector<Sched> cands;
+        std::vector<double> score;  // launch seconds per DP cell (infinite: the barrier gave up)
+        int next = 0;
+        bool settled = false;
+        Sched best;
+    };
+    std::map<int, Tune> tune;
     char* tbuf = nullptr;  // pinned download buffer of the dense-table test hooks
     size_t tbuf_bytes = 0;
     bool last_graph = false;  // last batch ran as a captured graph
@@ -75,10 +86,12 @@ hipError_t launch_strict_count(const Inst& I, hipStream_t st);
 hipError_t launch_span_gen(const Inst& I, const EnergyTables* E, const int32_t* spec, int g,
                            int ext_layer, int num_cu, hipStream_t st);
 hipError_t launch_batch_init(const Inst* insts_dev, int ninst, BatchCtl* ctl, hipStream_t st);
-hipError_t persistent_occupancy(int threads, int* blocks_per_cu);
+// persistent schedules: (64, 1), (256, 4), (256, 1), (512, 8) as (threads, waves per work item)
+bool persistent_schedule_valid(int threads, int item_waves);
+hipError_t persistent_occupancy(int threads, int item_waves, int* blocks_per_cu);
 hipError_t launch_persistent(const Inst* insts_dev, int ninst, int nsteps, const EnergyTables* E,
-                             const int32_t* spec, BatchCtl* ctl, int grid, int threads, unsigned spin_cap,
-                             hipStream_t st);
+                             const int32_t* spec, BatchCtl* ctl, int grid, int threads, int item_waves,
+                             unsigned spin_cap, hipStream_t st);
 }  // namespace sd
 
 

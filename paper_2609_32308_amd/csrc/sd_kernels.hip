@@ -269,12 +269,12 @@ __device__ __forceinline__ int64_t PRt(const IT& I, int q, int l2) { return I.P(
 // left segment explicit (paths of l1 edges out of a1), right segment separable
 template <class IT>
 __device__ int64_t rsep_pair(const IT& I, const SmallE& S, int a1, int64_t Uab, int l1, int l2,
-                             int cl, int dl, int q, const int64_t* __restrict__ ob) {
+                             int cl, int dl, int q, const int64_t* __restrict__ ob, int lane) {
     const int X = mm_class(l1, l2), g2 = dl - cl;
     const int64_t base = Uab + fx(interior_base(S, l1, l2), I.shift) + PRt(I, q, l2);
     const int f0 = I.fwd_off()[a1 * 4 + l1 - 1], f1 = I.fwd_off()[a1 * 4 + l1];
     int64_t best = kINF;
-    for (int i = f0; i < f1; i++) {
+    for (int i = f0 + lane; i < f1; i += 64) {
         const int fm = I.fwd_meta()[i], c = fm >> 4, xi = (fm >> 2) & 3, xk = fm & 3;
         const int64_t o = ob[X * 4 + xi], idl = I.IDL()[ring_idx(c, g2, X, xk)];
         if (o < kINF && idl < kINF) best = mn(best, base + I.fwd_cost()[i] + o + idl);
@@ -285,12 +285,12 @@ __device__ int64_t rsep_pair(const IT& I, const SmallE& S, int a1, int64_t Uab, 
 // left segment separable, right segment explicit (paths of l2 edges into b1)
 template <class IT>
 __device__ int64_t lsep_pair(const IT& I, const SmallE& S, int b1, int64_t Uab, int l1, int l2,
-                             int cl, int dl, int p, const int64_t* __restrict__ oa) {
+                             int cl, int dl, int p, const int64_t* __restrict__ oa, int lane) {
     const int X = mm_class(l1, l2), g2 = dl - cl;
     const int64_t base = Uab + fx(interior_base(S, l1, l2), I.shift) + PLt(I, p, l1);
     const int r0 = I.bwd_off()[b1 * 4 + l2 - 1], r1 = I.bwd_off()[b1 * 4 + l2];
     int64_t best = kINF;
-    for (int j = r0; j < r1; j++) {
+    for (int j = r0 + lane; j < r1; j += 64) {
         const int bm = I.bwd_meta()[j], d = bm >> 4, xl = (bm >> 2) & 3, xj = bm & 3;
         const int64_t o = oa[X * 4 + xj], jdl = I.JDL()[ring_idx(d, g2, X, xl)];
         if (o < kINF && jdl < kINF) best = mn(best, base + I.bwd_cost()[j] + o + jdl);
@@ -342,10 +342,10 @@ __device__ int64_t one_sided(const IT& I, const SmallE& S, int a1, int b1, int64
         }
     }
     // 2x3 with the left side explicit, 3x2 with the right side explicit
-    if (lane == 0 && cap >= 5 && !sep_left(p, 2) && sep_right(q, 3))
-        best = mn(best, rsep_pair(I, S, a1, Uab, 2, 3, p + 3, q - 4, q, ob));
-    if (lane == 1 && cap >= 5 && sep_left(p, 3) && !sep_right(q, 2))
-        best = mn(best, lsep_pair(I, S, b1, Uab, 3, 2, p + 4, q - 3, p, oa));
+    if (cap >= 5 && !sep_left(p, 2) && sep_right(q, 3))
+        best = mn(best, rsep_pair(I, S, a1, Uab, 2, 3, p + 3, q - 4, q, ob, lane));
+    if (cap >= 5 && sep_left(p, 3) && !sep_right(q, 2))
+        best = mn(best, lsep_pair(I, S, b1, Uab, 3, 2, p + 4, q - 3, p, oa, lane));
     return best;
 }
 
@@ -354,6 +354,24 @@ struct GroupCounters {
     unsigned long long visits, feasible;
 };
 
+
+// The threads that work on one layer pair: the whole workgroup (ordered by workgroup barriers),
+// or a single wavefront of a workgroup whose waves each work on their own pair (ordered within the
+// wave; a workgroup barrier there would pair up unrelated points of different waves).
+struct BlockTeam {
+    __device__ int tid() const { return threadIdx.x; }
+    __device__ int size() const { return blockDim.x; }
+    __device__ void sync() const { __syncthreads(); }
+};
+struct WaveTeam {
+    __device__ int tid() const { return threadIdx.x & 63; }
+    __device__ int size() const { return 64; }
+    __device__ void sync() const {
+        __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+        __builtin_amdgcn_wave_barrier();
+        __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+    }
+};
 
 template <int NW>  // waves per workgroup
 struct GroupShared {
@@ -662,11 +680,12 @@ __device__ void append_candidates(const IT& I, int a_lo, int wa, int b_lo, int w
     }
 }
 
-template <int NW, class IT>
+template <int NW, class IT, class Team = BlockTeam>
 __device__ GroupCounters span_group(const IT& I, const SmallE& S, const EnergyTables* __restrict__ E,
-                                    const int32_t* __restrict__ spec, int p, int q, GroupShared<NW>& G) {
+                                    const int32_t* __restrict__ spec, int p, int q, GroupShared<NW>& G,
+                                    Team T = Team()) {
     const int g = q - p, s = I.shift;
-    const int tid = threadIdx.x, wave = tid >> 6, lane = tid & 63, nw = blockDim.x >> 6;
+    const int tid = T.tid(), wave = tid >> 6, lane = tid & 63, nw = T.size() >> 6;
     GroupCounters ctr{0, 0};
     const int a_lo = I.off()[p], a_hi = I.off()[p + 1], b_lo = I.off()[q], b_hi = I.off()[q + 1];
     const int wa = a_hi - a_lo, wb = b_hi - b_lo, ncell = wa * wb;
@@ -695,7 +714,7 @@ __device__ GroupCounters span_group(const IT& I, const SmallE& S, const EnergyTa
         }
         if (lane == 0) G.ncombo = base;
     }
-    __syncthreads();
+    T.sync();
     // phase 1: typed closed values; the parts of every (cell, type) job on separate waves
     // labelled pairs over 1, 2 or 4 waves: wide workgroups run spans with few layer pairs
     constexpr int nparts = NW >= 16 ? 6 : NW >= 8 ? 4 : 3;
@@ -707,7 +726,7 @@ __device__ GroupCounters span_group(const IT& I, const SmallE& S, const EnergyTa
         if (lane == 0 && v < kINF)
             __hip_atomic_fetch_min(&G.vbuf[ci][t], v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
     }
-    __syncthreads();
+    T.sync();
     // phase 2: branch value (eq. 2), S2 (eq. 7), P_S, S1 and the retention test (eq. 6); one
     // cell per wave from the first wave on.  Every scan reads only entries committed by earlier
     // spans.
@@ -738,7 +757,7 @@ __device__ GroupCounters span_group(const IT& I, const SmallE& S, const EnergyTa
         G.red[wave][0] = lm0;
         G.red[wave][1] = lm1;
     }
-    __syncthreads();
+    T.sync();
     if (wave == 0) {
         // LM: layer-pair minimum of the both-separable form
         if (lane == 0 && g >= 5) {
@@ -761,7 +780,7 @@ __device__ GroupCounters span_group(const IT& I, const SmallE& S, const EnergyTa
         if (wave >= w0) {
             int64_t m0 = kINF, m1 = kINF;
             const int qn = q + 1, ph = (p % 3) * 3 + (qn % 3), cap = min(g + 1 - 7, kMaxLoop);
-            for (int k = tid - 64 * w0; k < kPairCnt[kListFast][ph][cap]; k += blockDim.x - 64 * w0) {
+            for (int k = tid - 64 * w0; k < kPairCnt[kListFast][ph][cap]; k += T.size() - 64 * w0) {
                 const int code = kPairList[kListFast][ph][k], l1 = code & 31, l2 = (code >> 5) & 31;
                 const int cl = p + 1 + l1, dl = qn - 1 - l2, X = pair_class(l1, l2);
                 const int64_t lm = I.LM()[lm_idx(cl, dl - cl, X)];
@@ -777,7 +796,7 @@ __device__ GroupCounters span_group(const IT& I, const SmallE& S, const EnergyTa
                 G.red2[wave][1] = m1;
             }
         }
-        __syncthreads();
+        T.sync();
         if (tid == 64 * w0) {
             int64_t r0 = kINF, r1 = kINF;
             for (int w = w0; w < nw; w++) {
@@ -792,9 +811,9 @@ __device__ GroupCounters span_group(const IT& I, const SmallE& S, const EnergyTa
 }
 
 // ---- external column: X(a) for every a of layer L (one workgroup) ------------------------------
-template <class IT>
-__device__ void ext_column(const IT& I, const SmallE& S, int L, int64_t* red) {
-    const int tid = threadIdx.x;
+template <class IT, class Team = BlockTeam>
+__device__ void ext_column(const IT& I, const SmallE& S, int L, int64_t* red, Team T = Team()) {
+    const int tid = T.tid(), nt = T.size(), wave = tid >> 6;
     for (int a = I.off()[L]; a < I.off()[L + 1]; a++) {
         int64_t v = kINF;
         if (tid < 4) {
@@ -804,7 +823,7 @@ __device__ void ext_column(const IT& I, const SmallE& S, int L, int64_t* red) {
         if (L + 5 <= I.n) {
             const int bstart = I.off()[L + 5];
             const int64_t base = I.rowoff()[a] - I.off()[L + 1];
-            for (int bb = bstart + tid; bb < I.N; bb += blockDim.x) {
+            for (int bb = bstart + tid; bb < I.N; bb += nt) {
                 const int64_t* vr = I.V() + (base + bb) * 6;
                 const int64_t xb = I.X()[bb];
 #pragma unroll
@@ -814,14 +833,14 @@ __device__ void ext_column(const IT& I, const SmallE& S, int L, int64_t* red) {
                 }
             }
         }
-        red[tid] = v;
-        __syncthreads();
-        for (int w = blockDim.x / 2; w > 0; w >>= 1) {
-            if (tid < w) red[tid] = mn(red[tid], red[tid + w]);
-            __syncthreads();
+        v = wave_min(v);
+        if (nt > 64) {  // minimum over the waves
+            if ((tid & 63) == 0) red[wave] = v;
+            T.sync();
+            for (int w = 0; w < nt >> 6; w++) v = mn(v, red[w]);
         }
-        if (tid == 0) I.X()[a] = norm_inf(red[0]);
-        __syncthreads();
+        if (tid == 0) I.X()[a] = norm_inf(v);
+        T.sync();
     }
 }
 
@@ -1424,6 +1443,55 @@ __device__ bool grid_barrier(BatchCtl* ctl, unsigned spin_cap, int* s_flag) {
     return *s_flag == 0;
 }
 
+// Work items per instance at its span g = g0 + step: the layer pairs of span g, then one external
+// column (layer n - g + 1, one layer behind).  pref[i] is the exclusive prefix over instances and
+// pref[ninst] the step's total; each thread takes a contiguous run of instances.  Ends with a
+// workgroup barrier.
+template <int NT>
+__device__ void step_prefix(const Inst* __restrict__ insts, int ninst, int step, int* pref, int* wsum) {
+    const int per = (ninst + NT - 1) / NT, lo = threadIdx.x * per, hi = min(lo + per, ninst);
+    int sum = 0;
+    for (int i = lo; i < hi; i++) {
+        const int n = insts[i].n, g = insts[i].g0 + step;
+        sum += (g <= n ? n - g + 1 : 0) + ((g >= 2 && g <= n + 1) ? 1 : 0);
+    }
+    const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+    int incl = sum;
+#pragma unroll
+    for (int o = 1; o < 64; o <<= 1) {
+        const int v = __shfl_up(incl, o, 64);
+        if (lane >= o) incl += v;
+    }
+    if (lane == 63) wsum[w] = incl;
+    __syncthreads();
+    int base_w = 0;
+    for (int k = 0; k < w; k++) base_w += wsum[k];
+    int acc = base_w + incl - sum;
+    for (int i = lo; i < hi; i++) {
+        pref[i] = acc;
+        const int n = insts[i].n, g = insts[i].g0 + step;
+        acc += (g <= n ? n - g + 1 : 0) + ((g >= 2 && g <= n + 1) ? 1 : 0);
+    }
+    if (threadIdx.x == NT - 1) {
+        int tot = 0;
+        for (int k = 0; k < NT / 64; k++) tot += wsum[k];
+        pref[ninst] = tot;
+    }
+    __syncthreads();
+}
+
+// the last instance whose prefix is <= item
+__device__ __forceinline__ int item_instance(const int* pref, int ninst, int item) {
+    int lo = 0, hi = ninst - 1;
+    while (lo < hi) {
+        const int mid = (lo + hi + 1) >> 1;
+        if (pref[mid] <= item) lo = mid;
+        else hi = mid - 1;
+    }
+    return lo;
+}
+
+// Persistent batched launch, the workgroup's waves sharing each work item (NT = 64: one wave).
 template <int NT>
 __global__ __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(4))) void k_persistent(
     const Inst* __restrict__ insts, int ninst, int nsteps, const EnergyTables* __restrict__ E,
@@ -1443,40 +1511,7 @@ __global__ __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(4))) void k_
     __syncthreads();
     unsigned ticket = s_ticket, base = 0;
     for (int step = 0; step < nsteps; step++) {
-        // work items per instance at its span g = g0 + step: layer pairs of span g, then one
-        // external column (layer n - g + 1, one layer behind); exclusive prefix over instances,
-        // each thread taking a contiguous run of instances
-        {
-            const int per = (ninst + NT - 1) / NT, lo = threadIdx.x * per, hi = min(lo + per, ninst);
-            int sum = 0;
-            for (int i = lo; i < hi; i++) {
-                const int n = insts[i].n, g = insts[i].g0 + step;
-                sum += (g <= n ? n - g + 1 : 0) + ((g >= 2 && g <= n + 1) ? 1 : 0);
-            }
-            const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
-            int incl = sum;
-#pragma unroll
-            for (int o = 1; o < 64; o <<= 1) {
-                const int v = __shfl_up(incl, o, 64);
-                if (lane >= o) incl += v;
-            }
-            if (lane == 63) wsum[w] = incl;
-            __syncthreads();
-            int base_w = 0;
-            for (int k = 0; k < w; k++) base_w += wsum[k];
-            int acc = base_w + incl - sum;
-            for (int i = lo; i < hi; i++) {
-                pref[i] = acc;
-                const int n = insts[i].n, g = insts[i].g0 + step;
-                acc += (g <= n ? n - g + 1 : 0) + ((g >= 2 && g <= n + 1) ? 1 : 0);
-            }
-            if (threadIdx.x == NT - 1) {
-                int tot = 0;
-                for (int k = 0; k < NT / 64; k++) tot += wsum[k];
-                pref[ninst] = tot;
-            }
-        }
-        __syncthreads();
+        step_prefix<NT>(insts, ninst, step, pref, wsum);
         const unsigned total = (unsigned)pref[ninst];
         const unsigned lo_item = (unsigned)((uint64_t)total * grp / ngrp);
         const unsigned band = (unsigned)((uint64_t)total * (grp + 1) / ngrp) - lo_item;
@@ -1488,14 +1523,8 @@ __global__ __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(4))) void k_
             unsigned nxt = 0;
             if (drawer) nxt = atomicAdd(&ctl->next[grp].v, 1u);
             const int item = (int)(lo_item + (ticket - base));
-            int lo = 0, hi = ninst - 1;  // last instance whose prefix <= item
-            while (lo < hi) {
-                const int mid = (lo + hi + 1) >> 1;
-                if (pref[mid] <= item) lo = mid;
-                else hi = mid - 1;
-            }
             // the instance index is block-uniform
-            const int inst = __builtin_amdgcn_readfirstlane(lo);
+            const int inst = __builtin_amdgcn_readfirstlane(item_instance(pref, ninst, item));
             const Inst I = insts[inst];  // a few scalar registers: bases and sizes
             const int local = item - pref[inst], g = I.g0 + step;
             const int n = I.n, ncell_items = g <= n ? n - g + 1 : 0;
@@ -1509,6 +1538,53 @@ __global__ __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(4))) void k_
             __syncthreads();  // the item is done and the next ticket is published
             ticket = s_ticket;
             __syncthreads();  // every thread has read it before the next item's drawer writes
+        }
+        base += band;
+        if (!grid_barrier(ctl, spin_cap, &s_flag)) return;
+        if (blockIdx.x == 0 && threadIdx.x == 0) ctl->steps_done.v = step + 1;
+    }
+}
+
+// Persistent batched launch, every wave of the workgroup on its own work items: the waves share
+// the staged energy tables and the step's prefix, and each draws its own tickets and works on its
+// own layer pair with wave-level ordering only.  Between a step's prefix and the grid barrier no
+// workgroup barrier is executed, since the waves run different numbers of items.
+template <int NT>
+__global__ __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(4))) void k_persistent_waves(
+    const Inst* __restrict__ insts, int ninst, int nsteps, const EnergyTables* __restrict__ E,
+    const int32_t* __restrict__ spec, BatchCtl* ctl, unsigned spin_cap) {
+    __shared__ SmallE S;
+    __shared__ GroupShared<1> G[NT / 64];
+    __shared__ int pref[kMaxBatch + 1];
+    __shared__ int wsum[NT / 64];
+    __shared__ int s_flag;
+    stage_tables(S, E);
+    const unsigned grp = blockIdx.x & 7, ngrp = gridDim.x < 8 ? gridDim.x : 8;
+    const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
+    const WaveTeam T;
+    unsigned ticket = 0, base = 0;
+    if (lane == 0) ticket = atomicAdd(&ctl->next[grp].v, 1u);
+    ticket = __builtin_amdgcn_readfirstlane(ticket);
+    for (int step = 0; step < nsteps; step++) {
+        step_prefix<NT>(insts, ninst, step, pref, wsum);
+        const unsigned total = (unsigned)pref[ninst];
+        const unsigned lo_item = (unsigned)((uint64_t)total * grp / ngrp);
+        const unsigned band = (unsigned)((uint64_t)total * (grp + 1) / ngrp) - lo_item;
+        while (ticket < base + band) {
+            unsigned nxt = 0;
+            if (lane == 0) nxt = atomicAdd(&ctl->next[grp].v, 1u);  // drawn now, used after the item
+            const int item = (int)(lo_item + (ticket - base));
+            const int inst = __builtin_amdgcn_readfirstlane(item_instance(pref, ninst, item));
+            const Inst I = insts[inst];
+            const int local = item - pref[inst], g = I.g0 + step;
+            const int n = I.n, ncell_items = g <= n ? n - g + 1 : 0;
+            if (local < ncell_items) {
+                GroupCounters c = span_group(I, S, E, spec, local, local + g, G[wave], T);
+                flush_counters(I, c, local, lane);
+            } else {
+                ext_column(I, S, n - g + 1, nullptr, T);
+            }
+            ticket = __builtin_amdgcn_readfirstlane(nxt);
         }
         base += band;
         if (!grid_barrier(ctl, spin_cap, &s_flag)) return;
@@ -1651,20 +1727,34 @@ hipError_t launch_batch_init(const Inst* insts_dev, int ninst, BatchCtl* ctl, hi
     return hipGetLastError();
 }
 
-// threads per block: 64 (one wave per layer-pair item), 256 or 512 (4 or 8 waves share an item)
-hipError_t persistent_occupancy(int threads, int* blocks_per_cu) {
+// Schedule of the persistent launch: threads per workgroup and waves per work item.  64 threads:
+// one wave per item; 256 or 512 threads with item_waves = threads / 64: the waves share each
+// item; 256 threads with item_waves = 1: every wave on its own items.
+bool persistent_schedule_valid(int threads, int item_waves) {
+    return (threads == 64 && item_waves == 1) || (threads == 256 && (item_waves == 4 || item_waves == 1)) ||
+           (threads == 512 && item_waves == 8);
+}
+
+hipError_t persistent_occupancy(int threads, int item_waves, int* blocks_per_cu) {
+    if (!persistent_schedule_valid(threads, item_waves)) return hipErrorInvalidValue;
     if (threads == 64) return hipOccupancyMaxActiveBlocksPerMultiprocessor(blocks_per_cu, k_persistent<64>, 64, 0);
     if (threads == 512) return hipOccupancyMaxActiveBlocksPerMultiprocessor(blocks_per_cu, k_persistent<512>, 512, 0);
+    if (item_waves == 1)
+        return hipOccupancyMaxActiveBlocksPerMultiprocessor(blocks_per_cu, k_persistent_waves<256>, 256, 0);
     return hipOccupancyMaxActiveBlocksPerMultiprocessor(blocks_per_cu, k_persistent<256>, 256, 0);
 }
 
 hipError_t launch_persistent(const Inst* insts_dev, int ninst, int nsteps, const EnergyTables* E,
-                             const int32_t* spec, BatchCtl* ctl, int grid, int threads, unsigned spin_cap,
-                             hipStream_t st) {
+                             const int32_t* spec, BatchCtl* ctl, int grid, int threads, int item_waves,
+                             unsigned spin_cap, hipStream_t st) {
+    if (!persistent_schedule_valid(threads, item_waves)) return hipErrorInvalidValue;
     if (threads == 64)
         hipLaunchKernelGGL(k_persistent<64>, dim3(grid), dim3(64), 0, st, insts_dev, ninst, nsteps, E, spec, ctl, spin_cap);
     else if (threads == 512)
         hipLaunchKernelGGL(k_persistent<512>, dim3(grid), dim3(512), 0, st, insts_dev, ninst, nsteps, E, spec, ctl, spin_cap);
+    else if (item_waves == 1)
+        hipLaunchKernelGGL(k_persistent_waves<256>, dim3(grid), dim3(256), 0, st, insts_dev, ninst, nsteps, E, spec,
+                           ctl, spin_cap);
     else
         hipLaunchKernelGGL(k_persistent<256>, dim3(grid), dim3(256), 0, st, insts_dev, ninst, nsteps, E, spec, ctl, spin_cap);
     return hipGetLastError();

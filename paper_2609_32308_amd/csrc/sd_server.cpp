@@ -112,7 +112,8 @@ struct sd_server {
     char* aux_dev = nullptr;  // instance descriptors + barrier state
     void* staging = nullptr;
     size_t staging_bytes = 0;
-    int grid = 0, threads = 256;
+    int grid = 0, threads = 256, item_waves = 4;
+    int tuned = 0;  // 1: the schedule was fixed by the caller or settled by the context's tuner
 
     std::mutex mu;
     std::condition_variable cv, cv_done;
@@ -253,7 +254,8 @@ sd_status round_once(sd_server* S) {
     if (e == hipSuccess) e = launch_batch_init(insts, n, ctl, st);
     if (e == hipSuccess)
         e = launch_persistent(insts, n, S->cfg.steps_per_round, (const EnergyTables*)S->ctx->E_dev,
-                              (const int32_t*)S->ctx->spec_dev, ctl, S->grid, S->threads, 1u << 22, st);
+                              (const int32_t*)S->ctx->spec_dev, ctl, S->grid, S->threads, S->item_waves, 1u << 22,
+                              st);
     BatchCtl h;
     if (e == hipSuccess) e = hipMemcpyAsync(&h, ctl, sizeof(h), hipMemcpyDeviceToHost, st);
     if (e == hipSuccess) e = hipStreamSynchronize(st);
@@ -344,6 +346,8 @@ sd_status round_once(sd_server* S) {
                 r.graph_captured = 0;
                 r.sched_threads = S->threads;
                 r.sched_grid = S->grid;
+                r.sched_item_waves = S->item_waves;
+                r.sched_tuned = S->tuned;
                 r.t_fill_s = a.rq.t_admit > 0 ? now_s() - a.rq.t_admit : 0.0;
                 r.t_total_s = now_s() - a.rq.t_submit;
                 r.cand_slots = a.L.cand_slots;
@@ -406,20 +410,31 @@ extern "C" sd_status sd_server_start(sd_context* ctx, const sd_codon_table* tabl
         return fail(SD_E_NOMEM, "server pool allocation");
     }
     S->pool.init(cfg->pool_bytes);
-    int per_cu = 0;
-    e = persistent_occupancy(256, &per_cu);
-    if (e != hipSuccess || per_cu <= 0) {
-        hipFree(S->pool_dev);
-        hipFree(S->aux_dev);
-        delete S;
-        return hip_fail(e, "occupancy query");
-    }
-    if (ctx->opt.batch_threads > 0) {  // fixed by the caller (validated at context creation)
+    // the schedule: fixed by the caller (validated at context creation), else the one the context's
+    // tuner settled on for batches of >= 12 members, else 256 threads with four waves per item at
+    // full residency
+    if (ctx->opt.batch_threads > 0) {
         S->threads = ctx->opt.batch_threads;
         S->grid = ctx->opt.batch_per_cu * ctx->num_cu;
+        S->item_waves = ctx->opt.batch_item_waves ? ctx->opt.batch_item_waves : ctx->opt.batch_threads / 64;
+        S->tuned = 1;
+    } else if (ctx->batch_sched.grid > 0) {
+        S->threads = ctx->batch_sched.threads;
+        S->grid = ctx->batch_sched.grid;
+        S->item_waves = ctx->batch_sched.item_waves;
+        S->tuned = 1;
     } else {
-        S->threads = ctx->batch_grid > 0 ? ctx->batch_threads : 256;
-        S->grid = ctx->batch_grid > 0 ? ctx->batch_grid : per_cu * ctx->num_cu;
+        int per_cu = 0;
+        e = persistent_occupancy(256, 4, &per_cu);
+        if (e != hipSuccess || per_cu <= 0) {
+            hipFree(S->pool_dev);
+            hipFree(S->aux_dev);
+            delete S;
+            return hip_fail(e, "occupancy query");
+        }
+        S->threads = 256;
+        S->item_waves = 4;
+        S->grid = per_cu * ctx->num_cu;
     }
     S->loop = std::thread(server_main, S);
     *out = S;

@@ -55,7 +55,8 @@ def persistent(sd, rs):
         assert r.path == sd.PATH_PERSISTENT and r.graph_captured == 1 and r.cand_overflow == 0, \
             (r.path, r.graph_captured, r.cand_overflow)
         assert r.n_span_launches == 0
-        assert r.sched_threads in (64, 256, 512) and r.sched_grid > 0, (r.sched_threads, r.sched_grid)
+        assert (r.sched_threads, r.sched_item_waves) in ((64, 1), (256, 4), (256, 1), (512, 8)) and r.sched_grid > 0, \
+            (r.sched_threads, r.sched_item_waves, r.sched_grid)
 
 
 @functools.lru_cache(maxsize=None)
@@ -95,7 +96,7 @@ def test_batch_with_duplicates_and_single(sd, ctx, gt, gp):
 def test_batch_rejects_bad_member(sd, ctx, gt, gp):
     with pytest.raises(sd.SDError) as e:
         ctx.design_batch(["MKV", "MKB"], [0.0, 0.0], gt, gp)
-    assert e.value.code == -2
+    assert e.value.code == -2  # SD_E_PROTEIN
 
 
 def test_batch256_members_vs_golden(sd, ctx, gt, gp):
@@ -112,34 +113,37 @@ def test_batch256_members_vs_golden(sd, ctx, gt, gp):
         assert r.n_candidates == d["n_candidates"] and r.n_visits == d["visits_sparse"]
 
 
-@pytest.mark.parametrize("threads,per_cu", [(64, 2), (256, 1), (512, 1)])
-def test_fixed_schedules_equal_plain(sd, gt, gp, threads, per_cu):
-    # every persistent schedule the caller can fix (workgroup size x workgroups per CU) gives the
-    # plain results, whichever one the autotuner would have picked
+@pytest.mark.parametrize("threads,per_cu,item_waves", [(64, 2, 0), (256, 1, 0), (512, 1, 0), (256, 3, 1), (256, 1, 1)])
+def test_fixed_schedules_equal_plain(sd, gt, gp, threads, per_cu, item_waves):
+    # every persistent schedule the caller can fix (workgroup size x workgroups per CU x waves per
+    # work item) gives the plain results, whichever one the autotuner would have picked
     lens = [8, 33, 57, 21, 70]
     prots = [S.protein(A, 800 + i) for i, A in enumerate(lens)]
     lams = [0.0, 4.0, 0.0, 4.0, 2.0]
-    c = sd.Context(0, batch_threads=threads, batch_per_cu=per_cu)
-    say("schedule", threads, per_cu)
+    c = sd.Context(0, batch_threads=threads, batch_per_cu=per_cu, batch_item_waves=item_waves)
+    say("schedule", threads, per_cu, item_waves)
     rb = c.design_batch(prots, lams, gt, gp)
     persistent(sd, rb)
     for r in rb:  # the launch ran under the fixed schedule
         assert r.sched_threads == threads and r.sched_grid % per_cu == 0, (r.sched_threads, r.sched_grid)
+        assert r.sched_item_waves == (item_waves or threads // 64)
     for p, lam, r in zip(prots, lams, rb):
         assert key(r) == key(c.design(p, gt, gp, lam))
     c.close()
 
 
-@pytest.mark.parametrize("threads,per_cu", [(0, 0), (64, 1), (64, 2), (256, 1), (256, 2), (512, 1)])
-def test_member_tables_equal_dense_oracle(sd, gt, gp, params_path, weights, threads, per_cu):
+@pytest.mark.parametrize("threads,per_cu,item_waves",
+                         [(0, 0, 0), (64, 1, 0), (64, 2, 0), (256, 1, 0), (256, 2, 0), (512, 1, 0), (256, 1, 1),
+                          (256, 3, 1)])
+def test_member_tables_equal_dense_oracle(sd, gt, gp, params_path, weights, threads, per_cu, item_waves):
     # every typed value, branch value and multiloop value of each member, filled by the
     # persistent kernel under this schedule, equals the dense oracle's (Theorem 1); the members
     # span several layer-pair tiles and a ragged tail, both lambdas, in one launch
     prots = [S.protein(20, 1), S.protein(33, 2), S.protein(41, 3), S.protein(27, 4)]
     lams = [0.0, 4.0, 4.0, 0.0]
-    c = sd.Context(0, batch_threads=threads, batch_per_cu=per_cu)
+    c = sd.Context(0, batch_threads=threads, batch_per_cu=per_cu, batch_item_waves=item_waves)
     for m in range(len(prots)):
-        say("batch tables", threads, per_cu, "member", m)
+        say("batch tables", threads, per_cu, item_waves, "member", m)
         rb, T = c.design_batch_tables(prots, lams, gt, gp, m)
         persistent(sd, rb)
         d = oracle_tables(prots[m], lams[m], params_path, tuple(float(x) for x in weights))
@@ -176,3 +180,38 @@ def test_envelope_invalid_ranges(ctx, sd, gt, gp):
     with pytest.raises(sd.SDError) as e:
         ctx.lambda_envelope("MKV*", 0.0, 1.0, gt, gp, max_designs=1)
     assert e.value.code == -1
+
+
+@pytest.mark.parametrize("threads,per_cu,item_waves", [(512, 1, 1), (0, 0, 1), (64, 1, 4), (256, 1, 2)])
+def test_invalid_item_waves_rejected(sd, threads, per_cu, item_waves):
+    with pytest.raises(sd.SDError) as e:
+        sd.Context(0, batch_threads=threads, batch_per_cu=per_cu, batch_item_waves=item_waves)
+    assert e.value.code == -1  # SD_E_ARG
+
+
+def test_autotuner_explores_then_settles(sd, gt, gp):
+    # a new size class runs one candidate schedule per call, then every later call runs the
+    # fastest; the designs are the same under every schedule
+    lens = [30 + 7 * i for i in range(16)]
+    prots = [S.protein(A, 900 + i) for i, A in enumerate(lens)]
+    lams = [0.0 if i % 2 == 0 else 4.0 for i in range(len(prots))]
+    c = sd.Context(0)
+    seen, ref = [], None
+    for k in range(10):
+        say("tuning call", k)
+        rb = c.design_batch(prots, lams, gt, gp)
+        persistent(sd, rb)
+        keys = [key(r) for r in rb]
+        ref = ref or keys
+        assert keys == ref
+        sched = {(r.sched_threads, r.sched_grid, r.sched_item_waves, r.sched_tuned) for r in rb}
+        assert len(sched) == 1
+        seen.append(sched.pop())
+        if seen[-1][3] == 1:
+            break
+    explored = [x[:3] for x in seen if x[3] == 0]
+    assert len(explored) >= 2 and len(set(explored)) == len(explored), seen
+    assert seen[-1][3] == 1 and seen[-1][:3] in explored, seen
+    rb = c.design_batch(prots, lams, gt, gp)
+    assert {(r.sched_threads, r.sched_grid, r.sched_item_waves, r.sched_tuned) for r in rb} == {seen[-1]}
+    c.close()
