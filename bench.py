@@ -446,10 +446,11 @@ def main():
     for i in range(args.warmup):
         last = run_step(ctx, items, table, params, batch, motifs)
         progress(f"warmup step {i + 1}/{args.warmup}")
-    # the batched schedule's autotuner explores one candidate per call of a new size class: the
-    # timed steps start only once it has settled (untimed extra calls if the warmup was shorter)
+    # the autotuners (batched schedule; plain span tiles per span band) explore one candidate per
+    # call of a new size class: the timed steps start only once they have settled (untimed extra
+    # calls if the warmup was shorter)
     extra = 0
-    while batch and (last is None or not all(r.sched_tuned for r in last)) and extra < 16:
+    while (last is None or not all(r.sched_tuned for r in last)) and extra < 16:
         last = run_step(ctx, items, table, params, batch, motifs)
         extra += 1
         progress(f"untimed tuning step {extra}")
@@ -487,13 +488,13 @@ def main():
         "params_sha256": params.sha256,
     }
     ctx.close()
+    line["untimed_tuning_steps"] = extra
     if batch:
         line["batch"] = {"paths": sorted({r.path for r in results[-1]}),
                          "graph_captured": all(r.graph_captured == 1 for r in results[-1]),
                          "launch_s": sum(r.t_span_kernels_s for r in results[-1]),
                          "schedule": sorted({(r.sched_threads, r.sched_grid, r.sched_item_waves) for r in results[-1]}),
-                         "schedule_settled": all(r.sched_tuned == 1 for s_ in results for r in s_),
-                         "untimed_tuning_steps": extra}
+                         "schedule_settled": all(r.sched_tuned == 1 for s_ in results for r in s_)}
         if not args.no_side_legs:
             line.update(side_legs(sd, items, table, params, results[-1], elapsed / args.steps))
     if motifs:

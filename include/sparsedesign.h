@@ -67,9 +67,11 @@ typedef struct sd_options {
                               duration and count; an event between two launches adds a gap,
                               so k > 1 keeps the fill close to an untimed one              */
     int span_threads;      /* workgroup size of the plain-mode span step: 0 (library choice per
-                              span: 1024 while the span has at most one layer pair per CU, 512
-                              up to 12 pairs per CU, else 256), 64, 256, 512 or 1024;
-                              anything else gives SD_E_ARG at create */
+                              span, autotuned per span band; see span_item_waves), 64, 256, 512
+                              or 1024 for every span; anything else gives SD_E_ARG at create */
+    int span_item_waves;   /* with span_threads set: 0 (the workgroup's waves share each layer
+                              pair) or 1 with span_threads 256 (every wave on its own pair, four
+                              pairs per workgroup); must be 0 when span_threads is 0          */
     int batch_threads;     /* persistent (batched / served) launch: threads per workgroup, 64,
                               256 or 512, with batch_per_cu workgroups per CU; both 0: autotuned */
     int batch_per_cu;
@@ -123,7 +125,8 @@ typedef struct sd_result {
     int32_t sched_item_waves;/* ... and its waves per work item (0 for the plain paths)        */
     int32_t sched_tuned;     /* 1 if that schedule was fixed by the caller or is the autotuner's
                                 settled choice for the batch's size class; 0 while the tuner
-                                still explores (it runs one candidate per call)                */
+                                still explores (it runs one candidate per call).  Plain results:
+                                the same for the per-span-band tile choice of the span step   */
 } sd_result;
 
 /* sd_result.path: the fill behind a result.  Batched and served results come from the persistent

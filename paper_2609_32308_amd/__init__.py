@@ -52,7 +52,8 @@ class SDError(RuntimeError):
 
 class Options(C.Structure):
     _fields_ = [("retain_all", C.c_int), ("capacity_override", C.c_int), ("kernel_timing", C.c_int),
-                ("span_threads", C.c_int), ("batch_threads", C.c_int), ("batch_per_cu", C.c_int),
+                ("span_threads", C.c_int), ("span_item_waves", C.c_int), ("batch_threads", C.c_int),
+                ("batch_per_cu", C.c_int),
                 ("batch_item_waves", C.c_int), ("span_check", C.c_int)]
 
 
@@ -244,9 +245,11 @@ def _convert(r: _Result) -> Result:
 class Context:
     def __init__(self, device: int = 0, retain_all: bool = False, capacity_override: int = 0,
                  kernel_timing: int = 0, span_threads: int = 0, batch_threads: int = 0,
-                 batch_per_cu: int = 0, span_check: int = 0, batch_item_waves: int = 0):
+                 batch_per_cu: int = 0, span_check: int = 0, batch_item_waves: int = 0,
+                 span_item_waves: int = 0):
         opt = Options(int(retain_all), int(capacity_override), int(kernel_timing), int(span_threads),
-                      int(batch_threads), int(batch_per_cu), int(batch_item_waves), int(span_check))
+                      int(span_item_waves), int(batch_threads), int(batch_per_cu), int(batch_item_waves),
+                      int(span_check))
         h = C.c_void_p()
         _check(lib().sd_context_create(device, C.byref(opt), C.byref(h)), "sd_context_create")
         self.h = h

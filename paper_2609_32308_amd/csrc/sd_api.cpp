@@ -152,6 +152,10 @@ sd_status context_create(int device, const sd_options* opt, bool ext, void* ext_
         delete c;
         return fail(SD_E_ARG, "span_threads must be 0, 64, 256, 512 or 1024");
     }
+    if (c->opt.span_item_waves != 0 && !(c->opt.span_item_waves == 1 && c->opt.span_threads == 256)) {
+        delete c;
+        return fail(SD_E_ARG, "span_item_waves must be 0, or 1 with span_threads 256");
+    }
     if (c->opt.kernel_timing < 0) {
         delete c;
         return fail(SD_E_ARG, "kernel_timing must be >= 0");
@@ -427,12 +431,12 @@ hipError_t read_stats(const Inst& I, hipStream_t st, unsigned long long out[4]) 
     return hipSuccess;
 }
 
-// Workgroup size of the span step for a span with `pairs` layer pairs.  Eight or sixteen waves
-// per pair shorten each pair's critical path (more of its typed-value job parts run at once) but
-// leave fewer workgroups resident per CU (three of eight waves, against four of four), so eight
-// pay only up to about SPAN_WIDE_PER_CU pairs per CU (of 2, 3, 4, 6, 12 and 64, 12 was fastest
-// on a 1,976-aa design and 4 to 64 tied on a 300-aa one), and sixteen while there is at most one
-// pair per CU.
+// Tile of the span step for a span with `pairs` layer pairs when no tuning data decide it.  Eight
+// or sixteen waves per pair shorten each pair's critical path (more of its typed-value job parts
+// run at once) but leave fewer workgroups resident per CU (three of eight waves, against four of
+// four), so eight pay only up to about SPAN_WIDE_PER_CU pairs per CU (of 2, 3, 4, 6, 12 and 64,
+// 12 was fastest on a 1,976-aa design and 4 to 64 tied on a 300-aa one), and sixteen while there
+// is at most one pair per CU.
 #ifndef SPAN_WIDE_PER_CU
 #define SPAN_WIDE_PER_CU 12
 #endif
@@ -442,11 +446,25 @@ hipError_t read_stats(const Inst& I, hipStream_t st, unsigned long long out[4]) 
 sd_status run_plain_on(sd_context* c, const Lattice& L, Inst& I, const EnergyTables* Et, const int32_t* spec,
                        int kernel_timing, int64_t* overflow_span);
 
-int span_threads_for(const sd_context* c, int pairs) {
-    if (c->opt.span_threads) return c->opt.span_threads;
-    if (pairs <= SPAN_XWIDE_PER_CU * c->num_cu) return 1024;
-    return pairs <= SPAN_WIDE_PER_CU * c->num_cu ? 512 : 256;
+namespace {
+using SpanTile = sd_context::SpanTile;
+// candidate tiles of the span-band tuner, in the order the exploring designs run them
+constexpr int kSpanCandThreads[sd_context::kSpanCands] = {1024, 512, 256, 256};
+constexpr int kSpanCandWaves[sd_context::kSpanCands] = {16, 8, 4, 1};
+
+SpanTile span_tile_default(const sd_context* c, int pairs) {
+    SpanTile t;
+    t.threads = pairs <= SPAN_XWIDE_PER_CU * c->num_cu ? 1024 : pairs <= SPAN_WIDE_PER_CU * c->num_cu ? 512 : 256;
+    t.item_waves = t.threads / 64;
+    return t;
 }
+int span_band(int pairs) {
+    int b = 0;
+    while ((2 << b) <= pairs && b + 1 < sd_context::kSpanBands) b++;
+    return b;  // floor log2(pairs), capped
+}
+int span_class(const Lattice& L) { return (int)std::floor(std::log2(std::max(1, L.n))); }
+}  // namespace
 
 // Plain mode: one span-step launch per span length.  Returns the overflow span (0 if none).
 sd_status run_plain(sd_context* c, const Lattice& L, Inst& I, int64_t* overflow_span) {
@@ -459,7 +477,37 @@ sd_status run_plain_on(sd_context* c, const Lattice& L, Inst& I, const EnergyTab
                        int kernel_timing, int64_t* overflow_span) {
     hipStream_t st = c->stream;
     hipError_t e = launch_init(I, st);
+    // the span tiles: fixed by the caller, else the tuner's per-band choice for this length class;
+    // while the class explores, this design runs the next candidate tile for every span, with
+    // every launch timed
+    const bool fixed = c->opt.span_threads != 0 || L.generic || c->opt.span_check != 0;
+    sd_context::SpanTune* tune = fixed ? nullptr : &c->span_tune[span_class(L)];
+    const bool explore = tune && !tune->settled;
+    const int cand = explore ? tune->next : -1;
+    c->last_span_settled = !explore;
+    auto tile_for = [&](int pairs) {
+        SpanTile t;
+        if (c->opt.span_threads) {
+            t.threads = c->opt.span_threads;
+            t.item_waves = c->opt.span_item_waves ? c->opt.span_item_waves : c->opt.span_threads / 64;
+        } else if (explore) {
+            t.threads = kSpanCandThreads[cand];
+            t.item_waves = kSpanCandWaves[cand];
+        } else if (tune && tune->tuned[span_band(pairs)]) {
+            t = tune->best[span_band(pairs)];
+        } else {
+            t = span_tile_default(c, pairs);
+        }
+        return t;
+    };
     const bool timing = kernel_timing != 0;
+    while (explore && (int)c->bev.size() < sd_context::kSpanBands + 1 && e == hipSuccess) {
+        hipEvent_t ev;
+        e = hipEventCreate(&ev);
+        if (e == hipSuccess) c->bev.push_back(ev);
+    }
+    int band_now = -1, nbev = 0;
+    int bev_band[sd_context::kSpanBands + 1], bev_spans[sd_context::kSpanBands + 1];
     if (timing && (int)c->tev.size() < 2 * L.n) {
         while ((int)c->tev.size() < 2 * L.n && e == hipSuccess) {
             hipEvent_t ev;
@@ -467,7 +515,7 @@ sd_status run_plain_on(sd_context* c, const Lattice& L, Inst& I, const EnergyTab
             if (e == hipSuccess) c->tev.push_back(ev);
         }
     }
-    const int every = timing ? kernel_timing : 1;
+    const int every = kernel_timing > 0 ? kernel_timing : 1;
     // span_check debug mode (codon trie only): snapshot of the committed candidate counts and the
     // per-layer counters, restored before every second run of a step
     const bool check = c->opt.span_check != 0 && !L.generic;
@@ -490,6 +538,17 @@ sd_status run_plain_on(sd_context* c, const Lattice& L, Inst& I, const EnergyTab
     }
     for (int g = 1; g <= L.n && e == hipSuccess; g++) {
         const bool timed = timing && (g - 1) % every == 0;
+        if (explore && e == hipSuccess) {
+            const int b = span_band(L.n - g + 1);  // non-increasing in g
+            if (b != band_now && nbev < sd_context::kSpanBands) {
+                e = hipEventRecord(c->bev[nbev], st);
+                bev_band[nbev] = b;
+                bev_spans[nbev] = 0;
+                nbev++;
+                band_now = b;
+            }
+            bev_spans[nbev - 1]++;
+        }
         const int ext = g >= 2 ? L.n - g + 1 : -1;
         if (check) {
             e = hipMemcpyAsync(snap_cnt, I.ccnt(), cnt_b, hipMemcpyDeviceToDevice, st);
@@ -497,11 +556,11 @@ sd_status run_plain_on(sd_context* c, const Lattice& L, Inst& I, const EnergyTab
             if (e == hipSuccess) e = hipMemcpyAsync(snap_fea, I.feasible(), ctr_b, hipMemcpyDeviceToDevice, st);
         }
         if (timed && e == hipSuccess) e = hipEventRecord(c->tev[2 * (g - 1)], st);
-        const int threads = span_threads_for(c, L.n - g + 1);
+        const SpanTile tile = tile_for(L.n - g + 1);
         if (e == hipSuccess && L.generic)
             e = launch_span_gen(I, Et, spec, g, ext, c->num_cu, st);
         else if (e == hipSuccess)
-            e = launch_span(I, Et, spec, g, ext, threads, st);
+            e = launch_span(I, Et, spec, g, ext, tile.threads, tile.item_waves, st);
         if (timed && e == hipSuccess) e = hipEventRecord(c->tev[2 * (g - 1) + 1], st);
         if (check && e == hipSuccess) {
             // the same step again with another workgroup size from the same inputs
@@ -510,17 +569,23 @@ sd_status run_plain_on(sd_context* c, const Lattice& L, Inst& I, const EnergyTab
             if (e == hipSuccess && c->opt.span_check != 2)
                 e = hipMemcpyAsync(I.visits(), snap_vis, ctr_b, hipMemcpyDeviceToDevice, st);
             if (e == hipSuccess) e = hipMemcpyAsync(I.feasible(), snap_fea, ctr_b, hipMemcpyDeviceToDevice, st);
-            if (e == hipSuccess) e = launch_span(I, Et, spec, g, ext, threads == 256 ? 1024 : 256, st);
+            // another tile: sixteen shared waves, or independent waves after sixteen
+            SpanTile other;
+            other.threads = tile.threads == 1024 ? 256 : 1024;
+            other.item_waves = tile.threads == 1024 ? 1 : 16;
+            if (e == hipSuccess) e = launch_span(I, Et, spec, g, ext, other.threads, other.item_waves, st);
             if (e == hipSuccess) e = launch_checksum(I, g, dsum + 1, st);
             unsigned long long h[2] = {0, 0};
             if (e == hipSuccess) e = hipMemcpyAsync(h, dsum, sizeof(h), hipMemcpyDeviceToHost, st);
             if (e == hipSuccess) e = hipStreamSynchronize(st);
             if (e == hipSuccess && h[0] != h[1])
                 return fail(SD_E_INTERNAL, "span check: span " + std::to_string(g) + " wrote different values when run "
-                                           "again with " + std::to_string(threads == 256 ? 1024 : 256) +
-                                           " threads per workgroup instead of " + std::to_string(threads));
+                                           "again with " + std::to_string(other.threads) + " threads and " +
+                                           std::to_string(other.item_waves) + " waves per pair instead of " +
+                                           std::to_string(tile.threads) + " and " + std::to_string(tile.item_waves));
         }
     }
+    if (explore && nbev > 0 && e == hipSuccess) e = hipEventRecord(c->bev[nbev], st);
     if (e == hipSuccess) e = launch_ext(I, Et, 0, st);
     unsigned long long stats[4];
     if (e == hipSuccess) e = read_stats(I, st, stats);
@@ -529,7 +594,7 @@ sd_status run_plain_on(sd_context* c, const Lattice& L, Inst& I, const EnergyTab
     c->last_kernel_ms = 0.0;
     c->last_launches = L.n;
     c->last_timed = 0;
-    if (timing)
+    if (kernel_timing)
         for (int g = 1; g <= L.n; g += every) {
             float ms = 0.f;
             e = hipEventElapsedTime(&ms, c->tev[2 * (g - 1)], c->tev[2 * (g - 1) + 1]);
@@ -537,6 +602,41 @@ sd_status run_plain_on(sd_context* c, const Lattice& L, Inst& I, const EnergyTab
             c->last_kernel_ms += ms;
             c->last_timed++;
         }
+    if (explore) {
+        // time per span of each band under this candidate; after the last candidate, each band
+        // keeps its default tile unless another candidate was faster by more than 3 %
+        for (int i = 0; i < nbev; i++) {
+            float ms = 0.f;
+            e = hipEventElapsedTime(&ms, c->bev[i], c->bev[i + 1]);
+            if (e != hipSuccess) return hip_fail(e, "span tuning timing");
+            tune->us[cand][bev_band[i]] += 1e3 * ms;
+            tune->cnt[cand][bev_band[i]] += bev_spans[i];
+        }
+        if (++tune->next == sd_context::kSpanCands) {
+            for (int b = 0; b < sd_context::kSpanBands; b++) {
+                const SpanTile d = span_tile_default(c, (1 << b) + (1 << b) / 2);  // the band's middle
+                int dk = -1, best = -1;
+                double best_us = 0;
+                for (int k = 0; k < sd_context::kSpanCands; k++) {
+                    if (kSpanCandThreads[k] == d.threads && kSpanCandWaves[k] == d.item_waves) dk = k;
+                    if (!tune->cnt[k][b]) continue;
+                    const double m = tune->us[k][b] / tune->cnt[k][b];
+                    if (best < 0 || m < best_us) {
+                        best = k;
+                        best_us = m;
+                    }
+                }
+                if (best < 0) continue;
+                if (dk >= 0 && tune->cnt[dk][b] && best != dk &&
+                    best_us > 0.97 * (tune->us[dk][b] / tune->cnt[dk][b]))
+                    best = dk;
+                tune->best[b].threads = kSpanCandThreads[best];
+                tune->best[b].item_waves = kSpanCandWaves[best];
+                tune->tuned[b] = true;
+            }
+            tune->settled = true;
+        }
+    }
     c->last_visits = (int64_t)stats[0];
     c->last_feasible = (int64_t)stats[3];
     return SD_OK;
@@ -822,6 +922,7 @@ sd_status design_plain(sd_context* c, const char* protein, const sd_codon_table*
     out->t_span_kernels_s = c->last_kernel_ms * 1e-3;
     out->n_span_launches = c->last_launches;
     out->n_timed_launches = c->last_timed;
+    out->sched_tuned = c->last_span_settled ? 1 : 0;
     out->cand_slots = L.cand_slots;
     out->cand_slots_first = slots_first;
     out->cand_overflow = overflowed;

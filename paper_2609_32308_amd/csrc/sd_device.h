@@ -53,7 +53,27 @@ struct sd_context {
     double last_kernel_ms = 0.0;
     int64_t last_launches = 0;
     int64_t last_timed = 0;
-    std::vector<hipEvent_t> tev;  // kernel_timing: event pairs around span launches
+    std::vector<hipEvent_t> tev;  // kernel_timing / span tuning: event pairs around span launches
+    // Per-span-band tile of the plain span step (layer pairs of the span -> band floor log2),
+    // tuned per length class (floor log2 of the layer count): the first designs of a class run
+    // one candidate tile each for every span, timed per band between events at the band
+    // boundaries (spans run in order of decreasing pairs, so a band is a run of back-to-back
+    // launches); then each band keeps the default tile unless another was faster by a margin.
+    struct SpanTile {
+        int threads = 256, item_waves = 4;
+    };
+    static constexpr int kSpanBands = 16, kSpanCands = 4;
+    struct SpanTune {
+        int next = 0;
+        bool settled = false;
+        double us[kSpanCands][kSpanBands] = {};
+        int cnt[kSpanCands][kSpanBands] = {};
+        SpanTile best[kSpanBands];
+        bool tuned[kSpanBands] = {};
+    };
+    std::map<int, SpanTune> span_tune;
+    std::vector<hipEvent_t> bev;  // span tuning: events at band boundaries
+    bool last_span_settled = true;  // the last plain design's tiles were settled or fixed
     // span_check debug mode: snapshots of the committed counts and counters, digests
     char* dbg = nullptr;
     size_t dbg_bytes = 0;
@@ -70,8 +90,10 @@ hipError_t read_stats(const Inst& I, hipStream_t st, unsigned long long out[4]);
 void stage_inputs(const Lattice& L, const Inst& I, const char* devA, char* image);
 hipError_t upload_pair_order();
 hipError_t launch_init(const Inst& I, hipStream_t st);
+// one span step: threads per workgroup with item_waves = threads / 64 (the waves share each layer
+// pair), or 256 threads with item_waves = 1 (every wave on its own pair)
 hipError_t launch_span(const Inst& I, const EnergyTables* E, const int32_t* spec, int g,
-                       int ext_layer, int threads, hipStream_t st);
+                       int ext_layer, int threads, int item_waves, hipStream_t st);
 hipError_t launch_ext(const Inst& I, const EnergyTables* E, int L, hipStream_t st);
 // canonical traceback of one design (one wavefront) / of every design of a device Inst array
 hipError_t launch_trace(const Inst& I, const EnergyTables* E, const int32_t* spec, hipStream_t st);

@@ -26,6 +26,8 @@
 #include <stddef.h>
 #include <string.h>
 
+#include <type_traits>
+
 #include "sd_devutil.h"
 #include "sd_internal.h"
 
@@ -269,12 +271,12 @@ __device__ __forceinline__ int64_t PRt(const IT& I, int q, int l2) { return I.P(
 // left segment explicit (paths of l1 edges out of a1), right segment separable
 template <class IT>
 __device__ int64_t rsep_pair(const IT& I, const SmallE& S, int a1, int64_t Uab, int l1, int l2,
-                             int cl, int dl, int q, const int64_t* __restrict__ ob, int lane) {
+                             int cl, int dl, int q, const int64_t* __restrict__ ob, int first, int step) {
     const int X = mm_class(l1, l2), g2 = dl - cl;
     const int64_t base = Uab + fx(interior_base(S, l1, l2), I.shift) + PRt(I, q, l2);
     const int f0 = I.fwd_off()[a1 * 4 + l1 - 1], f1 = I.fwd_off()[a1 * 4 + l1];
     int64_t best = kINF;
-    for (int i = f0 + lane; i < f1; i += 64) {
+    for (int i = f0 + first; i < f1; i += step) {
         const int fm = I.fwd_meta()[i], c = fm >> 4, xi = (fm >> 2) & 3, xk = fm & 3;
         const int64_t o = ob[X * 4 + xi], idl = I.IDL()[ring_idx(c, g2, X, xk)];
         if (o < kINF && idl < kINF) best = mn(best, base + I.fwd_cost()[i] + o + idl);
@@ -285,12 +287,12 @@ __device__ int64_t rsep_pair(const IT& I, const SmallE& S, int a1, int64_t Uab, 
 // left segment separable, right segment explicit (paths of l2 edges into b1)
 template <class IT>
 __device__ int64_t lsep_pair(const IT& I, const SmallE& S, int b1, int64_t Uab, int l1, int l2,
-                             int cl, int dl, int p, const int64_t* __restrict__ oa, int lane) {
+                             int cl, int dl, int p, const int64_t* __restrict__ oa, int first, int step) {
     const int X = mm_class(l1, l2), g2 = dl - cl;
     const int64_t base = Uab + fx(interior_base(S, l1, l2), I.shift) + PLt(I, p, l1);
     const int r0 = I.bwd_off()[b1 * 4 + l2 - 1], r1 = I.bwd_off()[b1 * 4 + l2];
     int64_t best = kINF;
-    for (int j = r0 + lane; j < r1; j += 64) {
+    for (int j = r0 + first; j < r1; j += step) {
         const int bm = I.bwd_meta()[j], d = bm >> 4, xl = (bm >> 2) & 3, xj = bm & 3;
         const int64_t o = oa[X * 4 + xj], jdl = I.JDL()[ring_idx(d, g2, X, xl)];
         if (o < kINF && jdl < kINF) best = mn(best, base + I.bwd_cost()[j] + o + jdl);
@@ -306,7 +308,7 @@ __device__ __forceinline__ int64_t rs_idx(int state, int span, int l, int lab) {
     return ((int64_t)state * kLMRing + (span & (kLMRing - 1))) * 16 + (l - 1) * 4 + lab;
 }
 
-template <class IT>
+template <bool kSpread, class IT>
 __device__ int64_t one_sided(const IT& I, const SmallE& S, int a1, int b1, int64_t Uab, int p, int q,
                              int cap, int lane, const int64_t* __restrict__ ob,
                              const int64_t* __restrict__ oa) {
@@ -341,11 +343,20 @@ __device__ int64_t one_sided(const IT& I, const SmallE& S, int a1, int b1, int64
             if (ls < kINF && o < kINF) best = mn(best, Uab + I.bwd_cost()[e] + o + ls);
         }
     }
-    // 2x3 with the left side explicit, 3x2 with the right side explicit
-    if (cap >= 5 && !sep_left(p, 2) && sep_right(q, 3))
-        best = mn(best, rsep_pair(I, S, a1, Uab, 2, 3, p + 3, q - 4, q, ob, lane));
-    if (cap >= 5 && sep_left(p, 3) && !sep_right(q, 2))
-        best = mn(best, lsep_pair(I, S, b1, Uab, 3, 2, p + 4, q - 3, p, oa, lane));
+    // 2x3 with the left side explicit, 3x2 with the right side explicit: with kSpread one label
+    // path of the explicit side per lane, else lane 0 (2x3) and lane 1 (3x2) walk them all (the
+    // spread costs the 8- and 16-wave span kernels registers they do not have under their caps)
+    if (kSpread) {
+        if (cap >= 5 && !sep_left(p, 2) && sep_right(q, 3))
+            best = mn(best, rsep_pair(I, S, a1, Uab, 2, 3, p + 3, q - 4, q, ob, lane, 64));
+        if (cap >= 5 && sep_left(p, 3) && !sep_right(q, 2))
+            best = mn(best, lsep_pair(I, S, b1, Uab, 3, 2, p + 4, q - 3, p, oa, lane, 64));
+    } else {
+        if (lane == 0 && cap >= 5 && !sep_left(p, 2) && sep_right(q, 3))
+            best = mn(best, rsep_pair(I, S, a1, Uab, 2, 3, p + 3, q - 4, q, ob, 0, 1));
+        if (lane == 1 && cap >= 5 && sep_left(p, 3) && !sep_right(q, 2))
+            best = mn(best, lsep_pair(I, S, b1, Uab, 3, 2, p + 4, q - 3, p, oa, 0, 1));
+    }
     return best;
 }
 
@@ -432,7 +443,7 @@ __device__ int64_t ml_closure(const IT& I, const SmallE& S, int t, int a1, int64
 //   flattened items are dealt to these parts in blocks of 64;
 //   bulges of >= 3 bases and the multiloop closure: the last part when nparts >= 4, else part 0.
 // The parts of one (cell, type) run on different waves and meet in an LDS minimum.
-template <class IT>
+template <bool kSpread, class IT>
 __device__ int64_t closed_part(const IT& I, const SmallE& S, const EnergyTables* __restrict__ E,
                                const int32_t* __restrict__ spec, int a, int b, int t, int p, int q,
                                int part, int nparts, int64_t mini0, int64_t mini1, int lane, LabPair* lab) {
@@ -476,7 +487,7 @@ __device__ int64_t closed_part(const IT& I, const SmallE& S, const EnergyTables*
                 if (I.in_lab()[eb] != y) continue;
                 const int b1 = I.in_src()[eb];
                 const int64_t Uab = Ua + I.in_U()[eb];
-                v = mn(v, one_sided(I, S, a1, b1, Uab, p, q, cap, lane, I.OB() + (int64_t)(b1 * 6 + t) * 12, oa));
+                v = mn(v, one_sided<kSpread>(I, S, a1, b1, Uab, p, q, cap, lane, I.OB() + (int64_t)(b1 * 6 + t) * 12, oa));
             }
         }
         if (g >= 12) {
@@ -722,7 +733,8 @@ __device__ GroupCounters span_group(const IT& I, const SmallE& S, const EnergyTa
     for (int k = wave; k < njobs; k += nw) {
         const int cmb = G.combo[k / nparts], ci = cmb / 6, t = cmb - 6 * ci;
         const int a = a_lo + ci / wb, b = b_lo + ci % wb;
-        const int64_t v = closed_part(I, S, E, spec, a, b, t, p, q, k % nparts, nparts, mini0, mini1, lane, G.lab[wave]);
+        const int64_t v = closed_part<(NW <= 4)>(I, S, E, spec, a, b, t, p, q, k % nparts, nparts, mini0, mini1, lane,
+                                                  G.lab[wave]);
         if (lane == 0 && v < kINF)
             __hip_atomic_fetch_min(&G.vbuf[ci][t], v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
     }
@@ -813,7 +825,7 @@ __device__ GroupCounters span_group(const IT& I, const SmallE& S, const EnergyTa
 // ---- external column: X(a) for every a of layer L (one workgroup) ------------------------------
 template <class IT, class Team = BlockTeam>
 __device__ void ext_column(const IT& I, const SmallE& S, int L, int64_t* red, Team T = Team()) {
-    const int tid = T.tid(), nt = T.size(), wave = tid >> 6;
+    const int tid = T.tid(), nt = T.size();
     for (int a = I.off()[L]; a < I.off()[L + 1]; a++) {
         int64_t v = kINF;
         if (tid < 4) {
@@ -833,11 +845,16 @@ __device__ void ext_column(const IT& I, const SmallE& S, int L, int64_t* red, Te
                 }
             }
         }
-        v = wave_min(v);
-        if (nt > 64) {  // minimum over the waves
-            if ((tid & 63) == 0) red[wave] = v;
+        if constexpr (std::is_same<Team, WaveTeam>::value) {
+            v = wave_min(v);
+        } else {  // tree over the workgroup (the wave reduction costs the 512-thread span kernel a spill)
+            red[tid] = v;
             T.sync();
-            for (int w = 0; w < nt >> 6; w++) v = mn(v, red[w]);
+            for (int w = nt / 2; w > 0; w >>= 1) {
+                if (tid < w) red[tid] = mn(red[tid], red[tid + w]);
+                T.sync();
+            }
+            v = red[0];
         }
         if (tid == 0) I.X()[a] = norm_inf(v);
         T.sync();
@@ -882,6 +899,32 @@ void k_span(Inst I, const EnergyTables* __restrict__ E, const int32_t* __restric
     // each wave counted its own cells
     const int lane = threadIdx.x & 63;
     flush_counters(I, c, p, lane);
+}
+
+// The span step with every wave on its own layer pair: four pairs per workgroup and one staging of
+// the energy tables, for spans with many more layer pairs than the chip holds workgroups.  Items
+// are the span's layer pairs, then the external column; workgroup x takes the four consecutive
+// items of band xcd_band(x).  No workgroup barrier follows the staging: the waves' items are
+// independent and some waves have none.
+template <int NT>
+__global__ __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(4))) void k_span_waves(
+    Inst I, const EnergyTables* __restrict__ E, const int32_t* __restrict__ spec, int g, int ext_layer, int npairs) {
+    constexpr int NWV = NT / 64;
+    __shared__ SmallE S;
+    __shared__ GroupShared<1> G[NWV];
+    stage_tables(S, E);
+    __syncthreads();
+    const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
+    const int items = npairs + (ext_layer >= 0 ? 1 : 0);
+    const int nblk = (items + NWV - 1) / NWV;
+    const int item = xcd_band(blockIdx.x, nblk) * NWV + wave;
+    const WaveTeam T;
+    if (item < npairs) {
+        GroupCounters c = span_group(I, S, E, spec, item, item + g, G[wave], T);
+        flush_counters(I, c, item, lane);
+    } else if (item == npairs && ext_layer >= 0) {
+        ext_column(I, S, ext_layer, nullptr, T);
+    }
 }
 
 __global__ __launch_bounds__(256) void k_ext(Inst I, const EnergyTables* __restrict__ E, int L) {
@@ -1690,11 +1733,16 @@ hipError_t launch_init(const Inst& I, hipStream_t st) {
 
 // one span step: cells of span g plus the external column of layer ext_layer (or -1)
 hipError_t launch_span(const Inst& I, const EnergyTables* E, const int32_t* spec, int g,
-                       int ext_layer, int threads, hipStream_t st) {
+                       int ext_layer, int threads, int item_waves, hipStream_t st) {
     const int layers = I.n - g + 1;
     const int nblk = layers > 0 ? layers : 0;
     const int total = nblk + (ext_layer >= 0 ? 1 : 0);
     if (total == 0) return hipSuccess;
+    if (item_waves == 1 && threads == 256) {  // every wave on its own pair, four per workgroup
+        hipLaunchKernelGGL(k_span_waves<256>, dim3((total + 3) / 4), dim3(256), 0, st, I, E, spec, g, ext_layer, nblk);
+        return hipGetLastError();
+    }
+    if (item_waves != threads / 64) return hipErrorInvalidValue;
     switch (threads) {
     case 64: hipLaunchKernelGGL(k_span<64>, dim3(total), dim3(64), 0, st, I, E, spec, g, ext_layer, nblk); break;
     case 256: hipLaunchKernelGGL(k_span<256>, dim3(total), dim3(256), 0, st, I, E, spec, g, ext_layer, nblk); break;

@@ -135,6 +135,7 @@ extern "C" sd_status sd_design_noalloc(sd_context* c, const char* protein, const
         out->cand_slots_first = slots_first;
         out->cand_overflow = overflowed;
         out->path = SD_PATH_PLAIN;
+        out->sched_tuned = c->last_span_settled ? 1 : 0;
         return SD_OK;
     } catch (const std::bad_alloc&) {
         return fail(SD_E_NOMEM, "host allocation");

@@ -411,8 +411,9 @@ extern "C" sd_status sd_server_start(sd_context* ctx, const sd_codon_table* tabl
     }
     S->pool.init(cfg->pool_bytes);
     // the schedule: fixed by the caller (validated at context creation), else the one the context's
-    // tuner settled on for batches of >= 12 members, else 256 threads with four waves per item at
-    // full residency
+    // tuner settled on for batches of >= 12 members, else 256 threads with every wave on its own
+    // items at full residency (a server's mix holds thousands of layer pairs per step, the regime
+    // where independent waves win)
     if (ctx->opt.batch_threads > 0) {
         S->threads = ctx->opt.batch_threads;
         S->grid = ctx->opt.batch_per_cu * ctx->num_cu;
@@ -425,7 +426,7 @@ extern "C" sd_status sd_server_start(sd_context* ctx, const sd_codon_table* tabl
         S->tuned = 1;
     } else {
         int per_cu = 0;
-        e = persistent_occupancy(256, 4, &per_cu);
+        e = persistent_occupancy(256, 1, &per_cu);
         if (e != hipSuccess || per_cu <= 0) {
             hipFree(S->pool_dev);
             hipFree(S->aux_dev);
@@ -433,7 +434,7 @@ extern "C" sd_status sd_server_start(sd_context* ctx, const sd_codon_table* tabl
             return hip_fail(e, "occupancy query");
         }
         S->threads = 256;
-        S->item_waves = 4;
+        S->item_waves = 1;
         S->grid = per_cu * ctx->num_cu;
     }
     S->loop = std::thread(server_main, S);

@@ -76,12 +76,15 @@ def oracle_tables(p, lam, oparams, weights):
     return _ORACLE_TABLES[k]
 
 
-@pytest.fixture(scope="module", params=[0, 64, 256, 512, 1024])
+@pytest.fixture(scope="module", params=[(0, 0), (64, 0), (256, 0), (512, 0), (1024, 0), (256, 1)],
+                ids=["tuned", "64", "256", "512", "1024", "256waves"])
 def span_ctx(request, sd):
-    # 0: the library's per-span choice; the others force one span-kernel instantiation for every
-    # span (k_span<64>: one wave, three job parts; <256>: three parts; <512>: four parts, 80-VGPR
-    # cap; <1024>: six parts)
-    c = sd.Context(0, span_threads=request.param)
+    # (0, 0): the library's per-span-band choice (its tuner explores every candidate tile on the
+    # first designs of a length class); the others force one span kernel for every span
+    # (k_span<64>: one wave, three job parts; <256>: three parts; <512>: four parts, 80-VGPR cap;
+    # <1024>: six parts; k_span_waves<256>: every wave on its own layer pair)
+    threads, waves = request.param
+    c = sd.Context(0, span_threads=threads, span_item_waves=waves)
     yield c
     c.close()
 
@@ -192,3 +195,31 @@ def test_plain925_1976_vs_golden(i, ctx, gtable, gparams):
     g = _golden("plain925_1976", 4)[i]
     say("plain925_1976", g["A"], g["lambda"])
     _check_golden(ctx.design(g["protein"], gtable, gparams, g["lambda"]), g)
+
+
+def test_span_band_tuner_explores_then_settles(sd, gtable, gparams):
+    # the first four designs of a length class each run one candidate tile for every span (every
+    # launch timed); later designs of the class run each span band's fastest tile; the designs
+    # are the same throughout
+    c = sd.Context(0)
+    p = S.protein(90, 5)
+    flags, keys = [], {}
+    for k in range(6):
+        lam = 4.0 if k % 2 else 0.0
+        say("span tuner design", k)
+        r = c.design(p, gtable, gparams, lam)
+        flags.append(r.sched_tuned)
+        key = (r.mrna, r.structure, r.energy, r.objective_fixed, r.n_candidates, r.n_visits)
+        assert keys.setdefault(lam, key) == key
+    assert flags == [0, 0, 0, 0, 1, 1], flags
+    fixed = sd.Context(0, span_threads=512)
+    assert fixed.design(p, gtable, gparams, 0.0).sched_tuned == 1
+    fixed.close()
+    c.close()
+
+
+@pytest.mark.parametrize("threads,waves", [(512, 1), (0, 1), (1024, 1), (256, 4)])
+def test_invalid_span_item_waves_rejected(sd, threads, waves):
+    with pytest.raises(sd.SDError) as e:
+        sd.Context(0, span_threads=threads, span_item_waves=waves)
+    assert e.value.code == -1  # SD_E_ARG
