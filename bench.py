@@ -92,7 +92,7 @@ def kernel_source_sha():
     return h.hexdigest()
 
 
-COUNTER_FILES = {"plain300": "k_span_plain300_counters.json", "batch256": "k_persistent_batch256_counters.json",
+COUNTER_FILES = {"plain300": "k_span_plain300_counters.json", "batch256": "k_persistent_waves_batch256_counters.json",
                  "motifs": "k_gen_closed_motifs_105aa_counters.json"}
 
 
