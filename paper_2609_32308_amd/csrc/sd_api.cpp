@@ -10,6 +10,8 @@
 #include <mutex>
 #include <sstream>
 #include <string>
+#include <algorithm>
+#include <thread>
 #include <vector>
 
 #include "../../include/sparsedesign.h"
@@ -861,7 +863,8 @@ sd_status trace_and_finish_on(sd_context* c, const Lattice& L, const Inst& I, co
     sd_status s = fetch_trace(c, L, I, T);
     if (s) return s;
     TraceResult R;
-    if (finish_trace(L, T, R)) return fail(SD_E_INTERNAL, "traceback self-check failed");
+    std::string why;
+    if (finish_trace(L, T, R, &why)) return fail(SD_E_INTERNAL, "traceback self-check failed: " + why);
     int64_t Z = 0;
     for (int v = 0; v < L.N; v++) Z += T.counts[v];
     return fill_result(L, R, T.xs, Z, visits, feasible, out);
@@ -1468,17 +1471,37 @@ sd_status design_batch_impl(sd_context* ctx, int n, const char* const* proteins,
         while (done < n) {
             const int m = std::min(n - done, kMaxBatch);
             const double t0 = now_s();
+            // the members' automata and layouts, built on up to 16 host threads (each build reads
+            // only its protein, the shared read-only tables and the sizer); the first failing
+            // member in order is reported
             std::vector<Lattice> Ls(m);
-            std::string err;
-            for (int i = 0; i < m; i++) {
-                std::vector<float> frac;
-                int rc = build_lattice(proteins[done + i], table->t, params->p, lambdas[done + i],
-                                       policy_for(ctx, proteins[done + i], lambdas[done + i], frac), Ls[i], err);
-                if (rc) {
-                    for (int j = 0; j < done; j++) sd_result_free(&outs[j]);
-                    return fail((sd_status)rc, "batch member " + std::to_string(done + i) + ": " + err);
-                }
+            std::vector<int> rcs(m, 0);
+            std::vector<std::string> errs(m);
+            {
+                const int nt = std::max(1, std::min({m, 16, (int)std::thread::hardware_concurrency()}));
+                auto work = [&](int t) {
+                    for (int i = t; i < m; i += nt) {
+                        try {
+                            std::vector<float> frac;
+                            rcs[i] = build_lattice(proteins[done + i], table->t, params->p, lambdas[done + i],
+                                                   policy_for(ctx, proteins[done + i], lambdas[done + i], frac), Ls[i],
+                                                   errs[i]);
+                        } catch (const std::bad_alloc&) {
+                            rcs[i] = SD_E_NOMEM;
+                            errs[i] = "host allocation";
+                        }
+                    }
+                };
+                std::vector<std::thread> pool;
+                for (int t = 1; t < nt; t++) pool.emplace_back(work, t);
+                work(0);
+                for (auto& th : pool) th.join();
             }
+            for (int i = 0; i < m; i++)
+                if (rcs[i]) {
+                    for (int j = 0; j < done; j++) sd_result_free(&outs[j]);
+                    return fail((sd_status)rcs[i], "batch member " + std::to_string(done + i) + ": " + errs[i]);
+                }
             sd_status s = ensure_params(ctx, params);
             sd_context::Sched sc;
             int cls = -1;
@@ -1548,8 +1571,10 @@ sd_status design_batch_impl(sd_context* ctx, int n, const char* const* proteins,
                     dense_tables(Ls[i], TT, D);
                 }
                 TraceResult R;
-                if (finish_trace(Ls[i], T, R)) {
-                    s = fail(SD_E_INTERNAL, "traceback self-check failed");
+                std::string why;
+                if (finish_trace(Ls[i], T, R, &why)) {
+                    s = fail(SD_E_INTERNAL, "traceback self-check failed for batch member " + std::to_string(gi) +
+                                                " (" + std::to_string(Ls[i].n) + " layers): " + why);
                     break;
                 }
                 int64_t Z = 0;

@@ -335,7 +335,8 @@ sd_status round_once(sd_server* S) {
             sd_result r;
             memset(&r, 0, sizeof(r));
             TraceResult R;
-            s = finish_trace(a.L, T, R) ? fail(SD_E_INTERNAL, "traceback self-check failed") : SD_OK;
+            std::string why;
+            s = finish_trace(a.L, T, R, &why) ? fail(SD_E_INTERNAL, "traceback self-check failed: " + why) : SD_OK;
             if (!s) {
                 int64_t Z = 0;
                 for (int v = 0; v < a.L.N; v++) Z += T.counts[v];

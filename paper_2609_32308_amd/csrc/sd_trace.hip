@@ -31,6 +31,7 @@
 
 #include "sd_devutil.h"
 #include "sd_internal.h"
+#include "sd_trace_status.h"
 
 namespace sd {
 namespace {
@@ -221,35 +222,166 @@ struct SegIter {
     }
 };
 
+// Waves per design: deferred decisions of independent sub-intervals (the rest of the external
+// loop beside a closed pair; the left part of a multiloop split beside its last branch) are taken
+// by whichever wave is free.
+constexpr int kTraceWaves = 8;
+constexpr unsigned kTraceSpinCap = 1u << 24;  // polls before a wait is declared failed
+
+// one wave's scratch for the decision it is working on
+struct TraceScratch {
+    int pre[kNumPairs + 1];  // tuples of the two-loop pairs before pair k
+    int jl[64];              // in-edges of b labelled y (closing edge of a pair)
+    int hpre[65];            // generic hairpins: prefix of in-degrees of the b1 of jl
+};
+
 struct TraceLds {
     SmallE S;
     LoopMin M;
-    int pre[kNumPairs + 1];           // tuples of the two-loop pairs before pair k
     unsigned char pl1[kNumPairs], pl2[kNumPairs];
-    int jl[64];                       // in-edges of b labelled y (closing edge of a pair)
-    int hpre[65];                     // generic hairpins: prefix of in-degrees of the b1 of jl
+    TraceScratch w[kTraceWaves];
+    // the shared stack of deferred frames (frames in region A, its top here), guarded by `lock`
+    int lock, sp, busy, failed, dup;
+    unsigned long long E, U;  // sums over the waves (two's complement)
 };
 
-// The wavefront's replay state; every lane holds the same values.
+// A wavefront's replay state; every lane holds the same values.
 struct Tracer {
     const Inst& I;
     TraceLds& L;
+    TraceScratch& W;
     const int32_t* spec;
     int lane;
     int64_t E = 0, U = 0;
-    int sp = 0;
     bool fail = false;
     bool dup = false;  // a position emitted twice (lane 0's view, broadcast at the end)
     TFrame next;
     bool have_next = false;
 
-    __device__ Tracer(const Inst& I_, TraceLds& L_, const int32_t* sp_, int ln) : I(I_), L(L_), spec(sp_), lane(ln) {}
+    __device__ Tracer(const Inst& I_, TraceLds& L_, TraceScratch& W_, const int32_t* sp_, int ln)
+        : I(I_), L(L_), W(W_), spec(sp_), lane(ln) {}
 
     __device__ int64_t fxe(int64_t e) const { return e * ((int64_t)1 << I.shift); }
 
+    // the stack's lock: lane 0 spins, the whole wave then orders its accesses after it
+    __device__ bool lock() {
+        int ok = 1;
+        if (lane == 0) {
+            unsigned spins = 0;
+            while (atomicCAS(&L.lock, 0, 1) != 0) {
+                if (++spins > kTraceSpinCap) {
+                    ok = 0;
+                    break;
+                }
+                __builtin_amdgcn_s_sleep(1);
+            }
+        }
+        ok = bcast(ok);
+        __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "workgroup");
+        if (!ok) fail_all(kTrWait);
+        return ok;
+    }
+    // A workgroup-scope release waits only for LDS operations, so the frame a push stored, or the
+    // frame a take is still loading from a slot a later push may reuse, is waited for explicitly
+    // (vmcnt 0) before the lock is given up.  All waves of the design share this CU's L2.
+    __device__ void unlock() {
+        __builtin_amdgcn_fence(__ATOMIC_RELEASE, "workgroup");
+        __builtin_amdgcn_s_waitcnt(0x0F70);  // vmcnt(0), expcnt and lgkmcnt untouched
+        __builtin_amdgcn_wave_barrier();
+        if (lane == 0) atomicExch(&L.lock, 0);
+    }
+    // ends every wave's replay; the first reason recorded is the one reported
+    __device__ void fail_all(int reason) {
+        fail = true;
+        if (lane == 0) atomicCAS(&L.failed, 0, reason);
+    }
+    // Frames move between waves through region A.  Stack slots are reused, so they are written
+    // and read with agent-scope atomic accesses (to L2, past this CU's L1 copy of the slot); the
+    // lock's release and acquire order them.
+    __device__ static void store_frame(TFrame* p, const TFrame& f) {
+        __hip_atomic_store(&p->kind, f.kind, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        __hip_atomic_store(&p->a, f.a, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        __hip_atomic_store(&p->b, f.b, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        __hip_atomic_store(&p->t, f.t, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    }
+    __device__ static TFrame load_frame(TFrame* p) {
+        return TFrame{__hip_atomic_load(&p->kind, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT),
+                      __hip_atomic_load(&p->a, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT),
+                      __hip_atomic_load(&p->b, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT),
+                      __hip_atomic_load(&p->t, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT)};
+    }
+    // defers a decision to the shared stack (at most n + 2 frames: each covers a disjoint interval)
     __device__ void push(int kind, int a, int b, int t) {
-        if (lane == 0) I.tr_stack()[sp] = TFrame{kind, a, b, t};
-        sp++;
+        if (!lock()) return;
+        int over = 0;
+        if (lane == 0) {
+            const int slot = L.sp;
+            if (slot >= I.n + 2) {
+                over = 1;
+            } else {
+                store_frame(I.tr_stack() + slot, TFrame{kind, a, b, t});
+                L.sp = slot + 1;
+            }
+        }
+        unlock();
+        if (bcast(over)) fail_all(kTrStack);
+    }
+    // The next deferred frame once this wave's chain has ended (a wave counted busy stops being
+    // busy first): true with a frame (the wave is busy again), false when no wave is busy and the
+    // stack is empty, or on failure.  Waiting waves poll the stack's state with plain loads and
+    // take the lock only to pop a frame or to confirm the end, so that they do not keep the lock
+    // from the busy waves' pushes.
+    __device__ bool take(TFrame& f, bool was_busy) {
+        if (was_busy) {
+            if (!lock()) return false;
+            if (lane == 0) L.busy--;
+            unlock();
+        }
+        for (unsigned spins = 0;; spins++) {
+            int look = 0;  // 1: a frame to pop or a possible end, 2: failed
+            if (lane == 0) {
+                const int fl = __hip_atomic_load(&L.failed, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
+                const int sp = __hip_atomic_load(&L.sp, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
+                const int bz = __hip_atomic_load(&L.busy, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
+                look = fl ? 2 : (sp > 0 || bz == 0) ? 1 : 0;
+            }
+            look = bcast(look);
+            if (look == 2) return false;
+            if (look == 1) {
+                if (!lock()) return false;
+                int st = 0;  // 0: wait, 1: frame, 2: done
+                TFrame h{0, 0, 0, 0};
+                if (lane == 0) {
+                    if (L.failed) {
+                        st = 2;
+                    } else if (L.sp > 0) {
+                        h = load_frame(I.tr_stack() + --L.sp);
+                        L.busy++;
+                        st = 1;
+                    } else if (L.busy == 0) {
+                        st = 2;
+                    }
+                }
+                unlock();
+                st = bcast(st);
+                if (st == 1) {
+                    f = TFrame{bcast(h.kind), bcast(h.a), bcast(h.b), bcast(h.t)};
+                    // a frame names states of this design (a corrupted one would index out of range)
+                    if (f.kind < kFX || f.kind > kFBR || f.a < 0 || f.a >= I.N || f.b < -1 || f.b >= I.N ||
+                        f.t < -1 || f.t >= 6) {
+                        fail_all(kTrFrame);
+                        return false;
+                    }
+                    return true;
+                }
+                if (st == 2) return false;
+            }
+            if (spins > kTraceSpinCap) {
+                fail_all(kTrWait);
+                return false;
+            }
+            __builtin_amdgcn_s_sleep(4);
+        }
     }
     __device__ void go(int kind, int a, int b, int t) {
         next = TFrame{kind, a, b, t};
@@ -410,14 +542,14 @@ __device__ bool Tracer::hairpin(int a, int b, int t, int64_t v, int ea, int a1) 
         const bool lab = j < ib1 && I.in_lab()[j] == y;
         const unsigned long long msk = __ballot(lab);
         const int at = nj + __popcll(msk & ((1ull << lane) - 1));
-        if (lab && at < 64) L.jl[at] = j;
+        if (lab && at < 64) W.jl[at] = j;
         nj += __popcll(msk);
     }
     if (nj > 64) nj = 64;  // a state has at most 64 in-edges (4 labels x 16 sources)
     __builtin_amdgcn_wave_barrier();
     int deg = 0;
     if (lane < nj) {
-        const int b1 = I.in_src()[L.jl[lane]];
+        const int b1 = I.in_src()[W.jl[lane]];
         deg = I.in_start()[b1 + 1] - I.in_start()[b1];
     }
     int incl = deg;
@@ -425,8 +557,8 @@ __device__ bool Tracer::hairpin(int a, int b, int t, int64_t v, int ea, int a1) 
         const int w = __shfl_up(incl, o, 64);
         if (lane >= o) incl += w;
     }
-    if (lane < nj) L.hpre[lane + 1] = incl;
-    if (lane == 0) L.hpre[0] = 0;
+    if (lane < nj) W.hpre[lane + 1] = incl;
+    if (lane == 0) W.hpre[0] = 0;
     __builtin_amdgcn_wave_barrier();
     const int per = bcast(__shfl(incl, 63, 64));
     const int total = 4 * per;
@@ -437,9 +569,9 @@ __device__ bool Tracer::hairpin(int a, int b, int t, int64_t v, int ea, int a1) 
         if (idx < total) {
             const int x2 = idx / per, r = idx - x2 * per;
             int jj = 0;
-            while (jj + 1 < nj && L.hpre[jj + 1] <= r) jj++;
-            const int j = L.jl[jj], b1 = I.in_src()[j];
-            const int j2 = I.in_start()[b1] + (r - L.hpre[jj]);
+            while (jj + 1 < nj && W.hpre[jj + 1] <= r) jj++;
+            const int j = W.jl[jj], b1 = I.in_src()[j];
+            const int j2 = I.in_start()[b1] + (r - W.hpre[jj]);
             const int e1 = a1 * 4 + x2, a2 = I.out_dst()[e1];
             if (a2 >= 0) {
                 const int64_t gg = tgap(I, a2, I.in_src()[j2]);
@@ -454,9 +586,9 @@ __device__ bool Tracer::hairpin(int a, int b, int t, int64_t v, int ea, int a1) 
             const int win = base + first_lane(msk);
             const int x2 = win / per, r = win - x2 * per;
             int jj = 0;
-            while (jj + 1 < nj && L.hpre[jj + 1] <= r) jj++;
-            const int j = L.jl[jj], b1 = I.in_src()[j];
-            const int j2 = I.in_start()[b1] + (r - L.hpre[jj]);
+            while (jj + 1 < nj && W.hpre[jj + 1] <= r) jj++;
+            const int j = W.jl[jj], b1 = I.in_src()[j];
+            const int j2 = I.in_start()[b1] + (r - W.hpre[jj]);
             const int e1 = a1 * 4 + x2;
             emit_out(ea);
             emit_out(e1);
@@ -482,7 +614,7 @@ __device__ bool Tracer::twoloop(int a, int b, int t, int64_t v, int ea, int a1) 
         const bool lab = j < ib1 && I.in_lab()[j] == y;
         const unsigned long long msk = __ballot(lab);
         const int at = nj + __popcll(msk & ((1ull << lane) - 1));
-        if (lab && at < 64) L.jl[at] = j;
+        if (lab && at < 64) W.jl[at] = j;
         nj += __popcll(msk);
     }
     if (nj > 64) nj = 64;
@@ -512,12 +644,12 @@ __device__ bool Tracer::twoloop(int a, int b, int t, int64_t v, int ea, int a1) 
         int acc = incl - sum;
         for (int i = 0; i < 8; i++) {
             const int k = lane * 8 + i;
-            if (k <= kNumPairs) L.pre[k] = acc;
+            if (k <= kNumPairs) W.pre[k] = acc;
             acc += cnt[i];
         }
         __builtin_amdgcn_wave_barrier();
     }
-    const int total = L.pre[kNumPairs];
+    const int total = W.pre[kNumPairs];
     const int64_t Ua = I.out_U()[ea];
     // four groups per lane and round (group T = base + lane + 64 k): their independent loads are
     // issued together, then each group's lower bound is tested and, rarely, its alternatives
@@ -537,19 +669,19 @@ __device__ bool Tracer::twoloop(int a, int b, int t, int64_t v, int ea, int a1) 
             int lo = 0, hi = kNumPairs - 1;  // last pair whose prefix <= T
             while (lo < hi) {
                 const int mid = (lo + hi + 1) >> 1;
-                if (L.pre[mid] <= T) lo = mid;
+                if (W.pre[mid] <= T) lo = mid;
                 else hi = mid - 1;
             }
             const int l1 = L.pl1[lo], l2 = L.pl2[lo];
             const int cl = la + 1 + l1, dl = lb - 1 - l2;
             const int c0 = I.off()[cl], d0 = I.off()[dl];
             const int wc = I.off()[cl + 1] - c0, wd = I.off()[dl + 1] - d0;
-            const int r = T - L.pre[lo], jj = r / (wc * wd), ci = (r / wd) % wc, di = r % wd;
+            const int r = T - W.pre[lo], jj = r / (wc * wd), ci = (r / wd) % wc, di = r % wd;
             tl1[k] = l1;
             tl2[k] = l2;
             tc[k] = c0 + ci;
             td[k] = d0 + di;
-            tj[k] = L.jl[jj];
+            tj[k] = W.jl[jj];
         }
 #pragma unroll
         for (int k = 0; k < kPer; k++) {
@@ -602,14 +734,14 @@ __device__ bool Tracer::twoloop(int a, int b, int t, int64_t v, int ea, int a1) 
         int lo = 0, hi = kNumPairs - 1;
         while (lo < hi) {
             const int mid = (lo + hi + 1) >> 1;
-            if (L.pre[mid] <= best) lo = mid;
+            if (W.pre[mid] <= best) lo = mid;
             else hi = mid - 1;
         }
         const int k = lo, l1 = L.pl1[k], l2 = L.pl2[k];
         const int cl = la + 1 + l1, dl = lb - 1 - l2;
         const int wc = I.off()[cl + 1] - I.off()[cl], wd = I.off()[dl + 1] - I.off()[dl];
-        const int r = best - L.pre[k], jj = r / (wc * wd), ci = (r / wd) % wc, di = r % wd;
-        const int j = L.jl[jj], b1 = I.in_src()[j], c = I.off()[cl] + ci, d = I.off()[dl] + di;
+        const int r = best - W.pre[k], jj = r / (wc * wd), ci = (r / wd) % wc, di = r % wd;
+        const int j = W.jl[jj], b1 = I.in_src()[j], c = I.off()[cl] + ci, d = I.off()[dl] + di;
         Seg sl, sr;
         seg_at(I, a1, c, l1, p, sl);
         seg_at(I, d, b1, l2, q, sr);
@@ -758,9 +890,9 @@ __device__ void Tracer::s2(int a, int b) {
 
 __device__ void trace_instance(const Inst& I, const EnergyTables* __restrict__ E, const int32_t* __restrict__ spec,
                                TraceLds& L) {
-    const int lane = threadIdx.x;
+    const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
     stage_tables(L.S, E);
-    for (int k = lane; k < kNumPairs; k += 64) {  // (l1, l2) in canonical order
+    for (int k = tid; k < kNumPairs; k += blockDim.x) {  // (l1, l2) in canonical order
         int l1 = 0, r = k;
         while (r >= 31 - l1) {
             r -= 31 - l1;
@@ -769,30 +901,48 @@ __device__ void trace_instance(const Inst& I, const EnergyTables* __restrict__ E
         L.pl1[k] = (unsigned char)l1;
         L.pl2[k] = (unsigned char)r;
     }
-    for (int p = lane; p < I.n; p += 64) {
+    for (int p = tid; p < I.n; p += blockDim.x) {
         I.tr_seq()[p] = -1;
         I.tr_pair()[p] = -1;
     }
+    if (tid == 0) {
+        L.lock = 0;
+        L.sp = 0;
+        L.busy = 1;  // wave 0 starts busy with X(s)
+        L.failed = 0;
+        L.dup = 0;
+        L.E = 0;
+        L.U = 0;
+    }
+    __syncthreads();  // every wave's share of the energy tables is staged
+    if (wave == 0) loop_minima(L.S, L.M, lane);
+    // A position is initialised by one wave and later written by whichever wave emits it: every
+    // wave waits for its initialising stores before the barrier (which by itself waits only for
+    // LDS operations), so that no -1 can land after an emitted value.
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "workgroup");
+    __builtin_amdgcn_s_waitcnt(0x0F70);  // vmcnt(0)
     __syncthreads();
-    loop_minima(L.S, L.M, lane);
-    __syncthreads();
-    __threadfence_block();
-    Tracer tr(I, L, spec, lane);
+    Tracer tr(I, L, L.w[wave], spec, lane);
     const int64_t xs = I.X()[0];
-    if (xs >= kINF) tr.fail = true;
-    tr.go(kFX, 0, -1, -1);
+    if (wave == 0) {
+        if (xs >= kINF) tr.fail_all(kTrUnreachable);
+        tr.go(kFX, 0, -1, -1);
+    }
+    bool busy = wave == 0;
     for (;;) {
-        if (tr.fail) break;
+        if (tr.fail) {
+            tr.fail_all(kTrNoMatch);  // a no-match decision (other reasons were recorded already)
+            break;
+        }
         TFrame f;
         if (tr.have_next) {
             f = tr.next;
             tr.have_next = false;
         } else {
-            if (tr.sp == 0) break;
-            tr.sp--;
-            TFrame h{0, 0, 0, 0};
-            if (lane == 0) h = I.tr_stack()[tr.sp];
-            f = TFrame{bcast(h.kind), bcast(h.a), bcast(h.b), bcast(h.t)};
+            // this wave's chain has ended (or it never had one): a deferred frame, or the end
+            const bool got = tr.take(f, busy);
+            busy = got;
+            if (!got) break;
         }
         switch (f.kind) {
             case kFX: tr.ext(f.a); break;
@@ -804,21 +954,28 @@ __device__ void trace_instance(const Inst& I, const EnergyTables* __restrict__ E
     }
     const int dup = bcast(tr.dup ? 1 : 0);
     if (lane == 0) {
-        I.tr_res()[0] = tr.E;
-        I.tr_res()[1] = tr.U;
-        I.tr_res()[2] = (tr.fail || dup) ? 0 : 1;
+        atomicAdd(&L.E, (unsigned long long)tr.E);
+        atomicAdd(&L.U, (unsigned long long)tr.U);
+        if (dup) atomicOr(&L.dup, 1);
+    }
+    __syncthreads();
+    if (tid == 0) {
+        I.tr_res()[0] = (long long)L.E;
+        I.tr_res()[1] = (long long)L.U;
+        I.tr_res()[2] = L.failed ? L.failed : L.dup ? kTrDup : kTrOk;
         I.tr_res()[3] = xs;
     }
 }
 
-__global__ __launch_bounds__(64) void k_trace(Inst I, const EnergyTables* __restrict__ E,
-                                               const int32_t* __restrict__ spec) {
+__global__ __launch_bounds__(64 * kTraceWaves) void k_trace(Inst I, const EnergyTables* __restrict__ E,
+                                                            const int32_t* __restrict__ spec) {
     __shared__ TraceLds L;
     trace_instance(I, E, spec, L);
 }
 
-__global__ __launch_bounds__(64) void k_trace_many(const Inst* __restrict__ insts, const EnergyTables* __restrict__ E,
-                                                    const int32_t* __restrict__ spec) {
+__global__ __launch_bounds__(64 * kTraceWaves) void k_trace_many(const Inst* __restrict__ insts,
+                                                                 const EnergyTables* __restrict__ E,
+                                                                 const int32_t* __restrict__ spec) {
     __shared__ TraceLds L;
     const Inst I = insts[blockIdx.x];
     trace_instance(I, E, spec, L);
@@ -837,14 +994,14 @@ __global__ void k_strict_count(Inst I) {
 }  // namespace
 
 hipError_t launch_trace(const Inst& I, const EnergyTables* E, const int32_t* spec, hipStream_t st) {
-    hipLaunchKernelGGL(k_trace, dim3(1), dim3(64), 0, st, I, E, spec);
+    hipLaunchKernelGGL(k_trace, dim3(1), dim3(64 * kTraceWaves), 0, st, I, E, spec);
     return hipGetLastError();
 }
 
 hipError_t launch_trace_many(const Inst* insts_dev, int n, const EnergyTables* E, const int32_t* spec,
                              hipStream_t st) {
     if (n <= 0) return hipSuccess;
-    hipLaunchKernelGGL(k_trace_many, dim3(n), dim3(64), 0, st, insts_dev, E, spec);
+    hipLaunchKernelGGL(k_trace_many, dim3(n), dim3(64 * kTraceWaves), 0, st, insts_dev, E, spec);
     return hipGetLastError();
 }
 

@@ -7,6 +7,7 @@
 #include <vector>
 
 #include "sd_lattice.h"
+#include "sd_trace_status.h"
 
 namespace sd {
 
@@ -38,7 +39,8 @@ struct TraceResult {
 
 // Builds the strings and checks the design exactly: the emitted bases spell a complete path
 // s -> t of the automaton, its rounded costs sum to the traceback's path cost, and
-// E * 2^s + path cost equals X(s).  SD_E_INTERNAL if any check fails.
-int finish_trace(const Lattice& L, const TraceOut& T, TraceResult& R);
+// E * 2^s + path cost equals X(s).  SD_E_INTERNAL if any check fails; *why (if given) then
+// names the check.
+int finish_trace(const Lattice& L, const TraceOut& T, TraceResult& R, std::string* why = nullptr);
 
 }  // namespace sd
