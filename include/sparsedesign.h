@@ -201,7 +201,8 @@ sd_status sd_design_noalloc(sd_context *ctx, const char *protein, const sd_codon
                             const sd_params *params, double lambda_kcal, sd_result *out);
 
 /* n designs in one persistent, graph-captured launch (all instances advance one span per grid
- * barrier; the schedule is autotuned on a sample of the batch or fixed by sd_options).
+ * barrier; the schedule is fixed by sd_options or autotuned: the first calls of a size class
+ * each run one candidate schedule, later calls the fastest, reported in sd_result.sched_*).
  * proteins[i] (as for sd_design) with lambdas[i]; outs[i] (array of n) receives each result,
  * identical to sd_design's.  Members whose learned reservation overflows, or a launch whose
  * barrier gives up, are recomputed exactly in plain mode.  On error no output owns memory and
