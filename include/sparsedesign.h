@@ -359,10 +359,12 @@ sd_status sd_occupancy(sd_context *ctx, int n, const char *const *proteins, cons
  * A server thread admits queued requests FIFO while a slot is free and the request's device
  * state fits the pool (tables sized exactly from the automaton, candidate segments from the
  * context's sizing policy), runs one persistent launch of steps_per_round span steps over all
- * active requests (each at its own span), and retires finished ones (traceback on host worker
- * threads), freeing their memory for the next admissions.  While a server runs, its context must
- * not be used by other calls.  Results are identical to sd_design; t_total_s is the latency from
- * submission to completion. */
+ * active requests (each at its own span), and retires finished ones (their tracebacks in one
+ * device launch), freeing their memory for the next admissions.  A launch's schedule is the one
+ * fixed in the context's sd_options, else chosen per round from the mix: every wave on its own
+ * layer pairs when the round starts with at least 12 pairs per resident wave, else four waves
+ * per pair.  While a server runs, its context must not be used by other calls.  Results are
+ * identical to sd_design; t_total_s is the latency from submission to completion. */
 typedef struct sd_server sd_server;
 typedef struct sd_server_cfg {
     size_t pool_bytes;   /* device memory for the DP state of admitted requests (>= 1 MiB)  */

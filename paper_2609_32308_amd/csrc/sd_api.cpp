@@ -1400,7 +1400,6 @@ void tune_record(sd_context* c, int cls, const std::vector<Lattice>& batch, bool
         if (T.score[k] < T.score[b]) b = k;
     T.best = T.cands[b];
     T.settled = true;
-    if (batch.size() >= 12) c->batch_sched = T.best;  // the server's schedule unless the caller fixed one
 }
 
 }  // namespace sd

@@ -23,7 +23,6 @@ struct sd_context {
     struct Sched {
         int grid = 0, threads = 256, item_waves = 4;
     };
-    Sched batch_sched;  // the server's schedule: tuned on batches of >= 12 members (grid 0: none yet)
     // Tuner state per (length, member-count) class: the candidate schedules, run one per batched
     // call until each has been measured, then the fastest for every later call of the class.
     struct Tune {

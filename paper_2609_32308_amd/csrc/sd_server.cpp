@@ -112,8 +112,9 @@ struct sd_server {
     char* aux_dev = nullptr;  // instance descriptors + barrier state
     void* staging = nullptr;
     size_t staging_bytes = 0;
-    int grid = 0, threads = 256, item_waves = 4;
-    int tuned = 0;  // 1: the schedule was fixed by the caller or settled by the context's tuner
+    int grid = 0, threads = 256, item_waves = 4;  // the schedule of the current round
+    bool fixed = false;                           // fixed by the caller's options
+    int grid_shared = 0, grid_waves = 0;          // full-residency grids of the two schedules
 
     std::mutex mu;
     std::condition_variable cv, cv_done;
@@ -250,6 +251,18 @@ sd_status round_once(sd_server* S) {
     BatchCtl* ctl = (BatchCtl*)(S->aux_dev + sizeof(Inst) * kMaxBatch);
     hipStream_t st = S->ctx->stream;
     const double t0 = now_s();
+    if (!S->fixed) {
+        // Every wave on its own items when the round starts with at least 12 layer pairs per
+        // resident wave; else four waves share each item.  A mix of about 30 requests (an 8 GiB
+        // pool) holds too few pairs per step for independent waves (715 against 687 designs/min);
+        // 256 requests (a 64 GiB pool) hold enough (1.24x).
+        int64_t items = 0;
+        for (int i = 0; i < n; i++) items += std::max(0, S->active[i].L.n - S->active[i].g + 1);
+        const bool waves = items >= 12 * (int64_t)S->grid_waves * 4;
+        S->threads = 256;
+        S->item_waves = waves ? 1 : 4;
+        S->grid = waves ? S->grid_waves : S->grid_shared;
+    }
     hipError_t e = hipMemcpyAsync(insts, Is.data(), sizeof(Inst) * n, hipMemcpyHostToDevice, st);
     if (e == hipSuccess) e = launch_batch_init(insts, n, ctl, st);
     if (e == hipSuccess)
@@ -348,7 +361,7 @@ sd_status round_once(sd_server* S) {
                 r.sched_threads = S->threads;
                 r.sched_grid = S->grid;
                 r.sched_item_waves = S->item_waves;
-                r.sched_tuned = S->tuned;
+                r.sched_tuned = 1;
                 r.t_fill_s = a.rq.t_admit > 0 ? now_s() - a.rq.t_admit : 0.0;
                 r.t_total_s = now_s() - a.rq.t_submit;
                 r.cand_slots = a.L.cand_slots;
@@ -411,32 +424,26 @@ extern "C" sd_status sd_server_start(sd_context* ctx, const sd_codon_table* tabl
         return fail(SD_E_NOMEM, "server pool allocation");
     }
     S->pool.init(cfg->pool_bytes);
-    // the schedule: fixed by the caller (validated at context creation), else the one the context's
-    // tuner settled on for batches of >= 12 members, else 256 threads with every wave on its own
-    // items at full residency (a server's mix holds thousands of layer pairs per step, the regime
-    // where independent waves win)
+    // the schedule: fixed by the caller (validated at context creation), else chosen per round
+    // from the mix (round_once) between the full-residency grids of the two 256-thread schedules
     if (ctx->opt.batch_threads > 0) {
+        S->fixed = true;
         S->threads = ctx->opt.batch_threads;
         S->grid = ctx->opt.batch_per_cu * ctx->num_cu;
         S->item_waves = ctx->opt.batch_item_waves ? ctx->opt.batch_item_waves : ctx->opt.batch_threads / 64;
-        S->tuned = 1;
-    } else if (ctx->batch_sched.grid > 0) {
-        S->threads = ctx->batch_sched.threads;
-        S->grid = ctx->batch_sched.grid;
-        S->item_waves = ctx->batch_sched.item_waves;
-        S->tuned = 1;
     } else {
-        int per_cu = 0;
-        e = persistent_occupancy(256, 1, &per_cu);
-        if (e != hipSuccess || per_cu <= 0) {
+        int pc_s = 0, pc_w = 0;
+        e = persistent_occupancy(256, 4, &pc_s);
+        if (e == hipSuccess) e = persistent_occupancy(256, 1, &pc_w);
+        if (e != hipSuccess || pc_s <= 0 || pc_w <= 0) {
             hipFree(S->pool_dev);
             hipFree(S->aux_dev);
             delete S;
             return hip_fail(e, "occupancy query");
         }
-        S->threads = 256;
-        S->item_waves = 1;
-        S->grid = per_cu * ctx->num_cu;
+        S->grid_shared = pc_s * ctx->num_cu;
+        S->grid_waves = pc_w * ctx->num_cu;
+        S->grid = S->grid_shared;
     }
     S->loop = std::thread(server_main, S);
     *out = S;
