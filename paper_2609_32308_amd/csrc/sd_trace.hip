@@ -2,9 +2,12 @@
 // fill is complete and reconstructs every decision from the stored costs; Sec. 7: optima are
 // often tied, so one fixed order of alternatives makes the emitted design reproducible).
 //
-// One wavefront per design replays the decisions from X(s).  At each decision the alternatives
-// are enumerated in a fixed order and the first whose value equals the stored value exactly is
-// taken:
+// A workgroup of eight wavefronts per design replays the decisions from X(s).  A decision either
+// continues in the same wave or also defers an independent sub-interval (the rest of the external
+// loop beside a closed pair, the left part of a multiloop split), which a free wave takes from a
+// shared stack.  At each decision the alternatives are enumerated in a fixed order and the first
+// whose value equals the stored value exactly is taken, so the design does not depend on which
+// wave replays which interval:
 //   X(a):   unpaired out-edges by label; then branches (b by state index, pair type in the order
 //           AU, CG, GC, GU, UA, UG)
 //   V_t:    hairpin (sizes 3, 4, 6: paths in lexicographic base order; other sizes: x_{i+1} by
@@ -15,9 +18,9 @@
 //   S2:     right unpaired edge (in-edge order), then candidates c of C_b by state index (eq. 7)
 //   branch: pair type order
 //   gaps:   the minimum-cost path that takes the smallest base staying on a minimum path
-// The lanes evaluate alternatives side by side and the first match is the lowest set lane of a
-// ballot (or the wave minimum of the matching indices), which is what a sequential replay in
-// this order picks.  Two-loop alternatives are grouped by (l1, l2, closing edge, c, d); a group
+// The lanes of a wave evaluate alternatives side by side and the first match is the lowest set
+// lane of a ballot (or the wave minimum of the matching indices), which is what a sequential
+// replay in this order picks.  Two-loop alternatives are grouped by (l1, l2, closing edge, c, d); a group
 // is enumerated only if an exact lower bound (segment costs at their minima, the gap costs;
 // the loop energy at the minimum of its table over boundary bases and inner types) does not
 // already exceed the stored value.  The decisions only read the completed tables, so the design
