@@ -71,6 +71,8 @@ def test_served_equals_oracle_and_alone(sd, env, oparams, weights):
     alone = sd.Context(0)
     for (p, lam), r in zip(reqs, res):
         assert r.path == sd.PATH_PERSISTENT and r.cand_overflow == 0
+        # the round that finished the request ran one of the two 256-thread schedules
+        assert (r.sched_threads, r.sched_item_waves, r.sched_tuned) in ((256, 4, 1), (256, 1, 1)) and r.sched_grid > 0
         a = alone.design(p, gt, gp, lam)
         assert key(r) == key(a)
         say("oracle", len(p), lam)
