@@ -116,3 +116,32 @@ def test_motif_lattice_size_errors():
     with pytest.raises(sd.SDError) as e:
         sd.motif_lattice_size("MZ", ["GA"])
     assert e.value.code == -2
+
+
+def _c_layout(tmp_path, structs):
+    """sizeof and every field's offset of the header's structs, from a C program built with gcc"""
+    import subprocess
+    inc = os.path.join(os.path.dirname(os.path.dirname(os.path.abspath(__file__))), "include")
+    lines = ["#include <stddef.h>", "#include <stdio.h>", '#include "sparsedesign.h"', "int main(void) {"]
+    for cname, fields in structs:
+        lines.append(f'printf("{cname} size %zu\\n", sizeof({cname}));')
+        for f in fields:
+            lines.append(f'printf("{cname} {f} %zu\\n", offsetof({cname}, {f}));')
+    lines += ["return 0;", "}"]
+    src, exe = tmp_path / "layout.c", tmp_path / "layout"
+    src.write_text("\n".join(lines))
+    subprocess.run(["gcc", "-std=c11", "-I", inc, str(src), "-o", str(exe)], check=True)
+    out = subprocess.run([str(exe)], check=True, capture_output=True, text=True).stdout
+    return {tuple(l.split()[:2]): int(l.split()[2]) for l in out.splitlines()}
+
+
+def test_binding_structs_match_the_header_layout(tmp_path):
+    # the ctypes mirrors of the header's structs have the same size and field offsets
+    import ctypes
+    pairs = [("sd_options", sd.Options), ("sd_result", sd._Result), ("sd_server_cfg", sd.ServerCfg),
+             ("sd_server_stats", sd.ServerStats)]
+    c = _c_layout(tmp_path, [(cn, [f for f, _ in py._fields_]) for cn, py in pairs])
+    for cn, py in pairs:
+        assert c[(cn, "size")] == ctypes.sizeof(py), cn
+        for f, _ in py._fields_:
+            assert c[(cn, f)] == getattr(py, f).offset, (cn, f)
