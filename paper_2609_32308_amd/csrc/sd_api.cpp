@@ -606,7 +606,8 @@ sd_status run_plain_on(sd_context* c, const Lattice& L, Inst& I, const EnergyTab
         }
     if (explore) {
         // time per span of each band under this candidate; after the last candidate, each band
-        // keeps its default tile unless another candidate was faster by more than 3 %
+        // keeps its default tile unless another candidate was faster by more than 3 % over at
+        // least 16 spans (the smallest bands hold a few spans each, too few to rank tiles)
         for (int i = 0; i < nbev; i++) {
             float ms = 0.f;
             e = hipEventElapsedTime(&ms, c->bev[i], c->bev[i + 1]);
@@ -630,7 +631,7 @@ sd_status run_plain_on(sd_context* c, const Lattice& L, Inst& I, const EnergyTab
                 }
                 if (best < 0) continue;
                 if (dk >= 0 && tune->cnt[dk][b] && best != dk &&
-                    best_us > 0.97 * (tune->us[dk][b] / tune->cnt[dk][b]))
+                    (tune->cnt[best][b] < 16 || best_us > 0.97 * (tune->us[dk][b] / tune->cnt[dk][b])))
                     best = dk;
                 tune->best[b].threads = kSpanCandThreads[best];
                 tune->best[b].item_waves = kSpanCandWaves[best];
