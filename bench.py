@@ -466,6 +466,14 @@ def main():
     fill = sum(r.t_fill_s for s_ in results for r in s_)
     designs = len(items) * args.steps
     counters = profile_record(args.workload)
+    kernel = "k_gen_closed+k_span_gen" if motifs else None
+    if batch:
+        # the persistent kernel the settled schedule ran; the committed counters count only if
+        # they were taken on that kernel
+        r0 = results[-1][0]
+        kernel = "k_persistent_waves" if (r0.sched_item_waves == 1 and r0.sched_threads != 64) else "k_persistent"
+        if counters and not counters.get("kernel", "").startswith(kernel + "<"):
+            counters = None
     line = {
         "metric": METRIC,
         "value": step_cells * args.steps / fill,
@@ -484,7 +492,7 @@ def main():
         "designs_per_min": designs / elapsed * 60.0,
         "fill_ms_per_step": fill / args.steps * 1e3,
         "per_design": per_design_stats(items, results[-1]),
-        "roofline": roofline_for(results, counters, batch, "k_gen_closed+k_span_gen" if motifs else None),
+        "roofline": roofline_for(results, counters, batch, kernel),
         "params_sha256": params.sha256,
     }
     ctx.close()
