@@ -215,3 +215,17 @@ def test_autotuner_explores_then_settles(sd, gt, gp):
     rb = c.design_batch(prots, lams, gt, gp)
     assert {(r.sched_threads, r.sched_grid, r.sched_item_waves, r.sched_tuned) for r in rb} == {seen[-1]}
     c.close()
+
+
+def test_batch_beyond_one_launch(sd, ctx, gt, gp):
+    # more members than one persistent launch holds (1,024): the batch runs as consecutive
+    # launches, and members on both sides of the split equal their plain designs
+    n = 1030
+    prots = [S.protein(4 + (i % 9), 3000 + i) for i in range(n)]
+    lams = [0.0 if i % 3 else 4.0 for i in range(n)]
+    say("batch of", n)
+    rb = ctx.design_batch(prots, lams, gt, gp)
+    assert len(rb) == n
+    persistent(sd, rb)
+    for i in (0, 1, 511, 1022, 1023, 1024, 1025, 1029):
+        assert key(rb[i]) == key(ctx.design(prots[i], gt, gp, lams[i])), i

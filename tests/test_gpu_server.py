@@ -45,8 +45,8 @@ def _requests(n, seed, lo=20, hi=140):
     return [(S.protein(A, seed * 1000 + i), 0.0 if i % 2 == 0 else 4.0) for i, A in enumerate(lens)]
 
 
-def _serve(sd, gp, gt, reqs, pool, max_active, steps, gaps):
-    ctx = sd.Context(0)
+def _serve(sd, gp, gt, reqs, pool, max_active, steps, gaps, **ctx_opts):
+    ctx = sd.Context(0, **ctx_opts)
     srv = sd.Server(ctx, gt, gp, pool_bytes=pool, max_active=max_active, steps_per_round=steps)
     tickets = []
     for (p, lam), gap in zip(reqs, gaps):
@@ -134,3 +134,21 @@ def test_stop_with_requests_still_queued(sd, env):
     p, lam = reqs[0]
     assert key(ctx.design(p, gt, gp, lam)) == key(sd.Context(0).design(p, gt, gp, lam))
     ctx.close()
+
+
+@pytest.mark.parametrize("item_waves", [1, 4])
+def test_fixed_schedule_serving_equals_alone(sd, env, item_waves):
+    # a schedule fixed in the context's options serves every round: independent waves and shared
+    # items both give the designs of sd_design
+    gp, gt = env
+    reqs = _requests(12, 33)
+    say("fixed schedule serving", item_waves)
+    res, st = _serve(sd, gp, gt, reqs, pool=2 << 30, max_active=64, steps=16, gaps=[0.002] * len(reqs),
+                     batch_threads=256, batch_per_cu=4, batch_item_waves=item_waves)
+    assert st["fallbacks"] == 0 and st["completed"] == len(reqs)
+    alone = sd.Context(0)
+    for (p, lam), r in zip(reqs, res):
+        assert r.path == sd.PATH_PERSISTENT
+        assert (r.sched_threads, r.sched_item_waves, r.sched_tuned) == (256, item_waves, 1)
+        assert key(r) == key(alone.design(p, gt, gp, lam))
+    alone.close()
