@@ -172,11 +172,31 @@ sd_status sd_context_create_external(void *hip_stream, void *dev_pool, size_t po
                                      const sd_options *opt, sd_context **out);
 void sd_context_destroy(sd_context *ctx);
 
+/* Tuning cache for processes that should not re-explore schedules a previous process measured.
+ * sd_tuning_save writes the context's settled choices to the text file `path` (overwritten): a
+ * header line "sparsedesign-tuning 1", a line "device gfx950 <compute units>", then one line
+ * "batch <class> <grid> <threads> <item_waves>" per settled batched-launch class (the class of
+ * the batch tuner: floor log2 of the members' mean length times 8 plus min(4, floor log2 of the
+ * member count)) and one line "span <class> <band> <threads> <item_waves>" per tuned span band
+ * of the plain path (class floor log2 of the mRNA length in nucleotides, band floor log2 of the
+ * span's layer pairs).  Classes still exploring are not written.  SD_E_ARG if the file cannot be written.
+ * sd_tuning_load installs such a file's entries as settled choices of `ctx` (replacing those of
+ * the same classes), so their first designs run the saved schedules without exploring.  The whole
+ * file is checked first and nothing is installed if any part fails: SD_E_ARG for a missing or
+ * malformed file, a device line of another architecture or compute-unit count, a batched
+ * schedule this device cannot keep resident, or a span tile the library does not have.
+ * Schedules fixed in the context's options still take precedence. */
+sd_status sd_tuning_save(const sd_context *ctx, const char *path);
+sd_status sd_tuning_load(sd_context *ctx, const char *path);
+
 /* One design, plain mode (Sec. 4.1 recurrences in the span order of Sec. 5, Algorithm 1): the
  * automaton of `protein` (NUL-terminated one-letter string, optional final '*') is built on the
  * host and uploaded, the forward fill runs as one span-step kernel launch per span length on
- * the context's stream, the tables are copied back and the canonical first-match traceback runs
- * on the host (deferred traceback, Sec. 5) with an exact self-check.  lambda_kcal >= 0 weights
+ * the context's stream, and the canonical first-match traceback (deferred traceback, Sec. 5)
+ * runs on the device over the resident tables; only the chosen path (one base and pair partner
+ * per nucleotide, the energy, the path cost) is copied back, and the host builds the strings and
+ * checks the design exactly (the bases spell a path of the automaton whose costs add up to the
+ * optimum's).  lambda_kcal >= 0 weights
  * the codon cost (eq. 1).  On success *out is filled and owns two strings (sd_result_free); on
  * error *out is untouched: SD_E_PROTEIN / SD_E_CODON_TABLE / SD_E_LAMBDA / SD_E_RANGE for bad
  * inputs (no kernel launched), SD_E_NOMEM / SD_E_DEVICE for allocation or HIP failures,

@@ -41,6 +41,7 @@ EXPORTS = [
     "sd_design_motifs_tables", "sd_motif_lattice_size", "sd_context_create_external",
     "sd_sizer_request_bytes", "sd_fixed_shift", "sd_design_batch_tables",
     "sd_sizer_predict_host", "sd_design_noalloc", "sd_multiloop_abstract",
+    "sd_tuning_save", "sd_tuning_load",
 ]
 
 
@@ -103,6 +104,8 @@ def lib():
         L.sd_codon_table_free.argtypes = [vp]
         L.sd_context_create.argtypes = [C.c_int, C.POINTER(Options), C.POINTER(vp)]
         L.sd_context_destroy.argtypes = [vp]
+        L.sd_tuning_save.argtypes = [vp, C.c_char_p]
+        L.sd_tuning_load.argtypes = [vp, C.c_char_p]
         L.sd_design.argtypes = [vp, C.c_char_p, vp, vp, C.c_double, C.POINTER(_Result)]
         L.sd_design_noalloc.argtypes = [vp, C.c_char_p, vp, vp, C.c_double, C.POINTER(_Result)]
         L.sd_design_motifs.argtypes = [vp, C.c_char_p, C.POINTER(C.c_char_p), C.c_int, vp, vp, C.c_double,
@@ -273,6 +276,14 @@ class Context:
             self.h = None
 
     __del__ = close
+
+    def tuning_save(self, path: str) -> None:
+        """Writes the context's settled schedule choices to a text file (sd_tuning_save)."""
+        _check(lib().sd_tuning_save(self.h, str(path).encode()), "sd_tuning_save")
+
+    def tuning_load(self, path: str) -> None:
+        """Installs a tuning file's choices as settled (sd_tuning_load; all or nothing)."""
+        _check(lib().sd_tuning_load(self.h, str(path).encode()), "sd_tuning_load")
 
     def design(self, protein: str, table: CodonTable, params: Params, lam: float) -> Result:
         r = _Result()

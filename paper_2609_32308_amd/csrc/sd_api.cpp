@@ -243,6 +243,7 @@ extern "C" void sd_context_destroy(sd_context* c) {
     if (c->ev0) hipEventDestroy(c->ev0);
     if (c->ev1) hipEventDestroy(c->ev1);
     for (hipEvent_t ev : c->tev) hipEventDestroy(ev);
+    for (hipEvent_t ev : c->bev) hipEventDestroy(ev);
     if (c->dbg) hipFree(c->dbg);
     if (c->stream && !c->external) hipStreamDestroy(c->stream);
     delete c;
@@ -1656,4 +1657,106 @@ extern "C" sd_status sd_occupancy(sd_context* ctx, int n, const char* const* pro
     if (!outs)
         for (auto& r : tmp) sd_result_free(&r);
     return SD_OK;
+}
+
+// Tuning file (text): a header line, the device line (architecture, CU count), then one line per
+// settled persistent schedule ("batch class grid threads item_waves") and per tuned span band
+// ("span class band threads item_waves").
+extern "C" sd_status sd_tuning_save(const sd_context* c, const char* path) {
+    using namespace sd;
+    if (!c || !path) return fail(SD_E_ARG, "null argument");
+    try {
+        std::ostringstream os;
+        os << "sparsedesign-tuning 1\n" << "device gfx950 " << c->num_cu << "\n";
+        for (const auto& kv : c->tune)
+            if (kv.second.settled)
+                os << "batch " << kv.first << " " << kv.second.best.grid << " " << kv.second.best.threads << " "
+                   << kv.second.best.item_waves << "\n";
+        for (const auto& kv : c->span_tune)
+            if (kv.second.settled)
+                for (int b = 0; b < sd_context::kSpanBands; b++)
+                    if (kv.second.tuned[b])
+                        os << "span " << kv.first << " " << b << " " << kv.second.best[b].threads << " "
+                           << kv.second.best[b].item_waves << "\n";
+        std::ofstream f(path, std::ios::trunc);
+        f << os.str();
+        f.close();
+        if (!f) return fail(SD_E_ARG, std::string("cannot write ") + path);
+        return SD_OK;
+    } catch (...) {
+        return fail(SD_E_INTERNAL, "unexpected exception");
+    }
+}
+
+extern "C" sd_status sd_tuning_load(sd_context* c, const char* path) {
+    using namespace sd;
+    if (!c || !path) return fail(SD_E_ARG, "null argument");
+    try {
+        std::ifstream f(path);
+        if (!f) return fail(SD_E_ARG, std::string("cannot read ") + path);
+        std::string line;
+        if (!std::getline(f, line) || line != "sparsedesign-tuning 1") return fail(SD_E_ARG, "not a tuning file");
+        std::string w1, arch;
+        int cus = 0;
+        if (!std::getline(f, line)) return fail(SD_E_ARG, "tuning file without a device line");
+        {
+            std::istringstream is(line);
+            if (!(is >> w1 >> arch >> cus) || w1 != "device") return fail(SD_E_ARG, "malformed device line");
+            if (arch != "gfx950" || cus != c->num_cu)
+                return fail(SD_E_ARG, "tuning file written for " + arch + " with " + std::to_string(cus) +
+                                          " CUs; this device is gfx950 with " + std::to_string(c->num_cu));
+        }
+        // parse and validate everything before installing anything
+        std::map<int, sd_context::Sched> batch;
+        std::map<int, std::map<int, sd_context::SpanTile>> span;
+        for (int ln = 3; std::getline(f, line); ln++) {
+            if (line.empty()) continue;
+            std::istringstream is(line);
+            std::string kind;
+            int cls = 0, x = 0, threads = 0, iw = 0;
+            const std::string where = " at line " + std::to_string(ln);
+            if (!(is >> kind >> cls >> x >> threads >> iw)) return fail(SD_E_ARG, "malformed tuning line" + where);
+            if (kind == "batch") {
+                int per_cu = 0;
+                if (!persistent_schedule_valid(threads, iw) || persistent_occupancy(threads, iw, &per_cu) != hipSuccess ||
+                    x <= 0 || x % c->num_cu != 0 || x / c->num_cu > per_cu)
+                    return fail(SD_E_ARG, "persistent schedule this device cannot run" + where);
+                sd_context::Sched sc;
+                sc.grid = x;
+                sc.threads = threads;
+                sc.item_waves = iw;
+                batch[cls] = sc;
+            } else if (kind == "span") {
+                bool ok = false;
+                for (int k = 0; k < sd_context::kSpanCands; k++)
+                    ok |= kSpanCandThreads[k] == threads && kSpanCandWaves[k] == iw;
+                ok &= x >= 0 && x < sd_context::kSpanBands;
+                if (!ok) return fail(SD_E_ARG, "span tile this library does not have" + where);
+                sd_context::SpanTile t;
+                t.threads = threads;
+                t.item_waves = iw;
+                span[cls][x] = t;
+            } else {
+                return fail(SD_E_ARG, "unknown tuning entry" + where);
+            }
+        }
+        for (const auto& kv : batch) {
+            sd_context::Tune& T = c->tune[kv.first];
+            T = sd_context::Tune();
+            T.settled = true;
+            T.best = kv.second;
+        }
+        for (const auto& kv : span) {
+            sd_context::SpanTune& T = c->span_tune[kv.first];
+            T = sd_context::SpanTune();
+            T.settled = true;
+            for (const auto& bt : kv.second) {
+                T.tuned[bt.first] = true;
+                T.best[bt.first] = bt.second;
+            }
+        }
+        return SD_OK;
+    } catch (...) {
+        return fail(SD_E_INTERNAL, "unexpected exception");
+    }
 }
