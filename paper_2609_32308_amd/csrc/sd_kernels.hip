@@ -384,16 +384,30 @@ struct WaveTeam {
     }
 };
 
+// A value every lane of the wave holds (read from one LDS address), moved to a scalar register so
+// that the addresses and loop bounds derived from it stay scalar.
+__device__ __forceinline__ int uni(int x) { return __builtin_amdgcn_readfirstlane(x); }
+__device__ __forceinline__ int64_t uni(int64_t x) {
+    const int hi = __builtin_amdgcn_readfirstlane((int)(x >> 32)), lo = __builtin_amdgcn_readfirstlane((int)x);
+    return (int64_t)(((uint64_t)(uint32_t)hi << 32) | (uint32_t)lo);
+}
+
 template <int NW>  // waves per workgroup
 struct GroupShared {
     int64_t vbuf[kMaxWidth * kMaxWidth][6];  // typed closed values of this layer pair's cells
     int64_t cellB[kMaxWidth * kMaxWidth];
     int keep[kMaxWidth * kMaxWidth];          // 0 none, 1 strict, 2 retained non-strict
-    int combo[kMaxWidth * kMaxWidth * 6];     // (cell, type) jobs with an out-edge of label x
+    uint8_t combo[kMaxWidth * kMaxWidth * 6]; // (cell, type) jobs with an out-edge of label x
     int ncombo;
     int64_t red[NW][2];
     int64_t red2[NW][2];
     LabPair lab[NW][16];
+    // the pair's automaton and segment metadata, read once per pair
+    int adst[kMaxWidth][4];      // out-edge targets of the left states by label (-1 none)
+    int64_t aU[kMaxWidth][4];    //   and their costs
+    int bin[kMaxWidth + 1];      // in-edge range starts of the right states (and the end)
+    int bcnt[kMaxWidth], bcap[kMaxWidth];
+    int64_t boff[kMaxWidth];     // committed count, capacity and offset of each C_b
 };
 
 // Bulges of >= 3 bases through the in-edge b1 -> b: the unpaired side costs its gap (tail +
@@ -425,13 +439,14 @@ template <class IT>
 __device__ int64_t ml_closure(const IT& I, const SmallE& S, int t, int a1, int64_t Ua, int y, int ib0,
                               int ib1, int p, int g, int lane) {
     int64_t v = kINF;
+    // the inner pair (a1, b1) spans layers p + 1 .. q - 1 (edges join consecutive layers): at
+    // least 10 layers apart from g = 12 on
     if (g < 12) return v;
     const int32_t mlc = S.ml_closing + S.ml_intern + au_pen(S, t);
+    const int64_t a1row = I.rowoff()[a1] - I.off()[p + 2];
     for (int eb = ib0 + lane; eb < ib1; eb += 64) {
         if (I.in_lab()[eb] != y) continue;
-        const int b1 = I.in_src()[eb];
-        if (I.layer()[b1] - (p + 1) < 10) continue;
-        v = mn(v, I.S2()[cell_of(I, a1, b1)] + Ua + I.in_U()[eb] + fx(mlc, I.shift));
+        v = mn(v, I.S2()[a1row + I.in_src()[eb]] + Ua + I.in_U()[eb] + fx(mlc, I.shift));
     }
     return v;
 }
@@ -446,12 +461,12 @@ __device__ int64_t ml_closure(const IT& I, const SmallE& S, int t, int a1, int64
 template <bool kSpread, class IT>
 __device__ int64_t closed_part(const IT& I, const SmallE& S, const EnergyTables* __restrict__ E,
                                const int32_t* __restrict__ spec, int a, int b, int t, int p, int q,
-                               int part, int nparts, int64_t mini0, int64_t mini1, int lane, LabPair* lab) {
+                               int part, int nparts, int64_t mini0, int64_t mini1, int lane, LabPair* lab,
+                               int a1, int64_t Ua, int ib0, int ib1) {
+    // a1 / Ua: the out-edge of a labelled x (type t's first base) and its cost; ib0 / ib1: b's
+    // in-edge range
     const int g = q - p, s = I.shift;
-    const int a1 = I.out_dst()[a * 4 + kTX[t]];
-    const int64_t Ua = I.out_U()[a * 4 + kTX[t]];
     const int y = kTY[t];
-    const int ib0 = I.in_start()[b], ib1 = I.in_start()[b + 1];
     const int ph = (p % 3) * 3 + (q % 3), cap = min(g - 7, kMaxLoop);
     int64_t v = kINF;
     // bulges of >= 3 bases and the multiloop closure go with the last labelled part when the
@@ -614,19 +629,22 @@ __device__ void produce_state(const IT& I, const SmallE& S, const GroupShared<NW
 // flag: 0 none, 1 strict, 2 retained non-strict (retain-all control).
 template <class IT>
 __device__ int multiloop_cell(const IT& I, int a, int b, int p, int q, int64_t cell, int64_t Bv, int lane,
-                              GroupCounters& ctr) {
-    const int committed = I.ccnt()[b];
-    const int64_t cbase = I.coff()[b];
-    const int ib0 = I.in_start()[b], ib1 = I.in_start()[b + 1];
+                              GroupCounters& ctr, int committed, int64_t cbase, int ib0, int ib1,
+                              const int* adst, const int64_t* aU) {
+    // Every edge joins consecutive layers, so the in-edge sources of b lie in layer q - 1 and the
+    // out-edge targets of a in layer p + 1: both are inner states of the pair exactly when g >= 2,
+    // and their cells are found without reading their layers.  committed / cbase: C_b's count and
+    // offset; ib0 / ib1: b's in-edge range; adst / aU: a's out-edge targets by label (-1 none)
+    // and their costs.
+    const int g = q - p;
+    const int64_t arow = cell - b;  // cell(a, c) = arow + c for every c
+    const int64_t* __restrict__ S1r = I.S1() + arow;
+    const int64_t* __restrict__ S2r = I.S2() + arow;
     int64_t s2 = kINF;
-    for (int eb = ib0 + lane; eb < ib1; eb += 64) {
-        const int bp = I.in_src()[eb];
-        if (I.layer()[bp] > p) s2 = mn(s2, I.S2()[cell_of(I, a, bp)] + I.in_U()[eb] + I.mlbase_fx);
-    }
-    const int64_t arow = I.rowoff()[a] - I.off()[p + 1];
+    if (g >= 2)
+        for (int eb = ib0 + lane; eb < ib1; eb += 64) s2 = mn(s2, S2r[I.in_src()[eb]] + I.in_U()[eb] + I.mlbase_fx);
     const int* __restrict__ cc = I.cc() + cbase;
     const int64_t* __restrict__ cB = I.cB() + cbase;
-    const int64_t* __restrict__ S1r = I.S1() + arow;
     // four entries per lane and round, their loads issued together: the gathers of S1(a, c)
     // depend on the start states, so one entry at a time would serialise two load latencies
     // per 64 entries
@@ -641,14 +659,12 @@ __device__ int multiloop_cell(const IT& I, int a, int b, int p, int q, int64_t c
     for (; k < committed; k += 64) s2 = mn(s2, S1r[cc[k] & 0x7fffffff] + cB[k]);
     s2 = norm_inf(wave_min(s2));
     int64_t ps = s2;
-    if (lane < 4) {
-        const int ap = I.out_dst()[a * 4 + lane];
-        if (ap >= 0 && I.layer()[ap] < q)
-            ps = mn(ps, I.S1()[cell_of(I, ap, b)] + I.out_U()[a * 4 + lane] + I.mlbase_fx);
-    }
-    for (int eb = ib0 + lane; eb < ib1; eb += 64) {
-        const int bp = I.in_src()[eb];
-        if (I.layer()[bp] > p) ps = mn(ps, I.S1()[cell_of(I, a, bp)] + I.in_U()[eb] + I.mlbase_fx);
+    if (g >= 2) {
+        if (lane < 4) {
+            const int ap = adst[lane];
+            if (ap >= 0) ps = mn(ps, I.S1()[I.rowoff()[ap] + (b - I.off()[p + 2])] + aU[lane] + I.mlbase_fx);
+        }
+        for (int eb = ib0 + lane; eb < ib1; eb += 64) ps = mn(ps, S1r[I.in_src()[eb]] + I.in_U()[eb] + I.mlbase_fx);
     }
     ps = norm_inf(wave_min(ps));
     int keep = 0;
@@ -664,31 +680,48 @@ __device__ int multiloop_cell(const IT& I, int a, int b, int p, int q, int64_t c
     return keep;
 }
 
+// The same with the per-pair metadata read from the instance.
+template <class IT>
+__device__ int multiloop_cell(const IT& I, int a, int b, int p, int q, int64_t cell, int64_t Bv, int lane,
+                              GroupCounters& ctr) {
+    return multiloop_cell(I, a, b, p, q, cell, Bv, lane, ctr, I.ccnt()[b], I.coff()[b], I.in_start()[b],
+                          I.in_start()[b + 1], I.out_dst() + a * 4, I.out_U() + a * 4);
+}
+
 // Appends the retained entries (a, B(a, b)) of layer pair (p, q) to the segments C_b in
 // start-state order, one lane per right endpoint: the caller's workgroup owns these segments in
 // step g (endpoint ownership), so no atomics are needed and the layout is deterministic.  An
 // append beyond a segment's capacity records the earliest overflowing span instead.
 template <class IT>
 __device__ void append_candidates(const IT& I, int a_lo, int wa, int b_lo, int wb, const int* keep,
-                                  const int64_t* cellB, int g, int lane) {
+                                  const int64_t* cellB, int g, int lane, int committed, int cap,
+                                  int64_t base) {
+    // committed / cap / base: lane < wb's segment C_(b_lo + lane), count, capacity and offset
     int added = 0;
     if (lane < wb) {
-        const int b = b_lo + lane;
-        const int committed = I.ccnt()[b];
         for (int ia = 0; ia < wa; ia++) {
             const int ci = ia * wb + lane;
             if (!keep[ci]) continue;
             const int slot = committed + added;
-            if (slot < I.ccap()[b]) {
-                I.cc()[I.coff()[b] + slot] = (a_lo + ia) | (keep[ci] == 1 ? 0 : (int)0x80000000);
-                I.cB()[I.coff()[b] + slot] = cellB[ci];
+            if (slot < cap) {
+                I.cc()[base + slot] = (a_lo + ia) | (keep[ci] == 1 ? 0 : (int)0x80000000);
+                I.cB()[base + slot] = cellB[ci];
             } else {
                 atomicMin(&I.stats()[2], (unsigned long long)g);
             }
             added++;
         }
-        if (added) I.ccnt()[b] = min(committed + added, I.ccap()[b]);
+        if (added) I.ccnt()[b_lo + lane] = min(committed + added, cap);
     }
+}
+
+// The same with the segments' counts, capacities and offsets read from the instance.
+template <class IT>
+__device__ void append_candidates(const IT& I, int a_lo, int wa, int b_lo, int wb, const int* keep,
+                                  const int64_t* cellB, int g, int lane) {
+    const bool mine = lane < wb;
+    append_candidates(I, a_lo, wa, b_lo, wb, keep, cellB, g, lane, mine ? I.ccnt()[b_lo + lane] : 0,
+                      mine ? I.ccap()[b_lo + lane] : 0, mine ? I.coff()[b_lo + lane] : 0);
 }
 
 template <int NW, class IT, class Team = BlockTeam>
@@ -709,6 +742,18 @@ __device__ GroupCounters span_group(const IT& I, const SmallE& S, const EnergyTa
     // (cell, type) jobs: the type's first label leaves a and its last label enters b (any other
     // type is infeasible for the cell); typed values cleared
     if (wave == 0) {
+        if (lane < 4 * wa) {
+            const int e = a_lo * 4 + lane;
+            G.adst[lane >> 2][lane & 3] = I.out_dst()[e];
+            G.aU[lane >> 2][lane & 3] = I.out_U()[e];
+        } else if (lane >= 16 && lane <= 16 + wb) {
+            G.bin[lane - 16] = I.in_start()[b_lo + lane - 16];
+        } else if (lane >= 32 && lane < 32 + wb) {
+            const int b = b_lo + lane - 32;
+            G.bcnt[lane - 32] = I.ccnt()[b];
+            G.bcap[lane - 32] = I.ccap()[b];
+            G.boff[lane - 32] = I.coff()[b];
+        }
         int base = 0;
         for (int k0 = 0; k0 < ncell * 6; k0 += 64) {
             const int k = k0 + lane;
@@ -720,7 +765,7 @@ __device__ GroupCounters span_group(const IT& I, const SmallE& S, const EnergyTa
                       ((I.inmask()[b_lo + ci % wb] >> kTY[t]) & 1);
             }
             const unsigned long long m = __ballot(job);
-            if (job) G.combo[base + __popcll(m & ((1ull << lane) - 1ull))] = k;
+            if (job) G.combo[base + __popcll(m & ((1ull << lane) - 1ull))] = (uint8_t)k;
             base += __popcll(m);
         }
         if (lane == 0) G.ncombo = base;
@@ -732,9 +777,10 @@ __device__ GroupCounters span_group(const IT& I, const SmallE& S, const EnergyTa
     const int njobs = nparts * G.ncombo;
     for (int k = wave; k < njobs; k += nw) {
         const int cmb = G.combo[k / nparts], ci = cmb / 6, t = cmb - 6 * ci;
-        const int a = a_lo + ci / wb, b = b_lo + ci % wb;
+        const int ia = ci / wb, ib = ci - wb * ia, a = a_lo + ia, b = b_lo + ib;
         const int64_t v = closed_part<(NW <= 4)>(I, S, E, spec, a, b, t, p, q, k % nparts, nparts, mini0, mini1, lane,
-                                                  G.lab[wave]);
+                                                  G.lab[wave], uni(G.adst[ia][kTX[t]]), uni(G.aU[ia][kTX[t]]),
+                                                  uni(G.bin[ib]), uni(G.bin[ib + 1]));
         if (lane == 0 && v < kINF)
             __hip_atomic_fetch_min(&G.vbuf[ci][t], v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
     }
@@ -743,7 +789,7 @@ __device__ GroupCounters span_group(const IT& I, const SmallE& S, const EnergyTa
     // cell per wave from the first wave on.  Every scan reads only entries committed by earlier
     // spans.
     for (int ci = wave; ci < ncell; ci += nw) {
-        const int a = a_lo + ci / wb, b = b_lo + ci % wb;
+        const int ia = ci / wb, ib = ci - wb * ia, a = a_lo + ia, b = b_lo + ib;
         const int64_t cell = I.rowoff()[a] + (b - I.off()[p + 1]);
         int64_t Bv = kINF;
         for (int t = 0; t < 6; t++) {
@@ -751,7 +797,8 @@ __device__ GroupCounters span_group(const IT& I, const SmallE& S, const EnergyTa
             if (lane == t) I.V()[cell * 6 + t] = v;
             if (v < kINF) Bv = mn(Bv, v + fx(S.ml_intern + au_pen(S, t), s));
         }
-        const int keep = multiloop_cell(I, a, b, p, q, cell, Bv, lane, ctr);
+        const int keep = multiloop_cell(I, a, b, p, q, cell, Bv, lane, ctr, uni(G.bcnt[ib]), uni(G.boff[ib]),
+                                        uni(G.bin[ib]), uni(G.bin[ib + 1]), G.adst[ia], G.aU[ia]);
         if (lane == 0) {
             G.keep[ci] = keep;
             G.cellB[ci] = Bv;
@@ -783,7 +830,9 @@ __device__ GroupCounters span_group(const IT& I, const SmallE& S, const EnergyTa
         }
         // appends in start-state order, one lane per right endpoint (this group owns C_b in
         // this step)
-        append_candidates(I, a_lo, wa, b_lo, wb, G.keep, G.cellB, g, lane);
+        const bool mine = lane < wb;
+        append_candidates(I, a_lo, wa, b_lo, wb, G.keep, G.cellB, g, lane, mine ? G.bcnt[lane] : 0,
+                          mine ? G.bcap[lane] : 0, mine ? G.boff[lane] : (int64_t)0);
     }
     // both-separable minima of the next span's pair (p, q + 1), by the waves other than wave 0
     // (busy with the appends): they read LM of spans <= g - 7, complete before this step
