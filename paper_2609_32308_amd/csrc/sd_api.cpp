@@ -333,8 +333,15 @@ InstLayout layout_instance(const Lattice& L, char* A, char* B, Inst& I) {
     bool ok = L.fwd_crow.size() == L.fwd_meta.size() && (int64_t)L.inmask.size() == N && (int64_t)L.fwd_off.size() == 4 * N + 1 && (int64_t)L.bwd_off.size() == 4 * N + 1 &&
               (int64_t)L.hpB.size() == 16 * N && (int64_t)L.OB.size() == 72 * N && (int64_t)L.OA.size() == 72 * N;
     for (const Ext& e : ea) ok = ok && e.bytes <= e.slot;
+    // the span kernels locate the cells of edge neighbours from the layering: every edge must
+    // join consecutive layers (the in-edges are the out-edges reversed)
+    for (int64_t e = 0; ok && e < 4 * N && e < (int64_t)L.out_dst.size(); e++) {
+        const int d = L.out_dst[e];
+        ok = d < 0 || (d < N && L.layer[d] == L.layer[e / 4] + 1);
+    }
     if (!ok) {
-        // a layout that does not hold its arrays is a library bug: refuse to place the instance
+        // a layout that does not hold its arrays, or an automaton whose edges skip layers, is a
+        // library bug: refuse to place the instance
         InstLayout bad;
         bad.a_bytes = bad.b_bytes = 0;
         return bad;
