@@ -433,24 +433,6 @@ __device__ int64_t long_bulges(const IT& I, const SmallE& S, int t, int a1, int 
     return v;
 }
 
-// Multiloop closure (ML_closing + ML_intern + AU) + S2 of the interior, over the in-edges of b
-// labelled y.
-template <class IT>
-__device__ int64_t ml_closure(const IT& I, const SmallE& S, int t, int a1, int64_t Ua, int y, int ib0,
-                              int ib1, int p, int g, int lane) {
-    int64_t v = kINF;
-    // the inner pair (a1, b1) spans layers p + 1 .. q - 1 (edges join consecutive layers): at
-    // least 10 layers apart from g = 12 on
-    if (g < 12) return v;
-    const int32_t mlc = S.ml_closing + S.ml_intern + au_pen(S, t);
-    const int64_t a1row = I.rowoff()[a1] - I.off()[p + 2];
-    for (int eb = ib0 + lane; eb < ib1; eb += 64) {
-        if (I.in_lab()[eb] != y) continue;
-        v = mn(v, I.S2()[a1row + I.in_src()[eb]] + Ua + I.in_U()[eb] + fx(mlc, I.shift));
-    }
-    return v;
-}
-
 // One part of the typed closed value V_t(a, b), with the lanes of one wave:
 //   part 0: hairpin, stacks and bulges of 1-2 bases;
 //   part 1: interior loops with a separable side (one-sided, both separable);
@@ -472,6 +454,12 @@ __device__ int64_t closed_part(const IT& I, const SmallE& S, const EnergyTables*
     // bulges of >= 3 bases and the multiloop closure go with the last labelled part when the
     // labelled list is split, else with part 0
     const bool long_here = part == (nparts >= 4 ? nparts - 1 : 0);
+    // multiloop closure (ML_closing + ML_intern + AU + S2 of the interior (a1, b1)) over the same
+    // in-edges: b1 lies in layer q - 1 and a1 in layer p + 1, at least 10 layers apart from
+    // g = 12 on; its S2 value is read before the in-edge's other loops so that it overlaps them
+    const bool ml_here = long_here && g >= 12;
+    const int64_t a1row = ml_here ? I.rowoff()[a1] - I.off()[p + 2] : 0;
+    const int64_t mlc = fx(S.ml_closing + S.ml_intern + au_pen(S, t), s);
     if (part == 0) {
         v = hairpin_lane(I, S, spec, a, b, t, a1, Ua, p, g, lane);
         if (g >= 7) {
@@ -479,22 +467,24 @@ __device__ int64_t closed_part(const IT& I, const SmallE& S, const EnergyTables*
                 if (I.in_lab()[eb] != y) continue;
                 const int b1 = I.in_src()[eb];
                 const int64_t Uab = Ua + I.in_U()[eb];
+                const int64_t s2 = ml_here ? I.S2()[a1row + b1] : kINF;
                 v = mn(v, bulge_lanes(I, S, t, a1, b1, Uab, p, q, cap, lane));
                 if (long_here) v = mn(v, long_bulges(I, S, t, a1, b1, Uab, p, q, cap, lane));
+                if (s2 < kINF) v = mn(v, s2 + Uab + mlc);
             }
         }
-        if (long_here) v = mn(v, ml_closure(I, S, t, a1, Ua, y, ib0, ib1, p, g, lane));
     } else if (part >= 2) {
         if (g >= 7) {
             for (int eb = ib0; eb < ib1; eb++) {
                 if (I.in_lab()[eb] != y) continue;
                 const int b1 = I.in_src()[eb];
                 const int64_t Uab = Ua + I.in_U()[eb];
+                const int64_t s2 = ml_here ? I.S2()[a1row + b1] : kINF;
                 v = mn(v, labelled_pairs(I, S, E, t, a1, b1, Uab, ph, cap, lane, lab, part - 2, nparts - 2));
                 if (long_here) v = mn(v, long_bulges(I, S, t, a1, b1, Uab, p, q, cap, lane));
+                if (s2 < kINF) v = mn(v, s2 + Uab + mlc);
             }
         }
-        if (long_here) v = mn(v, ml_closure(I, S, t, a1, Ua, y, ib0, ib1, p, g, lane));
     } else {
         if (g >= 7) {
             const int64_t* oa = I.OA() + (int64_t)(a1 * 6 + t) * 12;
@@ -538,9 +528,10 @@ __device__ void produce_state(const IT& I, const SmallE& S, const GroupShared<NW
         const int lab = lane & 3, grp = lane >> 2;
         const int qc = p + g + 1, pc = p - 1;  // consumer closing layers (left / right state)
         int64_t o[4] = {kINF, kINF, kINF, kINF};
-        // one separable length at a time: unrolling keeps both lengths' ring values and tails
-        // live at once, which made the 80-VGPR instantiation spill here
-#pragma unroll 1
+        // one separable length at a time in workgroup teams: unrolling keeps both lengths' ring
+        // values and tails live at once, which made the 80-VGPR instantiation spill here; a
+        // one-wave team (128 VGPRs) issues both lengths' loads together
+#pragma unroll (NW == 1 ? 2 : 1)
         for (int h = 0; h < 2; h++) {
             const int ls = 3 + grp + 16 * h, g2 = g - ls;
             if (ls > 29 || g2 < 5) continue;
