@@ -441,7 +441,7 @@ __device__ int64_t long_bulges(const IT& I, const SmallE& S, int t, int a1, int 
 //   bulges of >= 3 bases and the multiloop closure: the last part when nparts >= 4, else part 0.
 // The parts of one (cell, type) run on different waves and meet in an LDS minimum.
 template <bool kSpread, class IT>
-__device__ int64_t closed_part(const IT& I, const SmallE& S, const EnergyTables* __restrict__ E,
+__device__ __forceinline__ int64_t closed_lanes(const IT& I, const SmallE& S, const EnergyTables* __restrict__ E,
                                const int32_t* __restrict__ spec, int a, int b, int t, int p, int q,
                                int part, int nparts, int64_t mini0, int64_t mini1, int lane, LabPair* lab,
                                int a1, int64_t Ua, int ib0, int ib1) {
@@ -508,7 +508,16 @@ __device__ int64_t closed_part(const IT& I, const SmallE& S, const EnergyTables*
             }
         }
     }
-    return norm_inf(wave_min(v));
+    return v;  // this lane's minimum
+}
+
+template <bool kSpread, class IT>
+__device__ int64_t closed_part(const IT& I, const SmallE& S, const EnergyTables* __restrict__ E,
+                               const int32_t* __restrict__ spec, int a, int b, int t, int p, int q,
+                               int part, int nparts, int64_t mini0, int64_t mini1, int lane, LabPair* lab,
+                               int a1, int64_t Ua, int ib0, int ib1) {
+    return norm_inf(wave_min(closed_lanes<kSpread>(I, S, E, spec, a, b, t, p, q, part, nparts, mini0, mini1, lane,
+                                                   lab, a1, Ua, ib0, ib1)));
 }
 
 // Per-state tables of span g for later two-loops, one state per wave (lanes as noted):
@@ -765,7 +774,24 @@ __device__ GroupCounters span_group(const IT& I, const SmallE& S, const EnergyTa
     // phase 1: typed closed values; the parts of every (cell, type) job on separate waves
     // labelled pairs over 1, 2 or 4 waves: wide workgroups run spans with few layer pairs
     constexpr int nparts = NW >= 16 ? 6 : NW >= 8 ? 4 : 3;
-    const int njobs = nparts * G.ncombo;
+    if constexpr (NW == 1) {
+        // one wave runs every part of a job: one reduction per job, and the value is stored
+        // directly (each (cell, type) is one job)
+        for (int j = 0; j < G.ncombo; j++) {
+            const int cmb = G.combo[j], ci = cmb / 6, t = cmb - 6 * ci;
+            const int ia = ci / wb, ib = ci - wb * ia, a = a_lo + ia, b = b_lo + ib;
+            const int a1 = uni(G.adst[ia][kTX[t]]), i0 = uni(G.bin[ib]), i1 = uni(G.bin[ib + 1]);
+            const int64_t Ua = uni(G.aU[ia][kTX[t]]);
+            int64_t v = kINF;
+#pragma unroll
+            for (int part = 0; part < nparts; part++)
+                v = mn(v, closed_lanes<true>(I, S, E, spec, a, b, t, p, q, part, nparts, mini0, mini1, lane,
+                                             G.lab[wave], a1, Ua, i0, i1));
+            v = norm_inf(wave_min(v));
+            if (lane == 0) G.vbuf[ci][t] = v;
+        }
+    }
+    const int njobs = NW == 1 ? 0 : nparts * G.ncombo;
     for (int k = wave; k < njobs; k += nw) {
         const int cmb = G.combo[k / nparts], ci = cmb / 6, t = cmb - 6 * ci;
         const int ia = ci / wb, ib = ci - wb * ia, a = a_lo + ia, b = b_lo + ib;
