@@ -7,8 +7,8 @@
 //   2. runs one persistent launch of `steps_per_round` span steps over every active instance,
 //      each at its own span (new instances start at span 1 and are initialised by the launch);
 //   3. retires instances that passed their last span: the canonical traceback of all of them
-//      runs on the device in one launch (one wavefront each), only its O(n) outputs are copied
-//      back, and their pool memory is released at once.
+//      runs on the device in one launch (one workgroup of eight wavefronts each), only its O(n)
+//      outputs are copied back, and their pool memory is released at once.
 // An instance whose candidate reservation overflowed is recomputed exactly in plain mode with
 // worst-case segments, so every result equals the standalone design.
 #include <hip/hip_runtime.h>
