@@ -1526,7 +1526,7 @@ sd_status design_batch_impl(sd_context* ctx, int n, const char* const* proteins,
             // span_check debug mode: the whole launch again under another schedule, then a digest
             // of every member's tables from each run must agree
             if (!s && ok && ctx->opt.span_check) s = check_batch_rerun(ctx, Ls, Is, sc, &insts_dev);
-            // the canonical traceback of every member in one launch (one wavefront each)
+            // the canonical traceback of every member in one launch (eight wavefronts each)
             if (!s && ok) {
                 hipError_t e = launch_trace_many(insts_dev, m, (const EnergyTables*)ctx->E_dev,
                                                  (const int32_t*)ctx->spec_dev, ctx->stream);

@@ -94,7 +94,8 @@ hipError_t launch_init(const Inst& I, hipStream_t st);
 hipError_t launch_span(const Inst& I, const EnergyTables* E, const int32_t* spec, int g,
                        int ext_layer, int threads, int item_waves, hipStream_t st);
 hipError_t launch_ext(const Inst& I, const EnergyTables* E, int L, hipStream_t st);
-// canonical traceback of one design (one wavefront) / of every design of a device Inst array
+// canonical traceback of one design (one workgroup of eight wavefronts) / of every design of a
+// device Inst array (one such workgroup each)
 hipError_t launch_trace(const Inst& I, const EnergyTables* E, const int32_t* spec, hipStream_t st);
 hipError_t launch_trace_many(const Inst* insts_dev, int n, const EnergyTables* E, const int32_t* spec,
                              hipStream_t st);

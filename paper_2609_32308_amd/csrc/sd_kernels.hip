@@ -1,12 +1,13 @@
 // gfx950 kernels of the span wavefront (Sec. 5, Algorithm 1, re-designed for the GPU).
 //
-// One step per span length g.  A workgroup (4, 8 or 16 wavefronts) owns one layer pair
-// (p, q = p + g) and therefore every cell (a, b) with a in layer p and b in layer q; it is the
-// only writer of the candidate segments C_b of its right endpoints in this step (the
-// endpoint-ownership rule of Sec. 5), so appends need no atomics and land in start-state order.
-// Its waves split the (cell, type) jobs of the closed values into parts, and inside a part or a
-// cell the lanes split the enumeration and the candidate-prefix scan of eq. (7), then reduce with
-// wavefront min shuffles.  One extra workgroup fills the external column one layer behind.
+// One step per span length g.  A team owns one layer pair (p, q = p + g) and therefore every
+// cell (a, b) with a in layer p and b in layer q: a workgroup of 4, 8 or 16 wavefronts, or one
+// wavefront of a workgroup whose waves work on pairs of their own.  It is the only writer of the
+// candidate segments C_b of its right endpoints in this step (the endpoint-ownership rule of
+// Sec. 5), so appends need no atomics and land in start-state order.  Its waves split the
+// (cell, type) jobs of the closed values into parts, and inside a part or a cell the lanes split
+// the enumeration and the candidate-prefix scan of eq. (7), then reduce with wavefront min
+// shuffles.  One extra team fills the external column one layer behind.
 // Generic lattices (a forbidden-motif matcher intersected with the codon automaton) have their
 // own span kernels in a section of their own below.
 //
@@ -439,7 +440,8 @@ __device__ int64_t long_bulges(const IT& I, const SmallE& S, int t, int a1, int 
 //   parts 2 .. nparts-1: interior loops with both sides explicit (labelled short paths), whose
 //   flattened items are dealt to these parts in blocks of 64;
 //   bulges of >= 3 bases and the multiloop closure: the last part when nparts >= 4, else part 0.
-// The parts of one (cell, type) run on different waves and meet in an LDS minimum.
+// Returns this lane's minimum.  The parts of one (cell, type) run on different waves and meet in
+// an LDS minimum, or, in a one-wave group, run one after another into one wave reduction.
 template <bool kSpread, class IT>
 __device__ __forceinline__ int64_t closed_lanes(const IT& I, const SmallE& S, const EnergyTables* __restrict__ E,
                                const int32_t* __restrict__ spec, int a, int b, int t, int p, int q,
@@ -740,7 +742,9 @@ __device__ GroupCounters span_group(const IT& I, const SmallE& S, const EnergyTa
         mini1 = I.MINI()[mini_idx(p, g, 1)];
     }
     // (cell, type) jobs: the type's first label leaves a and its last label enters b (any other
-    // type is infeasible for the cell); typed values cleared
+    // type is infeasible for the cell); typed values cleared.  Alongside, the pair's metadata is
+    // read once: lanes 0-15 the out-edges of the left states, 16-20 the in-edge range starts of
+    // the right states (and the end of the last), 32-35 their candidate segments.
     if (wave == 0) {
         if (lane < 4 * wa) {
             const int e = a_lo * 4 + lane;
