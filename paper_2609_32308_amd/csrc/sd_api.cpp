@@ -1699,6 +1699,8 @@ extern "C" sd_status sd_tuning_load(sd_context* c, const char* path) {
     using namespace sd;
     if (!c || !path) return fail(SD_E_ARG, "null argument");
     try {
+        hipError_t e = hipSetDevice(c->device);
+        if (e != hipSuccess) return hip_fail(e, "hipSetDevice");
         std::ifstream f(path);
         if (!f) return fail(SD_E_ARG, std::string("cannot read ") + path);
         std::string line;
