@@ -372,11 +372,20 @@ struct GroupCounters {
 // wave; a workgroup barrier there would pair up unrelated points of different waves).
 struct BlockTeam {
     __device__ int tid() const { return threadIdx.x; }
+    __device__ int lane() const { return threadIdx.x & 63; }
     __device__ int size() const { return blockDim.x; }
     __device__ void sync() const { __syncthreads(); }
 };
 struct WaveTeam {
     __device__ int tid() const { return threadIdx.x & 63; }
+    // The lane index produced per call: a one-wave team runs inside the persistent loop, and lane
+    // predicates derived from threadIdx would be hoisted to the kernel entry and held for the
+    // whole launch, where they crowd the scalar registers and are spilled to vector lanes.
+    __device__ int lane() const {
+        int l;
+        asm volatile("v_mbcnt_lo_u32_b32 %0, -1, 0\n\tv_mbcnt_hi_u32_b32 %0, -1, %0" : "=v"(l));
+        return l;
+    }
     __device__ int size() const { return 64; }
     __device__ void sync() const {
         __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
@@ -731,7 +740,7 @@ __device__ GroupCounters span_group(const IT& I, const SmallE& S, const EnergyTa
                                     const int32_t* __restrict__ spec, int p, int q, GroupShared<NW>& G,
                                     Team T = Team()) {
     const int g = q - p, s = I.shift;
-    const int tid = T.tid(), wave = tid >> 6, lane = tid & 63, nw = T.size() >> 6;
+    const int tid = T.tid(), wave = tid >> 6, lane = T.lane(), nw = T.size() >> 6;
     GroupCounters ctr{0, 0};
     const int a_lo = I.off()[p], a_hi = I.off()[p + 1], b_lo = I.off()[q], b_hi = I.off()[q + 1];
     const int wa = a_hi - a_lo, wb = b_hi - b_lo, ncell = wa * wb;
