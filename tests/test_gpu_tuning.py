@@ -138,3 +138,20 @@ def test_bad_files_are_refused_whole(sd, env, batch, saved):
     assert sched(c.design_batch(prots, lams, gt, gp))[3] == 0
     assert c.design(saved["plain"][0], gt, gp, 0.0).sched_tuned == 0
     c.close()
+
+
+def test_fresh_context_saves_an_empty_tuning_file(sd, env, batch, tmp_path):
+    # nothing settled: the file holds only the header and the device line, and loading it leaves
+    # every class exploring
+    gp, gt = env
+    prots, lams = batch
+    c = sd.Context(0)
+    f = tmp_path / "empty.tuning"
+    c.tuning_save(f)
+    lines = f.read_text().splitlines()
+    assert len(lines) == 2 and lines[0] == "sparsedesign-tuning 1" and lines[1].startswith("device gfx950 ")
+    c2 = sd.Context(0)
+    c2.tuning_load(f)
+    assert sched(c2.design_batch(prots, lams, gt, gp))[3] == 0
+    c2.close()
+    c.close()
